@@ -1,0 +1,1030 @@
+/*
+ * mlk_oracle.c -- plain double-precision CPU oracle for the coupled
+ * Yee-FDTD / quantum-emitter time step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is compiled into liboracle and is
+ * loaded by the test-suite, by the package smoke check and by the CPU
+ * baseline leg of the benchmark.  The HIP library never links, includes or
+ * calls it, and it shares no code, header or table with that library.
+ *
+ * Every quantity is FP64.  Each routine is the direct definition of one
+ * step of the method, in the order the method takes them:
+ *   - Maxwell's curl equations with the molecular current (Sec. II.A.1,
+ *     eq. Maxwell), constitutive relation D = eps_r E with a static
+ *     per-cell eps_r and mu = mu0 (eq. Dromega and the text after it),
+ *     discretised on Yee's staggered grid;
+ *   - textbook convolutional PML backed by a perfect conductor, periodic
+ *     and metallic walls (the boundary conditions of Sec. III);
+ *   - Gaussian kernel normalised to unit integral, the regularised field
+ *     E~ = int E . gamma kappa (eqs. Polarization_mol, E_regu_Emi);
+ *   - von Neumann step of each emitter under H0 - E~ . mu (eq.
+ *     von-Neumann-tls), with an optional pure-dephasing Lindblad term
+ *     (Sec. II.B.1, the QuTiP-style open model);
+ *   - the dipole derivative Tr(rho_dot mu) (eq. dipole_derivative) and,
+ *     for the two-level system, its closed form -2 w0 mu01 Im(rho01);
+ *   - the molecular current J = sum_m gamma mu_dot kappa (eqs. J_mol,
+ *     Polarization_mol) that drives the next E update;
+ *   - soft sources and detectors (probe, populations, Poynting flux,
+ *     discrete energy).
+ * The per-step order (field -> emitter -> mu_dot -> current) is the
+ * exchange described in Sec. III (the socket hub's data flow).
+ *
+ * Units are natural: c = eps0 = mu0 = hbar = 1, lengths in cells of size dx.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORA_PEC 0
+#define ORA_PERIODIC 1
+#define ORA_CPML 2
+
+#define ORA_OK 0
+#define ORA_EINVAL 1
+#define ORA_ENOMEM 2
+
+typedef double complex cplx;
+
+typedef struct {
+  int n;          /* number of levels */
+  int tls;        /* 1: exact SU(2) propagator of the basic TLS driver */
+  double pos[3], sigma, gamma;
+  double d[3];    /* dipole operator mu^c = d^c M */
+  double en[6];   /* H0 eigenvalues (H0 is diagonal in this basis) */
+  double M[36];   /* real symmetric, n x n row-major */
+  double gphi;    /* pure-dephasing rate of the Lindblad term */
+  cplx rho[36];
+  int lo[3][3], len[3][3]; /* [component][axis] window start (unwrapped) and length */
+  double* w[3];            /* normalised weights per component, x fastest */
+  double Et[3], mudot[3];
+} ora_emitter;
+
+typedef struct {
+  int kind;  /* 0 plane, 1 point */
+  int axis, index, comp, ijk[3];
+  double amp, omega, tau, t0;
+} ora_source;
+
+typedef struct {
+  double* v;
+  int64_t len, cap;
+} ora_series;
+
+typedef struct ora_sim {
+  int N[3];
+  double dx, dt, courant;
+  int bc[6], npml[6];
+  double pml_m, pml_sscale, pml_kmax, pml_amax, R;
+  size_t ncell;
+  double *E[3], *H[3], *Hprev[3], *J[3], *eps;
+  double *psiE[3][3], *psiH[3][3]; /* [field component][derivative axis] */
+  /* 1-D CPML tables: [axis][0 = integer positions, 1 = half-integer] */
+  double *tb[3][2], *tc[3][2], *tk[3][2];
+  unsigned char* tin[3][2];
+  int64_t step;
+  ora_emitter* em;
+  int nem, cap_em;
+  ora_source* src;
+  int nsrc;
+  int nprobe;
+  int probe_comp[64], probe_ijk[64][3];
+  ora_series probe_series[64];
+  int flux_on, flux_axis, flux_index;
+  ora_series flux_series;
+  double flux_total;
+  double* flux_Eu; /* E^n on the flux plane, saved before the E update */
+  double* flux_Ev;
+  int pop_every;
+  ora_series pop_series;
+  int energy_on;
+  ora_series energy_series;
+} ora_sim;
+
+static void series_push(ora_series* s, double v) {
+  if (s->len == s->cap) {
+    int64_t nc = s->cap ? 2 * s->cap : 1024;
+    double* p = (double*)realloc(s->v, (size_t)nc * sizeof(double));
+    if (!p) { fprintf(stderr, "oracle: out of memory\n"); abort(); }
+    s->v = p;
+    s->cap = nc;
+  }
+  s->v[s->len++] = v;
+}
+
+static inline size_t IDX(const ora_sim* s, int i, int j, int k) {
+  return (size_t)i + (size_t)s->N[0] * ((size_t)j + (size_t)s->N[1] * (size_t)k);
+}
+
+/* Value of a field array at integer index (i,j,k) with the wall rules:
+ * periodic axes wrap; beyond a metallic (or PML-backing) wall the value is
+ * the tangential E on the wall, i.e. zero. */
+static inline double fetch(const ora_sim* s, const double* a, int i, int j, int k) {
+  int q[3] = {i, j, k};
+  for (int ax = 0; ax < 3; ++ax) {
+    if (q[ax] < 0 || q[ax] >= s->N[ax]) {
+      if (s->bc[2 * ax] == ORA_PERIODIC) {
+        q[ax] = ((q[ax] % s->N[ax]) + s->N[ax]) % s->N[ax];
+      } else {
+        return 0.0;
+      }
+    }
+  }
+  return a[IDX(s, q[0], q[1], q[2])];
+}
+
+/* CPML grading at coordinate x along an axis (textbook convolutional PML,
+ * polynomial grading of order m for sigma and kappa, linear alpha). */
+static void pml_profile(const ora_sim* s, int ax, double x, double* b, double* c, double* kinv,
+                        unsigned char* inside) {
+  double Nn = (double)s->N[ax];
+  double depth = -1.0, d = 0.0;
+  if (s->bc[2 * ax] == ORA_CPML && x < (double)s->npml[2 * ax]) {
+    d = (double)s->npml[2 * ax];
+    depth = d - x;
+  } else if (s->bc[2 * ax + 1] == ORA_CPML && x > Nn - (double)s->npml[2 * ax + 1]) {
+    d = (double)s->npml[2 * ax + 1];
+    depth = x - (Nn - d);
+  }
+  if (depth < 0.0) {
+    *b = 1.0; *c = 0.0; *kinv = 1.0; *inside = 0;
+    return;
+  }
+  double u = depth / d;
+  double smax = s->pml_sscale * (s->pml_m + 1.0) / s->dx;
+  double sig = smax * pow(u, s->pml_m);
+  double kap = 1.0 + (s->pml_kmax - 1.0) * pow(u, s->pml_m);
+  double alp = s->pml_amax * (1.0 - u);
+  *b = exp(-(sig / kap + alp) * s->dt);
+  *c = (sig > 0.0) ? sig * (*b - 1.0) / (sig * kap + kap * kap * alp) : 0.0;
+  *kinv = 1.0 / kap;
+  *inside = 1;
+}
+
+/* Spatial derivative with the CPML stretching: (1/kappa) dF + psi, where
+ * psi <- b psi + c dF.  Outside the layers it is dF itself. */
+static inline double stretched(const ora_sim* s, int ax, int half, int pos, double dF, double* psi,
+                               size_t id) {
+  if (!s->tin[ax][half][pos]) return dF;
+  psi[id] = s->tb[ax][half][pos] * psi[id] + s->tc[ax][half][pos] * dF;
+  return s->tk[ax][half][pos] * dF + psi[id];
+}
+
+ora_sim* ora_create(const int* N, double dx, double courant, const int* bc, const int* npml,
+                    double pml_m, double pml_sscale, double pml_kmax, double pml_amax, double R,
+                    int* status) {
+  *status = ORA_EINVAL;
+  if (courant <= 0.0 || courant > 1.0 / sqrt(3.0) || dx <= 0.0 || R <= 0.0) return NULL;
+  for (int ax = 0; ax < 3; ++ax) {
+    if (N[ax] < 1) return NULL;
+    if ((bc[2 * ax] == ORA_PERIODIC) != (bc[2 * ax + 1] == ORA_PERIODIC)) return NULL;
+    for (int f = 0; f < 2; ++f) {
+      if (bc[2 * ax + f] < 0 || bc[2 * ax + f] > 2) return NULL;
+      if (bc[2 * ax + f] == ORA_CPML && (npml[2 * ax + f] < 1 || npml[2 * ax + f] > N[ax] / 2))
+        return NULL;
+    }
+  }
+  ora_sim* s = (ora_sim*)calloc(1, sizeof(ora_sim));
+  if (!s) { *status = ORA_ENOMEM; return NULL; }
+  memcpy(s->N, N, 3 * sizeof(int));
+  s->dx = dx;
+  s->courant = courant;
+  s->dt = courant * dx; /* c = 1 */
+  memcpy(s->bc, bc, 6 * sizeof(int));
+  for (int f = 0; f < 6; ++f) s->npml[f] = (bc[f] == ORA_CPML) ? npml[f] : 0;
+  s->pml_m = pml_m;
+  s->pml_sscale = pml_sscale;
+  s->pml_kmax = pml_kmax;
+  s->pml_amax = pml_amax;
+  s->R = R;
+  s->ncell = (size_t)N[0] * N[1] * N[2];
+  for (int c = 0; c < 3; ++c) {
+    s->E[c] = (double*)calloc(s->ncell, sizeof(double));
+    s->H[c] = (double*)calloc(s->ncell, sizeof(double));
+    s->J[c] = (double*)calloc(s->ncell, sizeof(double));
+  }
+  s->eps = (double*)malloc(s->ncell * sizeof(double));
+  for (size_t q = 0; q < s->ncell; ++q) s->eps[q] = 1.0;
+  for (int ax = 0; ax < 3; ++ax) {
+    int has = (bc[2 * ax] == ORA_CPML) || (bc[2 * ax + 1] == ORA_CPML);
+    for (int c = 0; c < 3; ++c) {
+      if (has && c != ax) {
+        s->psiE[c][ax] = (double*)calloc(s->ncell, sizeof(double));
+        s->psiH[c][ax] = (double*)calloc(s->ncell, sizeof(double));
+      }
+    }
+    for (int h = 0; h < 2; ++h) {
+      s->tb[ax][h] = (double*)malloc(N[ax] * sizeof(double));
+      s->tc[ax][h] = (double*)malloc(N[ax] * sizeof(double));
+      s->tk[ax][h] = (double*)malloc(N[ax] * sizeof(double));
+      s->tin[ax][h] = (unsigned char*)malloc(N[ax]);
+      for (int i = 0; i < N[ax]; ++i)
+        pml_profile(s, ax, (double)i + 0.5 * h, &s->tb[ax][h][i], &s->tc[ax][h][i],
+                    &s->tk[ax][h][i], &s->tin[ax][h][i]);
+    }
+  }
+  *status = ORA_OK;
+  return s;
+}
+
+void ora_destroy(ora_sim* s) {
+  if (!s) return;
+  for (int c = 0; c < 3; ++c) {
+    free(s->E[c]); free(s->H[c]); free(s->Hprev[c]); free(s->J[c]);
+    for (int ax = 0; ax < 3; ++ax) { free(s->psiE[c][ax]); free(s->psiH[c][ax]); }
+    for (int h = 0; h < 2; ++h) {
+      free(s->tb[c][h]); free(s->tc[c][h]); free(s->tk[c][h]); free(s->tin[c][h]);
+    }
+  }
+  free(s->eps);
+  for (int m = 0; m < s->nem; ++m)
+    for (int c = 0; c < 3; ++c) free(s->em[m].w[c]);
+  free(s->em);
+  free(s->src);
+  for (int p = 0; p < s->nprobe; ++p) free(s->probe_series[p].v);
+  free(s->flux_series.v); free(s->flux_Eu); free(s->flux_Ev);
+  free(s->pop_series.v);
+  free(s->energy_series.v);
+  free(s);
+}
+
+double ora_dt(const ora_sim* s) { return s->dt; }
+int64_t ora_step_count(const ora_sim* s) { return s->step; }
+
+int ora_set_eps(ora_sim* s, const double* eps) {
+  for (size_t q = 0; q < s->ncell; ++q)
+    if (!(eps[q] >= 1.0)) return ORA_EINVAL;
+  memcpy(s->eps, eps, s->ncell * sizeof(double));
+  return ORA_OK;
+}
+
+/* comp 0..2 = Ex,Ey,Ez (E^n); 3..5 = Hx,Hy,Hz (H^{n-1/2}) */
+int ora_set_field(ora_sim* s, int comp, const double* v) {
+  if (comp < 0 || comp > 5) return ORA_EINVAL;
+  double* dst = comp < 3 ? s->E[comp] : s->H[comp - 3];
+  memcpy(dst, v, s->ncell * sizeof(double));
+  return ORA_OK;
+}
+
+int ora_get_field(const ora_sim* s, int comp, double* v) {
+  if (comp < 0 || comp > 5) return ORA_EINVAL;
+  const double* src = comp < 3 ? s->E[comp] : s->H[comp - 3];
+  memcpy(v, src, s->ncell * sizeof(double));
+  return ORA_OK;
+}
+
+/* ---------------------------------------------------------------- kernel */
+
+/* Window of component c of an emitter: every Yee point of that component
+ * whose offset from the centre is within R*sigma on each axis; weights
+ * are the Gaussian exp(-|p-r|^2 / 2 sigma^2) normalised to unit sum, the
+ * discrete form of a unit-integral kernel (eq. Polarization_mol). */
+static int build_window(ora_sim* s, ora_emitter* e) {
+  double rs = s->R * e->sigma;
+  for (int ax = 0; ax < 3; ++ax) {
+    if (s->bc[2 * ax] == ORA_PERIODIC) {
+      /* a periodic axis of one cell is an invariant direction (2-D run) */
+      if (s->N[ax] > 1 && (double)s->N[ax] < 2.0 * rs + 2.0) return ORA_EINVAL;
+    } else {
+      double lo = (double)s->npml[2 * ax], hi = (double)(s->N[ax] - s->npml[2 * ax + 1]);
+      if (e->pos[ax] - (rs + 1.0) < lo || e->pos[ax] + (rs + 1.0) > hi) return ORA_EINVAL;
+    }
+  }
+  for (int c = 0; c < 3; ++c) {
+    for (int ax = 0; ax < 3; ++ax) {
+      double sh = (ax == c) ? 0.5 : 0.0;
+      if (s->N[ax] == 1 && s->bc[2 * ax] == ORA_PERIODIC) {
+        /* invariant direction: the kernel is uniform along it, so the window
+         * is the single cell layer and its factor cancels in the normalisation */
+        e->lo[c][ax] = 0;
+        e->len[c][ax] = 1;
+        continue;
+      }
+      int first = 1, lo = 0, hi = -1;
+      int a0 = (int)floor(e->pos[ax] - rs) - 2, a1 = (int)ceil(e->pos[ax] + rs) + 2;
+      for (int i = a0; i <= a1; ++i) {
+        double off = (double)i + sh - e->pos[ax];
+        if (off * off <= rs * rs) {
+          if (first) { lo = i; first = 0; }
+          hi = i;
+        }
+      }
+      e->lo[c][ax] = lo;
+      e->len[c][ax] = hi - lo + 1;
+      if (e->len[c][ax] < 1) return ORA_EINVAL;
+    }
+    int L0 = e->len[c][0], L1 = e->len[c][1], L2 = e->len[c][2];
+    e->w[c] = (double*)malloc((size_t)L0 * L1 * L2 * sizeof(double));
+    if (!e->w[c]) return ORA_ENOMEM;
+    double sum = 0.0;
+    for (int kk = 0; kk < L2; ++kk)
+      for (int jj = 0; jj < L1; ++jj)
+        for (int ii = 0; ii < L0; ++ii) {
+          double p[3] = {e->lo[c][0] + ii + (c == 0 ? 0.5 : 0.0),
+                         e->lo[c][1] + jj + (c == 1 ? 0.5 : 0.0),
+                         e->lo[c][2] + kk + (c == 2 ? 0.5 : 0.0)};
+          double r2 = 0.0;
+          for (int ax = 0; ax < 3; ++ax) r2 += (p[ax] - e->pos[ax]) * (p[ax] - e->pos[ax]);
+          double g = exp(-r2 / (2.0 * e->sigma * e->sigma));
+          e->w[c][ii + L0 * (jj + L1 * kk)] = g;
+          sum += g;
+        }
+    for (int q = 0; q < L0 * L1 * L2; ++q) e->w[c][q] /= sum;
+  }
+  return ORA_OK;
+}
+
+static inline size_t window_cell(const ora_sim* s, const ora_emitter* e, int c, int ii, int jj,
+                                 int kk) {
+  int q[3] = {e->lo[c][0] + ii, e->lo[c][1] + jj, e->lo[c][2] + kk};
+  for (int ax = 0; ax < 3; ++ax) q[ax] = ((q[ax] % s->N[ax]) + s->N[ax]) % s->N[ax];
+  return IDX(s, q[0], q[1], q[2]);
+}
+
+static int grow_emitters(ora_sim* s, int n) {
+  if (s->nem + n <= s->cap_em) return ORA_OK;
+  int nc = s->cap_em ? s->cap_em : 16;
+  while (nc < s->nem + n) nc *= 2;
+  ora_emitter* p = (ora_emitter*)realloc(s->em, (size_t)nc * sizeof(ora_emitter));
+  if (!p) return ORA_ENOMEM;
+  s->em = p;
+  s->cap_em = nc;
+  return ORA_OK;
+}
+
+/* Two-level emitters: H0 = diag(0, w0), mu = d sigma_x (eq. von-Neumann-tls).
+ * rho0 per emitter: (rho11, Re rho01, Im rho01). */
+int ora_add_tls(ora_sim* s, int n, const double* pos, const double* sigma, const double* gamma,
+                const double* omega0, const double* dipole, const double* rho0) {
+  if (grow_emitters(s, n)) return ORA_ENOMEM;
+  for (int q = 0; q < n; ++q) {
+    double p11 = rho0[3 * q], r = rho0[3 * q + 1], im = rho0[3 * q + 2];
+    if (!(p11 >= 0.0 && p11 <= 1.0) || r * r + im * im > p11 * (1.0 - p11) * (1.0 + 1e-12) + 1e-300)
+      return ORA_EINVAL;
+    if (!(sigma[q] > 0.0)) return ORA_EINVAL;
+  }
+  int base = s->nem;
+  for (int q = 0; q < n; ++q) {
+    ora_emitter* e = &s->em[base + q];
+    memset(e, 0, sizeof(*e));
+    e->n = 2;
+    e->tls = 1;
+    memcpy(e->pos, pos + 3 * q, 3 * sizeof(double));
+    e->sigma = sigma[q];
+    e->gamma = gamma[q];
+    memcpy(e->d, dipole + 3 * q, 3 * sizeof(double));
+    e->en[0] = 0.0;
+    e->en[1] = omega0[q];
+    e->M[1] = 1.0;
+    e->M[2] = 1.0;
+    e->gphi = 0.0;
+    double p11 = rho0[3 * q];
+    cplx r01 = rho0[3 * q + 1] + I * rho0[3 * q + 2];
+    e->rho[0] = 1.0 - p11;
+    e->rho[1] = r01;
+    e->rho[2] = conj(r01);
+    e->rho[3] = p11;
+    int st = build_window(s, e);
+    if (st) {
+      for (int c = 0; c < 3; ++c) free(e->w[c]);
+      for (int r2 = 0; r2 < q; ++r2)
+        for (int c = 0; c < 3; ++c) free(s->em[base + r2].w[c]);
+      return st;
+    }
+  }
+  s->nem += n;
+  return ORA_OK;
+}
+
+/* Multilevel emitters with pure dephasing (QuTiP-style open model).
+ * nlev[q] in 2..6; energies packed at eoff, M (n*n real symmetric) and
+ * rho0 (n*n complex, interleaved re/im) packed at moff. */
+int ora_add_multilevel(ora_sim* s, int n, const int* nlev, const int64_t* eoff,
+                       const int64_t* moff, const double* energies, const double* mop,
+                       const double* dipole, const double* gphi, const double* rho0,
+                       const double* pos, const double* sigma, const double* gamma) {
+  if (grow_emitters(s, n)) return ORA_ENOMEM;
+  for (int q = 0; q < n; ++q) {
+    int L = nlev[q];
+    if (L < 2 || L > 6 || !(sigma[q] > 0.0) || !(gphi[q] >= 0.0)) return ORA_EINVAL;
+    const double* Mq = mop + moff[q];
+    for (int a = 0; a < L; ++a)
+      for (int b = 0; b < L; ++b)
+        if (Mq[a * L + b] != Mq[b * L + a]) return ORA_EINVAL;
+  }
+  int base = s->nem;
+  for (int q = 0; q < n; ++q) {
+    ora_emitter* e = &s->em[base + q];
+    memset(e, 0, sizeof(*e));
+    int L = nlev[q];
+    e->n = L;
+    e->tls = 0;
+    memcpy(e->pos, pos + 3 * q, 3 * sizeof(double));
+    e->sigma = sigma[q];
+    e->gamma = gamma[q];
+    memcpy(e->d, dipole + 3 * q, 3 * sizeof(double));
+    for (int a = 0; a < L; ++a) e->en[a] = energies[eoff[q] + a];
+    for (int a = 0; a < L * L; ++a) {
+      e->M[a] = mop[moff[q] + a];
+      e->rho[a] = rho0[2 * (moff[q] + a)] + I * rho0[2 * (moff[q] + a) + 1];
+    }
+    e->gphi = gphi[q];
+    int st = build_window(s, e);
+    if (st) {
+      for (int c = 0; c < 3; ++c) free(e->w[c]);
+      for (int r2 = 0; r2 < q; ++r2)
+        for (int c = 0; c < 3; ++c) free(s->em[base + r2].w[c]);
+      return st;
+    }
+  }
+  s->nem += n;
+  return ORA_OK;
+}
+
+int ora_num_emitters(const ora_sim* s) { return s->nem; }
+
+int ora_get_rho(const ora_sim* s, int m, double* out) {
+  if (m < 0 || m >= s->nem) return ORA_EINVAL;
+  const ora_emitter* e = &s->em[m];
+  for (int a = 0; a < e->n * e->n; ++a) {
+    out[2 * a] = creal(e->rho[a]);
+    out[2 * a + 1] = cimag(e->rho[a]);
+  }
+  return e->n;
+}
+
+int ora_set_rho(ora_sim* s, int m, const double* in) {
+  if (m < 0 || m >= s->nem) return ORA_EINVAL;
+  ora_emitter* e = &s->em[m];
+  for (int a = 0; a < e->n * e->n; ++a) e->rho[a] = in[2 * a] + I * in[2 * a + 1];
+  return ORA_OK;
+}
+
+/* Window weights of emitter m, component c, and their grid indices. */
+int ora_get_window(const ora_sim* s, int m, int c, int64_t* idx, double* w, int cap) {
+  const ora_emitter* e = &s->em[m];
+  int L0 = e->len[c][0], L1 = e->len[c][1], L2 = e->len[c][2];
+  if (L0 * L1 * L2 > cap) return -1;
+  int q = 0;
+  for (int kk = 0; kk < L2; ++kk)
+    for (int jj = 0; jj < L1; ++jj)
+      for (int ii = 0; ii < L0; ++ii, ++q) {
+        idx[q] = (int64_t)window_cell(s, e, c, ii, jj, kk);
+        w[q] = e->w[c][q];
+      }
+  return q;
+}
+
+void ora_get_emitter_io(const ora_sim* s, double* Et, double* mudot) {
+  for (int m = 0; m < s->nem; ++m)
+    for (int c = 0; c < 3; ++c) {
+      if (Et) Et[3 * m + c] = s->em[m].Et[c];
+      if (mudot) mudot[3 * m + c] = s->em[m].mudot[c];
+    }
+}
+
+/* ---------------------------------------------------------- sources etc. */
+
+int ora_add_plane_source(ora_sim* s, int axis, int index, int comp, double amp, double omega,
+                         double tau, double t0) {
+  if (axis < 0 || axis > 2 || comp < 0 || comp > 2 || index < 0 || index >= s->N[axis] ||
+      !(tau > 0.0))
+    return ORA_EINVAL;
+  ora_source* p = (ora_source*)realloc(s->src, (s->nsrc + 1) * sizeof(ora_source));
+  if (!p) return ORA_ENOMEM;
+  s->src = p;
+  ora_source* q = &s->src[s->nsrc++];
+  memset(q, 0, sizeof(*q));
+  q->kind = 0; q->axis = axis; q->index = index; q->comp = comp;
+  q->amp = amp; q->omega = omega; q->tau = tau; q->t0 = t0;
+  return ORA_OK;
+}
+
+int ora_add_point_source(ora_sim* s, int comp, const int* ijk, double amp, double omega,
+                         double tau, double t0) {
+  if (comp < 0 || comp > 2 || !(tau > 0.0)) return ORA_EINVAL;
+  for (int ax = 0; ax < 3; ++ax)
+    if (ijk[ax] < 0 || ijk[ax] >= s->N[ax]) return ORA_EINVAL;
+  ora_source* p = (ora_source*)realloc(s->src, (s->nsrc + 1) * sizeof(ora_source));
+  if (!p) return ORA_ENOMEM;
+  s->src = p;
+  ora_source* q = &s->src[s->nsrc++];
+  memset(q, 0, sizeof(*q));
+  q->kind = 1; q->comp = comp;
+  memcpy(q->ijk, ijk, 3 * sizeof(int));
+  q->amp = amp; q->omega = omega; q->tau = tau; q->t0 = t0;
+  return ORA_OK;
+}
+
+/* Gaussian-pulse time profile of the plane-wave excitation (App. B,
+ * plasmonic heating: a Gaussian pulse with a centre frequency and a width). */
+static double pulse(const ora_source* q, double t) {
+  double u = t - q->t0;
+  return cos(q->omega * u) * exp(-u * u / (2.0 * q->tau * q->tau));
+}
+
+int ora_add_probe(ora_sim* s, int comp, const int* ijk) {
+  if (s->nprobe >= 64 || comp < 0 || comp > 5) return -1;
+  for (int ax = 0; ax < 3; ++ax)
+    if (ijk[ax] < 0 || ijk[ax] >= s->N[ax]) return -1;
+  int id = s->nprobe++;
+  s->probe_comp[id] = comp;
+  memcpy(s->probe_ijk[id], ijk, 3 * sizeof(int));
+  memset(&s->probe_series[id], 0, sizeof(ora_series));
+  return id;
+}
+
+int ora_add_flux_plane(ora_sim* s, int axis, int index) {
+  if (axis < 0 || axis > 2 || index < 1 || index >= s->N[axis] || s->flux_on) return ORA_EINVAL;
+  s->flux_on = 1;
+  s->flux_axis = axis;
+  s->flux_index = index;
+  int u = (axis + 1) % 3, v = (axis + 2) % 3;
+  size_t np = (size_t)s->N[u] * s->N[v];
+  s->flux_Eu = (double*)calloc(np, sizeof(double));
+  s->flux_Ev = (double*)calloc(np, sizeof(double));
+  return ORA_OK;
+}
+
+void ora_record_populations(ora_sim* s, int every) { s->pop_every = every; }
+int ora_record_energy(ora_sim* s, int on) {
+  if (on && !s->Hprev[0])
+    for (int c = 0; c < 3; ++c) {
+      s->Hprev[c] = (double*)calloc(s->ncell, sizeof(double));
+      if (!s->Hprev[c]) return ORA_ENOMEM;
+    }
+  s->energy_on = on;
+  return ORA_OK;
+}
+
+int64_t ora_get_series(const ora_sim* s, int which, int id, double* out, int64_t cap) {
+  const ora_series* q = NULL;
+  if (which == 0) { if (id < 0 || id >= s->nprobe) return -1; q = &s->probe_series[id]; }
+  else if (which == 1) q = &s->flux_series;
+  else if (which == 2) q = &s->pop_series;
+  else if (which == 3) q = &s->energy_series;
+  else return -1;
+  if (out) {
+    int64_t n = q->len < cap ? q->len : cap;
+    memcpy(out, q->v, (size_t)n * sizeof(double));
+  }
+  return q->len;
+}
+
+double ora_flux_total(const ora_sim* s) { return s->flux_total; }
+
+/* ------------------------------------------------------------ the fields */
+
+/* H^{n+1/2} = H^{n-1/2} - dt curl E^n  (eq. Maxwell, second line, B = H). */
+static void update_H(ora_sim* s) {
+  const int nx = s->N[0], ny = s->N[1], nz = s->N[2];
+  const double dt = s->dt, idx = 1.0 / s->dx;
+  double *Ex = s->E[0], *Ey = s->E[1], *Ez = s->E[2];
+  double *Hx = s->H[0], *Hy = s->H[1], *Hz = s->H[2];
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        size_t id = IDX(s, i, j, k);
+        double dEz_dy = (fetch(s, Ez, i, j + 1, k) - Ez[id]) * idx;
+        double dEy_dz = (fetch(s, Ey, i, j, k + 1) - Ey[id]) * idx;
+        double dEx_dz = (fetch(s, Ex, i, j, k + 1) - Ex[id]) * idx;
+        double dEz_dx = (fetch(s, Ez, i + 1, j, k) - Ez[id]) * idx;
+        double dEy_dx = (fetch(s, Ey, i + 1, j, k) - Ey[id]) * idx;
+        double dEx_dy = (fetch(s, Ex, i, j + 1, k) - Ex[id]) * idx;
+        /* H components sit at half-integer positions along their derivative axes */
+        double cx = stretched(s, 1, 1, j, dEz_dy, s->psiH[0][1], id) -
+                    stretched(s, 2, 1, k, dEy_dz, s->psiH[0][2], id);
+        double cy = stretched(s, 2, 1, k, dEx_dz, s->psiH[1][2], id) -
+                    stretched(s, 0, 1, i, dEz_dx, s->psiH[1][0], id);
+        double cz = stretched(s, 0, 1, i, dEy_dx, s->psiH[2][0], id) -
+                    stretched(s, 1, 1, j, dEx_dy, s->psiH[2][1], id);
+        Hx[id] -= dt * cx;
+        Hy[id] -= dt * cy;
+        Hz[id] -= dt * cz;
+      }
+}
+
+/* E^{n+1} = E^n + (dt/eps_r) (curl H^{n+1/2} - J^{n+1/2})  (eq. Maxwell,
+ * first line, D = eps_r E), then the tangential E on metallic walls is 0. */
+static void update_E(ora_sim* s) {
+  const int nx = s->N[0], ny = s->N[1], nz = s->N[2];
+  const double dt = s->dt, idx = 1.0 / s->dx;
+  double *Ex = s->E[0], *Ey = s->E[1], *Ez = s->E[2];
+  double *Hx = s->H[0], *Hy = s->H[1], *Hz = s->H[2];
+  double *Jx = s->J[0], *Jy = s->J[1], *Jz = s->J[2];
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        size_t id = IDX(s, i, j, k);
+        double dHz_dy = (Hz[id] - fetch(s, Hz, i, j - 1, k)) * idx;
+        double dHy_dz = (Hy[id] - fetch(s, Hy, i, j, k - 1)) * idx;
+        double dHx_dz = (Hx[id] - fetch(s, Hx, i, j, k - 1)) * idx;
+        double dHz_dx = (Hz[id] - fetch(s, Hz, i - 1, j, k)) * idx;
+        double dHy_dx = (Hy[id] - fetch(s, Hy, i - 1, j, k)) * idx;
+        double dHx_dy = (Hx[id] - fetch(s, Hx, i, j - 1, k)) * idx;
+        /* E components sit at integer positions along their derivative axes */
+        double cx = stretched(s, 1, 0, j, dHz_dy, s->psiE[0][1], id) -
+                    stretched(s, 2, 0, k, dHy_dz, s->psiE[0][2], id);
+        double cy = stretched(s, 2, 0, k, dHx_dz, s->psiE[1][2], id) -
+                    stretched(s, 0, 0, i, dHz_dx, s->psiE[1][0], id);
+        double cz = stretched(s, 0, 0, i, dHy_dx, s->psiE[2][0], id) -
+                    stretched(s, 1, 0, j, dHx_dy, s->psiE[2][1], id);
+        double ce = dt / s->eps[id];
+        Ex[id] += ce * (cx - Jx[id]);
+        Ey[id] += ce * (cy - Jy[id]);
+        Ez[id] += ce * (cz - Jz[id]);
+      }
+  /* metallic walls (also behind each PML): E tangential to the wall plane
+   * at index 0 of that axis is held at zero */
+  for (int ax = 0; ax < 3; ++ax) {
+    if (s->bc[2 * ax] == ORA_PERIODIC) continue;
+    int u = (ax + 1) % 3, v = (ax + 2) % 3;
+    for (int c = 0; c < 3; ++c) {
+      if (c == ax) continue;
+      for (int jv = 0; jv < s->N[v]; ++jv)
+        for (int iu = 0; iu < s->N[u]; ++iu) {
+          int q[3];
+          q[ax] = 0; q[u] = iu; q[v] = jv;
+          s->E[c][IDX(s, q[0], q[1], q[2])] = 0.0;
+        }
+    }
+  }
+}
+
+/* ------------------------------------------------------------ emitters */
+
+/* E~_m^c = gamma_m sum_p w^c_{m,p} E_c(p)  (eq. E_regu_Emi, discrete). */
+static void gather_one(const ora_sim* s, ora_emitter* e) {
+  for (int c = 0; c < 3; ++c) {
+    int L0 = e->len[c][0], L1 = e->len[c][1], L2 = e->len[c][2];
+    double acc = 0.0;
+    for (int kk = 0; kk < L2; ++kk)
+      for (int jj = 0; jj < L1; ++jj)
+        for (int ii = 0; ii < L0; ++ii)
+          acc += e->w[c][ii + L0 * (jj + L1 * kk)] * s->E[c][window_cell(s, e, c, ii, jj, kk)];
+    e->Et[c] = e->gamma * acc;
+  }
+}
+
+static void matmul(int n, const cplx* A, const cplx* B, cplx* C) {
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) {
+      cplx acc = 0.0;
+      for (int q = 0; q < n; ++q) acc += A[a * n + q] * B[q * n + b];
+      C[a * n + b] = acc;
+    }
+}
+
+static void adjoint(int n, const cplx* A, cplx* B) {
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) B[a * n + b] = conj(A[b * n + a]);
+}
+
+/* rho <- U rho U^dagger */
+static void conjugate_by(int n, const cplx* U, cplx* rho) {
+  cplx T[36], Ud[36], R[36];
+  matmul(n, U, rho, T);
+  adjoint(n, U, Ud);
+  matmul(n, T, Ud, R);
+  memcpy(rho, R, (size_t)n * n * sizeof(cplx));
+}
+
+/* Cyclic Jacobi eigen-decomposition of a real symmetric n x n matrix:
+ * A = Q diag(lam) Q^T (columns of Q are eigenvectors). */
+void ora_jacobi_eig(int n, const double* Ain, double* lam, double* Q) {
+  double A[36];
+  memcpy(A, Ain, (size_t)n * n * sizeof(double));
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) Q[a * n + b] = (a == b) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int a = 0; a < n; ++a)
+      for (int b = 0; b < n; ++b) {
+        tot += A[a * n + b] * A[a * n + b];
+        if (a != b) off += A[a * n + b] * A[a * n + b];
+      }
+    if (off <= 1e-34 * tot || off == 0.0) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        double apq = A[p * n + q];
+        if (apq == 0.0) continue;
+        double app = A[p * n + p], aqq = A[q * n + q];
+        /* rotation angle that annihilates A[p][q] */
+        double theta = (aqq - app) / (2.0 * apq);
+        double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+        for (int r = 0; r < n; ++r) {
+          double arp = A[r * n + p], arq = A[r * n + q];
+          A[r * n + p] = c * arp - sn * arq;
+          A[r * n + q] = sn * arp + c * arq;
+        }
+        for (int r = 0; r < n; ++r) {
+          double apr = A[p * n + r], aqr = A[q * n + r];
+          A[p * n + r] = c * apr - sn * aqr;
+          A[q * n + r] = sn * apr + c * aqr;
+        }
+        for (int r = 0; r < n; ++r) {
+          double qrp = Q[r * n + p], qrq = Q[r * n + q];
+          Q[r * n + p] = c * qrp - sn * qrq;
+          Q[r * n + q] = sn * qrp + c * qrq;
+        }
+      }
+  }
+  for (int a = 0; a < n; ++a) lam[a] = A[a * n + a];
+}
+
+/* Effective Hamiltonian H0 - E~ . mu with mu^c = d^c M (eq. von-Neumann-tls). */
+static void effective_h(const ora_emitter* e, double* Heff) {
+  double g = e->Et[0] * e->d[0] + e->Et[1] * e->d[1] + e->Et[2] * e->d[2];
+  int n = e->n;
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) Heff[a * n + b] = (a == b ? e->en[a] : 0.0) - g * e->M[a * n + b];
+}
+
+/* Two-level exact propagator over dt for constant E~:
+ * H = (w0/2) I + h.sigma with h = (-g, 0, -w0/2), V = cos(|h|dt) - i sin(|h|dt) h.sigma/|h|. */
+static void step_tls(const ora_sim* s, ora_emitter* e) {
+  double g = e->Et[0] * e->d[0] + e->Et[1] * e->d[1] + e->Et[2] * e->d[2];
+  double w0 = e->en[1] - e->en[0];
+  double hx = -g, hz = -0.5 * w0;
+  double Om = sqrt(hx * hx + hz * hz);
+  double ph = Om * s->dt;
+  double cs = cos(ph), sn = (Om > 0.0) ? sin(ph) / Om : s->dt;
+  cplx V[4];
+  V[0] = cs - I * sn * hz;
+  V[1] = -I * sn * hx;
+  V[2] = -I * sn * hx;
+  V[3] = cs + I * sn * hz;
+  conjugate_by(2, V, e->rho);
+}
+
+/* Exact pure-dephasing map over tau: coherences decay as exp(-gphi tau). */
+static void dephase(ora_emitter* e, double tau) {
+  double f = exp(-e->gphi * tau);
+  for (int a = 0; a < e->n; ++a)
+    for (int b = 0; b < e->n; ++b)
+      if (a != b) e->rho[a * e->n + b] *= f;
+}
+
+/* Strang splitting: dephasing(dt/2), unitary exp(-i Heff dt), dephasing(dt/2). */
+static void step_lindblad(const ora_sim* s, ora_emitter* e) {
+  int n = e->n;
+  double Heff[36] = {0}, lam[6], Q[36];
+  dephase(e, 0.5 * s->dt);
+  effective_h(e, Heff);
+  ora_jacobi_eig(n, Heff, lam, Q);
+  cplx U[36];
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) {
+      cplx acc = 0.0;
+      for (int q = 0; q < n; ++q) acc += Q[a * n + q] * cexp(-I * lam[q] * s->dt) * Q[b * n + q];
+      U[a * n + b] = acc;
+    }
+  conjugate_by(n, U, e->rho);
+  dephase(e, 0.5 * s->dt);
+}
+
+/* Full right-hand side: -i[Heff, rho] + sum_k (L rho L^+ - {L^+ L, rho}/2),
+ * L_k = sqrt(gphi) |k><k| (standard GKSL dissipator). */
+static void rhs(const ora_emitter* e, cplx* out) {
+  int n = e->n;
+  double Heff[36];
+  effective_h(e, Heff);
+  cplx Hc[36], A[36], B[36];
+  for (int a = 0; a < n * n; ++a) Hc[a] = Heff[a];
+  matmul(n, Hc, e->rho, A);
+  matmul(n, e->rho, Hc, B);
+  for (int a = 0; a < n * n; ++a) out[a] = -I * (A[a] - B[a]);
+  for (int k = 0; k < n; ++k) {
+    cplx P[36];
+    memset(P, 0, sizeof(P));
+    P[k * n + k] = 1.0;
+    cplx PrP[36], Pr[36], rP[36], T[36];
+    matmul(n, P, e->rho, Pr);
+    matmul(n, Pr, P, PrP);
+    matmul(n, e->rho, P, rP);
+    (void)T;
+    for (int a = 0; a < n * n; ++a) out[a] += e->gphi * (PrP[a] - 0.5 * (Pr[a] + rP[a]));
+  }
+}
+
+/* d<mu>/dt = Tr(rho_dot mu) (eq. dipole_derivative); for the TLS its closed
+ * form -2 w0 Im(rho01) d. */
+static void dipole_rate(ora_emitter* e) {
+  if (e->tls) {
+    double w0 = e->en[1] - e->en[0];
+    double f = -2.0 * w0 * cimag(e->rho[1]);
+    for (int c = 0; c < 3; ++c) e->mudot[c] = f * e->d[c];
+    return;
+  }
+  int n = e->n;
+  cplx rd[36];
+  rhs(e, rd);
+  cplx tr = 0.0;
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) tr += rd[a * n + b] * e->M[b * n + a];
+  for (int c = 0; c < 3; ++c) e->mudot[c] = creal(tr) * e->d[c];
+}
+
+/* Brute-force Tr(rho_dot mu^c) for any emitter (test helper). */
+void ora_dipole_rate_trace(const ora_sim* s, int m, const double* Et, double* out) {
+  ora_emitter e = s->em[m];
+  memcpy(e.Et, Et, 3 * sizeof(double));
+  int n = e.n;
+  cplx rd[36];
+  rhs(&e, rd);
+  cplx tr = 0.0;
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) tr += rd[a * n + b] * e.M[b * n + a];
+  for (int c = 0; c < 3; ++c) out[c] = creal(tr) * e.d[c];
+}
+
+static void emitter_advance(const ora_sim* s, ora_emitter* e) {
+  if (e->tls) step_tls(s, e);
+  else step_lindblad(s, e);
+  dipole_rate(e);
+}
+
+/* Advance every emitter by one step under a prescribed field E~ (M x 3),
+ * without any grid: the classical-path mode of eq. E_analytical. */
+void ora_emitters_step_prescribed(ora_sim* s, const double* Et) {
+#pragma omp parallel for schedule(static)
+  for (int m = 0; m < s->nem; ++m) {
+    memcpy(s->em[m].Et, Et + 3 * m, 3 * sizeof(double));
+    emitter_advance(s, &s->em[m]);
+  }
+}
+
+/* Gather of the current E into E~ (M x 3). */
+void ora_gather(ora_sim* s, double* Et) {
+#pragma omp parallel for schedule(static)
+  for (int m = 0; m < s->nem; ++m) gather_one(s, &s->em[m]);
+  if (Et)
+    for (int m = 0; m < s->nem; ++m)
+      for (int c = 0; c < 3; ++c) Et[3 * m + c] = s->em[m].Et[c];
+}
+
+/* J_c(p) = sum_m gamma_m mu_dot_m^c w^c_{m,p} / dx^3 (eqs. J_mol and
+ * Polarization_mol with the kernel's unit integral); emitters in index order. */
+static void scatter_into(const ora_sim* s, const double* mudot, double* const J[3]) {
+  double iv = 1.0 / (s->dx * s->dx * s->dx);
+  for (int m = 0; m < s->nem; ++m) {
+    const ora_emitter* e = &s->em[m];
+    for (int c = 0; c < 3; ++c) {
+      double amp = e->gamma * mudot[3 * m + c] * iv;
+      int L0 = e->len[c][0], L1 = e->len[c][1], L2 = e->len[c][2];
+      for (int kk = 0; kk < L2; ++kk)
+        for (int jj = 0; jj < L1; ++jj)
+          for (int ii = 0; ii < L0; ++ii)
+            J[c][window_cell(s, e, c, ii, jj, kk)] += amp * e->w[c][ii + L0 * (jj + L1 * kk)];
+    }
+  }
+}
+
+/* Scatter of a given mu_dot (M x 3) into fresh current arrays (test helper). */
+void ora_scatter(const ora_sim* s, const double* mudot, double* Jx, double* Jy, double* Jz) {
+  memset(Jx, 0, s->ncell * sizeof(double));
+  memset(Jy, 0, s->ncell * sizeof(double));
+  memset(Jz, 0, s->ncell * sizeof(double));
+  double* J[3] = {Jx, Jy, Jz};
+  scatter_into(s, mudot, J);
+}
+
+/* Soft source currents at t = (n + 1/2) dt. */
+static void add_sources(ora_sim* s, double t) {
+  for (int q = 0; q < s->nsrc; ++q) {
+    const ora_source* src = &s->src[q];
+    double sv = src->amp * pulse(src, t);
+    if (src->kind == 1) {
+      s->J[src->comp][IDX(s, src->ijk[0], src->ijk[1], src->ijk[2])] +=
+          sv / (s->dx * s->dx * s->dx);
+      continue;
+    }
+    /* current sheet of surface density amp*s(t) on plane `index` of `axis` */
+    for (int k = 0; k < s->N[2]; ++k)
+      for (int j = 0; j < s->N[1]; ++j)
+        for (int i = 0; i < s->N[0]; ++i) {
+          int q3[3] = {i, j, k};
+          if (q3[src->axis] != src->index) continue;
+          s->J[src->comp][IDX(s, i, j, k)] += sv / s->dx;
+        }
+  }
+}
+
+static void flux_save_plane(ora_sim* s) {
+  int a = s->flux_axis, u = (a + 1) % 3, v = (a + 2) % 3;
+  for (int jv = 0; jv < s->N[v]; ++jv)
+    for (int iu = 0; iu < s->N[u]; ++iu) {
+      int q[3];
+      q[a] = s->flux_index; q[u] = iu; q[v] = jv;
+      size_t id = IDX(s, q[0], q[1], q[2]);
+      s->flux_Eu[iu + (size_t)s->N[u] * jv] = s->E[u][id];
+      s->flux_Ev[iu + (size_t)s->N[u] * jv] = s->E[v][id];
+    }
+}
+
+/* F^{n+1/2} = sum over the plane of (E_u H_v - E_v H_u) dx^2 with E averaged
+ * over n and n+1 and H averaged over the two half-cells across the plane. */
+static double flux_eval(const ora_sim* s) {
+  int a = s->flux_axis, u = (a + 1) % 3, v = (a + 2) % 3;
+  double F = 0.0;
+  for (int jv = 0; jv < s->N[v]; ++jv)
+    for (int iu = 0; iu < s->N[u]; ++iu) {
+      int q[3], r[3];
+      q[a] = s->flux_index; q[u] = iu; q[v] = jv;
+      r[a] = s->flux_index - 1; r[u] = iu; r[v] = jv;
+      size_t id = IDX(s, q[0], q[1], q[2]), jd = IDX(s, r[0], r[1], r[2]);
+      size_t pp = iu + (size_t)s->N[u] * jv;
+      double Eu = 0.5 * (s->flux_Eu[pp] + s->E[u][id]);
+      double Ev = 0.5 * (s->flux_Ev[pp] + s->E[v][id]);
+      double Hv = 0.5 * (s->H[v][id] + s->H[v][jd]);
+      double Hu = 0.5 * (s->H[u][id] + s->H[u][jd]);
+      F += Eu * Hv - Ev * Hu;
+    }
+  return F * s->dx * s->dx;
+}
+
+/* W^n = 1/2 sum eps |E^n|^2 + 1/2 sum H^{n+1/2} . H^{n-1/2}  (times dx^3). */
+static double energy(const ora_sim* s) {
+  double w = 0.0;
+  for (size_t q = 0; q < s->ncell; ++q) {
+    double e2 = s->E[0][q] * s->E[0][q] + s->E[1][q] * s->E[1][q] + s->E[2][q] * s->E[2][q];
+    double hh = s->H[0][q] * s->Hprev[0][q] + s->H[1][q] * s->Hprev[1][q] +
+                s->H[2][q] * s->Hprev[2][q];
+    w += 0.5 * s->eps[q] * e2 + 0.5 * hh;
+  }
+  return w * s->dx * s->dx * s->dx;
+}
+
+/* One full coupled step n -> n+1. */
+static void step_once(ora_sim* s) {
+  double t_half = ((double)s->step + 0.5) * s->dt;
+  if (s->energy_on)
+    for (int c = 0; c < 3; ++c) memcpy(s->Hprev[c], s->H[c], s->ncell * sizeof(double));
+  /* 1. H^{n+1/2} from E^n */
+  update_H(s);
+  if (s->energy_on) series_push(&s->energy_series, energy(s));
+  /* 2-4. field -> emitters -> dipole rates (E~^n, rho^{n+1/2}, mu_dot^{n+1/2}) */
+#pragma omp parallel for schedule(static)
+  for (int m = 0; m < s->nem; ++m) {
+    gather_one(s, &s->em[m]);
+    emitter_advance(s, &s->em[m]);
+  }
+  /* 5. molecular plus source current J^{n+1/2} */
+  for (int c = 0; c < 3; ++c) memset(s->J[c], 0, s->ncell * sizeof(double));
+  if (s->nem) {
+    double* md = (double*)malloc((size_t)s->nem * 3 * sizeof(double));
+    for (int m = 0; m < s->nem; ++m)
+      for (int c = 0; c < 3; ++c) md[3 * m + c] = s->em[m].mudot[c];
+    scatter_into(s, md, s->J);
+    free(md);
+  }
+  add_sources(s, t_half);
+  if (s->flux_on) flux_save_plane(s);
+  /* 6. E^{n+1} */
+  update_E(s);
+  /* 7. detectors */
+  for (int p = 0; p < s->nprobe; ++p) {
+    int c = s->probe_comp[p];
+    const double* a = c < 3 ? s->E[c] : s->H[c - 3];
+    series_push(&s->probe_series[p],
+                a[IDX(s, s->probe_ijk[p][0], s->probe_ijk[p][1], s->probe_ijk[p][2])]);
+  }
+  if (s->flux_on) {
+    double F = flux_eval(s);
+    series_push(&s->flux_series, F);
+    s->flux_total += s->dt * F;
+  }
+  if (s->pop_every > 0 && s->step % s->pop_every == 0)
+    for (int m = 0; m < s->nem; ++m)
+      for (int k = 1; k < s->em[m].n; ++k)
+        series_push(&s->pop_series, creal(s->em[m].rho[k * s->em[m].n + k]));
+  s->step++;
+}
+
+void ora_step(ora_sim* s, int64_t nsteps) {
+  for (int64_t q = 0; q < nsteps; ++q) step_once(s);
+}
+
+int ora_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+void ora_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}

@@ -1,0 +1,605 @@
+"""Pins of the FP64 CPU oracle against closed forms, invariants and the paper's own
+decay law.  None of these re-types an oracle formula: each checks a property the
+mathematics or the paper fixes, chosen so that a dropped term, a wrong sign, a
+wrong index or a transposed operand in the oracle fails one of them.
+"""
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle.oracle import Oracle, jacobi_eig
+
+S = 0.5
+
+
+def _theta(kvec):
+    """Phase advance per step of a Yee eigenmode: sin^2(theta/2) = S^2 sum sin^2(k_a/2)."""
+    k = np.asarray(kvec, dtype=np.float64)
+    return 2.0 * np.arcsin(S * np.sqrt(np.sum(np.sin(k / 2.0) ** 2)))
+
+
+def _coords(n, comp):
+    """Coordinates (x, y, z) of the Yee points of E component comp, arrays (nz,ny,nx)."""
+    k, j, i = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    x, y, z = i.astype(float), j.astype(float), k.astype(float)
+    if comp == 0:
+        x = x + 0.5
+    elif comp == 1:
+        y = y + 0.5
+    else:
+        z = z + 0.5
+    return x, y, z
+
+
+# --------------------------------------------------------------- P-1 / P-2
+
+@pytest.mark.parametrize("comp,kidx", [(2, (1, 2, 0)), (0, (0, 1, 3)), (1, (2, 0, 1))])
+def test_periodic_plane_wave_follows_yee_dispersion(comp, kidx):
+    """Transverse discrete plane wave, H^{-1/2} = 0: E^n = E^0 cos((n+1/2)th)/cos(th/2)
+    with the Yee numerical dispersion relation (Yee's scheme, Sec. II.A.1)."""
+    n, steps = 32, 1000
+    kvec = 2 * np.pi * np.array(kidx) / n
+    x, y, z = _coords(n, comp)
+    e0 = np.cos(kvec[0] * x + kvec[1] * y + kvec[2] * z)
+    o = Oracle((n, n, n), bc=("periodic",) * 6)
+    o.set_field(comp, e0)
+    o.step(steps)
+    th = _theta(kvec)
+    ref = e0 * np.cos((steps + 0.5) * th) / np.cos(th / 2)
+    got = o.get_field(comp)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-12
+    for c in range(3):
+        if c != comp:
+            assert np.max(np.abs(o.get_field(c))) < 1e-13
+
+
+@pytest.mark.parametrize("comp,modes", [(2, (1, 1, 0)), (0, (0, 1, 1))])
+def test_pec_cavity_mode(comp, modes):
+    """TM_110 (and its rotation) of a PEC box: E = sin(pi m y/N) sin(...) obeys the same
+    discrete law with k_a = pi m_a / N; tangential E vanishes on the walls."""
+    n, steps = 32, 1000
+    x, y, z = _coords(n, comp)
+    kvec = np.pi * np.array(modes) / n
+    e0 = np.ones((n, n, n))
+    for a, (coord, m) in enumerate(zip((x, y, z), modes)):
+        if a != comp and m:
+            e0 = e0 * np.sin(np.pi * m * coord / n)
+    o = Oracle((n, n, n), bc=("pec",) * 6)
+    o.set_field(comp, e0)
+    o.step(steps)
+    th = _theta(kvec)
+    ref = e0 * np.cos((steps + 0.5) * th) / np.cos(th / 2)
+    got = o.get_field(comp)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-12
+
+
+# ------------------------------------------------------------------- P-3
+
+def _random_state(n, bc, rng):
+    E = [rng.standard_normal((n, n, n)) for _ in range(3)]
+    H = [rng.standard_normal((n, n, n)) for _ in range(3)]
+    if bc == "pec":  # tangential E on the index-0 wall planes is zero
+        E[0][0, :, :] = 0; E[0][:, 0, :] = 0
+        E[1][0, :, :] = 0; E[1][:, :, 0] = 0
+        E[2][:, 0, :] = 0; E[2][:, :, 0] = 0
+    return E, H
+
+
+@pytest.mark.parametrize("bc", ["pec", "periodic"])
+def test_discrete_energy_is_conserved(bc):
+    """W^n = 1/2 sum eps|E^n|^2 + 1/2 sum H^{n+1/2}.H^{n-1/2} is exactly invariant for the
+    Yee leapfrog without sources or absorbers, for any eps and any initial data."""
+    n, steps = 14, 2000
+    rng = np.random.default_rng(11)
+    o = Oracle((n, n, n), bc=(bc,) * 6)
+    o.set_eps(rng.uniform(1.0, 4.0, (n, n, n)))
+    E, H = _random_state(n, bc, rng)
+    for c in range(3):
+        o.set_field(c, E[c])
+        o.set_field(3 + c, H[c])
+    o.record_energy(True)
+    o.step(steps)
+    W = o.energy_series()
+    assert W.size == steps
+    assert np.max(np.abs(W - W[0])) / abs(W[0]) < 1e-12
+
+
+def test_energy_not_conserved_with_cpml():
+    """Sanity: the PML really absorbs (energy decreases)."""
+    n = 24
+    rng = np.random.default_rng(3)
+    o = Oracle((n, n, n), bc=("cpml",) * 6, cpml=(6,) * 6)
+    E, H = _random_state(n, "pec", rng)
+    for c in range(3):
+        o.set_field(c, E[c] * 0)
+    o.add_point_source(2, (12, 12, 12), 1.0, 0.5, 8.0, 40.0)
+    o.record_energy(True)
+    o.step(400)
+    W = o.energy_series()
+    assert W[-1] < 0.2 * np.max(W)
+
+
+# ------------------------------------------------------------------- P-4
+
+def _div_D(o, eps):
+    E = [o.get_field(c) for c in range(3)]
+    D = [eps * e for e in E]
+    div = (D[0] - np.roll(D[0], 1, axis=2)) + (D[1] - np.roll(D[1], 1, axis=1)) + \
+          (D[2] - np.roll(D[2], 1, axis=0))
+    return div
+
+
+def _div(J):
+    return (J[0] - np.roll(J[0], 1, axis=2)) + (J[1] - np.roll(J[1], 1, axis=1)) + \
+           (J[2] - np.roll(J[2], 1, axis=0))
+
+
+@pytest.mark.parametrize("bc", ["pec", "periodic"])
+def test_charge_identity_with_emitters_and_source(bc):
+    """eps(E^{n+1}-E^n) = dt(curl H - J) and div curl = 0 give, from E^0 = 0,
+    div(eps E^n) = -dt sum_k div J^{k+1/2} with J the scattered molecular current plus
+    the source (eqs. Maxwell and J_mol)."""
+    n, steps = 16, 60
+    rng = np.random.default_rng(5)
+    eps = rng.uniform(1.0, 3.0, (n, n, n))
+    o = Oracle((n, n, n), bc=(bc,) * 6)
+    o.set_eps(eps)
+    pos = np.array([[7.3, 8.1, 7.7], [8.6, 7.2, 8.4], [8.0, 8.0, 8.0]])
+    dip = np.array([[0.3, -0.2, 0.4], [0.0, 0.5, 0.1], [0.2, 0.2, -0.3]])
+    rho = np.tile([0.5, 0.5, 0.0], (3, 1))
+    o.add_tls(pos, [1.0, 0.8, 1.2], [1.0, 0.5, 1.5], [0.25, 0.3, 0.2], dip, rho)
+    amp, w, tau, t0 = 0.7, 0.3, 6.0, 15.0
+    o.add_point_source(1, (5, 9, 6), amp, w, tau, t0)
+    Jsum = [np.zeros((n, n, n)) for _ in range(3)]
+    for q in range(steps):
+        o.step(1)
+        _, md = o.emitter_io()
+        J = o.scatter(md)
+        t = (q + 0.5) * o.dt
+        J[1][6, 9, 5] += amp * np.cos(w * (t - t0)) * np.exp(-(t - t0) ** 2 / (2 * tau ** 2))
+        for c in range(3):
+            Jsum[c] += J[c]
+    lhs = _div_D(o, eps)
+    rhs = -o.dt * _div(Jsum)
+    inner = (slice(1, n - 1),) * 3 if bc == "pec" else (slice(None),) * 3
+    scale = np.max(np.abs(rhs[inner]))
+    assert scale > 1e-6
+    assert np.max(np.abs(lhs[inner] - rhs[inner])) < 1e-12 * scale
+
+
+# ------------------------------------------------------------------- P-5
+
+def test_linearity_and_superposition():
+    n = 20
+    runs = []
+    for (a, b) in [(1.0, 0.0), (0.0, 1.0), (1.0, 1.0), (2.5, 0.0)]:
+        o = Oracle((n, n, n), bc=("cpml",) * 6, cpml=(5,) * 6)
+        o.set_eps(np.where(np.arange(n)[:, None, None] > 10, 2.0, 1.0) * np.ones((n, n, n)))
+        if a:
+            o.add_point_source(2, (8, 9, 10), a, 0.4, 4.0, 12.0)
+        if b:
+            o.add_plane_source(2, 7, 1, b, 0.3, 5.0, 15.0)
+        o.step(80)
+        runs.append(np.stack(o.fields()))
+    A, B, AB, A25 = runs
+    assert np.linalg.norm(AB - A - B) / np.linalg.norm(AB) < 1e-13
+    assert np.linalg.norm(A25 - 2.5 * A) / np.linalg.norm(A25) < 1e-13
+
+
+# ------------------------------------------------------------------- P-6
+
+def _probe_run(shape, bc, cpml, src, probes, steps, eps=None):
+    o = Oracle(shape, bc=bc, cpml=cpml)
+    if eps is not None:
+        o.set_eps(eps)
+    if src[0] == "point":
+        o.add_point_source(*src[1:])
+    else:
+        o.add_plane_source(*src[1:])
+    ids = [o.add_probe(c, ijk) for c, ijk in probes]
+    o.step(steps)
+    return [o.probe(p) for p in ids]
+
+
+def test_cpml_reflection_2d_normal_and_oblique():
+    """2-D (z-invariant) pulse hitting the x and y PML: compare with a domain so large that
+    nothing returns within the run.  Normal and 45-degree incidence."""
+    bc2 = ("cpml",) * 4 + ("periodic",) * 2
+    n, d, steps = 60, 10, 260
+    c = n // 2
+    probes = [(2, (c, n - d - 2, 0)), (2, (n - d - 4, n - d - 4, 0))]
+    src = ("point", 2, (c, c, 0), 1.0, 0.3, 6.0, 25.0)
+    small = _probe_run((n, n, 1), bc2, (d, d, d, d, 0, 0), src, probes, steps)
+    big_n = n + 2 * 150
+    off = 150
+    probes_big = [(cc, (i + off, j + off, 0)) for cc, (i, j, _) in probes]
+    src_big = ("point", 2, (c + off, c + off, 0), 1.0, 0.3, 6.0, 25.0)
+    big = _probe_run((big_n, big_n, 1), ("pec",) * 4 + ("periodic",) * 2, (0,) * 6, src_big,
+                     probes_big, steps)
+    for s_, b_ in zip(small, big):
+        refl = np.max(np.abs(s_ - b_)) / np.max(np.abs(b_))
+        assert refl < 5e-3, refl
+
+
+def test_cpml_reflection_z_plane_wave():
+    """Plane-wave pulse (x/y periodic, one cell wide) through the z PML."""
+    d, nz, steps = 10, 80, 300
+    src = ("plane", 2, 40, 1, 1.0, 0.25, 8.0, 30.0)
+    small = _probe_run((1, 1, nz), ("periodic",) * 4 + ("cpml",) * 2, (0, 0, 0, 0, d, d), src,
+                       [(1, (0, 0, nz - d - 3))], steps)
+    big = _probe_run((1, 1, nz + 400), ("periodic",) * 4 + ("pec",) * 2, (0,) * 6,
+                     ("plane", 2, 240, 1, 1.0, 0.25, 8.0, 30.0), [(1, (0, 0, 200 + nz - d - 3))],
+                     steps)
+    refl = np.max(np.abs(small[0] - big[0])) / np.max(np.abs(big[0]))
+    assert refl < 5e-3, refl
+
+
+# ------------------------------------------------------------------- P-7
+
+def _one_tls_oracle(pos, n=20, sigma=1.0, gamma=1.0, bc=("pec",) * 6):
+    o = Oracle((n, n, n), bc=bc)
+    o.add_tls(np.array([pos]), [sigma], [gamma], [0.25], np.array([[0.1, 0.2, 0.3]]),
+              np.array([[0.5, 0.5, 0.0]]))
+    return o
+
+
+def test_kernel_window_staggering_and_normalisation():
+    """A centre on a cell corner: the window of E_x holds 6 half-integer x points and 7
+    integer y, z points (R = 3 sigma, inclusive), weights sum to 1 and their centroid is
+    the emitter position (kernel normalised to unit integral, eq. Polarization_mol)."""
+    n = 20
+    o = _one_tls_oracle((10.0, 10.0, 10.0), n=n)
+    for c in range(3):
+        idx, w = o.window(0, c)
+        assert abs(w.sum() - 1.0) < 1e-15
+        assert idx.size == 6 * 7 * 7
+        i = idx % n
+        j = (idx // n) % n
+        k = idx // (n * n)
+        pts = np.stack([i, j, k], 1).astype(float)
+        pts[:, c] += 0.5
+        assert np.allclose(pts.T @ w, [10.0, 10.0, 10.0], atol=1e-13)
+        # offsets along the staggered axis are +-0.5..2.5, along the others 0..3
+        assert set(np.unique(np.abs(pts[:, c] - 10.0))) == {0.5, 1.5, 2.5}
+        for a in range(3):
+            if a != c:
+                assert set(np.unique(np.abs(pts[:, a] - 10.0))) == {0.0, 1.0, 2.0, 3.0}
+        # weights are a Gaussian in the distance: monotone, ratio fixed by sigma
+        r2 = np.sum((pts - 10.0) ** 2, axis=1)
+        order = np.argsort(r2)
+        assert np.all(np.diff(w[order]) <= 1e-18)
+    # a generic position keeps unit sum
+    o2 = _one_tls_oracle((9.37, 10.81, 10.05), n=n, sigma=1.3)
+    for c in range(3):
+        _, w = o2.window(0, c)
+        assert abs(w.sum() - 1.0) < 1e-15
+
+
+def test_gather_uniform_field_and_scatter_adjointness():
+    n = 20
+    rng = np.random.default_rng(9)
+    o = Oracle((n, n, n), bc=("periodic",) * 6)
+    M = 5
+    pos = rng.uniform(4.5, 15.5, (M, 3))
+    gam = rng.uniform(0.5, 1.5, M)
+    o.add_tls(pos, rng.uniform(0.8, 1.2, M), gam, np.full(M, 0.25), rng.standard_normal((M, 3)),
+              np.tile([0.5, 0.5, 0.0], (M, 1)))
+    E0 = np.array([0.3, -1.1, 0.7])
+    for c in range(3):
+        o.set_field(c, np.full((n, n, n), E0[c]))
+    Et = o.gather()
+    assert np.allclose(Et, gam[:, None] * E0[None, :], rtol=2e-14, atol=0)
+    # total scattered current is gamma * mu_dot (unit-integral kernel, dx = 1)
+    v = rng.standard_normal((M, 3))
+    J = o.scatter(v)
+    tot = np.array([J[c].sum() for c in range(3)])
+    assert np.allclose(tot, (gam[:, None] * v).sum(0), rtol=1e-14, atol=1e-15)
+    # <gather(E), v> = <E, scatter(v)>  (the coupling V = -E~ . mu is symmetric)
+    Ef = [rng.standard_normal((n, n, n)) for _ in range(3)]
+    for c in range(3):
+        o.set_field(c, Ef[c])
+    lhs = np.sum(o.gather() * v)
+    rhs = sum(np.sum(Ef[c] * J[c]) for c in range(3))
+    assert abs(lhs - rhs) < 1e-13 * max(1.0, abs(lhs))
+
+
+def test_periodic_window_wraps():
+    n = 16
+    o = _one_tls_oracle((0.2, 8.0, 15.9), n=n, bc=("periodic",) * 6)
+    for c in range(3):
+        idx, w = o.window(0, c)
+        assert idx.min() >= 0 and idx.max() < n ** 3
+        assert abs(w.sum() - 1.0) < 1e-15
+
+
+def test_emitter_too_close_to_wall_is_rejected():
+    with pytest.raises(ValueError):
+        _one_tls_oracle((3.5, 10.0, 10.0), n=20)
+    with pytest.raises(ValueError):
+        o = Oracle((24, 24, 24), bc=("cpml",) * 6, cpml=(6,) * 6)
+        o.add_tls(np.array([[9.0, 12.0, 12.0]]), [1.0], [1.0], [0.25], np.array([[0, 0, .1]]),
+                  np.array([[0.0, 0.0, 0.0]]))
+
+
+# ------------------------------------------------------------ P-8 .. P-11
+
+def _tls(n_emit, omega0, dip, rho0):
+    o = Oracle((1, 1, 1), bc=("periodic",) * 6)
+    o.add_tls(np.tile([0.5, 0.5, 0.5], (n_emit, 1)), np.ones(n_emit), np.ones(n_emit), omega0,
+              dip, rho0)
+    return o
+
+
+def test_tls_undriven_precession():
+    """E~ = 0: rho01(t) = rho01(0) exp(i w0 t), populations constant (H0 = diag(0, w0))."""
+    w0 = np.array([0.25, 0.31])
+    rho0 = np.array([[0.3, 0.2, 0.35], [0.5, 0.5, 0.0]])
+    o = _tls(2, w0, np.array([[0, 0, 0.1], [0.1, 0, 0]]), rho0)
+    steps = 777
+    for _ in range(steps):
+        o.emitters_step_prescribed(np.zeros((2, 3)))
+    st = o.tls_state()
+    t = steps * o.dt
+    r01 = (rho0[:, 1] + 1j * rho0[:, 2]) * np.exp(1j * w0 * t)
+    assert np.allclose(st[:, 0], rho0[:, 0], atol=1e-13)
+    assert np.allclose(st[:, 1] + 1j * st[:, 2], r01, atol=1e-13)
+
+
+def test_tls_static_field_rabi_exact():
+    """Static field from |g>: P_e(t) = 4g^2/(w0^2+4g^2) sin^2(sqrt(w0^2+4g^2) t/2), g = E.d."""
+    w0, E0 = 0.25, np.array([0.0, 0.0, 1.3])
+    dips = np.array([[0, 0, 0.05], [0.02, 0, 0.08], [0, 0, 0.2]])
+    o = _tls(3, np.full(3, w0), dips, np.zeros((3, 3)))
+    g = dips @ E0
+    for q in range(1, 601):
+        o.emitters_step_prescribed(np.tile(E0, (3, 1)))
+        if q % 100 == 0:
+            t = q * o.dt
+            W = np.sqrt(w0 ** 2 + 4 * g ** 2)
+            ref = 4 * g ** 2 / W ** 2 * np.sin(W * t / 2) ** 2
+            assert np.allclose(o.tls_state()[:, 0], ref, atol=1e-12, rtol=0)
+
+
+def test_tls_resonant_rabi_rwa():
+    """Resonant cos drive: P_e = sin^2(E0 d t / 2) within the rotating-wave error ~ 2g/w0."""
+    w0, d, E0 = 0.25, 0.05, 0.1
+    o = _tls(1, [w0], np.array([[0, 0, d]]), np.zeros((1, 3)))
+    gR = E0 * d
+    steps = int(round(np.pi / gR / o.dt))
+    errs = []
+    for n in range(steps):
+        o.emitters_step_prescribed(np.array([[0, 0, E0 * np.cos(w0 * n * o.dt)]]))
+        t = (n + 1) * o.dt
+        errs.append(abs(o.tls_state()[0, 0] - np.sin(gR * t / 2) ** 2))
+    assert max(errs) < 2 * gR / w0
+    assert o.tls_state()[0, 0] > 0.97
+
+
+def test_tls_dipole_rate_closed_form_matches_trace():
+    """-2 w0 Im(rho01) d (eq. dipole_derivative, closed form) equals Tr(rho_dot mu)."""
+    rng = np.random.default_rng(2)
+    M = 6
+    rho0 = []
+    for _ in range(M):
+        p = rng.uniform(0.05, 0.95)
+        a = rng.uniform(0, 2 * np.pi)
+        r = rng.uniform(0, 1) * np.sqrt(p * (1 - p))
+        rho0.append([p, r * np.cos(a), r * np.sin(a)])
+    rho0 = np.array(rho0)
+    dip = rng.standard_normal((M, 3))
+    w0 = rng.uniform(0.2, 0.3, M)
+    o = _tls(M, w0, dip, rho0)
+    Et = rng.standard_normal((M, 3))
+    o.emitters_step_prescribed(Et)
+    _, md = o.emitter_io()
+    for m in range(M):
+        tr = o.dipole_rate_trace(m, Et[m])
+        assert np.allclose(md[m], tr, rtol=1e-13, atol=1e-16)
+    st = o.tls_state()
+    assert np.allclose(md, (-2 * w0 * st[:, 2])[:, None] * dip, rtol=1e-14)
+
+
+def test_jacobi_matches_numpy_eigh():
+    rng = np.random.default_rng(4)
+    for L in range(2, 7):
+        A = rng.standard_normal((L, L))
+        A = A + A.T
+        lam, Q = jacobi_eig(A)
+        assert np.allclose(np.sort(lam), np.linalg.eigvalsh(A), atol=1e-13)
+        assert np.allclose(Q @ np.diag(lam) @ Q.T, A, atol=1e-13)
+        assert np.allclose(Q.T @ Q, np.eye(L), atol=1e-14)
+
+
+def _ml_oracle(courant, nlev, energies, mops, dip, gphi, rho0):
+    o = Oracle((1, 1, 1), bc=("periodic",) * 6, courant=courant)
+    n = len(nlev)
+    o.add_multilevel(nlev, energies, mops, dip, gphi, rho0, np.tile([0.5, 0.5, 0.5], (n, 1)),
+                     np.ones(n), np.ones(n))
+    return o
+
+
+def _rand_model(rng, L):
+    ev = np.concatenate([[0.0, 0.25], np.sort(rng.uniform(0.3, 0.9, L - 2))])
+    Mm = rng.standard_normal((L, L))
+    Mm = 0.5 * (Mm + Mm.T)
+    np.fill_diagonal(Mm, 0)
+    A = rng.standard_normal((L, L)) + 1j * rng.standard_normal((L, L))
+    rho = A @ A.conj().T
+    rho /= np.trace(rho).real
+    return ev, Mm, rho
+
+
+def test_lindblad_pure_dephasing_closed_form():
+    """E~ = 0: rho_jk(t) = rho_jk(0) exp((i(E_k - E_j) - gphi) t) for j != k, populations fixed."""
+    rng = np.random.default_rng(7)
+    L, g = 5, 3e-3
+    ev, Mm, rho = _rand_model(rng, L)
+    o = _ml_oracle(0.5, [L], [ev], [Mm], np.array([[0, 0, 0.1]]), [g], [rho])
+    steps = 400
+    for _ in range(steps):
+        o.emitters_step_prescribed(np.zeros((1, 3)))
+    t = steps * o.dt
+    jj, kk = np.meshgrid(np.arange(L), np.arange(L), indexing="ij")
+    ref = rho * np.exp(1j * (ev[kk] - ev[jj]) * t) * np.where(jj == kk, 1.0, np.exp(-g * t))
+    assert np.allclose(o.rho(0), ref, atol=1e-13)
+
+
+def test_lindblad_two_level_without_dephasing_equals_tls_path():
+    rng = np.random.default_rng(8)
+    w0 = 0.27
+    rho = np.array([[0.6, 0.3 - 0.2j], [0.3 + 0.2j, 0.4]])
+    dip = np.array([[0.05, -0.02, 0.04]])
+    ml = _ml_oracle(0.5, [2], [np.array([0.0, w0])], [np.array([[0, 1.0], [1.0, 0]])], dip, [0.0],
+                    [rho])
+    tl = _tls(1, [w0], dip, np.array([[0.4, 0.3, -0.2]]))
+    for _ in range(300):
+        Et = rng.standard_normal((1, 3)) * 0.8
+        ml.emitters_step_prescribed(Et)
+        tl.emitters_step_prescribed(Et)
+    assert np.allclose(ml.rho(0), tl.rho(0), atol=1e-13)
+    assert np.allclose(ml.emitter_io()[1], tl.emitter_io()[1], atol=1e-15)
+
+
+def test_lindblad_state_stays_physical():
+    rng = np.random.default_rng(12)
+    L = 6
+    ev, Mm, rho = _rand_model(rng, L)
+    o = _ml_oracle(0.5, [L], [ev], [Mm], np.array([[0.2, 0.1, -0.3]]), [0.01], [rho])
+    for _ in range(500):
+        o.emitters_step_prescribed(rng.standard_normal((1, 3)))
+        r = o.rho(0)
+        assert abs(np.trace(r) - 1) < 2e-12
+        assert np.allclose(r, r.conj().T, atol=1e-15)
+        assert np.min(np.linalg.eigvalsh(r)) > -1e-14
+
+
+def _liouvillian(H, g, L):
+    """Superoperator of -i[H,.] + dephasing on row-major vec(rho)."""
+    I = np.eye(L)
+    Lsup = -1j * (np.kron(H, I) - np.kron(I, H.T))
+    for k in range(L):
+        P = np.zeros((L, L))
+        P[k, k] = 1.0
+        Lsup += g * (np.kron(P, P.T) - 0.5 * np.kron(P, I) - 0.5 * np.kron(I, P.T))
+    return Lsup
+
+
+def test_lindblad_strang_is_second_order_against_expm():
+    """Static field: compare with expm of the full Liouvillian; halving dt cuts the error
+    by 4 (Strang splitting of the unitary and dephasing parts)."""
+    rng = np.random.default_rng(13)
+    L, g = 4, 0.05
+    ev, Mm, rho = _rand_model(rng, L)
+    dip = np.array([[0.0, 0.0, 0.4]])
+    E = np.array([[0.0, 0.0, 0.7]])
+    T = 20.0
+    H = np.diag(ev) - (E[0] @ dip[0]) * Mm
+    exact = (scipy.linalg.expm(_liouvillian(H, g, L) * T) @ rho.ravel()).reshape(L, L)
+    errs = []
+    for courant in (0.5, 0.25):
+        o = _ml_oracle(courant, [L], [ev], [Mm], dip, [g], [rho])
+        for _ in range(int(round(T / o.dt))):
+            o.emitters_step_prescribed(E)
+        errs.append(np.linalg.norm(o.rho(0) - exact))
+    order = np.log2(errs[0] / errs[1])
+    assert 1.9 < order < 2.1, (errs, order)
+
+
+def test_multilevel_dipole_rate_is_trace():
+    """For the open model the oracle evaluates Tr(rho_dot mu) from the full right-hand side;
+    cross-check with the closed form d^c (-i Tr(rho[M,H0]) - gphi Tr(rho M))."""
+    rng = np.random.default_rng(14)
+    L, g = 5, 0.02
+    ev, Mm, rho = _rand_model(rng, L)
+    dip = np.array([[0.1, -0.2, 0.3]])
+    o = _ml_oracle(0.5, [L], [ev], [Mm], dip, [g], [rho])
+    Et = np.array([[0.3, 0.1, -0.2]])
+    o.emitters_step_prescribed(Et)
+    r = o.rho(0)
+    H0 = np.diag(ev)
+    val = (-1j * np.trace(r @ (Mm @ H0 - H0 @ Mm)) - g * np.trace(r @ Mm)).real
+    assert np.allclose(o.emitter_io()[1][0], val * dip[0], rtol=1e-12, atol=1e-17)
+
+
+# ------------------------------------------------------- P-12 .. P-14, P-16
+
+def _decay_run(shape, bc, cpml, pos, dip, steps, w0=0.25, state=(np.sqrt(0.9999), 0.01)):
+    N = len(pos)
+    o = Oracle(shape, bc=bc, cpml=cpml)
+    cg, ce = state
+    o.add_tls(np.array(pos), np.ones(N), np.ones(N), np.full(N, w0), np.array(dip),
+              np.tile([ce * ce, cg * ce, 0.0], (N, 1)))
+    o.record_populations(1)
+    o.step(steps)
+    P = o.populations()
+    t = (np.arange(steps) + 0.5) * o.dt
+    return t, P
+
+
+def _rate(t, P, t_min=200.0):
+    sel = t > t_min
+    return -np.polyfit(t[sel], np.log(P[sel]), 1)[0]
+
+
+@pytest.mark.slow
+def test_superradiance_2d_matches_paper_rate():
+    """2-D vacuum (z-invariant grid), TLS in the weak-excitation state (c_g, c_e) =
+    (sqrt 0.9999, 0.01) (Sec. IV.A, App. B): P_e decays as exp(-N gamma t) with
+    gamma = mu^2 w^2 / (2 hbar eps0 c^2) (eq. population_decay_superradiance), times the
+    Gaussian kernel's form factor exp(-(w sigma)^2).  N = 1 and N = 4 collocated; the
+    d/sqrt(N) rescaling of App. B gives per-emitter states identical to N = 1."""
+    n, d, steps, w0, mu = 128, 16, 4000, 0.25, 0.1
+    shape, bc, cp = (n, n, 1), ("cpml",) * 4 + ("periodic",) * 2, (d, d, d, d, 0, 0)
+    gamma = mu ** 2 * w0 ** 2 / 2 * np.exp(-w0 ** 2)
+    c = [n / 2, n / 2, 0.5]
+    t, P1 = _decay_run(shape, bc, cp, [c], [[0, 0, mu]], steps)
+    assert abs(_rate(t, P1[:, 0]) / gamma - 1) < 0.02
+    t, P4 = _decay_run(shape, bc, cp, [c] * 4, [[0, 0, mu]] * 4, steps)
+    for q in range(4):
+        assert abs(_rate(t, P4[:, q]) / (4 * gamma) - 1) < 0.02
+    t, P4s = _decay_run(shape, bc, cp, [c] * 4, [[0, 0, mu / 2]] * 4, steps)
+    for q in range(4):
+        assert np.max(np.abs(P4s[:, q] - P1[:, 0])) < 1e-13 * np.max(P1)
+
+
+@pytest.mark.slow
+def test_fermi_golden_rule_decay_3d():
+    """3-D free space: Gamma = w0^3 d^2 / (3 pi) exp(-(w0 sigma)^2) (textbook spontaneous
+    emission rate with the Gaussian form factor), within grid dispersion and PML error."""
+    n, cp, steps, w0, mu = 48, 12, 5000, 0.25, 0.2
+    G = w0 ** 3 * mu ** 2 / (3 * np.pi) * np.exp(-w0 ** 2)
+    t, P = _decay_run((n, n, n), ("cpml",) * 6, (cp,) * 6, [[n / 2] * 3], [[0, 0, mu]], steps)
+    assert abs(_rate(t, P[:, 0]) / G - 1) < 0.03
+
+
+def test_excited_state_is_stationary():
+    """|e> has rho01 = 0, so mu_dot = 0 and nothing is ever emitted (semiclassical): the
+    probe stays exactly zero and the population stays 1 up to rounding."""
+    o = Oracle((32, 32, 32))
+    o.add_tls(np.array([[16.0, 16.0, 16.0]]), [1.0], [1.0], [0.25], np.array([[0, 0, 0.01]]),
+              np.array([[1.0, 0.0, 0.0]]))
+    pid = o.add_probe(2, (24, 16, 16))
+    o.record_populations(1)
+    o.step(200)
+    assert np.all(o.probe(pid) == 0.0)
+    assert np.max(np.abs(o.populations() - 1.0)) < 200 * 5e-16
+
+
+def test_coupled_energy_stays_bounded():
+    """Field energy W^n plus emitter energy Tr(rho H0) drifts only at O(dt^2) in a PEC box."""
+    n = 20
+    o = Oracle((n, n, n))
+    o.add_tls(np.array([[10.0, 10.0, 10.0]]), [1.0], [1.0], [0.25], np.array([[0, 0, 0.3]]),
+              np.array([[0.5, 0.5, 0.0]]))
+    o.record_energy(True)
+    o.record_populations(1)
+    o.step(3000)
+    W = o.energy_series()
+    P = o.populations()[:, 0]
+    emit = 0.25 * P                         # Tr(rho^{n+1/2} H0)
+    Pm = np.concatenate([[0.5], P[:-1]])    # rho^{n-1/2}
+    tot = W + 0.25 * 0.5 * (P + Pm)
+    exchanged = np.max(W) - np.min(W)
+    assert exchanged > 1e-3 * 0.25
+    assert np.max(np.abs(tot - tot[0])) < 0.05 * exchanged
+    assert np.isfinite(emit).all()
