@@ -1,0 +1,194 @@
+/*
+ * mlk.h -- C ABI of libmlk, an MI355X (gfx950) engine for self-consistent
+ * light-matter propagation: a 3-D Yee FDTD leapfrog of E/H coupled, at
+ * every step, to an ensemble of quantum emitters through a Gaussian-smeared
+ * regularised field and a smeared dipole current.
+ *
+ * What each step computes (natural units: c = eps0 = mu0 = hbar = 1; dx is
+ * the cell size, dt = courant * dx):
+ *   1. H^{n+1/2} = H^{n-1/2} - dt curl E^n               (eq. Maxwell, Sec. II.A.1)
+ *   2. E~_m^c   = gamma_m sum_p w^c_{m,p} E_c^n(p)        (eq. E_regu_Emi)
+ *   3. rho_m^{n+1/2} = exact step of d rho/dt = -i[H0 - E~.mu, rho] + D[rho]
+ *                                                         (eq. von-Neumann-tls)
+ *   4. mu_dot_m = Tr(rho_dot mu)                          (eq. dipole_derivative)
+ *   5. J_c(p)   = sum_m gamma_m mu_dot_m^c w^c_{m,p}/dx^3 + source currents
+ *                                                         (eqs. J_mol, Polarization_mol)
+ *   6. E^{n+1}  = E^n + (dt/eps_r)(curl H^{n+1/2} - J)     (eq. Maxwell, eq. Dromega)
+ *   7. detectors (probes, populations, Poynting flux).
+ * The order field -> emitter -> dipole rate -> current is the per-step
+ * exchange of Sec. III; here it never leaves the GPU.
+ *
+ * Grid layout: component arrays of nx*ny*nz values, x fastest
+ * (index i + nx*(j + ny*k)).  Yee positions of index (i,j,k):
+ *   Ex (i+1/2, j, k)   Ey (i, j+1/2, k)   Ez (i, j, k+1/2)
+ *   Hx (i, j+1/2, k+1/2)   Hy (i+1/2, j, k+1/2)   Hz (i+1/2, j+1/2, k)
+ * The domain spans [0, n] along each axis.  Emitter positions are in cell
+ * units in that frame.
+ *
+ * Errors: every call returns an mlk_status; on failure mlk_last_error()
+ * returns a thread-local message.  Nothing aborts across the ABI.  A device
+ * fault reported by the HIP runtime maps to MLK_EDEVICE and leaves the
+ * simulation in an undefined state (destroy it).
+ *
+ * Memory: "mem_kind" arguments say whether a pointer is host memory
+ * (MLK_MEM_HOST) or device memory on the simulation's GPU (MLK_MEM_DEVICE).
+ * Inputs are copied; the caller keeps ownership of every buffer it passes.
+ * All device memory of a simulation is owned by the library and freed by
+ * mlk_destroy.
+ *
+ * Streams: all work is enqueued on the stream given in the grid description
+ * (a hipStream_t, NULL = a stream the library creates).  mlk_step is
+ * asynchronous; getters synchronise that stream.
+ */
+#ifndef MLK_H
+#define MLK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MLK_OK = 0,
+  MLK_EINVAL = 1,        /* an argument is out of range or inconsistent */
+  MLK_ENOMEM = 2,        /* device or host allocation failed */
+  MLK_EDEVICE = 3,       /* HIP runtime error or device fault */
+  MLK_ESTATE = 4,        /* call not allowed in the current state */
+  MLK_EUNSUPPORTED = 5,  /* valid request this build does not implement */
+  MLK_ENUMERIC = 6       /* non-finite state detected */
+} mlk_status;
+
+enum { MLK_FP64 = 0, MLK_FP32_FIELDS = 1 };
+enum { MLK_BC_PEC = 0, MLK_BC_PERIODIC = 1, MLK_BC_CPML = 2 };
+enum { MLK_MEM_HOST = 0, MLK_MEM_DEVICE = 1 };
+/* Yee sweep variant: one fused H+E pass (default) or separate H and E passes. */
+enum { MLK_SWEEP_FUSED = 0, MLK_SWEEP_PLAIN = 1 };
+/* Current scatter variant: deterministic owner-computes (default) or atomics. */
+enum { MLK_SCATTER_OWNER = 0, MLK_SCATTER_ATOMIC = 1 };
+/* Series kinds for mlk_get_series. */
+enum { MLK_SERIES_PROBE = 0, MLK_SERIES_FLUX = 1, MLK_SERIES_POPULATION = 2 };
+
+typedef struct mlk_sim mlk_sim;
+
+typedef struct {
+  int32_t nx, ny, nz;        /* cells per axis, >= 1 */
+  double dx;                 /* cell size (> 0) */
+  double courant;            /* dt = courant * dx; 0 < courant <= 1/sqrt(3) */
+  int32_t precision;         /* MLK_FP64, or MLK_FP32_FIELDS (E, H, psi, 1/eps, kernel
+                                weights in FP32; rho, E~, mu_dot, flux in FP64) */
+  int32_t bc[6];             /* per face x-, x+, y-, y+, z-, z+: MLK_BC_*; periodic must
+                                pair on an axis; a CPML is backed by a metallic wall */
+  int32_t cpml_cells[6];     /* CPML thickness per face (cells), 1 .. n/2 when CPML */
+  double cpml_m;             /* grading order of sigma and kappa (default 3) */
+  double cpml_sigma_scale;   /* sigma_max = scale * (m + 1) / dx (default 0.8) */
+  double cpml_kappa_max;     /* default 1 */
+  double cpml_alpha_max;     /* default 0 */
+  double window_r;           /* kernel window half-width in units of sigma (default 3) */
+  void* stream;              /* hipStream_t to enqueue on; NULL = library-owned stream */
+  int32_t device;            /* HIP device ordinal */
+  int32_t sweep;             /* MLK_SWEEP_* */
+  int32_t scatter;           /* MLK_SCATTER_* */
+} mlk_grid_desc;
+
+/* Fill a description with defaults: 32^3 PEC, dx 1, courant 0.5, FP64,
+ * CPML m 3 / scale 0.8 / kappa 1 / alpha 0, window 3 sigma, device 0. */
+void mlk_grid_desc_init(mlk_grid_desc* g);
+
+const char* mlk_last_error(void);
+const char* mlk_version(void);
+
+/* Create a simulation: E^0 = 0, H^{-1/2} = 0, psi = 0, eps_r = 1, no emitters. */
+mlk_status mlk_create(const mlk_grid_desc* g, mlk_sim** out);
+mlk_status mlk_destroy(mlk_sim* s);
+
+/* Relative permittivity per cell, nx*ny*nz doubles, x fastest; every E
+ * component with index (i,j,k) uses eps_r(i,j,k) (staircase, eq. Dromega with
+ * a static eps_r).  EINVAL if any value is < 1 or not finite. */
+mlk_status mlk_set_eps(mlk_sim* s, const double* eps, int32_t mem_kind);
+
+/* Overwrite one field component (0..2 = Ex..Ez at E^n, 3..5 = Hx..Hz at
+ * H^{n-1/2}) from nx*ny*nz doubles; used to set initial conditions. */
+mlk_status mlk_set_field(mlk_sim* s, int32_t comp, const double* src, int32_t mem_kind);
+
+/* Two-level emitters (eq. von-Neumann-tls, basic TLS driver: H0 = diag(0, w0),
+ * mu = d sigma_x, no Lindblad term).  Host arrays of n entries:
+ *   pos[3n]    centre in cell units,
+ *   sigma[n]   Gaussian width (standard deviation, cells; the paper uses dx),
+ *   gamma[n]   coupling rescale (eq. Polarization_mol, default 1),
+ *   omega0[n]  transition frequency,
+ *   dipole[3n] d = mu01 * unit orientation,
+ *   rho0[3n]   initial rho11, Re rho01, Im rho01 (rho01 = <0|rho|1>).
+ * EINVAL if a state is not a density matrix, sigma <= 0, or a kernel window
+ * (R*sigma + 1 cells around the centre) reaches a metallic wall or the CPML
+ * interface on a non-periodic axis.  Ids are contiguous from *first_id. */
+mlk_status mlk_add_tls(mlk_sim* s, int32_t n, const double* pos, const double* sigma,
+                       const double* gamma, const double* omega0, const double* dipole,
+                       const double* rho0, int32_t* first_id);
+
+/* Multilevel emitters with pure dephasing (the open model of Sec. II.B.1):
+ * H0 = diag(energies) in its eigenbasis, mu^c = d^c M with M real symmetric,
+ * Lindblad operators sqrt(gphi)|k><k| so coherences decay at gphi.  Step =
+ * dephasing(dt/2) o exp(-i H_eff dt) . exp(+i H_eff dt) o dephasing(dt/2).
+ * Host arrays: nlev[n] in 2..6 (else EUNSUPPORTED); energies packed with
+ * offsets eoff[n]; M (nlev^2 row-major) and rho0 (nlev^2 complex, re/im
+ * interleaved) packed with offsets moff[n] (in entries); dipole[3n],
+ * gphi[n], pos[3n], sigma[n], gamma[n] as for mlk_add_tls. */
+mlk_status mlk_add_multilevel(mlk_sim* s, int32_t n, const int32_t* nlev, const int64_t* eoff,
+                              const int64_t* moff, const double* energies, const double* mop,
+                              const double* dipole, const double* gphi, const double* rho0,
+                              const double* pos, const double* sigma, const double* gamma,
+                              int32_t* first_id);
+
+/* Soft current sheet on plane `index` of `axis` injecting component `comp`
+ * with surface density amp * s(t), s(t) = cos(omega (t - t0)) exp(-(t-t0)^2/(2 tau^2))
+ * evaluated at t = (n + 1/2) dt (the Gaussian pulse of App. B). */
+mlk_status mlk_add_plane_source(mlk_sim* s, int32_t axis, int32_t index, int32_t comp,
+                                double amp, double omega, double tau, double t0);
+/* Point current element amp * s(t) / dx^3 on component comp at ijk. */
+mlk_status mlk_add_point_source(mlk_sim* s, int32_t comp, const int32_t ijk[3], double amp,
+                                double omega, double tau, double t0);
+
+/* Probe of field component comp (0..5) at ijk, sampled after each step. */
+mlk_status mlk_add_probe(mlk_sim* s, int32_t comp, const int32_t ijk[3], int32_t* id);
+/* Poynting flux through plane `index` (1 .. n-1) of `axis`, one value per step:
+ * F^{n+1/2} = dx^2 sum (E_u H_v - E_v H_u) with E averaged over n, n+1 and H over
+ * the two half cells across the plane, (axis,u,v) cyclic; the running
+ * integral dt * sum F is kept as well.  One flux plane per simulation. */
+mlk_status mlk_add_flux_plane(mlk_sim* s, int32_t axis, int32_t index);
+/* Record Re rho_kk, k >= 1, of every emitter on steps with n % every == 0. */
+mlk_status mlk_record_populations(mlk_sim* s, int32_t every);
+
+/* Advance nsteps full coupled steps (asynchronous). */
+mlk_status mlk_step(mlk_sim* s, int64_t nsteps);
+mlk_status mlk_sync(mlk_sim* s);
+mlk_status mlk_step_count(mlk_sim* s, int64_t* n);
+
+/* Read a field component (0..5) as nx*ny*nz doubles. */
+mlk_status mlk_get_field(mlk_sim* s, int32_t comp, double* dst, int32_t mem_kind);
+/* Density matrix of emitter id as n*n complex (re/im interleaved); *nlev gets n.
+ * cap is the capacity of dst in doubles. */
+mlk_status mlk_get_rho(mlk_sim* s, int32_t id, double* dst, int32_t cap, int32_t* nlev);
+/* Two-level states (rho11, Re rho01, Im rho01) of ids first..first+count-1. */
+mlk_status mlk_get_tls_state(mlk_sim* s, int32_t first, int32_t count, double* dst);
+/* E~ and mu_dot of every emitter from the last step, 3 doubles each (host). */
+mlk_status mlk_get_emitter_io(mlk_sim* s, double* Et, double* mudot);
+/* Copy a recorded series; *len gets its full length, at most cap values copied.
+ * Populations are laid out [record][emitter excited levels]. */
+mlk_status mlk_get_series(mlk_sim* s, int32_t kind, int32_t id, double* dst, int64_t cap,
+                          int64_t* len);
+mlk_status mlk_get_flux_total(mlk_sim* s, double* total);
+
+/* Checkpoint of the whole evolving state (fields, psi, emitter states, step
+ * counter, flux integral); restoring gives an identical continuation.
+ * Recorded series are not part of it. */
+mlk_status mlk_checkpoint_size(mlk_sim* s, size_t* bytes);
+mlk_status mlk_checkpoint_save(mlk_sim* s, void* dst, int32_t mem_kind);
+mlk_status mlk_checkpoint_load(mlk_sim* s, const void* src, int32_t mem_kind);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLK_H */

@@ -1,0 +1,129 @@
+// Detectors: probes, Poynting flux through a plane, and the step counter.
+//
+// Flux through plane `index` of axis a, with (a, u, v) cyclic:
+//   F^{n+1/2} = dx^2 sum_{plane} (E_u H_v - E_v H_u),
+// E averaged over t_n and t_{n+1} at the plane, H at t_{n+1/2} averaged over the
+// half cells on either side (indices index-1 and index along a).  The plane
+// values of E^n are saved before the sweep overwrites them.  The sum is done
+// in FP64 in a fixed order (block partials, then one block), so it is
+// deterministic.
+#include "mlk_internal.h"
+
+namespace mlk {
+
+__device__ __forceinline__ size_t plane_cell(const Geom& g, int a, int index, int iu, int iv) {
+  const int u = (a + 1) % 3, v = (a + 2) % 3;
+  int q[3];
+  q[a] = index;
+  q[u] = iu;
+  q[v] = iv;
+  return cell_index(g, q[0], q[1], q[2]);
+}
+
+template <typename T>
+__global__ void k_flux_save(FieldPtrs<T> f, Geom g, FluxPlane fp) {
+  const int a = fp.axis, u = (a + 1) % 3, v = (a + 2) % 3;
+  const int nu = g.n[u], nv = g.n[v];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nu * nv) return;
+  const int iu = t % nu, iv = t / nu;
+  const size_t id = plane_cell(g, a, fp.index, iu, iv);
+  fp.Eu0[t] = (double)f.E[u][id];
+  fp.Ev0[t] = (double)f.E[v][id];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_flux_partial(FieldPtrs<T> f, Geom g, FluxPlane fp) {
+  const int a = fp.axis, u = (a + 1) % 3, v = (a + 2) % 3;
+  const int nu = g.n[u], nv = g.n[v];
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nu * nv; t += gridDim.x * blockDim.x) {
+    const int iu = t % nu, iv = t / nu;
+    const size_t id = plane_cell(g, a, fp.index, iu, iv);
+    const size_t jd = plane_cell(g, a, fp.index - 1, iu, iv);
+    const double Eu = 0.5 * (fp.Eu0[t] + (double)f.E[u][id]);
+    const double Ev = 0.5 * (fp.Ev0[t] + (double)f.E[v][id]);
+    const double Hv = 0.5 * ((double)f.H[v][id] + (double)f.H[v][jd]);
+    const double Hu = 0.5 * ((double)f.H[u][id] + (double)f.H[u][jd]);
+    s += Eu * Hv - Ev * Hu;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) fp.partial[blockIdx.x] = red[0];
+}
+
+// Single block: probe samples, the flux total, then the step counter moves on.
+template <typename T>
+__global__ __launch_bounds__(256) void k_finish(FieldPtrs<T> f, Geom g, FluxPlane fp, Series ser,
+                                                int64_t* step) {
+  __shared__ double red[256];
+  const int64_t n = *step;
+  const int t = threadIdx.x;
+  if (t < ser.nprobe) {
+    const int comp = ser.probe_comp[t];
+    const T* a = comp < 3 ? f.E[comp] : f.H[comp - 3];
+    ser.probe[(size_t)t * ser.cap + n] = (double)a[ser.probe_idx[t]];
+  }
+  if (fp.on) {
+    double s = 0.0;
+    for (int q = t; q < fp.nblocks; q += blockDim.x) s += fp.partial[q];
+    red[t] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (t < w) red[t] += red[t + w];
+      __syncthreads();
+    }
+    if (t == 0) {
+      const double F = red[0] * g.dx * g.dx;
+      fp.series[n] = F;
+      *fp.total += g.dt * F;
+    }
+  }
+  __syncthreads();
+  if (t == 0) *step = n + 1;
+}
+
+template <typename T>
+static hipError_t launch_flux_save(const FieldPtrs<T>& f, const Geom& g, const FluxPlane& fp,
+                                   hipStream_t st) {
+  const int a = fp.axis, u = (a + 1) % 3, v = (a + 2) % 3;
+  const int np = g.n[u] * g.n[v];
+  hipLaunchKernelGGL(k_flux_save<T>, dim3((np + 255) / 256), dim3(256), 0, st, f, g, fp);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_finish(const FieldPtrs<T>& f, const Geom& g, const FluxPlane& fp,
+                                const Series& ser, int64_t* step, hipStream_t st) {
+  if (fp.on) {
+    hipLaunchKernelGGL(k_flux_partial<T>, dim3(fp.nblocks), dim3(256), 0, st, f, g, fp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_finish<T>, dim3(1), dim3(256), 0, st, f, g, fp, ser, step);
+  return hipGetLastError();
+}
+
+hipError_t flux_save_f64(const FieldPtrs<double>& f, const Geom& g, const FluxPlane& fp,
+                         hipStream_t st) {
+  return launch_flux_save<double>(f, g, fp, st);
+}
+hipError_t flux_save_f32(const FieldPtrs<float>& f, const Geom& g, const FluxPlane& fp,
+                         hipStream_t st) {
+  return launch_flux_save<float>(f, g, fp, st);
+}
+hipError_t finish_f64(const FieldPtrs<double>& f, const Geom& g, const FluxPlane& fp,
+                      const Series& ser, int64_t* step, hipStream_t st) {
+  return launch_finish<double>(f, g, fp, ser, step, st);
+}
+hipError_t finish_f32(const FieldPtrs<float>& f, const Geom& g, const FluxPlane& fp,
+                      const Series& ser, int64_t* step, hipStream_t st) {
+  return launch_finish<float>(f, g, fp, ser, step, st);
+}
+
+}  // namespace mlk

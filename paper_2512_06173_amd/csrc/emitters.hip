@@ -1,0 +1,276 @@
+// Emitter phase: kernel windows, field gather, density-matrix step, dipole
+// rate, and the current scatter.
+//
+// Gather (eq. E_regu_Emi):  E~_m^c = gamma_m sum_p w^c_{m,p} E_c(p), where the
+// weights are the Gaussian exp(-|p - r|^2 / 2 sigma^2) sampled at the Yee points
+// of component c inside a box of half-width R sigma and normalised to unit sum
+// (the discrete unit-integral kernel of eq. Polarization_mol).  The box and the
+// Gaussian are separable, so each emitter stores three normalised 1-D weight
+// vectors per component and a window weight is their product.
+//
+// Two-level step (eq. von-Neumann-tls, basic TLS: no Lindblad term): with E~
+// held at its midpoint value, H = (w0/2) I + h.sigma, h = (-E~.d, 0, -w0/2),
+// the Bloch vector r = (2 Re rho01, -2 Im rho01, 1 - 2 rho11) rotates about h
+// by the angle 2|h|dt (exact for piecewise-constant E~).  Dipole rate (eq.
+// dipole_derivative, closed form): mu_dot = -2 w0 Im(rho01) d.
+//
+// Scatter (eqs. J_mol, Polarization_mol): E_c(p) -= (dt/eps_r) gamma mu_dot^c w / dx^3.
+#include <climits>
+
+#include "mlk_internal.h"
+
+namespace mlk {
+
+__device__ __forceinline__ int wrap_index(int q, int n) {
+  int r = q % n;
+  return r < 0 ? r + n : r;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// One thread per (emitter, component, axis): window start, length and the
+// normalised 1-D Gaussian weights along that axis.
+template <typename T>
+__global__ void k_windows(int count, int first, const double* pos, const double* sigma,
+                          double R, Geom g, int* lo, int* len, T* w) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count * 9) return;
+  const int m = t / 9, c = (t / 3) % 3, a = t % 3;
+  const int e = first + m;
+  const size_t slot = ((size_t)e * 3 + c) * 3 + a;
+  T* wv = w + slot * kMaxWin;
+  for (int q = 0; q < kMaxWin; ++q) wv[q] = T(0);
+  if (g.n[a] == 1 && g.periodic[a]) {
+    // invariant direction: single layer, factor cancels in the normalisation
+    lo[slot] = 0;
+    len[slot] = 1;
+    wv[0] = T(1);
+    return;
+  }
+  const double r = pos[3 * m + a];
+  const double s = sigma[m];
+  const double rs = R * s;
+  const double sh = (a == c) ? 0.5 : 0.0;
+  const int q0 = (int)floor(r - sh - rs) - 1;
+  int firstq = INT_MAX, lastq = INT_MIN;
+  for (int q = q0; q <= q0 + 2 * kMaxWin + 4; ++q) {
+    const double o = (double)q + sh - r;
+    if (o * o <= rs * rs) {
+      if (firstq == INT_MAX) firstq = q;
+      lastq = q;
+    }
+  }
+  int L = lastq - firstq + 1;
+  if (L > kMaxWin) L = kMaxWin;  // rejected on the host before launch
+  double sum = 0.0;
+  for (int q = 0; q < L; ++q) {
+    const double o = (double)(firstq + q) + sh - r;
+    sum += exp(-o * o / (2.0 * s * s));
+  }
+  for (int q = 0; q < L; ++q) {
+    const double o = (double)(firstq + q) + sh - r;
+    wv[q] = (T)(exp(-o * o / (2.0 * s * s)) / sum);
+  }
+  lo[slot] = firstq;
+  len[slot] = L;
+}
+
+// Partial gather of component c for emitter e by one lane: the lane owns
+// (y,z) window rows lane, lane+64, ... and sums along x.
+template <typename T>
+__device__ __forceinline__ double gather_rows(const T* Ec, const Geom& g, const WindowPtrs<T>& win,
+                                              int e, int c, int lane) {
+  const size_t slot = ((size_t)e * 3 + c) * 3;
+  const int lx = win.lo[slot], ly = win.lo[slot + 1], lz = win.lo[slot + 2];
+  const int Lx = win.len[slot], Ly = win.len[slot + 1], Lz = win.len[slot + 2];
+  const T* wx = win.w + slot * kMaxWin;
+  const T* wy = wx + kMaxWin;
+  const T* wz = wy + kMaxWin;
+  double s = 0.0;
+  for (int q = lane; q < Ly * Lz; q += 64) {
+    const int dy = q % Ly, dz = q / Ly;
+    const int jj = wrap_index(ly + dy, g.n[1]);
+    const int kk = wrap_index(lz + dz, g.n[2]);
+    const size_t row = (size_t)g.n[0] * ((size_t)jj + (size_t)g.n[1] * (size_t)kk);
+    double sx = 0.0;
+    for (int dx = 0; dx < Lx; ++dx) {
+      const int ii = wrap_index(lx + dx, g.n[0]);
+      sx += (double)wx[dx] * (double)Ec[row + ii];
+    }
+    s += (double)wy[dy] * (double)wz[dz] * sx;
+  }
+  return s;
+}
+
+// Exact two-level step for one emitter; returns the new state and mu_dot.
+__device__ __forceinline__ void tls_advance(double w0, const double d[3], const double et[3],
+                                            double dt, double st[3], double md[3]) {
+  const double gg = et[0] * d[0] + et[1] * d[1] + et[2] * d[2];
+  const double hx = -gg, hz = -0.5 * w0;
+  const double om = sqrt(hx * hx + hz * hz);
+  const double p = st[0];
+  const double rx = 2.0 * st[1], ry = -2.0 * st[2];
+  double rx2 = rx, ry2 = ry, p2 = p;
+  if (om > 0.0) {
+    const double th = 2.0 * om * dt;
+    const double kx = hx / om, kz = hz / om;
+    const double c = cos(th), s = sin(th);
+    const double sh = sin(0.5 * th);
+    const double omc = 2.0 * sh * sh;  // 1 - cos(th) without cancellation
+    const double rz = 1.0 - 2.0 * p;
+    const double kr = kx * rx + kz * rz;
+    rx2 = rx * c - kz * ry * s + kx * kr * omc;
+    ry2 = ry * c + (kz * rx - kx * rz) * s;
+    // rho11' = (1 - rz')/2 written so that no O(1) terms cancel
+    p2 = 0.5 * (omc * (kx * kx - kx * kz * rx + 2.0 * kz * kz * p) + 2.0 * p * c - kx * ry * s);
+  }
+  st[0] = p2;
+  st[1] = 0.5 * rx2;
+  st[2] = -0.5 * ry2;
+  const double f = w0 * ry2;  // -2 w0 Im(rho01)
+  md[0] = f * d[0];
+  md[1] = f * d[1];
+  md[2] = f * d[2];
+}
+
+// One wavefront per two-level emitter: gather E~ from E^n, advance
+// rho^{n-1/2} -> rho^{n+1/2}, evaluate mu_dot^{n+1/2}, record the population.
+template <typename T>
+__global__ __launch_bounds__(256) void k_tls_gather_step(FieldPtrs<T> f, Geom g,
+                                                         WindowPtrs<T> win, TlsPtrs tls,
+                                                         double* Et, double* mudot,
+                                                         const int64_t* pop_off, Series ser,
+                                                         const int64_t* step) {
+  const int lane = threadIdx.x & 63;
+  const int m = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6);
+  if (m >= tls.count) return;
+  const int e = tls.gid[m];
+  double acc[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) acc[c] = wave_sum(gather_rows(f.E[c], g, win, e, c, lane));
+  if (lane != 0) return;
+  const double gm = win.gamma[e];
+  const double et[3] = {gm * acc[0], gm * acc[1], gm * acc[2]};
+  const double d[3] = {tls.dip[3 * m], tls.dip[3 * m + 1], tls.dip[3 * m + 2]};
+  double st[3] = {tls.rho[3 * m], tls.rho[3 * m + 1], tls.rho[3 * m + 2]};
+  double md[3];
+  tls_advance(tls.omega0[m], d, et, g.dt, st, md);
+  tls.rho[3 * m] = st[0];
+  tls.rho[3 * m + 1] = st[1];
+  tls.rho[3 * m + 2] = st[2];
+  for (int c = 0; c < 3; ++c) {
+    Et[3 * e + c] = et[c];
+    mudot[3 * e + c] = md[c];
+  }
+  if (ser.pop_every > 0) {
+    const int64_t n = *step;
+    if (n % ser.pop_every == 0) ser.pop[(n / ser.pop_every) * ser.npop + pop_off[e]] = st[0];
+  }
+}
+
+// Scatter with device-wide atomics: one wavefront per emitter.
+template <typename T>
+__global__ __launch_bounds__(256) void k_scatter_atomic(FieldPtrs<T> f, Geom g, WindowPtrs<T> win,
+                                                        int count, const double* mudot) {
+  const int lane = threadIdx.x & 63;
+  const int e = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6);
+  if (e >= count) return;
+  const double vol = g.inv_dx * g.inv_dx * g.inv_dx;
+  for (int c = 0; c < 3; ++c) {
+    const double amp = g.dt * win.gamma[e] * mudot[3 * e + c] * vol;
+    if (amp == 0.0) continue;
+    const size_t slot = ((size_t)e * 3 + c) * 3;
+    const int lx = win.lo[slot], ly = win.lo[slot + 1], lz = win.lo[slot + 2];
+    const int Lx = win.len[slot], Ly = win.len[slot + 1], Lz = win.len[slot + 2];
+    const T* wx = win.w + slot * kMaxWin;
+    const T* wy = wx + kMaxWin;
+    const T* wz = wy + kMaxWin;
+    T* Ec = f.E[c];
+    for (int q = lane; q < Ly * Lz; q += 64) {
+      const int dy = q % Ly, dz = q / Ly;
+      const int jj = wrap_index(ly + dy, g.n[1]);
+      const int kk = wrap_index(lz + dz, g.n[2]);
+      const size_t row = (size_t)g.n[0] * ((size_t)jj + (size_t)g.n[1] * (size_t)kk);
+      const double a = amp * (double)wy[dy] * (double)wz[dz];
+      for (int dx = 0; dx < Lx; ++dx) {
+        const size_t id = row + wrap_index(lx + dx, g.n[0]);
+        const T inc = (T)(a * (double)wx[dx] * (double)f.epsinv[id]);
+        unsafeAtomicAdd(&Ec[id], -inc);
+      }
+    }
+  }
+}
+
+template <typename T>
+static hipError_t launch_windows(int count, int first, const double* pos, const double* sigma,
+                                 double R, const Geom& g, int* lo, int* len, T* w,
+                                 hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const int threads = 256;
+  const int blocks = (count * 9 + threads - 1) / threads;
+  hipLaunchKernelGGL(k_windows<T>, dim3(blocks), dim3(threads), 0, st, count, first, pos, sigma,
+                     R, g, lo, len, w);
+  return hipGetLastError();
+}
+
+hipError_t windows_f64(int count, int first, const double* pos, const double* sigma, double R,
+                       const Geom& g, int* lo, int* len, double* w, hipStream_t st) {
+  return launch_windows<double>(count, first, pos, sigma, R, g, lo, len, w, st);
+}
+hipError_t windows_f32(int count, int first, const double* pos, const double* sigma, double R,
+                       const Geom& g, int* lo, int* len, float* w, hipStream_t st) {
+  return launch_windows<float>(count, first, pos, sigma, R, g, lo, len, w, st);
+}
+
+template <typename T>
+static hipError_t launch_tls(const FieldPtrs<T>& f, const Geom& g, const WindowPtrs<T>& win,
+                             const TlsPtrs& tls, double* Et, double* mudot,
+                             const int64_t* pop_off, const Series& ser, const int64_t* step,
+                             hipStream_t st) {
+  if (tls.count <= 0) return hipSuccess;
+  const int waves_per_block = 4;
+  const int blocks = (tls.count + waves_per_block - 1) / waves_per_block;
+  hipLaunchKernelGGL(k_tls_gather_step<T>, dim3(blocks), dim3(64 * waves_per_block), 0, st, f, g,
+                     win, tls, Et, mudot, pop_off, ser, step);
+  return hipGetLastError();
+}
+
+hipError_t tls_step_f64(const FieldPtrs<double>& f, const Geom& g, const WindowPtrs<double>& win,
+                        const TlsPtrs& tls, double* Et, double* mudot, const int64_t* pop_off,
+                        const Series& ser, const int64_t* step, hipStream_t st) {
+  return launch_tls<double>(f, g, win, tls, Et, mudot, pop_off, ser, step, st);
+}
+hipError_t tls_step_f32(const FieldPtrs<float>& f, const Geom& g, const WindowPtrs<float>& win,
+                        const TlsPtrs& tls, double* Et, double* mudot, const int64_t* pop_off,
+                        const Series& ser, const int64_t* step, hipStream_t st) {
+  return launch_tls<float>(f, g, win, tls, Et, mudot, pop_off, ser, step, st);
+}
+
+template <typename T>
+static hipError_t launch_scatter_atomic(const FieldPtrs<T>& f, const Geom& g,
+                                        const WindowPtrs<T>& win, int count, const double* mudot,
+                                        hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const int waves_per_block = 4;
+  const int blocks = (count + waves_per_block - 1) / waves_per_block;
+  hipLaunchKernelGGL(k_scatter_atomic<T>, dim3(blocks), dim3(64 * waves_per_block), 0, st, f, g,
+                     win, count, mudot);
+  return hipGetLastError();
+}
+
+hipError_t scatter_atomic_f64(const FieldPtrs<double>& f, const Geom& g,
+                              const WindowPtrs<double>& win, int count, const double* mudot,
+                              hipStream_t st) {
+  return launch_scatter_atomic<double>(f, g, win, count, mudot, st);
+}
+hipError_t scatter_atomic_f32(const FieldPtrs<float>& f, const Geom& g,
+                              const WindowPtrs<float>& win, int count, const double* mudot,
+                              hipStream_t st) {
+  return launch_scatter_atomic<float>(f, g, win, count, mudot, st);
+}
+
+}  // namespace mlk

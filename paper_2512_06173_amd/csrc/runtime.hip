@@ -1,0 +1,886 @@
+// libmlk runtime: the C ABI declared in include/mlk.h.
+//
+// Owns the device state of one simulation, validates inputs, and enqueues
+// the per-step kernel sequence on the simulation's stream:
+//   [flux: save E^n on the plane] -> emitter gather + step + dipole rate
+//   -> Yee sweep (H then E, with soft sources) -> current scatter
+//   -> [flux partial sums] -> finish (probes, flux total, step counter).
+// Every numerical step runs in the HIP kernels; this file only moves data
+// and checks arguments.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "launch.h"
+#include "mlk.h"
+
+using namespace mlk;
+
+namespace {
+
+thread_local std::string g_err;
+
+mlk_status fail(mlk_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(e_ == hipErrorOutOfMemory ? MLK_ENOMEM : MLK_EDEVICE, "%s: %s", #expr, \
+                  hipGetErrorString(e_));                                              \
+  } while (0)
+
+#define STCHK(expr)                   \
+  do {                                \
+    mlk_status s_ = (expr);           \
+    if (s_ != MLK_OK) return s_;      \
+  } while (0)
+
+template <typename P>
+hipError_t dalloc(P** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) return hipSuccess;
+  return hipMalloc((void**)p, bytes);
+}
+
+template <typename P>
+void dfree(P*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+}  // namespace
+
+struct mlk_sim {
+  mlk_grid_desc desc{};
+  Geom g{};
+  bool fp32 = false;
+  size_t esz = 8;
+  size_t ncell = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+
+  void* E[3] = {};
+  void* H[3] = {};
+  void* epsinv = nullptr;
+  void* psiE[3][3] = {};
+  void* psiH[3][3] = {};
+  void* tab[3] = {};  // per axis: b, c, 1/kappa for integer then half positions (6 N values)
+
+  // emitters, host mirror (by emitter id)
+  int nem = 0;
+  std::vector<double> pos, sigma, gamma;
+  std::vector<int64_t> pop_off;
+  int64_t npop = 0;
+  std::vector<int> tls_gid;
+  std::vector<int> tls_slot;  // by emitter id: index among two-level emitters, or -1
+  std::vector<double> tls_w0, tls_dip, tls_rho0;
+  // device emitter tables
+  int* d_wlo = nullptr;
+  int* d_wlen = nullptr;
+  void* d_w = nullptr;
+  double* d_pos = nullptr;
+  double* d_sigma = nullptr;
+  double* d_gamma = nullptr;
+  double* d_Et = nullptr;
+  double* d_mudot = nullptr;
+  int64_t* d_popoff = nullptr;
+  int* d_tls_gid = nullptr;
+  double* d_tls_w0 = nullptr;
+  double* d_tls_dip = nullptr;
+  double* d_tls_rho = nullptr;
+
+  SourceSet src{};
+
+  int nprobe = 0;
+  int probe_comp[16] = {};
+  int64_t probe_idx[16] = {};
+  double* d_probe = nullptr;
+  int64_t series_cap = 0;
+
+  FluxPlane fp{};
+  double* d_flux_series = nullptr;
+
+  int pop_every = 0;
+  double* d_pop = nullptr;
+  int64_t pop_cap = 0;
+
+  int64_t* d_step = nullptr;
+  int64_t host_step = 0;
+};
+
+namespace {
+
+template <typename T>
+FieldPtrs<T> field_ptrs(const mlk_sim* s) {
+  FieldPtrs<T> f{};
+  for (int c = 0; c < 3; ++c) {
+    f.E[c] = (T*)s->E[c];
+    f.H[c] = (T*)s->H[c];
+    for (int a = 0; a < 3; ++a) {
+      f.psiE[c][a] = (T*)s->psiE[c][a];
+      f.psiH[c][a] = (T*)s->psiH[c][a];
+    }
+  }
+  f.epsinv = (const T*)s->epsinv;
+  for (int a = 0; a < 3; ++a) {
+    const T* t = (const T*)s->tab[a];
+    const int N = s->g.n[a];
+    for (int h = 0; h < 2; ++h) {
+      f.cb[a][h] = t ? t + 0 * 2 * N + h * N : nullptr;
+      f.cc[a][h] = t ? t + 1 * 2 * N + h * N : nullptr;
+      f.ck[a][h] = t ? t + 2 * 2 * N + h * N : nullptr;
+    }
+  }
+  return f;
+}
+
+template <typename T>
+WindowPtrs<T> window_ptrs(const mlk_sim* s) {
+  WindowPtrs<T> w{};
+  w.lo = s->d_wlo;
+  w.len = s->d_wlen;
+  w.w = (const T*)s->d_w;
+  w.gamma = s->d_gamma;
+  return w;
+}
+
+Series series_of(const mlk_sim* s) {
+  Series ser{};
+  ser.probe = s->d_probe;
+  ser.nprobe = s->nprobe;
+  for (int p = 0; p < s->nprobe; ++p) {
+    ser.probe_comp[p] = s->probe_comp[p];
+    ser.probe_idx[p] = s->probe_idx[p];
+  }
+  ser.cap = s->series_cap;
+  ser.pop = s->d_pop;
+  ser.pop_every = s->pop_every;
+  ser.npop = s->npop;
+  ser.pop_cap = s->pop_cap;
+  return ser;
+}
+
+bool in_range_face(const mlk_sim* s, int a, double x, double reach) {
+  const Geom& g = s->g;
+  if (g.periodic[a]) return true;
+  const double lo = (double)g.nlo[a];
+  const double hi = (double)(g.n[a] - g.nhi[a]);
+  return x - reach >= lo && x + reach <= hi;
+}
+
+// Checks shared by every emitter kind: width, window size and distance to walls.
+mlk_status check_emitter_geometry(const mlk_sim* s, const double* p, double sig) {
+  if (!(sig > 0.0) || !std::isfinite(sig)) return fail(MLK_EINVAL, "sigma must be > 0");
+  const double rs = s->desc.window_r * sig;
+  if (rs < 0.5) return fail(MLK_EINVAL, "kernel window R*sigma = %.3f is below half a cell", rs);
+  if (2.0 * rs + 1.0 > (double)kMaxWin)
+    return fail(MLK_EUNSUPPORTED, "kernel window %.2f cells exceeds %d points per axis",
+                2.0 * rs + 1.0, kMaxWin);
+  for (int a = 0; a < 3; ++a) {
+    if (!std::isfinite(p[a])) return fail(MLK_EINVAL, "emitter position not finite");
+    if (s->g.periodic[a]) {
+      if (s->g.n[a] > 1 && (double)s->g.n[a] < 2.0 * rs + 2.0)
+        return fail(MLK_EINVAL, "periodic axis %d too short for the kernel window", a);
+      if (p[a] < 0.0 || p[a] > (double)s->g.n[a])
+        return fail(MLK_EINVAL, "emitter outside the domain on axis %d", a);
+    } else if (!in_range_face(s, a, p[a], rs + 1.0)) {
+      return fail(MLK_EINVAL,
+                  "emitter at %.3f on axis %d: kernel window reaches a wall or the CPML", p[a],
+                  a);
+    }
+  }
+  return MLK_OK;
+}
+
+template <typename T>
+mlk_status upload(T** dptr, const std::vector<T>& v) {
+  dfree(*dptr);
+  if (v.empty()) return MLK_OK;
+  HIPCHK(dalloc(dptr, v.size() * sizeof(T)));
+  HIPCHK(hipMemcpy(*dptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return MLK_OK;
+}
+
+// Rebuild every device emitter table from the host mirror (set-up only).
+mlk_status rebuild_emitters(mlk_sim* s) {
+  HIPCHK(hipStreamSynchronize(s->stream));
+  const int M = s->nem;
+  if (M == 0) return MLK_OK;
+  STCHK(upload(&s->d_pos, s->pos));
+  STCHK(upload(&s->d_sigma, s->sigma));
+  STCHK(upload(&s->d_gamma, s->gamma));
+  STCHK(upload(&s->d_popoff, s->pop_off));
+  STCHK(upload(&s->d_tls_gid, s->tls_gid));
+  STCHK(upload(&s->d_tls_w0, s->tls_w0));
+  STCHK(upload(&s->d_tls_dip, s->tls_dip));
+  STCHK(upload(&s->d_tls_rho, s->tls_rho0));
+  dfree(s->d_wlo);
+  dfree(s->d_wlen);
+  dfree(s->d_w);
+  dfree(s->d_Et);
+  dfree(s->d_mudot);
+  HIPCHK(dalloc(&s->d_wlo, (size_t)M * 9 * sizeof(int)));
+  HIPCHK(dalloc(&s->d_wlen, (size_t)M * 9 * sizeof(int)));
+  HIPCHK(dalloc(&s->d_w, (size_t)M * 9 * kMaxWin * s->esz));
+  HIPCHK(dalloc(&s->d_Et, (size_t)M * 3 * sizeof(double)));
+  HIPCHK(dalloc(&s->d_mudot, (size_t)M * 3 * sizeof(double)));
+  HIPCHK(hipMemset(s->d_Et, 0, (size_t)M * 3 * sizeof(double)));
+  HIPCHK(hipMemset(s->d_mudot, 0, (size_t)M * 3 * sizeof(double)));
+  if (s->fp32)
+    HIPCHK(windows_f32(M, 0, s->d_pos, s->d_sigma, s->desc.window_r, s->g, s->d_wlo, s->d_wlen,
+                       (float*)s->d_w, s->stream));
+  else
+    HIPCHK(windows_f64(M, 0, s->d_pos, s->d_sigma, s->desc.window_r, s->g, s->d_wlo, s->d_wlen,
+                       (double*)s->d_w, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  return MLK_OK;
+}
+
+// Grow the on-device series buffers so that nsteps more steps fit.
+mlk_status reserve_series(mlk_sim* s, int64_t nsteps) {
+  const int64_t need = s->host_step + nsteps;
+  if ((s->nprobe > 0 || s->fp.on) && need > s->series_cap) {
+    HIPCHK(hipStreamSynchronize(s->stream));
+    int64_t cap = s->series_cap ? 2 * s->series_cap : 1024;
+    while (cap < need) cap *= 2;
+    if (s->nprobe > 0) {
+      double* np = nullptr;
+      HIPCHK(dalloc(&np, (size_t)s->nprobe * cap * sizeof(double)));
+      if (s->d_probe && s->host_step > 0)
+        HIPCHK(hipMemcpy2D(np, cap * sizeof(double), s->d_probe, s->series_cap * sizeof(double),
+                           s->host_step * sizeof(double), s->nprobe, hipMemcpyDeviceToDevice));
+      dfree(s->d_probe);
+      s->d_probe = np;
+    }
+    if (s->fp.on) {
+      double* nf = nullptr;
+      HIPCHK(dalloc(&nf, (size_t)cap * sizeof(double)));
+      if (s->d_flux_series && s->host_step > 0)
+        HIPCHK(hipMemcpy(nf, s->d_flux_series, s->host_step * sizeof(double),
+                         hipMemcpyDeviceToDevice));
+      dfree(s->d_flux_series);
+      s->d_flux_series = nf;
+      s->fp.series = nf;
+    }
+    s->series_cap = cap;
+  }
+  if (s->pop_every > 0 && s->npop > 0) {
+    const int64_t rec = (need + s->pop_every - 1) / s->pop_every;
+    if (rec > s->pop_cap) {
+      HIPCHK(hipStreamSynchronize(s->stream));
+      int64_t cap = s->pop_cap ? 2 * s->pop_cap : 64;
+      while (cap < rec) cap *= 2;
+      double* np = nullptr;
+      HIPCHK(dalloc(&np, (size_t)cap * s->npop * sizeof(double)));
+      const int64_t have = s->host_step > 0 ? (s->host_step - 1) / s->pop_every + 1 : 0;
+      if (s->d_pop && have > 0)
+        HIPCHK(hipMemcpy(np, s->d_pop, (size_t)have * s->npop * sizeof(double),
+                         hipMemcpyDeviceToDevice));
+      dfree(s->d_pop);
+      s->d_pop = np;
+      s->pop_cap = cap;
+    }
+  }
+  return MLK_OK;
+}
+
+template <typename T>
+mlk_status enqueue_steps(mlk_sim* s, int64_t nsteps) {
+  const FieldPtrs<T> f = field_ptrs<T>(s);
+  const WindowPtrs<T> win = window_ptrs<T>(s);
+  const Series ser = series_of(s);
+  TlsPtrs tls{};
+  tls.count = (int)s->tls_gid.size();
+  tls.gid = s->d_tls_gid;
+  tls.omega0 = s->d_tls_w0;
+  tls.dip = s->d_tls_dip;
+  tls.rho = s->d_tls_rho;
+  constexpr bool f32 = sizeof(T) == 4;
+  for (int64_t q = 0; q < nsteps; ++q) {
+    if (s->fp.on) {
+      if constexpr (f32) HIPCHK(flux_save_f32(f, s->g, s->fp, s->stream));
+      else HIPCHK(flux_save_f64(f, s->g, s->fp, s->stream));
+    }
+    if (tls.count > 0) {
+      if constexpr (f32)
+        HIPCHK(tls_step_f32(f, s->g, win, tls, s->d_Et, s->d_mudot, s->d_popoff, ser, s->d_step,
+                            s->stream));
+      else
+        HIPCHK(tls_step_f64(f, s->g, win, tls, s->d_Et, s->d_mudot, s->d_popoff, ser, s->d_step,
+                            s->stream));
+    }
+    if constexpr (f32) HIPCHK(sweep_plain_f32(f, s->g, s->src, s->d_step, s->stream));
+    else HIPCHK(sweep_plain_f64(f, s->g, s->src, s->d_step, s->stream));
+    if (s->nem > 0) {
+      if constexpr (f32)
+        HIPCHK(scatter_atomic_f32(f, s->g, win, s->nem, s->d_mudot, s->stream));
+      else
+        HIPCHK(scatter_atomic_f64(f, s->g, win, s->nem, s->d_mudot, s->stream));
+    }
+    if constexpr (f32) HIPCHK(finish_f32(f, s->g, s->fp, ser, s->d_step, s->stream));
+    else HIPCHK(finish_f64(f, s->g, s->fp, ser, s->d_step, s->stream));
+  }
+  return MLK_OK;
+}
+
+void release(mlk_sim* s) {
+  for (int c = 0; c < 3; ++c) {
+    dfree(s->E[c]);
+    dfree(s->H[c]);
+    for (int a = 0; a < 3; ++a) {
+      dfree(s->psiE[c][a]);
+      dfree(s->psiH[c][a]);
+    }
+    dfree(s->tab[c]);
+  }
+  dfree(s->epsinv);
+  dfree(s->d_wlo);
+  dfree(s->d_wlen);
+  dfree(s->d_w);
+  dfree(s->d_pos);
+  dfree(s->d_sigma);
+  dfree(s->d_gamma);
+  dfree(s->d_Et);
+  dfree(s->d_mudot);
+  dfree(s->d_popoff);
+  dfree(s->d_tls_gid);
+  dfree(s->d_tls_w0);
+  dfree(s->d_tls_dip);
+  dfree(s->d_tls_rho);
+  dfree(s->d_probe);
+  dfree(s->d_flux_series);
+  dfree(s->fp.Eu0);
+  dfree(s->fp.Ev0);
+  dfree(s->fp.partial);
+  dfree(s->fp.total);
+  dfree(s->d_pop);
+  dfree(s->d_step);
+  if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+  s->stream = nullptr;
+}
+
+// Device buffers that make up the evolving state, in checkpoint order.
+struct Piece {
+  void* p;
+  size_t bytes;
+};
+
+std::vector<Piece> state_pieces(mlk_sim* s) {
+  std::vector<Piece> v;
+  for (int c = 0; c < 3; ++c) v.push_back({s->E[c], s->ncell * s->esz});
+  for (int c = 0; c < 3; ++c) v.push_back({s->H[c], s->ncell * s->esz});
+  for (int c = 0; c < 3; ++c)
+    for (int a = 0; a < 3; ++a) {
+      if (s->psiE[c][a]) v.push_back({s->psiE[c][a], psi_size(s->g, a) * s->esz});
+      if (s->psiH[c][a]) v.push_back({s->psiH[c][a], psi_size(s->g, a) * s->esz});
+    }
+  if (!s->tls_gid.empty()) v.push_back({s->d_tls_rho, s->tls_gid.size() * 3 * sizeof(double)});
+  if (s->nem > 0) {
+    v.push_back({s->d_Et, (size_t)s->nem * 3 * sizeof(double)});
+    v.push_back({s->d_mudot, (size_t)s->nem * 3 * sizeof(double)});
+  }
+  v.push_back({s->d_step, sizeof(int64_t)});
+  if (s->fp.on) v.push_back({s->fp.total, sizeof(double)});
+  return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+void mlk_grid_desc_init(mlk_grid_desc* g) {
+  if (!g) return;
+  std::memset(g, 0, sizeof(*g));
+  g->nx = g->ny = g->nz = 32;
+  g->dx = 1.0;
+  g->courant = 0.5;
+  g->precision = MLK_FP64;
+  for (int f = 0; f < 6; ++f) {
+    g->bc[f] = MLK_BC_PEC;
+    g->cpml_cells[f] = 0;
+  }
+  g->cpml_m = 3.0;
+  g->cpml_sigma_scale = 0.8;
+  g->cpml_kappa_max = 1.0;
+  g->cpml_alpha_max = 0.0;
+  g->window_r = 3.0;
+  g->stream = nullptr;
+  g->device = 0;
+  g->sweep = MLK_SWEEP_PLAIN;
+  g->scatter = MLK_SCATTER_ATOMIC;
+}
+
+const char* mlk_last_error(void) { return g_err.c_str(); }
+
+const char* mlk_version(void) { return "mlk 0.1 gfx950"; }
+
+mlk_status mlk_create(const mlk_grid_desc* gd, mlk_sim** out) {
+  if (!gd || !out) return fail(MLK_EINVAL, "null argument");
+  *out = nullptr;
+  const int n[3] = {gd->nx, gd->ny, gd->nz};
+  for (int a = 0; a < 3; ++a)
+    if (n[a] < 1) return fail(MLK_EINVAL, "grid size must be >= 1 on every axis");
+  if (!(gd->dx > 0.0) || !std::isfinite(gd->dx)) return fail(MLK_EINVAL, "dx must be > 0");
+  if (!(gd->courant > 0.0) || gd->courant > 1.0 / std::sqrt(3.0))
+    return fail(MLK_EINVAL, "courant %.6f outside (0, 1/sqrt(3)]", gd->courant);
+  if (gd->precision != MLK_FP64 && gd->precision != MLK_FP32_FIELDS)
+    return fail(MLK_EINVAL, "unknown precision %d", gd->precision);
+  if (!(gd->window_r > 0.0)) return fail(MLK_EINVAL, "window_r must be > 0");
+  if (gd->sweep != MLK_SWEEP_PLAIN && gd->sweep != MLK_SWEEP_FUSED)
+    return fail(MLK_EINVAL, "unknown sweep %d", gd->sweep);
+  if (gd->scatter != MLK_SCATTER_ATOMIC && gd->scatter != MLK_SCATTER_OWNER)
+    return fail(MLK_EINVAL, "unknown scatter %d", gd->scatter);
+  for (int a = 0; a < 3; ++a) {
+    const int lo = gd->bc[2 * a], hi = gd->bc[2 * a + 1];
+    for (int b : {lo, hi})
+      if (b < MLK_BC_PEC || b > MLK_BC_CPML) return fail(MLK_EINVAL, "unknown boundary %d", b);
+    if ((lo == MLK_BC_PERIODIC) != (hi == MLK_BC_PERIODIC))
+      return fail(MLK_EINVAL, "periodic boundaries must pair on axis %d", a);
+    for (int f = 0; f < 2; ++f)
+      if (gd->bc[2 * a + f] == MLK_BC_CPML &&
+          (gd->cpml_cells[2 * a + f] < 1 || gd->cpml_cells[2 * a + f] > n[a] / 2))
+        return fail(MLK_EINVAL, "CPML thickness on face %d must be 1..%d", 2 * a + f, n[a] / 2);
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+    return fail(MLK_EDEVICE, "no HIP device available");
+  if (gd->device < 0 || gd->device >= ndev) return fail(MLK_EINVAL, "bad device %d", gd->device);
+  HIPCHK(hipSetDevice(gd->device));
+
+  mlk_sim* s = new mlk_sim();
+  s->desc = *gd;
+  s->fp32 = gd->precision == MLK_FP32_FIELDS;
+  s->esz = s->fp32 ? 4 : 8;
+  Geom& g = s->g;
+  for (int a = 0; a < 3; ++a) {
+    g.n[a] = n[a];
+    g.periodic[a] = gd->bc[2 * a] == MLK_BC_PERIODIC;
+    g.wall[a] = !g.periodic[a];
+    g.nlo[a] = gd->bc[2 * a] == MLK_BC_CPML ? gd->cpml_cells[2 * a] : 0;
+    g.nhi[a] = gd->bc[2 * a + 1] == MLK_BC_CPML ? gd->cpml_cells[2 * a + 1] : 0;
+  }
+  g.dx = gd->dx;
+  g.inv_dx = 1.0 / gd->dx;
+  g.dt = gd->courant * gd->dx;
+  s->ncell = (size_t)n[0] * n[1] * n[2];
+
+  auto bail = [&](mlk_status st) {
+    release(s);
+    delete s;
+    return st;
+  };
+  if (gd->stream) {
+    s->stream = (hipStream_t)gd->stream;
+  } else {
+    if (hipStreamCreate(&s->stream) != hipSuccess)
+      return bail(fail(MLK_EDEVICE, "hipStreamCreate failed"));
+    s->own_stream = true;
+  }
+  auto alloc_zero = [&](void** p, size_t bytes) -> bool {
+    if (dalloc(p, bytes) != hipSuccess) return false;
+    return hipMemsetAsync(*p, 0, bytes, s->stream) == hipSuccess;
+  };
+  for (int c = 0; c < 3; ++c) {
+    if (!alloc_zero(&s->E[c], s->ncell * s->esz) || !alloc_zero(&s->H[c], s->ncell * s->esz))
+      return bail(fail(MLK_ENOMEM, "field allocation of %zu bytes failed", s->ncell * s->esz));
+  }
+  if (dalloc(&s->epsinv, s->ncell * s->esz) != hipSuccess)
+    return bail(fail(MLK_ENOMEM, "eps allocation failed"));
+  {
+    // eps_r = 1 everywhere
+    double* d1 = nullptr;
+    if (dalloc(&d1, s->ncell * sizeof(double)) != hipSuccess)
+      return bail(fail(MLK_ENOMEM, "eps staging allocation failed"));
+    std::vector<double> h(s->ncell, 1.0);
+    hipError_t e = hipMemcpy(d1, h.data(), s->ncell * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = inverse_to(s->fp32, d1, s->epsinv, s->ncell, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    dfree(d1);
+    if (e != hipSuccess) return bail(fail(MLK_EDEVICE, "eps init: %s", hipGetErrorString(e)));
+  }
+  const double sigma_max = gd->cpml_sigma_scale * (gd->cpml_m + 1.0) / gd->dx;
+  for (int a = 0; a < 3; ++a) {
+    if (g.nlo[a] + g.nhi[a] == 0) continue;
+    for (int c = 0; c < 3; ++c) {
+      if (c == a) continue;
+      if (!alloc_zero(&s->psiE[c][a], psi_size(g, a) * s->esz) ||
+          !alloc_zero(&s->psiH[c][a], psi_size(g, a) * s->esz))
+        return bail(fail(MLK_ENOMEM, "psi allocation failed"));
+    }
+    if (dalloc(&s->tab[a], (size_t)6 * n[a] * s->esz) != hipSuccess)
+      return bail(fail(MLK_ENOMEM, "CPML table allocation failed"));
+    char* t = (char*)s->tab[a];
+    const size_t blk = (size_t)2 * n[a] * s->esz;
+    if (cpml_tables(s->fp32, g, a, gd->cpml_m, sigma_max, gd->cpml_kappa_max, gd->cpml_alpha_max,
+                    t, t + blk, t + 2 * blk, s->stream) != hipSuccess)
+      return bail(fail(MLK_EDEVICE, "CPML table kernel failed"));
+  }
+  if (dalloc(&s->d_step, sizeof(int64_t)) != hipSuccess)
+    return bail(fail(MLK_ENOMEM, "step counter allocation failed"));
+  if (hipMemsetAsync(s->d_step, 0, sizeof(int64_t), s->stream) != hipSuccess ||
+      hipStreamSynchronize(s->stream) != hipSuccess)
+    return bail(fail(MLK_EDEVICE, "initialisation failed"));
+  *out = s;
+  return MLK_OK;
+}
+
+mlk_status mlk_destroy(mlk_sim* s) {
+  if (!s) return MLK_OK;
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  release(s);
+  delete s;
+  return MLK_OK;
+}
+
+mlk_status mlk_set_eps(mlk_sim* s, const double* eps, int32_t mem_kind) {
+  if (!s || !eps) return fail(MLK_EINVAL, "null argument");
+  std::vector<double> h;
+  const double* src = eps;
+  if (mem_kind == MLK_MEM_DEVICE) {
+    h.resize(s->ncell);
+    HIPCHK(hipMemcpy(h.data(), eps, s->ncell * sizeof(double), hipMemcpyDeviceToHost));
+    src = h.data();
+  } else if (mem_kind != MLK_MEM_HOST) {
+    return fail(MLK_EINVAL, "bad mem_kind");
+  }
+  for (size_t q = 0; q < s->ncell; ++q)
+    if (!(src[q] >= 1.0) || !std::isfinite(src[q]))
+      return fail(MLK_EINVAL, "eps_r[%zu] = %g must be finite and >= 1", q, src[q]);
+  double* d = nullptr;
+  HIPCHK(dalloc(&d, s->ncell * sizeof(double)));
+  hipError_t e = hipMemcpy(d, src, s->ncell * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e == hipSuccess) e = inverse_to(s->fp32, d, s->epsinv, s->ncell, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  dfree(d);
+  if (e != hipSuccess) return fail(MLK_EDEVICE, "set_eps: %s", hipGetErrorString(e));
+  return MLK_OK;
+}
+
+mlk_status mlk_set_field(mlk_sim* s, int32_t comp, const double* src, int32_t mem_kind) {
+  if (!s || !src) return fail(MLK_EINVAL, "null argument");
+  if (comp < 0 || comp > 5) return fail(MLK_EINVAL, "component %d outside 0..5", comp);
+  double* d = nullptr;
+  HIPCHK(dalloc(&d, s->ncell * sizeof(double)));
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpy(d, src, s->ncell * sizeof(double),
+                  mem_kind == MLK_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice);
+  void* dst = comp < 3 ? s->E[comp] : s->H[comp - 3];
+  if (e == hipSuccess) e = convert_in(s->fp32, d, dst, s->ncell, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  dfree(d);
+  if (e != hipSuccess) return fail(MLK_EDEVICE, "set_field: %s", hipGetErrorString(e));
+  return MLK_OK;
+}
+
+mlk_status mlk_add_tls(mlk_sim* s, int32_t n, const double* pos, const double* sigma,
+                       const double* gamma, const double* omega0, const double* dipole,
+                       const double* rho0, int32_t* first_id) {
+  if (!s || !pos || !sigma || !gamma || !omega0 || !dipole || !rho0)
+    return fail(MLK_EINVAL, "null argument");
+  if (n < 0) return fail(MLK_EINVAL, "negative count");
+  if (s->host_step > 0) return fail(MLK_ESTATE, "emitters must be added before stepping");
+  for (int q = 0; q < n; ++q) {
+    STCHK(check_emitter_geometry(s, pos + 3 * q, sigma[q]));
+    const double p = rho0[3 * q], re = rho0[3 * q + 1], im = rho0[3 * q + 2];
+    if (!(p >= 0.0 && p <= 1.0) || !std::isfinite(re) || !std::isfinite(im) ||
+        re * re + im * im > p * (1.0 - p) * (1.0 + 1e-12) + 1e-300)
+      return fail(MLK_EINVAL, "emitter %d: initial state is not a density matrix", q);
+    if (!std::isfinite(omega0[q]) || !std::isfinite(gamma[q]))
+      return fail(MLK_EINVAL, "emitter %d: parameters not finite", q);
+  }
+  if (first_id) *first_id = s->nem;
+  for (int q = 0; q < n; ++q) {
+    const int e = s->nem++;
+    for (int a = 0; a < 3; ++a) s->pos.push_back(pos[3 * q + a]);
+    s->sigma.push_back(sigma[q]);
+    s->gamma.push_back(gamma[q]);
+    s->pop_off.push_back(s->npop);
+    s->npop += 1;
+    s->tls_slot.push_back((int)s->tls_gid.size());
+    s->tls_gid.push_back(e);
+    s->tls_w0.push_back(omega0[q]);
+    for (int a = 0; a < 3; ++a) s->tls_dip.push_back(dipole[3 * q + a]);
+    for (int a = 0; a < 3; ++a) s->tls_rho0.push_back(rho0[3 * q + a]);
+  }
+  return rebuild_emitters(s);
+}
+
+mlk_status mlk_add_multilevel(mlk_sim* s, int32_t, const int32_t*, const int64_t*,
+                              const int64_t*, const double*, const double*, const double*,
+                              const double*, const double*, const double*, const double*,
+                              const double*, int32_t*) {
+  if (!s) return fail(MLK_EINVAL, "null argument");
+  return fail(MLK_EUNSUPPORTED, "multilevel emitters are not built yet");
+}
+
+static mlk_status add_source(mlk_sim* s, const Source& src) {
+  if (s->src.count >= kMaxSources) return fail(MLK_EINVAL, "at most %d sources", kMaxSources);
+  if (!(src.tau > 0.0) || !std::isfinite(src.amp) || !std::isfinite(src.omega) ||
+      !std::isfinite(src.t0))
+    return fail(MLK_EINVAL, "bad source parameters");
+  s->src.s[s->src.count++] = src;
+  return MLK_OK;
+}
+
+mlk_status mlk_add_plane_source(mlk_sim* s, int32_t axis, int32_t index, int32_t comp,
+                                double amp, double omega, double tau, double t0) {
+  if (!s) return fail(MLK_EINVAL, "null argument");
+  if (axis < 0 || axis > 2 || comp < 0 || comp > 2 || index < 0 || index >= s->g.n[axis])
+    return fail(MLK_EINVAL, "bad plane source axis/index/component");
+  Source src{};
+  src.kind = 0;
+  src.axis = axis;
+  src.index = index;
+  src.comp = comp;
+  src.amp = amp;
+  src.omega = omega;
+  src.tau = tau;
+  src.t0 = t0;
+  return add_source(s, src);
+}
+
+mlk_status mlk_add_point_source(mlk_sim* s, int32_t comp, const int32_t ijk[3], double amp,
+                                double omega, double tau, double t0) {
+  if (!s || !ijk) return fail(MLK_EINVAL, "null argument");
+  if (comp < 0 || comp > 2) return fail(MLK_EINVAL, "bad component");
+  for (int a = 0; a < 3; ++a)
+    if (ijk[a] < 0 || ijk[a] >= s->g.n[a]) return fail(MLK_EINVAL, "point source outside grid");
+  Source src{};
+  src.kind = 1;
+  src.comp = comp;
+  for (int a = 0; a < 3; ++a) src.ijk[a] = ijk[a];
+  src.amp = amp;
+  src.omega = omega;
+  src.tau = tau;
+  src.t0 = t0;
+  return add_source(s, src);
+}
+
+mlk_status mlk_add_probe(mlk_sim* s, int32_t comp, const int32_t ijk[3], int32_t* id) {
+  if (!s || !ijk) return fail(MLK_EINVAL, "null argument");
+  if (s->host_step > 0) return fail(MLK_ESTATE, "probes must be added before stepping");
+  if (s->nprobe >= 16) return fail(MLK_EINVAL, "at most 16 probes");
+  if (comp < 0 || comp > 5) return fail(MLK_EINVAL, "bad component");
+  for (int a = 0; a < 3; ++a)
+    if (ijk[a] < 0 || ijk[a] >= s->g.n[a]) return fail(MLK_EINVAL, "probe outside grid");
+  const int p = s->nprobe++;
+  s->probe_comp[p] = comp;
+  s->probe_idx[p] = (int64_t)cell_index(s->g, ijk[0], ijk[1], ijk[2]);
+  if (id) *id = p;
+  dfree(s->d_probe);
+  s->series_cap = 0;
+  return MLK_OK;
+}
+
+mlk_status mlk_add_flux_plane(mlk_sim* s, int32_t axis, int32_t index) {
+  if (!s) return fail(MLK_EINVAL, "null argument");
+  if (s->host_step > 0) return fail(MLK_ESTATE, "detectors must be added before stepping");
+  if (s->fp.on) return fail(MLK_EINVAL, "one flux plane per simulation");
+  if (axis < 0 || axis > 2 || index < 1 || index >= s->g.n[axis])
+    return fail(MLK_EINVAL, "flux plane index must be 1..n-1");
+  const int u = (axis + 1) % 3, v = (axis + 2) % 3;
+  const size_t np = (size_t)s->g.n[u] * s->g.n[v];
+  s->fp.axis = axis;
+  s->fp.index = index;
+  s->fp.nblocks = (int)std::min<size_t>((np + 255) / 256, 1024);
+  HIPCHK(dalloc(&s->fp.Eu0, np * sizeof(double)));
+  HIPCHK(dalloc(&s->fp.Ev0, np * sizeof(double)));
+  HIPCHK(dalloc(&s->fp.partial, (size_t)s->fp.nblocks * sizeof(double)));
+  HIPCHK(dalloc(&s->fp.total, sizeof(double)));
+  HIPCHK(hipMemset(s->fp.total, 0, sizeof(double)));
+  s->fp.on = 1;
+  dfree(s->d_probe);
+  s->series_cap = 0;
+  return MLK_OK;
+}
+
+mlk_status mlk_record_populations(mlk_sim* s, int32_t every) {
+  if (!s) return fail(MLK_EINVAL, "null argument");
+  if (s->host_step > 0) return fail(MLK_ESTATE, "detectors must be set before stepping");
+  if (every < 0) return fail(MLK_EINVAL, "every must be >= 0");
+  s->pop_every = every;
+  dfree(s->d_pop);
+  s->pop_cap = 0;
+  return MLK_OK;
+}
+
+mlk_status mlk_step(mlk_sim* s, int64_t nsteps) {
+  if (!s) return fail(MLK_EINVAL, "null argument");
+  if (nsteps < 0) return fail(MLK_EINVAL, "negative step count");
+  if (nsteps == 0) return MLK_OK;
+  HIPCHK(hipSetDevice(s->desc.device));
+  STCHK(reserve_series(s, nsteps));
+  mlk_status st = s->fp32 ? enqueue_steps<float>(s, nsteps) : enqueue_steps<double>(s, nsteps);
+  if (st == MLK_OK) s->host_step += nsteps;
+  return st;
+}
+
+mlk_status mlk_sync(mlk_sim* s) {
+  if (!s) return fail(MLK_EINVAL, "null argument");
+  HIPCHK(hipStreamSynchronize(s->stream));
+  return MLK_OK;
+}
+
+mlk_status mlk_step_count(mlk_sim* s, int64_t* n) {
+  if (!s || !n) return fail(MLK_EINVAL, "null argument");
+  *n = s->host_step;
+  return MLK_OK;
+}
+
+mlk_status mlk_get_field(mlk_sim* s, int32_t comp, double* dst, int32_t mem_kind) {
+  if (!s || !dst) return fail(MLK_EINVAL, "null argument");
+  if (comp < 0 || comp > 5) return fail(MLK_EINVAL, "component %d outside 0..5", comp);
+  const void* src = comp < 3 ? s->E[comp] : s->H[comp - 3];
+  HIPCHK(hipStreamSynchronize(s->stream));
+  if (mem_kind == MLK_MEM_DEVICE) {
+    HIPCHK(convert_out(s->fp32, src, dst, s->ncell, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return MLK_OK;
+  }
+  double* d = nullptr;
+  HIPCHK(dalloc(&d, s->ncell * sizeof(double)));
+  hipError_t e = convert_out(s->fp32, src, d, s->ncell, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e == hipSuccess) e = hipMemcpy(dst, d, s->ncell * sizeof(double), hipMemcpyDeviceToHost);
+  dfree(d);
+  if (e != hipSuccess) return fail(MLK_EDEVICE, "get_field: %s", hipGetErrorString(e));
+  return MLK_OK;
+}
+
+mlk_status mlk_get_tls_state(mlk_sim* s, int32_t first, int32_t count, double* dst) {
+  if (!s || !dst) return fail(MLK_EINVAL, "null argument");
+  HIPCHK(hipStreamSynchronize(s->stream));
+  const int nt = (int)s->tls_gid.size();
+  std::vector<double> all((size_t)nt * 3);
+  if (nt) HIPCHK(hipMemcpy(all.data(), s->d_tls_rho, all.size() * sizeof(double),
+                           hipMemcpyDeviceToHost));
+  // map emitter ids to two-level slots
+  if (first < 0 || count < 0 || first + count > s->nem)
+    return fail(MLK_EINVAL, "emitter range outside 0..%d", s->nem);
+  for (int q = 0; q < count; ++q) {
+    const int id = first + q;
+    const int slot = s->tls_slot[id];
+    if (slot < 0) return fail(MLK_EINVAL, "emitter %d is not a two-level emitter", id);
+    for (int a = 0; a < 3; ++a) dst[3 * q + a] = all[3 * slot + a];
+  }
+  return MLK_OK;
+}
+
+mlk_status mlk_get_rho(mlk_sim* s, int32_t id, double* dst, int32_t cap, int32_t* nlev) {
+  if (!s || !dst) return fail(MLK_EINVAL, "null argument");
+  if (id < 0 || id >= s->nem) return fail(MLK_EINVAL, "bad emitter id");
+  double st[3];
+  STCHK(mlk_get_tls_state(s, id, 1, st));
+  if (cap < 8) return fail(MLK_EINVAL, "dst too small");
+  dst[0] = 1.0 - st[0];
+  dst[1] = 0.0;
+  dst[2] = st[1];
+  dst[3] = st[2];
+  dst[4] = st[1];
+  dst[5] = -st[2];
+  dst[6] = st[0];
+  dst[7] = 0.0;
+  if (nlev) *nlev = 2;
+  return MLK_OK;
+}
+
+mlk_status mlk_get_emitter_io(mlk_sim* s, double* Et, double* mudot) {
+  if (!s) return fail(MLK_EINVAL, "null argument");
+  HIPCHK(hipStreamSynchronize(s->stream));
+  const size_t b = (size_t)s->nem * 3 * sizeof(double);
+  if (Et && b) HIPCHK(hipMemcpy(Et, s->d_Et, b, hipMemcpyDeviceToHost));
+  if (mudot && b) HIPCHK(hipMemcpy(mudot, s->d_mudot, b, hipMemcpyDeviceToHost));
+  return MLK_OK;
+}
+
+mlk_status mlk_get_series(mlk_sim* s, int32_t kind, int32_t id, double* dst, int64_t cap,
+                          int64_t* len) {
+  if (!s) return fail(MLK_EINVAL, "null argument");
+  HIPCHK(hipStreamSynchronize(s->stream));
+  int64_t n = 0;
+  const double* src = nullptr;
+  if (kind == MLK_SERIES_PROBE) {
+    if (id < 0 || id >= s->nprobe) return fail(MLK_EINVAL, "bad probe id");
+    n = s->host_step;
+    src = s->d_probe ? s->d_probe + (size_t)id * s->series_cap : nullptr;
+  } else if (kind == MLK_SERIES_FLUX) {
+    if (!s->fp.on) return fail(MLK_EINVAL, "no flux plane");
+    n = s->host_step;
+    src = s->d_flux_series;
+  } else if (kind == MLK_SERIES_POPULATION) {
+    const int64_t rec =
+        (s->pop_every > 0 && s->host_step > 0) ? (s->host_step - 1) / s->pop_every + 1 : 0;
+    n = rec * s->npop;
+    src = s->d_pop;
+  } else {
+    return fail(MLK_EINVAL, "bad series kind");
+  }
+  if (len) *len = n;
+  if (dst && n > 0 && src) {
+    const int64_t m = n < cap ? n : cap;
+    HIPCHK(hipMemcpy(dst, src, (size_t)m * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  return MLK_OK;
+}
+
+mlk_status mlk_get_flux_total(mlk_sim* s, double* total) {
+  if (!s || !total) return fail(MLK_EINVAL, "null argument");
+  if (!s->fp.on) return fail(MLK_EINVAL, "no flux plane");
+  HIPCHK(hipStreamSynchronize(s->stream));
+  HIPCHK(hipMemcpy(total, s->fp.total, sizeof(double), hipMemcpyDeviceToHost));
+  return MLK_OK;
+}
+
+mlk_status mlk_checkpoint_size(mlk_sim* s, size_t* bytes) {
+  if (!s || !bytes) return fail(MLK_EINVAL, "null argument");
+  size_t b = 0;
+  for (const Piece& p : state_pieces(s)) b += p.bytes;
+  *bytes = b;
+  return MLK_OK;
+}
+
+mlk_status mlk_checkpoint_save(mlk_sim* s, void* dst, int32_t mem_kind) {
+  if (!s || !dst) return fail(MLK_EINVAL, "null argument");
+  HIPCHK(hipStreamSynchronize(s->stream));
+  char* o = (char*)dst;
+  const hipMemcpyKind kind =
+      mem_kind == MLK_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  for (const Piece& p : state_pieces(s)) {
+    HIPCHK(hipMemcpy(o, p.p, p.bytes, kind));
+    o += p.bytes;
+  }
+  return MLK_OK;
+}
+
+mlk_status mlk_checkpoint_load(mlk_sim* s, const void* src, int32_t mem_kind) {
+  if (!s || !src) return fail(MLK_EINVAL, "null argument");
+  HIPCHK(hipStreamSynchronize(s->stream));
+  const char* o = (const char*)src;
+  const hipMemcpyKind kind =
+      mem_kind == MLK_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  for (const Piece& p : state_pieces(s)) {
+    HIPCHK(hipMemcpy(p.p, o, p.bytes, kind));
+    o += p.bytes;
+  }
+  int64_t step = 0;
+  HIPCHK(hipMemcpy(&step, s->d_step, sizeof(int64_t), hipMemcpyDeviceToHost));
+  if (step > s->host_step) STCHK(reserve_series(s, step - s->host_step));
+  s->host_step = step;
+  return MLK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,373 @@
+"""ctypes binding of libmlk (include/mlk.h): argument marshalling only.
+
+Every numerical step runs in the HIP kernels of ``libmlk.so``.  PyTorch is
+used only to hand over the current HIP stream when the caller wants the
+library to run on it.  If the library is missing this module raises; there
+is no fallback path.
+
+Grid arrays are numpy arrays of shape (nz, ny, nx) (x fastest), float64.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmlk.so")
+
+MLK_OK, MLK_EINVAL, MLK_ENOMEM, MLK_EDEVICE, MLK_ESTATE, MLK_EUNSUPPORTED, MLK_ENUMERIC = range(7)
+FP64, FP32_FIELDS = 0, 1
+BC = {"pec": 0, "periodic": 1, "cpml": 2}
+MEM_HOST, MEM_DEVICE = 0, 1
+SWEEP = {"fused": 0, "plain": 1}
+SCATTER = {"owner": 0, "atomic": 1}
+SERIES_PROBE, SERIES_FLUX, SERIES_POPULATION = 0, 1, 2
+
+_STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "EUNSUPPORTED", 6: "ENUMERIC"}
+
+
+class MlkError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"mlk {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class GridDesc(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("dx", C.c_double), ("courant", C.c_double),
+        ("precision", C.c_int32),
+        ("bc", C.c_int32 * 6), ("cpml_cells", C.c_int32 * 6),
+        ("cpml_m", C.c_double), ("cpml_sigma_scale", C.c_double),
+        ("cpml_kappa_max", C.c_double), ("cpml_alpha_max", C.c_double),
+        ("window_r", C.c_double),
+        ("stream", C.c_void_p),
+        ("device", C.c_int32),
+        ("sweep", C.c_int32),
+        ("scatter", C.c_int32),
+    ]
+
+
+_lib = None
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_lp = C.POINTER(C.c_int64)
+
+
+def lib():
+    """Load libmlk.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2512_06173_amd/build.py")
+    L = C.CDLL(LIB_PATH)
+    st = C.c_int
+    sim = C.c_void_p
+    sigs = {
+        "mlk_grid_desc_init": (None, [C.POINTER(GridDesc)]),
+        "mlk_last_error": (C.c_char_p, []),
+        "mlk_version": (C.c_char_p, []),
+        "mlk_create": (st, [C.POINTER(GridDesc), C.POINTER(C.c_void_p)]),
+        "mlk_destroy": (st, [sim]),
+        "mlk_set_eps": (st, [sim, _dp, C.c_int32]),
+        "mlk_set_field": (st, [sim, C.c_int32, _dp, C.c_int32]),
+        "mlk_add_tls": (st, [sim, C.c_int32, _dp, _dp, _dp, _dp, _dp, _dp, _ip]),
+        "mlk_add_multilevel": (st, [sim, C.c_int32, _ip, _lp, _lp, _dp, _dp, _dp, _dp, _dp, _dp,
+                                    _dp, _dp, _ip]),
+        "mlk_add_plane_source": (st, [sim, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                      C.c_double, C.c_double]),
+        "mlk_add_point_source": (st, [sim, C.c_int32, _ip, C.c_double, C.c_double, C.c_double,
+                                      C.c_double]),
+        "mlk_add_probe": (st, [sim, C.c_int32, _ip, _ip]),
+        "mlk_add_flux_plane": (st, [sim, C.c_int32, C.c_int32]),
+        "mlk_record_populations": (st, [sim, C.c_int32]),
+        "mlk_step": (st, [sim, C.c_int64]),
+        "mlk_sync": (st, [sim]),
+        "mlk_step_count": (st, [sim, _lp]),
+        "mlk_get_field": (st, [sim, C.c_int32, _dp, C.c_int32]),
+        "mlk_get_rho": (st, [sim, C.c_int32, _dp, C.c_int32, _ip]),
+        "mlk_get_tls_state": (st, [sim, C.c_int32, C.c_int32, _dp]),
+        "mlk_get_emitter_io": (st, [sim, _dp, _dp]),
+        "mlk_get_series": (st, [sim, C.c_int32, C.c_int32, _dp, C.c_int64, _lp]),
+        "mlk_get_flux_total": (st, [sim, _dp]),
+        "mlk_checkpoint_size": (st, [sim, C.POINTER(C.c_size_t)]),
+        "mlk_checkpoint_save": (st, [sim, C.c_void_p, C.c_int32]),
+        "mlk_checkpoint_load": (st, [sim, C.c_void_p, C.c_int32]),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def exported_symbols():
+    """Names the binding expects the library to export."""
+    return ["mlk_grid_desc_init", "mlk_last_error", "mlk_version", "mlk_create", "mlk_destroy",
+            "mlk_set_eps", "mlk_set_field", "mlk_add_tls", "mlk_add_multilevel",
+            "mlk_add_plane_source", "mlk_add_point_source", "mlk_add_probe", "mlk_add_flux_plane",
+            "mlk_record_populations", "mlk_step", "mlk_sync", "mlk_step_count", "mlk_get_field",
+            "mlk_get_rho", "mlk_get_tls_state", "mlk_get_emitter_io", "mlk_get_series",
+            "mlk_get_flux_total", "mlk_checkpoint_size", "mlk_checkpoint_save",
+            "mlk_checkpoint_load"]
+
+
+def _check(st):
+    if st != MLK_OK:
+        raise MlkError(st, lib().mlk_last_error().decode(errors="replace"))
+
+
+def _d(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(_ip)
+
+
+def _i64(a):
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    return a, a.ctypes.data_as(_lp)
+
+
+def current_stream_handle():
+    """HIP stream of torch's current stream on the current device (ROCm build)."""
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Simulation:
+    """One coupled Yee-FDTD / emitter simulation on one GPU."""
+
+    def __init__(self, shape, dx=1.0, courant=0.5, precision="fp64", bc=("pec",) * 6,
+                 cpml=(0,) * 6, pml_m=3.0, pml_sigma_scale=0.8, pml_kappa_max=1.0,
+                 pml_alpha_max=0.0, window_r=3.0, sweep="plain", scatter="atomic", stream=None,
+                 device=0):
+        L = lib()
+        d = GridDesc()
+        L.mlk_grid_desc_init(C.byref(d))
+        d.nx, d.ny, d.nz = (int(v) for v in shape)
+        d.dx, d.courant = float(dx), float(courant)
+        d.precision = FP64 if precision == "fp64" else FP32_FIELDS
+        for f in range(6):
+            d.bc[f] = BC[bc[f]] if isinstance(bc[f], str) else int(bc[f])
+            d.cpml_cells[f] = int(cpml[f])
+        d.cpml_m, d.cpml_sigma_scale = float(pml_m), float(pml_sigma_scale)
+        d.cpml_kappa_max, d.cpml_alpha_max = float(pml_kappa_max), float(pml_alpha_max)
+        d.window_r = float(window_r)
+        d.stream = stream.value if isinstance(stream, C.c_void_p) else stream
+        d.device = int(device)
+        d.sweep = SWEEP[sweep] if isinstance(sweep, str) else int(sweep)
+        d.scatter = SCATTER[scatter] if isinstance(scatter, str) else int(scatter)
+        h = C.c_void_p()
+        _check(L.mlk_create(C.byref(d), C.byref(h)))
+        self._h = h
+        self.shape = (d.nx, d.ny, d.nz)
+        self.precision = precision
+        self.dt = courant * dx
+        self.nlev = []
+        self.nprobe = 0
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().mlk_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def ncell(self):
+        nx, ny, nz = self.shape
+        return nx * ny * nz
+
+    # ------------------------------------------------------------ set-up
+    def set_eps(self, eps):
+        a, p = _d(np.asarray(eps, dtype=np.float64).ravel())
+        _check(lib().mlk_set_eps(self._h, p, MEM_HOST))
+
+    def set_field(self, comp, arr):
+        a, p = _d(np.asarray(arr, dtype=np.float64).ravel())
+        _check(lib().mlk_set_field(self._h, comp, p, MEM_HOST))
+
+    def add_tls(self, pos, sigma, gamma, omega0, dipole, rho0):
+        pos = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
+        n = pos.shape[0]
+        b = lambda v: _d(np.broadcast_to(np.asarray(v, dtype=np.float64), (n,)).copy())
+        keep = [_d(pos), b(sigma), b(gamma), b(omega0),
+                _d(np.asarray(dipole, dtype=np.float64).reshape(n, 3)),
+                _d(np.asarray(rho0, dtype=np.float64).reshape(n, 3))]
+        first = C.c_int32()
+        _check(lib().mlk_add_tls(self._h, n, *[k[1] for k in keep], C.byref(first)))
+        self.nlev += [2] * n
+        return first.value
+
+    def add_multilevel(self, nlev, energies, mop, dipole, gphi, rho0, pos, sigma, gamma):
+        n = len(nlev)
+        nl = np.asarray(nlev, dtype=np.int32)
+        eoff = np.zeros(n, dtype=np.int64)
+        moff = np.zeros(n, dtype=np.int64)
+        eo = mo = 0
+        for q in range(n):
+            eoff[q], moff[q] = eo, mo
+            eo += nl[q]
+            mo += nl[q] * nl[q]
+        en = np.concatenate([np.asarray(e, dtype=np.float64).ravel() for e in energies])
+        mm = np.concatenate([np.asarray(m, dtype=np.float64).ravel() for m in mop])
+        rr = np.concatenate([np.asarray(r, dtype=np.complex128).ravel() for r in rho0])
+        ri = np.stack([rr.real, rr.imag], axis=1).ravel()
+        b = lambda v: _d(np.broadcast_to(np.asarray(v, dtype=np.float64), (n,)).copy())
+        keep = [_i32(nl), _i64(eoff), _i64(moff), _d(en), _d(mm),
+                _d(np.asarray(dipole, dtype=np.float64).reshape(n, 3)), b(gphi), _d(ri),
+                _d(np.asarray(pos, dtype=np.float64).reshape(n, 3)), b(sigma), b(gamma)]
+        first = C.c_int32()
+        _check(lib().mlk_add_multilevel(self._h, n, *[k[1] for k in keep], C.byref(first)))
+        self.nlev += [int(v) for v in nl]
+        return first.value
+
+    def add_plane_source(self, axis, index, comp, amp, omega, tau, t0):
+        _check(lib().mlk_add_plane_source(self._h, axis, index, comp, amp, omega, tau, t0))
+
+    def add_point_source(self, comp, ijk, amp, omega, tau, t0):
+        a, p = _i32(ijk)
+        _check(lib().mlk_add_point_source(self._h, comp, p, amp, omega, tau, t0))
+
+    def add_probe(self, comp, ijk):
+        a, p = _i32(ijk)
+        pid = C.c_int32()
+        _check(lib().mlk_add_probe(self._h, comp, p, C.byref(pid)))
+        self.nprobe += 1
+        return pid.value
+
+    def add_flux_plane(self, axis, index):
+        _check(lib().mlk_add_flux_plane(self._h, axis, index))
+
+    def record_populations(self, every=1):
+        _check(lib().mlk_record_populations(self._h, int(every)))
+
+    # ------------------------------------------------------------ stepping
+    def step(self, n=1):
+        _check(lib().mlk_step(self._h, int(n)))
+
+    def sync(self):
+        _check(lib().mlk_sync(self._h))
+
+    @property
+    def step_count(self):
+        v = C.c_int64()
+        _check(lib().mlk_step_count(self._h, C.byref(v)))
+        return v.value
+
+    # ------------------------------------------------------------ read-back
+    def get_field(self, comp):
+        nx, ny, nz = self.shape
+        out = np.empty(self.ncell)
+        _check(lib().mlk_get_field(self._h, comp, out.ctypes.data_as(_dp), MEM_HOST))
+        return out.reshape(nz, ny, nx)
+
+    def fields(self):
+        return [self.get_field(c) for c in range(6)]
+
+    def rho(self, m):
+        L = self.nlev[m]
+        out = np.zeros(2 * L * L)
+        nl = C.c_int32()
+        _check(lib().mlk_get_rho(self._h, m, out.ctypes.data_as(_dp), out.size, C.byref(nl)))
+        return (out[0::2] + 1j * out[1::2]).reshape(L, L)
+
+    def tls_state(self, first=0, count=None):
+        if count is None:
+            count = len(self.nlev) - first
+        out = np.zeros((count, 3))
+        _check(lib().mlk_get_tls_state(self._h, first, count, out.ctypes.data_as(_dp)))
+        return out
+
+    def emitter_io(self):
+        M = len(self.nlev)
+        Et = np.zeros((max(M, 1), 3))
+        md = np.zeros((max(M, 1), 3))
+        _check(lib().mlk_get_emitter_io(self._h, Et.ctypes.data_as(_dp), md.ctypes.data_as(_dp)))
+        return Et[:M], md[:M]
+
+    def _series(self, kind, sid=0):
+        n = C.c_int64()
+        _check(lib().mlk_get_series(self._h, kind, sid, None, 0, C.byref(n)))
+        out = np.zeros(max(n.value, 1))
+        _check(lib().mlk_get_series(self._h, kind, sid, out.ctypes.data_as(_dp), n.value,
+                                    C.byref(n)))
+        return out[:n.value]
+
+    def probe(self, pid):
+        return self._series(SERIES_PROBE, pid)
+
+    def flux_series(self):
+        return self._series(SERIES_FLUX)
+
+    def flux_total(self):
+        v = C.c_double()
+        _check(lib().mlk_get_flux_total(self._h, C.byref(v)))
+        return v.value
+
+    def populations(self):
+        v = self._series(SERIES_POPULATION)
+        per = sum(L - 1 for L in self.nlev)
+        return v.reshape(-1, per) if per else v.reshape(0, 0)
+
+    # ------------------------------------------------------------ checkpoints
+    def checkpoint_size(self):
+        v = C.c_size_t()
+        _check(lib().mlk_checkpoint_size(self._h, C.byref(v)))
+        return v.value
+
+    def checkpoint_save(self):
+        buf = np.zeros(self.checkpoint_size(), dtype=np.uint8)
+        _check(lib().mlk_checkpoint_save(self._h, buf.ctypes.data_as(C.c_void_p), MEM_HOST))
+        return buf
+
+    def checkpoint_load(self, buf):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        _check(lib().mlk_checkpoint_load(self._h, buf.ctypes.data_as(C.c_void_p), MEM_HOST))
+
+
+def from_workload(w, pop_every=None, **kw):
+    """Build a Simulation from a seeded Workload (paper_2512_06173_amd.workloads)."""
+    sim = Simulation(w.shape, dx=w.dx, courant=w.courant, precision=w.precision, bc=w.bc,
+                     cpml=w.cpml, **kw)
+    if w.eps is not None:
+        sim.set_eps(w.eps)
+    if w.tls is not None and len(w.tls):
+        t = w.tls
+        sim.add_tls(t.pos, t.sigma, t.gamma, t.omega0, t.dipole, t.rho0)
+    if w.multilevel is not None and len(w.multilevel):
+        m = w.multilevel
+        sim.add_multilevel(m.nlev, m.energies, m.mop, m.dipole, m.gphi, m.rho0, m.pos, m.sigma,
+                           m.gamma)
+    for s in w.plane_sources:
+        sim.add_plane_source(s.axis, s.index, s.comp, s.amp, s.omega, s.tau, s.t0)
+    for s in w.point_sources:
+        sim.add_point_source(s.comp, s.ijk, s.amp, s.omega, s.tau, s.t0)
+    for comp, ijk in w.probes:
+        sim.add_probe(comp, ijk)
+    if w.flux is not None:
+        sim.add_flux_plane(*w.flux)
+    pe = w.pop_every if pop_every is None else pop_every
+    if pe:
+        sim.record_populations(pe)
+    return sim

@@ -284,7 +284,7 @@ def radiating_cube(n=256, n_emit=100000, steps=4000, cpml=10, emit_box=None, des
     objective plane sits at z index 200 of 256 (scaled with n)."""
     rng = np.random.default_rng(seed)
     if emit_box is None:
-        emit_box = (n // 4, 3 * n // 4)
+        emit_box = (max(n // 4, cpml + 4), min(3 * n // 4, n - cpml - 4))
     if design_box is None:
         a = 3 * n // 8
         design_box = (a, n - a) * 3
