@@ -18,6 +18,7 @@
 #include <climits>
 
 #include "mlk_internal.h"
+#include "tls_math.h"
 
 namespace mlk {
 
@@ -32,20 +33,20 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// One thread per (emitter, component, axis): window start, length and the
-// normalised 1-D Gaussian weights along that axis.
+// One thread per (emitter, axis, position variant): window start, length and
+// the normalised 1-D Gaussian weights along that axis.  The window holds the
+// points q + v/2 with (q + v/2 - r)^2 <= (R sigma)^2; on an invariant axis
+// (one periodic cell) it is that cell with weight 1.
 template <typename T>
-__global__ void k_windows(int count, int first, const double* pos, const double* sigma,
-                          double R, Geom g, int* lo, int* len, T* w) {
+__global__ void k_windows(int count, const double* pos, const double* sigma, double R, Geom g,
+                          int* lo, int* len, T* w) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= count * 9) return;
-  const int m = t / 9, c = (t / 3) % 3, a = t % 3;
-  const int e = first + m;
-  const size_t slot = ((size_t)e * 3 + c) * 3 + a;
-  T* wv = w + slot * kMaxWin;
+  if (t >= count * 6) return;
+  const int m = t / 6, a = (t / 2) % 3, v = t % 2;
+  const int slot = win_slot(m, a, v);
+  T* wv = w + (size_t)slot * kMaxWin;
   for (int q = 0; q < kMaxWin; ++q) wv[q] = T(0);
   if (g.n[a] == 1 && g.periodic[a]) {
-    // invariant direction: single layer, factor cancels in the normalisation
     lo[slot] = 0;
     len[slot] = 1;
     wv[0] = T(1);
@@ -54,10 +55,10 @@ __global__ void k_windows(int count, int first, const double* pos, const double*
   const double r = pos[3 * m + a];
   const double s = sigma[m];
   const double rs = R * s;
-  const double sh = (a == c) ? 0.5 : 0.0;
+  const double sh = 0.5 * v;
   const int q0 = (int)floor(r - sh - rs) - 1;
   int firstq = INT_MAX, lastq = INT_MIN;
-  for (int q = q0; q <= q0 + 2 * kMaxWin + 4; ++q) {
+  for (int q = q0; q <= q0 + kMaxWin + 3; ++q) {
     const double o = (double)q + sh - r;
     if (o * o <= rs * rs) {
       if (firstq == INT_MAX) firstq = q;
@@ -79,62 +80,71 @@ __global__ void k_windows(int count, int first, const double* pos, const double*
   len[slot] = L;
 }
 
+// One thread per (emitter, axis, variant): the union-window record of the
+// binned kernels (see WinRec).
+template <typename T>
+__global__ void k_records(int count, const int* lo, const int* len, const T* w, WinRec<T>* rec) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count * 6) return;
+  const int m = t / 6, a = (t / 2) % 3, v = t % 2;
+  const int lo0 = lo[win_slot(m, a, 0)], n0 = len[win_slot(m, a, 0)];
+  const int lo1 = lo[win_slot(m, a, 1)], n1 = len[win_slot(m, a, 1)];
+  const int org = min(lo0, lo1);
+  const int end = max(lo0 + n0, lo1 + n1);
+  const int l = v ? lo1 : lo0, n = v ? n1 : n0;
+  const T* wv = w + (size_t)win_slot(m, a, v) * kMaxWin;
+  WinRec<T>& r = rec[m];
+  for (int d = 0; d < kMaxWin; ++d) {
+    const int k = org + d - l;
+    r.wr[a][v][d] = (k >= 0 && k < n) ? wv[k] : T(0);
+  }
+  if (v == 0) {
+    r.org[a] = org;
+    r.n[a] = min(end - org, kMaxWin);
+  }
+  if (t % 6 == 0) {
+    // largest product of 1-D factors over the three component windows
+    double best = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      double p = 1.0;
+      for (int b = 0; b < 3; ++b) {
+        const int sl = win_slot(m, b, b == c);
+        double mx = 0.0;
+        for (int d = 0; d < len[sl]; ++d) mx = fmax(mx, (double)w[(size_t)sl * kMaxWin + d]);
+        p *= mx;
+      }
+      best = fmax(best, p);
+    }
+    r.wmax = (float)(best * (1.0 + 1e-6));
+    r.pad = 0;
+  }
+}
+
 // Partial gather of component c for emitter e by one lane: the lane owns
 // (y,z) window rows lane, lane+64, ... and sums along x.
 template <typename T>
 __device__ __forceinline__ double gather_rows(const T* Ec, const Geom& g, const WindowPtrs<T>& win,
                                               int e, int c, int lane) {
-  const size_t slot = ((size_t)e * 3 + c) * 3;
-  const int lx = win.lo[slot], ly = win.lo[slot + 1], lz = win.lo[slot + 2];
-  const int Lx = win.len[slot], Ly = win.len[slot + 1], Lz = win.len[slot + 2];
-  const T* wx = win.w + slot * kMaxWin;
-  const T* wy = wx + kMaxWin;
-  const T* wz = wy + kMaxWin;
+  const int sx = win_slot(e, 0, c == 0), sy = win_slot(e, 1, c == 1), sz = win_slot(e, 2, c == 2);
+  const int lx = win.lo[sx], ly = win.lo[sy], lz = win.lo[sz];
+  const int Lx = win.len[sx], Ly = win.len[sy], Lz = win.len[sz];
+  const T* wx = win.w + (size_t)sx * kMaxWin;
+  const T* wy = win.w + (size_t)sy * kMaxWin;
+  const T* wz = win.w + (size_t)sz * kMaxWin;
   double s = 0.0;
   for (int q = lane; q < Ly * Lz; q += 64) {
     const int dy = q % Ly, dz = q / Ly;
     const int jj = wrap_index(ly + dy, g.n[1]);
     const int kk = wrap_index(lz + dz, g.n[2]);
     const size_t row = (size_t)g.n[0] * ((size_t)jj + (size_t)g.n[1] * (size_t)kk);
-    double sx = 0.0;
+    double sx2 = 0.0;
     for (int dx = 0; dx < Lx; ++dx) {
       const int ii = wrap_index(lx + dx, g.n[0]);
-      sx += (double)wx[dx] * (double)Ec[row + ii];
+      sx2 += (double)wx[dx] * (double)Ec[row + ii];
     }
-    s += (double)wy[dy] * (double)wz[dz] * sx;
+    s += (double)wy[dy] * (double)wz[dz] * sx2;
   }
   return s;
-}
-
-// Exact two-level step for one emitter; returns the new state and mu_dot.
-__device__ __forceinline__ void tls_advance(double w0, const double d[3], const double et[3],
-                                            double dt, double st[3], double md[3]) {
-  const double gg = et[0] * d[0] + et[1] * d[1] + et[2] * d[2];
-  const double hx = -gg, hz = -0.5 * w0;
-  const double om = sqrt(hx * hx + hz * hz);
-  const double p = st[0];
-  const double rx = 2.0 * st[1], ry = -2.0 * st[2];
-  double rx2 = rx, ry2 = ry, p2 = p;
-  if (om > 0.0) {
-    const double th = 2.0 * om * dt;
-    const double kx = hx / om, kz = hz / om;
-    const double c = cos(th), s = sin(th);
-    const double sh = sin(0.5 * th);
-    const double omc = 2.0 * sh * sh;  // 1 - cos(th) without cancellation
-    const double rz = 1.0 - 2.0 * p;
-    const double kr = kx * rx + kz * rz;
-    rx2 = rx * c - kz * ry * s + kx * kr * omc;
-    ry2 = ry * c + (kz * rx - kx * rz) * s;
-    // rho11' = (1 - rz')/2 written so that no O(1) terms cancel
-    p2 = 0.5 * (omc * (kx * kx - kx * kz * rx + 2.0 * kz * kz * p) + 2.0 * p * c - kx * ry * s);
-  }
-  st[0] = p2;
-  st[1] = 0.5 * rx2;
-  st[2] = -0.5 * ry2;
-  const double f = w0 * ry2;  // -2 w0 Im(rho01)
-  md[0] = f * d[0];
-  md[1] = f * d[1];
-  md[2] = f * d[2];
 }
 
 // One wavefront per two-level emitter: gather E~ from E^n, advance
@@ -183,12 +193,12 @@ __global__ __launch_bounds__(256) void k_scatter_atomic(FieldPtrs<T> f, Geom g, 
   for (int c = 0; c < 3; ++c) {
     const double amp = g.dt * win.gamma[e] * mudot[3 * e + c] * vol;
     if (amp == 0.0) continue;
-    const size_t slot = ((size_t)e * 3 + c) * 3;
-    const int lx = win.lo[slot], ly = win.lo[slot + 1], lz = win.lo[slot + 2];
-    const int Lx = win.len[slot], Ly = win.len[slot + 1], Lz = win.len[slot + 2];
-    const T* wx = win.w + slot * kMaxWin;
-    const T* wy = wx + kMaxWin;
-    const T* wz = wy + kMaxWin;
+    const int sx = win_slot(e, 0, c == 0), sy = win_slot(e, 1, c == 1), sz = win_slot(e, 2, c == 2);
+    const int lx = win.lo[sx], ly = win.lo[sy], lz = win.lo[sz];
+    const int Lx = win.len[sx], Ly = win.len[sy], Lz = win.len[sz];
+    const T* wx = win.w + (size_t)sx * kMaxWin;
+    const T* wy = win.w + (size_t)sy * kMaxWin;
+    const T* wz = win.w + (size_t)sz * kMaxWin;
     T* Ec = f.E[c];
     for (int q = lane; q < Ly * Lz; q += 64) {
       const int dy = q % Ly, dz = q / Ly;
@@ -206,24 +216,40 @@ __global__ __launch_bounds__(256) void k_scatter_atomic(FieldPtrs<T> f, Geom g, 
 }
 
 template <typename T>
-static hipError_t launch_windows(int count, int first, const double* pos, const double* sigma,
-                                 double R, const Geom& g, int* lo, int* len, T* w,
-                                 hipStream_t st) {
+static hipError_t launch_windows(int count, const double* pos, const double* sigma, double R,
+                                 const Geom& g, int* lo, int* len, T* w, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   const int threads = 256;
-  const int blocks = (count * 9 + threads - 1) / threads;
-  hipLaunchKernelGGL(k_windows<T>, dim3(blocks), dim3(threads), 0, st, count, first, pos, sigma,
-                     R, g, lo, len, w);
+  const int blocks = (count * 6 + threads - 1) / threads;
+  hipLaunchKernelGGL(k_windows<T>, dim3(blocks), dim3(threads), 0, st, count, pos, sigma, R, g,
+                     lo, len, w);
   return hipGetLastError();
 }
 
-hipError_t windows_f64(int count, int first, const double* pos, const double* sigma, double R,
-                       const Geom& g, int* lo, int* len, double* w, hipStream_t st) {
-  return launch_windows<double>(count, first, pos, sigma, R, g, lo, len, w, st);
+hipError_t windows_f64(int count, const double* pos, const double* sigma, double R, const Geom& g,
+                       int* lo, int* len, double* w, hipStream_t st) {
+  return launch_windows<double>(count, pos, sigma, R, g, lo, len, w, st);
 }
-hipError_t windows_f32(int count, int first, const double* pos, const double* sigma, double R,
-                       const Geom& g, int* lo, int* len, float* w, hipStream_t st) {
-  return launch_windows<float>(count, first, pos, sigma, R, g, lo, len, w, st);
+
+template <typename T>
+static hipError_t launch_records(int count, const int* lo, const int* len, const T* w,
+                                 WinRec<T>* rec, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_records<T>, dim3((count * 6 + 255) / 256), dim3(256), 0, st, count, lo, len,
+                     w, rec);
+  return hipGetLastError();
+}
+hipError_t records_f64(int count, const int* lo, const int* len, const double* w,
+                       WinRec<double>* rec, hipStream_t st) {
+  return launch_records<double>(count, lo, len, w, rec, st);
+}
+hipError_t records_f32(int count, const int* lo, const int* len, const float* w,
+                       WinRec<float>* rec, hipStream_t st) {
+  return launch_records<float>(count, lo, len, w, rec, st);
+}
+hipError_t windows_f32(int count, const double* pos, const double* sigma, double R, const Geom& g,
+                       int* lo, int* len, float* w, hipStream_t st) {
+  return launch_windows<float>(count, pos, sigma, R, g, lo, len, w, st);
 }
 
 template <typename T>

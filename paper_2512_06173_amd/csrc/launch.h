@@ -16,10 +16,14 @@ hipError_t sweep_plain_f64(const FieldPtrs<double>& f, const Geom& g, const Sour
 hipError_t sweep_plain_f32(const FieldPtrs<float>& f, const Geom& g, const SourceSet& src,
                            const int64_t* step, hipStream_t st);
 
-hipError_t windows_f64(int count, int first, const double* pos, const double* sigma, double R,
-                       const Geom& g, int* lo, int* len, double* w, hipStream_t st);
-hipError_t windows_f32(int count, int first, const double* pos, const double* sigma, double R,
-                       const Geom& g, int* lo, int* len, float* w, hipStream_t st);
+hipError_t windows_f64(int count, const double* pos, const double* sigma, double R, const Geom& g,
+                       int* lo, int* len, double* w, hipStream_t st);
+hipError_t windows_f32(int count, const double* pos, const double* sigma, double R, const Geom& g,
+                       int* lo, int* len, float* w, hipStream_t st);
+hipError_t records_f64(int count, const int* lo, const int* len, const double* w,
+                       WinRec<double>* rec, hipStream_t st);
+hipError_t records_f32(int count, const int* lo, const int* len, const float* w,
+                       WinRec<float>* rec, hipStream_t st);
 hipError_t tls_step_f64(const FieldPtrs<double>& f, const Geom& g, const WindowPtrs<double>& win,
                         const TlsPtrs& tls, double* Et, double* mudot, const int64_t* pop_off,
                         const Series& ser, const int64_t* step, hipStream_t st);
@@ -41,5 +45,22 @@ hipError_t finish_f64(const FieldPtrs<double>& f, const Geom& g, const FluxPlane
                       const Series& ser, int64_t* step, hipStream_t st);
 hipError_t finish_f32(const FieldPtrs<float>& f, const Geom& g, const FluxPlane& fp,
                       const Series& ser, int64_t* step, hipStream_t st);
+
+hipError_t bin_gather_step_f64(const FieldPtrs<double>& f, const Geom& g, const BinPtrs& b,
+                               const WindowPtrs<double>& win, const TlsPtrs& tls,
+                               const int* tls_slot, double* Et, double* mudot,
+                               const int64_t* pop_off, const Series& ser, const int64_t* step,
+                               hipStream_t st);
+hipError_t bin_gather_step_f32(const FieldPtrs<float>& f, const Geom& g, const BinPtrs& b,
+                               const WindowPtrs<float>& win, const TlsPtrs& tls,
+                               const int* tls_slot, double* Et, double* mudot,
+                               const int64_t* pop_off, const Series& ser, const int64_t* step,
+                               hipStream_t st);
+hipError_t bin_scatter_f64(const FieldPtrs<double>& f, const Geom& g, const BinPtrs& b,
+                           const WindowPtrs<double>& win, const double* mudot, hipStream_t st);
+hipError_t bin_scatter_f32(const FieldPtrs<float>& f, const Geom& g, const BinPtrs& b,
+                           const WindowPtrs<float>& win, const double* mudot, hipStream_t st);
+// bin edge lengths (cells) of the gather (G) and scatter (S) bins for a field precision
+void bin_shape(bool fp32, int G[3], int S[3]);
 
 }  // namespace mlk

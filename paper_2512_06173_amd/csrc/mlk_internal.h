@@ -8,7 +8,8 @@
 
 namespace mlk {
 
-constexpr int kMaxWin = 12;     // kernel window points per axis (R*sigma <= 5.5 cells)
+constexpr int kMaxWin = 8;      // kernel window points per axis (R*sigma <= 3.5 cells)
+constexpr int kHalo = 4;        // reach of a window beyond its centre cell (R*sigma + 1/2)
 constexpr int kMaxSources = 8;  // soft sources per simulation
 constexpr int kMaxLevels = 6;   // multilevel emitters: 2..6 levels
 
@@ -79,15 +80,36 @@ struct SourceSet {
   Source s[kMaxSources];
 };
 
-// Emitter tables (structure of arrays).  Window data per emitter m,
-// component c, axis a at [(m*3 + c)*3 + a].
+// Kernel windows of the emitters.  For emitter m, axis a and position variant v
+// (v = 0: integer positions, v = 1: half-integer positions; component c uses
+// v = 1 on its own axis and v = 0 on the others), slot q = m*6 + 2a + v holds
+// the first (unwrapped) index lo[q], the length len[q] <= kMaxWin and the
+// normalised 1-D weights w[q*kMaxWin ...].
+// The same window in the form the binned kernels stage in LDS.  Per axis the
+// union of the two position variants starts at org[a] and spans n[a] <= kMaxWin
+// points (the integer points of [r - R sigma - 1/2, r + R sigma]); wr[a][v][d] is
+// the weight of variant v at point org[a] + d, zero outside that variant's
+// window, so loops over the union need no bounds checks.
+template <typename T>
+struct alignas(16) WinRec {
+  int org[3];
+  int n[3];
+  float wmax;  // largest 3-D weight of any component's window
+  int pad;
+  T wr[3][2][kMaxWin];
+};
+
 template <typename T>
 struct WindowPtrs {
-  const int* lo;     // first (unwrapped) index of the window
-  const int* len;    // number of points
-  const T* w;        // normalised 1-D weights, kMaxWin per (m, c, a)
+  const int* lo;
+  const int* len;
+  const T* w;
   const double* gamma;
+  const WinRec<T>* rec;  // [M]
 };
+
+__host__ __device__ inline int win_slot(int m, int a, int v) { return m * 6 + 2 * a + v; }
+
 
 struct TlsPtrs {
   int count;
@@ -131,6 +153,22 @@ struct FluxPlane {
   int nblocks;
   double* series;   // [cap]
   double* total;    // running dt * sum F
+};
+
+// Binned emitter phase.
+// Gather bins: every emitter belongs to the bin of its centre cell; the
+// workgroup of a bin stages the bin plus a halo of kHalo cells.
+// Scatter bins: every (bin, emitter) pair whose window touches the bin.
+struct BinPtrs {
+  int nbx, nby, nbz;        // scatter bins per axis
+  int ngather;              // gather bins holding at least one centre
+  const int* gbin_org;      // [3*ngather] bin origin in unwrapped cells (centre-cell frame)
+  const int* gbin_start;    // [ngather+1] CSR into gbin_em
+  const int* gbin_em;       // emitter ids
+  int nscatter;             // scatter bins touched by at least one window
+  const int* sbin_id;       // [nscatter]
+  const int* sbin_start;    // [nscatter+1] CSR into sbin_em
+  const int* sbin_em;       // emitter id of each pair
 };
 
 }  // namespace mlk

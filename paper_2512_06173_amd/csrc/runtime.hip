@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <climits>
 #include <string>
 #include <vector>
 
@@ -90,6 +91,7 @@ struct mlk_sim {
   int* d_wlo = nullptr;
   int* d_wlen = nullptr;
   void* d_w = nullptr;
+  void* d_rec = nullptr;  // WinRec<T>[M]
   double* d_pos = nullptr;
   double* d_sigma = nullptr;
   double* d_gamma = nullptr;
@@ -100,6 +102,16 @@ struct mlk_sim {
   double* d_tls_w0 = nullptr;
   double* d_tls_dip = nullptr;
   double* d_tls_rho = nullptr;
+  // binned emitter phase
+  int nbx = 0, nby = 0, nbz = 0;
+  int ngather = 0, nscatter = 0;
+  int* d_gbin_org = nullptr;
+  int* d_gbin_start = nullptr;
+  int* d_gbin_em = nullptr;
+  int* d_sbin_id = nullptr;
+  int* d_sbin_start = nullptr;
+  int* d_sbin_em = nullptr;
+  int* d_tls_slot = nullptr;
 
   SourceSet src{};
 
@@ -153,6 +165,7 @@ WindowPtrs<T> window_ptrs(const mlk_sim* s) {
   w.len = s->d_wlen;
   w.w = (const T*)s->d_w;
   w.gamma = s->d_gamma;
+  w.rec = (const WinRec<T>*)s->d_rec;
   return w;
 }
 
@@ -213,6 +226,121 @@ mlk_status upload(T** dptr, const std::vector<T>& v) {
   return MLK_OK;
 }
 
+BinPtrs bin_ptrs(const mlk_sim* s) {
+  BinPtrs b{};
+  b.nbx = s->nbx;
+  b.nby = s->nby;
+  b.nbz = s->nbz;
+  b.ngather = s->ngather;
+  b.gbin_org = s->d_gbin_org;
+  b.gbin_start = s->d_gbin_start;
+  b.gbin_em = s->d_gbin_em;
+  b.nscatter = s->nscatter;
+  b.sbin_id = s->d_sbin_id;
+  b.sbin_start = s->d_sbin_start;
+  b.sbin_em = s->d_sbin_em;
+  return b;
+}
+
+// Emitter bins (index bookkeeping only).  Gather bins group emitters by the
+// bin of their centre cell; scatter bins list, for every bin, the emitters
+// whose windows (as computed on the device) touch it.
+mlk_status build_bins(mlk_sim* s) {
+  const Geom& g = s->g;
+  int G[3], B[3];
+  bin_shape(s->fp32, G, B);
+  int nb[3];
+  for (int a = 0; a < 3; ++a) nb[a] = (g.n[a] + B[a] - 1) / B[a];
+  s->nbx = nb[0];
+  s->nby = nb[1];
+  s->nbz = nb[2];
+  const int M = s->nem;
+  std::vector<int> lo((size_t)M * 6), len((size_t)M * 6);
+  HIPCHK(hipMemcpy(lo.data(), s->d_wlo, lo.size() * sizeof(int), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(len.data(), s->d_wlen, len.size() * sizeof(int), hipMemcpyDeviceToHost));
+
+  // gather: key = bin of the (unwrapped) centre cell
+  struct Key {
+    int b[3];
+    int e;
+  };
+  std::vector<Key> keys(M);
+  for (int e = 0; e < M; ++e) {
+    keys[e].e = e;
+    for (int a = 0; a < 3; ++a) {
+      const int c = (int)std::floor(s->pos[3 * e + a]);
+      keys[e].b[a] = (c >= 0 ? c : c - G[a] + 1) / G[a];
+    }
+  }
+  std::stable_sort(keys.begin(), keys.end(), [](const Key& x, const Key& y) {
+    if (x.b[2] != y.b[2]) return x.b[2] < y.b[2];
+    if (x.b[1] != y.b[1]) return x.b[1] < y.b[1];
+    return x.b[0] < y.b[0];
+  });
+  std::vector<int> gorg, gstart, gem;
+  for (int q = 0; q < M; ++q) {
+    if (q == 0 || keys[q].b[0] != keys[q - 1].b[0] || keys[q].b[1] != keys[q - 1].b[1] ||
+        keys[q].b[2] != keys[q - 1].b[2]) {
+      gstart.push_back(q);
+      for (int a = 0; a < 3; ++a) gorg.push_back(keys[q].b[a] * G[a]);
+    }
+    gem.push_back(keys[q].e);
+  }
+  gstart.push_back(M);
+  s->ngather = (int)gstart.size() - 1;
+
+  // scatter: bins touched by the union of each emitter's windows
+  const size_t nball = (size_t)nb[0] * nb[1] * nb[2];
+  std::vector<std::vector<int>> per_em(M);
+  for (int e = 0; e < M; ++e) {
+    std::vector<int> ax[3];
+    for (int a = 0; a < 3; ++a) {
+      const int s0 = win_slot(e, a, 0), s1 = win_slot(e, a, 1);
+      const int u0 = std::min(lo[s0], lo[s1]);
+      const int u1 = std::max(lo[s0] + len[s0], lo[s1] + len[s1]);
+      for (int q = u0; q < u1; ++q) {
+        int w = q % g.n[a];
+        if (w < 0) w += g.n[a];
+        const int bq = w / B[a];
+        if (std::find(ax[a].begin(), ax[a].end(), bq) == ax[a].end()) ax[a].push_back(bq);
+      }
+    }
+    for (int bz : ax[2])
+      for (int by : ax[1])
+        for (int bx : ax[0]) per_em[e].push_back(bx + nb[0] * (by + nb[1] * bz));
+  }
+  std::vector<int> count(nball, 0);
+  size_t npairs = 0;
+  for (int e = 0; e < M; ++e)
+    for (int b : per_em[e]) {
+      ++count[b];
+      ++npairs;
+    }
+  if (npairs > (size_t)INT32_MAX) return fail(MLK_EUNSUPPORTED, "too many emitter-bin pairs");
+  std::vector<int> sid, sstart(1, 0), slot_of(nball, -1);
+  for (size_t b = 0; b < nball; ++b)
+    if (count[b]) {
+      slot_of[b] = (int)sid.size();
+      sid.push_back((int)b);
+      sstart.push_back(sstart.back() + count[b]);
+    }
+  std::vector<int> fill(sstart.begin(), sstart.end() - 1), sem(npairs);
+  // emitters in gather order, so neighbouring pairs touch neighbouring windows
+  for (int q = 0; q < M; ++q) {
+    const int e = gem[q];
+    for (int b : per_em[e]) sem[fill[slot_of[b]]++] = e;
+  }
+  s->nscatter = (int)sid.size();
+  STCHK(upload(&s->d_gbin_org, gorg));
+  STCHK(upload(&s->d_gbin_start, gstart));
+  STCHK(upload(&s->d_gbin_em, gem));
+  STCHK(upload(&s->d_sbin_id, sid));
+  STCHK(upload(&s->d_sbin_start, sstart));
+  STCHK(upload(&s->d_sbin_em, sem));
+  STCHK(upload(&s->d_tls_slot, s->tls_slot));
+  return MLK_OK;
+}
+
 // Rebuild every device emitter table from the host mirror (set-up only).
 mlk_status rebuild_emitters(mlk_sim* s) {
   HIPCHK(hipStreamSynchronize(s->stream));
@@ -231,21 +359,31 @@ mlk_status rebuild_emitters(mlk_sim* s) {
   dfree(s->d_w);
   dfree(s->d_Et);
   dfree(s->d_mudot);
-  HIPCHK(dalloc(&s->d_wlo, (size_t)M * 9 * sizeof(int)));
-  HIPCHK(dalloc(&s->d_wlen, (size_t)M * 9 * sizeof(int)));
-  HIPCHK(dalloc(&s->d_w, (size_t)M * 9 * kMaxWin * s->esz));
+  HIPCHK(dalloc(&s->d_wlo, (size_t)M * 6 * sizeof(int)));
+  HIPCHK(dalloc(&s->d_wlen, (size_t)M * 6 * sizeof(int)));
+  HIPCHK(dalloc(&s->d_w, (size_t)M * 6 * kMaxWin * s->esz));
   HIPCHK(dalloc(&s->d_Et, (size_t)M * 3 * sizeof(double)));
   HIPCHK(dalloc(&s->d_mudot, (size_t)M * 3 * sizeof(double)));
   HIPCHK(hipMemset(s->d_Et, 0, (size_t)M * 3 * sizeof(double)));
   HIPCHK(hipMemset(s->d_mudot, 0, (size_t)M * 3 * sizeof(double)));
   if (s->fp32)
-    HIPCHK(windows_f32(M, 0, s->d_pos, s->d_sigma, s->desc.window_r, s->g, s->d_wlo, s->d_wlen,
+    HIPCHK(windows_f32(M, s->d_pos, s->d_sigma, s->desc.window_r, s->g, s->d_wlo, s->d_wlen,
                        (float*)s->d_w, s->stream));
   else
-    HIPCHK(windows_f64(M, 0, s->d_pos, s->d_sigma, s->desc.window_r, s->g, s->d_wlo, s->d_wlen,
+    HIPCHK(windows_f64(M, s->d_pos, s->d_sigma, s->desc.window_r, s->g, s->d_wlo, s->d_wlen,
                        (double*)s->d_w, s->stream));
+  dfree(s->d_rec);
+  if (s->fp32) {
+    HIPCHK(dalloc(&s->d_rec, (size_t)M * sizeof(WinRec<float>)));
+    HIPCHK(records_f32(M, s->d_wlo, s->d_wlen, (const float*)s->d_w, (WinRec<float>*)s->d_rec,
+                       s->stream));
+  } else {
+    HIPCHK(dalloc(&s->d_rec, (size_t)M * sizeof(WinRec<double>)));
+    HIPCHK(records_f64(M, s->d_wlo, s->d_wlen, (const double*)s->d_w, (WinRec<double>*)s->d_rec,
+                       s->stream));
+  }
   HIPCHK(hipStreamSynchronize(s->stream));
-  return MLK_OK;
+  return build_bins(s);
 }
 
 // Grow the on-device series buffers so that nsteps more steps fit.
@@ -308,10 +446,27 @@ mlk_status enqueue_steps(mlk_sim* s, int64_t nsteps) {
   tls.dip = s->d_tls_dip;
   tls.rho = s->d_tls_rho;
   constexpr bool f32 = sizeof(T) == 4;
+  const bool binned = s->desc.scatter == MLK_SCATTER_OWNER && s->nem > 0;
+  const BinPtrs bins = bin_ptrs(s);
   for (int64_t q = 0; q < nsteps; ++q) {
     if (s->fp.on) {
       if constexpr (f32) HIPCHK(flux_save_f32(f, s->g, s->fp, s->stream));
       else HIPCHK(flux_save_f64(f, s->g, s->fp, s->stream));
+    }
+    if (binned) {
+      if constexpr (f32)
+        HIPCHK(bin_gather_step_f32(f, s->g, bins, win, tls, s->d_tls_slot, s->d_Et, s->d_mudot,
+                                   s->d_popoff, ser, s->d_step, s->stream));
+      else
+        HIPCHK(bin_gather_step_f64(f, s->g, bins, win, tls, s->d_tls_slot, s->d_Et, s->d_mudot,
+                                   s->d_popoff, ser, s->d_step, s->stream));
+      if constexpr (f32) HIPCHK(sweep_plain_f32(f, s->g, s->src, s->d_step, s->stream));
+      else HIPCHK(sweep_plain_f64(f, s->g, s->src, s->d_step, s->stream));
+      if constexpr (f32) HIPCHK(bin_scatter_f32(f, s->g, bins, win, s->d_mudot, s->stream));
+      else HIPCHK(bin_scatter_f64(f, s->g, bins, win, s->d_mudot, s->stream));
+      if constexpr (f32) HIPCHK(finish_f32(f, s->g, s->fp, ser, s->d_step, s->stream));
+      else HIPCHK(finish_f64(f, s->g, s->fp, ser, s->d_step, s->stream));
+      continue;
     }
     if (tls.count > 0) {
       if constexpr (f32)
@@ -349,6 +504,7 @@ void release(mlk_sim* s) {
   dfree(s->d_wlo);
   dfree(s->d_wlen);
   dfree(s->d_w);
+  dfree(s->d_rec);
   dfree(s->d_pos);
   dfree(s->d_sigma);
   dfree(s->d_gamma);
@@ -359,6 +515,13 @@ void release(mlk_sim* s) {
   dfree(s->d_tls_w0);
   dfree(s->d_tls_dip);
   dfree(s->d_tls_rho);
+  dfree(s->d_gbin_org);
+  dfree(s->d_gbin_start);
+  dfree(s->d_gbin_em);
+  dfree(s->d_sbin_id);
+  dfree(s->d_sbin_start);
+  dfree(s->d_sbin_em);
+  dfree(s->d_tls_slot);
   dfree(s->d_probe);
   dfree(s->d_flux_series);
   dfree(s->fp.Eu0);
@@ -419,7 +582,7 @@ void mlk_grid_desc_init(mlk_grid_desc* g) {
   g->stream = nullptr;
   g->device = 0;
   g->sweep = MLK_SWEEP_PLAIN;
-  g->scatter = MLK_SCATTER_ATOMIC;
+  g->scatter = MLK_SCATTER_OWNER;
 }
 
 const char* mlk_last_error(void) { return g_err.c_str(); }
