@@ -11,10 +11,23 @@ hipError_t inverse_to(bool fp32, const double* src, void* dst, size_t n, hipStre
 hipError_t convert_in(bool fp32, const double* src, void* dst, size_t n, hipStream_t st);
 hipError_t convert_out(bool fp32, const void* src, double* dst, size_t n, hipStream_t st);
 
-hipError_t sweep_plain_f64(const FieldPtrs<double>& f, const Geom& g, const SourceSet& src,
-                           const int64_t* step, hipStream_t st);
-hipError_t sweep_plain_f32(const FieldPtrs<float>& f, const Geom& g, const SourceSet& src,
-                           const int64_t* step, hipStream_t st);
+hipError_t sweep_plain_f64(const FieldPtrs<double>& in, const FieldPtrs<double>& out,
+                           const Geom& g, const Box* boxes, int nbox, bool h_pass, bool e_pass,
+                           hipStream_t st);
+hipError_t sweep_plain_f32(const FieldPtrs<float>& in, const FieldPtrs<float>& out, const Geom& g,
+                           const Box* boxes, int nbox, bool h_pass, bool e_pass, hipStream_t st);
+hipError_t sweep_shell_f64(const FieldPtrs<double>& in, const FieldPtrs<double>& out,
+                           const Geom& g, const Box& inner, bool h_pass, hipStream_t st);
+hipError_t sweep_shell_f32(const FieldPtrs<float>& in, const FieldPtrs<float>& out, const Geom& g,
+                           const Box& inner, bool h_pass, hipStream_t st);
+hipError_t sources_f64(const FieldPtrs<double>& f, const Geom& g, const SourceSet& src,
+                       const int64_t* step, hipStream_t st);
+hipError_t sources_f32(const FieldPtrs<float>& f, const Geom& g, const SourceSet& src,
+                       const int64_t* step, hipStream_t st);
+hipError_t sweep_fused_f64(const FieldPtrs<double>& a, const FieldPtrs<double>& b, const Geom& g,
+                           const Box& box, int kz, hipStream_t st);
+hipError_t sweep_fused_f32(const FieldPtrs<float>& a, const FieldPtrs<float>& b, const Geom& g,
+                           const Box& box, int kz, hipStream_t st);
 
 hipError_t windows_f64(int count, const double* pos, const double* sigma, double R, const Geom& g,
                        int* lo, int* len, double* w, hipStream_t st);

@@ -25,6 +25,15 @@ struct Geom {
   double dx;
 };
 
+// Workgroup barrier that orders LDS only: global loads in flight (prefetches)
+// stay in flight across it, unlike __syncthreads(), whose fence also waits for
+// every outstanding global memory operation.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __host__ __device__ inline size_t cell_index(const Geom& g, int i, int j, int k) {
   return (size_t)i + (size_t)g.n[0] * ((size_t)j + (size_t)g.n[1] * (size_t)k);
 }
@@ -55,17 +64,58 @@ __host__ __device__ inline size_t psi_size(const Geom& g, int a) {
   return s;
 }
 
-// Field storage of one precision.
+// Field storage of one precision.  All CPML psi arrays of a field buffer live
+// in one allocation (see psi_offset) and all CPML coefficient tables in another
+// (see tab_offset), so a kernel needs two pointers for them.
 template <typename T>
 struct FieldPtrs {
   T* E[3];
   T* H[3];
   const T* epsinv;
-  T* psiE[3][3];  // [E component][derivative axis], null when that axis has no CPML
-  T* psiH[3][3];
-  const T* cb[3][2];  // CPML tables per axis: [0] integer positions, [1] half-integer
-  const T* cc[3][2];
-  const T* ck[3][2];
+  T* psi;
+  const T* tab;
+};
+
+__host__ __device__ inline bool has_cpml(const Geom& g, int a) { return g.nlo[a] + g.nhi[a] > 0; }
+
+// psi arrays: for each axis a with a CPML, in axis order, four arrays of
+// psi_size(g, a) values: E of the lower-numbered other component, E of the
+// higher, then H of the lower and of the higher.  field: 0 = E, 1 = H.
+__host__ __device__ inline size_t psi_offset(const Geom& g, int field, int c, int a) {
+  size_t off = 0;
+  for (int b = 0; b < a; ++b)
+    if (has_cpml(g, b)) off += 4 * psi_size(g, b);
+  const int lower = a == 0 ? 1 : 0;
+  return off + (size_t)(2 * field + (c == lower ? 0 : 1)) * psi_size(g, a);
+}
+
+__host__ __device__ inline size_t psi_total(const Geom& g) {
+  size_t t = 0;
+  for (int a = 0; a < 3; ++a)
+    if (has_cpml(g, a)) t += 4 * psi_size(g, a);
+  return t;
+}
+
+// CPML tables: for each axis with a CPML, in axis order, b, c and 1/kappa, each
+// at the n integer positions then the n half-integer positions.
+__host__ __device__ inline size_t tab_offset(const Geom& g, int a) {
+  size_t off = 0;
+  for (int b = 0; b < a; ++b)
+    if (has_cpml(g, b)) off += 6 * (size_t)g.n[b];
+  return off;
+}
+
+__host__ __device__ inline size_t tab_total(const Geom& g) {
+  size_t t = 0;
+  for (int a = 0; a < 3; ++a)
+    if (has_cpml(g, a)) t += 6 * (size_t)g.n[a];
+  return t;
+}
+
+// Half-open box of cells [lo, hi) per axis.
+struct Box {
+  int lo[3];
+  int hi[3];
 };
 
 struct Source {

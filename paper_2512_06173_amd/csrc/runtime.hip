@@ -72,12 +72,15 @@ struct mlk_sim {
   hipStream_t stream = nullptr;
   bool own_stream = false;
 
-  void* E[3] = {};
+  void* E[3] = {};  // current fields
   void* H[3] = {};
+  void* E2[3] = {};  // second buffers of the fused sweep (swapped every step)
+  void* H2[3] = {};
+  void* psi2 = nullptr;
+  int kz = 0;       // z planes per workgroup of the fused sweep
   void* epsinv = nullptr;
-  void* psiE[3][3] = {};
-  void* psiH[3][3] = {};
-  void* tab[3] = {};  // per axis: b, c, 1/kappa for integer then half positions (6 N values)
+  void* psi = nullptr;  // every CPML psi array of the current buffer (psi_offset layout)
+  void* tab = nullptr;  // CPML coefficient tables (tab_offset layout)
 
   // emitters, host mirror (by emitter id)
   int nem = 0;
@@ -135,26 +138,37 @@ struct mlk_sim {
 namespace {
 
 template <typename T>
+FieldPtrs<T> field_ptrs(const mlk_sim* s);
+
+template <typename T>
+FieldPtrs<T> spare_ptrs(const mlk_sim* s) {
+  FieldPtrs<T> f = field_ptrs<T>(s);
+  for (int c = 0; c < 3; ++c) {
+    f.E[c] = (T*)s->E2[c];
+    f.H[c] = (T*)s->H2[c];
+  }
+  f.psi = (T*)s->psi2;
+  return f;
+}
+
+void swap_buffers(mlk_sim* s) {
+  for (int c = 0; c < 3; ++c) {
+    std::swap(s->E[c], s->E2[c]);
+    std::swap(s->H[c], s->H2[c]);
+  }
+  std::swap(s->psi, s->psi2);
+}
+
+template <typename T>
 FieldPtrs<T> field_ptrs(const mlk_sim* s) {
   FieldPtrs<T> f{};
   for (int c = 0; c < 3; ++c) {
     f.E[c] = (T*)s->E[c];
     f.H[c] = (T*)s->H[c];
-    for (int a = 0; a < 3; ++a) {
-      f.psiE[c][a] = (T*)s->psiE[c][a];
-      f.psiH[c][a] = (T*)s->psiH[c][a];
-    }
   }
   f.epsinv = (const T*)s->epsinv;
-  for (int a = 0; a < 3; ++a) {
-    const T* t = (const T*)s->tab[a];
-    const int N = s->g.n[a];
-    for (int h = 0; h < 2; ++h) {
-      f.cb[a][h] = t ? t + 0 * 2 * N + h * N : nullptr;
-      f.cc[a][h] = t ? t + 1 * 2 * N + h * N : nullptr;
-      f.ck[a][h] = t ? t + 2 * 2 * N + h * N : nullptr;
-    }
-  }
+  f.psi = (T*)s->psi;
+  f.tab = (const T*)s->tab;
   return f;
 }
 
@@ -434,9 +448,53 @@ mlk_status reserve_series(mlk_sim* s, int64_t nsteps) {
   return MLK_OK;
 }
 
+// Interior box of the fused sweep: the cells whose own update and recomputed
+// halo avoid every CPML layer (one cell of margin above the low layers).  The
+// cells outside it form the CPML shell.
+Box interior_box(const Geom& g) {
+  Box inner{};
+  for (int a = 0; a < 3; ++a) {
+    inner.lo[a] = g.nlo[a] > 0 ? g.nlo[a] + 1 : 0;
+    inner.hi[a] = g.n[a] - g.nhi[a];
+    if (inner.hi[a] < inner.lo[a]) inner.hi[a] = inner.lo[a];
+  }
+  return inner;
+}
+
+template <typename T>
+mlk_status sweep(mlk_sim* s) {
+  constexpr bool f32 = sizeof(T) == 4;
+  const FieldPtrs<T> f = field_ptrs<T>(s);
+  if (s->desc.sweep == MLK_SWEEP_FUSED) {
+    const FieldPtrs<T> nf = spare_ptrs<T>(s);
+    const Box inner = interior_box(s->g);
+    if constexpr (f32) {
+      HIPCHK(sweep_fused_f32(f, nf, s->g, inner, s->kz, s->stream));
+      HIPCHK(sweep_shell_f32(f, nf, s->g, inner, true, s->stream));
+      HIPCHK(sweep_shell_f32(f, nf, s->g, inner, false, s->stream));
+    } else {
+      HIPCHK(sweep_fused_f64(f, nf, s->g, inner, s->kz, s->stream));
+      HIPCHK(sweep_shell_f64(f, nf, s->g, inner, true, s->stream));
+      HIPCHK(sweep_shell_f64(f, nf, s->g, inner, false, s->stream));
+    }
+    swap_buffers(s);
+  } else {
+    Box all{};
+    for (int a = 0; a < 3; ++a) {
+      all.lo[a] = 0;
+      all.hi[a] = s->g.n[a];
+    }
+    if constexpr (f32) HIPCHK(sweep_plain_f32(f, f, s->g, &all, 1, true, true, s->stream));
+    else HIPCHK(sweep_plain_f64(f, f, s->g, &all, 1, true, true, s->stream));
+  }
+  const FieldPtrs<T> cur = field_ptrs<T>(s);
+  if constexpr (f32) HIPCHK(sources_f32(cur, s->g, s->src, s->d_step, s->stream));
+  else HIPCHK(sources_f64(cur, s->g, s->src, s->d_step, s->stream));
+  return MLK_OK;
+}
+
 template <typename T>
 mlk_status enqueue_steps(mlk_sim* s, int64_t nsteps) {
-  const FieldPtrs<T> f = field_ptrs<T>(s);
   const WindowPtrs<T> win = window_ptrs<T>(s);
   const Series ser = series_of(s);
   TlsPtrs tls{};
@@ -449,6 +507,7 @@ mlk_status enqueue_steps(mlk_sim* s, int64_t nsteps) {
   const bool binned = s->desc.scatter == MLK_SCATTER_OWNER && s->nem > 0;
   const BinPtrs bins = bin_ptrs(s);
   for (int64_t q = 0; q < nsteps; ++q) {
+    FieldPtrs<T> f = field_ptrs<T>(s);
     if (s->fp.on) {
       if constexpr (f32) HIPCHK(flux_save_f32(f, s->g, s->fp, s->stream));
       else HIPCHK(flux_save_f64(f, s->g, s->fp, s->stream));
@@ -460,15 +519,7 @@ mlk_status enqueue_steps(mlk_sim* s, int64_t nsteps) {
       else
         HIPCHK(bin_gather_step_f64(f, s->g, bins, win, tls, s->d_tls_slot, s->d_Et, s->d_mudot,
                                    s->d_popoff, ser, s->d_step, s->stream));
-      if constexpr (f32) HIPCHK(sweep_plain_f32(f, s->g, s->src, s->d_step, s->stream));
-      else HIPCHK(sweep_plain_f64(f, s->g, s->src, s->d_step, s->stream));
-      if constexpr (f32) HIPCHK(bin_scatter_f32(f, s->g, bins, win, s->d_mudot, s->stream));
-      else HIPCHK(bin_scatter_f64(f, s->g, bins, win, s->d_mudot, s->stream));
-      if constexpr (f32) HIPCHK(finish_f32(f, s->g, s->fp, ser, s->d_step, s->stream));
-      else HIPCHK(finish_f64(f, s->g, s->fp, ser, s->d_step, s->stream));
-      continue;
-    }
-    if (tls.count > 0) {
+    } else if (tls.count > 0) {
       if constexpr (f32)
         HIPCHK(tls_step_f32(f, s->g, win, tls, s->d_Et, s->d_mudot, s->d_popoff, ser, s->d_step,
                             s->stream));
@@ -476,9 +527,12 @@ mlk_status enqueue_steps(mlk_sim* s, int64_t nsteps) {
         HIPCHK(tls_step_f64(f, s->g, win, tls, s->d_Et, s->d_mudot, s->d_popoff, ser, s->d_step,
                             s->stream));
     }
-    if constexpr (f32) HIPCHK(sweep_plain_f32(f, s->g, s->src, s->d_step, s->stream));
-    else HIPCHK(sweep_plain_f64(f, s->g, s->src, s->d_step, s->stream));
-    if (s->nem > 0) {
+    STCHK(sweep<T>(s));
+    f = field_ptrs<T>(s);
+    if (binned) {
+      if constexpr (f32) HIPCHK(bin_scatter_f32(f, s->g, bins, win, s->d_mudot, s->stream));
+      else HIPCHK(bin_scatter_f64(f, s->g, bins, win, s->d_mudot, s->stream));
+    } else if (s->nem > 0) {
       if constexpr (f32)
         HIPCHK(scatter_atomic_f32(f, s->g, win, s->nem, s->d_mudot, s->stream));
       else
@@ -494,12 +548,12 @@ void release(mlk_sim* s) {
   for (int c = 0; c < 3; ++c) {
     dfree(s->E[c]);
     dfree(s->H[c]);
-    for (int a = 0; a < 3; ++a) {
-      dfree(s->psiE[c][a]);
-      dfree(s->psiH[c][a]);
-    }
-    dfree(s->tab[c]);
+    dfree(s->E2[c]);
+    dfree(s->H2[c]);
   }
+  dfree(s->psi);
+  dfree(s->psi2);
+  dfree(s->tab);
   dfree(s->epsinv);
   dfree(s->d_wlo);
   dfree(s->d_wlen);
@@ -544,11 +598,7 @@ std::vector<Piece> state_pieces(mlk_sim* s) {
   std::vector<Piece> v;
   for (int c = 0; c < 3; ++c) v.push_back({s->E[c], s->ncell * s->esz});
   for (int c = 0; c < 3; ++c) v.push_back({s->H[c], s->ncell * s->esz});
-  for (int c = 0; c < 3; ++c)
-    for (int a = 0; a < 3; ++a) {
-      if (s->psiE[c][a]) v.push_back({s->psiE[c][a], psi_size(s->g, a) * s->esz});
-      if (s->psiH[c][a]) v.push_back({s->psiH[c][a], psi_size(s->g, a) * s->esz});
-    }
+  if (s->psi) v.push_back({s->psi, psi_total(s->g) * s->esz});
   if (!s->tls_gid.empty()) v.push_back({s->d_tls_rho, s->tls_gid.size() * 3 * sizeof(double)});
   if (s->nem > 0) {
     v.push_back({s->d_Et, (size_t)s->nem * 3 * sizeof(double)});
@@ -581,7 +631,7 @@ void mlk_grid_desc_init(mlk_grid_desc* g) {
   g->window_r = 3.0;
   g->stream = nullptr;
   g->device = 0;
-  g->sweep = MLK_SWEEP_PLAIN;
+  g->sweep = MLK_SWEEP_FUSED;
   g->scatter = MLK_SCATTER_OWNER;
 }
 
@@ -655,9 +705,19 @@ mlk_status mlk_create(const mlk_grid_desc* gd, mlk_sim** out) {
     if (dalloc(p, bytes) != hipSuccess) return false;
     return hipMemsetAsync(*p, 0, bytes, s->stream) == hipSuccess;
   };
+  const bool fused = gd->sweep == MLK_SWEEP_FUSED;
   for (int c = 0; c < 3; ++c) {
     if (!alloc_zero(&s->E[c], s->ncell * s->esz) || !alloc_zero(&s->H[c], s->ncell * s->esz))
       return bail(fail(MLK_ENOMEM, "field allocation of %zu bytes failed", s->ncell * s->esz));
+    if (fused && (!alloc_zero(&s->E2[c], s->ncell * s->esz) ||
+                  !alloc_zero(&s->H2[c], s->ncell * s->esz)))
+      return bail(fail(MLK_ENOMEM, "field allocation of %zu bytes failed", s->ncell * s->esz));
+  }
+  {
+    // z planes per workgroup of the fused sweep: enough workgroups to fill the chip
+    const int ntile = ((n[0] + 63) / 64) * ((n[1] + 3) / 4);
+    int kz = (int)(((long long)n[2] * ntile + 2047) / 2048);
+    s->kz = std::max(8, std::min(kz, n[2]));
   }
   if (dalloc(&s->epsinv, s->ncell * s->esz) != hipSuccess)
     return bail(fail(MLK_ENOMEM, "eps allocation failed"));
@@ -674,21 +734,20 @@ mlk_status mlk_create(const mlk_grid_desc* gd, mlk_sim** out) {
     if (e != hipSuccess) return bail(fail(MLK_EDEVICE, "eps init: %s", hipGetErrorString(e)));
   }
   const double sigma_max = gd->cpml_sigma_scale * (gd->cpml_m + 1.0) / gd->dx;
-  for (int a = 0; a < 3; ++a) {
-    if (g.nlo[a] + g.nhi[a] == 0) continue;
-    for (int c = 0; c < 3; ++c) {
-      if (c == a) continue;
-      if (!alloc_zero(&s->psiE[c][a], psi_size(g, a) * s->esz) ||
-          !alloc_zero(&s->psiH[c][a], psi_size(g, a) * s->esz))
-        return bail(fail(MLK_ENOMEM, "psi allocation failed"));
-    }
-    if (dalloc(&s->tab[a], (size_t)6 * n[a] * s->esz) != hipSuccess)
+  if (psi_total(g) > 0) {
+    if (!alloc_zero(&s->psi, psi_total(g) * s->esz) ||
+        (fused && !alloc_zero(&s->psi2, psi_total(g) * s->esz)))
+      return bail(fail(MLK_ENOMEM, "psi allocation failed"));
+    if (dalloc(&s->tab, tab_total(g) * s->esz) != hipSuccess)
       return bail(fail(MLK_ENOMEM, "CPML table allocation failed"));
-    char* t = (char*)s->tab[a];
-    const size_t blk = (size_t)2 * n[a] * s->esz;
-    if (cpml_tables(s->fp32, g, a, gd->cpml_m, sigma_max, gd->cpml_kappa_max, gd->cpml_alpha_max,
-                    t, t + blk, t + 2 * blk, s->stream) != hipSuccess)
-      return bail(fail(MLK_EDEVICE, "CPML table kernel failed"));
+    for (int a = 0; a < 3; ++a) {
+      if (!has_cpml(g, a)) continue;
+      char* t = (char*)s->tab + tab_offset(g, a) * s->esz;
+      const size_t blk = (size_t)2 * n[a] * s->esz;
+      if (cpml_tables(s->fp32, g, a, gd->cpml_m, sigma_max, gd->cpml_kappa_max,
+                      gd->cpml_alpha_max, t, t + blk, t + 2 * blk, s->stream) != hipSuccess)
+        return bail(fail(MLK_EDEVICE, "CPML table kernel failed"));
+    }
   }
   if (dalloc(&s->d_step, sizeof(int64_t)) != hipSuccess)
     return bail(fail(MLK_ENOMEM, "step counter allocation failed"));

@@ -22,18 +22,24 @@ __device__ __forceinline__ T bwd(const T* a, size_t id, int q, int n, int period
   return periodic ? a[id + (size_t)(n - 1) * s] : T(0);
 }
 
-// Convolutional PML stretching of a derivative d taken along axis a:
-// psi <- b psi + c d ; d <- d / kappa + psi  (inside the layers only).
+// Convolutional PML stretching of a derivative d taken along axis a, at the
+// positions of `field` (0: E, integer positions along a; 1: H, half-integer)
+// for component c:  psi <- b psi + c d ;  d <- d / kappa + psi  (inside the
+// layers only).  psi is read from `in` and, if `out` is set, the new value is
+// stored there (the fused sweep reads one buffer and writes the other; halo
+// recomputations store nothing).
 template <typename T>
-__device__ __forceinline__ T stretch(const FieldPtrs<T>& f, const Geom& g, T* psi, int a, int half,
-                                     int i, int j, int k, T d) {
-  if (psi == nullptr) return d;
+__device__ __forceinline__ T stretch(const Geom& g, const T* tab, const T* in, T* out, int field,
+                                     int c, int a, int i, int j, int k, T d) {
+  if (!has_cpml(g, a)) return d;
   const int q = a == 0 ? i : (a == 1 ? j : k);
   if (!in_layer(g, a, q)) return d;
-  const size_t pid = psi_index(g, a, i, j, k);
-  const T p = f.cb[a][half][q] * psi[pid] + f.cc[a][half][q] * d;
-  psi[pid] = p;
-  return f.ck[a][half][q] * d + p;
+  const size_t po = psi_offset(g, field, c, a) + psi_index(g, a, i, j, k);
+  const int n = g.n[a];
+  const T* t = tab + tab_offset(g, a) + (size_t)field * n + q;
+  const T p = t[0] * in[po] + t[2 * n] * d;
+  if (out) out[po] = p;
+  return t[4 * n] * d + p;
 }
 
 // True when E component c at (i,j,k) lies on a metallic wall plane (index 0
@@ -47,35 +53,6 @@ __device__ __forceinline__ bool tangential_wall(const Geom& g, int c, int i, int
 __device__ __forceinline__ double pulse_value(const Source& s, double t) {
   const double u = t - s.t0;
   return s.amp * cos(s.omega * u) * exp(-u * u / (2.0 * s.tau * s.tau));
-}
-
-// Source current density at cell (i,j,k) for the step read from *step,
-// evaluated at t = (n + 1/2) dt; added to J[comp].
-template <typename T>
-__device__ __forceinline__ void source_current(const SourceSet& src, const Geom& g,
-                                               const int64_t* step, int i, int j, int k, T J[3]) {
-#pragma unroll
-  for (int q = 0; q < kMaxSources; ++q) {
-    if (q >= src.count) break;
-    const Source& s = src.s[q];
-    bool hit;
-    double scale;
-    if (s.kind == 0) {
-      const int pos = s.axis == 0 ? i : (s.axis == 1 ? j : k);
-      hit = pos == s.index;
-      scale = g.inv_dx;
-    } else {
-      hit = i == s.ijk[0] && j == s.ijk[1] && k == s.ijk[2];
-      scale = g.inv_dx * g.inv_dx * g.inv_dx;
-    }
-    if (hit) {
-      const double t = ((double)(*step) + 0.5) * g.dt;
-      const T v = (T)(pulse_value(s, t) * scale);
-      if (s.comp == 0) J[0] += v;
-      else if (s.comp == 1) J[1] += v;
-      else J[2] += v;
-    }
-  }
 }
 
 }  // namespace mlk

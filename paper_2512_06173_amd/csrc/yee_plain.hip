@@ -1,98 +1,265 @@
-// Plain (unfused) Yee sweeps: one pass for H, one for E, one thread per cell.
-// This is the reference GPU sweep (and the "plain" variant of the benchmark);
-// the fused single-pass sweep lives in yee_fused.hip.
+// Plain (unfused) Yee sweeps: one pass for H, one for E, one thread per cell,
+// over a box of cells.
 //
-// H^{n+1/2} = H^{n-1/2} - dt curl E^n,  E^{n+1} = E^n + (dt/eps_r)(curl H^{n+1/2} - J_src)
+// H^{n+1/2} = H^{n-1/2} - dt curl E^n,   E^{n+1} = E^n + (dt/eps_r) curl H^{n+1/2}
 // (eq. Maxwell with D = eps_r E, B = H), convolutional PML stretching of each
 // spatial derivative inside the absorbing layers, metallic (tangential E = 0)
-// or periodic closure.  The molecular current is added by the scatter pass.
+// or periodic closure.  Source and molecular currents are added by their own
+// passes.
+//
+// The passes read one field buffer (`in`) and write another (`out`); with
+// in == out they update in place, which is how the plain sweep runs on the whole
+// grid.  The fused sweep uses them, out of place, on the CPML shell: the cells
+// outside its interior box, enumerated compactly by one launch per pass.
 #include "mlk_internal.h"
 #include "yee_common.h"
 
 namespace mlk {
 
+// H^{n+1/2} at cell (i,j,k) from E^n of `in`.
 template <typename T>
-__global__ __launch_bounds__(256) void k_update_h(FieldPtrs<T> f, Geom g) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z;
-  if (i >= g.n[0] || j >= g.n[1]) return;
+__device__ __forceinline__ void update_h_cell(const FieldPtrs<T>& in, const FieldPtrs<T>& out,
+                                              const Geom& g, int i, int j, int k) {
   const size_t sx = 1, sy = (size_t)g.n[0], sz = (size_t)g.n[0] * g.n[1];
   const size_t id = cell_index(g, i, j, k);
   const T idx = (T)g.inv_dx;
-  const T ex = f.E[0][id], ey = f.E[1][id], ez = f.E[2][id];
-  T dEz_dy = (fwd(f.E[2], id, j, g.n[1], g.periodic[1], sy) - ez) * idx;
-  T dEy_dz = (fwd(f.E[1], id, k, g.n[2], g.periodic[2], sz) - ey) * idx;
-  T dEx_dz = (fwd(f.E[0], id, k, g.n[2], g.periodic[2], sz) - ex) * idx;
-  T dEz_dx = (fwd(f.E[2], id, i, g.n[0], g.periodic[0], sx) - ez) * idx;
-  T dEy_dx = (fwd(f.E[1], id, i, g.n[0], g.periodic[0], sx) - ey) * idx;
-  T dEx_dy = (fwd(f.E[0], id, j, g.n[1], g.periodic[1], sy) - ex) * idx;
-  dEz_dy = stretch(f, g, f.psiH[0][1], 1, 1, i, j, k, dEz_dy);
-  dEy_dz = stretch(f, g, f.psiH[0][2], 2, 1, i, j, k, dEy_dz);
-  dEx_dz = stretch(f, g, f.psiH[1][2], 2, 1, i, j, k, dEx_dz);
-  dEz_dx = stretch(f, g, f.psiH[1][0], 0, 1, i, j, k, dEz_dx);
-  dEy_dx = stretch(f, g, f.psiH[2][0], 0, 1, i, j, k, dEy_dx);
-  dEx_dy = stretch(f, g, f.psiH[2][1], 1, 1, i, j, k, dEx_dy);
+  const T ex = in.E[0][id], ey = in.E[1][id], ez = in.E[2][id];
+  T dEz_dy = (fwd(in.E[2], id, j, g.n[1], g.periodic[1], sy) - ez) * idx;
+  T dEy_dz = (fwd(in.E[1], id, k, g.n[2], g.periodic[2], sz) - ey) * idx;
+  T dEx_dz = (fwd(in.E[0], id, k, g.n[2], g.periodic[2], sz) - ex) * idx;
+  T dEz_dx = (fwd(in.E[2], id, i, g.n[0], g.periodic[0], sx) - ez) * idx;
+  T dEy_dx = (fwd(in.E[1], id, i, g.n[0], g.periodic[0], sx) - ey) * idx;
+  T dEx_dy = (fwd(in.E[0], id, j, g.n[1], g.periodic[1], sy) - ex) * idx;
+  dEz_dy = stretch(g, in.tab, in.psi, out.psi, 1, 0, 1, i, j, k, dEz_dy);
+  dEy_dz = stretch(g, in.tab, in.psi, out.psi, 1, 0, 2, i, j, k, dEy_dz);
+  dEx_dz = stretch(g, in.tab, in.psi, out.psi, 1, 1, 2, i, j, k, dEx_dz);
+  dEz_dx = stretch(g, in.tab, in.psi, out.psi, 1, 1, 0, i, j, k, dEz_dx);
+  dEy_dx = stretch(g, in.tab, in.psi, out.psi, 1, 2, 0, i, j, k, dEy_dx);
+  dEx_dy = stretch(g, in.tab, in.psi, out.psi, 1, 2, 1, i, j, k, dEx_dy);
   const T dt = (T)g.dt;
-  f.H[0][id] -= dt * (dEz_dy - dEy_dz);
-  f.H[1][id] -= dt * (dEx_dz - dEz_dx);
-  f.H[2][id] -= dt * (dEy_dx - dEx_dy);
+  out.H[0][id] = in.H[0][id] - dt * (dEz_dy - dEy_dz);
+  out.H[1][id] = in.H[1][id] - dt * (dEx_dz - dEz_dx);
+  out.H[2][id] = in.H[2][id] - dt * (dEy_dx - dEx_dy);
 }
 
+// E^{n+1} at cell (i,j,k); H^{n+1/2} is read from `out` (already advanced
+// everywhere), E^n from `in`.
 template <typename T>
-__global__ __launch_bounds__(256) void k_update_e(FieldPtrs<T> f, Geom g, SourceSet src,
-                                                  const int64_t* step) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z;
-  if (i >= g.n[0] || j >= g.n[1]) return;
+__device__ __forceinline__ void update_e_cell(const FieldPtrs<T>& in, const FieldPtrs<T>& out,
+                                              const Geom& g, int i, int j, int k) {
   const size_t sx = 1, sy = (size_t)g.n[0], sz = (size_t)g.n[0] * g.n[1];
   const size_t id = cell_index(g, i, j, k);
   const T idx = (T)g.inv_dx;
-  const T hx = f.H[0][id], hy = f.H[1][id], hz = f.H[2][id];
-  T dHz_dy = (hz - bwd(f.H[2], id, j, g.n[1], g.periodic[1], sy)) * idx;
-  T dHy_dz = (hy - bwd(f.H[1], id, k, g.n[2], g.periodic[2], sz)) * idx;
-  T dHx_dz = (hx - bwd(f.H[0], id, k, g.n[2], g.periodic[2], sz)) * idx;
-  T dHz_dx = (hz - bwd(f.H[2], id, i, g.n[0], g.periodic[0], sx)) * idx;
-  T dHy_dx = (hy - bwd(f.H[1], id, i, g.n[0], g.periodic[0], sx)) * idx;
-  T dHx_dy = (hx - bwd(f.H[0], id, j, g.n[1], g.periodic[1], sy)) * idx;
-  dHz_dy = stretch(f, g, f.psiE[0][1], 1, 0, i, j, k, dHz_dy);
-  dHy_dz = stretch(f, g, f.psiE[0][2], 2, 0, i, j, k, dHy_dz);
-  dHx_dz = stretch(f, g, f.psiE[1][2], 2, 0, i, j, k, dHx_dz);
-  dHz_dx = stretch(f, g, f.psiE[1][0], 0, 0, i, j, k, dHz_dx);
-  dHy_dx = stretch(f, g, f.psiE[2][0], 0, 0, i, j, k, dHy_dx);
-  dHx_dy = stretch(f, g, f.psiE[2][1], 1, 0, i, j, k, dHx_dy);
-  T J[3] = {T(0), T(0), T(0)};
-  source_current(src, g, step, i, j, k, J);
-  const T ce = (T)g.dt * f.epsinv[id];
-  const T cx = dHz_dy - dHy_dz - J[0];
-  const T cy = dHx_dz - dHz_dx - J[1];
-  const T cz = dHy_dx - dHx_dy - J[2];
-  f.E[0][id] = tangential_wall(g, 0, i, j, k) ? T(0) : f.E[0][id] + ce * cx;
-  f.E[1][id] = tangential_wall(g, 1, i, j, k) ? T(0) : f.E[1][id] + ce * cy;
-  f.E[2][id] = tangential_wall(g, 2, i, j, k) ? T(0) : f.E[2][id] + ce * cz;
+  const T hx = out.H[0][id], hy = out.H[1][id], hz = out.H[2][id];
+  T dHz_dy = (hz - bwd(out.H[2], id, j, g.n[1], g.periodic[1], sy)) * idx;
+  T dHy_dz = (hy - bwd(out.H[1], id, k, g.n[2], g.periodic[2], sz)) * idx;
+  T dHx_dz = (hx - bwd(out.H[0], id, k, g.n[2], g.periodic[2], sz)) * idx;
+  T dHz_dx = (hz - bwd(out.H[2], id, i, g.n[0], g.periodic[0], sx)) * idx;
+  T dHy_dx = (hy - bwd(out.H[1], id, i, g.n[0], g.periodic[0], sx)) * idx;
+  T dHx_dy = (hx - bwd(out.H[0], id, j, g.n[1], g.periodic[1], sy)) * idx;
+  dHz_dy = stretch(g, in.tab, in.psi, out.psi, 0, 0, 1, i, j, k, dHz_dy);
+  dHy_dz = stretch(g, in.tab, in.psi, out.psi, 0, 0, 2, i, j, k, dHy_dz);
+  dHx_dz = stretch(g, in.tab, in.psi, out.psi, 0, 1, 2, i, j, k, dHx_dz);
+  dHz_dx = stretch(g, in.tab, in.psi, out.psi, 0, 1, 0, i, j, k, dHz_dx);
+  dHy_dx = stretch(g, in.tab, in.psi, out.psi, 0, 2, 0, i, j, k, dHy_dx);
+  dHx_dy = stretch(g, in.tab, in.psi, out.psi, 0, 2, 1, i, j, k, dHx_dy);
+  const T ce = (T)g.dt * in.epsinv[id];
+  const T cx = dHz_dy - dHy_dz;
+  const T cy = dHx_dz - dHz_dx;
+  const T cz = dHy_dx - dHx_dy;
+  out.E[0][id] = tangential_wall(g, 0, i, j, k) ? T(0) : in.E[0][id] + ce * cx;
+  out.E[1][id] = tangential_wall(g, 1, i, j, k) ? T(0) : in.E[1][id] + ce * cy;
+  out.E[2][id] = tangential_wall(g, 2, i, j, k) ? T(0) : in.E[2][id] + ce * cz;
+}
+
+template <typename T, bool H>
+__global__ __launch_bounds__(256) void k_update_box(FieldPtrs<T> in, FieldPtrs<T> out, Geom g,
+                                                    Box box) {
+  const int i = box.lo[0] + blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = box.lo[1] + blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = box.lo[2] + blockIdx.z;
+  if (i >= box.hi[0] || j >= box.hi[1]) return;
+  if (H) update_h_cell(in, out, g, i, j, k);
+  else update_e_cell(in, out, g, i, j, k);
+}
+
+// The cells of the grid outside an interior box, enumerated in memory order:
+// the whole planes below and above the box in z, then, plane by plane inside
+// it, the whole rows below and above it in y followed by the two x strips of
+// each remaining row.
+struct ShellMap {
+  Box in;
+  int nzlo;              // whole planes below the box
+  long long nslab;       // cells in the whole planes (both sides)
+  int ylo_rows;          // whole rows below the box, per middle plane
+  int full_cells;        // cells in the whole rows of one middle plane
+  int strip;             // cells in the two x strips of one row
+  int per_plane;         // shell cells of one middle plane
+  long long total;
+};
+
+__device__ __forceinline__ void shell_cell(const Geom& g, const ShellMap& m, long long t, int& i,
+                                           int& j, int& k) {
+  const int nx = g.n[0], ny = g.n[1];
+  if (t < m.nslab) {
+    const long long plane = (long long)nx * ny;
+    const int p = (int)(t / plane);
+    const int r = (int)(t - (long long)p * plane);
+    k = p < m.nzlo ? p : m.in.hi[2] + (p - m.nzlo);
+    j = r / nx;
+    i = r - j * nx;
+    return;
+  }
+  const long long u = t - m.nslab;
+  const int p = (int)(u / m.per_plane);
+  int r = (int)(u - (long long)p * m.per_plane);
+  k = m.in.lo[2] + p;
+  if (r < m.full_cells) {
+    const int row = r / nx;
+    i = r - row * nx;
+    j = row < m.ylo_rows ? row : m.in.hi[1] + (row - m.ylo_rows);
+    return;
+  }
+  r -= m.full_cells;
+  const int row = r / m.strip;
+  const int c = r - row * m.strip;
+  j = m.in.lo[1] + row;
+  i = c < m.in.lo[0] ? c : m.in.hi[0] + (c - m.in.lo[0]);
+}
+
+template <typename T, bool H>
+__global__ __launch_bounds__(256) void k_update_shell(FieldPtrs<T> in, FieldPtrs<T> out, Geom g,
+                                                      ShellMap m) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m.total) return;
+  int i, j, k;
+  shell_cell(g, m, t, i, j, k);
+  if (H) update_h_cell(in, out, g, i, j, k);
+  else update_e_cell(in, out, g, i, j, k);
+}
+
+// Soft source currents J at t = (n + 1/2) dt:  E -= (dt/eps_r) J.  One thread per
+// cell of each source's support (a plane, or one cell); metallic-wall cells of
+// the driven component keep E = 0.
+template <typename T>
+__global__ void k_sources(FieldPtrs<T> f, Geom g, SourceSet src, const int64_t* step) {
+  const int q = blockIdx.y;
+  if (q >= src.count) return;
+  const Source& s = src.s[q];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int i, j, k;
+  double scale;
+  if (s.kind == 0) {
+    const int u = (s.axis + 1) % 3, v = (s.axis + 2) % 3;
+    if (t >= g.n[u] * g.n[v]) return;
+    int p[3];
+    p[s.axis] = s.index;
+    p[u] = t % g.n[u];
+    p[v] = t / g.n[u];
+    i = p[0];
+    j = p[1];
+    k = p[2];
+    scale = g.inv_dx;
+  } else {
+    if (t > 0) return;
+    i = s.ijk[0];
+    j = s.ijk[1];
+    k = s.ijk[2];
+    scale = g.inv_dx * g.inv_dx * g.inv_dx;
+  }
+  if (tangential_wall(g, s.comp, i, j, k)) return;
+  const double tm = ((double)(*step) + 0.5) * g.dt;
+  const size_t id = cell_index(g, i, j, k);
+  const double J = pulse_value(s, tm) * scale;
+  f.E[s.comp][id] -= (T)((double)g.dt * (double)f.epsinv[id] * J);
 }
 
 template <typename T>
-static hipError_t launch_plain(const FieldPtrs<T>& f, const Geom& g, const SourceSet& src,
-                               const int64_t* step, hipStream_t st) {
+static hipError_t launch_plain(const FieldPtrs<T>& in, const FieldPtrs<T>& out, const Geom& g,
+                               const Box* boxes, int nbox, bool h_pass, bool e_pass,
+                               hipStream_t st) {
   dim3 block(64, 4, 1);
-  dim3 grid((g.n[0] + 63) / 64, (g.n[1] + 3) / 4, g.n[2]);
-  hipLaunchKernelGGL(k_update_h<T>, grid, block, 0, st, f, g);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_update_e<T>, grid, block, 0, st, f, g, src, step);
+  for (int pass = 0; pass < 2; ++pass) {
+    if ((pass == 0 && !h_pass) || (pass == 1 && !e_pass)) continue;
+    for (int q = 0; q < nbox; ++q) {
+      const Box& b = boxes[q];
+      const int ex = b.hi[0] - b.lo[0], ey = b.hi[1] - b.lo[1], ez = b.hi[2] - b.lo[2];
+      if (ex <= 0 || ey <= 0 || ez <= 0) continue;
+      dim3 grid((ex + 63) / 64, (ey + 3) / 4, ez);
+      if (pass == 0) hipLaunchKernelGGL((k_update_box<T, true>), grid, block, 0, st, in, out, g, b);
+      else hipLaunchKernelGGL((k_update_box<T, false>), grid, block, 0, st, in, out, g, b);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+static hipError_t launch_shell(const FieldPtrs<T>& in, const FieldPtrs<T>& out, const Geom& g,
+                               const Box& inner, bool h_pass, hipStream_t st) {
+  ShellMap m{};
+  m.in = inner;
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const int wy = inner.hi[1] - inner.lo[1], wz = inner.hi[2] - inner.lo[2];
+  m.nzlo = inner.lo[2];
+  m.nslab = (long long)(nz - wz) * nx * ny;
+  m.ylo_rows = inner.lo[1];
+  m.full_cells = (ny - wy) * nx;
+  m.strip = inner.lo[0] + (nx - inner.hi[0]);
+  m.per_plane = m.full_cells + wy * m.strip;
+  m.total = m.nslab + (long long)wz * m.per_plane;
+  if (m.total == 0) return hipSuccess;
+  const long long blocks = (m.total + 255) / 256;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (h_pass)
+    hipLaunchKernelGGL((k_update_shell<T, true>), dim3((unsigned)blocks), dim3(256), 0, st, in,
+                       out, g, m);
+  else
+    hipLaunchKernelGGL((k_update_shell<T, false>), dim3((unsigned)blocks), dim3(256), 0, st, in,
+                       out, g, m);
   return hipGetLastError();
 }
 
-hipError_t sweep_plain_f64(const FieldPtrs<double>& f, const Geom& g, const SourceSet& src,
-                           const int64_t* step, hipStream_t st) {
-  return launch_plain<double>(f, g, src, step, st);
+template <typename T>
+static hipError_t launch_sources(const FieldPtrs<T>& f, const Geom& g, const SourceSet& src,
+                                 const int64_t* step, hipStream_t st) {
+  if (src.count == 0) return hipSuccess;
+  int maxp = 1;
+  for (int q = 0; q < src.count; ++q)
+    if (src.s[q].kind == 0) {
+      const int u = (src.s[q].axis + 1) % 3, v = (src.s[q].axis + 2) % 3;
+      maxp = max(maxp, g.n[u] * g.n[v]);
+    }
+  hipLaunchKernelGGL(k_sources<T>, dim3((maxp + 255) / 256, src.count), dim3(256), 0, st, f, g,
+                     src, step);
+  return hipGetLastError();
 }
 
-hipError_t sweep_plain_f32(const FieldPtrs<float>& f, const Geom& g, const SourceSet& src,
-                           const int64_t* step, hipStream_t st) {
-  return launch_plain<float>(f, g, src, step, st);
+hipError_t sweep_plain_f64(const FieldPtrs<double>& in, const FieldPtrs<double>& out,
+                           const Geom& g, const Box* boxes, int nbox, bool h_pass, bool e_pass,
+                           hipStream_t st) {
+  return launch_plain<double>(in, out, g, boxes, nbox, h_pass, e_pass, st);
+}
+hipError_t sweep_plain_f32(const FieldPtrs<float>& in, const FieldPtrs<float>& out, const Geom& g,
+                           const Box* boxes, int nbox, bool h_pass, bool e_pass, hipStream_t st) {
+  return launch_plain<float>(in, out, g, boxes, nbox, h_pass, e_pass, st);
+}
+hipError_t sweep_shell_f64(const FieldPtrs<double>& in, const FieldPtrs<double>& out,
+                           const Geom& g, const Box& inner, bool h_pass, hipStream_t st) {
+  return launch_shell<double>(in, out, g, inner, h_pass, st);
+}
+hipError_t sweep_shell_f32(const FieldPtrs<float>& in, const FieldPtrs<float>& out, const Geom& g,
+                           const Box& inner, bool h_pass, hipStream_t st) {
+  return launch_shell<float>(in, out, g, inner, h_pass, st);
+}
+hipError_t sources_f64(const FieldPtrs<double>& f, const Geom& g, const SourceSet& src,
+                       const int64_t* step, hipStream_t st) {
+  return launch_sources<double>(f, g, src, step, st);
+}
+hipError_t sources_f32(const FieldPtrs<float>& f, const Geom& g, const SourceSet& src,
+                       const int64_t* step, hipStream_t st) {
+  return launch_sources<float>(f, g, src, step, st);
 }
 
 }  // namespace mlk

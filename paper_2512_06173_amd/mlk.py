@@ -148,7 +148,7 @@ class Simulation:
 
     def __init__(self, shape, dx=1.0, courant=0.5, precision="fp64", bc=("pec",) * 6,
                  cpml=(0,) * 6, pml_m=3.0, pml_sigma_scale=0.8, pml_kappa_max=1.0,
-                 pml_alpha_max=0.0, window_r=3.0, sweep="plain", scatter="owner", stream=None,
+                 pml_alpha_max=0.0, window_r=3.0, sweep="fused", scatter="owner", stream=None,
                  device=0):
         L = lib()
         d = GridDesc()

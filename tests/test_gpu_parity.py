@@ -115,10 +115,19 @@ def _sources_workload(shape, bc, cpml, precision, steps, seed=1):
                       precision=precision)
 
 
+@pytest.mark.parametrize("sweep", ["fused", "plain"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_cpml_dielectric_sources(precision):
+def test_cpml_dielectric_sources(precision, sweep):
     w = _sources_workload((40, 36, 44), ("cpml",) * 6, (8, 6, 7, 5, 8, 9), precision, 220)
-    sim, ora = run_both(w)
+    sim, ora = run_both(w, sweep=sweep)
+    check(sim, ora, w)
+
+
+def test_fused_sweep_many_tiles_and_chunks_fp64():
+    """Several x tiles (one ragged), many y tiles and z chunks, CPML on all faces,
+    dielectric, point and plane sources: fused sweep against the oracle."""
+    w = _sources_workload((150, 37, 70), ("cpml",) * 6, (9, 7, 5, 6, 10, 8), "fp64", 120)
+    sim, ora = run_both(w, sweep="fused")
     check(sim, ora, w)
 
 
@@ -138,8 +147,8 @@ def test_ragged_mixed_boundaries_fp64():
                      omega0=rng.uniform(0.24, 0.26, M), dipole=0.3 * rng.standard_normal((M, 3)),
                      rho0=np.tile([0.5, 0.5, 0.0], (M, 1)))
     w.pop_every = 1
-    for scatter in ("owner", "atomic"):
-        sim, ora = run_both(w, scatter=scatter)
+    for scatter, sweep in (("owner", "fused"), ("atomic", "plain"), ("owner", "plain")):
+        sim, ora = run_both(w, scatter=scatter, sweep=sweep)
         check(sim, ora, w)
 
 
@@ -253,4 +262,23 @@ def test_two_dimensional_superradiance_run(precision):
                                 rho0=np.tile([1e-4, np.sqrt(0.9999) * 0.01, 0.0], (4, 1))),
                    probes=[(2, (n // 2 + 10, n // 2, 0))])
     sim, ora = run_both(w)
+    check(sim, ora, w)
+
+
+@pytest.mark.parametrize("sweep", ["fused", "plain"])
+def test_shell_and_interior_regions_fp64(sweep):
+    """Asymmetric CPML thicknesses (one face metallic) so that the fused sweep's interior
+    box and its shell slabs have uneven sizes; emitters and sources straddle the seams."""
+    rng = np.random.default_rng(33)
+    nx, ny, nz = 77, 45, 52
+    w = _sources_workload((nx, ny, nz), ("cpml", "pec", "pec", "cpml", "cpml", "cpml"),
+                          (7, 0, 0, 9, 6, 11), "fp64", 140)
+    M = 25
+    pos = np.column_stack([rng.uniform(12, nx - 5, M), rng.uniform(5, ny - 14, M),
+                           rng.uniform(11, nz - 16, M)])
+    w.tls = W.TLSSet(pos=pos, sigma=np.ones(M), gamma=np.ones(M),
+                     omega0=rng.uniform(0.24, 0.26, M), dipole=0.3 * rng.standard_normal((M, 3)),
+                     rho0=np.tile([0.5, 0.5, 0.0], (M, 1)))
+    w.pop_every = 2
+    sim, ora = run_both(w, sweep=sweep)
     check(sim, ora, w)
