@@ -1,0 +1,219 @@
+"""Throughput of the coupled Yee / quantum-emitter step on one MI355X.
+
+One step is one pass of the whole coupled leapfrog (H update, field gather,
+emitter step, dipole rate, current scatter, E update, sources, detectors)
+over the radiating-cube workload: a 256^3 grid with 10-cell CPML on every
+face, 100,000 two-level emitters in the central 128^3 box starting in the
+superposition state, and a Poynting-flux plane at z = 200.  Fields are FP32,
+emitter states FP64; everything stays on the device.
+
+Prints ONE JSON line: Gcell-updates/s of the fused FP32 step (the value),
+emitter-steps/s, the fused/plain FP32/FP64 comparison on the same GPU, the
+roofline of the dominant kernel (the fused interior sweep) measured with HIP
+events on the library's stream, and the CPU oracle timed on the host cores
+on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu] [--no-compare]
+    python bench.py --copy-calib     # plain copy kernel of known size (counter scaling)
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FUSED_SRC = os.path.join(ROOT, "paper_2512_06173_amd", "csrc", "yee_fused.hip")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_fused_f32_radiating_cube_256_traffic.md")
+# Algorithmic bytes, per unit (see the roofline section of the design notes):
+#   cell-step: read + write of the 6 field components and one read of 1/eps_r
+#   CPML layer membership: read + write of the 4 psi values of that axis
+#   two-level emitter step: state, parameters, E~ and mu_dot
+CELL_WORDS = 13
+PSI_WORDS = 8
+TLS_STEP_BYTES = 100
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=1000)
+    p.add_argument("--warmup", type=int, default=50)
+    p.add_argument("--n", type=int, default=256, help="grid edge (cells)")
+    p.add_argument("--emitters", type=int, default=100000)
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--no-compare", action="store_true", help="skip the plain/FP64 legs")
+    p.add_argument("--cpu-steps", type=int, default=10)
+    p.add_argument("--copy-calib", action="store_true")
+    return p.parse_args()
+
+
+def layer_memberships(shape, cpml):
+    """Sum over axes of the cells lying in that axis's CPML layers."""
+    nx, ny, nz = shape
+    n = (nx, ny, nz)
+    tot = 0
+    for a in range(3):
+        lo, hi = cpml[2 * a], cpml[2 * a + 1]
+        tot += (lo + hi) * (nx * ny * nz // n[a])
+    return tot
+
+
+def copy_calibration():
+    import torch
+    nbytes = 256 << 20
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": nbytes, "launches": 5}), flush=True)
+
+
+def traffic_from_profile(launch_cells):
+    """HBM bytes per launch of the fused kernel from the committed counter summary,
+    or None when it is absent or was taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    txt = open(TRAFFIC_SUMMARY).read()
+    want = hashlib.sha256(open(FUSED_SRC, "rb").read()).hexdigest()
+    m = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", txt)
+    t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    c = re.search(r"cells_per_launch:\s*(\d+)", txt)
+    if not (m and t and c) or m.group(1) != want or int(c.group(1)) != launch_cells:
+        return None
+    return float(t.group(1))
+
+
+def run_gpu(w, precision, sweep, steps, warmup, timing):
+    import torch
+    from paper_2512_06173_amd import mlk
+    sim = mlk.from_workload(w, precision=precision, sweep=sweep, scatter="owner",
+                            stream=mlk.current_stream_handle())
+    sim.step(warmup)
+    sim.sync()
+    sim.set_timing(timing)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    phases = {}
+    if timing:
+        for name in mlk.PHASES:
+            ms, n = sim.phase_time(name)
+            if n:
+                phases[name] = (ms, n)
+    box = sim.interior_box()
+    sim.close()
+    return dt, phases, box
+
+
+def cpu_baseline(w, steps):
+    from oracle import oracle
+    from oracle.feed import build_oracle
+    oracle.build()
+    ora = build_oracle(w)
+    ora.step(1)  # first touch of the arrays
+    t0 = time.perf_counter()
+    ora.step(steps)
+    dt = time.perf_counter() - t0
+    cells = w.shape[0] * w.shape[1] * w.shape[2]
+    return {"value": cells * steps / dt / 1e9, "unit": "Gcell-updates/s",
+            "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{steps} steps of the same {w.shape[0]}x{w.shape[1]}x{w.shape[2]} "
+                      f"workload with all {len(w.tls.pos)} emitters (FP64, after 1 untimed "
+                      f"step); {dt:.1f} s",
+            "emitter_steps_per_s": len(w.tls.pos) * steps / dt}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus > 1 or world > 1:
+        print("bench.py measures one GPU: multi-GPU sharding of the grid is described in the "
+              "design notes but not built; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calib:
+        copy_calibration()
+        return
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    from paper_2512_06173_amd import workloads as W
+    from paper_2512_06173_amd import mlk
+    mlk.lib()
+
+    w = W.radiating_cube(n=args.n, n_emit=args.emitters)
+    nx, ny, nz = w.shape
+    cells = nx * ny * nz
+    nem = len(w.tls.pos)
+    esz = 4
+    memb = layer_memberships(w.shape, w.cpml)
+    step_bytes = cells * CELL_WORDS * esz + memb * PSI_WORDS * esz + nem * TLS_STEP_BYTES
+
+    dt, phases, box = run_gpu(w, "fp32", "fused", args.steps, args.warmup, True)
+    ms_step = dt * 1e3 / args.steps
+    gcells = cells * args.steps / dt / 1e9
+    emit_rate = nem * args.steps / dt
+
+    # dominant kernel: the fused interior sweep (one launch per step)
+    sweep_ms, sweep_n = phases["sweep"]
+    lo, hi = box
+    launch_cells = (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2])
+    launch_bytes = launch_cells * CELL_WORDS * esz
+    t_launch = sweep_ms / sweep_n * 1e-3
+    achieved = launch_bytes / t_launch / 1e9
+    traffic = traffic_from_profile(launch_cells)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "kernel": "k_fused<float>",
+                "bytes_per_launch": launch_bytes, "avg_launch_us": round(t_launch * 1e6, 2)}
+    emitter_ms = sum(phases[p][0] for p in ("emitters", "scatter") if p in phases)
+    out = {
+        "metric": "Gcell-updates/s + emitter-steps/s (fused vs plain FP64); adjoint/forward "
+                  "time ratio",
+        "value": round(gcells, 3), "unit": "Gcell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"radiating cube {nx}^3, CPML 10 on 6 faces, {nem} two-level "
+                               f"emitters in the central box, flux plane z={w.flux[1]}; "
+                               f"FP32 fields, FP64 emitter states",
+                   "cells": cells, "emitters": nem, "sweep": "fused", "scatter": "owner"},
+        "emitter_steps_per_s": round(emit_rate, 1),
+        "emitter_phase_steps_per_s": round(nem * args.steps / (emitter_ms * 1e-3), 1)
+        if emitter_ms else None,
+        "step_roofline": {"bytes_per_step": step_bytes,
+                          "achieved_GBs": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
+                          "frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "phases_us_per_step": {k: round(v[0] * 1e3 / args.steps, 2) for k, v in phases.items()},
+        "roofline": roofline,
+        "adjoint_forward_ratio": None,
+    }
+    if not args.no_compare:
+        cmp = {}
+        ksteps = max(1, args.steps // 5)
+        for prec, sweep in (("fp32", "plain"), ("fp64", "fused"), ("fp64", "plain")):
+            d, _, _ = run_gpu(w, prec, sweep, ksteps, max(1, args.warmup // 2), False)
+            cmp[f"{sweep}_{prec}"] = {"gcell_updates_per_s": round(cells * ksteps / d / 1e9, 3),
+                                      "emitter_steps_per_s": round(nem * ksteps / d, 1),
+                                      "ms_per_step": round(d * 1e3 / ksteps, 4),
+                                      "steps": ksteps}
+        cmp["fused_fp32"] = {"gcell_updates_per_s": round(gcells, 3),
+                             "emitter_steps_per_s": round(emit_rate, 1),
+                             "ms_per_step": round(ms_step, 4), "steps": args.steps}
+        out["comparison"] = cmp
+    out["cpu_baseline"] = None if args.no_cpu else cpu_baseline(w, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

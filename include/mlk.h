@@ -187,6 +187,36 @@ mlk_status mlk_checkpoint_size(mlk_sim* s, size_t* bytes);
 mlk_status mlk_checkpoint_save(mlk_sim* s, void* dst, int32_t mem_kind);
 mlk_status mlk_checkpoint_load(mlk_sim* s, const void* src, int32_t mem_kind);
 
+/* Per-phase timing of the step loop with HIP events recorded on the sim's
+ * stream around each phase of every step (off by default; turning it on
+ * costs one event pair per phase per step).  mlk_set_timing(s, on) also
+ * clears the accumulated times.  mlk_get_phase_time waits for the stream and
+ * returns, for one phase, the summed elapsed time in ms and the number of
+ * timed launches of it.  Phases:
+ *   EMITTERS      field gather + emitter step + dipole rate (steps 2-4)
+ *   SWEEP         the stencil kernel of the Yee sweep: the fused interior
+ *                 kernel, or in the plain mode the H and E passes (steps 1, 6)
+ *   SHELL         the CPML-shell passes of the fused mode (steps 1, 6)
+ *   SOURCES       soft source currents (step 5)
+ *   SCATTER       molecular current scatter into E (step 5)
+ *   DETECTORS     flux plane save, probes, flux series, step counter (step 7) */
+enum {
+  MLK_PHASE_EMITTERS = 0,
+  MLK_PHASE_SWEEP = 1,
+  MLK_PHASE_SHELL = 2,
+  MLK_PHASE_SOURCES = 3,
+  MLK_PHASE_SCATTER = 4,
+  MLK_PHASE_DETECTORS = 5,
+  MLK_PHASE_COUNT = 6
+};
+mlk_status mlk_set_timing(mlk_sim* s, int32_t on);
+mlk_status mlk_get_phase_time(mlk_sim* s, int32_t phase, double* total_ms, int64_t* launches);
+
+/* Interior box of the fused sweep as {lo_x, lo_y, lo_z, hi_x, hi_y, hi_z}
+ * (half-open): the cells that the fused kernel owns, away from every CPML
+ * layer; the cells outside it are updated by the CPML-shell passes. */
+mlk_status mlk_get_interior_box(mlk_sim* s, int32_t box[6]);
+
 #ifdef __cplusplus
 }
 #endif

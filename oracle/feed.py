@@ -1,6 +1,5 @@
-"""Feed a seeded workload to the CPU oracle (test helper)."""
-import numpy as np
-
+"""Feed a seeded workload (the dataclasses of paper_2512_06173_amd.workloads, read by
+attribute only) to the CPU oracle.  Test infrastructure, like the rest of oracle/."""
 from oracle.oracle import Oracle
 
 

@@ -1,23 +1,27 @@
 // Tile-binned emitter phase.
 //
-// gather + step (eq. E_regu_Emi, then eq. von-Neumann-tls and eq.
-// dipole_derivative): the emitters are grouped by the bin of their centre
-// cell.  The workgroup of a bin stages E over the bin plus a halo of kHalo
-// cells in LDS, which holds every window of its emitters; one wavefront then
-// takes one emitter at a time, 64 lanes over the (x, y) points of its window
-// and a loop over z, all three components per pass, sums in FP64, and lane 0
-// advances the two-level state and writes E~ and mu_dot.
+// gather (eq. E_regu_Emi): the emitters are grouped by the bin of their
+// centre cell.  The workgroup of a bin stages E over the bin plus a halo of
+// kHalo cells in LDS, which holds every window of its emitters.  Eight lanes
+// serve one emitter, lane i taking the x offset i of its window: a lane sums
+// the window rows along y in the field precision, weights them along z into
+// FP64, and the eight lanes of the emitter add up their sums (FP64).  Bins are
+// handed out XCD by XCD so that neighbouring bins, whose halos overlap, share
+// one L2.
+//
+// step (eq. von-Neumann-tls, eq. dipole_derivative): one thread per two-level
+// emitter advances its state with the exact propagator and writes mu_dot.
 //
 // scatter (eqs. J_mol, Polarization_mol):  E_c(p) -= (dt/eps_r(p)) gamma mu_dot^c
 // w^c_{m,p} / dx^3.  A workgroup owns a bin of cells and takes every emitter
-// whose window touches the bin; contributions are summed in LDS (as 64-bit
-// fixed-point integers, see k_scatter_bins) and each cell is written once by
-// its owner (no global atomics).
+// whose window touches the bin, again eight lanes per emitter; contributions
+// are summed in LDS (as fixed-point integers, see k_scatter_bins) and each
+// cell is written once by its owner (no global atomics).
 //
 // Window weights are the separable factors wx wy wz set up by k_windows, kept
 // per emitter as a union-window record (WinRec); a component uses the
-// half-integer variant on its own axis.  Records of a chunk of emitters are
-// copied into LDS with 16-byte loads, so the inner loops touch LDS only.
+// half-integer variant on its own axis.  Records are copied into LDS with
+// 16-byte loads, so the inner loops touch LDS only.
 #include "mlk_internal.h"
 #include "tls_math.h"
 
@@ -27,15 +31,15 @@ template <typename T>
 struct BinCfg;
 template <>
 struct BinCfg<float> {
-  // gather: 16 x 8 x 8 bins, 24 x 16 x 16 tile (74 KB); scatter: 32 x 8 x 8 bins
-  static constexpr int GX = 16, GY = 8, GZ = 8, GCHUNK = 16;
-  static constexpr int SX = 32, SY = 8, SZ = 8, SCHUNK = 32;
+  // gather: 16 x 8 x 8 bins, 24 x 16 x 16 tile (74 KB); scatter: 16^3 bins (48 KB)
+  static constexpr int GX = 16, GY = 8, GZ = 8;
+  static constexpr int SX = 16, SY = 16, SZ = 16;
 };
 template <>
 struct BinCfg<double> {
-  // gather: 8 x 8 x 8 bins, 16 x 16 x 16 tile (98 KB); scatter: 32 x 8 x 8 bins
-  static constexpr int GX = 8, GY = 8, GZ = 8, GCHUNK = 16;
-  static constexpr int SX = 32, SY = 8, SZ = 8, SCHUNK = 16;
+  // gather: 8 x 8 x 8 bins, 16 x 16 x 16 tile (98 KB); scatter: 16 x 16 x 8 bins (48 KB)
+  static constexpr int GX = 8, GY = 8, GZ = 8;
+  static constexpr int SX = 16, SY = 16, SZ = 8;
 };
 
 void bin_shape(bool fp32, int G[3], int S[3]) {
@@ -50,6 +54,10 @@ void bin_shape(bool fp32, int G[3], int S[3]) {
 
 namespace {
 
+constexpr int kLanesPerEmitter = 8;  // = kMaxWin: one lane per window x offset
+constexpr int kThreads = 512;
+constexpr int kGroups = kThreads / kLanesPerEmitter;  // emitters in flight per workgroup
+
 __device__ __forceinline__ int wrap_once(int q, int n) {
   q += q < 0 ? n : 0;
   q -= q >= n ? n : 0;
@@ -62,41 +70,68 @@ __device__ __forceinline__ double wave_sum64(double v) {
   return v;
 }
 
-// Copy the window records of emitters ids[0..cn) into LDS (16-byte pieces).
-template <typename T, int NT>
-__device__ __forceinline__ void stage_records(const WinRec<T>* rec, const int* ids, int cn,
-                                              WinRec<T>* dst, int tid) {
-  constexpr int R4 = sizeof(WinRec<T>) / sizeof(int4);
-  for (int i = tid; i < cn * R4; i += NT) {
-    const int slot = i / R4, part = i % R4;
-    const int4* src = reinterpret_cast<const int4*>(rec + ids[slot]);
-    reinterpret_cast<int4*>(dst + slot)[part] = src[part];
-  }
+__device__ __forceinline__ double group_sum8(double v) {
+  v += __shfl_xor(v, 4, kLanesPerEmitter);
+  v += __shfl_xor(v, 2, kLanesPerEmitter);
+  v += __shfl_xor(v, 1, kLanesPerEmitter);
+  return v;
+}
+
+// XCD-aware order: hardware hands consecutive workgroups to the 8 XCDs in turn;
+// give each XCD a contiguous range of bins.
+__device__ __forceinline__ int xcd_block(int bid, int nblocks) {
+  const int q8 = nblocks / 8;
+  return bid < 8 * q8 ? (bid % 8) * q8 + bid / 8 : bid;
+}
+
+// The part of an emitter's window record that one of its eight lanes needs,
+// in registers: the union window, the lane's own x weights and every y and z
+// weight (the eight lanes read the same record, one cache line at a time).
+template <typename T>
+struct LaneWin {
+  int org[3], n[3];
+  T wx0, wx1;
+  T wy[2][kMaxWin], wz[2][kMaxWin];
+};
+
+template <typename T>
+__device__ __forceinline__ void load_lane_win(const WinRec<T>& r, int i, LaneWin<T>& w) {
+  const int4 o = *reinterpret_cast<const int4*>(&r.org[0]);  // org[0..2], n[0]
+  const int2 nn = *reinterpret_cast<const int2*>(&r.n[1]);
+  w.org[0] = o.x;
+  w.org[1] = o.y;
+  w.org[2] = o.z;
+  w.n[0] = o.w;
+  w.n[1] = nn.x;
+  w.n[2] = nn.y;
+  w.wx0 = r.wr[0][0][i];
+  w.wx1 = r.wr[0][1][i];
+#pragma unroll
+  for (int v = 0; v < 2; ++v)
+#pragma unroll
+    for (int d = 0; d < kMaxWin; ++d) {
+      w.wy[v][d] = r.wr[1][v][d];
+      w.wz[v][d] = r.wr[2][v][d];
+    }
 }
 
 }  // namespace
 
-// gather + two-level step; see the file comment.
+// gather; see the file comment.  Writes E~ = gamma * sum w E (FP64) per emitter.
 template <typename T>
-__global__ __launch_bounds__(512) void k_gather_step(FieldPtrs<T> f, Geom g, BinPtrs bins,
-                                                     WindowPtrs<T> win, TlsPtrs tls,
-                                                     const int* tls_slot, double* Et,
-                                                     double* mudot, const int64_t* pop_off,
-                                                     Series ser, const int64_t* step) {
+__global__ __launch_bounds__(kThreads) void k_gather_bins(FieldPtrs<T> f, Geom g, BinPtrs bins,
+                                                          WindowPtrs<T> win, double* Et) {
   constexpr int BX = BinCfg<T>::GX, BY = BinCfg<T>::GY, BZ = BinCfg<T>::GZ;
-  constexpr int CH = BinCfg<T>::GCHUNK;
   constexpr int TX = BX + 2 * kHalo, TY = BY + 2 * kHalo, TZ = BZ + 2 * kHalo;
-  constexpr int NW = 8, NT = 512;
   __shared__ T sE[3][TX * TY * TZ];
-  __shared__ WinRec<T> sW[CH];
-  __shared__ double sEt[CH][3];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x;
+  const int bin = xcd_block(blockIdx.x, bins.ngather);
   // tile origin in the unwrapped frame of the emitters' window indices
-  const int x0 = bins.gbin_org[3 * blockIdx.x] - kHalo;
-  const int y0 = bins.gbin_org[3 * blockIdx.x + 1] - kHalo;
-  const int z0 = bins.gbin_org[3 * blockIdx.x + 2] - kHalo;
+  const int x0 = bins.gbin_org[3 * bin] - kHalo;
+  const int y0 = bins.gbin_org[3 * bin + 1] - kHalo;
+  const int z0 = bins.gbin_org[3 * bin + 2] - kHalo;
 
-  for (int t = tid; t < TX * TY * TZ; t += NT) {
+  for (int t = tid; t < TX * TY * TZ; t += kThreads) {
     const int li = t % TX, lj = (t / TX) % TY, lk = t / (TX * TY);
     int q[3] = {x0 + li, y0 + lj, z0 + lk};
     bool ok = true;
@@ -121,66 +156,74 @@ __global__ __launch_bounds__(512) void k_gather_step(FieldPtrs<T> f, Geom g, Bin
     sE[2][t] = v2;
   }
 
-  const int ix = lane & 7, iy = lane >> 3;
-  const int q0 = bins.gbin_start[blockIdx.x], q1 = bins.gbin_start[blockIdx.x + 1];
-  for (int c0 = q0; c0 < q1; c0 += CH) {
-    const int cn = min(CH, q1 - c0);
-    stage_records<T, NT>(win.rec, bins.gbin_em + c0, cn, sW, tid);
-    __syncthreads();
-    for (int k = wave; k < cn; k += NW) {
-      const WinRec<T>& w = sW[k];
-      double ax = 0.0, ay = 0.0, az = 0.0;
-      if (ix < w.n[0] && iy < w.n[1]) {
-        const T wx0 = w.wr[0][0][ix], wx1 = w.wr[0][1][ix];
-        const T wy0 = w.wr[1][0][iy], wy1 = w.wr[1][1][iy];
-        const T cx = wx1 * wy0, cy = wx0 * wy1, cz = wx0 * wy0;
-        // unwrapped window coordinates lie inside the tile by construction
-        int s = (w.org[0] + ix - x0) + TX * (w.org[1] + iy - y0) + TX * TY * (w.org[2] - z0);
-        const int nz = w.n[2];
-        for (int d = 0; d < nz; ++d, s += TX * TY) {
-          const T wz0 = w.wr[2][0][d], wz1 = w.wr[2][1][d];
-          ax += (double)(cx * wz0) * (double)sE[0][s];
-          ay += (double)(cy * wz0) * (double)sE[1][s];
-          az += (double)(cz * wz1) * (double)sE[2][s];
+  __syncthreads();
+
+  const int grp = tid / kLanesPerEmitter, i = tid % kLanesPerEmitter;
+  const int q0 = bins.gbin_start[bin], q1 = bins.gbin_start[bin + 1];
+  for (int q = q0 + grp; q < q1; q += kGroups) {  // uniform across the eight lanes of a group
+    const int e = bins.gbin_em[q];
+    LaneWin<T> w;
+    load_lane_win(win.rec[e], i, w);
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    if (i < w.n[0]) {
+      const int ny = w.n[1], nz = w.n[2];
+      int s = (w.org[0] + i - x0) + TX * (w.org[1] - y0) + TX * TY * (w.org[2] - z0);
+#pragma unroll
+      for (int k = 0; k < kMaxWin; ++k, s += TX * TY) {
+        if (k < nz) {
+          T sx = T(0), sy = T(0), sz = T(0);
+#pragma unroll
+          for (int j = 0; j < kMaxWin; ++j) {
+            if (j < ny) {
+              const int p = s + TX * j;
+              sx += w.wy[0][j] * sE[0][p];
+              sy += w.wy[1][j] * sE[1][p];
+              sz += w.wy[0][j] * sE[2][p];
+            }
+          }
+          ax += (double)(w.wz[0][k] * sx);
+          ay += (double)(w.wz[0][k] * sy);
+          az += (double)(w.wz[1][k] * sz);
         }
       }
-      ax = wave_sum64(ax);
-      ay = wave_sum64(ay);
-      az = wave_sum64(az);
-      if (lane == 0) {
-        sEt[k][0] = ax;
-        sEt[k][1] = ay;
-        sEt[k][2] = az;
-      }
+      // Ex sits at half-integer x (variant 1); Ey, Ez at integer x
+      ax *= (double)w.wx1;
+      ay *= (double)w.wx0;
+      az *= (double)w.wx0;
     }
-    __syncthreads();
-    // one thread per emitter: E~, the exact two-level step, mu_dot, population
-    if (tid < cn) {
-      const int e = bins.gbin_em[c0 + tid];
+    ax = group_sum8(ax);
+    ay = group_sum8(ay);
+    az = group_sum8(az);
+    if (i == 0) {
       const double gm = win.gamma[e];
-      const double et[3] = {gm * sEt[tid][0], gm * sEt[tid][1], gm * sEt[tid][2]};
-      Et[3 * e] = et[0];
-      Et[3 * e + 1] = et[1];
-      Et[3 * e + 2] = et[2];
-      const int m = tls_slot[e];
-      if (m >= 0) {
-        const double d[3] = {tls.dip[3 * m], tls.dip[3 * m + 1], tls.dip[3 * m + 2]};
-        double st[3] = {tls.rho[3 * m], tls.rho[3 * m + 1], tls.rho[3 * m + 2]};
-        double md[3];
-        tls_advance(tls.omega0[m], d, et, g.dt, st, md);
-        tls.rho[3 * m] = st[0];
-        tls.rho[3 * m + 1] = st[1];
-        tls.rho[3 * m + 2] = st[2];
-        mudot[3 * e] = md[0];
-        mudot[3 * e + 1] = md[1];
-        mudot[3 * e + 2] = md[2];
-        if (ser.pop_every > 0) {
-          const int64_t n = *step;
-          if (n % ser.pop_every == 0) ser.pop[(n / ser.pop_every) * ser.npop + pop_off[e]] = st[0];
-        }
-      }
+      Et[3 * e] = gm * ax;
+      Et[3 * e + 1] = gm * ay;
+      Et[3 * e + 2] = gm * az;
     }
-    __syncthreads();
+  }
+}
+
+// Exact two-level step of every two-level emitter under its E~ (one thread each).
+__global__ __launch_bounds__(256) void k_tls_step(TlsPtrs tls, double dt, const double* Et,
+                                                  double* mudot, const int64_t* pop_off,
+                                                  Series ser, const int64_t* step) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= tls.count) return;
+  const int e = tls.gid[m];
+  const double et[3] = {Et[3 * e], Et[3 * e + 1], Et[3 * e + 2]};
+  const double d[3] = {tls.dip[3 * m], tls.dip[3 * m + 1], tls.dip[3 * m + 2]};
+  double st[3] = {tls.rho[3 * m], tls.rho[3 * m + 1], tls.rho[3 * m + 2]};
+  double md[3];
+  tls_advance(tls.omega0[m], d, et, dt, st, md);
+  tls.rho[3 * m] = st[0];
+  tls.rho[3 * m + 1] = st[1];
+  tls.rho[3 * m + 2] = st[2];
+  mudot[3 * e] = md[0];
+  mudot[3 * e + 1] = md[1];
+  mudot[3 * e + 2] = md[2];
+  if (ser.pop_every > 0) {
+    const int64_t n = *step;
+    if (n % ser.pop_every == 0) ser.pop[(n / ser.pop_every) * ser.npop + pop_off[e]] = st[0];
   }
 }
 
@@ -192,7 +235,7 @@ struct Acc<float> {
   using U = unsigned int;
   using S = int;
   static constexpr int BITS = 30;
-  __device__ static S round(double v) { return __float2int_rn((float)v); }
+  __device__ static S round(float v) { return __float2int_rn(v); }
 };
 template <>
 struct Acc<double> {
@@ -208,18 +251,16 @@ struct Acc<double> {
 // 2^-BITS of a bound on any cell's sum (|amp| times the largest window weight,
 // summed over the bin's emitters): 2^-62 for FP64 fields, far below FP64
 // rounding; 2^-30 for FP32 fields, at the level of FP32 rounding of a cell's
-// sum.
+// sum.  A contribution is formed in the field precision.
 template <typename T>
-__global__ __launch_bounds__(512) void k_scatter_bins(FieldPtrs<T> f, Geom g, BinPtrs bins,
-                                                      WindowPtrs<T> win, const double* mudot) {
+__global__ __launch_bounds__(kThreads) void k_scatter_bins(FieldPtrs<T> f, Geom g, BinPtrs bins,
+                                                           WindowPtrs<T> win,
+                                                           const double* mudot) {
   using A = Acc<T>;
   constexpr int BX = BinCfg<T>::SX, BY = BinCfg<T>::SY, BZ = BinCfg<T>::SZ;
-  constexpr int CH = BinCfg<T>::SCHUNK;
-  constexpr int PX = BX + 8, PLANE = PX * BY, CELLS = PLANE * BZ;
-  constexpr int NW = 8, NT = 512;
+  constexpr int CELLS = BX * BY * BZ;
+  constexpr int NW = kThreads / 64;
   __shared__ typename A::U sJ[3][CELLS];
-  __shared__ WinRec<T> sW[CH];
-  __shared__ double sAmp[CH][3];
   __shared__ double sRed[NW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int b = bins.sbin_id[blockIdx.x];
@@ -228,13 +269,13 @@ __global__ __launch_bounds__(512) void k_scatter_bins(FieldPtrs<T> f, Geom g, Bi
   const int ex = min(BX, g.n[0] - x0), ey = min(BY, g.n[1] - y0), ez = min(BZ, g.n[2] - z0);
   const int q0 = bins.sbin_start[blockIdx.x], q1 = bins.sbin_start[blockIdx.x + 1];
   const double amp0 = g.dt * g.inv_dx * g.inv_dx * g.inv_dx;
-  for (int t = tid; t < CELLS; t += NT) {
+  for (int t = tid; t < CELLS; t += kThreads) {
     sJ[0][t] = 0;
     sJ[1][t] = 0;
     sJ[2][t] = 0;
   }
   double bound = 0.0;
-  for (int q = q0 + tid; q < q1; q += NT) {
+  for (int q = q0 + tid; q < q1; q += kThreads) {
     const int e = bins.sbin_em[q];
     const double ge = fabs(amp0 * win.gamma[e]) * (double)win.rec[e].wmax;
     bound += ge * (fabs(mudot[3 * e]) + fabs(mudot[3 * e + 1]) + fabs(mudot[3 * e + 2]));
@@ -251,61 +292,44 @@ __global__ __launch_bounds__(512) void k_scatter_bins(FieldPtrs<T> f, Geom g, Bi
   const double scale = ldexp(1.0, A::BITS - ebits);
   const double inv_scale = ldexp(1.0, ebits - A::BITS);
 
-  const int ix = lane & 7, iy = lane >> 3;
-  for (int c0 = q0; c0 < q1; c0 += CH) {
-    const int cn = min(CH, q1 - c0);
-    stage_records<T, NT>(win.rec, bins.sbin_em + c0, cn, sW, tid);
-    if (tid < cn) {
-      const int e = bins.sbin_em[c0 + tid];
-      const double ge = amp0 * win.gamma[e] * scale;
-      sAmp[tid][0] = ge * mudot[3 * e];
-      sAmp[tid][1] = ge * mudot[3 * e + 1];
-      sAmp[tid][2] = ge * mudot[3 * e + 2];
-    }
-    __syncthreads();
-    for (int k = wave; k < cn; k += NW) {
-      const WinRec<T>& w = sW[k];
-      // z points of the window inside this bin: window offsets d in [d0, d1).  A
-      // periodic axis held by a single bin may see a window from both ends; then
-      // every offset is wrapped on its own.
-      const int nz = w.n[2];
-      const bool whole = g.periodic[2] && ez == g.n[2];
-      int zs = w.org[2] - z0;
-      if (g.periodic[2] && !whole) {
-        if (zs + nz <= 0) zs += g.n[2];
-        else if (zs >= ez) zs -= g.n[2];
-      }
-      const int d0 = whole ? 0 : max(0, -zs), d1 = whole ? nz : min(nz, ez - zs);
-      if (d0 >= d1) continue;  // uniform across the wave
-      if (ix >= w.n[0] || iy >= w.n[1]) continue;
-      const int li = wrap_once(w.org[0] + ix, g.n[0]) - x0;
-      const int lj = wrap_once(w.org[1] + iy, g.n[1]) - y0;
-      if (li < 0 || li >= ex || lj < 0 || lj >= ey) continue;
-      const double wx0 = (double)w.wr[0][0][ix], wx1 = (double)w.wr[0][1][ix];
-      const double wy0 = (double)w.wr[1][0][iy], wy1 = (double)w.wr[1][1][iy];
-      const double cx = sAmp[k][0] * wx1 * wy0, cy = sAmp[k][1] * wx0 * wy1,
-                   cz = sAmp[k][2] * wx0 * wy0;
-      const int base = li + PX * lj;
-      for (int d = d0; d < d1; ++d) {
-        const int lk = whole ? wrap_once(w.org[2] + d, g.n[2]) : zs + d;
-        const int s = base + PLANE * lk;
-        const typename A::S vx = A::round(cx * (double)w.wr[2][0][d]);
-        const typename A::S vy = A::round(cy * (double)w.wr[2][0][d]);
-        const typename A::S vz = A::round(cz * (double)w.wr[2][1][d]);
+  const int grp = tid / kLanesPerEmitter, i = tid % kLanesPerEmitter;
+  for (int q = q0 + grp; q < q1; q += kGroups) {
+    const int e = bins.sbin_em[q];
+    LaneWin<T> w;
+    load_lane_win(win.rec[e], i, w);
+    if (i >= w.n[0]) continue;
+    const int li = wrap_once(w.org[0] + i, g.n[0]) - x0;
+    if (li < 0 || li >= ex) continue;
+    const double ge = amp0 * win.gamma[e] * scale;
+    const T cx = (T)(ge * mudot[3 * e]) * w.wx1, cy = (T)(ge * mudot[3 * e + 1]) * w.wx0,
+            cz = (T)(ge * mudot[3 * e + 2]) * w.wx0;
+    const int ny = w.n[1], nz = w.n[2];
+#pragma unroll
+    for (int k = 0; k < kMaxWin; ++k) {
+      const int lk = wrap_once(w.org[2] + k, g.n[2]) - z0;
+      if (k >= nz || lk < 0 || lk >= ez) continue;
+      const T cxk = cx * w.wz[0][k], cyk = cy * w.wz[0][k], czk = cz * w.wz[1][k];
+#pragma unroll
+      for (int j = 0; j < kMaxWin; ++j) {
+        const int lj = wrap_once(w.org[1] + j, g.n[1]) - y0;
+        if (j >= ny || lj < 0 || lj >= ey) continue;
+        const int s = li + BX * (lj + BY * lk);
+        const typename A::S vx = A::round(cxk * w.wy[0][j]);
+        const typename A::S vy = A::round(cyk * w.wy[1][j]);
+        const typename A::S vz = A::round(czk * w.wy[0][j]);
         if (vx != 0) atomicAdd(&sJ[0][s], (typename A::U)vx);
         if (vy != 0) atomicAdd(&sJ[1][s], (typename A::U)vy);
         if (vz != 0) atomicAdd(&sJ[2][s], (typename A::U)vz);
       }
     }
-    __syncthreads();
   }
+  __syncthreads();
   // owner write: E -= (dt/eps) J on the touched cells of this bin
-  for (int t = tid; t < BX * BY * BZ; t += NT) {
+  for (int t = tid; t < CELLS; t += kThreads) {
     const int li = t % BX, lj = (t / BX) % BY, lk = t / (BX * BY);
     if (li >= ex || lj >= ey || lk >= ez) continue;
-    const int s = li + PX * lj + PLANE * lk;
-    const typename A::S j0 = (typename A::S)sJ[0][s], j1 = (typename A::S)sJ[1][s],
-                        j2 = (typename A::S)sJ[2][s];
+    const typename A::S j0 = (typename A::S)sJ[0][t], j1 = (typename A::S)sJ[1][t],
+                        j2 = (typename A::S)sJ[2][t];
     if (j0 == 0 && j1 == 0 && j2 == 0) continue;
     const size_t id = cell_index(g, x0 + li, y0 + lj, z0 + lk);
     const T ei = f.epsinv[id];
@@ -318,12 +342,14 @@ __global__ __launch_bounds__(512) void k_scatter_bins(FieldPtrs<T> f, Geom g, Bi
 template <typename T>
 static hipError_t launch_gather_step(const FieldPtrs<T>& f, const Geom& g, const BinPtrs& b,
                                      const WindowPtrs<T>& win, const TlsPtrs& tls,
-                                     const int* tls_slot, double* Et, double* mudot,
-                                     const int64_t* pop_off, const Series& ser,
-                                     const int64_t* step, hipStream_t st) {
+                                     double* Et, double* mudot, const int64_t* pop_off,
+                                     const Series& ser, const int64_t* step, hipStream_t st) {
   if (b.ngather <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather_step<T>, dim3(b.ngather), dim3(512), 0, st, f, g, b, win, tls,
-                     tls_slot, Et, mudot, pop_off, ser, step);
+  hipLaunchKernelGGL(k_gather_bins<T>, dim3(b.ngather), dim3(kThreads), 0, st, f, g, b, win, Et);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || tls.count == 0) return e;
+  hipLaunchKernelGGL(k_tls_step, dim3((tls.count + 255) / 256), dim3(256), 0, st, tls, g.dt, Et,
+                     mudot, pop_off, ser, step);
   return hipGetLastError();
 }
 
@@ -331,25 +357,22 @@ template <typename T>
 static hipError_t launch_scatter(const FieldPtrs<T>& f, const Geom& g, const BinPtrs& b,
                                  const WindowPtrs<T>& win, const double* mudot, hipStream_t st) {
   if (b.nscatter <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scatter_bins<T>, dim3(b.nscatter), dim3(512), 0, st, f, g, b, win, mudot);
+  hipLaunchKernelGGL(k_scatter_bins<T>, dim3(b.nscatter), dim3(kThreads), 0, st, f, g, b, win,
+                     mudot);
   return hipGetLastError();
 }
 
 hipError_t bin_gather_step_f64(const FieldPtrs<double>& f, const Geom& g, const BinPtrs& b,
-                               const WindowPtrs<double>& win, const TlsPtrs& tls,
-                               const int* tls_slot, double* Et, double* mudot,
-                               const int64_t* pop_off, const Series& ser, const int64_t* step,
-                               hipStream_t st) {
-  return launch_gather_step<double>(f, g, b, win, tls, tls_slot, Et, mudot, pop_off, ser, step,
-                                    st);
+                               const WindowPtrs<double>& win, const TlsPtrs& tls, double* Et,
+                               double* mudot, const int64_t* pop_off, const Series& ser,
+                               const int64_t* step, hipStream_t st) {
+  return launch_gather_step<double>(f, g, b, win, tls, Et, mudot, pop_off, ser, step, st);
 }
 hipError_t bin_gather_step_f32(const FieldPtrs<float>& f, const Geom& g, const BinPtrs& b,
-                               const WindowPtrs<float>& win, const TlsPtrs& tls,
-                               const int* tls_slot, double* Et, double* mudot,
-                               const int64_t* pop_off, const Series& ser, const int64_t* step,
-                               hipStream_t st) {
-  return launch_gather_step<float>(f, g, b, win, tls, tls_slot, Et, mudot, pop_off, ser, step,
-                                   st);
+                               const WindowPtrs<float>& win, const TlsPtrs& tls, double* Et,
+                               double* mudot, const int64_t* pop_off, const Series& ser,
+                               const int64_t* step, hipStream_t st) {
+  return launch_gather_step<float>(f, g, b, win, tls, Et, mudot, pop_off, ser, step, st);
 }
 hipError_t bin_scatter_f64(const FieldPtrs<double>& f, const Geom& g, const BinPtrs& b,
                            const WindowPtrs<double>& win, const double* mudot, hipStream_t st) {

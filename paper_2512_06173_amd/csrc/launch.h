@@ -60,15 +60,13 @@ hipError_t finish_f32(const FieldPtrs<float>& f, const Geom& g, const FluxPlane&
                       const Series& ser, int64_t* step, hipStream_t st);
 
 hipError_t bin_gather_step_f64(const FieldPtrs<double>& f, const Geom& g, const BinPtrs& b,
-                               const WindowPtrs<double>& win, const TlsPtrs& tls,
-                               const int* tls_slot, double* Et, double* mudot,
-                               const int64_t* pop_off, const Series& ser, const int64_t* step,
-                               hipStream_t st);
+                               const WindowPtrs<double>& win, const TlsPtrs& tls, double* Et,
+                               double* mudot, const int64_t* pop_off, const Series& ser,
+                               const int64_t* step, hipStream_t st);
 hipError_t bin_gather_step_f32(const FieldPtrs<float>& f, const Geom& g, const BinPtrs& b,
-                               const WindowPtrs<float>& win, const TlsPtrs& tls,
-                               const int* tls_slot, double* Et, double* mudot,
-                               const int64_t* pop_off, const Series& ser, const int64_t* step,
-                               hipStream_t st);
+                               const WindowPtrs<float>& win, const TlsPtrs& tls, double* Et,
+                               double* mudot, const int64_t* pop_off, const Series& ser,
+                               const int64_t* step, hipStream_t st);
 hipError_t bin_scatter_f64(const FieldPtrs<double>& f, const Geom& g, const BinPtrs& b,
                            const WindowPtrs<double>& win, const double* mudot, hipStream_t st);
 hipError_t bin_scatter_f32(const FieldPtrs<float>& f, const Geom& g, const BinPtrs& b,

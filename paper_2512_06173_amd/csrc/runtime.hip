@@ -13,6 +13,7 @@
 #include <cstring>
 #include <climits>
 #include <string>
+#include <array>
 #include <vector>
 
 #include "launch.h"
@@ -65,6 +66,13 @@ void dfree(P*& p) {
 
 struct mlk_sim {
   mlk_grid_desc desc{};
+  // phase timing: event pool, pending (phase, start event, end event) marks
+  bool timing = false;
+  std::vector<hipEvent_t> events;
+  size_t next_event = 0;
+  std::vector<std::array<int, 3>> marks;
+  double phase_ms[MLK_PHASE_COUNT] = {};
+  int64_t phase_n[MLK_PHASE_COUNT] = {};
   Geom g{};
   bool fp32 = false;
   size_t esz = 8;
@@ -448,6 +456,49 @@ mlk_status reserve_series(mlk_sim* s, int64_t nsteps) {
   return MLK_OK;
 }
 
+// Phase timing: record an event before a phase; `mark_end` records the
+// closing event and keeps the pair until mlk_get_phase_time reads it.
+hipError_t next_event(mlk_sim* s, hipEvent_t* ev) {
+  if (s->next_event == s->events.size()) {
+    hipEvent_t e;
+    hipError_t err = hipEventCreate(&e);
+    if (err != hipSuccess) return err;
+    s->events.push_back(e);
+  }
+  *ev = s->events[s->next_event++];
+  return hipSuccess;
+}
+
+int mark_begin(mlk_sim* s) {
+  if (!s->timing) return -1;
+  hipEvent_t e;
+  if (next_event(s, &e) != hipSuccess) return -1;
+  if (hipEventRecord(e, s->stream) != hipSuccess) return -1;
+  return (int)s->next_event - 1;
+}
+
+void mark_end(mlk_sim* s, int phase, int begin) {
+  if (begin < 0) return;
+  hipEvent_t e;
+  if (next_event(s, &e) != hipSuccess) return;
+  if (hipEventRecord(e, s->stream) != hipSuccess) return;
+  s->marks.push_back({phase, begin, (int)s->next_event - 1});
+}
+
+// Fold the pending marks into the per-phase totals (the stream must be idle).
+hipError_t collect_marks(mlk_sim* s) {
+  for (const auto& m : s->marks) {
+    float ms = 0.f;
+    hipError_t e = hipEventElapsedTime(&ms, s->events[m[1]], s->events[m[2]]);
+    if (e != hipSuccess) return e;
+    s->phase_ms[m[0]] += ms;
+    s->phase_n[m[0]] += 1;
+  }
+  s->marks.clear();
+  s->next_event = 0;
+  return hipSuccess;
+}
+
 // Interior box of the fused sweep: the cells whose own update and recomputed
 // halo avoid every CPML layer (one cell of margin above the low layers).  The
 // cells outside it form the CPML shell.
@@ -468,15 +519,19 @@ mlk_status sweep(mlk_sim* s) {
   if (s->desc.sweep == MLK_SWEEP_FUSED) {
     const FieldPtrs<T> nf = spare_ptrs<T>(s);
     const Box inner = interior_box(s->g);
+    int t0 = mark_begin(s);
+    if constexpr (f32) HIPCHK(sweep_fused_f32(f, nf, s->g, inner, s->kz, s->stream));
+    else HIPCHK(sweep_fused_f64(f, nf, s->g, inner, s->kz, s->stream));
+    mark_end(s, MLK_PHASE_SWEEP, t0);
+    t0 = mark_begin(s);
     if constexpr (f32) {
-      HIPCHK(sweep_fused_f32(f, nf, s->g, inner, s->kz, s->stream));
       HIPCHK(sweep_shell_f32(f, nf, s->g, inner, true, s->stream));
       HIPCHK(sweep_shell_f32(f, nf, s->g, inner, false, s->stream));
     } else {
-      HIPCHK(sweep_fused_f64(f, nf, s->g, inner, s->kz, s->stream));
       HIPCHK(sweep_shell_f64(f, nf, s->g, inner, true, s->stream));
       HIPCHK(sweep_shell_f64(f, nf, s->g, inner, false, s->stream));
     }
+    mark_end(s, MLK_PHASE_SHELL, t0);
     swap_buffers(s);
   } else {
     Box all{};
@@ -484,12 +539,18 @@ mlk_status sweep(mlk_sim* s) {
       all.lo[a] = 0;
       all.hi[a] = s->g.n[a];
     }
+    const int t0 = mark_begin(s);
     if constexpr (f32) HIPCHK(sweep_plain_f32(f, f, s->g, &all, 1, true, true, s->stream));
     else HIPCHK(sweep_plain_f64(f, f, s->g, &all, 1, true, true, s->stream));
+    mark_end(s, MLK_PHASE_SWEEP, t0);
   }
-  const FieldPtrs<T> cur = field_ptrs<T>(s);
-  if constexpr (f32) HIPCHK(sources_f32(cur, s->g, s->src, s->d_step, s->stream));
-  else HIPCHK(sources_f64(cur, s->g, s->src, s->d_step, s->stream));
+  if (s->src.count > 0) {
+    const FieldPtrs<T> cur = field_ptrs<T>(s);
+    const int t0 = mark_begin(s);
+    if constexpr (f32) HIPCHK(sources_f32(cur, s->g, s->src, s->d_step, s->stream));
+    else HIPCHK(sources_f64(cur, s->g, s->src, s->d_step, s->stream));
+    mark_end(s, MLK_PHASE_SOURCES, t0);
+  }
   return MLK_OK;
 }
 
@@ -509,16 +570,19 @@ mlk_status enqueue_steps(mlk_sim* s, int64_t nsteps) {
   for (int64_t q = 0; q < nsteps; ++q) {
     FieldPtrs<T> f = field_ptrs<T>(s);
     if (s->fp.on) {
+      const int t0 = mark_begin(s);
       if constexpr (f32) HIPCHK(flux_save_f32(f, s->g, s->fp, s->stream));
       else HIPCHK(flux_save_f64(f, s->g, s->fp, s->stream));
+      mark_end(s, MLK_PHASE_DETECTORS, t0);
     }
+    int t0 = mark_begin(s);
     if (binned) {
       if constexpr (f32)
-        HIPCHK(bin_gather_step_f32(f, s->g, bins, win, tls, s->d_tls_slot, s->d_Et, s->d_mudot,
-                                   s->d_popoff, ser, s->d_step, s->stream));
+        HIPCHK(bin_gather_step_f32(f, s->g, bins, win, tls, s->d_Et, s->d_mudot, s->d_popoff,
+                                   ser, s->d_step, s->stream));
       else
-        HIPCHK(bin_gather_step_f64(f, s->g, bins, win, tls, s->d_tls_slot, s->d_Et, s->d_mudot,
-                                   s->d_popoff, ser, s->d_step, s->stream));
+        HIPCHK(bin_gather_step_f64(f, s->g, bins, win, tls, s->d_Et, s->d_mudot, s->d_popoff,
+                                   ser, s->d_step, s->stream));
     } else if (tls.count > 0) {
       if constexpr (f32)
         HIPCHK(tls_step_f32(f, s->g, win, tls, s->d_Et, s->d_mudot, s->d_popoff, ser, s->d_step,
@@ -527,8 +591,10 @@ mlk_status enqueue_steps(mlk_sim* s, int64_t nsteps) {
         HIPCHK(tls_step_f64(f, s->g, win, tls, s->d_Et, s->d_mudot, s->d_popoff, ser, s->d_step,
                             s->stream));
     }
+    mark_end(s, MLK_PHASE_EMITTERS, t0);
     STCHK(sweep<T>(s));
     f = field_ptrs<T>(s);
+    t0 = mark_begin(s);
     if (binned) {
       if constexpr (f32) HIPCHK(bin_scatter_f32(f, s->g, bins, win, s->d_mudot, s->stream));
       else HIPCHK(bin_scatter_f64(f, s->g, bins, win, s->d_mudot, s->stream));
@@ -538,13 +604,18 @@ mlk_status enqueue_steps(mlk_sim* s, int64_t nsteps) {
       else
         HIPCHK(scatter_atomic_f64(f, s->g, win, s->nem, s->d_mudot, s->stream));
     }
+    mark_end(s, MLK_PHASE_SCATTER, t0);
+    t0 = mark_begin(s);
     if constexpr (f32) HIPCHK(finish_f32(f, s->g, s->fp, ser, s->d_step, s->stream));
     else HIPCHK(finish_f64(f, s->g, s->fp, ser, s->d_step, s->stream));
+    mark_end(s, MLK_PHASE_DETECTORS, t0);
   }
   return MLK_OK;
 }
 
 void release(mlk_sim* s) {
+  for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
+  s->events.clear();
   for (int c = 0; c < 3; ++c) {
     dfree(s->E[c]);
     dfree(s->H[c]);
@@ -949,6 +1020,39 @@ mlk_status mlk_step(mlk_sim* s, int64_t nsteps) {
   mlk_status st = s->fp32 ? enqueue_steps<float>(s, nsteps) : enqueue_steps<double>(s, nsteps);
   if (st == MLK_OK) s->host_step += nsteps;
   return st;
+}
+
+mlk_status mlk_set_timing(mlk_sim* s, int32_t on) {
+  if (!s) return fail(MLK_EINVAL, "null argument");
+  HIPCHK(hipStreamSynchronize(s->stream));
+  s->marks.clear();
+  s->next_event = 0;
+  for (int p = 0; p < MLK_PHASE_COUNT; ++p) {
+    s->phase_ms[p] = 0.0;
+    s->phase_n[p] = 0;
+  }
+  s->timing = on != 0;
+  return MLK_OK;
+}
+
+mlk_status mlk_get_phase_time(mlk_sim* s, int32_t phase, double* total_ms, int64_t* launches) {
+  if (!s || !total_ms || !launches) return fail(MLK_EINVAL, "null argument");
+  if (phase < 0 || phase >= MLK_PHASE_COUNT) return fail(MLK_EINVAL, "phase %d unknown", phase);
+  HIPCHK(hipStreamSynchronize(s->stream));
+  HIPCHK(collect_marks(s));
+  *total_ms = s->phase_ms[phase];
+  *launches = s->phase_n[phase];
+  return MLK_OK;
+}
+
+mlk_status mlk_get_interior_box(mlk_sim* s, int32_t box[6]) {
+  if (!s || !box) return fail(MLK_EINVAL, "null argument");
+  const Box b = interior_box(s->g);
+  for (int a = 0; a < 3; ++a) {
+    box[a] = b.lo[a];
+    box[3 + a] = b.hi[a];
+  }
+  return MLK_OK;
 }
 
 mlk_status mlk_sync(mlk_sim* s) {

@@ -97,6 +97,9 @@ def lib():
         "mlk_checkpoint_size": (st, [sim, C.POINTER(C.c_size_t)]),
         "mlk_checkpoint_save": (st, [sim, C.c_void_p, C.c_int32]),
         "mlk_checkpoint_load": (st, [sim, C.c_void_p, C.c_int32]),
+        "mlk_set_timing": (st, [sim, C.c_int32]),
+        "mlk_get_phase_time": (st, [sim, C.c_int32, _dp, _lp]),
+        "mlk_get_interior_box": (st, [sim, _ip]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(L, name)
@@ -114,7 +117,8 @@ def exported_symbols():
             "mlk_record_populations", "mlk_step", "mlk_sync", "mlk_step_count", "mlk_get_field",
             "mlk_get_rho", "mlk_get_tls_state", "mlk_get_emitter_io", "mlk_get_series",
             "mlk_get_flux_total", "mlk_checkpoint_size", "mlk_checkpoint_save",
-            "mlk_checkpoint_load"]
+            "mlk_checkpoint_load", "mlk_set_timing", "mlk_get_phase_time",
+            "mlk_get_interior_box"]
 
 
 def _check(st):
@@ -346,10 +350,32 @@ class Simulation:
         _check(lib().mlk_checkpoint_load(self._h, buf.ctypes.data_as(C.c_void_p), MEM_HOST))
 
 
+    # ------------------------------------------------------------ timing
+    def set_timing(self, on=True):
+        """Turn per-phase HIP-event timing of the step loop on or off (clears totals)."""
+        _check(lib().mlk_set_timing(self._h, 1 if on else 0))
+
+    def phase_time(self, phase):
+        """(summed ms, timed launches) of a phase name from PHASES."""
+        ms = C.c_double()
+        n = C.c_int64()
+        _check(lib().mlk_get_phase_time(self._h, PHASES[phase], C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def interior_box(self):
+        """Interior box of the fused sweep, ((lo_x, lo_y, lo_z), (hi_x, hi_y, hi_z))."""
+        b, pb = _i32(np.zeros(6))
+        _check(lib().mlk_get_interior_box(self._h, pb))
+        return tuple(int(v) for v in b[:3]), tuple(int(v) for v in b[3:])
+
+
+PHASES = {"emitters": 0, "sweep": 1, "shell": 2, "sources": 3, "scatter": 4, "detectors": 5}
+
+
 def from_workload(w, pop_every=None, **kw):
     """Build a Simulation from a seeded Workload (paper_2512_06173_amd.workloads)."""
-    sim = Simulation(w.shape, dx=w.dx, courant=w.courant, precision=w.precision, bc=w.bc,
-                     cpml=w.cpml, **kw)
+    kw.setdefault("precision", w.precision)
+    sim = Simulation(w.shape, dx=w.dx, courant=w.courant, bc=w.bc, cpml=w.cpml, **kw)
     if w.eps is not None:
         sim.set_eps(w.eps)
     if w.tls is not None and len(w.tls):

@@ -9,7 +9,7 @@ import pytest
 
 from oracle.oracle import Oracle
 from paper_2512_06173_amd import workloads as W
-from tests.oracle_runner import build_oracle
+from oracle.feed import build_oracle
 
 pytestmark = pytest.mark.gpu
 
