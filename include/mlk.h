@@ -129,12 +129,17 @@ mlk_status mlk_add_tls(mlk_sim* s, int32_t n, const double* pos, const double* s
 
 /* Multilevel emitters with pure dephasing (the open model of Sec. II.B.1):
  * H0 = diag(energies) in its eigenbasis, mu^c = d^c M with M real symmetric,
- * Lindblad operators sqrt(gphi)|k><k| so coherences decay at gphi.  Step =
- * dephasing(dt/2) o exp(-i H_eff dt) . exp(+i H_eff dt) o dephasing(dt/2).
+ * Lindblad operators sqrt(gphi)|k><k| so coherences decay at gphi.  One step is
+ * dephasing(dt/2), then rho <- U rho U^+ with U = exp(-i H_eff dt) (exact for
+ * piecewise-constant E~), then dephasing(dt/2); mu_dot = Tr(rho_dot mu) at the
+ * new state (eq. dipole_derivative).  The state is kept in FP64 in both modes.
  * Host arrays: nlev[n] in 2..6 (else EUNSUPPORTED); energies packed with
- * offsets eoff[n]; M (nlev^2 row-major) and rho0 (nlev^2 complex, re/im
- * interleaved) packed with offsets moff[n] (in entries); dipole[3n],
- * gphi[n], pos[3n], sigma[n], gamma[n] as for mlk_add_tls. */
+ * offsets eoff[n]; M (nlev^2 row-major, exactly symmetric) and rho0 (nlev^2
+ * complex, re/im interleaved; Hermitian, unit trace, else EINVAL) packed with
+ * offsets moff[n] (in entries); dipole[3n], gphi[n] >= 0, pos[3n], sigma[n],
+ * gamma[n] as for mlk_add_tls.  The arrays are copied.  Ids are contiguous from
+ * *first_id and shared with the two-level emitters; populations Re rho_kk,
+ * k = 1..nlev-1, follow the emitter's earlier ones in a population record. */
 mlk_status mlk_add_multilevel(mlk_sim* s, int32_t n, const int32_t* nlev, const int64_t* eoff,
                               const int64_t* moff, const double* energies, const double* mop,
                               const double* dipole, const double* gphi, const double* rho0,

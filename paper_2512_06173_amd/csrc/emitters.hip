@@ -1,24 +1,20 @@
-// Emitter phase: kernel windows, field gather, density-matrix step, dipole
-// rate, and the current scatter.
+// Emitter set-up and the atomic scatter variant.
 //
-// Gather (eq. E_regu_Emi):  E~_m^c = gamma_m sum_p w^c_{m,p} E_c(p), where the
-// weights are the Gaussian exp(-|p - r|^2 / 2 sigma^2) sampled at the Yee points
-// of component c inside a box of half-width R sigma and normalised to unit sum
-// (the discrete unit-integral kernel of eq. Polarization_mol).  The box and the
-// Gaussian are separable, so each emitter stores three normalised 1-D weight
-// vectors per component and a window weight is their product.
+// Windows (eq. Polarization_mol, eq. E_regu_Emi): for component c the weights are
+// the Gaussian exp(-|p - r|^2 / 2 sigma^2) sampled at the Yee points of c inside a
+// box of half-width R sigma and normalised to unit sum (the discrete unit-integral
+// kernel).  The box and the Gaussian are separable, so each emitter stores three
+// normalised 1-D weight vectors per component and a window weight is their
+// product; k_records repacks them as the union-window records of the binned
+// kernels.
 //
-// Two-level step (eq. von-Neumann-tls, basic TLS: no Lindblad term): with E~
-// held at its midpoint value, H = (w0/2) I + h.sigma, h = (-E~.d, 0, -w0/2),
-// the Bloch vector r = (2 Re rho01, -2 Im rho01, 1 - 2 rho11) rotates about h
-// by the angle 2|h|dt (exact for piecewise-constant E~).  Dipole rate (eq.
-// dipole_derivative, closed form): mu_dot = -2 w0 Im(rho01) d.
-//
-// Scatter (eqs. J_mol, Polarization_mol): E_c(p) -= (dt/eps_r) gamma mu_dot^c w / dx^3.
+// Atomic scatter (eqs. J_mol, Polarization_mol): E_c(p) -= (dt/eps_r) gamma mu_dot^c
+// w / dx^3 with one wavefront per emitter and floating-point atomics: the sum
+// order is not fixed, so results agree with the owner-computes scatter only to
+// rounding.
 #include <climits>
 
 #include "mlk_internal.h"
-#include "tls_math.h"
 
 namespace mlk {
 
@@ -27,11 +23,6 @@ __device__ __forceinline__ int wrap_index(int q, int n) {
   return r < 0 ? r + n : r;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
 
 // One thread per (emitter, axis, position variant): window start, length and
 // the normalised 1-D Gaussian weights along that axis.  The window holds the
@@ -120,69 +111,6 @@ __global__ void k_records(int count, const int* lo, const int* len, const T* w, 
   }
 }
 
-// Partial gather of component c for emitter e by one lane: the lane owns
-// (y,z) window rows lane, lane+64, ... and sums along x.
-template <typename T>
-__device__ __forceinline__ double gather_rows(const T* Ec, const Geom& g, const WindowPtrs<T>& win,
-                                              int e, int c, int lane) {
-  const int sx = win_slot(e, 0, c == 0), sy = win_slot(e, 1, c == 1), sz = win_slot(e, 2, c == 2);
-  const int lx = win.lo[sx], ly = win.lo[sy], lz = win.lo[sz];
-  const int Lx = win.len[sx], Ly = win.len[sy], Lz = win.len[sz];
-  const T* wx = win.w + (size_t)sx * kMaxWin;
-  const T* wy = win.w + (size_t)sy * kMaxWin;
-  const T* wz = win.w + (size_t)sz * kMaxWin;
-  double s = 0.0;
-  for (int q = lane; q < Ly * Lz; q += 64) {
-    const int dy = q % Ly, dz = q / Ly;
-    const int jj = wrap_index(ly + dy, g.n[1]);
-    const int kk = wrap_index(lz + dz, g.n[2]);
-    const size_t row = (size_t)g.n[0] * ((size_t)jj + (size_t)g.n[1] * (size_t)kk);
-    double sx2 = 0.0;
-    for (int dx = 0; dx < Lx; ++dx) {
-      const int ii = wrap_index(lx + dx, g.n[0]);
-      sx2 += (double)wx[dx] * (double)Ec[row + ii];
-    }
-    s += (double)wy[dy] * (double)wz[dz] * sx2;
-  }
-  return s;
-}
-
-// One wavefront per two-level emitter: gather E~ from E^n, advance
-// rho^{n-1/2} -> rho^{n+1/2}, evaluate mu_dot^{n+1/2}, record the population.
-template <typename T>
-__global__ __launch_bounds__(256) void k_tls_gather_step(FieldPtrs<T> f, Geom g,
-                                                         WindowPtrs<T> win, TlsPtrs tls,
-                                                         double* Et, double* mudot,
-                                                         const int64_t* pop_off, Series ser,
-                                                         const int64_t* step) {
-  const int lane = threadIdx.x & 63;
-  const int m = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6);
-  if (m >= tls.count) return;
-  const int e = tls.gid[m];
-  double acc[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) acc[c] = wave_sum(gather_rows(f.E[c], g, win, e, c, lane));
-  if (lane != 0) return;
-  const double gm = win.gamma[e];
-  const double et[3] = {gm * acc[0], gm * acc[1], gm * acc[2]};
-  const double d[3] = {tls.dip[3 * m], tls.dip[3 * m + 1], tls.dip[3 * m + 2]};
-  double st[3] = {tls.rho[3 * m], tls.rho[3 * m + 1], tls.rho[3 * m + 2]};
-  double md[3];
-  tls_advance(tls.omega0[m], d, et, g.dt, st, md);
-  tls.rho[3 * m] = st[0];
-  tls.rho[3 * m + 1] = st[1];
-  tls.rho[3 * m + 2] = st[2];
-  for (int c = 0; c < 3; ++c) {
-    Et[3 * e + c] = et[c];
-    mudot[3 * e + c] = md[c];
-  }
-  if (ser.pop_every > 0) {
-    const int64_t n = *step;
-    if (n % ser.pop_every == 0) ser.pop[(n / ser.pop_every) * ser.npop + pop_off[e]] = st[0];
-  }
-}
-
-// Scatter with device-wide atomics: one wavefront per emitter.
 template <typename T>
 __global__ __launch_bounds__(256) void k_scatter_atomic(FieldPtrs<T> f, Geom g, WindowPtrs<T> win,
                                                         int count, const double* mudot) {
@@ -250,30 +178,6 @@ hipError_t records_f32(int count, const int* lo, const int* len, const float* w,
 hipError_t windows_f32(int count, const double* pos, const double* sigma, double R, const Geom& g,
                        int* lo, int* len, float* w, hipStream_t st) {
   return launch_windows<float>(count, pos, sigma, R, g, lo, len, w, st);
-}
-
-template <typename T>
-static hipError_t launch_tls(const FieldPtrs<T>& f, const Geom& g, const WindowPtrs<T>& win,
-                             const TlsPtrs& tls, double* Et, double* mudot,
-                             const int64_t* pop_off, const Series& ser, const int64_t* step,
-                             hipStream_t st) {
-  if (tls.count <= 0) return hipSuccess;
-  const int waves_per_block = 4;
-  const int blocks = (tls.count + waves_per_block - 1) / waves_per_block;
-  hipLaunchKernelGGL(k_tls_gather_step<T>, dim3(blocks), dim3(64 * waves_per_block), 0, st, f, g,
-                     win, tls, Et, mudot, pop_off, ser, step);
-  return hipGetLastError();
-}
-
-hipError_t tls_step_f64(const FieldPtrs<double>& f, const Geom& g, const WindowPtrs<double>& win,
-                        const TlsPtrs& tls, double* Et, double* mudot, const int64_t* pop_off,
-                        const Series& ser, const int64_t* step, hipStream_t st) {
-  return launch_tls<double>(f, g, win, tls, Et, mudot, pop_off, ser, step, st);
-}
-hipError_t tls_step_f32(const FieldPtrs<float>& f, const Geom& g, const WindowPtrs<float>& win,
-                        const TlsPtrs& tls, double* Et, double* mudot, const int64_t* pop_off,
-                        const Series& ser, const int64_t* step, hipStream_t st) {
-  return launch_tls<float>(f, g, win, tls, Et, mudot, pop_off, ser, step, st);
 }
 
 template <typename T>

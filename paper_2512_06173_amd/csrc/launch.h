@@ -20,6 +20,10 @@ hipError_t sweep_shell_f64(const FieldPtrs<double>& in, const FieldPtrs<double>&
                            const Geom& g, const Box& inner, bool h_pass, hipStream_t st);
 hipError_t sweep_shell_f32(const FieldPtrs<float>& in, const FieldPtrs<float>& out, const Geom& g,
                            const Box& inner, bool h_pass, hipStream_t st);
+// Multilevel step of every slot; range[n]..range[n+1] are the slots with n levels.
+hipError_t ml_step(const MlDev& ml, const int* range, double dt, const double* Et, double* mudot,
+                   const int64_t* pop_off, const Series& ser, const int64_t* step,
+                   hipStream_t st);
 hipError_t sources_f64(const FieldPtrs<double>& f, const Geom& g, const SourceSet& src,
                        const int64_t* step, hipStream_t st);
 hipError_t sources_f32(const FieldPtrs<float>& f, const Geom& g, const SourceSet& src,
@@ -37,12 +41,6 @@ hipError_t records_f64(int count, const int* lo, const int* len, const double* w
                        WinRec<double>* rec, hipStream_t st);
 hipError_t records_f32(int count, const int* lo, const int* len, const float* w,
                        WinRec<float>* rec, hipStream_t st);
-hipError_t tls_step_f64(const FieldPtrs<double>& f, const Geom& g, const WindowPtrs<double>& win,
-                        const TlsPtrs& tls, double* Et, double* mudot, const int64_t* pop_off,
-                        const Series& ser, const int64_t* step, hipStream_t st);
-hipError_t tls_step_f32(const FieldPtrs<float>& f, const Geom& g, const WindowPtrs<float>& win,
-                        const TlsPtrs& tls, double* Et, double* mudot, const int64_t* pop_off,
-                        const Series& ser, const int64_t* step, hipStream_t st);
 hipError_t scatter_atomic_f64(const FieldPtrs<double>& f, const Geom& g,
                               const WindowPtrs<double>& win, int count, const double* mudot,
                               hipStream_t st);

@@ -169,17 +169,18 @@ struct TlsPtrs {
   double* rho;             // [3M] rho11, Re rho01, Im rho01
 };
 
-struct MlPtrs {
+// Multilevel emitters on the device, structure-of-arrays over the slots
+// (slot = entry index; slots are grouped by level count).  Matrices sit in a
+// kMaxLevels x kMaxLevels frame: entry (a, b) of slot m is at
+// (a * kMaxLevels + b) * count + m (complex: re at 2q, im at 2q + 1).
+struct MlDev {
   int count;
-  const int* gid;          // [M] emitter id of each multilevel emitter
-  const int* nlev;         // [M]
-  const int64_t* eoff;     // energies offset
-  const int64_t* moff;     // matrix offset (entries)
-  const double* energies;
-  const double* mop;
-  const double* dip;       // [3M]
-  const double* gphi;      // [M]
-  double* rho;             // complex n*n interleaved, at 2*moff
+  const int* gid;       // [count] emitter id
+  const double* en;     // [kMaxLevels][count] H0 eigenvalues
+  const double* M;      // [kMaxLevels^2][count] real symmetric
+  const double* dip;    // [3][count]
+  const double* gphi;   // [count]
+  double* rho;          // [2 kMaxLevels^2][count]
 };
 
 struct Series {

@@ -98,6 +98,17 @@ struct mlk_sim {
   std::vector<int> tls_gid;
   std::vector<int> tls_slot;  // by emitter id: index among two-level emitters, or -1
   std::vector<double> tls_w0, tls_dip, tls_rho0;
+  // multilevel emitters, host mirror in add order (matrices in a kMaxLevels frame)
+  std::vector<int> ml_gid, ml_nlev;
+  std::vector<double> ml_en, ml_M, ml_dip, ml_gphi, ml_rho0;  // 6, 36, 3, 1, 72 per emitter
+  std::vector<int> ml_slot;   // by emitter id: device slot among multilevel emitters, or -1
+  int ml_range[kMaxLevels + 2] = {};  // device slots with n levels: ml_range[n]..ml_range[n+1]
+  int* d_ml_gid = nullptr;
+  double* d_ml_en = nullptr;
+  double* d_ml_M = nullptr;
+  double* d_ml_dip = nullptr;
+  double* d_ml_gphi = nullptr;
+  double* d_ml_rho = nullptr;
   // device emitter tables
   int* d_wlo = nullptr;
   int* d_wlen = nullptr;
@@ -363,6 +374,58 @@ mlk_status build_bins(mlk_sim* s) {
   return MLK_OK;
 }
 
+// Device layout of the multilevel emitters: slots sorted by level count (stable
+// in id order), every array entry-major over the slots.
+mlk_status upload_multilevel(mlk_sim* s) {
+  const int nml = (int)s->ml_gid.size();
+  s->ml_slot.assign(s->nem, -1);
+  for (int& r : s->ml_range) r = 0;
+  if (nml == 0) return MLK_OK;
+  std::vector<int> order(nml);
+  for (int q = 0; q < nml; ++q) order[q] = q;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return s->ml_nlev[x] < s->ml_nlev[y]; });
+  constexpr int L = kMaxLevels;
+  std::vector<int> gid(nml);
+  std::vector<double> en((size_t)L * nml, 0.0), M((size_t)L * L * nml, 0.0),
+      dip((size_t)3 * nml), gphi(nml), rho((size_t)2 * L * L * nml, 0.0);
+  for (int m = 0; m < nml; ++m) {
+    const int q = order[m];
+    gid[m] = s->ml_gid[q];
+    s->ml_slot[gid[m]] = m;
+    for (int a = 0; a < L; ++a) en[(size_t)a * nml + m] = s->ml_en[(size_t)L * q + a];
+    for (int a = 0; a < L * L; ++a) M[(size_t)a * nml + m] = s->ml_M[(size_t)L * L * q + a];
+    for (int a = 0; a < 2 * L * L; ++a)
+      rho[(size_t)a * nml + m] = s->ml_rho0[(size_t)2 * L * L * q + a];
+    for (int c = 0; c < 3; ++c) dip[(size_t)c * nml + m] = s->ml_dip[3 * q + c];
+    gphi[m] = s->ml_gphi[q];
+  }
+  for (int n = 0; n <= L + 1; ++n) {
+    int c = 0;
+    for (int m = 0; m < nml; ++m) c += s->ml_nlev[order[m]] < n;
+    s->ml_range[n] = c;
+  }
+  STCHK(upload(&s->d_ml_gid, gid));
+  STCHK(upload(&s->d_ml_en, en));
+  STCHK(upload(&s->d_ml_M, M));
+  STCHK(upload(&s->d_ml_dip, dip));
+  STCHK(upload(&s->d_ml_gphi, gphi));
+  STCHK(upload(&s->d_ml_rho, rho));
+  return MLK_OK;
+}
+
+MlDev ml_dev(mlk_sim* s) {
+  MlDev d{};
+  d.count = (int)s->ml_gid.size();
+  d.gid = s->d_ml_gid;
+  d.en = s->d_ml_en;
+  d.M = s->d_ml_M;
+  d.dip = s->d_ml_dip;
+  d.gphi = s->d_ml_gphi;
+  d.rho = s->d_ml_rho;
+  return d;
+}
+
 // Rebuild every device emitter table from the host mirror (set-up only).
 mlk_status rebuild_emitters(mlk_sim* s) {
   HIPCHK(hipStreamSynchronize(s->stream));
@@ -376,6 +439,7 @@ mlk_status rebuild_emitters(mlk_sim* s) {
   STCHK(upload(&s->d_tls_w0, s->tls_w0));
   STCHK(upload(&s->d_tls_dip, s->tls_dip));
   STCHK(upload(&s->d_tls_rho, s->tls_rho0));
+  STCHK(upload_multilevel(s));
   dfree(s->d_wlo);
   dfree(s->d_wlen);
   dfree(s->d_w);
@@ -567,6 +631,7 @@ mlk_status enqueue_steps(mlk_sim* s, int64_t nsteps) {
   constexpr bool f32 = sizeof(T) == 4;
   const bool binned = s->desc.scatter == MLK_SCATTER_OWNER && s->nem > 0;
   const BinPtrs bins = bin_ptrs(s);
+  const MlDev ml = ml_dev(s);
   for (int64_t q = 0; q < nsteps; ++q) {
     FieldPtrs<T> f = field_ptrs<T>(s);
     if (s->fp.on) {
@@ -576,20 +641,17 @@ mlk_status enqueue_steps(mlk_sim* s, int64_t nsteps) {
       mark_end(s, MLK_PHASE_DETECTORS, t0);
     }
     int t0 = mark_begin(s);
-    if (binned) {
+    if (s->nem > 0) {
+      // gather of every emitter, then the two-level and the multilevel steps
       if constexpr (f32)
         HIPCHK(bin_gather_step_f32(f, s->g, bins, win, tls, s->d_Et, s->d_mudot, s->d_popoff,
                                    ser, s->d_step, s->stream));
       else
         HIPCHK(bin_gather_step_f64(f, s->g, bins, win, tls, s->d_Et, s->d_mudot, s->d_popoff,
                                    ser, s->d_step, s->stream));
-    } else if (tls.count > 0) {
-      if constexpr (f32)
-        HIPCHK(tls_step_f32(f, s->g, win, tls, s->d_Et, s->d_mudot, s->d_popoff, ser, s->d_step,
-                            s->stream));
-      else
-        HIPCHK(tls_step_f64(f, s->g, win, tls, s->d_Et, s->d_mudot, s->d_popoff, ser, s->d_step,
-                            s->stream));
+      if (ml.count > 0)
+        HIPCHK(ml_step(ml, s->ml_range, s->g.dt, s->d_Et, s->d_mudot, s->d_popoff, ser,
+                       s->d_step, s->stream));
     }
     mark_end(s, MLK_PHASE_EMITTERS, t0);
     STCHK(sweep<T>(s));
@@ -640,6 +702,12 @@ void release(mlk_sim* s) {
   dfree(s->d_tls_w0);
   dfree(s->d_tls_dip);
   dfree(s->d_tls_rho);
+  dfree(s->d_ml_gid);
+  dfree(s->d_ml_en);
+  dfree(s->d_ml_M);
+  dfree(s->d_ml_dip);
+  dfree(s->d_ml_gphi);
+  dfree(s->d_ml_rho);
   dfree(s->d_gbin_org);
   dfree(s->d_gbin_start);
   dfree(s->d_gbin_em);
@@ -671,6 +739,8 @@ std::vector<Piece> state_pieces(mlk_sim* s) {
   for (int c = 0; c < 3; ++c) v.push_back({s->H[c], s->ncell * s->esz});
   if (s->psi) v.push_back({s->psi, psi_total(s->g) * s->esz});
   if (!s->tls_gid.empty()) v.push_back({s->d_tls_rho, s->tls_gid.size() * 3 * sizeof(double)});
+  if (!s->ml_gid.empty())
+    v.push_back({s->d_ml_rho, s->ml_gid.size() * 2 * kMaxLevels * kMaxLevels * sizeof(double)});
   if (s->nem > 0) {
     v.push_back({s->d_Et, (size_t)s->nem * 3 * sizeof(double)});
     v.push_back({s->d_mudot, (size_t)s->nem * 3 * sizeof(double)});
@@ -912,12 +982,70 @@ mlk_status mlk_add_tls(mlk_sim* s, int32_t n, const double* pos, const double* s
   return rebuild_emitters(s);
 }
 
-mlk_status mlk_add_multilevel(mlk_sim* s, int32_t, const int32_t*, const int64_t*,
-                              const int64_t*, const double*, const double*, const double*,
-                              const double*, const double*, const double*, const double*,
-                              const double*, int32_t*) {
-  if (!s) return fail(MLK_EINVAL, "null argument");
-  return fail(MLK_EUNSUPPORTED, "multilevel emitters are not built yet");
+mlk_status mlk_add_multilevel(mlk_sim* s, int32_t n, const int32_t* nlev, const int64_t* eoff,
+                              const int64_t* moff, const double* energies, const double* mop,
+                              const double* dipole, const double* gphi, const double* rho0,
+                              const double* pos, const double* sigma, const double* gamma,
+                              int32_t* first_id) {
+  if (!s || !nlev || !eoff || !moff || !energies || !mop || !dipole || !gphi || !rho0 || !pos ||
+      !sigma || !gamma)
+    return fail(MLK_EINVAL, "null argument");
+  if (n < 0) return fail(MLK_EINVAL, "negative count");
+  if (s->host_step > 0) return fail(MLK_ESTATE, "emitters must be added before stepping");
+  for (int q = 0; q < n; ++q) {
+    const int L = nlev[q];
+    if (L < 2 || L > kMaxLevels)
+      return fail(MLK_EUNSUPPORTED, "emitter %d: %d levels (2..%d supported)", q, L, kMaxLevels);
+    if (eoff[q] < 0 || moff[q] < 0) return fail(MLK_EINVAL, "emitter %d: negative offset", q);
+    STCHK(check_emitter_geometry(s, pos + 3 * q, sigma[q]));
+    if (!(gphi[q] >= 0.0) || !std::isfinite(gphi[q]) || !std::isfinite(gamma[q]))
+      return fail(MLK_EINVAL, "emitter %d: parameters not finite or negative dephasing", q);
+    const double* E = energies + eoff[q];
+    const double* M = mop + moff[q];
+    const double* r = rho0 + 2 * moff[q];
+    double trace = 0.0;
+    for (int a = 0; a < L; ++a) {
+      if (!std::isfinite(E[a])) return fail(MLK_EINVAL, "emitter %d: energy not finite", q);
+      trace += r[2 * (a * L + a)];
+      if (!(r[2 * (a * L + a)] >= -1e-12) || std::fabs(r[2 * (a * L + a) + 1]) > 1e-12)
+        return fail(MLK_EINVAL, "emitter %d: initial state is not a density matrix", q);
+      for (int b = 0; b < L; ++b) {
+        if (!std::isfinite(M[a * L + b]) || M[a * L + b] != M[b * L + a])
+          return fail(MLK_EINVAL, "emitter %d: dipole matrix not real symmetric", q);
+        const double dre = r[2 * (a * L + b)] - r[2 * (b * L + a)];
+        const double dim = r[2 * (a * L + b) + 1] + r[2 * (b * L + a) + 1];
+        if (!(std::fabs(dre) <= 1e-12 && std::fabs(dim) <= 1e-12))
+          return fail(MLK_EINVAL, "emitter %d: initial state is not Hermitian", q);
+      }
+    }
+    if (!(std::fabs(trace - 1.0) <= 1e-10))
+      return fail(MLK_EINVAL, "emitter %d: initial state has trace %g", q, trace);
+  }
+  if (first_id) *first_id = s->nem;
+  constexpr int F = kMaxLevels;
+  for (int q = 0; q < n; ++q) {
+    const int e = s->nem++;
+    const int L = nlev[q];
+    for (int a = 0; a < 3; ++a) s->pos.push_back(pos[3 * q + a]);
+    s->sigma.push_back(sigma[q]);
+    s->gamma.push_back(gamma[q]);
+    s->pop_off.push_back(s->npop);
+    s->npop += L - 1;
+    s->tls_slot.push_back(-1);
+    s->ml_gid.push_back(e);
+    s->ml_nlev.push_back(L);
+    for (int a = 0; a < F; ++a) s->ml_en.push_back(a < L ? energies[eoff[q] + a] : 0.0);
+    for (int a = 0; a < F; ++a)
+      for (int b = 0; b < F; ++b)
+        s->ml_M.push_back(a < L && b < L ? mop[moff[q] + a * L + b] : 0.0);
+    for (int a = 0; a < F; ++a)
+      for (int b = 0; b < F; ++b)
+        for (int c = 0; c < 2; ++c)
+          s->ml_rho0.push_back(a < L && b < L ? rho0[2 * (moff[q] + a * L + b) + c] : 0.0);
+    for (int c = 0; c < 3; ++c) s->ml_dip.push_back(dipole[3 * q + c]);
+    s->ml_gphi.push_back(gphi[q]);
+  }
+  return rebuild_emitters(s);
 }
 
 static mlk_status add_source(mlk_sim* s, const Source& src) {
@@ -1109,6 +1237,24 @@ mlk_status mlk_get_tls_state(mlk_sim* s, int32_t first, int32_t count, double* d
 mlk_status mlk_get_rho(mlk_sim* s, int32_t id, double* dst, int32_t cap, int32_t* nlev) {
   if (!s || !dst) return fail(MLK_EINVAL, "null argument");
   if (id < 0 || id >= s->nem) return fail(MLK_EINVAL, "bad emitter id");
+  const int slot = s->ml_slot.empty() ? -1 : s->ml_slot[id];
+  if (slot >= 0) {
+    int n = 2;
+    for (int k = 2; k <= kMaxLevels; ++k)
+      if (slot >= s->ml_range[k] && slot < s->ml_range[k + 1]) n = k;
+    if (cap < 2 * n * n) return fail(MLK_EINVAL, "dst too small");
+    HIPCHK(hipStreamSynchronize(s->stream));
+    const size_t cnt = s->ml_gid.size();
+    for (int a = 0; a < n; ++a)
+      for (int b = 0; b < n; ++b)
+        for (int c = 0; c < 2; ++c) {
+          const size_t q = (size_t)(2 * (a * kMaxLevels + b) + c) * cnt + slot;
+          HIPCHK(hipMemcpy(dst + 2 * (a * n + b) + c, s->d_ml_rho + q, sizeof(double),
+                           hipMemcpyDeviceToHost));
+        }
+    if (nlev) *nlev = n;
+    return MLK_OK;
+  }
   double st[3];
   STCHK(mlk_get_tls_state(s, id, 1, st));
   if (cap < 8) return fail(MLK_EINVAL, "dst too small");

@@ -282,3 +282,75 @@ def test_shell_and_interior_regions_fp64(sweep):
     w.pop_every = 2
     sim, ora = run_both(w, sweep=sweep)
     check(sim, ora, w)
+
+
+def _small_bragg(precision, n_emit=48, steps=300, dmag=0.2, gphi=1e-3, seed=3):
+    w = W.bragg(nx=16, ny=16, nz=112, n_emit=n_emit, steps=steps, pairs_per_mirror=3,
+                precision=precision, seed=seed)
+    ml = w.multilevel
+    ml.dipole = ml.dipole * (dmag / 0.01)
+    ml.gphi = np.full(len(ml), gphi)
+    w.pop_every = 3
+    return w
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_bragg_multilevel(precision):
+    """Multilevel (2-6 level) Lindblad emitters in a small Bragg resonator, periodic
+    x/y, CPML z, a probe in the defect."""
+    w = _small_bragg(precision)
+    sim, ora = run_both(w)
+    check(sim, ora, w)
+    if precision == "fp64":
+        for m in (0, 7, len(w.multilevel) - 1):
+            d = np.max(np.abs(sim.rho(m) - ora.rho(m)))
+            say(f"  rho[{m}] max abs = {d:.3e}")
+            assert d <= 1e-12
+
+
+def test_multilevel_strong_dephasing_fp64():
+    w = _small_bragg("fp64", n_emit=20, steps=200, dmag=0.3, gphi=0.05, seed=11)
+    sim, ora = run_both(w)
+    check(sim, ora, w)
+
+
+def test_two_level_multilevel_matches_tls_path_fp64():
+    """A two-level emitter entered as a multilevel one (M = sigma_x, E = (0, w0), no
+    dephasing) takes the same step as the two-level kernel."""
+    rng = np.random.default_rng(5)
+    n, M = 24, 6
+    pos = rng.uniform(8, 16, size=(M, 3))
+    w0 = rng.uniform(0.24, 0.26, M)
+    dip = 0.3 * rng.standard_normal((M, 3))
+    c = np.sqrt(0.5)
+    runs = []
+    for kind in ("tls", "ml"):
+        sim = mlk().Simulation((n, n, n), precision="fp64")
+        if kind == "tls":
+            sim.add_tls(pos, np.ones(M), np.ones(M), w0, dip, np.tile([0.5, 0.5, 0.0], (M, 1)))
+        else:
+            rho = np.array([[0.5, 0.5], [0.5, 0.5]], dtype=complex)
+            sim.add_multilevel([2] * M, [np.array([0.0, w]) for w in w0],
+                               [np.array([[0.0, 1.0], [1.0, 0.0]])] * M, dip, np.zeros(M),
+                               [rho] * M, pos, np.ones(M), np.ones(M))
+        sim.record_populations(1)
+        sim.step(200)
+        runs.append((sim.fields(), sim.populations()))
+    e = rel_l2(runs[0][0], runs[1][0])
+    d = np.max(np.abs(runs[0][1] - runs[1][1]))
+    say(f"  tls vs multilevel: fields rel L2 {e:.3e}, populations {d:.3e}")
+    assert e <= 1e-12 and d <= 1e-12
+
+
+def test_mixed_tls_and_multilevel_fp64():
+    w = _small_bragg("fp64", n_emit=16, steps=200, seed=4)
+    rng = np.random.default_rng(9)
+    zc = w.multilevel.pos[:, 2].mean()
+    Mt = 10
+    pos = np.column_stack([rng.uniform(0, 16, Mt), rng.uniform(0, 16, Mt),
+                           rng.uniform(zc - 5, zc + 5, Mt)])
+    w.tls = W.TLSSet(pos=pos, sigma=np.ones(Mt), gamma=np.ones(Mt),
+                     omega0=rng.uniform(0.24, 0.26, Mt), dipole=0.2 * rng.standard_normal((Mt, 3)),
+                     rho0=np.tile([0.5, 0.5, 0.0], (Mt, 1)))
+    sim, ora = run_both(w)
+    check(sim, ora, w)
