@@ -193,9 +193,10 @@ mlk_status mlk_checkpoint_save(mlk_sim* s, void* dst, int32_t mem_kind);
 mlk_status mlk_checkpoint_load(mlk_sim* s, const void* src, int32_t mem_kind);
 
 /* Per-phase timing of the step loop with HIP events recorded on the sim's
- * stream around each phase of every step (off by default; turning it on
- * costs one event pair per phase per step).  mlk_set_timing(s, on) also
- * clears the accumulated times.  mlk_get_phase_time waits for the stream and
+ * stream around the timed phases of every step (off by default; each timed
+ * phase costs one event pair per step).  mlk_set_timing(s, phases) times the
+ * phases whose bit (1 << MLK_PHASE_x) is set in `phases` (0: off,
+ * MLK_TIMING_ALL: every phase) and clears the accumulated times.  mlk_get_phase_time waits for the stream and
  * returns, for one phase, the summed elapsed time in ms and the number of
  * timed launches of it.  Phases:
  *   EMITTERS      field gather + emitter step + dipole rate (steps 2-4)
@@ -212,7 +213,8 @@ enum {
   MLK_PHASE_SOURCES = 3,
   MLK_PHASE_SCATTER = 4,
   MLK_PHASE_DETECTORS = 5,
-  MLK_PHASE_COUNT = 6
+  MLK_PHASE_COUNT = 6,
+  MLK_TIMING_ALL = (1 << 6) - 1
 };
 mlk_status mlk_set_timing(mlk_sim* s, int32_t on);
 mlk_status mlk_get_phase_time(mlk_sim* s, int32_t phase, double* total_ms, int64_t* launches);

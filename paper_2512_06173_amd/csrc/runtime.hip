@@ -67,7 +67,7 @@ void dfree(P*& p) {
 struct mlk_sim {
   mlk_grid_desc desc{};
   // phase timing: event pool, pending (phase, start event, end event) marks
-  bool timing = false;
+  int timing = 0;  // bit p set: phase p is timed
   std::vector<hipEvent_t> events;
   size_t next_event = 0;
   std::vector<std::array<int, 3>> marks;
@@ -533,8 +533,8 @@ hipError_t next_event(mlk_sim* s, hipEvent_t* ev) {
   return hipSuccess;
 }
 
-int mark_begin(mlk_sim* s) {
-  if (!s->timing) return -1;
+int mark_begin(mlk_sim* s, int phase) {
+  if (!(s->timing & (1 << phase))) return -1;
   hipEvent_t e;
   if (next_event(s, &e) != hipSuccess) return -1;
   if (hipEventRecord(e, s->stream) != hipSuccess) return -1;
@@ -583,11 +583,11 @@ mlk_status sweep(mlk_sim* s) {
   if (s->desc.sweep == MLK_SWEEP_FUSED) {
     const FieldPtrs<T> nf = spare_ptrs<T>(s);
     const Box inner = interior_box(s->g);
-    int t0 = mark_begin(s);
+    int t0 = mark_begin(s, MLK_PHASE_SWEEP);
     if constexpr (f32) HIPCHK(sweep_fused_f32(f, nf, s->g, inner, s->kz, s->stream));
     else HIPCHK(sweep_fused_f64(f, nf, s->g, inner, s->kz, s->stream));
     mark_end(s, MLK_PHASE_SWEEP, t0);
-    t0 = mark_begin(s);
+    t0 = mark_begin(s, MLK_PHASE_SHELL);
     if constexpr (f32) {
       HIPCHK(sweep_shell_f32(f, nf, s->g, inner, true, s->stream));
       HIPCHK(sweep_shell_f32(f, nf, s->g, inner, false, s->stream));
@@ -603,14 +603,14 @@ mlk_status sweep(mlk_sim* s) {
       all.lo[a] = 0;
       all.hi[a] = s->g.n[a];
     }
-    const int t0 = mark_begin(s);
+    const int t0 = mark_begin(s, MLK_PHASE_SWEEP);
     if constexpr (f32) HIPCHK(sweep_plain_f32(f, f, s->g, &all, 1, true, true, s->stream));
     else HIPCHK(sweep_plain_f64(f, f, s->g, &all, 1, true, true, s->stream));
     mark_end(s, MLK_PHASE_SWEEP, t0);
   }
   if (s->src.count > 0) {
     const FieldPtrs<T> cur = field_ptrs<T>(s);
-    const int t0 = mark_begin(s);
+    const int t0 = mark_begin(s, MLK_PHASE_SOURCES);
     if constexpr (f32) HIPCHK(sources_f32(cur, s->g, s->src, s->d_step, s->stream));
     else HIPCHK(sources_f64(cur, s->g, s->src, s->d_step, s->stream));
     mark_end(s, MLK_PHASE_SOURCES, t0);
@@ -635,12 +635,12 @@ mlk_status enqueue_steps(mlk_sim* s, int64_t nsteps) {
   for (int64_t q = 0; q < nsteps; ++q) {
     FieldPtrs<T> f = field_ptrs<T>(s);
     if (s->fp.on) {
-      const int t0 = mark_begin(s);
+      const int t0 = mark_begin(s, MLK_PHASE_DETECTORS);
       if constexpr (f32) HIPCHK(flux_save_f32(f, s->g, s->fp, s->stream));
       else HIPCHK(flux_save_f64(f, s->g, s->fp, s->stream));
       mark_end(s, MLK_PHASE_DETECTORS, t0);
     }
-    int t0 = mark_begin(s);
+    int t0 = mark_begin(s, MLK_PHASE_EMITTERS);
     if (s->nem > 0) {
       // gather of every emitter, then the two-level and the multilevel steps
       if constexpr (f32)
@@ -656,7 +656,7 @@ mlk_status enqueue_steps(mlk_sim* s, int64_t nsteps) {
     mark_end(s, MLK_PHASE_EMITTERS, t0);
     STCHK(sweep<T>(s));
     f = field_ptrs<T>(s);
-    t0 = mark_begin(s);
+    t0 = mark_begin(s, MLK_PHASE_SCATTER);
     if (binned) {
       if constexpr (f32) HIPCHK(bin_scatter_f32(f, s->g, bins, win, s->d_mudot, s->stream));
       else HIPCHK(bin_scatter_f64(f, s->g, bins, win, s->d_mudot, s->stream));
@@ -667,7 +667,7 @@ mlk_status enqueue_steps(mlk_sim* s, int64_t nsteps) {
         HIPCHK(scatter_atomic_f64(f, s->g, win, s->nem, s->d_mudot, s->stream));
     }
     mark_end(s, MLK_PHASE_SCATTER, t0);
-    t0 = mark_begin(s);
+    t0 = mark_begin(s, MLK_PHASE_DETECTORS);
     if constexpr (f32) HIPCHK(finish_f32(f, s->g, s->fp, ser, s->d_step, s->stream));
     else HIPCHK(finish_f64(f, s->g, s->fp, ser, s->d_step, s->stream));
     mark_end(s, MLK_PHASE_DETECTORS, t0);
@@ -1159,7 +1159,7 @@ mlk_status mlk_set_timing(mlk_sim* s, int32_t on) {
     s->phase_ms[p] = 0.0;
     s->phase_n[p] = 0;
   }
-  s->timing = on != 0;
+  s->timing = on & ((1 << MLK_PHASE_COUNT) - 1);
   return MLK_OK;
 }
 

@@ -351,9 +351,18 @@ class Simulation:
 
 
     # ------------------------------------------------------------ timing
-    def set_timing(self, on=True):
-        """Turn per-phase HIP-event timing of the step loop on or off (clears totals)."""
-        _check(lib().mlk_set_timing(self._h, 1 if on else 0))
+    def set_timing(self, phases=True):
+        """Per-phase HIP-event timing of the step loop (clears totals): True times every
+        phase, False none, or an iterable of names from PHASES."""
+        if phases is True:
+            mask = (1 << len(PHASES)) - 1
+        elif phases is False or phases is None:
+            mask = 0
+        else:
+            mask = 0
+            for name in phases:
+                mask |= 1 << PHASES[name]
+        _check(lib().mlk_set_timing(self._h, mask))
 
     def phase_time(self, phase):
         """(summed ms, timed launches) of a phase name from PHASES."""
