@@ -603,3 +603,49 @@ def test_coupled_energy_stays_bounded():
     assert exchanged > 1e-3 * 0.25
     assert np.max(np.abs(tot - tot[0])) < 0.05 * exchanged
     assert np.isfinite(emit).all()
+
+
+def test_flux_is_the_energy_flow_through_the_plane():
+    """Summation by parts of the Yee updates (PEC walls, no current above the plane)
+    gives exact energy balances for the part of the box above plane k0:
+      region A = every component with index >= k0:
+        W_A^{n+1} - W_A^n = dt sum [Ebar_x(k0) H_y(k0-1) - Ebar_y(k0) H_x(k0-1)]
+      region B = Ex, Ey, Hz with index >= k0+1 and Ez, Hx, Hy with index >= k0:
+        W_B^{n+1} - W_B^n = dt sum [Ebar_x(k0) H_y(k0) - Ebar_y(k0) H_x(k0)]
+    with Ebar = (E^n + E^{n+1})/2, H = H^{n+1/2} and W^n = 1/2 sum eps E^n.E^n +
+    1/2 sum H^{n+1/2}.H^{n-1/2} over the region.  Their mean is dt times the time-centred
+    flux with the z-averaged H, so the flux detector must equal it exactly."""
+    nx, ny, nz, k0, steps = 12, 10, 24, 15, 160
+    rng = np.random.default_rng(21)
+    o = Oracle((nx, ny, nz))
+    eps = np.ones((nz, ny, nx))
+    eps[:k0 - 2] = rng.uniform(1.0, 3.0, (k0 - 2, ny, nx))
+    o.set_eps(eps)
+    o.add_point_source(2, (5, 4, 6), 1.0, 0.4, 4.0, 15.0)
+    o.add_point_source(0, (7, 5, 8), -0.6, 0.3, 5.0, 20.0)
+    o.add_flux_plane(2, k0)
+    states = []
+    for n in range(steps + 2):
+        states.append([o.get_field(c).copy() for c in range(6)])
+        o.step(1)
+    F = o.flux_series()
+
+    def energy(n, lo):
+        # lo[c]: first z index of component c (Ex, Ey, Ez, Hx, Hy, Hz) in the region
+        En, Hm, Hp = states[n][:3], states[n][3:], states[n + 1][3:]
+        w = 0.0
+        for c in range(3):
+            w += 0.5 * np.sum(eps[lo[c]:] * En[c][lo[c]:] ** 2)
+            w += 0.5 * np.sum(Hp[c][lo[3 + c]:] * Hm[c][lo[3 + c]:])
+        return w
+
+    A = (k0, k0, k0, k0, k0, k0)
+    B = (k0 + 1, k0 + 1, k0, k0, k0, k0 + 1)
+    dA = np.array([energy(n + 1, A) - energy(n, A) for n in range(steps)])
+    dB = np.array([energy(n + 1, B) - energy(n, B) for n in range(steps)])
+    dt = 0.5
+    scale = np.max(np.abs(dA)) + np.max(np.abs(dB))
+    assert scale > 0
+    assert np.max(np.abs(0.5 * (dA + dB) - dt * F[:steps])) <= 1e-12 * scale
+    # a wrong half-plane (only one side of the average) is caught
+    assert np.max(np.abs(dA - dt * F[:steps])) > 1e-6 * scale
