@@ -224,6 +224,39 @@ mlk_status mlk_get_phase_time(mlk_sim* s, int32_t phase, double* total_ms, int64
  * layer; the cells outside it are updated by the CPML-shell passes. */
 mlk_status mlk_get_interior_box(mlk_sim* s, int32_t box[6]);
 
+/* ------------------------------------------------------------------ batches
+ * Many independent sims stepped together (each one an independent run of the
+ * method; the batch result equals its members run one by one, bit for bit).
+ * Every phase of a step is one launch over the work of all members, so a
+ * step costs about a dozen launches whatever the number of domains.  Members
+ * must share precision, sweep mode, device and step count, use the
+ * owner-computes scatter, and belong to no other batch; the batch runs on the
+ * first member's stream.  While in a batch a member cannot be destroyed or
+ * re-tuned; its getters wait for the batch's work.  mlk_batch_step enqueues
+ * nsteps steps.  mlk_batch_capture records steps_per_replay steps (even in the
+ * fused mode, whose two field buffers alternate) into a hipGraph;
+ * mlk_batch_replay launches it nreplays times (re-capturing by itself when a
+ * recorded series had to grow).  The sims keep their state and can be stepped
+ * on their own after mlk_batch_destroy. */
+typedef struct mlk_batch mlk_batch;
+mlk_status mlk_batch_create(mlk_sim* const* sims, int32_t n, mlk_batch** out);
+mlk_status mlk_batch_step(mlk_batch* b, int64_t nsteps);
+mlk_status mlk_batch_capture(mlk_batch* b, int64_t steps_per_replay);
+mlk_status mlk_batch_replay(mlk_batch* b, int64_t nreplays);
+mlk_status mlk_batch_sync(mlk_batch* b);
+mlk_status mlk_batch_destroy(mlk_batch* b);
+
+/* Tile shape of the fused sweep: rows per workgroup ty (4 or 8) and z planes
+ * per workgroup kz.  mlk_autotune times every pair on the sim's own grid (the
+ * state is left untouched) and keeps the fastest; with cache_path (NULL: no
+ * cache) results are read from and added to a JSON file keyed by precision,
+ * grid and interior box.  The result does not depend on the tile shape (each
+ * cell's arithmetic is the same), only the speed does.  Plain-sweep sims have
+ * nothing to tune. */
+mlk_status mlk_autotune(mlk_sim* s, const char* cache_path);
+mlk_status mlk_set_tuning(mlk_sim* s, int32_t ty, int32_t kz);
+mlk_status mlk_get_tuning(mlk_sim* s, int32_t* ty, int32_t* kz);
+
 #ifdef __cplusplus
 }
 #endif

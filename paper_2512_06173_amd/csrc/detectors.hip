@@ -21,10 +21,10 @@ __device__ __forceinline__ size_t plane_cell(const Geom& g, int a, int index, in
 }
 
 template <typename T>
-__global__ void k_flux_save(FieldPtrs<T> f, Geom g, FluxPlane fp) {
+__device__ __forceinline__ void flux_save_body(const FieldPtrs<T>& f, const Geom& g,
+                                               const FluxPlane& fp, int t) {
   const int a = fp.axis, u = (a + 1) % 3, v = (a + 2) % 3;
   const int nu = g.n[u], nv = g.n[v];
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nu * nv) return;
   const int iu = t % nu, iv = t / nu;
   const size_t id = plane_cell(g, a, fp.index, iu, iv);
@@ -32,13 +32,15 @@ __global__ void k_flux_save(FieldPtrs<T> f, Geom g, FluxPlane fp) {
   fp.Ev0[t] = (double)f.E[v][id];
 }
 
+// Partial flux of block b of nb (grid-stride over the plane).
 template <typename T>
-__global__ __launch_bounds__(256) void k_flux_partial(FieldPtrs<T> f, Geom g, FluxPlane fp) {
+__device__ __forceinline__ void flux_partial_body(const FieldPtrs<T>& f, const Geom& g,
+                                                  const FluxPlane& fp, int b, int nb) {
   const int a = fp.axis, u = (a + 1) % 3, v = (a + 2) % 3;
   const int nu = g.n[u], nv = g.n[v];
   __shared__ double red[256];
   double s = 0.0;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nu * nv; t += gridDim.x * blockDim.x) {
+  for (int t = b * blockDim.x + threadIdx.x; t < nu * nv; t += nb * blockDim.x) {
     const int iu = t % nu, iv = t / nu;
     const size_t id = plane_cell(g, a, fp.index, iu, iv);
     const size_t jd = plane_cell(g, a, fp.index - 1, iu, iv);
@@ -54,13 +56,14 @@ __global__ __launch_bounds__(256) void k_flux_partial(FieldPtrs<T> f, Geom g, Fl
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) fp.partial[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) fp.partial[b] = red[0];
 }
 
 // Single block: probe samples, the flux total, then the step counter moves on.
 template <typename T>
-__global__ __launch_bounds__(256) void k_finish(FieldPtrs<T> f, Geom g, FluxPlane fp, Series ser,
-                                                int64_t* step) {
+__device__ __forceinline__ void finish_body(const FieldPtrs<T>& f, const Geom& g,
+                                            const FluxPlane& fp, const Series& ser,
+                                            int64_t* step) {
   __shared__ double red[256];
   const int64_t n = *step;
   const int t = threadIdx.x;
@@ -86,6 +89,33 @@ __global__ __launch_bounds__(256) void k_finish(FieldPtrs<T> f, Geom g, FluxPlan
   }
   __syncthreads();
   if (t == 0) *step = n + 1;
+}
+
+template <typename T>
+__global__ void k_flux_save(FieldPtrs<T> f, Geom g, FluxPlane fp) {
+  flux_save_body(f, g, fp, blockIdx.x * blockDim.x + threadIdx.x);
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_flux_partial(FieldPtrs<T> f, Geom g, FluxPlane fp) {
+  flux_partial_body(f, g, fp, blockIdx.x, gridDim.x);
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_finish(FieldPtrs<T> f, Geom g, FluxPlane fp, Series ser,
+                                                int64_t* step) {
+  finish_body(f, g, fp, ser, step);
+}
+
+// Batched forms: kind 0 flux save, 1 flux partials, 2 finish (one block per job).
+template <typename T, int KIND>
+__global__ __launch_bounds__(256) void k_detect_batch(const FluxJob<T>* jobs, const int* start,
+                                                      int njobs) {
+  const int j = find_job(start, njobs, blockIdx.x);
+  const FluxJob<T>& J = jobs[j];
+  const int lb = blockIdx.x - start[j];
+  if (lb >= J.nblocks) return;
+  if (KIND == 0) flux_save_body(J.f, J.g, J.fp, lb * blockDim.x + threadIdx.x);
+  else if (KIND == 1) flux_partial_body(J.f, J.g, J.fp, lb, J.nblocks);
+  else finish_body(J.f, J.g, J.fp, J.ser, J.step);
 }
 
 template <typename T>
@@ -124,6 +154,27 @@ hipError_t finish_f64(const FieldPtrs<double>& f, const Geom& g, const FluxPlane
 hipError_t finish_f32(const FieldPtrs<float>& f, const Geom& g, const FluxPlane& fp,
                       const Series& ser, int64_t* step, hipStream_t st) {
   return launch_finish<float>(f, g, fp, ser, step, st);
+}
+
+template <typename T>
+static hipError_t launch_detect_batch(const FluxJob<T>* jobs, const int* start, int njobs,
+                                      int nblocks, int kind, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  if (kind == 0)
+    hipLaunchKernelGGL((k_detect_batch<T, 0>), dim3(nblocks), dim3(256), 0, st, jobs, start, njobs);
+  else if (kind == 1)
+    hipLaunchKernelGGL((k_detect_batch<T, 1>), dim3(nblocks), dim3(256), 0, st, jobs, start, njobs);
+  else
+    hipLaunchKernelGGL((k_detect_batch<T, 2>), dim3(nblocks), dim3(256), 0, st, jobs, start, njobs);
+  return hipGetLastError();
+}
+hipError_t detect_batch_f64(const FluxJob<double>* jobs, const int* start, int njobs, int nblocks,
+                            int kind, hipStream_t st) {
+  return launch_detect_batch<double>(jobs, start, njobs, nblocks, kind, st);
+}
+hipError_t detect_batch_f32(const FluxJob<float>* jobs, const int* start, int njobs, int nblocks,
+                            int kind, hipStream_t st) {
+  return launch_detect_batch<float>(jobs, start, njobs, nblocks, kind, st);
 }
 
 }  // namespace mlk

@@ -119,13 +119,14 @@ __device__ __forceinline__ void load_lane_win(const WinRec<T>& r, int i, LaneWin
 
 // gather; see the file comment.  Writes E~ = gamma * sum w E (FP64) per emitter.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_gather_bins(FieldPtrs<T> f, Geom g, BinPtrs bins,
-                                                          WindowPtrs<T> win, double* Et) {
+__device__ __forceinline__ void gather_body(const FieldPtrs<T>& f, const Geom& g,
+                                            const BinPtrs& bins, const WindowPtrs<T>& win,
+                                            double* Et, int bid) {
   constexpr int BX = BinCfg<T>::GX, BY = BinCfg<T>::GY, BZ = BinCfg<T>::GZ;
   constexpr int TX = BX + 2 * kHalo, TY = BY + 2 * kHalo, TZ = BZ + 2 * kHalo;
   __shared__ T sE[3][TX * TY * TZ];
   const int tid = threadIdx.x;
-  const int bin = xcd_block(blockIdx.x, bins.ngather);
+  const int bin = xcd_block(bid, bins.ngather);
   // tile origin in the unwrapped frame of the emitters' window indices
   const int x0 = bins.gbin_org[3 * bin] - kHalo;
   const int y0 = bins.gbin_org[3 * bin + 1] - kHalo;
@@ -203,11 +204,26 @@ __global__ __launch_bounds__(kThreads) void k_gather_bins(FieldPtrs<T> f, Geom g
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gather_bins(FieldPtrs<T> f, Geom g, BinPtrs bins,
+                                                          WindowPtrs<T> win, double* Et) {
+  gather_body(f, g, bins, win, Et, blockIdx.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gather_batch(const GatherJob<T>* jobs,
+                                                           const int* start, int njobs) {
+  const int j = find_job(start, njobs, blockIdx.x);
+  const GatherJob<T>& J = jobs[j];
+  const int bid = blockIdx.x - start[j];
+  if (bid >= J.nblocks) return;
+  gather_body(J.f, J.g, J.bins, J.win, J.Et, bid);
+}
+
 // Exact two-level step of every two-level emitter under its E~ (one thread each).
-__global__ __launch_bounds__(256) void k_tls_step(TlsPtrs tls, double dt, const double* Et,
-                                                  double* mudot, const int64_t* pop_off,
-                                                  Series ser, const int64_t* step) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void tls_body(const TlsPtrs& tls, double dt, const double* Et,
+                                         double* mudot, const int64_t* pop_off, const Series& ser,
+                                         const int64_t* step, int m) {
   if (m >= tls.count) return;
   const int e = tls.gid[m];
   const double et[3] = {Et[3 * e], Et[3 * e + 1], Et[3 * e + 2]};
@@ -225,6 +241,21 @@ __global__ __launch_bounds__(256) void k_tls_step(TlsPtrs tls, double dt, const 
     const int64_t n = *step;
     if (n % ser.pop_every == 0) ser.pop[(n / ser.pop_every) * ser.npop + pop_off[e]] = st[0];
   }
+}
+
+__global__ __launch_bounds__(256) void k_tls_step(TlsPtrs tls, double dt, const double* Et,
+                                                  double* mudot, const int64_t* pop_off,
+                                                  Series ser, const int64_t* step) {
+  tls_body(tls, dt, Et, mudot, pop_off, ser, step, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_tls_batch(const TlsJob* jobs, const int* start,
+                                                   int njobs) {
+  const int j = find_job(start, njobs, blockIdx.x);
+  const TlsJob& J = jobs[j];
+  const int lb = blockIdx.x - start[j];
+  if (lb >= J.nblocks) return;
+  tls_body(J.tls, J.dt, J.Et, J.mudot, J.pop_off, J.ser, J.step, lb * blockDim.x + threadIdx.x);
 }
 
 // Fixed-point accumulator of the scatter: 32-bit for FP32 fields, 64-bit for FP64.
@@ -253,9 +284,9 @@ struct Acc<double> {
 // rounding; 2^-30 for FP32 fields, at the level of FP32 rounding of a cell's
 // sum.  A contribution is formed in the field precision.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_scatter_bins(FieldPtrs<T> f, Geom g, BinPtrs bins,
-                                                           WindowPtrs<T> win,
-                                                           const double* mudot) {
+__device__ __forceinline__ void scatter_body(const FieldPtrs<T>& f, const Geom& g,
+                                             const BinPtrs& bins, const WindowPtrs<T>& win,
+                                             const double* mudot, int bid) {
   using A = Acc<T>;
   constexpr int BX = BinCfg<T>::SX, BY = BinCfg<T>::SY, BZ = BinCfg<T>::SZ;
   constexpr int CELLS = BX * BY * BZ;
@@ -263,11 +294,11 @@ __global__ __launch_bounds__(kThreads) void k_scatter_bins(FieldPtrs<T> f, Geom 
   __shared__ typename A::U sJ[3][CELLS];
   __shared__ double sRed[NW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int b = bins.sbin_id[blockIdx.x];
+  const int b = bins.sbin_id[bid];
   const int bx = b % bins.nbx, by = (b / bins.nbx) % bins.nby, bz = b / (bins.nbx * bins.nby);
   const int x0 = bx * BX, y0 = by * BY, z0 = bz * BZ;
   const int ex = min(BX, g.n[0] - x0), ey = min(BY, g.n[1] - y0), ez = min(BZ, g.n[2] - z0);
-  const int q0 = bins.sbin_start[blockIdx.x], q1 = bins.sbin_start[blockIdx.x + 1];
+  const int q0 = bins.sbin_start[bid], q1 = bins.sbin_start[bid + 1];
   const double amp0 = g.dt * g.inv_dx * g.inv_dx * g.inv_dx;
   for (int t = tid; t < CELLS; t += kThreads) {
     sJ[0][t] = 0;
@@ -340,6 +371,23 @@ __global__ __launch_bounds__(kThreads) void k_scatter_bins(FieldPtrs<T> f, Geom 
 }
 
 template <typename T>
+__global__ __launch_bounds__(kThreads) void k_scatter_bins(FieldPtrs<T> f, Geom g, BinPtrs bins,
+                                                           WindowPtrs<T> win,
+                                                           const double* mudot) {
+  scatter_body(f, g, bins, win, mudot, blockIdx.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_scatter_batch(const ScatterJob<T>* jobs,
+                                                            const int* start, int njobs) {
+  const int j = find_job(start, njobs, blockIdx.x);
+  const ScatterJob<T>& J = jobs[j];
+  const int bid = blockIdx.x - start[j];
+  if (bid >= J.nblocks) return;
+  scatter_body(J.f, J.g, J.bins, J.win, J.mudot, bid);
+}
+
+template <typename T>
 static hipError_t launch_gather_step(const FieldPtrs<T>& f, const Geom& g, const BinPtrs& b,
                                      const WindowPtrs<T>& win, const TlsPtrs& tls,
                                      double* Et, double* mudot, const int64_t* pop_off,
@@ -381,6 +429,43 @@ hipError_t bin_scatter_f64(const FieldPtrs<double>& f, const Geom& g, const BinP
 hipError_t bin_scatter_f32(const FieldPtrs<float>& f, const Geom& g, const BinPtrs& b,
                            const WindowPtrs<float>& win, const double* mudot, hipStream_t st) {
   return launch_scatter<float>(f, g, b, win, mudot, st);
+}
+
+template <typename T>
+static hipError_t launch_gather_batch(const GatherJob<T>* jobs, const int* start, int njobs,
+                                      int nblocks, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_batch<T>, dim3(nblocks), dim3(kThreads), 0, st, jobs, start, njobs);
+  return hipGetLastError();
+}
+template <typename T>
+static hipError_t launch_scatter_batch(const ScatterJob<T>* jobs, const int* start, int njobs,
+                                       int nblocks, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_batch<T>, dim3(nblocks), dim3(kThreads), 0, st, jobs, start, njobs);
+  return hipGetLastError();
+}
+hipError_t gather_batch_f64(const GatherJob<double>* jobs, const int* start, int njobs,
+                            int nblocks, hipStream_t st) {
+  return launch_gather_batch<double>(jobs, start, njobs, nblocks, st);
+}
+hipError_t gather_batch_f32(const GatherJob<float>* jobs, const int* start, int njobs,
+                            int nblocks, hipStream_t st) {
+  return launch_gather_batch<float>(jobs, start, njobs, nblocks, st);
+}
+hipError_t scatter_batch_f64(const ScatterJob<double>* jobs, const int* start, int njobs,
+                             int nblocks, hipStream_t st) {
+  return launch_scatter_batch<double>(jobs, start, njobs, nblocks, st);
+}
+hipError_t scatter_batch_f32(const ScatterJob<float>* jobs, const int* start, int njobs,
+                             int nblocks, hipStream_t st) {
+  return launch_scatter_batch<float>(jobs, start, njobs, nblocks, st);
+}
+hipError_t tls_batch(const TlsJob* jobs, const int* start, int njobs, int nblocks,
+                     hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tls_batch, dim3(nblocks), dim3(256), 0, st, jobs, start, njobs);
+  return hipGetLastError();
 }
 
 }  // namespace mlk

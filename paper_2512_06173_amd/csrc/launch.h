@@ -29,9 +29,9 @@ hipError_t sources_f64(const FieldPtrs<double>& f, const Geom& g, const SourceSe
 hipError_t sources_f32(const FieldPtrs<float>& f, const Geom& g, const SourceSet& src,
                        const int64_t* step, hipStream_t st);
 hipError_t sweep_fused_f64(const FieldPtrs<double>& a, const FieldPtrs<double>& b, const Geom& g,
-                           const Box& box, int kz, hipStream_t st);
+                           const Box& box, int kz, int ty, hipStream_t st);
 hipError_t sweep_fused_f32(const FieldPtrs<float>& a, const FieldPtrs<float>& b, const Geom& g,
-                           const Box& box, int kz, hipStream_t st);
+                           const Box& box, int kz, int ty, hipStream_t st);
 
 hipError_t windows_f64(int count, const double* pos, const double* sigma, double R, const Geom& g,
                        int* lo, int* len, double* w, hipStream_t st);
@@ -71,5 +71,39 @@ hipError_t bin_scatter_f32(const FieldPtrs<float>& f, const Geom& g, const BinPt
                            const WindowPtrs<float>& win, const double* mudot, hipStream_t st);
 // bin edge lengths (cells) of the gather (G) and scatter (S) bins for a field precision
 void bin_shape(bool fp32, int G[3], int S[3]);
+
+// ---- batched launches (one launch per phase over the jobs of many domains)
+template <typename T>
+void fused_job_shape(FusedJob<T>& J);
+ShellMap shell_map(const Geom& g, const Box& inner);
+int source_blocks_of(const Geom& g, const SourceSet& src);
+hipError_t sweep_fused_batch_f64(const FusedJob<double>* jobs, const int* start, int njobs,
+                                 int nblocks, int ty, hipStream_t st);
+hipError_t sweep_fused_batch_f32(const FusedJob<float>* jobs, const int* start, int njobs,
+                                 int nblocks, int ty, hipStream_t st);
+hipError_t shell_batch_f64(const ShellJob<double>* jobs, const int* start, int njobs, int nblocks,
+                           bool h_pass, hipStream_t st);
+hipError_t shell_batch_f32(const ShellJob<float>* jobs, const int* start, int njobs, int nblocks,
+                           bool h_pass, hipStream_t st);
+hipError_t sources_batch_f64(const SourceJob<double>* jobs, const int* start, int njobs,
+                             int nblocks, hipStream_t st);
+hipError_t sources_batch_f32(const SourceJob<float>* jobs, const int* start, int njobs,
+                             int nblocks, hipStream_t st);
+hipError_t gather_batch_f64(const GatherJob<double>* jobs, const int* start, int njobs,
+                            int nblocks, hipStream_t st);
+hipError_t gather_batch_f32(const GatherJob<float>* jobs, const int* start, int njobs,
+                            int nblocks, hipStream_t st);
+hipError_t tls_batch(const TlsJob* jobs, const int* start, int njobs, int nblocks,
+                     hipStream_t st);
+hipError_t ml_batch(const MlJob* jobs, const int* start, int njobs, int nblocks, int nl,
+                    hipStream_t st);
+hipError_t scatter_batch_f64(const ScatterJob<double>* jobs, const int* start, int njobs,
+                             int nblocks, hipStream_t st);
+hipError_t scatter_batch_f32(const ScatterJob<float>* jobs, const int* start, int njobs,
+                             int nblocks, hipStream_t st);
+hipError_t detect_batch_f64(const FluxJob<double>* jobs, const int* start, int njobs, int nblocks,
+                            int kind, hipStream_t st);
+hipError_t detect_batch_f32(const FluxJob<float>* jobs, const int* start, int njobs, int nblocks,
+                            int kind, hipStream_t st);
 
 }  // namespace mlk

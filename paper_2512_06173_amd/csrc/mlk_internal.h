@@ -222,4 +222,112 @@ struct BinPtrs {
   const int* sbin_em;       // emitter id of each pair
 };
 
+// ---------------------------------------------------------------- batches
+// A batched launch covers the jobs of several domains: job j owns blocks
+// [start[j], start[j+1]) of the grid; starts are multiples of 8 so that the
+// XCD-aware block order of a job is preserved.
+__device__ inline int find_job(const int* start, int njobs, int b) {
+  int lo = 0, hi = njobs;  // start[lo] <= b < start[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (start[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <typename T>
+struct FusedJob {
+  FieldPtrs<T> a, b;
+  Geom g;
+  Box box;
+  int kz, ty, ntx, nty, nblocks;
+};
+
+// The cells of the grid outside an interior box, enumerated in memory order:
+// the whole planes below and above the box in z, then, plane by plane inside
+// it, the whole rows below and above it in y followed by the two x strips of
+// each remaining row.
+struct ShellMap {
+  Box in;
+  int nzlo;              // whole planes below the box
+  long long nslab;       // cells in the whole planes (both sides)
+  int ylo_rows;          // whole rows below the box, per middle plane
+  int full_cells;        // cells in the whole rows of one middle plane
+  int strip;             // cells in the two x strips of one row
+  int per_plane;         // shell cells of one middle plane
+  long long total;
+};
+
+template <typename T>
+struct ShellJob {
+  FieldPtrs<T> in, out;
+  Geom g;
+  ShellMap m;
+  int nblocks;
+};
+
+template <typename T>
+struct SourceJob {
+  FieldPtrs<T> f;
+  Geom g;
+  SourceSet src;
+  const int64_t* step;
+  int bx;       // blocks per source
+  int nblocks;  // bx * src.count
+};
+
+template <typename T>
+struct GatherJob {
+  FieldPtrs<T> f;
+  Geom g;
+  BinPtrs bins;
+  WindowPtrs<T> win;
+  double* Et;
+  int nblocks;  // bins.ngather
+};
+
+struct TlsJob {
+  TlsPtrs tls;
+  double dt;
+  const double* Et;
+  double* mudot;
+  const int64_t* pop_off;
+  Series ser;
+  const int64_t* step;
+  int nblocks;
+};
+
+struct MlJob {
+  MlDev ml;
+  int first, count;  // slots of one level count
+  double dt;
+  const double* Et;
+  double* mudot;
+  const int64_t* pop_off;
+  Series ser;
+  const int64_t* step;
+  int nblocks;
+};
+
+template <typename T>
+struct ScatterJob {
+  FieldPtrs<T> f;
+  Geom g;
+  BinPtrs bins;
+  WindowPtrs<T> win;
+  const double* mudot;
+  int nblocks;  // bins.nscatter
+};
+
+template <typename T>
+struct FluxJob {
+  FieldPtrs<T> f;
+  Geom g;
+  FluxPlane fp;
+  Series ser;
+  int64_t* step;
+  int nblocks;
+};
+
 }  // namespace mlk

@@ -80,13 +80,12 @@ __device__ __forceinline__ void jacobi(double (&A)[N][N], double (&Q)[N][N]) {
 }  // namespace
 
 template <int N>
-__global__ __launch_bounds__(64) void k_ml_step(MlDev ml, int first, int count, double dt,
-                                                const double* Et, double* mudot,
-                                                const int64_t* pop_off, Series ser,
-                                                const int64_t* step) {
+__device__ __forceinline__ void ml_body(const MlDev& ml, int first, int count, double dt,
+                                        const double* Et, double* mudot, const int64_t* pop_off,
+                                        const Series& ser, const int64_t* step, int t) {
   constexpr int NS = N * (N + 1) / 2;
-  const int m = first + blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= first + count) return;
+  const int m = first + t;
+  if (t >= count) return;
   const size_t st = (size_t)ml.count;
   const int e = ml.gid[m];
   const double gphi = ml.gphi[m];
@@ -194,6 +193,41 @@ __global__ __launch_bounds__(64) void k_ml_step(MlDev ml, int first, int count, 
   mudot[3 * e] = tr * ml.dip[m];
   mudot[3 * e + 1] = tr * ml.dip[st + m];
   mudot[3 * e + 2] = tr * ml.dip[2 * st + m];
+}
+
+template <int N>
+__global__ __launch_bounds__(64) void k_ml_step(MlDev ml, int first, int count, double dt,
+                                                const double* Et, double* mudot,
+                                                const int64_t* pop_off, Series ser,
+                                                const int64_t* step) {
+  ml_body<N>(ml, first, count, dt, Et, mudot, pop_off, ser, step,
+             blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+template <int N>
+__global__ __launch_bounds__(64) void k_ml_batch(const MlJob* jobs, const int* start, int njobs) {
+  const int j = find_job(start, njobs, blockIdx.x);
+  const MlJob& J = jobs[j];
+  const int lb = blockIdx.x - start[j];
+  if (lb >= J.nblocks) return;
+  ml_body<N>(J.ml, J.first, J.count, J.dt, J.Et, J.mudot, J.pop_off, J.ser, J.step,
+             lb * blockDim.x + threadIdx.x);
+}
+
+// Batched multilevel step; every job of the table has `nl` levels.
+hipError_t ml_batch(const MlJob* jobs, const int* start, int njobs, int nblocks, int nl,
+                    hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  const dim3 grid(nblocks), block(64);
+  switch (nl) {
+    case 2: hipLaunchKernelGGL(k_ml_batch<2>, grid, block, 0, st, jobs, start, njobs); break;
+    case 3: hipLaunchKernelGGL(k_ml_batch<3>, grid, block, 0, st, jobs, start, njobs); break;
+    case 4: hipLaunchKernelGGL(k_ml_batch<4>, grid, block, 0, st, jobs, start, njobs); break;
+    case 5: hipLaunchKernelGGL(k_ml_batch<5>, grid, block, 0, st, jobs, start, njobs); break;
+    case 6: hipLaunchKernelGGL(k_ml_batch<6>, grid, block, 0, st, jobs, start, njobs); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t ml_step(const MlDev& ml, const int* range, double dt, const double* Et, double* mudot,

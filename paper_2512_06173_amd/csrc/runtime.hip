@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <climits>
+#include <algorithm>
 #include <string>
 #include <array>
 #include <vector>
@@ -86,6 +87,9 @@ struct mlk_sim {
   void* H2[3] = {};
   void* psi2 = nullptr;
   int kz = 0;       // z planes per workgroup of the fused sweep
+  int ty = 4;       // y rows per workgroup of the fused sweep (4 or 8)
+  hipStream_t batch_stream = nullptr;  // stream of the batch this sim belongs to
+  bool in_batch = false;
   void* epsinv = nullptr;
   void* psi = nullptr;  // every CPML psi array of the current buffer (psi_offset layout)
   void* tab = nullptr;  // CPML coefficient tables (tab_offset layout)
@@ -155,6 +159,15 @@ struct mlk_sim {
 };
 
 namespace {
+
+// Wait for every piece of work on the sim: its own stream and, while it is a
+// member of a batch, the batch's stream.
+mlk_status sync_sim(mlk_sim* s) {
+  HIPCHK(hipStreamSynchronize(s->stream));
+  if (s->batch_stream) HIPCHK(hipStreamSynchronize(s->batch_stream));
+  return MLK_OK;
+}
+
 
 template <typename T>
 FieldPtrs<T> field_ptrs(const mlk_sim* s);
@@ -428,7 +441,7 @@ MlDev ml_dev(mlk_sim* s) {
 
 // Rebuild every device emitter table from the host mirror (set-up only).
 mlk_status rebuild_emitters(mlk_sim* s) {
-  HIPCHK(hipStreamSynchronize(s->stream));
+  STCHK(sync_sim(s));
   const int M = s->nem;
   if (M == 0) return MLK_OK;
   STCHK(upload(&s->d_pos, s->pos));
@@ -468,7 +481,7 @@ mlk_status rebuild_emitters(mlk_sim* s) {
     HIPCHK(records_f64(M, s->d_wlo, s->d_wlen, (const double*)s->d_w, (WinRec<double>*)s->d_rec,
                        s->stream));
   }
-  HIPCHK(hipStreamSynchronize(s->stream));
+  STCHK(sync_sim(s));
   return build_bins(s);
 }
 
@@ -476,7 +489,7 @@ mlk_status rebuild_emitters(mlk_sim* s) {
 mlk_status reserve_series(mlk_sim* s, int64_t nsteps) {
   const int64_t need = s->host_step + nsteps;
   if ((s->nprobe > 0 || s->fp.on) && need > s->series_cap) {
-    HIPCHK(hipStreamSynchronize(s->stream));
+    STCHK(sync_sim(s));
     int64_t cap = s->series_cap ? 2 * s->series_cap : 1024;
     while (cap < need) cap *= 2;
     if (s->nprobe > 0) {
@@ -503,7 +516,7 @@ mlk_status reserve_series(mlk_sim* s, int64_t nsteps) {
   if (s->pop_every > 0 && s->npop > 0) {
     const int64_t rec = (need + s->pop_every - 1) / s->pop_every;
     if (rec > s->pop_cap) {
-      HIPCHK(hipStreamSynchronize(s->stream));
+      STCHK(sync_sim(s));
       int64_t cap = s->pop_cap ? 2 * s->pop_cap : 64;
       while (cap < rec) cap *= 2;
       double* np = nullptr;
@@ -584,8 +597,8 @@ mlk_status sweep(mlk_sim* s) {
     const FieldPtrs<T> nf = spare_ptrs<T>(s);
     const Box inner = interior_box(s->g);
     int t0 = mark_begin(s, MLK_PHASE_SWEEP);
-    if constexpr (f32) HIPCHK(sweep_fused_f32(f, nf, s->g, inner, s->kz, s->stream));
-    else HIPCHK(sweep_fused_f64(f, nf, s->g, inner, s->kz, s->stream));
+    if constexpr (f32) HIPCHK(sweep_fused_f32(f, nf, s->g, inner, s->kz, s->ty, s->stream));
+    else HIPCHK(sweep_fused_f64(f, nf, s->g, inner, s->kz, s->ty, s->stream));
     mark_end(s, MLK_PHASE_SWEEP, t0);
     t0 = mark_begin(s, MLK_PHASE_SHELL);
     if constexpr (f32) {
@@ -901,6 +914,7 @@ mlk_status mlk_create(const mlk_grid_desc* gd, mlk_sim** out) {
 
 mlk_status mlk_destroy(mlk_sim* s) {
   if (!s) return MLK_OK;
+  if (s->in_batch) return fail(MLK_ESTATE, "destroy the batch this sim belongs to first");
   if (s->stream) (void)hipStreamSynchronize(s->stream);
   release(s);
   delete s;
@@ -1144,6 +1158,7 @@ mlk_status mlk_step(mlk_sim* s, int64_t nsteps) {
   if (nsteps < 0) return fail(MLK_EINVAL, "negative step count");
   if (nsteps == 0) return MLK_OK;
   HIPCHK(hipSetDevice(s->desc.device));
+  if (s->batch_stream) HIPCHK(hipStreamSynchronize(s->batch_stream));
   STCHK(reserve_series(s, nsteps));
   mlk_status st = s->fp32 ? enqueue_steps<float>(s, nsteps) : enqueue_steps<double>(s, nsteps);
   if (st == MLK_OK) s->host_step += nsteps;
@@ -1152,7 +1167,7 @@ mlk_status mlk_step(mlk_sim* s, int64_t nsteps) {
 
 mlk_status mlk_set_timing(mlk_sim* s, int32_t on) {
   if (!s) return fail(MLK_EINVAL, "null argument");
-  HIPCHK(hipStreamSynchronize(s->stream));
+  STCHK(sync_sim(s));
   s->marks.clear();
   s->next_event = 0;
   for (int p = 0; p < MLK_PHASE_COUNT; ++p) {
@@ -1166,7 +1181,7 @@ mlk_status mlk_set_timing(mlk_sim* s, int32_t on) {
 mlk_status mlk_get_phase_time(mlk_sim* s, int32_t phase, double* total_ms, int64_t* launches) {
   if (!s || !total_ms || !launches) return fail(MLK_EINVAL, "null argument");
   if (phase < 0 || phase >= MLK_PHASE_COUNT) return fail(MLK_EINVAL, "phase %d unknown", phase);
-  HIPCHK(hipStreamSynchronize(s->stream));
+  STCHK(sync_sim(s));
   HIPCHK(collect_marks(s));
   *total_ms = s->phase_ms[phase];
   *launches = s->phase_n[phase];
@@ -1185,7 +1200,7 @@ mlk_status mlk_get_interior_box(mlk_sim* s, int32_t box[6]) {
 
 mlk_status mlk_sync(mlk_sim* s) {
   if (!s) return fail(MLK_EINVAL, "null argument");
-  HIPCHK(hipStreamSynchronize(s->stream));
+  STCHK(sync_sim(s));
   return MLK_OK;
 }
 
@@ -1199,10 +1214,10 @@ mlk_status mlk_get_field(mlk_sim* s, int32_t comp, double* dst, int32_t mem_kind
   if (!s || !dst) return fail(MLK_EINVAL, "null argument");
   if (comp < 0 || comp > 5) return fail(MLK_EINVAL, "component %d outside 0..5", comp);
   const void* src = comp < 3 ? s->E[comp] : s->H[comp - 3];
-  HIPCHK(hipStreamSynchronize(s->stream));
+  STCHK(sync_sim(s));
   if (mem_kind == MLK_MEM_DEVICE) {
     HIPCHK(convert_out(s->fp32, src, dst, s->ncell, s->stream));
-    HIPCHK(hipStreamSynchronize(s->stream));
+    STCHK(sync_sim(s));
     return MLK_OK;
   }
   double* d = nullptr;
@@ -1217,7 +1232,7 @@ mlk_status mlk_get_field(mlk_sim* s, int32_t comp, double* dst, int32_t mem_kind
 
 mlk_status mlk_get_tls_state(mlk_sim* s, int32_t first, int32_t count, double* dst) {
   if (!s || !dst) return fail(MLK_EINVAL, "null argument");
-  HIPCHK(hipStreamSynchronize(s->stream));
+  STCHK(sync_sim(s));
   const int nt = (int)s->tls_gid.size();
   std::vector<double> all((size_t)nt * 3);
   if (nt) HIPCHK(hipMemcpy(all.data(), s->d_tls_rho, all.size() * sizeof(double),
@@ -1243,7 +1258,7 @@ mlk_status mlk_get_rho(mlk_sim* s, int32_t id, double* dst, int32_t cap, int32_t
     for (int k = 2; k <= kMaxLevels; ++k)
       if (slot >= s->ml_range[k] && slot < s->ml_range[k + 1]) n = k;
     if (cap < 2 * n * n) return fail(MLK_EINVAL, "dst too small");
-    HIPCHK(hipStreamSynchronize(s->stream));
+    STCHK(sync_sim(s));
     const size_t cnt = s->ml_gid.size();
     for (int a = 0; a < n; ++a)
       for (int b = 0; b < n; ++b)
@@ -1272,7 +1287,7 @@ mlk_status mlk_get_rho(mlk_sim* s, int32_t id, double* dst, int32_t cap, int32_t
 
 mlk_status mlk_get_emitter_io(mlk_sim* s, double* Et, double* mudot) {
   if (!s) return fail(MLK_EINVAL, "null argument");
-  HIPCHK(hipStreamSynchronize(s->stream));
+  STCHK(sync_sim(s));
   const size_t b = (size_t)s->nem * 3 * sizeof(double);
   if (Et && b) HIPCHK(hipMemcpy(Et, s->d_Et, b, hipMemcpyDeviceToHost));
   if (mudot && b) HIPCHK(hipMemcpy(mudot, s->d_mudot, b, hipMemcpyDeviceToHost));
@@ -1282,7 +1297,7 @@ mlk_status mlk_get_emitter_io(mlk_sim* s, double* Et, double* mudot) {
 mlk_status mlk_get_series(mlk_sim* s, int32_t kind, int32_t id, double* dst, int64_t cap,
                           int64_t* len) {
   if (!s) return fail(MLK_EINVAL, "null argument");
-  HIPCHK(hipStreamSynchronize(s->stream));
+  STCHK(sync_sim(s));
   int64_t n = 0;
   const double* src = nullptr;
   if (kind == MLK_SERIES_PROBE) {
@@ -1312,7 +1327,7 @@ mlk_status mlk_get_series(mlk_sim* s, int32_t kind, int32_t id, double* dst, int
 mlk_status mlk_get_flux_total(mlk_sim* s, double* total) {
   if (!s || !total) return fail(MLK_EINVAL, "null argument");
   if (!s->fp.on) return fail(MLK_EINVAL, "no flux plane");
-  HIPCHK(hipStreamSynchronize(s->stream));
+  STCHK(sync_sim(s));
   HIPCHK(hipMemcpy(total, s->fp.total, sizeof(double), hipMemcpyDeviceToHost));
   return MLK_OK;
 }
@@ -1327,7 +1342,7 @@ mlk_status mlk_checkpoint_size(mlk_sim* s, size_t* bytes) {
 
 mlk_status mlk_checkpoint_save(mlk_sim* s, void* dst, int32_t mem_kind) {
   if (!s || !dst) return fail(MLK_EINVAL, "null argument");
-  HIPCHK(hipStreamSynchronize(s->stream));
+  STCHK(sync_sim(s));
   char* o = (char*)dst;
   const hipMemcpyKind kind =
       mem_kind == MLK_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
@@ -1340,7 +1355,7 @@ mlk_status mlk_checkpoint_save(mlk_sim* s, void* dst, int32_t mem_kind) {
 
 mlk_status mlk_checkpoint_load(mlk_sim* s, const void* src, int32_t mem_kind) {
   if (!s || !src) return fail(MLK_EINVAL, "null argument");
-  HIPCHK(hipStreamSynchronize(s->stream));
+  STCHK(sync_sim(s));
   const char* o = (const char*)src;
   const hipMemcpyKind kind =
       mem_kind == MLK_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
@@ -1352,6 +1367,598 @@ mlk_status mlk_checkpoint_load(mlk_sim* s, const void* src, int32_t mem_kind) {
   HIPCHK(hipMemcpy(&step, s->d_step, sizeof(int64_t), hipMemcpyDeviceToHost));
   if (step > s->host_step) STCHK(reserve_series(s, step - s->host_step));
   s->host_step = step;
+  return MLK_OK;
+}
+
+}  // extern "C"
+
+// ====================================================================== batches
+//
+// A batch steps many independent sims together: every phase of the step is one
+// launch over the jobs of all members (see find_job), so a step costs about a
+// dozen launches whatever the number of domains.  The job tables hold device
+// pointers; the fused sweep's two field buffers alternate, so each table exists
+// for both buffer parities.  A captured hipGraph replays a fixed number of
+// steps (even in the fused mode, so that every replay starts on the same
+// parity).
+
+namespace {
+
+template <typename J>
+struct DevTable {
+  J* jobs = nullptr;
+  int* start = nullptr;
+  int njobs = 0;
+  int nblocks = 0;
+};
+
+template <typename J>
+void free_table(DevTable<J>& t) {
+  dfree(t.jobs);
+  dfree(t.start);
+  t = DevTable<J>{};
+}
+
+// Upload the non-empty jobs; job starts are padded to multiples of 8 blocks.
+template <typename J>
+mlk_status make_table(DevTable<J>& t, const std::vector<J>& all) {
+  free_table(t);
+  std::vector<J> jobs;
+  for (const J& j : all)
+    if (j.nblocks > 0) jobs.push_back(j);
+  if (jobs.empty()) return MLK_OK;
+  std::vector<int> st(jobs.size() + 1);
+  long long acc = 0;
+  for (size_t q = 0; q < jobs.size(); ++q) {
+    st[q] = (int)acc;
+    acc += ((long long)jobs[q].nblocks + 7) / 8 * 8;
+    if (acc > 0x7fffffffLL) return fail(MLK_EUNSUPPORTED, "batch grid too large");
+  }
+  st[jobs.size()] = (int)acc;
+  STCHK(upload(&t.jobs, jobs));
+  STCHK(upload(&t.start, st));
+  t.njobs = (int)jobs.size();
+  t.nblocks = (int)acc;
+  return MLK_OK;
+}
+
+TlsPtrs tls_ptrs(const mlk_sim* s) {
+  TlsPtrs tls{};
+  tls.count = (int)s->tls_gid.size();
+  tls.gid = s->d_tls_gid;
+  tls.omega0 = s->d_tls_w0;
+  tls.dip = s->d_tls_dip;
+  tls.rho = s->d_tls_rho;
+  return tls;
+}
+
+template <typename T>
+struct BatchTables {
+  DevTable<FluxJob<T>> fsave, fpart, finish;
+  DevTable<GatherJob<T>> gather;
+  DevTable<FusedJob<T>> fused[2];  // by TY: 4, 8
+  DevTable<ShellJob<T>> shell;
+  DevTable<SourceJob<T>> sources;
+  DevTable<ScatterJob<T>> scatter;
+  void release() {
+    free_table(fsave);
+    free_table(fpart);
+    free_table(finish);
+    free_table(gather);
+    for (auto& f : fused) free_table(f);
+    free_table(shell);
+    free_table(sources);
+    free_table(scatter);
+  }
+};
+
+int ty_slot(int ty) { return ty == 8 ? 1 : 0; }
+
+}  // namespace
+
+struct mlk_batch {
+  std::vector<mlk_sim*> sims;
+  bool fp32 = false;
+  bool fused = false;
+  hipStream_t stream = nullptr;
+  int parity = 0;  // number of buffer swaps since the tables were built, mod 2
+  BatchTables<float> t32[2];
+  BatchTables<double> t64[2];
+  DevTable<TlsJob> tls;
+  DevTable<MlJob> ml[kMaxLevels + 1];
+  std::vector<const void*> series_snapshot;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int64_t replay_steps = 0;
+  int capture_parity = 0;  // buffer parity the captured steps start from
+};
+
+namespace {
+
+std::vector<const void*> series_pointers(const mlk_batch* b) {
+  std::vector<const void*> v;
+  for (const mlk_sim* s : b->sims) {
+    v.push_back(s->d_probe);
+    v.push_back(s->d_flux_series);
+    v.push_back(s->d_pop);
+  }
+  return v;
+}
+
+// Job tables for the current state of the members; parity q means q swaps of
+// the fused buffers after now.
+template <typename T>
+mlk_status build_tables(mlk_batch* b, BatchTables<T> (&tab)[2]) {
+  for (int q = 0; q < 2; ++q) {
+    std::vector<FluxJob<T>> fs, fpj, fin;
+    std::vector<GatherJob<T>> ga;
+    std::vector<FusedJob<T>> fu[2];
+    std::vector<ShellJob<T>> sh;
+    std::vector<SourceJob<T>> so;
+    std::vector<ScatterJob<T>> sc;
+    for (mlk_sim* s : b->sims) {
+      if (q == 1 && b->fused) swap_buffers(s);
+      const FieldPtrs<T> cur = field_ptrs<T>(s);
+      const FieldPtrs<T> nxt = b->fused ? spare_ptrs<T>(s) : cur;
+      const Series ser = series_of(s);
+      if (s->fp.on) {
+        const int a = s->fp.axis;
+        const int np = s->g.n[(a + 1) % 3] * s->g.n[(a + 2) % 3];
+        fs.push_back({cur, s->g, s->fp, ser, s->d_step, (np + 255) / 256});
+        fpj.push_back({nxt, s->g, s->fp, ser, s->d_step, s->fp.nblocks});
+      }
+      fin.push_back({nxt, s->g, s->fp, ser, s->d_step, 1});
+      if (s->nem > 0) {
+        ga.push_back({cur, s->g, bin_ptrs(s), window_ptrs<T>(s), s->d_Et, s->ngather});
+        sc.push_back({nxt, s->g, bin_ptrs(s), window_ptrs<T>(s), s->d_mudot, s->nscatter});
+      }
+      Box inner{};
+      if (b->fused) {
+        inner = interior_box(s->g);
+        FusedJob<T> J{};
+        J.a = cur;
+        J.b = nxt;
+        J.g = s->g;
+        J.box = inner;
+        J.kz = s->kz;
+        J.ty = s->ty;
+        fused_job_shape(J);
+        fu[ty_slot(s->ty)].push_back(J);
+      }
+      ShellJob<T> S{};
+      S.in = cur;
+      S.out = nxt;
+      S.g = s->g;
+      S.m = shell_map(s->g, inner);
+      S.nblocks = (int)((S.m.total + 255) / 256);
+      sh.push_back(S);
+      if (s->src.count > 0) {
+        SourceJob<T> J{};
+        J.f = nxt;
+        J.g = s->g;
+        J.src = s->src;
+        J.step = s->d_step;
+        J.bx = source_blocks_of(s->g, s->src);
+        J.nblocks = J.bx * s->src.count;
+        so.push_back(J);
+      }
+      if (q == 1 && b->fused) swap_buffers(s);
+    }
+    BatchTables<T>& t = tab[q];
+    STCHK(make_table(t.fsave, fs));
+    STCHK(make_table(t.fpart, fpj));
+    STCHK(make_table(t.finish, fin));
+    STCHK(make_table(t.gather, ga));
+    for (int k = 0; k < 2; ++k) STCHK(make_table(t.fused[k], fu[k]));
+    STCHK(make_table(t.shell, sh));
+    STCHK(make_table(t.sources, so));
+    STCHK(make_table(t.scatter, sc));
+  }
+  std::vector<TlsJob> tj;
+  std::vector<MlJob> mj[kMaxLevels + 1];
+  for (mlk_sim* s : b->sims) {
+    const Series ser = series_of(s);
+    const TlsPtrs tls = tls_ptrs(s);
+    if (tls.count > 0)
+      tj.push_back({tls, s->g.dt, s->d_Et, s->d_mudot, s->d_popoff, ser, s->d_step,
+                    (tls.count + 255) / 256});
+    const MlDev ml = ml_dev(s);
+    for (int n = 2; n <= kMaxLevels; ++n) {
+      const int first = s->ml_range[n], count = s->ml_range[n + 1] - s->ml_range[n];
+      if (count > 0)
+        mj[n].push_back({ml, first, count, s->g.dt, s->d_Et, s->d_mudot, s->d_popoff, ser,
+                         s->d_step, (count + 63) / 64});
+    }
+  }
+  STCHK(make_table(b->tls, tj));
+  for (int n = 2; n <= kMaxLevels; ++n) STCHK(make_table(b->ml[n], mj[n]));
+  b->parity = 0;
+  b->series_snapshot = series_pointers(b);
+  return MLK_OK;
+}
+
+mlk_status rebuild_tables(mlk_batch* b) {
+  for (auto& t : b->t32) t.release();
+  for (auto& t : b->t64) t.release();
+  free_table(b->tls);
+  for (auto& t : b->ml) free_table(t);
+  return b->fp32 ? build_tables<float>(b, b->t32) : build_tables<double>(b, b->t64);
+}
+
+// Enqueue one batched step on tables of parity q.
+template <typename T>
+mlk_status enqueue_batch_step(mlk_batch* b, const BatchTables<T>& t) {
+  constexpr bool f32 = sizeof(T) == 4;
+  hipStream_t st = b->stream;
+  auto detect = [&](const DevTable<FluxJob<T>>& d, int kind) -> hipError_t {
+    if constexpr (f32) return detect_batch_f32(d.jobs, d.start, d.njobs, d.nblocks, kind, st);
+    else return detect_batch_f64(d.jobs, d.start, d.njobs, d.nblocks, kind, st);
+  };
+  HIPCHK(detect(t.fsave, 0));
+  if constexpr (f32) HIPCHK(gather_batch_f32(t.gather.jobs, t.gather.start, t.gather.njobs,
+                                             t.gather.nblocks, st));
+  else HIPCHK(gather_batch_f64(t.gather.jobs, t.gather.start, t.gather.njobs, t.gather.nblocks,
+                               st));
+  HIPCHK(tls_batch(b->tls.jobs, b->tls.start, b->tls.njobs, b->tls.nblocks, st));
+  for (int n = 2; n <= kMaxLevels; ++n)
+    HIPCHK(ml_batch(b->ml[n].jobs, b->ml[n].start, b->ml[n].njobs, b->ml[n].nblocks, n, st));
+  const int tys[2] = {4, 8};
+  for (int k = 0; k < 2; ++k) {
+    const DevTable<FusedJob<T>>& f = t.fused[k];
+    if constexpr (f32) HIPCHK(sweep_fused_batch_f32(f.jobs, f.start, f.njobs, f.nblocks, tys[k], st));
+    else HIPCHK(sweep_fused_batch_f64(f.jobs, f.start, f.njobs, f.nblocks, tys[k], st));
+  }
+  for (int h = 1; h >= 0; --h) {
+    if constexpr (f32) HIPCHK(shell_batch_f32(t.shell.jobs, t.shell.start, t.shell.njobs,
+                                              t.shell.nblocks, h == 1, st));
+    else HIPCHK(shell_batch_f64(t.shell.jobs, t.shell.start, t.shell.njobs, t.shell.nblocks,
+                                h == 1, st));
+  }
+  if constexpr (f32) HIPCHK(sources_batch_f32(t.sources.jobs, t.sources.start, t.sources.njobs,
+                                              t.sources.nblocks, st));
+  else HIPCHK(sources_batch_f64(t.sources.jobs, t.sources.start, t.sources.njobs,
+                                t.sources.nblocks, st));
+  if constexpr (f32) HIPCHK(scatter_batch_f32(t.scatter.jobs, t.scatter.start, t.scatter.njobs,
+                                              t.scatter.nblocks, st));
+  else HIPCHK(scatter_batch_f64(t.scatter.jobs, t.scatter.start, t.scatter.njobs,
+                                t.scatter.nblocks, st));
+  HIPCHK(detect(t.fpart, 1));
+  HIPCHK(detect(t.finish, 2));
+  return MLK_OK;
+}
+
+// Make room in every member's series for n more steps; rebuild the tables (and
+// drop a captured graph) when a series had to move.
+mlk_status batch_reserve(mlk_batch* b, int64_t n) {
+  for (mlk_sim* s : b->sims) STCHK(reserve_series(s, n));
+  if (series_pointers(b) != b->series_snapshot) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->replay_steps = 0;
+    STCHK(rebuild_tables(b));
+  }
+  return MLK_OK;
+}
+
+// Enqueue n steps starting from the batch's current parity (no host bookkeeping).
+mlk_status enqueue_batch(mlk_batch* b, int64_t n, int parity0) {
+  for (int64_t k = 0; k < n; ++k) {
+    const int q = b->fused ? (int)((parity0 + k) & 1) : 0;
+    if (b->fp32) STCHK(enqueue_batch_step<float>(b, b->t32[q]));
+    else STCHK(enqueue_batch_step<double>(b, b->t64[q]));
+  }
+  return MLK_OK;
+}
+
+void batch_advance(mlk_batch* b, int64_t n) {
+  for (mlk_sim* s : b->sims) {
+    s->host_step += n;
+    if (b->fused && (n & 1)) swap_buffers(s);
+  }
+  if (b->fused) b->parity = (int)((b->parity + n) & 1);
+}
+
+}  // namespace
+
+extern "C" {
+
+mlk_status mlk_batch_create(mlk_sim* const* sims, int32_t n, mlk_batch** out) {
+  if (!sims || !out || n <= 0) return fail(MLK_EINVAL, "null argument or empty batch");
+  *out = nullptr;
+  auto* b = new mlk_batch();
+  for (int q = 0; q < n; ++q) {
+    mlk_sim* s = sims[q];
+    if (!s) {
+      delete b;
+      return fail(MLK_EINVAL, "member %d is null", q);
+    }
+    for (mlk_sim* o : b->sims)
+      if (o == s) {
+        delete b;
+        return fail(MLK_EINVAL, "member %d appears twice", q);
+      }
+    const mlk_sim* s0 = sims[0];
+    if (s->fp32 != s0->fp32 || s->desc.sweep != s0->desc.sweep || s->host_step != s0->host_step ||
+        s->desc.device != s0->desc.device) {
+      delete b;
+      return fail(MLK_EINVAL, "members must share precision, sweep, device and step count");
+    }
+    if (s->nem > 0 && s->desc.scatter != MLK_SCATTER_OWNER) {
+      delete b;
+      return fail(MLK_EUNSUPPORTED, "batched members use the owner-computes scatter");
+    }
+    if (s->batch_stream) {
+      delete b;
+      return fail(MLK_ESTATE, "member %d already belongs to a batch", q);
+    }
+    b->sims.push_back(s);
+  }
+  b->fp32 = sims[0]->fp32;
+  b->fused = sims[0]->desc.sweep == MLK_SWEEP_FUSED;
+  b->stream = sims[0]->stream;
+  for (mlk_sim* s : b->sims) {
+    mlk_status st = sync_sim(s);
+    if (st != MLK_OK) {
+      delete b;
+      return st;
+    }
+  }
+  for (mlk_sim* s : b->sims) {
+    if (s != sims[0]) s->batch_stream = b->stream;
+    s->in_batch = true;
+  }
+  mlk_status st = rebuild_tables(b);
+  if (st != MLK_OK) {
+    for (mlk_sim* s : b->sims) {
+      s->batch_stream = nullptr;
+      s->in_batch = false;
+    }
+    for (auto& t : b->t32) t.release();
+    for (auto& t : b->t64) t.release();
+    delete b;
+    return st;
+  }
+  *out = b;
+  return MLK_OK;
+}
+
+mlk_status mlk_batch_step(mlk_batch* b, int64_t nsteps) {
+  if (!b) return fail(MLK_EINVAL, "null argument");
+  if (nsteps < 0) return fail(MLK_EINVAL, "negative step count");
+  if (nsteps == 0) return MLK_OK;
+  HIPCHK(hipSetDevice(b->sims[0]->desc.device));
+  for (mlk_sim* s : b->sims)
+    if (s->stream != b->stream) HIPCHK(hipStreamSynchronize(s->stream));
+  STCHK(batch_reserve(b, nsteps));
+  STCHK(enqueue_batch(b, nsteps, b->parity));
+  batch_advance(b, nsteps);
+  return MLK_OK;
+}
+
+mlk_status mlk_batch_capture(mlk_batch* b, int64_t steps_per_replay) {
+  if (!b) return fail(MLK_EINVAL, "null argument");
+  if (steps_per_replay <= 0) return fail(MLK_EINVAL, "steps per replay must be positive");
+  if (b->fused && (steps_per_replay & 1))
+    return fail(MLK_EINVAL, "the fused sweep alternates two buffers: capture an even step count");
+  HIPCHK(hipSetDevice(b->sims[0]->desc.device));
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->replay_steps = 0;
+  HIPCHK(hipStreamSynchronize(b->stream));
+  HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  mlk_status st = enqueue_batch(b, steps_per_replay, b->parity);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(b->stream, &g);
+  if (st != MLK_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return fail(MLK_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(MLK_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
+  }
+  b->graph = g;
+  b->exec = x;
+  b->replay_steps = steps_per_replay;
+  b->capture_parity = b->parity;
+  return MLK_OK;
+}
+
+mlk_status mlk_batch_replay(mlk_batch* b, int64_t nreplays) {
+  if (!b) return fail(MLK_EINVAL, "null argument");
+  if (!b->exec) return fail(MLK_ESTATE, "nothing captured");
+  if (nreplays < 0) return fail(MLK_EINVAL, "negative replay count");
+  HIPCHK(hipSetDevice(b->sims[0]->desc.device));
+  for (mlk_sim* s : b->sims)
+    if (s->stream != b->stream) HIPCHK(hipStreamSynchronize(s->stream));
+  const int64_t spr = b->replay_steps;
+  STCHK(batch_reserve(b, nreplays * spr));
+  if (!b->exec || b->capture_parity != b->parity) {
+    // a series had to grow (the captured pointers are stale), or odd eager steps
+    // since the capture left the fused buffers the other way round: capture again
+    STCHK(mlk_batch_capture(b, spr));
+  }
+  for (int64_t r = 0; r < nreplays; ++r) {
+    HIPCHK(hipGraphLaunch(b->exec, b->stream));
+    batch_advance(b, spr);
+  }
+  return MLK_OK;
+}
+
+mlk_status mlk_batch_sync(mlk_batch* b) {
+  if (!b) return fail(MLK_EINVAL, "null argument");
+  HIPCHK(hipStreamSynchronize(b->stream));
+  return MLK_OK;
+}
+
+mlk_status mlk_batch_destroy(mlk_batch* b) {
+  if (!b) return MLK_OK;
+  (void)hipStreamSynchronize(b->stream);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (auto& t : b->t32) t.release();
+  for (auto& t : b->t64) t.release();
+  free_table(b->tls);
+  for (auto& t : b->ml) free_table(t);
+  for (mlk_sim* s : b->sims) {
+    s->batch_stream = nullptr;
+    s->in_batch = false;
+  }
+  delete b;
+  return MLK_OK;
+}
+
+}  // extern "C"
+
+// ==================================================================== autotuner
+//
+// The fused sweep has two tile parameters: the rows per workgroup (TY = 4 or 8;
+// 64 x TY threads) and the z planes each workgroup marches (kz).  They trade
+// LDS halo re-reads (larger TY) and prologue cost (larger kz) against the
+// number of workgroups in flight.  mlk_autotune times every pair on the sim's
+// own grid (the kernel reads the current fields and writes the spare buffers,
+// which the next step overwrites, so the state is untouched) and keeps the
+// fastest.  Results are cached in a small JSON file keyed by precision, grid
+// and interior box, one entry per line.
+
+namespace {
+
+std::string tune_key(const mlk_sim* s) {
+  const Box b = interior_box(s->g);
+  char k[160];
+  std::snprintf(k, sizeof k, "%s %d %d %d %d %d %d %d %d %d", s->fp32 ? "fp32" : "fp64",
+                s->g.n[0], s->g.n[1], s->g.n[2], b.lo[0], b.lo[1], b.lo[2], b.hi[0], b.hi[1],
+                b.hi[2]);
+  return k;
+}
+
+struct TuneEntry {
+  std::string key;
+  int ty, kz;
+  double us;
+};
+
+std::vector<TuneEntry> read_cache(const char* path) {
+  std::vector<TuneEntry> v;
+  FILE* f = path ? std::fopen(path, "r") : nullptr;
+  if (!f) return v;
+  char line[512];
+  while (std::fgets(line, sizeof line, f)) {
+    char key[200];
+    TuneEntry e{};
+    if (std::sscanf(line, " \"%199[^\"]\": {\"ty\": %d, \"kz\": %d, \"us\": %lf", key, &e.ty, &e.kz,
+                    &e.us) == 4) {
+      e.key = key;
+      v.push_back(e);
+    }
+  }
+  std::fclose(f);
+  return v;
+}
+
+bool write_cache(const char* path, const std::vector<TuneEntry>& v) {
+  FILE* f = std::fopen(path, "w");
+  if (!f) return false;
+  std::fprintf(f, "{\n");
+  for (size_t q = 0; q < v.size(); ++q)
+    std::fprintf(f, "\"%s\": {\"ty\": %d, \"kz\": %d, \"us\": %.3f}%s\n", v[q].key.c_str(),
+                 v[q].ty, v[q].kz, v[q].us, q + 1 < v.size() ? "," : "");
+  std::fprintf(f, "}\n");
+  return std::fclose(f) == 0;
+}
+
+template <typename T>
+mlk_status time_fused(mlk_sim* s, int ty, int kz, double* us) {
+  const FieldPtrs<T> a = field_ptrs<T>(s), b = spare_ptrs<T>(s);
+  const Box inner = interior_box(s->g);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  hipError_t err = hipSuccess;
+  constexpr int kReps = 4;
+  for (int r = -1; r < kReps && err == hipSuccess; ++r) {
+    if (r == 0) err = hipEventRecord(e0, s->stream);
+    if (err == hipSuccess) {
+      if constexpr (sizeof(T) == 4) err = sweep_fused_f32(a, b, s->g, inner, kz, ty, s->stream);
+      else err = sweep_fused_f64(a, b, s->g, inner, kz, ty, s->stream);
+    }
+  }
+  if (err == hipSuccess) err = hipEventRecord(e1, s->stream);
+  if (err == hipSuccess) err = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIPCHK(err);
+  *us = 1e3 * ms / kReps;
+  return MLK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mlk_status mlk_set_tuning(mlk_sim* s, int32_t ty, int32_t kz) {
+  if (!s) return fail(MLK_EINVAL, "null argument");
+  if (ty != 4 && ty != 8) return fail(MLK_EINVAL, "rows per workgroup must be 4 or 8");
+  if (kz < 1) return fail(MLK_EINVAL, "planes per workgroup must be positive");
+  if (s->in_batch) return fail(MLK_ESTATE, "tune members before forming the batch");
+  s->ty = ty;
+  s->kz = kz;
+  return MLK_OK;
+}
+
+mlk_status mlk_get_tuning(mlk_sim* s, int32_t* ty, int32_t* kz) {
+  if (!s || !ty || !kz) return fail(MLK_EINVAL, "null argument");
+  *ty = s->ty;
+  *kz = s->kz;
+  return MLK_OK;
+}
+
+mlk_status mlk_autotune(mlk_sim* s, const char* cache_path) {
+  if (!s) return fail(MLK_EINVAL, "null argument");
+  if (s->in_batch) return fail(MLK_ESTATE, "tune members before forming the batch");
+  if (s->desc.sweep != MLK_SWEEP_FUSED) return MLK_OK;  // nothing to tune
+  const std::string key = tune_key(s);
+  std::vector<TuneEntry> cache = read_cache(cache_path);
+  for (const TuneEntry& e : cache)
+    if (e.key == key && (e.ty == 4 || e.ty == 8) && e.kz > 0) {
+      s->ty = e.ty;
+      s->kz = e.kz;
+      return MLK_OK;
+    }
+  HIPCHK(hipSetDevice(s->desc.device));
+  STCHK(sync_sim(s));
+  const Box inner = interior_box(s->g);
+  const int ez = inner.hi[2] - inner.lo[2];
+  if (ez <= 0) return MLK_OK;
+  double best = 1e300;
+  int bty = s->ty, bkz = s->kz;
+  for (int ty : {4, 8})
+    for (int kz : {4, 8, 16, 32, 64, 128}) {
+      if (kz > std::max(4, ez)) continue;
+      double us = 0.0;
+      STCHK(s->fp32 ? time_fused<float>(s, ty, kz, &us) : time_fused<double>(s, ty, kz, &us));
+      if (us < best) {
+        best = us;
+        bty = ty;
+        bkz = kz;
+      }
+    }
+  s->ty = bty;
+  s->kz = bkz;
+  if (cache_path) {
+    cache.push_back({key, bty, bkz, best});
+    if (!write_cache(cache_path, cache))
+      return fail(MLK_EINVAL, "cannot write the tuning cache %s", cache_path);
+  }
   return MLK_OK;
 }
 

@@ -83,18 +83,19 @@ __device__ __forceinline__ bool load3(const FieldPtrs<T>& f, Col col, Col pl, T 
 }
 
 template <typename T, int TY>
-__global__ __launch_bounds__(64 * TY) void k_fused(FieldPtrs<T> a, FieldPtrs<T> b, Geom g,
-                                                   Box box, int kz, int ntx, int nty,
-                                                   int nblocks) {
+__device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtrs<T>& b,
+                                           const Geom& g, const Box& box, int kz, int ntx,
+                                           int nty, int nblocks, int bid_in) {
   constexpr int EW = 66, EH = TY + 2;   // E plane in LDS: x in [-1, 64], y in [-1, TY]
   constexpr int HW = 65, HH = TY + 1;   // H plane in LDS: x in [-1, 63], y in [-1, TY-1]
   constexpr int NHALO = 2 * EW + 2 * TY;  // ring of the E plane
+  static_assert(64 * TY >= NHALO, "one thread per ring slot of the staged E plane");
   __shared__ T eL[2][3][EH * EW];
   __shared__ T hL[3][HH * HW];
 
   // XCD-aware tile order: consecutive blocks go to different XCDs; map the
   // blocks one XCD receives onto a contiguous range of tiles.
-  int bid = blockIdx.x;
+  int bid = bid_in;
   const int q8 = nblocks / 8;
   if (bid < 8 * q8) bid = (bid % 8) * q8 + bid / 8;
   const int tile_x = bid % ntx, tile_y = (bid / ntx) % nty, chunk = bid / (ntx * nty);
@@ -291,6 +292,24 @@ __global__ __launch_bounds__(64 * TY) void k_fused(FieldPtrs<T> a, FieldPtrs<T> 
 }
 
 template <typename T, int TY>
+__global__ __launch_bounds__(64 * TY) void k_fused(FieldPtrs<T> a, FieldPtrs<T> b, Geom g,
+                                                   Box box, int kz, int ntx, int nty,
+                                                   int nblocks) {
+  fused_body<T, TY>(a, b, g, box, kz, ntx, nty, nblocks, blockIdx.x);
+}
+
+// One launch over the jobs of a batch of domains (see BatchJobs).
+template <typename T, int TY>
+__global__ __launch_bounds__(64 * TY) void k_fused_batch(const FusedJob<T>* jobs,
+                                                         const int* start, int njobs) {
+  const int j = find_job(start, njobs, blockIdx.x);
+  const FusedJob<T>& J = jobs[j];
+  const int bid = blockIdx.x - start[j];
+  if (J.ty != TY || bid >= J.nblocks) return;
+  fused_body<T, TY>(J.a, J.b, J.g, J.box, J.kz, J.ntx, J.nty, J.nblocks, bid);
+}
+
+template <typename T, int TY>
 static hipError_t launch_fused(const FieldPtrs<T>& a, const FieldPtrs<T>& b, const Geom& g,
                                const Box& box, int kz, hipStream_t st) {
   const int ex = box.hi[0] - box.lo[0], ey = box.hi[1] - box.lo[1], ez = box.hi[2] - box.lo[2];
@@ -303,13 +322,56 @@ static hipError_t launch_fused(const FieldPtrs<T>& a, const FieldPtrs<T>& b, con
   return hipGetLastError();
 }
 
+// Tile grid of the fused kernel over a box: x tiles of 64 from the 128-byte
+// boundary at or below box.lo, y tiles of TY, z chunks of kz planes.
+template <typename T>
+void fused_job_shape(FusedJob<T>& J) {
+  const Box& box = J.box;
+  const int ex = box.hi[0] - box.lo[0], ey = box.hi[1] - box.lo[1], ez = box.hi[2] - box.lo[2];
+  if (ex <= 0 || ey <= 0 || ez <= 0) {
+    J.ntx = J.nty = J.nblocks = 0;
+    return;
+  }
+  J.ntx = (box.hi[0] - (box.lo[0] & ~31) + 63) / 64;
+  J.nty = (ey + J.ty - 1) / J.ty;
+  J.nblocks = J.ntx * J.nty * ((ez + J.kz - 1) / J.kz);
+}
+template void fused_job_shape<float>(FusedJob<float>&);
+template void fused_job_shape<double>(FusedJob<double>&);
+
+template <typename T>
+static hipError_t launch_fused_any(const FieldPtrs<T>& a, const FieldPtrs<T>& b, const Geom& g,
+                                   const Box& box, int kz, int ty, hipStream_t st) {
+  if (ty == 8) return launch_fused<T, 8>(a, b, g, box, kz, st);
+  return launch_fused<T, 4>(a, b, g, box, kz, st);
+}
+
+template <typename T>
+static hipError_t launch_fused_batch(const FusedJob<T>* jobs, const int* start, int njobs,
+                                     int nblocks, int ty, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  if (ty == 8)
+    hipLaunchKernelGGL((k_fused_batch<T, 8>), dim3(nblocks), dim3(512), 0, st, jobs, start, njobs);
+  else
+    hipLaunchKernelGGL((k_fused_batch<T, 4>), dim3(nblocks), dim3(256), 0, st, jobs, start, njobs);
+  return hipGetLastError();
+}
+
 hipError_t sweep_fused_f64(const FieldPtrs<double>& a, const FieldPtrs<double>& b, const Geom& g,
-                           const Box& box, int kz, hipStream_t st) {
-  return launch_fused<double, 4>(a, b, g, box, kz, st);
+                           const Box& box, int kz, int ty, hipStream_t st) {
+  return launch_fused_any<double>(a, b, g, box, kz, ty, st);
 }
 hipError_t sweep_fused_f32(const FieldPtrs<float>& a, const FieldPtrs<float>& b, const Geom& g,
-                           const Box& box, int kz, hipStream_t st) {
-  return launch_fused<float, 4>(a, b, g, box, kz, st);
+                           const Box& box, int kz, int ty, hipStream_t st) {
+  return launch_fused_any<float>(a, b, g, box, kz, ty, st);
+}
+hipError_t sweep_fused_batch_f64(const FusedJob<double>* jobs, const int* start, int njobs,
+                                 int nblocks, int ty, hipStream_t st) {
+  return launch_fused_batch<double>(jobs, start, njobs, nblocks, ty, st);
+}
+hipError_t sweep_fused_batch_f32(const FusedJob<float>* jobs, const int* start, int njobs,
+                                 int nblocks, int ty, hipStream_t st) {
+  return launch_fused_batch<float>(jobs, start, njobs, nblocks, ty, st);
 }
 
 }  // namespace mlk

@@ -83,21 +83,6 @@ __global__ __launch_bounds__(256) void k_update_box(FieldPtrs<T> in, FieldPtrs<T
   else update_e_cell(in, out, g, i, j, k);
 }
 
-// The cells of the grid outside an interior box, enumerated in memory order:
-// the whole planes below and above the box in z, then, plane by plane inside
-// it, the whole rows below and above it in y followed by the two x strips of
-// each remaining row.
-struct ShellMap {
-  Box in;
-  int nzlo;              // whole planes below the box
-  long long nslab;       // cells in the whole planes (both sides)
-  int ylo_rows;          // whole rows below the box, per middle plane
-  int full_cells;        // cells in the whole rows of one middle plane
-  int strip;             // cells in the two x strips of one row
-  int per_plane;         // shell cells of one middle plane
-  long long total;
-};
-
 __device__ __forceinline__ void shell_cell(const Geom& g, const ShellMap& m, long long t, int& i,
                                            int& j, int& k) {
   const int nx = g.n[0], ny = g.n[1];
@@ -138,15 +123,25 @@ __global__ __launch_bounds__(256) void k_update_shell(FieldPtrs<T> in, FieldPtrs
   else update_e_cell(in, out, g, i, j, k);
 }
 
+template <typename T, bool H>
+__global__ __launch_bounds__(256) void k_update_shell_batch(const ShellJob<T>* jobs,
+                                                            const int* start, int njobs) {
+  const int jb = find_job(start, njobs, blockIdx.x);
+  const ShellJob<T>& J = jobs[jb];
+  const long long t = (long long)(blockIdx.x - start[jb]) * blockDim.x + threadIdx.x;
+  if (t >= J.m.total) return;
+  int i, j, k;
+  shell_cell(J.g, J.m, t, i, j, k);
+  if (H) update_h_cell(J.in, J.out, J.g, i, j, k);
+  else update_e_cell(J.in, J.out, J.g, i, j, k);
+}
+
 // Soft source currents J at t = (n + 1/2) dt:  E -= (dt/eps_r) J.  One thread per
 // cell of each source's support (a plane, or one cell); metallic-wall cells of
 // the driven component keep E = 0.
 template <typename T>
-__global__ void k_sources(FieldPtrs<T> f, Geom g, SourceSet src, const int64_t* step) {
-  const int q = blockIdx.y;
-  if (q >= src.count) return;
-  const Source& s = src.s[q];
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void source_body(const FieldPtrs<T>& f, const Geom& g, const Source& s,
+                                            const int64_t* step, int t) {
   int i, j, k;
   double scale;
   if (s.kind == 0) {
@@ -175,6 +170,35 @@ __global__ void k_sources(FieldPtrs<T> f, Geom g, SourceSet src, const int64_t* 
 }
 
 template <typename T>
+__global__ void k_sources(FieldPtrs<T> f, Geom g, SourceSet src, const int64_t* step) {
+  const int q = blockIdx.y;
+  if (q >= src.count) return;
+  source_body(f, g, src.s[q], step, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sources_batch(const SourceJob<T>* jobs, const int* start,
+                                                       int njobs) {
+  const int jb = find_job(start, njobs, blockIdx.x);
+  const SourceJob<T>& J = jobs[jb];
+  const int lb = blockIdx.x - start[jb];
+  if (lb >= J.nblocks) return;
+  const int q = lb / J.bx;
+  source_body(J.f, J.g, J.src.s[q], J.step, (lb - q * J.bx) * blockDim.x + threadIdx.x);
+}
+
+// Blocks of 256 threads per source of a set (the largest support).
+inline int source_blocks(const Geom& g, const SourceSet& src) {
+  int maxp = 1;
+  for (int q = 0; q < src.count; ++q)
+    if (src.s[q].kind == 0) {
+      const int u = (src.s[q].axis + 1) % 3, v = (src.s[q].axis + 2) % 3;
+      maxp = max(maxp, g.n[u] * g.n[v]);
+    }
+  return (maxp + 255) / 256;
+}
+
+template <typename T>
 static hipError_t launch_plain(const FieldPtrs<T>& in, const FieldPtrs<T>& out, const Geom& g,
                                const Box* boxes, int nbox, bool h_pass, bool e_pass,
                                hipStream_t st) {
@@ -195,9 +219,7 @@ static hipError_t launch_plain(const FieldPtrs<T>& in, const FieldPtrs<T>& out, 
   return hipSuccess;
 }
 
-template <typename T>
-static hipError_t launch_shell(const FieldPtrs<T>& in, const FieldPtrs<T>& out, const Geom& g,
-                               const Box& inner, bool h_pass, hipStream_t st) {
+ShellMap shell_map(const Geom& g, const Box& inner) {
   ShellMap m{};
   m.in = inner;
   const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
@@ -209,6 +231,15 @@ static hipError_t launch_shell(const FieldPtrs<T>& in, const FieldPtrs<T>& out, 
   m.strip = inner.lo[0] + (nx - inner.hi[0]);
   m.per_plane = m.full_cells + wy * m.strip;
   m.total = m.nslab + (long long)wz * m.per_plane;
+  return m;
+}
+
+int source_blocks_of(const Geom& g, const SourceSet& src) { return source_blocks(g, src); }
+
+template <typename T>
+static hipError_t launch_shell(const FieldPtrs<T>& in, const FieldPtrs<T>& out, const Geom& g,
+                               const Box& inner, bool h_pass, hipStream_t st) {
+  const ShellMap m = shell_map(g, inner);
   if (m.total == 0) return hipSuccess;
   const long long blocks = (m.total + 255) / 256;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
@@ -225,13 +256,7 @@ template <typename T>
 static hipError_t launch_sources(const FieldPtrs<T>& f, const Geom& g, const SourceSet& src,
                                  const int64_t* step, hipStream_t st) {
   if (src.count == 0) return hipSuccess;
-  int maxp = 1;
-  for (int q = 0; q < src.count; ++q)
-    if (src.s[q].kind == 0) {
-      const int u = (src.s[q].axis + 1) % 3, v = (src.s[q].axis + 2) % 3;
-      maxp = max(maxp, g.n[u] * g.n[v]);
-    }
-  hipLaunchKernelGGL(k_sources<T>, dim3((maxp + 255) / 256, src.count), dim3(256), 0, st, f, g,
+  hipLaunchKernelGGL(k_sources<T>, dim3(source_blocks(g, src), src.count), dim3(256), 0, st, f, g,
                      src, step);
   return hipGetLastError();
 }
@@ -252,6 +277,41 @@ hipError_t sweep_shell_f64(const FieldPtrs<double>& in, const FieldPtrs<double>&
 hipError_t sweep_shell_f32(const FieldPtrs<float>& in, const FieldPtrs<float>& out, const Geom& g,
                            const Box& inner, bool h_pass, hipStream_t st) {
   return launch_shell<float>(in, out, g, inner, h_pass, st);
+}
+template <typename T>
+static hipError_t launch_shell_batch(const ShellJob<T>* jobs, const int* start, int njobs,
+                                     int nblocks, bool h_pass, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  if (h_pass)
+    hipLaunchKernelGGL((k_update_shell_batch<T, true>), dim3(nblocks), dim3(256), 0, st, jobs,
+                       start, njobs);
+  else
+    hipLaunchKernelGGL((k_update_shell_batch<T, false>), dim3(nblocks), dim3(256), 0, st, jobs,
+                       start, njobs);
+  return hipGetLastError();
+}
+template <typename T>
+static hipError_t launch_sources_batch(const SourceJob<T>* jobs, const int* start, int njobs,
+                                       int nblocks, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sources_batch<T>, dim3(nblocks), dim3(256), 0, st, jobs, start, njobs);
+  return hipGetLastError();
+}
+hipError_t shell_batch_f64(const ShellJob<double>* jobs, const int* start, int njobs, int nblocks,
+                           bool h_pass, hipStream_t st) {
+  return launch_shell_batch<double>(jobs, start, njobs, nblocks, h_pass, st);
+}
+hipError_t shell_batch_f32(const ShellJob<float>* jobs, const int* start, int njobs, int nblocks,
+                           bool h_pass, hipStream_t st) {
+  return launch_shell_batch<float>(jobs, start, njobs, nblocks, h_pass, st);
+}
+hipError_t sources_batch_f64(const SourceJob<double>* jobs, const int* start, int njobs,
+                             int nblocks, hipStream_t st) {
+  return launch_sources_batch<double>(jobs, start, njobs, nblocks, st);
+}
+hipError_t sources_batch_f32(const SourceJob<float>* jobs, const int* start, int njobs,
+                             int nblocks, hipStream_t st) {
+  return launch_sources_batch<float>(jobs, start, njobs, nblocks, st);
 }
 hipError_t sources_f64(const FieldPtrs<double>& f, const Geom& g, const SourceSet& src,
                        const int64_t* step, hipStream_t st) {

@@ -64,6 +64,12 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2512_06173_amd/build.py")
+    # torch ships its own HIP runtime under the same soname as the system one that
+    # libmlk links.  Loading torch first makes the library bind to that runtime, so the
+    # process holds one HIP runtime and torch's streams and device memory are valid
+    # handles for the library (loaded the other way round, two runtimes would share
+    # the GPU and torch would find no device).
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     st = C.c_int
     sim = C.c_void_p
@@ -100,6 +106,15 @@ def lib():
         "mlk_set_timing": (st, [sim, C.c_int32]),
         "mlk_get_phase_time": (st, [sim, C.c_int32, _dp, _lp]),
         "mlk_get_interior_box": (st, [sim, _ip]),
+        "mlk_batch_create": (st, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)]),
+        "mlk_batch_step": (st, [C.c_void_p, C.c_int64]),
+        "mlk_batch_capture": (st, [C.c_void_p, C.c_int64]),
+        "mlk_batch_replay": (st, [C.c_void_p, C.c_int64]),
+        "mlk_batch_sync": (st, [C.c_void_p]),
+        "mlk_batch_destroy": (st, [C.c_void_p]),
+        "mlk_autotune": (st, [sim, C.c_char_p]),
+        "mlk_set_tuning": (st, [sim, C.c_int32, C.c_int32]),
+        "mlk_get_tuning": (st, [sim, _ip, _ip]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(L, name)
@@ -118,7 +133,9 @@ def exported_symbols():
             "mlk_get_rho", "mlk_get_tls_state", "mlk_get_emitter_io", "mlk_get_series",
             "mlk_get_flux_total", "mlk_checkpoint_size", "mlk_checkpoint_save",
             "mlk_checkpoint_load", "mlk_set_timing", "mlk_get_phase_time",
-            "mlk_get_interior_box"]
+            "mlk_get_interior_box", "mlk_batch_create", "mlk_batch_step", "mlk_batch_capture",
+            "mlk_batch_replay", "mlk_batch_sync", "mlk_batch_destroy", "mlk_autotune",
+            "mlk_set_tuning", "mlk_get_tuning"]
 
 
 def _check(st):
@@ -182,7 +199,7 @@ class Simulation:
     def close(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            lib().mlk_destroy(h)
+            _check(lib().mlk_destroy(h))  # refused while the sim belongs to a batch
         self._h = None
 
     def __del__(self):
@@ -376,6 +393,62 @@ class Simulation:
         b, pb = _i32(np.zeros(6))
         _check(lib().mlk_get_interior_box(self._h, pb))
         return tuple(int(v) for v in b[:3]), tuple(int(v) for v in b[3:])
+
+
+    # ------------------------------------------------------------ tuning
+    def autotune(self, cache_path=None):
+        """Pick the fused sweep's tile shape by timing (optionally cached in JSON)."""
+        _check(lib().mlk_autotune(self._h, cache_path.encode() if cache_path else None))
+        return self.tuning()
+
+    def tuning(self):
+        ty, kz = C.c_int32(), C.c_int32()
+        _check(lib().mlk_get_tuning(self._h, C.byref(ty), C.byref(kz)))
+        return ty.value, kz.value
+
+    def set_tuning(self, ty, kz):
+        _check(lib().mlk_set_tuning(self._h, int(ty), int(kz)))
+
+
+class Batch:
+    """Independent simulations stepped together: one launch per phase for all of them,
+    optionally replayed from a captured hipGraph."""
+
+    def __init__(self, sims):
+        self.sims = list(sims)
+        arr = (C.c_void_p * len(self.sims))(*[s._h for s in self.sims])
+        h = C.c_void_p()
+        _check(lib().mlk_batch_create(arr, len(self.sims), C.byref(h)))
+        self._h = h
+
+    def step(self, n=1):
+        _check(lib().mlk_batch_step(self._h, int(n)))
+
+    def capture(self, steps_per_replay):
+        _check(lib().mlk_batch_capture(self._h, int(steps_per_replay)))
+
+    def replay(self, n=1):
+        _check(lib().mlk_batch_replay(self._h, int(n)))
+
+    def sync(self):
+        _check(lib().mlk_batch_sync(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().mlk_batch_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 PHASES = {"emitters": 0, "sweep": 1, "shell": 2, "sources": 3, "scatter": 4, "detectors": 5}

@@ -1,0 +1,156 @@
+"""Batched stepping: many independent domains stepped with one launch per phase (and
+replayed from a captured hipGraph) give, bit for bit, what each domain gives when
+stepped on its own; the fused sweep's tile shape changes speed, not results."""
+import numpy as np
+import pytest
+
+from oracle.feed import build_oracle
+from paper_2512_06173_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def mlk():
+    from paper_2512_06173_amd import mlk as m
+    return m
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def domains(precision, seed=4):
+    """Four cubic domains of uneven sizes (CPML 8, random eps blocks, 1-40 TLS), with a
+    point source, a probe and a flux plane on some of them."""
+    rng = np.random.default_rng(seed)
+    ws = []
+    for n in (32, 48, 40, 32):
+        w = W.batch_domain(rng, n, max_emit=40, steps=0, precision=precision)
+        ws.append(w)
+    ws[0].point_sources = [W.PointSource(2, (16, 16, 12), 1.0, 0.3, 5.0, 20.0)]
+    ws[0].probes = [(2, (18, 16, 20))]
+    ws[1].flux = (2, 36)
+    ws[1].pop_every = 2
+    ws[2].plane_sources = [W.PlaneSource(2, 10, 1, 0.5, 0.25, 8.0, 30.0)]
+    ws[2].probes = [(1, (20, 20, 30)), (4, (12, 20, 20))]
+    ws[3].pop_every = 1
+    return ws
+
+
+def same(a, b):
+    return all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def compare(sa, sb, w):
+    assert same(sa.fields(), sb.fields())
+    for p in range(len(w.probes)):
+        assert np.array_equal(sa.probe(p), sb.probe(p))
+    if w.flux is not None:
+        assert np.array_equal(sa.flux_series(), sb.flux_series())
+        assert sa.flux_total() == sb.flux_total()
+    if w.pop_every and w.n_emitters:
+        assert np.array_equal(sa.populations(), sb.populations())
+
+
+@pytest.mark.parametrize("sweep", ["fused", "plain"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batch_equals_members_alone(precision, sweep):
+    ws = domains(precision)
+    say(f"[batch] {precision} {sweep}: {[w.shape[0] for w in ws]}")
+    solo = [mlk().from_workload(w, sweep=sweep) for w in ws]
+    mem = [mlk().from_workload(w, sweep=sweep) for w in ws]
+    for s in solo:
+        s.step(57)
+    with mlk().Batch(mem) as b:
+        b.step(37)  # odd: the fused buffers end swapped
+        b.step(20)
+        b.sync()
+        for s, m, w in zip(solo, mem, ws):
+            compare(s, m, w)
+    # the members carry on alone
+    for s, m in zip(solo, mem):
+        s.step(3)
+        m.step(3)
+        assert same(s.fields(), m.fields())
+
+
+def test_batch_member_matches_oracle_fp64():
+    ws = domains("fp64", seed=8)
+    mem = [mlk().from_workload(w) for w in ws]
+    with mlk().Batch(mem) as b:
+        b.step(40)
+    ora = build_oracle(ws[1])
+    ora.step(40)
+    f, o = mem[1].fields(), ora.fields()
+    e = np.linalg.norm(np.concatenate([np.ravel(a - c) for a, c in zip(f, o)])) / \
+        np.linalg.norm(np.concatenate([np.ravel(c) for c in o]))
+    say(f"  member vs oracle rel L2 {e:.3e}")
+    assert e <= 1e-12
+
+
+def test_graph_replay_equals_eager_steps():
+    """Capture 10 steps, replay with unrelated eager GPU work and host reads between the
+    replays; every replay must match stepping eagerly.  The last replays run past the
+    recorded series' first capacity, which forces a re-capture."""
+    import torch
+    ws = domains("fp32", seed=6)
+    solo = [mlk().from_workload(w) for w in ws]
+    mem = [mlk().from_workload(w) for w in ws]
+    with mlk().Batch(mem) as b:
+        b.capture(10)
+        for r in range(3):
+            b.replay(1)
+            b.sync()
+            x = torch.ones(1 << 20, device="cuda").sum().item()  # eager work between replays
+            assert x == float(1 << 20)
+            for s in solo:
+                s.step(10)
+            for s, m, w in zip(solo, mem, ws):
+                compare(s, m, w)
+        b.replay(110)  # 1130 steps in all: the series grow past 1024 entries
+        b.sync()
+        for s in solo:
+            s.step(1100)
+        for s, m, w in zip(solo, mem, ws):
+            compare(s, m, w)
+
+
+def test_capture_needs_even_steps_in_fused_mode():
+    ws = domains("fp32")
+    mem = [mlk().from_workload(w) for w in ws[:2]]
+    with mlk().Batch(mem) as b:
+        with pytest.raises(mlk().MlkError):
+            b.capture(7)
+
+
+def test_member_cannot_be_destroyed_while_batched():
+    ws = domains("fp32")
+    mem = [mlk().from_workload(w) for w in ws[:2]]
+    b = mlk().Batch(mem)
+    with pytest.raises(mlk().MlkError):
+        mem[0].close()
+    b.close()
+    mem[0].close()
+
+
+def test_tile_shape_changes_speed_not_results(tmp_path):
+    w = W.radiating_cube(n=72, n_emit=300, steps=0, cpml=10, precision="fp32")
+    a = mlk().from_workload(w)
+    b = mlk().from_workload(w)
+    b.set_tuning(8, 5)
+    c = mlk().from_workload(w)
+    c.set_tuning(4, 64)
+    for s in (a, b, c):
+        s.step(25)
+    assert same(a.fields(), b.fields()) and same(a.fields(), c.fields())
+    with pytest.raises(mlk().MlkError):
+        c.set_tuning(2, 8)  # a 64 x 2 workgroup cannot stage the halo ring
+    cache = str(tmp_path / "tune.json")
+    t = a.autotune(cache)
+    say(f"  autotuned (ty, kz) = {t}")
+    assert t[0] in (4, 8) and t[1] >= 1
+    d = mlk().from_workload(w)
+    assert d.autotune(cache) == t  # read back from the cache
+    import json
+    entries = json.load(open(cache))
+    assert len(entries) == 1
