@@ -1028,3 +1028,442 @@ void ora_set_threads(int n) {
   (void)n;
 #endif
 }
+
+/* ================================================================ adjoint
+ *
+ * Reverse-mode discrete adjoint of the coupled step as the oracle executes it
+ * (two-level emitters only), for the objectives
+ *   kind 0: J = dt sum_n F^{n+1/2}        (time-integrated flux through the flux plane)
+ *   kind 1: J = sum_m w_m rho11_m          (populations after the last step)
+ * and its gradients with respect to eps_r of every cell of a box and to each
+ * emitter's dipole vector d_m.  The forward pass stores every E^n, H^{n+1/2},
+ * emitter state rho^{n-1/2} and E~^n (the oracle is for small grids), then the
+ * steps are undone in reverse.  Each linear update y = A x is transposed
+ * operation by operation: every contribution A_ij x_j of the forward pass is
+ * scattered back as xbar_j += A_ij ybar_i.  The state of the sim is restored
+ * afterwards. */
+
+/* index of the cell one step along axis a from (i,j,k) (delta = +1 or -1), with
+ * periodic wrap, or -1 when it lies beyond a non-periodic face */
+static long long nb_cell(const ora_sim* s, int i, int j, int k, int a, int delta) {
+  int q[3] = {i, j, k};
+  q[a] += delta;
+  if (q[a] < 0 || q[a] >= s->N[a]) {
+    if (s->bc[2 * a] != ORA_PERIODIC) return -1;
+    q[a] = (q[a] + s->N[a]) % s->N[a];
+  }
+  return (long long)IDX(s, q[0], q[1], q[2]);
+}
+
+/* curl terms of component c: axis, sign and the other field's component */
+static const int CURL_AX[3][2] = {{1, 2}, {2, 0}, {0, 1}};
+static const int CURL_SG[3][2] = {{1, -1}, {1, -1}, {1, -1}};
+static const int CURL_OT[3][2] = {{2, 1}, {0, 2}, {1, 0}};
+
+/* adjoint of the stretched derivative: w is the adjoint of the stretched value,
+ * *pb the adjoint of psi after the update (replaced by the adjoint before it);
+ * returns the adjoint of the plain derivative */
+static inline double stretched_bar(const ora_sim* s, int ax, int half, int pos, double w,
+                                   double* pb) {
+  if (!s->tin[ax][half][pos]) return w;
+  double b = s->tb[ax][half][pos], c = s->tc[ax][half][pos], kinv = s->tk[ax][half][pos];
+  double dbar = (kinv + c) * w + c * (*pb);
+  *pb = b * (w + *pb);
+  return dbar;
+}
+
+static int is_wall_E(const ora_sim* s, int c, int i, int j, int k) {
+  int q[3] = {i, j, k};
+  for (int ax = 0; ax < 3; ++ax)
+    if (ax != c && s->bc[2 * ax] != ORA_PERIODIC && q[ax] == 0) return 1;
+  return 0;
+}
+
+/* Transposed E update: Eb is the adjoint of E^{n+1} (replaced by that of E^n,
+ * through the identity part), Hb gains the curl part, psiEb is updated.
+ * Returns nothing; the adjoint of the current J is -(dt/eps) Eb_masked, which
+ * the caller forms from ub (the wall-masked Eb, filled here). */
+static void adjoint_update_E(const ora_sim* s, double* Eb[3], double* Hb[3], double* psiEb[3][3],
+                             double* ub[3]) {
+  const double dt = s->dt, idx = 1.0 / s->dx;
+  for (int k = 0; k < s->N[2]; ++k)
+    for (int j = 0; j < s->N[1]; ++j)
+      for (int i = 0; i < s->N[0]; ++i) {
+        size_t id = IDX(s, i, j, k);
+        int pos[3] = {i, j, k};
+        for (int c = 0; c < 3; ++c) {
+          double u = is_wall_E(s, c, i, j, k) ? 0.0 : Eb[c][id];
+          ub[c][id] = u;
+          Eb[c][id] = u; /* E^{n+1} = E^n + ... off the walls */
+          for (int t = 0; t < 2; ++t) {
+            int a = CURL_AX[c][t], h = CURL_OT[c][t];
+            double w = CURL_SG[c][t] * dt / s->eps[id] * u;
+            double dummy = 0.0;
+            double* pb = psiEb[c][a] ? &psiEb[c][a][id] : &dummy;
+            double dbar = stretched_bar(s, a, 0, pos[a], w, pb) * idx;
+            /* d = (H_h(cell) - H_h(cell - e_a)) / dx */
+            Hb[h][id] += dbar;
+            long long m = nb_cell(s, i, j, k, a, -1);
+            if (m >= 0) Hb[h][m] -= dbar;
+          }
+        }
+      }
+}
+
+/* Transposed H update: Hb is the adjoint of H^{n+1/2} (the identity part keeps
+ * it as that of H^{n-1/2}), Eb gains the curl part, psiHb is updated. */
+static void adjoint_update_H(const ora_sim* s, double* Eb[3], double* Hb[3], double* psiHb[3][3]) {
+  const double dt = s->dt, idx = 1.0 / s->dx;
+  for (int k = 0; k < s->N[2]; ++k)
+    for (int j = 0; j < s->N[1]; ++j)
+      for (int i = 0; i < s->N[0]; ++i) {
+        size_t id = IDX(s, i, j, k);
+        int pos[3] = {i, j, k};
+        for (int h = 0; h < 3; ++h) {
+          for (int t = 0; t < 2; ++t) {
+            int a = CURL_AX[h][t], e = CURL_OT[h][t];
+            double w = -CURL_SG[h][t] * dt * Hb[h][id];
+            double dummy = 0.0;
+            double* pb = psiHb[h][a] ? &psiHb[h][a][id] : &dummy;
+            double dbar = stretched_bar(s, a, 1, pos[a], w, pb) * idx;
+            /* d = (E_e(cell + e_a) - E_e(cell)) / dx */
+            long long m = nb_cell(s, i, j, k, a, +1);
+            if (m >= 0) Eb[e][m] += dbar;
+            Eb[e][id] -= dbar;
+          }
+        }
+      }
+}
+
+/* Two-level state s = (rho11, Re rho01, Im rho01) after one exact step under
+ * field g, by V rho V^+ as in step_tls. */
+static void tls_map(double w0, double dt, double g, const double in[3], double out[3]) {
+  double hx = -g, hz = -0.5 * w0;
+  double Om = sqrt(hx * hx + hz * hz);
+  double cs = cos(Om * dt), sn = (Om > 0.0) ? sin(Om * dt) / Om : dt;
+  cplx V[4] = {cs - I * sn * hz, -I * sn * hx, -I * sn * hx, cs + I * sn * hz};
+  cplx r[4] = {1.0 - in[0], in[1] + I * in[2], in[1] - I * in[2], in[0]};
+  conjugate_by(2, V, r);
+  out[0] = creal(r[3]);
+  out[1] = creal(r[1]);
+  out[2] = cimag(r[1]);
+}
+
+/* d(out)/dg of tls_map, from dV/dg: d(V r V^+) = dV r V^+ + V r dV^+. */
+static void tls_map_dg(double w0, double dt, double g, const double in[3], double dout[3]) {
+  double hx = -g, hz = -0.5 * w0;
+  double Om = sqrt(hx * hx + hz * hz);
+  double cs = cos(Om * dt), sn_raw = sin(Om * dt);
+  double sn = (Om > 0.0) ? sn_raw / Om : dt;
+  /* dOm/dg = g / Om; d(sin(Om dt)/Om)/dOm = dt cos/Om - sin/Om^2 */
+  double dOm = (Om > 0.0) ? g / Om : 0.0;
+  double dcs = -dt * sn_raw * dOm;
+  double dsn = (Om > 0.0) ? (dt * cs / Om - sn_raw / (Om * Om)) * dOm : 0.0;
+  /* V = cs I - i sn (hx sigma_x + hz sigma_z), dhx/dg = -1 */
+  cplx V[4] = {cs - I * sn * hz, -I * sn * hx, -I * sn * hx, cs + I * sn * hz};
+  cplx dV[4] = {dcs - I * dsn * hz, -I * (dsn * hx - sn), -I * (dsn * hx - sn), dcs + I * dsn * hz};
+  cplx r[4] = {1.0 - in[0], in[1] + I * in[2], in[1] - I * in[2], in[0]};
+  cplx Vd[4], dVd[4], T1[4], A[4], B[4];
+  adjoint(2, V, Vd);
+  adjoint(2, dV, dVd);
+  matmul(2, dV, r, T1);
+  matmul(2, T1, Vd, A);
+  matmul(2, V, r, T1);
+  matmul(2, T1, dVd, B);
+  dout[0] = creal(A[3] + B[3]);
+  dout[1] = creal(A[1] + B[1]);
+  dout[2] = cimag(A[1] + B[1]);
+}
+
+int ora_adjoint(ora_sim* s, int kind, const double* weights, int64_t T, const int* box,
+                double* grad_eps, double* grad_dip, double* value) {
+  if (T <= 0) return ORA_EINVAL;
+  if (kind == 0 && !s->flux_on) return ORA_EINVAL;
+  if (kind == 1 && !weights) return ORA_EINVAL;
+  for (int m = 0; m < s->nem; ++m)
+    if (!s->em[m].tls) return ORA_EINVAL;
+  for (int a = 0; a < 3; ++a)
+    if (box[a] < 0 || box[3 + a] > s->N[a] || box[a] >= box[3 + a]) return ORA_EINVAL;
+  const size_t nc = s->ncell, M = (size_t)s->nem;
+  /* snapshot of the evolving state, restored at the end */
+  double *E0[3], *H0[3], *pE0[3][3] = {{0}}, *pH0[3][3] = {{0}};
+  for (int c = 0; c < 3; ++c) {
+    E0[c] = (double*)malloc(nc * sizeof(double));
+    H0[c] = (double*)malloc(nc * sizeof(double));
+    memcpy(E0[c], s->E[c], nc * sizeof(double));
+    memcpy(H0[c], s->H[c], nc * sizeof(double));
+    for (int a = 0; a < 3; ++a) {
+      if (s->psiE[c][a]) {
+        pE0[c][a] = (double*)malloc(nc * sizeof(double));
+        memcpy(pE0[c][a], s->psiE[c][a], nc * sizeof(double));
+      }
+      if (s->psiH[c][a]) {
+        pH0[c][a] = (double*)malloc(nc * sizeof(double));
+        memcpy(pH0[c][a], s->psiH[c][a], nc * sizeof(double));
+      }
+    }
+  }
+  ora_emitter* em0 = (ora_emitter*)malloc((M ? M : 1) * sizeof(ora_emitter));
+  if (M) memcpy(em0, s->em, M * sizeof(ora_emitter));
+  int64_t step0 = s->step;
+  double ftot0 = s->flux_total;
+  int64_t len_probe[64], len_flux = s->flux_series.len, len_pop = s->pop_series.len,
+          len_en = s->energy_series.len;
+  for (int p = 0; p < s->nprobe; ++p) len_probe[p] = s->probe_series[p].len;
+
+  /* forward pass with the tape */
+  double* tE = (double*)malloc((size_t)(T + 1) * 3 * nc * sizeof(double));
+  double* tH = (double*)malloc((size_t)T * 3 * nc * sizeof(double));
+  double* tS = (double*)malloc((size_t)T * (M ? M : 1) * 3 * sizeof(double));
+  double* tG = (double*)malloc((size_t)T * (M ? M : 1) * 3 * sizeof(double));
+  if (!tE || !tH || !tS || !tG) { free(tE); free(tH); free(tS); free(tG); return ORA_ENOMEM; }
+  for (int c = 0; c < 3; ++c) memcpy(tE + (size_t)c * nc, s->E[c], nc * sizeof(double));
+  for (int64_t n = 0; n < T; ++n) {
+    for (size_t m = 0; m < M; ++m) {
+      double* st = tS + ((size_t)n * M + m) * 3;
+      st[0] = creal(s->em[m].rho[3]);
+      st[1] = creal(s->em[m].rho[1]);
+      st[2] = cimag(s->em[m].rho[1]);
+    }
+    step_once(s);
+    for (int c = 0; c < 3; ++c) {
+      memcpy(tE + ((size_t)(n + 1) * 3 + c) * nc, s->E[c], nc * sizeof(double));
+      memcpy(tH + ((size_t)n * 3 + c) * nc, s->H[c], nc * sizeof(double));
+    }
+    for (size_t m = 0; m < M; ++m)
+      for (int c = 0; c < 3; ++c) tG[((size_t)n * M + m) * 3 + c] = s->em[m].Et[c];
+  }
+  double J = 0.0;
+  if (kind == 0) J = s->flux_total - ftot0;
+  else
+    for (size_t m = 0; m < M; ++m) J += weights[m] * creal(s->em[m].rho[3]);
+  *value = J;
+
+  /* reverse pass */
+  double *Eb[3], *Hb[3], *ub[3], *psiEb[3][3] = {{0}}, *psiHb[3][3] = {{0}};
+  for (int c = 0; c < 3; ++c) {
+    Eb[c] = (double*)calloc(nc, sizeof(double));
+    Hb[c] = (double*)calloc(nc, sizeof(double));
+    ub[c] = (double*)calloc(nc, sizeof(double));
+    for (int a = 0; a < 3; ++a) {
+      if (s->psiE[c][a]) psiEb[c][a] = (double*)calloc(nc, sizeof(double));
+      if (s->psiH[c][a]) psiHb[c][a] = (double*)calloc(nc, sizeof(double));
+    }
+  }
+  double* geps = (double*)calloc(nc, sizeof(double));
+  double* sb = (double*)calloc((M ? M : 1) * 3, sizeof(double));
+  double* gd = (double*)calloc((M ? M : 1) * 3, sizeof(double));
+  if (kind == 1)
+    for (size_t m = 0; m < M; ++m) sb[3 * m] = weights[m];
+  const int fa = s->flux_axis, fu = (fa + 1) % 3, fv = (fa + 2) % 3;
+  const double fc = 0.5 * s->dt * s->dx * s->dx;
+  const double iv = 1.0 / (s->dx * s->dx * s->dx);
+  for (int64_t n = T - 1; n >= 0; --n) {
+    const double* En = tE + (size_t)n * 3 * nc;
+    const double* En1 = tE + (size_t)(n + 1) * 3 * nc;
+    const double* Hh = tH + (size_t)n * 3 * nc;
+    /* flux F^{n+1/2}: its E^{n+1} and H^{n+1/2} parts */
+    if (kind == 0) {
+      for (int jv = 0; jv < s->N[fv]; ++jv)
+        for (int iu = 0; iu < s->N[fu]; ++iu) {
+          int q[3], r[3];
+          q[fa] = s->flux_index; q[fu] = iu; q[fv] = jv;
+          r[fa] = s->flux_index - 1; r[fu] = iu; r[fv] = jv;
+          size_t id = IDX(s, q[0], q[1], q[2]), jd = IDX(s, r[0], r[1], r[2]);
+          double Hv = 0.5 * (Hh[(size_t)fv * nc + id] + Hh[(size_t)fv * nc + jd]);
+          double Hu = 0.5 * (Hh[(size_t)fu * nc + id] + Hh[(size_t)fu * nc + jd]);
+          double Eu = 0.5 * (En[(size_t)fu * nc + id] + En1[(size_t)fu * nc + id]);
+          double Ev = 0.5 * (En[(size_t)fv * nc + id] + En1[(size_t)fv * nc + id]);
+          Eb[fu][id] += fc * Hv;
+          Eb[fv][id] -= fc * Hu;
+          Hb[fv][id] += fc * Eu;
+          Hb[fv][jd] += fc * Eu;
+          Hb[fu][id] -= fc * Ev;
+          Hb[fu][jd] -= fc * Ev;
+        }
+    }
+    /* eps: E^{n+1} - E^n = (dt/eps)(curl H - J), so dE^{n+1}/d eps = -(E^{n+1} - E^n)/eps */
+    for (size_t q = 0; q < nc; ++q)
+      for (int c = 0; c < 3; ++c)
+        geps[q] -= Eb[c][q] * (En1[(size_t)c * nc + q] - En[(size_t)c * nc + q]) / s->eps[q];
+    /* E update (fills ub, the wall-masked adjoint of E^{n+1}) */
+    adjoint_update_E(s, Eb, Hb, psiEb, ub);
+    /* J^{n+1/2} enters as -(dt/eps) J: the adjoint of mu_dot_m^c is
+       sum_p (gamma w_p / dx^3) * (-(dt/eps_p) ub_c(p)) */
+    double* mdb = (double*)calloc((M ? M : 1) * 3, sizeof(double));
+    for (size_t m = 0; m < M; ++m) {
+      const ora_emitter* e = &s->em[m];
+      for (int c = 0; c < 3; ++c) {
+        int L0 = e->len[c][0], L1 = e->len[c][1], L2 = e->len[c][2];
+        double acc = 0.0;
+        for (int kk = 0; kk < L2; ++kk)
+          for (int jj = 0; jj < L1; ++jj)
+            for (int ii = 0; ii < L0; ++ii) {
+              size_t p = window_cell(s, e, c, ii, jj, kk);
+              acc += e->w[c][ii + L0 * (jj + L1 * kk)] * (-s->dt / s->eps[p]) * ub[c][p];
+            }
+        mdb[3 * m + c] = e->gamma * iv * acc;
+      }
+    }
+    /* H update */
+    adjoint_update_H(s, Eb, Hb, psiHb);
+    /* emitters: mu_dot = -2 w0 Im(rho01') d, rho' = step(rho, g), g = E~ . d */
+    for (size_t m = 0; m < M; ++m) {
+      ora_emitter* e = &s->em[m];
+      const double* st = tS + ((size_t)n * M + m) * 3;
+      const double* Et = tG + ((size_t)n * M + m) * 3;
+      double w0 = e->en[1] - e->en[0];
+      double g = Et[0] * e->d[0] + Et[1] * e->d[1] + Et[2] * e->d[2];
+      double sp[3];
+      tls_map(w0, s->dt, g, st, sp);
+      double a = -2.0 * w0 * sp[2];
+      double abar = 0.0;
+      for (int c = 0; c < 3; ++c) {
+        gd[3 * m + c] += a * mdb[3 * m + c];
+        abar += mdb[3 * m + c] * e->d[c];
+      }
+      double spb[3] = {sb[3 * m], sb[3 * m + 1], sb[3 * m + 2] - 2.0 * w0 * abar};
+      /* the step is affine in the state: columns from basis states */
+      double z[3] = {0, 0, 0}, f0[3], col[3][3];
+      tls_map(w0, s->dt, g, z, f0);
+      for (int q = 0; q < 3; ++q) {
+        double eq[3] = {0, 0, 0};
+        eq[q] = 1.0;
+        double fq[3];
+        tls_map(w0, s->dt, g, eq, fq);
+        for (int r = 0; r < 3; ++r) col[q][r] = fq[r] - f0[r];
+      }
+      double dsp[3];
+      tls_map_dg(w0, s->dt, g, st, dsp);
+      double gbar = spb[0] * dsp[0] + spb[1] * dsp[1] + spb[2] * dsp[2];
+      for (int q = 0; q < 3; ++q)
+        sb[3 * m + q] = col[q][0] * spb[0] + col[q][1] * spb[1] + col[q][2] * spb[2];
+      for (int c = 0; c < 3; ++c) gd[3 * m + c] += gbar * Et[c];
+      /* E~ = gamma sum w E^n: scatter gbar d back into Eb */
+      for (int c = 0; c < 3; ++c) {
+        double amp = e->gamma * gbar * e->d[c];
+        int L0 = e->len[c][0], L1 = e->len[c][1], L2 = e->len[c][2];
+        for (int kk = 0; kk < L2; ++kk)
+          for (int jj = 0; jj < L1; ++jj)
+            for (int ii = 0; ii < L0; ++ii)
+              Eb[c][window_cell(s, e, c, ii, jj, kk)] += amp * e->w[c][ii + L0 * (jj + L1 * kk)];
+      }
+    }
+    free(mdb);
+    /* flux: its E^n part */
+    if (kind == 0) {
+      for (int jv = 0; jv < s->N[fv]; ++jv)
+        for (int iu = 0; iu < s->N[fu]; ++iu) {
+          int q[3], r[3];
+          q[fa] = s->flux_index; q[fu] = iu; q[fv] = jv;
+          r[fa] = s->flux_index - 1; r[fu] = iu; r[fv] = jv;
+          size_t id = IDX(s, q[0], q[1], q[2]), jd = IDX(s, r[0], r[1], r[2]);
+          double Hv = 0.5 * (Hh[(size_t)fv * nc + id] + Hh[(size_t)fv * nc + jd]);
+          double Hu = 0.5 * (Hh[(size_t)fu * nc + id] + Hh[(size_t)fu * nc + jd]);
+          Eb[fu][id] += fc * Hv;
+          Eb[fv][id] -= fc * Hu;
+        }
+    }
+  }
+  /* outputs */
+  size_t b = 0;
+  for (int k = box[2]; k < box[5]; ++k)
+    for (int j = box[1]; j < box[4]; ++j)
+      for (int i = box[0]; i < box[3]; ++i) grad_eps[b++] = geps[IDX(s, i, j, k)];
+  for (size_t m = 0; m < 3 * M; ++m) grad_dip[m] = gd[m];
+
+  /* restore */
+  for (int c = 0; c < 3; ++c) {
+    memcpy(s->E[c], E0[c], nc * sizeof(double));
+    memcpy(s->H[c], H0[c], nc * sizeof(double));
+    free(E0[c]); free(H0[c]); free(Eb[c]); free(Hb[c]); free(ub[c]);
+    for (int a = 0; a < 3; ++a) {
+      if (pE0[c][a]) { memcpy(s->psiE[c][a], pE0[c][a], nc * sizeof(double)); free(pE0[c][a]); }
+      if (pH0[c][a]) { memcpy(s->psiH[c][a], pH0[c][a], nc * sizeof(double)); free(pH0[c][a]); }
+      free(psiEb[c][a]); free(psiHb[c][a]);
+    }
+  }
+  for (size_t m = 0; m < M; ++m) {
+    /* keep the window arrays (same pointers), restore state */
+    memcpy(s->em[m].rho, em0[m].rho, sizeof(em0[m].rho));
+    memcpy(s->em[m].Et, em0[m].Et, sizeof(em0[m].Et));
+    memcpy(s->em[m].mudot, em0[m].mudot, sizeof(em0[m].mudot));
+  }
+  free(em0);
+  s->step = step0;
+  s->flux_total = ftot0;
+  s->flux_series.len = len_flux;
+  s->pop_series.len = len_pop;
+  s->energy_series.len = len_en;
+  for (int p = 0; p < s->nprobe; ++p) s->probe_series[p].len = len_probe[p];
+  free(tE); free(tH); free(tS); free(tG); free(geps); free(sb); free(gd);
+  return ORA_OK;
+}
+
+/* ---- the linear Yee/CPML step alone, on a packed state, and its transpose
+ * (for the dot-product test).  Packed state: E (3 nc), H (3 nc), then every
+ * allocated psiE[c][a], then every allocated psiH[c][a], in (c, a) order. */
+int64_t ora_state_len(const ora_sim* s) {
+  int64_t n = 6 * (int64_t)s->ncell;
+  for (int c = 0; c < 3; ++c)
+    for (int a = 0; a < 3; ++a) n += (s->psiE[c][a] ? (int64_t)s->ncell : 0) +
+                                     (s->psiH[c][a] ? (int64_t)s->ncell : 0);
+  return n;
+}
+
+static void pack_state(const ora_sim* s, double* const E[3], double* const H[3],
+                       double* const pE[3][3], double* const pH[3][3], double* out, int in) {
+  size_t nc = s->ncell, o = 0;
+  double* arrs[24];
+  int na = 0;
+  for (int c = 0; c < 3; ++c) arrs[na++] = E[c];
+  for (int c = 0; c < 3; ++c) arrs[na++] = H[c];
+  for (int c = 0; c < 3; ++c)
+    for (int a = 0; a < 3; ++a)
+      if (s->psiE[c][a]) arrs[na++] = pE[c][a];
+  for (int c = 0; c < 3; ++c)
+    for (int a = 0; a < 3; ++a)
+      if (s->psiH[c][a]) arrs[na++] = pH[c][a];
+  for (int q = 0; q < na; ++q, o += nc) {
+    if (in) memcpy(arrs[q], out + o, nc * sizeof(double));
+    else memcpy(out + o, arrs[q], nc * sizeof(double));
+  }
+}
+
+/* x <- L x: one source-free, emitter-free step (H update, E update) */
+void ora_linear_step(ora_sim* s, double* x) {
+  pack_state(s, s->E, s->H, s->psiE, s->psiH, x, 1);
+  update_H(s);
+  for (int c = 0; c < 3; ++c) memset(s->J[c], 0, s->ncell * sizeof(double));
+  update_E(s);
+  pack_state(s, s->E, s->H, s->psiE, s->psiH, x, 0);
+}
+
+/* y <- L^T y */
+void ora_linear_step_adjoint(ora_sim* s, double* y) {
+  size_t nc = s->ncell;
+  double *Eb[3], *Hb[3], *ub[3], *pE[3][3] = {{0}}, *pH[3][3] = {{0}};
+  for (int c = 0; c < 3; ++c) {
+    Eb[c] = (double*)malloc(nc * sizeof(double));
+    Hb[c] = (double*)malloc(nc * sizeof(double));
+    ub[c] = (double*)malloc(nc * sizeof(double));
+    for (int a = 0; a < 3; ++a) {
+      if (s->psiE[c][a]) pE[c][a] = (double*)malloc(nc * sizeof(double));
+      if (s->psiH[c][a]) pH[c][a] = (double*)malloc(nc * sizeof(double));
+    }
+  }
+  pack_state(s, Eb, Hb, pE, pH, y, 1);
+  adjoint_update_E(s, Eb, Hb, pE, ub);
+  adjoint_update_H(s, Eb, Hb, pH);
+  pack_state(s, Eb, Hb, pE, pH, y, 0);
+  for (int c = 0; c < 3; ++c) {
+    free(Eb[c]); free(Hb[c]); free(ub[c]);
+    for (int a = 0; a < 3; ++a) { free(pE[c][a]); free(pH[c][a]); }
+  }
+}
+
+int ora_set_tls_dipole(ora_sim* s, int m, const double* d) {
+  if (m < 0 || m >= s->nem) return ORA_EINVAL;
+  memcpy(s->em[m].d, d, 3 * sizeof(double));
+  return ORA_OK;
+}

@@ -84,6 +84,13 @@ def lib():
     L.ora_gather.argtypes = [C.c_void_p, _dp]
     L.ora_scatter.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
     L.ora_dipole_rate_trace.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
+    L.ora_adjoint.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int64, _ip, _dp, _dp,
+                              C.POINTER(C.c_double)]
+    L.ora_state_len.restype = C.c_int64
+    L.ora_state_len.argtypes = [C.c_void_p]
+    L.ora_linear_step.argtypes = [C.c_void_p, _dp]
+    L.ora_linear_step_adjoint.argtypes = [C.c_void_p, _dp]
+    L.ora_set_tls_dipole.argtypes = [C.c_void_p, C.c_int, _dp]
     L.ora_threads.restype = C.c_int
     L.ora_set_threads.argtypes = [C.c_int]
     _lib = L
@@ -274,6 +281,48 @@ class Oracle:
 
     def flux_total(self):
         return lib().ora_flux_total(self._h)
+
+    # ------------------------------------------------------------ adjoint
+    def adjoint(self, objective, nsteps, box, weights=None):
+        """Discrete adjoint over the next nsteps steps (two-level emitters only).
+        objective: "flux" (dt sum F over the steps) or "population" (sum_m w_m rho11_m at
+        the end).  box: ((x0, y0, z0), (x1, y1, z1)) half-open.  Returns (value,
+        grad_eps (z, y, x) over the box, grad_dipole (M, 3)); the state is unchanged."""
+        (x0, y0, z0), (x1, y1, z1) = box
+        b = np.array([x0, y0, z0, x1, y1, z1], dtype=np.int32)
+        ge = np.zeros((z1 - z0) * (y1 - y0) * (x1 - x0))
+        M = len(self.nlev)
+        gd = np.zeros(max(1, 3 * M))
+        val = C.c_double()
+        kind = {"flux": 0, "population": 1}[objective]
+        w = None
+        if kind == 1:
+            w = np.ascontiguousarray(np.broadcast_to(weights, (M,)), dtype=np.float64)
+        st = lib().ora_adjoint(self._h, kind, w.ctypes.data if w is not None else None,
+                               int(nsteps), b, ge, gd, C.byref(val))
+        if st != 0:
+            raise ValueError(f"oracle adjoint refused the request (status {st})")
+        return val.value, ge.reshape(z1 - z0, y1 - y0, x1 - x0), gd[:3 * M].reshape(M, 3)
+
+    def state_len(self):
+        return lib().ora_state_len(self._h)
+
+    def linear_step(self, x):
+        """One source- and emitter-free Yee/CPML step of a packed state (E, H, psi)."""
+        x = np.array(x, dtype=np.float64)
+        lib().ora_linear_step(self._h, x)
+        return x
+
+    def linear_step_adjoint(self, y):
+        """The transpose of linear_step."""
+        y = np.array(y, dtype=np.float64)
+        lib().ora_linear_step_adjoint(self._h, y)
+        return y
+
+    def set_tls_dipole(self, m, d):
+        d = np.ascontiguousarray(d, dtype=np.float64)
+        if lib().ora_set_tls_dipole(self._h, int(m), d) != 0:
+            raise ValueError("bad emitter index")
 
     def populations(self):
         """(nrec, sum_m (nlev_m - 1)) array of Re rho_kk, k >= 1, per recorded step."""
