@@ -224,6 +224,38 @@ mlk_status mlk_get_phase_time(mlk_sim* s, int32_t phase, double* total_ms, int64
  * layer; the cells outside it are updated by the CPML-shell passes. */
 mlk_status mlk_get_interior_box(mlk_sim* s, int32_t box[6]);
 
+/* ------------------------------------------------------------------ adjoint
+ * Gradients of an objective over the next nsteps steps, by the discrete adjoint
+ * (reverse mode) of the coupled step as executed, with respect to eps_r of every
+ * cell of design_box {x0, y0, z0, x1, y1, z1} (half-open) and to the dipole
+ * vector d of every two-level emitter.  Objectives:
+ *   MLK_OBJ_FLUX:       dt sum_n F^{n+1/2}, the flux through the sim's flux plane
+ *                       integrated over the steps;
+ *   MLK_OBJ_POPULATION: sum_m weights[m] rho11_m after the last step (weights per
+ *                       emitter id).
+ * The forward run keeps the whole state every ckpt_every steps in device
+ * memory; the reverse pass recomputes one segment at a time from its
+ * checkpoint and undoes it, so memory is one state per segment plus one
+ * segment of tape.  The result does not depend on ckpt_every.  Outputs (host
+ * memory, written): grad_eps (design-box cells, x fastest; may be NULL),
+ * grad_dipole (3 per emitter id; may be NULL), value (the objective).  The sim
+ * is left in the state it had before the call.  Multilevel emitters: the call
+ * returns MLK_EUNSUPPORTED. */
+enum { MLK_OBJ_FLUX = 0, MLK_OBJ_POPULATION = 1 };
+typedef struct mlk_objective {
+  int32_t kind;
+  const double* weights; /* population weights, one per emitter id (host) */
+} mlk_objective;
+mlk_status mlk_adjoint(mlk_sim* s, const mlk_objective* obj, int64_t nsteps, int32_t ckpt_every,
+                       const int32_t design_box[6], double* grad_eps, double* grad_dipole,
+                       double* value);
+
+/* eps_r over a box (values in box order, x fastest; >= 1), and the dipole
+ * vectors of the two-level emitters first..first+count-1: parameters that a
+ * design loop changes between runs. */
+mlk_status mlk_set_eps_box(mlk_sim* s, const int32_t box[6], const double* eps, int32_t mem_kind);
+mlk_status mlk_set_tls_dipoles(mlk_sim* s, int32_t first, int32_t count, const double* dipole);
+
 /* ------------------------------------------------------------------ batches
  * Many independent sims stepped together (each one an independent run of the
  * method; the batch result equals its members run one by one, bit for bit).

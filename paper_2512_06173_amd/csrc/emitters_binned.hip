@@ -118,7 +118,8 @@ __device__ __forceinline__ void load_lane_win(const WinRec<T>& r, int i, LaneWin
 }  // namespace
 
 // gather; see the file comment.  Writes E~ = gamma * sum w E (FP64) per emitter.
-template <typename T>
+// WEPS: gather eps_r^-1 E instead of E (the adjoint step needs it).
+template <typename T, bool WEPS = false>
 __device__ __forceinline__ void gather_body(const FieldPtrs<T>& f, const Geom& g,
                                             const BinPtrs& bins, const WindowPtrs<T>& win,
                                             double* Et, int bid) {
@@ -151,6 +152,12 @@ __device__ __forceinline__ void gather_body(const FieldPtrs<T>& f, const Geom& g
       v0 = f.E[0][id];
       v1 = f.E[1][id];
       v2 = f.E[2][id];
+      if (WEPS) {
+        const T ei = f.epsinv[id];
+        v0 *= ei;
+        v1 *= ei;
+        v2 *= ei;
+      }
     }
     sE[0][t] = v0;
     sE[1][t] = v1;
@@ -283,10 +290,13 @@ struct Acc<double> {
 // summed over the bin's emitters): 2^-62 for FP64 fields, far below FP64
 // rounding; 2^-30 for FP32 fields, at the level of FP32 rounding of a cell's
 // sum.  A contribution is formed in the field precision.
-template <typename T>
+// E_c(p) -= [eps_r^-1(p) if EPS] amp0 gamma a^c w^c_p over the windows, with
+// a = mudot (the forward current: amp0 = dt / dx^3, EPS) or any other per-emitter
+// amplitude (the adjoint step: amp0 = -1, no EPS).
+template <typename T, bool EPS = true>
 __device__ __forceinline__ void scatter_body(const FieldPtrs<T>& f, const Geom& g,
                                              const BinPtrs& bins, const WindowPtrs<T>& win,
-                                             const double* mudot, int bid) {
+                                             const double* mudot, double amp0, int bid) {
   using A = Acc<T>;
   constexpr int BX = BinCfg<T>::SX, BY = BinCfg<T>::SY, BZ = BinCfg<T>::SZ;
   constexpr int CELLS = BX * BY * BZ;
@@ -299,7 +309,6 @@ __device__ __forceinline__ void scatter_body(const FieldPtrs<T>& f, const Geom& 
   const int x0 = bx * BX, y0 = by * BY, z0 = bz * BZ;
   const int ex = min(BX, g.n[0] - x0), ey = min(BY, g.n[1] - y0), ez = min(BZ, g.n[2] - z0);
   const int q0 = bins.sbin_start[bid], q1 = bins.sbin_start[bid + 1];
-  const double amp0 = g.dt * g.inv_dx * g.inv_dx * g.inv_dx;
   for (int t = tid; t < CELLS; t += kThreads) {
     sJ[0][t] = 0;
     sJ[1][t] = 0;
@@ -363,7 +372,7 @@ __device__ __forceinline__ void scatter_body(const FieldPtrs<T>& f, const Geom& 
                         j2 = (typename A::S)sJ[2][t];
     if (j0 == 0 && j1 == 0 && j2 == 0) continue;
     const size_t id = cell_index(g, x0 + li, y0 + lj, z0 + lk);
-    const T ei = f.epsinv[id];
+    const T ei = EPS ? f.epsinv[id] : T(1);
     if (j0 != 0) f.E[0][id] -= ei * (T)((double)j0 * inv_scale);
     if (j1 != 0) f.E[1][id] -= ei * (T)((double)j1 * inv_scale);
     if (j2 != 0) f.E[2][id] -= ei * (T)((double)j2 * inv_scale);
@@ -374,7 +383,7 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_scatter_bins(FieldPtrs<T> f, Geom g, BinPtrs bins,
                                                            WindowPtrs<T> win,
                                                            const double* mudot) {
-  scatter_body(f, g, bins, win, mudot, blockIdx.x);
+  scatter_body(f, g, bins, win, mudot, g.dt * g.inv_dx * g.inv_dx * g.inv_dx, blockIdx.x);
 }
 
 template <typename T>
@@ -384,7 +393,8 @@ __global__ __launch_bounds__(kThreads) void k_scatter_batch(const ScatterJob<T>*
   const ScatterJob<T>& J = jobs[j];
   const int bid = blockIdx.x - start[j];
   if (bid >= J.nblocks) return;
-  scatter_body(J.f, J.g, J.bins, J.win, J.mudot, bid);
+  scatter_body(J.f, J.g, J.bins, J.win, J.mudot, J.g.dt * J.g.inv_dx * J.g.inv_dx * J.g.inv_dx,
+               bid);
 }
 
 template <typename T>
@@ -466,6 +476,53 @@ hipError_t tls_batch(const TlsJob* jobs, const int* start, int njobs, int nblock
   if (nblocks <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_tls_batch, dim3(nblocks), dim3(256), 0, st, jobs, start, njobs);
   return hipGetLastError();
+}
+
+// ---- adjoint-step variants
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gather_epsw(FieldPtrs<T> f, Geom g, BinPtrs bins,
+                                                          WindowPtrs<T> win, double* out) {
+  gather_body<T, true>(f, g, bins, win, out, blockIdx.x);
+}
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_scatter_plain(FieldPtrs<T> f, Geom g, BinPtrs bins,
+                                                            WindowPtrs<T> win, const double* amp,
+                                                            double amp0) {
+  scatter_body<T, false>(f, g, bins, win, amp, amp0, blockIdx.x);
+}
+template <typename T>
+static hipError_t launch_gather_epsw(const FieldPtrs<T>& f, const Geom& g, const BinPtrs& b,
+                                     const WindowPtrs<T>& win, double* out, hipStream_t st) {
+  if (b.ngather <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_epsw<T>, dim3(b.ngather), dim3(kThreads), 0, st, f, g, b, win, out);
+  return hipGetLastError();
+}
+template <typename T>
+static hipError_t launch_scatter_plain(const FieldPtrs<T>& f, const Geom& g, const BinPtrs& b,
+                                       const WindowPtrs<T>& win, const double* amp, double amp0,
+                                       hipStream_t st) {
+  if (b.nscatter <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_plain<T>, dim3(b.nscatter), dim3(kThreads), 0, st, f, g, b, win,
+                     amp, amp0);
+  return hipGetLastError();
+}
+hipError_t gather_epsw_f64(const FieldPtrs<double>& f, const Geom& g, const BinPtrs& b,
+                           const WindowPtrs<double>& win, double* out, hipStream_t st) {
+  return launch_gather_epsw<double>(f, g, b, win, out, st);
+}
+hipError_t gather_epsw_f32(const FieldPtrs<float>& f, const Geom& g, const BinPtrs& b,
+                           const WindowPtrs<float>& win, double* out, hipStream_t st) {
+  return launch_gather_epsw<float>(f, g, b, win, out, st);
+}
+hipError_t scatter_plain_f64(const FieldPtrs<double>& f, const Geom& g, const BinPtrs& b,
+                             const WindowPtrs<double>& win, const double* amp, double amp0,
+                             hipStream_t st) {
+  return launch_scatter_plain<double>(f, g, b, win, amp, amp0, st);
+}
+hipError_t scatter_plain_f32(const FieldPtrs<float>& f, const Geom& g, const BinPtrs& b,
+                             const WindowPtrs<float>& win, const double* amp, double amp0,
+                             hipStream_t st) {
+  return launch_scatter_plain<float>(f, g, b, win, amp, amp0, st);
 }
 
 }  // namespace mlk

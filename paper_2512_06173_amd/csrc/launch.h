@@ -106,4 +106,37 @@ hipError_t detect_batch_f64(const FluxJob<double>* jobs, const int* start, int n
 hipError_t detect_batch_f32(const FluxJob<float>* jobs, const int* start, int njobs, int nblocks,
                             int kind, hipStream_t st);
 
+// ---- adjoint
+hipError_t gather_epsw_f64(const FieldPtrs<double>& f, const Geom& g, const BinPtrs& b,
+                           const WindowPtrs<double>& win, double* out, hipStream_t st);
+hipError_t gather_epsw_f32(const FieldPtrs<float>& f, const Geom& g, const BinPtrs& b,
+                           const WindowPtrs<float>& win, double* out, hipStream_t st);
+hipError_t scatter_plain_f64(const FieldPtrs<double>& f, const Geom& g, const BinPtrs& b,
+                             const WindowPtrs<double>& win, const double* amp, double amp0,
+                             hipStream_t st);
+hipError_t scatter_plain_f32(const FieldPtrs<float>& f, const Geom& g, const BinPtrs& b,
+                             const WindowPtrs<float>& win, const double* amp, double amp0,
+                             hipStream_t st);
+hipError_t adj_sweep_f64(const AdjSweep<double>& a, const Geom& g, hipStream_t st);
+hipError_t adj_sweep_f32(const AdjSweep<float>& a, const Geom& g, hipStream_t st);
+hipError_t adj_flux_f64(const AdjSweep<double>& a, const Geom& g, int axis, int index,
+                        const double* tape, int part, hipStream_t st);
+hipError_t adj_flux_f32(const AdjSweep<float>& a, const Geom& g, int axis, int index,
+                        const double* tape, int part, hipStream_t st);
+hipError_t adj_eps_f64(const AdjSweep<double>& a, const Geom& g, const Box& box, const double* e_n,
+                       const double* e_n1, double* geps, hipStream_t st);
+hipError_t adj_eps_f32(const AdjSweep<float>& a, const Geom& g, const Box& box, const float* e_n,
+                       const float* e_n1, double* geps, hipStream_t st);
+hipError_t adj_tls(const TlsPtrs& tls, double dt, double mub_scale, const double* tape_s,
+                   const double* tape_et, const double* mub, double* sb, double* gd, double* etb,
+                   hipStream_t st);
+hipError_t pack_tape_f64(const FieldPtrs<double>& f, const Geom& g, const Box& box,
+                         double* box_out, const FluxPlane* fp, double* flux_out, hipStream_t st);
+hipError_t pack_tape_f32(const FieldPtrs<float>& f, const Geom& g, const Box& box, float* box_out,
+                         const FluxPlane* fp, double* flux_out, hipStream_t st);
+hipError_t eps_box_f64(const double* eps, const Geom& g, const Box& box, double* epsinv,
+                       hipStream_t st);
+hipError_t eps_box_f32(const double* eps, const Geom& g, const Box& box, float* epsinv,
+                       hipStream_t st);
+
 }  // namespace mlk

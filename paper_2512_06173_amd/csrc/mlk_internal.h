@@ -330,4 +330,15 @@ struct FluxJob {
   int nblocks;
 };
 
+// Adjoint fields of one sweep: adjoints of E and H, the forward's 1/eps and
+// CPML tables, and the adjoint of psi double-buffered (read psi[0], write psi[1]).
+template <typename T>
+struct AdjSweep {
+  T* E[3];
+  T* H[3];
+  const T* epsinv;
+  const T* tab;
+  T* psi[2];
+};
+
 }  // namespace mlk

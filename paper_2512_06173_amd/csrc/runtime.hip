@@ -215,6 +215,16 @@ WindowPtrs<T> window_ptrs(const mlk_sim* s) {
   return w;
 }
 
+TlsPtrs tls_ptrs(const mlk_sim* s) {
+  TlsPtrs tls{};
+  tls.count = (int)s->tls_gid.size();
+  tls.gid = s->d_tls_gid;
+  tls.omega0 = s->d_tls_w0;
+  tls.dip = s->d_tls_dip;
+  tls.rho = s->d_tls_rho;
+  return tls;
+}
+
 Series series_of(const mlk_sim* s) {
   Series ser{};
   ser.probe = s->d_probe;
@@ -635,12 +645,7 @@ template <typename T>
 mlk_status enqueue_steps(mlk_sim* s, int64_t nsteps) {
   const WindowPtrs<T> win = window_ptrs<T>(s);
   const Series ser = series_of(s);
-  TlsPtrs tls{};
-  tls.count = (int)s->tls_gid.size();
-  tls.gid = s->d_tls_gid;
-  tls.omega0 = s->d_tls_w0;
-  tls.dip = s->d_tls_dip;
-  tls.rho = s->d_tls_rho;
+  const TlsPtrs tls = tls_ptrs(s);
   constexpr bool f32 = sizeof(T) == 4;
   const bool binned = s->desc.scatter == MLK_SCATTER_OWNER && s->nem > 0;
   const BinPtrs bins = bin_ptrs(s);
@@ -1372,6 +1377,277 @@ mlk_status mlk_checkpoint_load(mlk_sim* s, const void* src, int32_t mem_kind) {
 
 }  // extern "C"
 
+// ====================================================================== adjoint
+//
+// Checkpointed reverse pass: the forward run saves the whole state every K
+// steps in device memory; then, segment by segment from the last, the state is
+// restored, the K steps are run again while a tape records what the reverse
+// steps need (E on the design box, the flux planes, every emitter's state
+// before the step and its E~), and the adjoint steps undo them in reverse.
+// Memory: one state per segment plus one segment of tape.  The sim is left as
+// it was before the call.
+
+namespace {
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  ~DevBuf() { dfree(p); }
+  hipError_t alloc(size_t n) {
+    dfree(p);
+    if (n == 0) return hipSuccess;
+    return dalloc(&p, n * sizeof(T));
+  }
+};
+
+template <typename T>
+mlk_status adjoint_run(mlk_sim* s, int kind, const double* weights, int64_t T_steps, int K,
+                       const Box& box, double* grad_eps, double* grad_dip, double* value) {
+  constexpr bool f32 = sizeof(T) == 4;
+  hipStream_t st = s->stream;
+  const int M = s->nem, nt = (int)s->tls_gid.size();
+  const size_t nc = s->ncell;
+  const size_t nb = (size_t)(box.hi[0] - box.lo[0]) * (box.hi[1] - box.lo[1]) * (box.hi[2] - box.lo[2]);
+  const int np = s->fp.on ? s->g.n[(s->fp.axis + 1) % 3] * s->g.n[(s->fp.axis + 2) % 3] : 0;
+  const int nseg = (int)((T_steps + K - 1) / K);
+  size_t ck = 0;
+  STCHK(mlk_checkpoint_size(s, &ck));
+  STCHK(reserve_series(s, T_steps));
+  const int64_t step0 = s->host_step;
+
+  DevBuf<char> ckpt;
+  HIPCHK(ckpt.alloc(ck * (size_t)nseg));
+  double ftot0 = 0.0;
+  if (s->fp.on) HIPCHK(hipMemcpy(&ftot0, s->fp.total, sizeof(double), hipMemcpyDeviceToHost));
+  // forward pass with the checkpoints
+  for (int seg = 0; seg < nseg; ++seg) {
+    STCHK(mlk_checkpoint_save(s, ckpt.p + ck * (size_t)seg, MLK_MEM_DEVICE));
+    const int64_t ns = std::min<int64_t>(K, T_steps - (int64_t)seg * K);
+    STCHK(enqueue_steps<T>(s, ns));
+    s->host_step += ns;
+  }
+  STCHK(sync_sim(s));
+  double J = 0.0;
+  if (kind == MLK_OBJ_FLUX) {
+    double f1 = 0.0;
+    HIPCHK(hipMemcpy(&f1, s->fp.total, sizeof(double), hipMemcpyDeviceToHost));
+    J = f1 - ftot0;
+  } else {
+    std::vector<double> rho((size_t)nt * 3);
+    if (nt) HIPCHK(hipMemcpy(rho.data(), s->d_tls_rho, rho.size() * sizeof(double),
+                             hipMemcpyDeviceToHost));
+    for (int m = 0; m < nt; ++m) J += weights[s->tls_gid[m]] * rho[3 * m];
+  }
+  *value = J;
+
+  // adjoint state
+  DevBuf<T> Eb[3], Hb[3], psib[2];
+  for (int c = 0; c < 3; ++c) {
+    HIPCHK(Eb[c].alloc(nc));
+    HIPCHK(Hb[c].alloc(nc));
+    HIPCHK(hipMemsetAsync(Eb[c].p, 0, nc * sizeof(T), st));
+    HIPCHK(hipMemsetAsync(Hb[c].p, 0, nc * sizeof(T), st));
+  }
+  const size_t npsi = psi_total(s->g);
+  for (int q = 0; q < 2; ++q) {
+    HIPCHK(psib[q].alloc(npsi));
+    if (npsi) HIPCHK(hipMemsetAsync(psib[q].p, 0, npsi * sizeof(T), st));
+  }
+  DevBuf<double> sb, gd, mub, etb, geps;
+  HIPCHK(sb.alloc((size_t)3 * nt));
+  HIPCHK(gd.alloc((size_t)3 * nt));
+  HIPCHK(mub.alloc((size_t)3 * M));
+  HIPCHK(etb.alloc((size_t)3 * M));
+  HIPCHK(geps.alloc(nb));
+  if (nt) HIPCHK(hipMemsetAsync(gd.p, 0, (size_t)3 * nt * sizeof(double), st));
+  if (M) HIPCHK(hipMemsetAsync(etb.p, 0, (size_t)3 * M * sizeof(double), st));
+  if (nb) HIPCHK(hipMemsetAsync(geps.p, 0, nb * sizeof(double), st));
+  if (nt) {
+    std::vector<double> s0((size_t)3 * nt, 0.0);
+    if (kind == MLK_OBJ_POPULATION)
+      for (int m = 0; m < nt; ++m) s0[3 * m] = weights[s->tls_gid[m]];
+    HIPCHK(hipMemcpy(sb.p, s0.data(), s0.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  // tape of one segment
+  DevBuf<T> tbox;
+  DevBuf<double> ts, tg, tf;
+  HIPCHK(tbox.alloc(nb * 3 * (size_t)(K + 1)));
+  HIPCHK(ts.alloc((size_t)3 * nt * K));
+  HIPCHK(tg.alloc((size_t)3 * M * K));
+  HIPCHK(tf.alloc((size_t)8 * np * K));
+
+  const WindowPtrs<T> win = window_ptrs<T>(s);
+  const BinPtrs bins = bin_ptrs(s);
+  const TlsPtrs tls = tls_ptrs(s);
+  AdjSweep<T> adj{};
+  for (int c = 0; c < 3; ++c) {
+    adj.E[c] = Eb[c].p;
+    adj.H[c] = Hb[c].p;
+  }
+  adj.epsinv = (const T*)s->epsinv;
+  adj.tab = (const T*)s->tab;
+  adj.psi[0] = psib[0].p;
+  adj.psi[1] = psib[1].p;
+  FieldPtrs<T> fb{};  // the adjoint of E as a field, for the gather and the scatter
+  for (int c = 0; c < 3; ++c) fb.E[c] = Eb[c].p;
+  fb.epsinv = (T*)s->epsinv;
+  const double mub_scale = -s->g.dt * s->g.inv_dx * s->g.inv_dx * s->g.inv_dx;
+  const FluxPlane* fpp = s->fp.on ? &s->fp : nullptr;
+
+  for (int seg = nseg - 1; seg >= 0; --seg) {
+    STCHK(mlk_checkpoint_load(s, ckpt.p + ck * (size_t)seg, MLK_MEM_DEVICE));
+    const int64_t ns = std::min<int64_t>(K, T_steps - (int64_t)seg * K);
+    // recompute the segment, recording the tape
+    if (nb) {
+      if constexpr (f32) HIPCHK(pack_tape_f32(field_ptrs<T>(s), s->g, box, tbox.p, nullptr, nullptr, st));
+      else HIPCHK(pack_tape_f64(field_ptrs<T>(s), s->g, box, tbox.p, nullptr, nullptr, st));
+    }
+    for (int64_t q = 0; q < ns; ++q) {
+      if (nt) HIPCHK(hipMemcpyAsync(ts.p + (size_t)3 * nt * q, s->d_tls_rho,
+                                    (size_t)3 * nt * sizeof(double), hipMemcpyDeviceToDevice, st));
+      STCHK(enqueue_steps<T>(s, 1));
+      s->host_step += 1;
+      if (M) HIPCHK(hipMemcpyAsync(tg.p + (size_t)3 * M * q, s->d_Et, (size_t)3 * M * sizeof(double),
+                                   hipMemcpyDeviceToDevice, st));
+      T* bo = nb ? tbox.p + nb * 3 * (size_t)(q + 1) : nullptr;
+      double* fo = kind == MLK_OBJ_FLUX ? tf.p + (size_t)8 * np * q : nullptr;
+      if constexpr (f32) HIPCHK(pack_tape_f32(field_ptrs<T>(s), s->g, box, bo, fpp, fo, st));
+      else HIPCHK(pack_tape_f64(field_ptrs<T>(s), s->g, box, bo, fpp, fo, st));
+    }
+    // reverse steps
+    for (int64_t q = ns - 1; q >= 0; --q) {
+      const double* tfq = tf.p + (size_t)8 * np * q;
+      if (kind == MLK_OBJ_FLUX) {
+        if constexpr (f32) HIPCHK(adj_flux_f32(adj, s->g, s->fp.axis, s->fp.index, tfq, 0, st));
+        else HIPCHK(adj_flux_f64(adj, s->g, s->fp.axis, s->fp.index, tfq, 0, st));
+      }
+      if (nb) {
+        const T* e0 = tbox.p + nb * 3 * (size_t)q;
+        const T* e1 = tbox.p + nb * 3 * (size_t)(q + 1);
+        if constexpr (f32) HIPCHK(adj_eps_f32(adj, s->g, box, e0, e1, geps.p, st));
+        else HIPCHK(adj_eps_f64(adj, s->g, box, e0, e1, geps.p, st));
+      }
+      if (M) {
+        if constexpr (f32) HIPCHK(gather_epsw_f32(fb, s->g, bins, win, mub.p, st));
+        else HIPCHK(gather_epsw_f64(fb, s->g, bins, win, mub.p, st));
+      }
+      if constexpr (f32) HIPCHK(adj_sweep_f32(adj, s->g, st));
+      else HIPCHK(adj_sweep_f64(adj, s->g, st));
+      std::swap(adj.psi[0], adj.psi[1]);
+      if (nt) {
+        HIPCHK(adj_tls(tls, s->g.dt, mub_scale, ts.p + (size_t)3 * nt * q,
+                       tg.p + (size_t)3 * M * q, mub.p, sb.p, gd.p, etb.p, st));
+        if constexpr (f32) HIPCHK(scatter_plain_f32(fb, s->g, bins, win, etb.p, -1.0, st));
+        else HIPCHK(scatter_plain_f64(fb, s->g, bins, win, etb.p, -1.0, st));
+      }
+      if (kind == MLK_OBJ_FLUX) {
+        if constexpr (f32) HIPCHK(adj_flux_f32(adj, s->g, s->fp.axis, s->fp.index, tfq, 1, st));
+        else HIPCHK(adj_flux_f64(adj, s->g, s->fp.axis, s->fp.index, tfq, 1, st));
+      }
+    }
+  }
+  // back to the state before the call
+  STCHK(mlk_checkpoint_load(s, ckpt.p, MLK_MEM_DEVICE));
+  s->host_step = step0;
+  STCHK(sync_sim(s));
+  if (nb && grad_eps) HIPCHK(hipMemcpy(grad_eps, geps.p, nb * sizeof(double), hipMemcpyDeviceToHost));
+  if (grad_dip) {
+    std::vector<double> g((size_t)3 * nt);
+    if (nt) HIPCHK(hipMemcpy(g.data(), gd.p, g.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int e = 0; e < 3 * M; ++e) grad_dip[e] = 0.0;
+    for (int m = 0; m < nt; ++m)
+      for (int c = 0; c < 3; ++c) grad_dip[3 * s->tls_gid[m] + c] = g[3 * m + c];
+  }
+  return MLK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mlk_status mlk_adjoint(mlk_sim* s, const mlk_objective* obj, int64_t nsteps, int32_t ckpt_every,
+                       const int32_t box[6], double* grad_eps, double* grad_dipole,
+                       double* value) {
+  if (!s || !obj || !box || !value) return fail(MLK_EINVAL, "null argument");
+  if (s->in_batch) return fail(MLK_ESTATE, "the sim belongs to a batch");
+  if (nsteps <= 0 || ckpt_every <= 0) return fail(MLK_EINVAL, "steps and checkpoint interval must be positive");
+  if (!s->ml_gid.empty()) return fail(MLK_EUNSUPPORTED, "the adjoint covers two-level emitters only");
+  if (obj->kind == MLK_OBJ_FLUX) {
+    if (!s->fp.on) return fail(MLK_EINVAL, "the flux objective needs a flux plane");
+  } else if (obj->kind == MLK_OBJ_POPULATION) {
+    if (!obj->weights) return fail(MLK_EINVAL, "the population objective needs weights");
+  } else {
+    return fail(MLK_EINVAL, "unknown objective %d", obj->kind);
+  }
+  Box b{};
+  for (int a = 0; a < 3; ++a) {
+    b.lo[a] = box[a];
+    b.hi[a] = box[3 + a];
+    if (b.lo[a] < 0 || b.hi[a] > s->g.n[a] || b.lo[a] > b.hi[a])
+      return fail(MLK_EINVAL, "design box outside the grid");
+  }
+  HIPCHK(hipSetDevice(s->desc.device));
+  STCHK(sync_sim(s));
+  const int K = (int)std::min<int64_t>(ckpt_every, nsteps);
+  return s->fp32 ? adjoint_run<float>(s, obj->kind, obj->weights, nsteps, K, b, grad_eps,
+                                      grad_dipole, value)
+                 : adjoint_run<double>(s, obj->kind, obj->weights, nsteps, K, b, grad_eps,
+                                       grad_dipole, value);
+}
+
+mlk_status mlk_set_eps_box(mlk_sim* s, const int32_t box[6], const double* eps, int32_t mem_kind) {
+  if (!s || !box || !eps) return fail(MLK_EINVAL, "null argument");
+  Box b{};
+  size_t nb = 1;
+  for (int a = 0; a < 3; ++a) {
+    b.lo[a] = box[a];
+    b.hi[a] = box[3 + a];
+    if (b.lo[a] < 0 || b.hi[a] > s->g.n[a] || b.lo[a] > b.hi[a])
+      return fail(MLK_EINVAL, "box outside the grid");
+    nb *= (size_t)(b.hi[a] - b.lo[a]);
+  }
+  if (nb == 0) return MLK_OK;
+  std::vector<double> h(nb);
+  if (mem_kind == MLK_MEM_DEVICE) {
+    STCHK(sync_sim(s));
+    HIPCHK(hipMemcpy(h.data(), eps, nb * sizeof(double), hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(h.data(), eps, nb * sizeof(double));
+  }
+  for (double v : h)
+    if (!(v >= 1.0) || !std::isfinite(v)) return fail(MLK_EINVAL, "eps_r must be finite and >= 1");
+  STCHK(sync_sim(s));
+  double* d = nullptr;
+  HIPCHK(dalloc(&d, nb * sizeof(double)));
+  hipError_t e = hipMemcpy(d, h.data(), nb * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = s->fp32 ? eps_box_f32(d, s->g, b, (float*)s->epsinv, s->stream)
+                : eps_box_f64(d, s->g, b, (double*)s->epsinv, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  dfree(d);
+  HIPCHK(e);
+  return MLK_OK;
+}
+
+mlk_status mlk_set_tls_dipoles(mlk_sim* s, int32_t first, int32_t count, const double* dipole) {
+  if (!s || !dipole) return fail(MLK_EINVAL, "null argument");
+  if (first < 0 || count < 0 || first + count > s->nem)
+    return fail(MLK_EINVAL, "emitter range outside 0..%d", s->nem);
+  for (int q = 0; q < count; ++q)
+    if (s->tls_slot[first + q] < 0)
+      return fail(MLK_EINVAL, "emitter %d is not a two-level emitter", first + q);
+  STCHK(sync_sim(s));
+  for (int q = 0; q < count; ++q) {
+    const int m = s->tls_slot[first + q];
+    for (int c = 0; c < 3; ++c) s->tls_dip[3 * m + c] = dipole[3 * q + c];
+  }
+  HIPCHK(hipMemcpy(s->d_tls_dip, s->tls_dip.data(), s->tls_dip.size() * sizeof(double),
+                   hipMemcpyHostToDevice));
+  return MLK_OK;
+}
+
+}  // extern "C"
+
 // ====================================================================== batches
 //
 // A batch steps many independent sims together: every phase of the step is one
@@ -1420,16 +1696,6 @@ mlk_status make_table(DevTable<J>& t, const std::vector<J>& all) {
   t.njobs = (int)jobs.size();
   t.nblocks = (int)acc;
   return MLK_OK;
-}
-
-TlsPtrs tls_ptrs(const mlk_sim* s) {
-  TlsPtrs tls{};
-  tls.count = (int)s->tls_gid.size();
-  tls.gid = s->d_tls_gid;
-  tls.omega0 = s->d_tls_w0;
-  tls.dip = s->d_tls_dip;
-  tls.rho = s->d_tls_rho;
-  return tls;
 }
 
 template <typename T>

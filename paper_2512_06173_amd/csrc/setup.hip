@@ -107,4 +107,33 @@ hipError_t convert_out(bool fp32, const void* src, double* dst, size_t n, hipStr
   return hipGetLastError();
 }
 
+// 1/eps_r over a box from its eps_r values (box order, x fastest).
+template <typename T>
+__global__ void k_eps_box(const double* eps, Geom g, Box box, T* epsinv) {
+  const int bx = box.hi[0] - box.lo[0], by = box.hi[1] - box.lo[1], bz = box.hi[2] - box.lo[2];
+  const size_t nb = (size_t)bx * by * bz;
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nb) return;
+  const int i = box.lo[0] + (int)(t % bx), j = box.lo[1] + (int)((t / bx) % by),
+            k = box.lo[2] + (int)(t / ((size_t)bx * by));
+  epsinv[cell_index(g, i, j, k)] = (T)(1.0 / eps[t]);
+}
+template <typename T>
+static hipError_t launch_eps_box(const double* eps, const Geom& g, const Box& box, T* epsinv,
+                                 hipStream_t st) {
+  const size_t nb = (size_t)(box.hi[0] - box.lo[0]) * (box.hi[1] - box.lo[1]) * (box.hi[2] - box.lo[2]);
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_eps_box<T>, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, eps, g,
+                     box, epsinv);
+  return hipGetLastError();
+}
+hipError_t eps_box_f64(const double* eps, const Geom& g, const Box& box, double* epsinv,
+                       hipStream_t st) {
+  return launch_eps_box<double>(eps, g, box, epsinv, st);
+}
+hipError_t eps_box_f32(const double* eps, const Geom& g, const Box& box, float* epsinv,
+                       hipStream_t st) {
+  return launch_eps_box<float>(eps, g, box, epsinv, st);
+}
+
 }  // namespace mlk

@@ -57,6 +57,10 @@ _ip = C.POINTER(C.c_int32)
 _lp = C.POINTER(C.c_int64)
 
 
+class Objective(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("weights", C.c_void_p)]
+
+
 def lib():
     """Load libmlk.so (raises if it has not been built)."""
     global _lib
@@ -112,6 +116,10 @@ def lib():
         "mlk_batch_replay": (st, [C.c_void_p, C.c_int64]),
         "mlk_batch_sync": (st, [C.c_void_p]),
         "mlk_batch_destroy": (st, [C.c_void_p]),
+        "mlk_adjoint": (st, [sim, C.POINTER(Objective), C.c_int64, C.c_int32, _ip, C.c_void_p,
+                             C.c_void_p, C.POINTER(C.c_double)]),
+        "mlk_set_eps_box": (st, [sim, _ip, _dp, C.c_int32]),
+        "mlk_set_tls_dipoles": (st, [sim, C.c_int32, C.c_int32, _dp]),
         "mlk_autotune": (st, [sim, C.c_char_p]),
         "mlk_set_tuning": (st, [sim, C.c_int32, C.c_int32]),
         "mlk_get_tuning": (st, [sim, _ip, _ip]),
@@ -135,7 +143,8 @@ def exported_symbols():
             "mlk_checkpoint_load", "mlk_set_timing", "mlk_get_phase_time",
             "mlk_get_interior_box", "mlk_batch_create", "mlk_batch_step", "mlk_batch_capture",
             "mlk_batch_replay", "mlk_batch_sync", "mlk_batch_destroy", "mlk_autotune",
-            "mlk_set_tuning", "mlk_get_tuning"]
+            "mlk_set_tuning", "mlk_get_tuning", "mlk_adjoint", "mlk_set_eps_box",
+            "mlk_set_tls_dipoles"]
 
 
 def _check(st):
@@ -395,6 +404,40 @@ class Simulation:
         return tuple(int(v) for v in b[:3]), tuple(int(v) for v in b[3:])
 
 
+    # ------------------------------------------------------------ adjoint
+    def adjoint(self, objective, nsteps, box, weights=None, checkpoint_every=200):
+        """Value and gradients of an objective over the next nsteps steps by the
+        checkpointed discrete adjoint.  objective: "flux" (dt sum F over the steps) or
+        "population" (sum_m weights[m] rho11_m at the end).  box: ((x0, y0, z0), (x1, y1,
+        z1)) half-open design box.  Returns (value, grad_eps (z, y, x) over the box,
+        grad_dipole (M, 3)); the state of the sim is unchanged."""
+        (x0, y0, z0), (x1, y1, z1) = box
+        b, pb = _i32(np.array([x0, y0, z0, x1, y1, z1]))
+        M = len(self.nlev)
+        ge = np.zeros(max(1, (z1 - z0) * (y1 - y0) * (x1 - x0)))
+        gd = np.zeros(max(1, 3 * M))
+        kind = {"flux": 0, "population": 1}[objective]
+        w = None
+        if kind == 1:
+            w = np.ascontiguousarray(np.broadcast_to(np.asarray(weights, dtype=np.float64), (M,)))
+        obj = Objective(kind, w.ctypes.data if w is not None else None)
+        val = C.c_double()
+        _check(lib().mlk_adjoint(self._h, C.byref(obj), int(nsteps), int(checkpoint_every), pb,
+                                 ge.ctypes.data, gd.ctypes.data, C.byref(val)))
+        return (val.value, ge[:(z1 - z0) * (y1 - y0) * (x1 - x0)].reshape(z1 - z0, y1 - y0, x1 - x0),
+                gd[:3 * M].reshape(M, 3))
+
+    def set_eps_box(self, box, eps):
+        """eps_r over a half-open box ((x0, y0, z0), (x1, y1, z1)); eps shaped (z, y, x)."""
+        (x0, y0, z0), (x1, y1, z1) = box
+        b, pb = _i32(np.array([x0, y0, z0, x1, y1, z1]))
+        e, pe = _d(np.asarray(eps, dtype=np.float64).reshape(-1))
+        _check(lib().mlk_set_eps_box(self._h, pb, pe, MEM_HOST))
+
+    def set_tls_dipoles(self, first, dipoles):
+        d, pd = _d(np.asarray(dipoles, dtype=np.float64).reshape(-1, 3))
+        _check(lib().mlk_set_tls_dipoles(self._h, int(first), d.shape[0], pd))
+
     # ------------------------------------------------------------ tuning
     def autotune(self, cache_path=None):
         """Pick the fused sweep's tile shape by timing (optionally cached in JSON)."""
@@ -449,6 +492,32 @@ class Batch:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def coupled_objective(sim, eps_box, dipoles, objective, nsteps, box, weights=None,
+                      checkpoint_every=200):
+    """Differentiable objective of a run: eps_box (z, y, x) sets eps_r in the design box
+    and dipoles (M, 3) the two-level emitters' dipoles, then nsteps coupled steps run
+    from the sim's current state (which is left unchanged).  The hand-written adjoint
+    computes the gradient together with the value (the forward pass of the adjoint
+    runs the steps anyway), and backward returns it."""
+    import torch
+
+    class _Fn(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, e, d):
+            sim.set_eps_box(box, e.detach().cpu().double().numpy())
+            sim.set_tls_dipoles(0, d.detach().cpu().double().numpy())
+            val, ge, gd = sim.adjoint(objective, nsteps, box, weights, checkpoint_every)
+            ctx.save_for_backward(torch.from_numpy(ge).to(e), torch.from_numpy(gd).to(d))
+            return torch.tensor(val, dtype=e.dtype, device=e.device)
+
+        @staticmethod
+        def backward(ctx, gout):
+            ge, gd = ctx.saved_tensors
+            return gout * ge, gout * gd
+
+    return _Fn.apply(eps_box, dipoles)
 
 
 PHASES = {"emitters": 0, "sweep": 1, "shell": 2, "sources": 3, "scatter": 4, "detectors": 5}

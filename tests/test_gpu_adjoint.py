@@ -1,0 +1,117 @@
+"""The checkpointed GPU adjoint against the FP64 oracle adjoint (itself pinned to
+central differences), its independence of the checkpoint interval, the state left as it
+was, and the torch.autograd wrapper."""
+import numpy as np
+import pytest
+
+from oracle.feed import build_oracle
+from paper_2512_06173_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+BOX = ((8, 8, 8), (14, 14, 14))
+
+
+def mlk():
+    from paper_2512_06173_amd import mlk as m
+    return m
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def problem(precision="fp64", seed=7):
+    """22^3, CPML 4, a point-source pulse, 6 strongly coupled TLS in the centre, flux
+    plane at z = 15; 60 steps (the problem of the oracle's adjoint pins)."""
+    rng = np.random.default_rng(seed)
+    n, M = 22, 6
+    pos = rng.uniform(9.5, 12.5, size=(M, 3))
+    tls = W.TLSSet(pos=pos, sigma=np.full(M, 0.8), gamma=np.ones(M),
+                   omega0=rng.uniform(0.45, 0.55, M), dipole=0.6 * rng.standard_normal((M, 3)),
+                   rho0=np.tile([0.5, 0.5, 0.0], (M, 1)))
+    eps = rng.uniform(1.0, 2.0, (n, n, n))
+    return W.Workload(name="adj", shape=(n, n, n), bc=("cpml",) * 6, cpml=(4,) * 6, eps=eps,
+                      tls=tls, point_sources=[W.PointSource(1, (11, 10, 9), 1.0, 0.5, 2.0, 6.0)],
+                      flux=(2, 15), steps=60, precision=precision)
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+
+
+@pytest.mark.parametrize("sweep", ["fused", "plain"])
+@pytest.mark.parametrize("objective", ["flux", "population"])
+def test_adjoint_matches_oracle_fp64(objective, sweep):
+    w = problem()
+    weights = np.linspace(1.0, 2.0, len(w.tls))
+    ov, oge, ogd = build_oracle(w).adjoint(objective, w.steps, BOX, weights=weights)
+    sim = mlk().from_workload(w, sweep=sweep)
+    gv, gge, ggd = sim.adjoint(objective, w.steps, BOX, weights=weights, checkpoint_every=25)
+    say(f"[adjoint] {objective} {sweep}: value {abs(gv - ov) / abs(ov):.2e}, "
+        f"eps {rel(gge, oge):.2e}, dipole {rel(ggd, ogd):.2e}")
+    assert abs(gv - ov) <= 1e-12 * abs(ov)
+    assert rel(gge, oge) <= 1e-10
+    assert rel(ggd, ogd) <= 1e-10
+
+
+@pytest.mark.parametrize("objective", ["flux", "population"])
+def test_adjoint_fp32_fields(objective):
+    w = problem("fp32")
+    weights = np.linspace(1.0, 2.0, len(w.tls))
+    ov, oge, ogd = build_oracle(w).adjoint(objective, w.steps, BOX, weights=weights)
+    sim = mlk().from_workload(w)
+    gv, gge, ggd = sim.adjoint(objective, w.steps, BOX, weights=weights, checkpoint_every=25)
+    say(f"[adjoint fp32] {objective}: value {abs(gv - ov) / abs(ov):.2e}, "
+        f"eps {rel(gge, oge):.2e}, dipole {rel(ggd, ogd):.2e}")
+    assert abs(gv - ov) <= 1e-4 * abs(ov)
+    assert rel(gge, oge) <= 1e-3
+    assert rel(ggd, ogd) <= 1e-3
+
+
+def test_checkpoint_interval_does_not_change_the_result():
+    w = problem()
+    out = []
+    for k in (7, 25, 60, 200):
+        sim = mlk().from_workload(w)
+        out.append(sim.adjoint("flux", w.steps, BOX, checkpoint_every=k))
+    for v, ge, gd in out[1:]:
+        assert v == out[0][0]
+        assert np.array_equal(ge, out[0][1]) and np.array_equal(gd, out[0][2])
+
+
+def test_adjoint_leaves_the_state_unchanged():
+    w = problem()
+    a = mlk().from_workload(w)
+    b = mlk().from_workload(w)
+    a.step(9)
+    b.step(9)
+    before = a.fields()
+    a.adjoint("flux", 30, BOX, checkpoint_every=8)
+    assert all(np.array_equal(x, y) for x, y in zip(before, a.fields()))
+    a.step(5)
+    b.step(5)
+    assert all(np.array_equal(x, y) for x, y in zip(a.fields(), b.fields()))
+    assert np.array_equal(a.flux_series(), b.flux_series())
+
+
+def test_torch_autograd_wrapper():
+    import torch
+    w = problem()
+    sim = mlk().from_workload(w)
+    (x0, y0, z0), (x1, y1, z1) = BOX
+    e = torch.tensor(w.eps[z0:z1, y0:y1, x0:x1], dtype=torch.float64, requires_grad=True)
+    d = torch.tensor(w.tls.dipole, dtype=torch.float64, requires_grad=True)
+    J = mlk().coupled_objective(sim, e, d, "flux", w.steps, BOX, checkpoint_every=20)
+    J.backward()
+    v, ge, gd = mlk().from_workload(w).adjoint("flux", w.steps, BOX, checkpoint_every=20)
+    assert float(J) == v
+    assert np.array_equal(e.grad.numpy(), ge) and np.array_equal(d.grad.numpy(), gd)
+
+
+def test_adjoint_refuses_multilevel_emitters():
+    w = W.bragg(nx=16, ny=16, nz=112, n_emit=4, steps=10, pairs_per_mirror=3, precision="fp64")
+    w.flux = (2, 90)
+    sim = mlk().from_workload(w)
+    with pytest.raises(mlk().MlkError):
+        sim.adjoint("flux", 10, ((2, 2, 40), (6, 6, 44)))
