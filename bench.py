@@ -13,7 +13,8 @@ roofline of the dominant kernel (the fused interior sweep) measured with HIP
 events on the library's stream, and the CPU oracle timed on the host cores
 on a bounded sample of the same workload.
 
-    python bench.py [--steps K] [--warmup W] [--no-cpu] [--no-compare]
+    python bench.py [--steps K] [--warmup W] [--no-cpu] [--no-compare] [--no-batch]
+                    [--no-adjoint] [--adjoint-steps N]
     python bench.py --copy-calib     # plain copy kernel of known size (counter scaling)
 """
 import argparse
@@ -49,6 +50,9 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-compare", action="store_true", help="skip the plain/FP64 legs")
     p.add_argument("--cpu-steps", type=int, default=30)
+    p.add_argument("--no-batch", action="store_true", help="skip the 64-domain batch leg")
+    p.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
+    p.add_argument("--adjoint-steps", type=int, default=4000)
     p.add_argument("--copy-calib", action="store_true")
     return p.parse_args()
 
@@ -113,6 +117,82 @@ def run_gpu(w, precision, sweep, steps, warmup, timing):
     box = sim.interior_box()
     sim.close()
     return dt, phases, box
+
+
+def batch_leg(steps, spr=20):
+    """64 independent domains (edges 32..96, CPML 8, 1..256 TLS each, FP32 fields):
+    batched (one launch per phase, replayed from a captured hipGraph) against the same
+    domains stepped one after another on the same stream."""
+    import torch
+    from paper_2512_06173_amd import mlk, workloads as W
+    ws = W.batch(n_domains=64, steps=0)
+    cells = sum(w.shape[0] * w.shape[1] * w.shape[2] for w in ws)
+    nem = sum(w.n_emitters for w in ws)
+    h = mlk.current_stream_handle()
+    reps = max(1, steps // spr)
+    nsteps = reps * spr
+    sims = [mlk.from_workload(w, stream=h) for w in ws]
+    for s in sims:
+        s.autotune()
+    b = mlk.Batch(sims)
+    b.step(2)
+    b.capture(spr)
+    b.replay(1)
+    b.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.replay(reps)
+    b.sync()
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    b.close()
+    for s in sims:
+        s.close()
+    sims = [mlk.from_workload(w, stream=h) for w in ws]
+    for s in sims:
+        s.step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in sims:
+        s.step(nsteps)
+    for s in sims:
+        s.sync()
+    torch.cuda.synchronize()
+    tu = time.perf_counter() - t0
+    for s in sims:
+        s.close()
+    return {"workload": f"{len(ws)} cubic domains, edges 32..96 (8 x U{{4..12}}), CPML 8, "
+                        f"eps per 8^3 block, {nem} TLS in all; FP32 fields",
+            "cells": cells, "emitters": nem, "steps": nsteps,
+            "batched_graph": {"gcell_updates_per_s": round(cells * nsteps / tb / 1e9, 3),
+                              "ms_per_step": round(tb * 1e3 / nsteps, 4)},
+            "one_by_one": {"gcell_updates_per_s": round(cells * nsteps / tu / 1e9, 3),
+                           "ms_per_step": round(tu * 1e3 / nsteps, 4)},
+            "speedup": round(tu / tb, 2)}
+
+
+def adjoint_leg(w, steps, ms_forward, ckpt=200):
+    """Gradients of the time-integrated flux through the z = 200 plane over `steps`
+    steps with respect to eps_r in the design box [96,160)^3 and every emitter's dipole,
+    checkpoint every `ckpt` steps.  Ratio = reverse pass (segment recomputation +
+    adjoint steps + gradient accumulation) / plain forward steps of the same count."""
+    from paper_2512_06173_amd import mlk
+    sim = mlk.from_workload(w, stream=mlk.current_stream_handle())
+    db = w.design_box  # (x0, x1, y0, y1, z0, z1)
+    box = ((db[0], db[2], db[4]), (db[1], db[3], db[5]))
+    t0 = time.perf_counter()
+    sim.adjoint("flux", steps, box, checkpoint_every=ckpt)
+    wall = time.perf_counter() - t0
+    f_ms, r_ms = sim.adjoint_times()
+    sim.close()
+    plain = ms_forward * steps
+    return {"workload": f"flux through z={w.flux[1]} over {steps} steps; d/d eps_r on the "
+                        f"design box {box[0]}..{box[1]} and d/d dipole of {len(w.tls.pos)} "
+                        f"emitters; checkpoint every {ckpt} steps",
+            "forward_with_checkpoints_ms": round(f_ms, 2), "reverse_ms": round(r_ms, 2),
+            "plain_forward_ms": round(plain, 2), "wall_s": round(wall, 2),
+            "adjoint_forward_ratio": round(r_ms / plain, 3),
+            "total_forward_ratio": round((f_ms + r_ms) / plain, 3)}
 
 
 def cpu_baseline(w, steps):
@@ -214,6 +294,12 @@ def main():
                              "emitter_steps_per_s": round(emit_rate, 1),
                              "ms_per_step": round(ms_step, 4), "steps": args.steps}
         out["comparison"] = cmp
+    if not args.no_adjoint:
+        adj = adjoint_leg(w, args.adjoint_steps, ms_step)
+        out["adjoint"] = adj
+        out["adjoint_forward_ratio"] = adj["adjoint_forward_ratio"]
+    if not args.no_batch:
+        out["batch"] = batch_leg(max(20, args.steps // 5))
     out["cpu_baseline"] = None if args.no_cpu else cpu_baseline(w, args.cpu_steps)
     print(json.dumps(out), flush=True)
 

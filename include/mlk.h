@@ -250,6 +250,11 @@ mlk_status mlk_adjoint(mlk_sim* s, const mlk_objective* obj, int64_t nsteps, int
                        const int32_t design_box[6], double* grad_eps, double* grad_dipole,
                        double* value);
 
+/* Device time of the last mlk_adjoint call (HIP events on the sim's stream): the
+ * forward run with its checkpoints, and the reverse pass (segment recomputation,
+ * adjoint steps and gradient accumulation). */
+mlk_status mlk_get_adjoint_times(mlk_sim* s, double* forward_ms, double* reverse_ms);
+
 /* eps_r over a box (values in box order, x fastest; >= 1), and the dipole
  * vectors of the two-level emitters first..first+count-1: parameters that a
  * design loop changes between runs. */

@@ -90,6 +90,7 @@ struct mlk_sim {
   int ty = 4;       // y rows per workgroup of the fused sweep (4 or 8)
   hipStream_t batch_stream = nullptr;  // stream of the batch this sim belongs to
   bool in_batch = false;
+  double adj_forward_ms = 0.0, adj_reverse_ms = 0.0;  // phases of the last adjoint call
   void* epsinv = nullptr;
   void* psi = nullptr;  // every CPML psi array of the current buffer (psi_offset layout)
   void* tab = nullptr;  // CPML coefficient tables (tab_offset layout)
@@ -1417,6 +1418,15 @@ mlk_status adjoint_run(mlk_sim* s, int kind, const double* weights, int64_t T_st
 
   DevBuf<char> ckpt;
   HIPCHK(ckpt.alloc(ck * (size_t)nseg));
+  hipEvent_t ev[3];
+  for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() {
+      for (int q = 0; q < 3; ++q) (void)hipEventDestroy(e[q]);
+    }
+  } ev_guard{ev};
+  HIPCHK(hipEventRecord(ev[0], st));
   double ftot0 = 0.0;
   if (s->fp.on) HIPCHK(hipMemcpy(&ftot0, s->fp.total, sizeof(double), hipMemcpyDeviceToHost));
   // forward pass with the checkpoints
@@ -1426,6 +1436,7 @@ mlk_status adjoint_run(mlk_sim* s, int kind, const double* weights, int64_t T_st
     STCHK(enqueue_steps<T>(s, ns));
     s->host_step += ns;
   }
+  HIPCHK(hipEventRecord(ev[1], st));
   STCHK(sync_sim(s));
   double J = 0.0;
   if (kind == MLK_OBJ_FLUX) {
@@ -1546,6 +1557,13 @@ mlk_status adjoint_run(mlk_sim* s, int kind, const double* weights, int64_t T_st
       }
     }
   }
+  HIPCHK(hipEventRecord(ev[2], st));
+  HIPCHK(hipEventSynchronize(ev[2]));
+  float f_ms = 0.f, r_ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&f_ms, ev[0], ev[1]));
+  HIPCHK(hipEventElapsedTime(&r_ms, ev[1], ev[2]));
+  s->adj_forward_ms = f_ms;
+  s->adj_reverse_ms = r_ms;
   // back to the state before the call
   STCHK(mlk_checkpoint_load(s, ckpt.p, MLK_MEM_DEVICE));
   s->host_step = step0;
@@ -1593,6 +1611,13 @@ mlk_status mlk_adjoint(mlk_sim* s, const mlk_objective* obj, int64_t nsteps, int
                                       grad_dipole, value)
                  : adjoint_run<double>(s, obj->kind, obj->weights, nsteps, K, b, grad_eps,
                                        grad_dipole, value);
+}
+
+mlk_status mlk_get_adjoint_times(mlk_sim* s, double* forward_ms, double* reverse_ms) {
+  if (!s || !forward_ms || !reverse_ms) return fail(MLK_EINVAL, "null argument");
+  *forward_ms = s->adj_forward_ms;
+  *reverse_ms = s->adj_reverse_ms;
+  return MLK_OK;
 }
 
 mlk_status mlk_set_eps_box(mlk_sim* s, const int32_t box[6], const double* eps, int32_t mem_kind) {

@@ -119,6 +119,7 @@ def lib():
         "mlk_adjoint": (st, [sim, C.POINTER(Objective), C.c_int64, C.c_int32, _ip, C.c_void_p,
                              C.c_void_p, C.POINTER(C.c_double)]),
         "mlk_set_eps_box": (st, [sim, _ip, _dp, C.c_int32]),
+        "mlk_get_adjoint_times": (st, [sim, _dp, _dp]),
         "mlk_set_tls_dipoles": (st, [sim, C.c_int32, C.c_int32, _dp]),
         "mlk_autotune": (st, [sim, C.c_char_p]),
         "mlk_set_tuning": (st, [sim, C.c_int32, C.c_int32]),
@@ -144,7 +145,7 @@ def exported_symbols():
             "mlk_get_interior_box", "mlk_batch_create", "mlk_batch_step", "mlk_batch_capture",
             "mlk_batch_replay", "mlk_batch_sync", "mlk_batch_destroy", "mlk_autotune",
             "mlk_set_tuning", "mlk_get_tuning", "mlk_adjoint", "mlk_set_eps_box",
-            "mlk_set_tls_dipoles"]
+            "mlk_set_tls_dipoles", "mlk_get_adjoint_times"]
 
 
 def _check(st):
@@ -426,6 +427,12 @@ class Simulation:
                                  ge.ctypes.data, gd.ctypes.data, C.byref(val)))
         return (val.value, ge[:(z1 - z0) * (y1 - y0) * (x1 - x0)].reshape(z1 - z0, y1 - y0, x1 - x0),
                 gd[:3 * M].reshape(M, 3))
+
+    def adjoint_times(self):
+        """(forward-with-checkpoints ms, reverse ms) of the last adjoint call."""
+        f, r = C.c_double(), C.c_double()
+        _check(lib().mlk_get_adjoint_times(self._h, C.byref(f), C.byref(r)))
+        return f.value, r.value
 
     def set_eps_box(self, box, eps):
         """eps_r over a half-open box ((x0, y0, z0), (x1, y1, z1)); eps shaped (z, y, x)."""
