@@ -1,0 +1,109 @@
+"""Parity at the full sizes of the workloads, in the launch configuration the benchmark
+times (fused sweep, owner-computes scatter, autotuned tiles), for as many steps as the
+CPU oracle finishes in seconds: whole fields, flux, probes and populations against the
+oracle.  Tolerances as in the small-grid parity tests."""
+import time
+
+import numpy as np
+import pytest
+
+from oracle.feed import build_oracle
+from paper_2512_06173_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL, FP32_FIELD_TOL, FP32_POP_TOL = 1e-12, 1e-4, 1e-6
+
+
+def mlk():
+    from paper_2512_06173_amd import mlk as m
+    return m
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def rel_l2(a, b):
+    """Relative L2 distance; absolute when the reference is exactly zero."""
+    a = np.concatenate([np.ravel(x) for x in a])
+    b = np.concatenate([np.ravel(x) for x in b])
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a - b)
+
+
+def compare(sim, ora, w, fp64):
+    ft = FP64_TOL if fp64 else FP32_FIELD_TOL
+    pt = FP64_TOL if fp64 else FP32_POP_TOL
+    e = rel_l2(sim.fields(), ora.fields())
+    say(f"  fields rel L2 {e:.2e}")
+    assert e <= ft
+    for p in range(len(w.probes)):
+        ep = rel_l2([sim.probe(p)], [ora.probe(p)])
+        assert ep <= ft
+    if w.flux is not None:
+        ef = rel_l2([sim.flux_series()], [ora.flux_series()])
+        say(f"  flux rel L2 {ef:.2e}")
+        assert ef <= ft
+    if w.pop_every and w.n_emitters:
+        d = np.max(np.abs(sim.populations() - ora.populations()))
+        say(f"  populations max abs {d:.2e}")
+        assert d <= pt
+
+
+def run(w, steps, **kw):
+    t0 = time.time()
+    sim = mlk().from_workload(w, stream=mlk().current_stream_handle(), **kw)
+    sim.autotune()
+    sim.step(steps)
+    sim.sync()
+    t1 = time.time()
+    ora = build_oracle(w)
+    ora.step(steps)
+    say(f"[fullsize] {w.name} {w.precision} {steps} steps: gpu {t1 - t0:.1f} s, "
+        f"oracle {time.time() - t1:.1f} s")
+    return sim, ora
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_radiating_cube_256(precision):
+    w = W.radiating_cube(precision=precision)
+    w.pop_every = 1
+    sim, ora = run(w, 14)  # the emitters' field reaches the flux plane at z = 200
+    assert np.any(ora.flux_series() != 0.0)
+    compare(sim, ora, w, precision == "fp64")
+
+
+def test_slab_128_with_source():
+    w = W.slab()
+    w.pop_every = 10
+    sim, ora = run(w, 700)  # the pulse (peak near step 466) has crossed the slab
+    assert np.max(ora.populations()) > 1e-9
+    compare(sim, ora, w, False)
+
+
+def test_bragg_64x64x1024_multilevel():
+    w = W.bragg()
+    w.pop_every = 2
+    sim, ora = run(w, 60)
+    compare(sim, ora, w, False)
+
+
+def test_batch_64_domains():
+    ws = W.batch(steps=0)
+    for w in ws:
+        w.pop_every = 1
+    h = mlk().current_stream_handle()
+    sims = [mlk().from_workload(w, stream=h) for w in ws]
+    with mlk().Batch(sims) as b:
+        b.step(40)
+        b.sync()
+    worst = 0.0
+    for w, s in zip(ws, sims):
+        o = build_oracle(w)
+        o.step(40)
+        worst = max(worst, rel_l2(s.fields(), o.fields()))
+        d = np.max(np.abs(s.populations() - o.populations())) if w.n_emitters else 0.0
+        assert d <= FP32_POP_TOL
+    say(f"[fullsize] batch of {len(ws)} domains, 40 steps: worst fields rel L2 {worst:.2e}")
+    assert worst <= FP32_FIELD_TOL
