@@ -99,6 +99,7 @@ def run_gpu(w, precision, sweep, steps, warmup, timing):
     from paper_2512_06173_amd import mlk
     sim = mlk.from_workload(w, precision=precision, sweep=sweep, scatter="owner",
                             stream=mlk.current_stream_handle())
+    sim.autotune()  # tile shape of the fused sweep (untimed; plain sweeps have none)
     sim.step(warmup)
     sim.sync()
     sim.set_timing(timing or False)
@@ -115,8 +116,9 @@ def run_gpu(w, precision, sweep, steps, warmup, timing):
             if n:
                 phases[name] = (ms, n)
     box = sim.interior_box()
+    tuning = sim.tuning()
     sim.close()
-    return dt, phases, box
+    return dt, phases, box, tuning
 
 
 def batch_leg(steps, spr=20):
@@ -240,9 +242,9 @@ def main():
     step_bytes = cells * CELL_WORDS * esz + memb * PSI_WORDS * esz + nem * TLS_STEP_BYTES
 
     # timed region: events around the fused sweep launch only
-    dt, phases, box = run_gpu(w, "fp32", "fused", args.steps, args.warmup, ["sweep"])
+    dt, phases, box, tuning = run_gpu(w, "fp32", "fused", args.steps, args.warmup, ["sweep"])
     # per-phase breakdown from a separate, shorter run with every phase timed
-    _, breakdown, _ = run_gpu(w, "fp32", "fused", max(1, args.steps // 5), 5, True)
+    _, breakdown, _, _ = run_gpu(w, "fp32", "fused", max(1, args.steps // 5), 5, True)
     ms_step = dt * 1e3 / args.steps
     gcells = cells * args.steps / dt / 1e9
     emit_rate = nem * args.steps / dt
@@ -257,7 +259,8 @@ def main():
     traffic = traffic_from_profile(launch_cells)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": "k_fused<float>",
+                "traffic": traffic, "kernel": f"k_fused<float, {tuning[0]}>",
+                "tile": {"ty": tuning[0], "kz": tuning[1]},
                 "bytes_per_launch": launch_bytes, "avg_launch_us": round(t_launch * 1e6, 2)}
     emitter_ms = sum(breakdown[p][0] / breakdown[p][1] for p in ("emitters", "scatter")
                      if p in breakdown)
@@ -285,7 +288,7 @@ def main():
         cmp = {}
         ksteps = max(1, args.steps // 5)
         for prec, sweep in (("fp32", "plain"), ("fp64", "fused"), ("fp64", "plain")):
-            d, _, _ = run_gpu(w, prec, sweep, ksteps, max(1, args.warmup // 2), False)
+            d, _, _, _ = run_gpu(w, prec, sweep, ksteps, max(1, args.warmup // 2), False)
             cmp[f"{sweep}_{prec}"] = {"gcell_updates_per_s": round(cells * ksteps / d / 1e9, 3),
                                       "emitter_steps_per_s": round(nem * ksteps / d, 1),
                                       "ms_per_step": round(d * 1e3 / ksteps, 4),

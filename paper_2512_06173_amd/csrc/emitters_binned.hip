@@ -84,6 +84,18 @@ __device__ __forceinline__ int xcd_block(int bid, int nblocks) {
   return bid < 8 * q8 ? (bid % 8) * q8 + bid / 8 : bid;
 }
 
+// Copy the window records of emitters ids[0..cn) into LDS (16-byte pieces).
+template <typename T, int NT>
+__device__ __forceinline__ void stage_records(const WinRec<T>* rec, const int* ids, int cn,
+                                              WinRec<T>* dst, int tid) {
+  constexpr int R4 = sizeof(WinRec<T>) / sizeof(int4);
+  for (int i = tid; i < cn * R4; i += NT) {
+    const int slot = i / R4, part = i % R4;
+    const int4* src = reinterpret_cast<const int4*>(rec + ids[slot]);
+    reinterpret_cast<int4*>(dst + slot)[part] = src[part];
+  }
+}
+
 // The part of an emitter's window record that one of its eight lanes needs,
 // in registers: the union window, the lane's own x weights and every y and z
 // weight (the eight lanes read the same record, one cache line at a time).
@@ -273,7 +285,9 @@ struct Acc<float> {
   using U = unsigned int;
   using S = int;
   static constexpr int BITS = 30;
-  __device__ static S round(float v) { return __float2int_rn(v); }
+  // onto the grid by truncation (one conversion); the grid step is 2^-30 of the
+  // bin's bound, far below the FP32 rounding of a cell's sum
+  __device__ static S round(float v) { return (S)v; }
 };
 template <>
 struct Acc<double> {
@@ -302,6 +316,7 @@ __device__ __forceinline__ void scatter_body(const FieldPtrs<T>& f, const Geom& 
   constexpr int CELLS = BX * BY * BZ;
   constexpr int NW = kThreads / 64;
   __shared__ typename A::U sJ[3][CELLS];
+  __shared__ WinRec<T> sW[kGroups];
   __shared__ double sRed[NW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int b = bins.sbin_id[bid];
@@ -332,34 +347,54 @@ __device__ __forceinline__ void scatter_body(const FieldPtrs<T>& f, const Geom& 
   const double scale = ldexp(1.0, A::BITS - ebits);
   const double inv_scale = ldexp(1.0, ebits - A::BITS);
 
+  // Eight lanes per (emitter, bin) pair, lane i on window x offset i; the group
+  // walks only the window rows (y, z offsets) that fall inside the bin, given as
+  // bit masks, with the weights read from the LDS copy of the record.
   const int grp = tid / kLanesPerEmitter, i = tid % kLanesPerEmitter;
-  for (int q = q0 + grp; q < q1; q += kGroups) {
-    const int e = bins.sbin_em[q];
-    LaneWin<T> w;
-    load_lane_win(win.rec[e], i, w);
-    if (i >= w.n[0]) continue;
+  for (int c0 = q0; c0 < q1; c0 += kGroups) {
+    const int cn = min(kGroups, q1 - c0);
+    if (c0 > q0) __syncthreads();  // the previous chunk's records are no longer read
+    stage_records<T, kThreads>(win.rec, bins.sbin_em + c0, cn, sW, tid);
+    __syncthreads();
+    if (grp >= cn) continue;
+    const WinRec<T>& w = sW[grp];
+    const int e = bins.sbin_em[c0 + grp];
+    // the window rows inside the bin as bit masks, with their LDS offsets and
+    // weights in registers: the loops below touch LDS only through the atomics
+    unsigned jm = 0, km = 0;
+    int rowoff[kMaxWin], planeoff[kMaxWin];
+    T wy0[kMaxWin], wy1[kMaxWin], wz0[kMaxWin], wz1[kMaxWin];
+#pragma unroll
+    for (int d = 0; d < kMaxWin; ++d) {
+      const int lj = wrap_once(w.org[1] + d, g.n[1]) - y0;
+      const int lk = wrap_once(w.org[2] + d, g.n[2]) - z0;
+      jm |= (d < w.n[1] && lj >= 0 && lj < ey) ? 1u << d : 0u;
+      km |= (d < w.n[2] && lk >= 0 && lk < ez) ? 1u << d : 0u;
+      rowoff[d] = BX * lj;
+      planeoff[d] = BX * BY * lk;
+      wy0[d] = w.wr[1][0][d];
+      wy1[d] = w.wr[1][1][d];
+      wz0[d] = w.wr[2][0][d];
+      wz1[d] = w.wr[2][1][d];
+    }
     const int li = wrap_once(w.org[0] + i, g.n[0]) - x0;
-    if (li < 0 || li >= ex) continue;
+    if (!(i < w.n[0] && li >= 0 && li < ex)) continue;
     const double ge = amp0 * win.gamma[e] * scale;
-    const T cx = (T)(ge * mudot[3 * e]) * w.wx1, cy = (T)(ge * mudot[3 * e + 1]) * w.wx0,
-            cz = (T)(ge * mudot[3 * e + 2]) * w.wx0;
-    const int ny = w.n[1], nz = w.n[2];
+    const T cx = (T)(ge * mudot[3 * e]) * w.wr[0][1][i];
+    const T cy = (T)(ge * mudot[3 * e + 1]) * w.wr[0][0][i];
+    const T cz = (T)(ge * mudot[3 * e + 2]) * w.wr[0][0][i];
 #pragma unroll
     for (int k = 0; k < kMaxWin; ++k) {
-      const int lk = wrap_once(w.org[2] + k, g.n[2]) - z0;
-      if (k >= nz || lk < 0 || lk >= ez) continue;
-      const T cxk = cx * w.wz[0][k], cyk = cy * w.wz[0][k], czk = cz * w.wz[1][k];
+      if (!((km >> k) & 1u)) continue;
+      const T cxk = cx * wz0[k], cyk = cy * wz0[k], czk = cz * wz1[k];
+      const int pk = planeoff[k] + li;
 #pragma unroll
       for (int j = 0; j < kMaxWin; ++j) {
-        const int lj = wrap_once(w.org[1] + j, g.n[1]) - y0;
-        if (j >= ny || lj < 0 || lj >= ey) continue;
-        const int s = li + BX * (lj + BY * lk);
-        const typename A::S vx = A::round(cxk * w.wy[0][j]);
-        const typename A::S vy = A::round(cyk * w.wy[1][j]);
-        const typename A::S vz = A::round(czk * w.wy[0][j]);
-        if (vx != 0) atomicAdd(&sJ[0][s], (typename A::U)vx);
-        if (vy != 0) atomicAdd(&sJ[1][s], (typename A::U)vy);
-        if (vz != 0) atomicAdd(&sJ[2][s], (typename A::U)vz);
+        if (!((jm >> j) & 1u)) continue;
+        const int s = pk + rowoff[j];
+        atomicAdd(&sJ[0][s], (typename A::U)A::round(cxk * wy0[j]));
+        atomicAdd(&sJ[1][s], (typename A::U)A::round(cyk * wy1[j]));
+        atomicAdd(&sJ[2][s], (typename A::U)A::round(czk * wy0[j]));
       }
     }
   }

@@ -387,6 +387,39 @@ mlk_status build_bins(mlk_sim* s) {
     const int e = gem[q];
     for (int b : per_em[e]) sem[fill[slot_of[b]]++] = e;
   }
+  // within a bin, pairs by decreasing number of window rows (y, z) inside it:
+  // the workgroup runs eight pairs per wavefront side by side, so similar row
+  // counts keep its lanes busy (stable: ties stay in gather order)
+  {
+    auto overlap = [&](int e, int a, int bq) {
+      const int s0 = win_slot(e, a, 0), s1 = win_slot(e, a, 1);
+      const int u0 = std::min(lo[s0], lo[s1]);
+      const int u1 = std::max(lo[s0] + len[s0], lo[s1] + len[s1]);
+      int c = 0;
+      for (int q = u0; q < u1; ++q) {
+        int w = q % g.n[a];
+        if (w < 0) w += g.n[a];
+        c += (w / B[a]) == bq;
+      }
+      return c;
+    };
+    std::vector<std::pair<int, int>> tmp;
+    for (size_t sl = 0; sl < sid.size(); ++sl) {
+      const int b = sid[sl];
+      const int bx = b % nb[0], by = (b / nb[0]) % nb[1], bz = b / (nb[0] * nb[1]);
+      tmp.clear();
+      for (int q = sstart[sl]; q < sstart[sl + 1]; ++q) {
+        const int e = sem[q];
+        const int rows = overlap(e, 0, bx) > 0 ? overlap(e, 1, by) * overlap(e, 2, bz) : 0;
+        tmp.push_back({-rows, e});
+      }
+      std::stable_sort(tmp.begin(), tmp.end(),
+                       [](const std::pair<int, int>& x, const std::pair<int, int>& y) {
+                         return x.first < y.first;
+                       });
+      for (size_t q = 0; q < tmp.size(); ++q) sem[sstart[sl] + q] = tmp[q].second;
+    }
+  }
   s->nscatter = (int)sid.size();
   STCHK(upload(&s->d_gbin_org, gorg));
   STCHK(upload(&s->d_gbin_start, gstart));
