@@ -145,35 +145,46 @@ __device__ __forceinline__ void gather_body(const FieldPtrs<T>& f, const Geom& g
   const int y0 = bins.gbin_org[3 * bin + 1] - kHalo;
   const int z0 = bins.gbin_org[3 * bin + 2] - kHalo;
 
-  for (int t = tid; t < TX * TY * TZ; t += kThreads) {
+  // stage the tile: every load of a thread is issued before the first LDS
+  // store, so they are in flight together (unconditional loads from a safe
+  // index; cells beyond a non-periodic face read as zero)
+  constexpr int NTILE = TX * TY * TZ;
+  static_assert(NTILE % kThreads == 0, "the tile is a whole number of workgroup passes");
+  constexpr int RF = NTILE / kThreads;
+  T v[RF][3];
+#pragma unroll
+  for (int r = 0; r < RF; ++r) {
+    const int t = tid + r * kThreads;
     const int li = t % TX, lj = (t / TX) % TY, lk = t / (TX * TY);
     int q[3] = {x0 + li, y0 + lj, z0 + lk};
     bool ok = true;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      if (g.periodic[a]) {
-        const int r = q[a] % g.n[a];
-        q[a] = r < 0 ? r + g.n[a] : r;
+    for (int ax = 0; ax < 3; ++ax) {
+      if (g.periodic[ax]) {
+        const int m = q[ax] % g.n[ax];
+        q[ax] = m < 0 ? m + g.n[ax] : m;
       } else {
-        ok = ok && q[a] >= 0 && q[a] < g.n[a];
+        ok = ok && q[ax] >= 0 && q[ax] < g.n[ax];
       }
     }
-    T v0 = T(0), v1 = T(0), v2 = T(0);
-    if (ok) {
-      const size_t id = cell_index(g, q[0], q[1], q[2]);
-      v0 = f.E[0][id];
-      v1 = f.E[1][id];
-      v2 = f.E[2][id];
-      if (WEPS) {
-        const T ei = f.epsinv[id];
-        v0 *= ei;
-        v1 *= ei;
-        v2 *= ei;
-      }
+    const size_t id = ok ? cell_index(g, q[0], q[1], q[2]) : 0;
+    T e0 = f.E[0][id], e1 = f.E[1][id], e2 = f.E[2][id];
+    if (WEPS) {
+      const T ei = f.epsinv[id];
+      e0 *= ei;
+      e1 *= ei;
+      e2 *= ei;
     }
-    sE[0][t] = v0;
-    sE[1][t] = v1;
-    sE[2][t] = v2;
+    v[r][0] = ok ? e0 : T(0);
+    v[r][1] = ok ? e1 : T(0);
+    v[r][2] = ok ? e2 : T(0);
+  }
+#pragma unroll
+  for (int r = 0; r < RF; ++r) {
+    const int t = tid + r * kThreads;
+    sE[0][t] = v[r][0];
+    sE[1][t] = v[r][1];
+    sE[2][t] = v[r][2];
   }
 
   __syncthreads();
@@ -399,19 +410,30 @@ __device__ __forceinline__ void scatter_body(const FieldPtrs<T>& f, const Geom& 
     }
   }
   __syncthreads();
-  // owner write: E -= (dt/eps) J on the touched cells of this bin
-  for (int t = tid; t < CELLS; t += kThreads) {
+  // owner write: E -= [eps^-1] J on the cells of this bin; the loads of a thread's
+  // cells are issued together (unconditional, from a safe index), then the stores
+  static_assert(CELLS % kThreads == 0, "the bin is a whole number of workgroup passes");
+  constexpr int RW = CELLS / kThreads;
+  typename A::S jv[RW][3];
+  size_t idw[RW];
+  T ev[RW][3], eiv[RW];
+#pragma unroll
+  for (int r = 0; r < RW; ++r) {
+    const int t = tid + r * kThreads;
     const int li = t % BX, lj = (t / BX) % BY, lk = t / (BX * BY);
-    if (li >= ex || lj >= ey || lk >= ez) continue;
-    const typename A::S j0 = (typename A::S)sJ[0][t], j1 = (typename A::S)sJ[1][t],
-                        j2 = (typename A::S)sJ[2][t];
-    if (j0 == 0 && j1 == 0 && j2 == 0) continue;
-    const size_t id = cell_index(g, x0 + li, y0 + lj, z0 + lk);
-    const T ei = EPS ? f.epsinv[id] : T(1);
-    if (j0 != 0) f.E[0][id] -= ei * (T)((double)j0 * inv_scale);
-    if (j1 != 0) f.E[1][id] -= ei * (T)((double)j1 * inv_scale);
-    if (j2 != 0) f.E[2][id] -= ei * (T)((double)j2 * inv_scale);
+    const bool in = li < ex && lj < ey && lk < ez;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) jv[r][c] = in ? (typename A::S)sJ[c][t] : 0;
+    idw[r] = in ? cell_index(g, x0 + li, y0 + lj, z0 + lk) : 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ev[r][c] = f.E[c][idw[r]];
+    eiv[r] = EPS ? f.epsinv[idw[r]] : T(1);
   }
+#pragma unroll
+  for (int r = 0; r < RW; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if (jv[r][c] != 0) f.E[c][idw[r]] = ev[r][c] - eiv[r] * (T)((double)jv[r][c] * inv_scale);
 }
 
 template <typename T>
