@@ -256,8 +256,19 @@ struct ShellMap {
   int full_cells;        // cells in the whole rows of one middle plane
   int strip;             // cells in the two x strips of one row
   int per_plane;         // shell cells of one middle plane
-  long long total;
+  long long total;       // below 2^31 (checked at launch)
+  // reciprocals for the index arithmetic (exact after one correction step)
+  double inv_plane, inv_per_plane, inv_nx, inv_strip;
 };
+
+// n / d for n < 2^31 from a rounded reciprocal of d: the quotient estimate is off
+// by at most one, which the remainder test corrects.
+__device__ __forceinline__ unsigned div_by(unsigned n, unsigned d, double inv) {
+  unsigned q = (unsigned)((double)n * inv);
+  const int r = (int)(n - q * d);
+  q = q + (r >= (int)d ? 1u : 0u) - (r < 0 ? 1u : 0u);
+  return q;
+}
 
 template <typename T>
 struct ShellJob {

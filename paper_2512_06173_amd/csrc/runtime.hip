@@ -1854,6 +1854,7 @@ mlk_status build_tables(mlk_batch* b, BatchTables<T> (&tab)[2]) {
       S.out = nxt;
       S.g = s->g;
       S.m = shell_map(s->g, inner);
+      if (S.m.total >= 0x7fffff00LL) return fail(MLK_EUNSUPPORTED, "domain too large for a batch");
       S.nblocks = (int)((S.m.total + 255) / 256);
       sh.push_back(S);
       if (s->src.count > 0) {

@@ -83,31 +83,31 @@ __global__ __launch_bounds__(256) void k_update_box(FieldPtrs<T> in, FieldPtrs<T
   else update_e_cell(in, out, g, i, j, k);
 }
 
-__device__ __forceinline__ void shell_cell(const Geom& g, const ShellMap& m, long long t, int& i,
+__device__ __forceinline__ void shell_cell(const Geom& g, const ShellMap& m, unsigned t, int& i,
                                            int& j, int& k) {
-  const int nx = g.n[0], ny = g.n[1];
-  if (t < m.nslab) {
-    const long long plane = (long long)nx * ny;
-    const int p = (int)(t / plane);
-    const int r = (int)(t - (long long)p * plane);
-    k = p < m.nzlo ? p : m.in.hi[2] + (p - m.nzlo);
-    j = r / nx;
-    i = r - j * nx;
+  const unsigned nx = (unsigned)g.n[0];
+  if ((long long)t < m.nslab) {
+    const unsigned plane = nx * (unsigned)g.n[1];
+    const unsigned p = div_by(t, plane, m.inv_plane);
+    const unsigned r = t - p * plane;
+    k = (int)p < m.nzlo ? (int)p : m.in.hi[2] + ((int)p - m.nzlo);
+    j = (int)div_by(r, nx, m.inv_nx);
+    i = (int)(r - (unsigned)j * nx);
     return;
   }
-  const long long u = t - m.nslab;
-  const int p = (int)(u / m.per_plane);
-  int r = (int)(u - (long long)p * m.per_plane);
-  k = m.in.lo[2] + p;
-  if (r < m.full_cells) {
-    const int row = r / nx;
-    i = r - row * nx;
+  const unsigned u = t - (unsigned)m.nslab;
+  const unsigned p = div_by(u, (unsigned)m.per_plane, m.inv_per_plane);
+  unsigned r = u - p * (unsigned)m.per_plane;
+  k = m.in.lo[2] + (int)p;
+  if ((int)r < m.full_cells) {
+    const int row = (int)div_by(r, nx, m.inv_nx);
+    i = (int)(r - (unsigned)row * nx);
     j = row < m.ylo_rows ? row : m.in.hi[1] + (row - m.ylo_rows);
     return;
   }
-  r -= m.full_cells;
-  const int row = r / m.strip;
-  const int c = r - row * m.strip;
+  r -= (unsigned)m.full_cells;
+  const int row = (int)div_by(r, (unsigned)m.strip, m.inv_strip);
+  const int c = (int)r - row * m.strip;
   j = m.in.lo[1] + row;
   i = c < m.in.lo[0] ? c : m.in.hi[0] + (c - m.in.lo[0]);
 }
@@ -115,8 +115,8 @@ __device__ __forceinline__ void shell_cell(const Geom& g, const ShellMap& m, lon
 template <typename T, bool H>
 __global__ __launch_bounds__(256) void k_update_shell(FieldPtrs<T> in, FieldPtrs<T> out, Geom g,
                                                       ShellMap m) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= m.total) return;
+  const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+  if ((long long)t >= m.total) return;
   int i, j, k;
   shell_cell(g, m, t, i, j, k);
   if (H) update_h_cell(in, out, g, i, j, k);
@@ -128,8 +128,8 @@ __global__ __launch_bounds__(256) void k_update_shell_batch(const ShellJob<T>* j
                                                             const int* start, int njobs) {
   const int jb = find_job(start, njobs, blockIdx.x);
   const ShellJob<T>& J = jobs[jb];
-  const long long t = (long long)(blockIdx.x - start[jb]) * blockDim.x + threadIdx.x;
-  if (t >= J.m.total) return;
+  const unsigned t = (blockIdx.x - start[jb]) * blockDim.x + threadIdx.x;
+  if ((long long)t >= J.m.total) return;
   int i, j, k;
   shell_cell(J.g, J.m, t, i, j, k);
   if (H) update_h_cell(J.in, J.out, J.g, i, j, k);
@@ -231,6 +231,10 @@ ShellMap shell_map(const Geom& g, const Box& inner) {
   m.strip = inner.lo[0] + (nx - inner.hi[0]);
   m.per_plane = m.full_cells + wy * m.strip;
   m.total = m.nslab + (long long)wz * m.per_plane;
+  m.inv_plane = 1.0 / ((double)nx * ny);
+  m.inv_per_plane = m.per_plane > 0 ? 1.0 / m.per_plane : 0.0;
+  m.inv_nx = 1.0 / nx;
+  m.inv_strip = m.strip > 0 ? 1.0 / m.strip : 0.0;
   return m;
 }
 
@@ -241,8 +245,8 @@ static hipError_t launch_shell(const FieldPtrs<T>& in, const FieldPtrs<T>& out, 
                                const Box& inner, bool h_pass, hipStream_t st) {
   const ShellMap m = shell_map(g, inner);
   if (m.total == 0) return hipSuccess;
+  if (m.total >= 0x7fffff00LL) return hipErrorInvalidValue;  // 32-bit cell index
   const long long blocks = (m.total + 255) / 256;
-  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
   if (h_pass)
     hipLaunchKernelGGL((k_update_shell<T, true>), dim3((unsigned)blocks), dim3(256), 0, st, in,
                        out, g, m);
