@@ -283,7 +283,7 @@ mlk_status mlk_batch_replay(mlk_batch* b, int64_t nreplays);
 mlk_status mlk_batch_sync(mlk_batch* b);
 mlk_status mlk_batch_destroy(mlk_batch* b);
 
-/* Tile shape of the fused sweep: rows per workgroup ty (4 or 8) and z planes
+/* Tile shape of the fused sweep: rows per workgroup ty (4, 8 or 16) and z planes
  * per workgroup kz.  mlk_autotune times every pair on the sim's own grid (the
  * state is left untouched) and keeps the fastest; with cache_path (NULL: no
  * cache) results are read from and added to a JSON file keyed by precision,

@@ -87,7 +87,7 @@ struct mlk_sim {
   void* H2[3] = {};
   void* psi2 = nullptr;
   int kz = 0;       // z planes per workgroup of the fused sweep
-  int ty = 4;       // y rows per workgroup of the fused sweep (4 or 8)
+  int ty = 4;       // y rows per workgroup of the fused sweep (4, 8 or 16)
   hipStream_t batch_stream = nullptr;  // stream of the batch this sim belongs to
   bool in_batch = false;
   double adj_forward_ms = 0.0, adj_reverse_ms = 0.0;  // phases of the last adjoint call
@@ -1760,7 +1760,7 @@ template <typename T>
 struct BatchTables {
   DevTable<FluxJob<T>> fsave, fpart, finish;
   DevTable<GatherJob<T>> gather;
-  DevTable<FusedJob<T>> fused[2];  // by TY: 4, 8
+  DevTable<FusedJob<T>> fused[3];  // by TY: 4, 8, 16
   DevTable<ShellJob<T>> shell;
   DevTable<SourceJob<T>> sources;
   DevTable<ScatterJob<T>> scatter;
@@ -1776,7 +1776,7 @@ struct BatchTables {
   }
 };
 
-int ty_slot(int ty) { return ty == 8 ? 1 : 0; }
+int ty_slot(int ty) { return ty == 16 ? 2 : (ty == 8 ? 1 : 0); }
 
 }  // namespace
 
@@ -1816,7 +1816,7 @@ mlk_status build_tables(mlk_batch* b, BatchTables<T> (&tab)[2]) {
   for (int q = 0; q < 2; ++q) {
     std::vector<FluxJob<T>> fs, fpj, fin;
     std::vector<GatherJob<T>> ga;
-    std::vector<FusedJob<T>> fu[2];
+    std::vector<FusedJob<T>> fu[3];
     std::vector<ShellJob<T>> sh;
     std::vector<SourceJob<T>> so;
     std::vector<ScatterJob<T>> sc;
@@ -1874,7 +1874,7 @@ mlk_status build_tables(mlk_batch* b, BatchTables<T> (&tab)[2]) {
     STCHK(make_table(t.fpart, fpj));
     STCHK(make_table(t.finish, fin));
     STCHK(make_table(t.gather, ga));
-    for (int k = 0; k < 2; ++k) STCHK(make_table(t.fused[k], fu[k]));
+    for (int k = 0; k < 3; ++k) STCHK(make_table(t.fused[k], fu[k]));
     STCHK(make_table(t.shell, sh));
     STCHK(make_table(t.sources, so));
     STCHK(make_table(t.scatter, sc));
@@ -1927,8 +1927,8 @@ mlk_status enqueue_batch_step(mlk_batch* b, const BatchTables<T>& t) {
   HIPCHK(tls_batch(b->tls.jobs, b->tls.start, b->tls.njobs, b->tls.nblocks, st));
   for (int n = 2; n <= kMaxLevels; ++n)
     HIPCHK(ml_batch(b->ml[n].jobs, b->ml[n].start, b->ml[n].njobs, b->ml[n].nblocks, n, st));
-  const int tys[2] = {4, 8};
-  for (int k = 0; k < 2; ++k) {
+  const int tys[3] = {4, 8, 16};
+  for (int k = 0; k < 3; ++k) {
     const DevTable<FusedJob<T>>& f = t.fused[k];
     if constexpr (f32) HIPCHK(sweep_fused_batch_f32(f.jobs, f.start, f.njobs, f.nblocks, tys[k], st));
     else HIPCHK(sweep_fused_batch_f64(f.jobs, f.start, f.njobs, f.nblocks, tys[k], st));
@@ -2144,8 +2144,8 @@ mlk_status mlk_batch_destroy(mlk_batch* b) {
 
 // ==================================================================== autotuner
 //
-// The fused sweep has two tile parameters: the rows per workgroup (TY = 4 or 8;
-// 64 x TY threads) and the z planes each workgroup marches (kz).  They trade
+// The fused sweep has two tile parameters: the rows per workgroup (TY = 4, 8 or
+// 16; 64 x TY threads) and the z planes each workgroup marches (kz).  They trade
 // LDS halo re-reads (larger TY) and prologue cost (larger kz) against the
 // number of workgroups in flight.  mlk_autotune times every pair on the sim's
 // own grid (the kernel reads the current fields and writes the spare buffers,
@@ -2207,7 +2207,7 @@ mlk_status time_fused(mlk_sim* s, int ty, int kz, double* us) {
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   hipError_t err = hipSuccess;
-  constexpr int kReps = 4;
+  constexpr int kReps = 10;
   for (int r = -1; r < kReps && err == hipSuccess; ++r) {
     if (r == 0) err = hipEventRecord(e0, s->stream);
     if (err == hipSuccess) {
@@ -2232,7 +2232,8 @@ extern "C" {
 
 mlk_status mlk_set_tuning(mlk_sim* s, int32_t ty, int32_t kz) {
   if (!s) return fail(MLK_EINVAL, "null argument");
-  if (ty != 4 && ty != 8) return fail(MLK_EINVAL, "rows per workgroup must be 4 or 8");
+  if (ty != 4 && ty != 8 && ty != 16)
+    return fail(MLK_EINVAL, "rows per workgroup must be 4, 8 or 16");
   if (kz < 1) return fail(MLK_EINVAL, "planes per workgroup must be positive");
   if (s->in_batch) return fail(MLK_ESTATE, "tune members before forming the batch");
   s->ty = ty;
@@ -2254,7 +2255,7 @@ mlk_status mlk_autotune(mlk_sim* s, const char* cache_path) {
   const std::string key = tune_key(s);
   std::vector<TuneEntry> cache = read_cache(cache_path);
   for (const TuneEntry& e : cache)
-    if (e.key == key && (e.ty == 4 || e.ty == 8) && e.kz > 0) {
+    if (e.key == key && (e.ty == 4 || e.ty == 8 || e.ty == 16) && e.kz > 0) {
       s->ty = e.ty;
       s->kz = e.kz;
       return MLK_OK;
@@ -2266,7 +2267,7 @@ mlk_status mlk_autotune(mlk_sim* s, const char* cache_path) {
   if (ez <= 0) return MLK_OK;
   double best = 1e300;
   int bty = s->ty, bkz = s->kz;
-  for (int ty : {4, 8})
+  for (int ty : {4, 8, 16})
     for (int kz : {4, 8, 16, 32, 64, 128}) {
       if (kz > std::max(4, ez)) continue;
       double us = 0.0;

@@ -342,6 +342,7 @@ template void fused_job_shape<double>(FusedJob<double>&);
 template <typename T>
 static hipError_t launch_fused_any(const FieldPtrs<T>& a, const FieldPtrs<T>& b, const Geom& g,
                                    const Box& box, int kz, int ty, hipStream_t st) {
+  if (ty == 16) return launch_fused<T, 16>(a, b, g, box, kz, st);
   if (ty == 8) return launch_fused<T, 8>(a, b, g, box, kz, st);
   return launch_fused<T, 4>(a, b, g, box, kz, st);
 }
@@ -350,7 +351,9 @@ template <typename T>
 static hipError_t launch_fused_batch(const FusedJob<T>* jobs, const int* start, int njobs,
                                      int nblocks, int ty, hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
-  if (ty == 8)
+  if (ty == 16)
+    hipLaunchKernelGGL((k_fused_batch<T, 16>), dim3(nblocks), dim3(1024), 0, st, jobs, start, njobs);
+  else if (ty == 8)
     hipLaunchKernelGGL((k_fused_batch<T, 8>), dim3(nblocks), dim3(512), 0, st, jobs, start, njobs);
   else
     hipLaunchKernelGGL((k_fused_batch<T, 4>), dim3(nblocks), dim3(256), 0, st, jobs, start, njobs);

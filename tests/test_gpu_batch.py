@@ -137,9 +137,9 @@ def test_tile_shape_changes_speed_not_results(tmp_path):
     w = W.radiating_cube(n=72, n_emit=300, steps=0, cpml=10, precision="fp32")
     a = mlk().from_workload(w)
     b = mlk().from_workload(w)
-    b.set_tuning(8, 5)
+    b.set_tuning(16, 5)
     c = mlk().from_workload(w)
-    c.set_tuning(4, 64)
+    c.set_tuning(8, 64)
     for s in (a, b, c):
         s.step(25)
     assert same(a.fields(), b.fields()) and same(a.fields(), c.fields())
@@ -148,7 +148,7 @@ def test_tile_shape_changes_speed_not_results(tmp_path):
     cache = str(tmp_path / "tune.json")
     t = a.autotune(cache)
     say(f"  autotuned (ty, kz) = {t}")
-    assert t[0] in (4, 8) and t[1] >= 1
+    assert t[0] in (4, 8, 16) and t[1] >= 1
     d = mlk().from_workload(w)
     assert d.autotune(cache) == t  # read back from the cache
     import json
