@@ -54,6 +54,8 @@ def parse():
     p.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
     p.add_argument("--adjoint-steps", type=int, default=4000)
     p.add_argument("--copy-calib", action="store_true")
+    p.add_argument("--tile", type=lambda v: tuple(int(x) for x in v.split(",")), default=None,
+                   help="fused tile TY,KZ instead of autotuning (profiling runs)")
     return p.parse_args()
 
 
@@ -94,12 +96,15 @@ def traffic_from_profile(launch_cells):
     return float(t.group(1))
 
 
-def run_gpu(w, precision, sweep, steps, warmup, timing):
+def run_gpu(w, precision, sweep, steps, warmup, timing, tile=None):
     import torch
     from paper_2512_06173_amd import mlk
     sim = mlk.from_workload(w, precision=precision, sweep=sweep, scatter="owner",
                             stream=mlk.current_stream_handle())
-    sim.autotune()  # tile shape of the fused sweep (untimed; plain sweeps have none)
+    if tile:
+        sim.set_tuning(*tile)
+    else:
+        sim.autotune()  # tile shape of the fused sweep (untimed; plain sweeps have none)
     sim.step(warmup)
     sim.sync()
     sim.set_timing(timing or False)
@@ -242,9 +247,11 @@ def main():
     step_bytes = cells * CELL_WORDS * esz + memb * PSI_WORDS * esz + nem * TLS_STEP_BYTES
 
     # timed region: events around the fused sweep launch only
-    dt, phases, box, tuning = run_gpu(w, "fp32", "fused", args.steps, args.warmup, ["sweep"])
+    dt, phases, box, tuning = run_gpu(w, "fp32", "fused", args.steps, args.warmup, ["sweep"],
+                                      args.tile)
     # per-phase breakdown from a separate, shorter run with every phase timed
-    _, breakdown, _, _ = run_gpu(w, "fp32", "fused", max(1, args.steps // 5), 5, True)
+    _, breakdown, _, _ = run_gpu(w, "fp32", "fused", max(1, args.steps // 5), 5, True,
+                                 tuning)
     ms_step = dt * 1e3 / args.steps
     gcells = cells * args.steps / dt / 1e9
     emit_rate = nem * args.steps / dt
@@ -253,7 +260,9 @@ def main():
     sweep_ms, sweep_n = phases["sweep"]
     lo, hi = box
     launch_cells = (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2])
-    launch_bytes = launch_cells * CELL_WORDS * esz
+    # cells of the launch inside the x CPML layers also read and write 8 psi words
+    xlayer_cells = (w.cpml[0] + w.cpml[1]) * (hi[1] - lo[1]) * (hi[2] - lo[2])
+    launch_bytes = launch_cells * CELL_WORDS * esz + xlayer_cells * PSI_WORDS * esz
     t_launch = sweep_ms / sweep_n * 1e-3
     achieved = launch_bytes / t_launch / 1e9
     traffic = traffic_from_profile(launch_cells)
@@ -261,7 +270,8 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "kernel": f"k_fused<float, {tuning[0]}>",
                 "tile": {"ty": tuning[0], "kz": tuning[1]},
-                "bytes_per_launch": launch_bytes, "avg_launch_us": round(t_launch * 1e6, 2)}
+                "cells_per_launch": launch_cells, "bytes_per_launch": launch_bytes,
+                "avg_launch_us": round(t_launch * 1e6, 2)}
     emitter_ms = sum(breakdown[p][0] / breakdown[p][1] for p in ("emitters", "scatter")
                      if p in breakdown)
     out = {

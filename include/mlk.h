@@ -284,8 +284,10 @@ mlk_status mlk_batch_sync(mlk_batch* b);
 mlk_status mlk_batch_destroy(mlk_batch* b);
 
 /* Tile shape of the fused sweep: rows per workgroup ty (4, 8 or 16) and z planes
- * per workgroup kz.  mlk_autotune times every pair on the sim's own grid (the
- * state is left untouched) and keeps the fastest; with cache_path (NULL: no
+ * per workgroup kz.  mlk_autotune times every pair on the sim's own grid, each
+ * as the fused launch plus the two CPML shell passes of a step, in three
+ * interleaved rounds (the state is left untouched; each pair keeps its best
+ * round) and keeps the fastest; with cache_path (NULL: no
  * cache) results are read from and added to a JSON file keyed by precision,
  * grid and interior box.  The result does not depend on the tile shape (each
  * cell's arithmetic is the same), only the speed does.  Plain-sweep sims have

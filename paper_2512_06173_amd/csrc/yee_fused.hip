@@ -3,11 +3,15 @@
 //   H^{n+1/2} = H^{n-1/2} - dt curl E^n
 //   E^{n+1}   = E^n + (dt/eps_r) curl H^{n+1/2}
 // (eq. Maxwell with D = eps_r E and B = H) with metallic or periodic closure.
-// This kernel covers the box of cells whose own update and recomputed halo
-// lie outside every CPML layer (the layers plus a one-cell margin are updated
-// by the plain passes, which carry the PML stretching); keeping the PML out
-// of this kernel keeps its register footprint, and with it its occupancy,
-// small.  Source and molecular currents are added by their own passes.
+// This kernel covers a box of cells whose y and z positions keep their own
+// update and recomputed halo outside the y and z CPML layers (those layers
+// plus a one-cell margin are updated by the plain passes, whole rows of the
+// grid).  Along x the box normally spans every column and cells in the x
+// layers stretch their x derivatives here: they are a few lanes at the two
+// ends of each row, which the plain passes would otherwise handle as short,
+// badly coalesced strips.  The host chooses that box only when no tile's
+// low-x halo column lies in an x layer, so halo recomputations never need
+// psi.  Source and molecular currents are added by their own passes.
 //
 // A workgroup owns a tile of 64 x TY columns and marches over a chunk of z
 // planes.  For plane k it stages E^n(k+1) (with a one-cell halo ring) in LDS,
@@ -92,6 +96,7 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
   static_assert(64 * TY >= NHALO, "one thread per ring slot of the staged E plane");
   __shared__ T eL[2][3][EH * EW];
   __shared__ T hL[3][HH * HW];
+  __shared__ T xc[2][3][64];  // x CPML b, c, 1/kappa of the tile's columns (E, H positions)
 
   // XCD-aware tile order: consecutive blocks go to different XCDs; map the
   // blocks one XCD receives onto a contiguous range of tiles.
@@ -138,6 +143,31 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
   const bool hy_on = ty == 0 && i < box.hi[0] && (y0 > 0 || g.periodic[1]);
   const int jh = y0 > 0 ? y0 - 1 : g.n[1] - 1;
   const size_t own_off = own ? (size_t)i + (size_t)g.n[0] * j : 0;
+  // x CPML: own cells in the x layers stretch their x derivatives, psi <- b psi
+  // + c d, d <- d / kappa + psi.  The coefficients of the tile's columns sit in
+  // LDS; psi (one array per field component, x compressed to the layers) is
+  // read at plane k through a 32-bit index (32-bit range checked on the host).
+  const bool xl = has_cpml(g, 0) && i >= box.lo[0] && i < box.hi[0] && j < box.hi[1] &&
+                  in_layer(g, 0, i);
+  const unsigned nl = (unsigned)(g.nlo[0] + g.nhi[0]);
+  const unsigned nlny = nl * (unsigned)g.n[1];
+  const size_t P = (size_t)nlny * (unsigned)g.n[2];  // psi values per component array
+  const unsigned li = xl ? (unsigned)layer_index(g, 0, i) : 0u;
+  const unsigned pb = li + nl * (unsigned)j, pby = li + nl * (unsigned)jh;
+  // psi arrays of axis x: E of y, E of z, H of y, H of z
+  auto psi_at = [&](const FieldPtrs<T>& f, int slot, unsigned id) -> T& {
+    return f.psi[(size_t)slot * P + id];
+  };
+  if (ty == 0 && xl) {
+    const T* t = a.tab + tab_offset(g, 0);
+    const int n = g.n[0];
+#pragma unroll
+    for (int fld = 0; fld < 2; ++fld) {
+      xc[fld][0][tx] = t[fld * n + i];
+      xc[fld][1][tx] = t[2 * n + fld * n + i];
+      xc[fld][2][tx] = t[4 * n + fld * n + i];
+    }
+  }
   const size_t hx_off = hx_on ? (size_t)ih + (size_t)g.n[0] * j : 0;
   const size_t hy_off = hy_on ? (size_t)i + (size_t)g.n[0] * jh : 0;
 
@@ -177,6 +207,11 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
       T dEy_dz = (ek[1] - em[1]) * idx;
       T dEx_dz = (ek[0] - em[0]) * idx;
       T dEz_dx = (E_at(pm, 2, tx + 1, ty) - em[2]) * idx;
+      if (xl) {
+        const unsigned kmw = (unsigned)(km < 0 ? km + g.n[2] : km);
+        const T q = xc[1][0][tx] * psi_at(a, 2, pb + nlny * kmw) + xc[1][1][tx] * dEz_dx;
+        dEz_dx = xc[1][2][tx] * dEz_dx + q;
+      }
       hpx = a.H[0][id] - dt * (dEz_dy - dEy_dz);
       hpy = a.H[1][id] - dt * (dEx_dz - dEz_dx);
     }
@@ -202,6 +237,18 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
     nHy[1] = a.H[2][hy_off + po];
   };
   prefetch_h(k0);
+  // psi of plane k for the x-layer cells, read one iteration ahead after the
+  // plane's field prefetch: own E y/z and H y/z, and H z of the low-y halo cell
+  T nP[4] = {T(0), T(0), T(0), T(0)}, nPy = T(0);
+  auto prefetch_psi = [&](int k) {
+    if (xl && k < k1) {
+      const unsigned pk = pb + nlny * (unsigned)k;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) nP[q] = psi_at(a, q, pk);
+      if (hy_on) nPy = psi_at(a, 3, pby + nlny * (unsigned)k);
+    }
+  };
+  prefetch_psi(k0);
 
   for (int k = k0; k < k1; ++k) {
     const int p0 = k & 1, p1 = (k + 1) & 1;
@@ -229,6 +276,16 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
       T dEz_dx = (E_at(p0, 2, tx + 1, ty) - ek[2]) * idx;
       T dEy_dx = (E_at(p0, 1, tx + 1, ty) - ek[1]) * idx;
       T dEx_dy = (E_at(p0, 0, tx, ty + 1) - ek[0]) * idx;
+      if (xl) {
+        const unsigned pk = pb + nlny * (unsigned)k;
+        const T bh = xc[1][0][tx], ch = xc[1][1][tx], kh = xc[1][2][tx];
+        const T qy = bh * nP[2] + ch * dEz_dx;
+        const T qz = bh * nP[3] + ch * dEy_dx;
+        psi_at(b, 2, pk) = qy;
+        psi_at(b, 3, pk) = qz;
+        dEz_dx = kh * dEz_dx + qy;
+        dEy_dx = kh * dEy_dx + qz;
+      }
       hx -= dt * (dEz_dy - dEy_dz);
       hy -= dt * (dEx_dz - dEz_dx);
       hz -= dt * (dEy_dx - dEx_dy);
@@ -261,6 +318,7 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
         T dEy_dz = (E_at(p1, 1, tx, -1) - E_at(p0, 1, tx, -1)) * idx;
         T dEy_dx = (E_at(p0, 1, tx + 1, -1) - E_at(p0, 1, tx, -1)) * idx;
         T dEx_dy = (E_at(p0, 0, tx, 0) - E_at(p0, 0, tx, -1)) * idx;
+        if (xl) dEy_dx = xc[1][2][tx] * dEy_dx + (xc[1][0][tx] * nPy + xc[1][1][tx] * dEy_dx);
         hxh = hyh_x - dt * (dEz_dy - dEy_dz);
         hzh = hyh_z - dt * (dEy_dx - dEx_dy);
       }
@@ -277,6 +335,16 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
       T dHz_dx = (hz - hL[2][(ty + 1) * HW + tx]) * idx;
       T dHy_dx = (hy - hL[1][(ty + 1) * HW + tx]) * idx;
       T dHx_dy = (hx - hL[0][ty * HW + tx + 1]) * idx;
+      if (xl) {
+        const unsigned pk = pb + nlny * (unsigned)k;
+        const T be = xc[0][0][tx], ce0 = xc[0][1][tx], ke = xc[0][2][tx];
+        const T qy = be * nP[0] + ce0 * dHz_dx;
+        const T qz = be * nP[1] + ce0 * dHy_dx;
+        psi_at(b, 0, pk) = qy;
+        psi_at(b, 1, pk) = qz;
+        dHz_dx = ke * dHz_dx + qy;
+        dHy_dx = ke * dHy_dx + qz;
+      }
       const T cx = dHz_dy - dHy_dz;
       const T cy = dHx_dz - dHz_dx;
       const T cz = dHy_dx - dHx_dy;
@@ -288,6 +356,7 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
     hpy = hy;
 #pragma unroll
     for (int c = 0; c < 3; ++c) ek[c] = ek1[c];
+    prefetch_psi(k + 1);
   }
 }
 

@@ -131,6 +131,20 @@ def test_fused_sweep_many_tiles_and_chunks_fp64():
     check(sim, ora, w)
 
 
+@pytest.mark.parametrize("nx, full", [(72, True), (70, False)])
+def test_fused_x_layers_and_fallback_box_fp64(nx, full):
+    """The fused sweep spans every x column and stretches x derivatives in the x CPML
+    layers, unless the low-x halo column of a 64-wide tile falls into a layer (nx = 70
+    with 8 layers: the second tile's halo column x = 63 is a layer cell); then the x
+    layers go to the plain passes.  Both boxes against the oracle."""
+    w = _sources_workload((nx, 30, 36), ("cpml",) * 6, (8, 8, 6, 7, 8, 6), "fp64", 150)
+    sim, ora = run_both(w, sweep="fused")
+    lo, hi = sim.interior_box()
+    assert (lo[0], hi[0]) == ((0, nx) if full else (9, nx - 8))
+    assert (lo[1], hi[1], lo[2], hi[2]) == (7, 23, 9, 30)
+    check(sim, ora, w)
+
+
 def test_ragged_mixed_boundaries_fp64():
     """x periodic with a ragged tail (nx not a multiple of 64), y metallic, z CPML; emitters
     whose windows wrap across the periodic axis."""
