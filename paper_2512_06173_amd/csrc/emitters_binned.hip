@@ -77,13 +77,6 @@ __device__ __forceinline__ double group_sum8(double v) {
   return v;
 }
 
-// XCD-aware order: hardware hands consecutive workgroups to the 8 XCDs in turn;
-// give each XCD a contiguous range of bins.
-__device__ __forceinline__ int xcd_block(int bid, int nblocks) {
-  const int q8 = nblocks / 8;
-  return bid < 8 * q8 ? (bid % 8) * q8 + bid / 8 : bid;
-}
-
 // Copy the window records of emitters ids[0..cn) into LDS (16-byte pieces).
 template <typename T, int NT>
 __device__ __forceinline__ void stage_records(const WinRec<T>* rec, const int* ids, int cn,

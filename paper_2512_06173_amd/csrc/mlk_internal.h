@@ -25,6 +25,14 @@ struct Geom {
   double dx;
 };
 
+// XCD-aware order: hardware hands consecutive workgroups to the 8 XCDs in turn;
+// map them so that each XCD gets a contiguous range of work items (tiles, bins,
+// rows), whose neighbours then meet in the same L2.
+__device__ __forceinline__ int xcd_block(int bid, int nblocks) {
+  const int q8 = nblocks / 8;
+  return bid < 8 * q8 ? (bid % 8) * q8 + bid / 8 : bid;
+}
+
 // Workgroup barrier that orders LDS only: global loads in flight (prefetches)
 // stay in flight across it, unlike __syncthreads(), whose fence also waits for
 // every outstanding global memory operation.
