@@ -77,18 +77,6 @@ __device__ __forceinline__ double group_sum8(double v) {
   return v;
 }
 
-// Copy the window records of emitters ids[0..cn) into LDS (16-byte pieces).
-template <typename T, int NT>
-__device__ __forceinline__ void stage_records(const WinRec<T>* rec, const int* ids, int cn,
-                                              WinRec<T>* dst, int tid) {
-  constexpr int R4 = sizeof(WinRec<T>) / sizeof(int4);
-  for (int i = tid; i < cn * R4; i += NT) {
-    const int slot = i / R4, part = i % R4;
-    const int4* src = reinterpret_cast<const int4*>(rec + ids[slot]);
-    reinterpret_cast<int4*>(dst + slot)[part] = src[part];
-  }
-}
-
 // The part of an emitter's window record that one of its eight lanes needs,
 // in registers: the union window, the lane's own x weights and every y and z
 // weight (the eight lanes read the same record, one cache line at a time).
@@ -319,8 +307,15 @@ __device__ __forceinline__ void scatter_body(const FieldPtrs<T>& f, const Geom& 
   constexpr int BX = BinCfg<T>::SX, BY = BinCfg<T>::SY, BZ = BinCfg<T>::SZ;
   constexpr int CELLS = BX * BY * BZ;
   constexpr int NW = kThreads / 64;
+  constexpr int R4 = sizeof(WinRec<T>) / sizeof(int4);       // 16-byte pieces of a record
+  constexpr int NP = (kGroups * R4 + kThreads - 1) / kThreads;  // pieces per thread and chunk
+  // pair ids of a bin kept in LDS (beyond: read from HBM); sized so that two
+  // workgroups still fit one CU's LDS
+  constexpr int kIdCap = sizeof(T) == 4 ? 4096 : 1024;
   __shared__ typename A::U sJ[3][CELLS];
   __shared__ WinRec<T> sW[kGroups];
+  __shared__ T sAmp[kGroups][3];
+  __shared__ int sId[kIdCap];
   __shared__ double sRed[NW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int b = bins.sbin_id[bid];
@@ -336,6 +331,7 @@ __device__ __forceinline__ void scatter_body(const FieldPtrs<T>& f, const Geom& 
   double bound = 0.0;
   for (int q = q0 + tid; q < q1; q += kThreads) {
     const int e = bins.sbin_em[q];
+    if (q - q0 < kIdCap) sId[q - q0] = e;
     const double ge = fabs(amp0 * win.gamma[e]) * (double)win.rec[e].wmax;
     bound += ge * (fabs(mudot[3 * e]) + fabs(mudot[3 * e + 1]) + fabs(mudot[3 * e + 2]));
   }
@@ -351,50 +347,102 @@ __device__ __forceinline__ void scatter_body(const FieldPtrs<T>& f, const Geom& 
   const double scale = ldexp(1.0, A::BITS - ebits);
   const double inv_scale = ldexp(1.0, ebits - A::BITS);
 
-  // Eight lanes per (emitter, bin) pair, lane i on window x offset i; the group
-  // walks only the window rows (y, z offsets) that fall inside the bin, given as
-  // bit masks, with the weights read from the LDS copy of the record.
+  // The pairs are taken in chunks of kGroups.  With FP32 fields the next
+  // chunk's window records and amplitudes (gamma, mu_dot) are loaded into
+  // registers while the current chunk is summed, and moved to LDS behind an
+  // LDS-only barrier, so their HBM latency overlaps the atomics instead of
+  // stalling every chunk.  FP64 records are twice as large: holding them across
+  // the sums would cost the second workgroup per CU, so FP64 loads each chunk
+  // right before storing it.
+  constexpr bool kPipe = sizeof(T) == 4;
+  typedef int piece_t __attribute__((ext_vector_type(4)));  // kept in registers
+  piece_t piece[NP];
+  double pg = 0.0, pm0 = 0.0, pm1 = 0.0, pm2 = 0.0;
+  // Eight lanes per (emitter, bin) pair, lane i on window x offset i.  The
+  // window rows (y) and planes (z) inside the bin are given as bit masks over
+  // the window offsets; the group walks exactly its cj x ck of them (the r-th
+  // set bit first moved, with its weights and LDS offset, into register r), so
+  // a wavefront runs its eight groups' loops side by side for as many steps as
+  // its longest group, and the host orders the pairs of a bin by (ck, cj) so
+  // that neighbouring groups have equal counts.
   const int grp = tid / kLanesPerEmitter, i = tid % kLanesPerEmitter;
+  // loads of the chunk at c: pieces (clamped to the chunk's last record) and, for
+  // tid < the chunk size, the amplitude inputs of pair tid
+#define MLK_STAGE_LOAD(c)                                                             \
+  {                                                                                  \
+    const int cl = min(kGroups, q1 - (c)) - 1;                                       \
+    _Pragma("unroll") for (int p = 0; p < NP; ++p) {                                 \
+      const int idx = tid + p * kThreads, sl = min(idx / R4, cl);                    \
+      const int q = (c) + sl;                                                        \
+      const int em = q - q0 < kIdCap ? sId[q - q0] : bins.sbin_em[q];                \
+      piece[p] = reinterpret_cast<const piece_t*>(win.rec + em)[idx % R4];           \
+    }                                                                                \
+    const int q = (c) + min(tid, cl);                                                \
+    const int em = q - q0 < kIdCap ? sId[q - q0] : bins.sbin_em[q];                  \
+    pg = win.gamma[em];                                                              \
+    pm0 = mudot[3 * em];                                                             \
+    pm1 = mudot[3 * em + 1];                                                         \
+    pm2 = mudot[3 * em + 2];                                                         \
+  }
+  if (kPipe) MLK_STAGE_LOAD(q0)
   for (int c0 = q0; c0 < q1; c0 += kGroups) {
     const int cn = min(kGroups, q1 - c0);
-    if (c0 > q0) __syncthreads();  // the previous chunk's records are no longer read
-    stage_records<T, kThreads>(win.rec, bins.sbin_em + c0, cn, sW, tid);
-    __syncthreads();
+    if (c0 > q0) lds_barrier();  // the previous chunk's records are no longer read
+    if (!kPipe) MLK_STAGE_LOAD(c0)
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const int idx = tid + p * kThreads;
+      if (idx < cn * R4) reinterpret_cast<piece_t*>(sW + idx / R4)[idx % R4] = piece[p];
+    }
+    if (tid < cn) {
+      const double ge = amp0 * pg * scale;
+      sAmp[tid][0] = (T)(ge * pm0);
+      sAmp[tid][1] = (T)(ge * pm1);
+      sAmp[tid][2] = (T)(ge * pm2);
+    }
+    lds_barrier();
+    if (kPipe && c0 + kGroups < q1) MLK_STAGE_LOAD(c0 + kGroups)
     if (grp >= cn) continue;
     const WinRec<T>& w = sW[grp];
-    const int e = bins.sbin_em[c0 + grp];
-    // the window rows inside the bin as bit masks, with their LDS offsets and
-    // weights in registers: the loops below touch LDS only through the atomics
     unsigned jm = 0, km = 0;
-    int rowoff[kMaxWin], planeoff[kMaxWin];
-    T wy0[kMaxWin], wy1[kMaxWin], wz0[kMaxWin], wz1[kMaxWin];
 #pragma unroll
     for (int d = 0; d < kMaxWin; ++d) {
       const int lj = wrap_once(w.org[1] + d, g.n[1]) - y0;
       const int lk = wrap_once(w.org[2] + d, g.n[2]) - z0;
       jm |= (d < w.n[1] && lj >= 0 && lj < ey) ? 1u << d : 0u;
       km |= (d < w.n[2] && lk >= 0 && lk < ez) ? 1u << d : 0u;
-      rowoff[d] = BX * lj;
-      planeoff[d] = BX * BY * lk;
-      wy0[d] = w.wr[1][0][d];
-      wy1[d] = w.wr[1][1][d];
-      wz0[d] = w.wr[2][0][d];
-      wz1[d] = w.wr[2][1][d];
     }
     const int li = wrap_once(w.org[0] + i, g.n[0]) - x0;
-    if (!(i < w.n[0] && li >= 0 && li < ex)) continue;
-    const double ge = amp0 * win.gamma[e] * scale;
-    const T cx = (T)(ge * mudot[3 * e]) * w.wr[0][1][i];
-    const T cy = (T)(ge * mudot[3 * e + 1]) * w.wr[0][0][i];
-    const T cz = (T)(ge * mudot[3 * e + 2]) * w.wr[0][0][i];
+    if (!(i < w.n[0] && li >= 0 && li < ex) || jm == 0 || km == 0) continue;
+    const int cj = __builtin_popcount(jm), ck = __builtin_popcount(km);
+    int rowoff[kMaxWin], planeoff[kMaxWin];
+    T wy0[kMaxWin], wy1[kMaxWin], wz0[kMaxWin], wz1[kMaxWin];
+    unsigned mj = jm, mk = km;
+#pragma unroll
+    for (int r = 0; r < kMaxWin; ++r) {
+      // offset of the r-th set bit (the last offset once the mask is spent)
+      const int ry = mj ? __builtin_ctz(mj) : kMaxWin - 1;
+      const int rz = mk ? __builtin_ctz(mk) : kMaxWin - 1;
+      mj &= mj - 1u;
+      mk &= mk - 1u;
+      rowoff[r] = BX * (wrap_once(w.org[1] + ry, g.n[1]) - y0);
+      planeoff[r] = BX * BY * (wrap_once(w.org[2] + rz, g.n[2]) - z0);
+      wy0[r] = w.wr[1][0][ry];
+      wy1[r] = w.wr[1][1][ry];
+      wz0[r] = w.wr[2][0][rz];
+      wz1[r] = w.wr[2][1][rz];
+    }
+    const T cx = sAmp[grp][0] * w.wr[0][1][i];
+    const T cy = sAmp[grp][1] * w.wr[0][0][i];
+    const T cz = sAmp[grp][2] * w.wr[0][0][i];
 #pragma unroll
     for (int k = 0; k < kMaxWin; ++k) {
-      if (!((km >> k) & 1u)) continue;
+      if (k >= ck) break;
       const T cxk = cx * wz0[k], cyk = cy * wz0[k], czk = cz * wz1[k];
       const int pk = planeoff[k] + li;
 #pragma unroll
       for (int j = 0; j < kMaxWin; ++j) {
-        if (!((jm >> j) & 1u)) continue;
+        if (j >= cj) break;
         const int s = pk + rowoff[j];
         atomicAdd(&sJ[0][s], (typename A::U)A::round(cxk * wy0[j]));
         atomicAdd(&sJ[1][s], (typename A::U)A::round(cyk * wy1[j]));
@@ -402,6 +450,7 @@ __device__ __forceinline__ void scatter_body(const FieldPtrs<T>& f, const Geom& 
       }
     }
   }
+#undef MLK_STAGE_LOAD
   __syncthreads();
   // owner write: E -= [eps^-1] J on the cells of this bin; the loads of a thread's
   // cells are issued together (unconditional, from a safe index), then the stores
@@ -430,14 +479,14 @@ __device__ __forceinline__ void scatter_body(const FieldPtrs<T>& f, const Geom& 
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_scatter_bins(FieldPtrs<T> f, Geom g, BinPtrs bins,
+__global__ __launch_bounds__(kThreads, 4) void k_scatter_bins(FieldPtrs<T> f, Geom g, BinPtrs bins,
                                                            WindowPtrs<T> win,
                                                            const double* mudot) {
   scatter_body(f, g, bins, win, mudot, g.dt * g.inv_dx * g.inv_dx * g.inv_dx, blockIdx.x);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_scatter_batch(const ScatterJob<T>* jobs,
+__global__ __launch_bounds__(kThreads, 4) void k_scatter_batch(const ScatterJob<T>* jobs,
                                                             const int* start, int njobs) {
   const int j = find_job(start, njobs, blockIdx.x);
   const ScatterJob<T>& J = jobs[j];
@@ -535,7 +584,7 @@ __global__ __launch_bounds__(kThreads) void k_gather_epsw(FieldPtrs<T> f, Geom g
   gather_body<T, true>(f, g, bins, win, out, blockIdx.x);
 }
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_scatter_plain(FieldPtrs<T> f, Geom g, BinPtrs bins,
+__global__ __launch_bounds__(kThreads, 4) void k_scatter_plain(FieldPtrs<T> f, Geom g, BinPtrs bins,
                                                             WindowPtrs<T> win, const double* amp,
                                                             double amp0) {
   scatter_body<T, false>(f, g, bins, win, amp, amp0, blockIdx.x);

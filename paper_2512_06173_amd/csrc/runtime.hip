@@ -387,9 +387,10 @@ mlk_status build_bins(mlk_sim* s) {
     const int e = gem[q];
     for (int b : per_em[e]) sem[fill[slot_of[b]]++] = e;
   }
-  // within a bin, pairs by decreasing number of window rows (y, z) inside it:
-  // the workgroup runs eight pairs per wavefront side by side, so similar row
-  // counts keep its lanes busy (stable: ties stay in gather order)
+  // within a bin, pairs by decreasing numbers of window planes (z), then rows
+  // (y), inside it: the workgroup runs eight pairs per wavefront side by side,
+  // each looping over its own planes and rows, so equal counts keep its lanes
+  // busy (stable: ties stay in gather order)
   {
     auto overlap = [&](int e, int a, int bq) {
       const int s0 = win_slot(e, a, 0), s1 = win_slot(e, a, 1);
@@ -410,7 +411,7 @@ mlk_status build_bins(mlk_sim* s) {
       tmp.clear();
       for (int q = sstart[sl]; q < sstart[sl + 1]; ++q) {
         const int e = sem[q];
-        const int rows = overlap(e, 0, bx) > 0 ? overlap(e, 1, by) * overlap(e, 2, bz) : 0;
+        const int rows = overlap(e, 0, bx) > 0 ? 16 * overlap(e, 2, bz) + overlap(e, 1, by) : 0;
         tmp.push_back({-rows, e});
       }
       std::stable_sort(tmp.begin(), tmp.end(),

@@ -263,6 +263,30 @@ def test_periodic_thin_axis_windows_wrap_inside_one_bin(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_periodic_axis_just_longer_than_a_bin(precision):
+    """y periodic with 18 cells (scatter bins of 16), z periodic with 12 (FP64 bins of 8):
+    the window of an emitter near the end of such an axis wraps round and meets the first
+    bin at both of its ends, so the window rows inside that bin are not one contiguous run
+    of window offsets."""
+    rng = np.random.default_rng(29)
+    nx, ny, nz = 40, 18, 12
+    M = 24
+    pos = np.column_stack([rng.uniform(0, nx, M), rng.uniform(0, ny, M), rng.uniform(0, nz, M)])
+    pos[:8, 1] = [16.3, 17.2, 15.6, 17.8, 0.4, 16.9, 1.5, 15.9]
+    pos[:8, 2] = [9.6, 10.4, 11.2, 9.1, 10.8, 0.3, 9.9, 11.7]
+    w = W.Workload(name="just_longer_periodic", shape=(nx, ny, nz), bc=("periodic",) * 6,
+                   steps=150, precision=precision, pop_every=3,
+                   tls=W.TLSSet(pos=pos, sigma=rng.uniform(0.8, 1.1, M),
+                                gamma=np.ones(M), omega0=rng.uniform(0.24, 0.26, M),
+                                dipole=0.3 * rng.standard_normal((M, 3)),
+                                rho0=np.tile([0.5, 0.5, 0.0], (M, 1))),
+                   probes=[(2, (5, 17, 0)), (1, (20, 0, 11))])
+    for scatter in ("owner", "atomic"):
+        sim, ora = run_both(w, scatter=scatter)
+        check(sim, ora, w)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_two_dimensional_superradiance_run(precision):
     """z-invariant grid (one periodic cell): the 2-D set-up of the paper's superradiance
     example, N = 4 collocated emitters in the weak-excitation state."""
