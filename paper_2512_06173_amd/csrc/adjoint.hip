@@ -31,10 +31,6 @@ namespace mlk {
 
 namespace {
 
-// curl terms of component c: derivative axis, sign, component of the other field
-__constant__ int kAx[3][2] = {{1, 2}, {2, 0}, {0, 1}};
-__constant__ int kOt[3][2] = {{2, 1}, {0, 2}, {1, 0}};
-
 template <typename T>
 struct AdjPtrs {
   T* E[3];           // adjoint of E
@@ -45,33 +41,13 @@ struct AdjPtrs {
   T* psi_out;        // adjoint of psi, written
 };
 
-__device__ __forceinline__ int axis_pos(int a, int i, int j, int k) {
-  return a == 0 ? i : (a == 1 ? j : k);
-}
-
-// Neighbour along axis a (delta = +-1) with periodic wrap; false beyond a
-// non-periodic face.
-__device__ __forceinline__ bool neighbour(const Geom& g, int a, int delta, int& i, int& j, int& k) {
-  int q[3] = {i, j, k};
-  q[a] += delta;
-  if (q[a] < 0 || q[a] >= g.n[a]) {
-    if (!g.periodic[a]) return false;
-    q[a] = q[a] < 0 ? q[a] + g.n[a] : q[a] - g.n[a];
-  }
-  i = q[0];
-  j = q[1];
-  k = q[2];
-  return true;
-}
-
 // Adjoint of the plain derivative from w, the adjoint of the stretched one, at
-// (i,j,k) for `field` (0: E, 1: H), component c, derivative axis a.
+// (i,j,k) for `field` (0: E, 1: H), component c, derivative axis a; `lay` says
+// whether the position lies in a CPML layer of axis a (q: its coordinate there).
 template <typename T>
-__device__ __forceinline__ T dbar(const Geom& g, const AdjPtrs<T>& p, int field, int c, int a,
-                                  int i, int j, int k, T w) {
-  if (!has_cpml(g, a)) return w;
-  const int q = axis_pos(a, i, j, k);
-  if (!in_layer(g, a, q)) return w;
+__device__ __forceinline__ T dbar(const Geom& g, const AdjPtrs<T>& p, bool lay, int field, int c,
+                                  int a, int q, int i, int j, int k, T w) {
+  if (!lay) return w;
   const size_t po = psi_offset(g, field, c, a) + psi_index(g, a, i, j, k);
   const int n = g.n[a];
   const T* t = p.tab + tab_offset(g, a) + (size_t)field * n + q;
@@ -79,41 +55,92 @@ __device__ __forceinline__ T dbar(const Geom& g, const AdjPtrs<T>& p, int field,
 }
 
 template <typename T>
-__device__ __forceinline__ void psib_update(const Geom& g, const AdjPtrs<T>& p, int field, int c,
-                                            int a, int i, int j, int k, T w) {
-  if (!has_cpml(g, a)) return;
-  const int q = axis_pos(a, i, j, k);
-  if (!in_layer(g, a, q)) return;
+__device__ __forceinline__ void psib_update(const Geom& g, const AdjPtrs<T>& p, bool lay,
+                                            int field, int c, int a, int q, int i, int j, int k,
+                                            T w) {
+  if (!lay) return;
   const size_t po = psi_offset(g, field, c, a) + psi_index(g, a, i, j, k);
   const int n = g.n[a];
   const T* t = p.tab + tab_offset(g, a) + (size_t)field * n + q;
   p.psi_out[po] = t[0] * (w + p.psi_in[po]);
 }
 
-// adjoint of E^{n+1} at (i,j,k), component c, masked on the metallic walls
-template <typename T>
-__device__ __forceinline__ T masked(const Geom& g, const AdjPtrs<T>& p, int c, int i, int j, int k) {
-  if ((c != 0 && g.wall[0] && i == 0) || (c != 1 && g.wall[1] && j == 0) ||
-      (c != 2 && g.wall[2] && k == 0))
-    return T(0);
-  return p.E[c][cell_index(g, i, j, k)];
+// A cell's neighbour one step along each axis (dir = +1 or -1): linear index,
+// coordinate along the axis, existence (false beyond a non-periodic face) and
+// CPML-layer membership.
+struct Nbrs {
+  size_t id[3];
+  int q[3];
+  bool ok[3], lay[3];
+};
+
+__device__ __forceinline__ Nbrs neighbours(const Geom& g, int i, int j, int k, size_t id, int dir) {
+  const size_t st[3] = {1, (size_t)g.n[0], (size_t)g.n[0] * g.n[1]};
+  const int q0[3] = {i, j, k};
+  Nbrs nb;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    int q = q0[a] + dir;
+    size_t nid = dir > 0 ? id + st[a] : id - st[a];
+    bool ok = true;
+    if (q < 0 || q >= g.n[a]) {
+      ok = g.periodic[a] != 0;
+      q = q < 0 ? q + g.n[a] : q - g.n[a];
+      nid = dir > 0 ? id - (size_t)(g.n[a] - 1) * st[a] : id + (size_t)(g.n[a] - 1) * st[a];
+    }
+    nb.id[a] = ok ? nid : id;
+    nb.q[a] = q;
+    nb.ok[a] = ok;
+    nb.lay[a] = ok && has_cpml(g, a) && in_layer(g, a, q);
+  }
+  return nb;
 }
+
+// curl terms of component c: derivative axis and component of the other field,
+// with the sign of the term
+constexpr int kAx[3][2] = {{1, 2}, {2, 0}, {0, 1}};
+constexpr int kOt[3][2] = {{2, 1}, {0, 2}, {1, 0}};
 
 }  // namespace
 
+// One thread per cell, 64 x 4 cells per workgroup over (x, y), one z plane per
+// grid row; neighbour values come through the caches.  Every field load of a
+// thread is issued up front, unconditionally (a missing neighbour reads the
+// cell itself and its term is zeroed afterwards), so the loads are in flight
+// together; only the CPML terms load inside branches.
+
 // Transposed E update.  Eb holds the adjoint of E^{n+1} and leaves holding that
-// of E^n (identity part, zero on the walls); Hb gains the curl part.
+// of E^n (identity part, zero on the walls, stored only where a wall zeroes it);
+// Hb gains the curl part.
 template <typename T>
 __global__ __launch_bounds__(256) void k_adj_E(AdjPtrs<T> p, Geom g) {
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t ncell = (size_t)g.n[0] * g.n[1] * g.n[2];
-  if (t >= ncell) return;
-  const int i = (int)(t % g.n[0]), j = (int)((t / g.n[0]) % g.n[1]), k = (int)(t / ((size_t)g.n[0] * g.n[1]));
+  const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
+  if (i >= g.n[0] || j >= g.n[1]) return;
+  const size_t id = (size_t)i + (size_t)g.n[0] * ((size_t)j + (size_t)g.n[1] * (size_t)k);
   const T dt = (T)g.dt, idx = (T)g.inv_dx;
+  const int qo[3] = {i, j, k};
+  const Nbrs nb = neighbours(g, i, j, k, id, +1);
+  T eo[3], hv[3], en[3][3], epn[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) eo[c] = p.E[c][id];
+  const T ei = p.epsinv[id];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    epn[a] = p.epsinv[nb.id[a]];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) en[a][c] = c != a ? p.E[c][nb.id[a]] : T(0);
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) hv[c] = p.H[c][id];
+  // wall planes through this cell (a wall zeroes the tangential E on it)
+  const bool w0 = g.wall[0] && i == 0, w1 = g.wall[1] && j == 0, w2 = g.wall[2] && k == 0;
+  const bool wl[3] = {w0, w1, w2};
   T u[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) u[c] = masked(g, p, c, i, j, k);
-  const T ei = p.epsinv[t];
+  for (int c = 0; c < 3; ++c) {
+    const bool m = (c != 0 && w0) || (c != 1 && w1) || (c != 2 && w2);
+    u[c] = m ? T(0) : eo[c];
+  }
   T hb[3] = {T(0), T(0), T(0)};
 #pragma unroll
   for (int c = 0; c < 3; ++c)
@@ -121,33 +148,48 @@ __global__ __launch_bounds__(256) void k_adj_E(AdjPtrs<T> p, Geom g) {
     for (int s = 0; s < 2; ++s) {
       const int a = kAx[c][s], h = kOt[c][s];
       const T sg = s == 0 ? T(1) : T(-1);
+      const bool lay = has_cpml(g, a) && in_layer(g, a, qo[a]);
       // own stencil: d = (H_h(cell) - H_h(cell - e_a)) / dx
       const T w = sg * dt * ei * u[c];
-      psib_update(g, p, 0, c, a, i, j, k, w);
-      hb[h] += dbar(g, p, 0, c, a, i, j, k, w) * idx;
-      // the stencil of the E cell above along a reads H_h(cell) with a minus sign
-      int ii = i, jj = j, kk = k;
-      if (neighbour(g, a, +1, ii, jj, kk)) {
-        const T wn = sg * dt * p.epsinv[cell_index(g, ii, jj, kk)] * masked(g, p, c, ii, jj, kk);
-        hb[h] -= dbar(g, p, 0, c, a, ii, jj, kk, wn) * idx;
-      }
-    }
+      psib_update(g, p, lay, 0, c, a, qo[a], i, j, k, w);
+      hb[h] += dbar(g, p, lay, 0, c, a, qo[a], i, j, k, w) * idx;
+      // the stencil of the E cell above along a reads H_h(cell) with a minus sign;
+      // that cell shares this cell's planes across the other two axes, so the
+      // walls through it are those of the other axes (no term beyond a face)
+      bool m = false;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    p.E[c][t] = u[c];
-    p.H[c][t] += hb[c];
+      for (int b = 0; b < 3; ++b) m = m || (b != a && b != c && wl[b]);
+      const T wn = (m || !nb.ok[a]) ? T(0) : sg * dt * epn[a] * en[a][c];
+      const int ii = a == 0 ? nb.q[0] : i, jj = a == 1 ? nb.q[1] : j, kk = a == 2 ? nb.q[2] : k;
+      hb[h] -= dbar(g, p, nb.lay[a], 0, c, a, nb.q[a], ii, jj, kk, wn) * idx;
+    }
+  if (w0 || w1 || w2) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) p.E[c][id] = u[c];
   }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) p.H[c][id] = hv[c] + hb[c];
 }
 
 // Transposed H update.  Hb holds the adjoint of H^{n+1/2} (unchanged: identity
 // part); Eb gains the curl part.
 template <typename T>
 __global__ __launch_bounds__(256) void k_adj_H(AdjPtrs<T> p, Geom g) {
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t ncell = (size_t)g.n[0] * g.n[1] * g.n[2];
-  if (t >= ncell) return;
-  const int i = (int)(t % g.n[0]), j = (int)((t / g.n[0]) % g.n[1]), k = (int)(t / ((size_t)g.n[0] * g.n[1]));
+  const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
+  if (i >= g.n[0] || j >= g.n[1]) return;
+  const size_t id = (size_t)i + (size_t)g.n[0] * ((size_t)j + (size_t)g.n[1] * (size_t)k);
   const T dt = (T)g.dt, idx = (T)g.inv_dx;
+  const int qo[3] = {i, j, k};
+  const Nbrs nb = neighbours(g, i, j, k, id, -1);
+  T hv[3], hn[3][3], ev[3];
+#pragma unroll
+  for (int h = 0; h < 3; ++h) hv[h] = p.H[h][id];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int h = 0; h < 3; ++h) hn[a][h] = h != a ? p.H[h][nb.id[a]] : T(0);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) ev[c] = p.E[c][id];
   T eb[3] = {T(0), T(0), T(0)};
 #pragma unroll
   for (int h = 0; h < 3; ++h)
@@ -155,19 +197,18 @@ __global__ __launch_bounds__(256) void k_adj_H(AdjPtrs<T> p, Geom g) {
     for (int s = 0; s < 2; ++s) {
       const int a = kAx[h][s], e = kOt[h][s];
       const T sg = s == 0 ? T(1) : T(-1);
+      const bool lay = has_cpml(g, a) && in_layer(g, a, qo[a]);
       // own stencil: d = (E_e(cell + e_a) - E_e(cell)) / dx, H -= dt sg s(d)
-      const T w = -sg * dt * p.H[h][t];
-      psib_update(g, p, 1, h, a, i, j, k, w);
-      eb[e] -= dbar(g, p, 1, h, a, i, j, k, w) * idx;
+      const T w = -sg * dt * hv[h];
+      psib_update(g, p, lay, 1, h, a, qo[a], i, j, k, w);
+      eb[e] -= dbar(g, p, lay, 1, h, a, qo[a], i, j, k, w) * idx;
       // the stencil of the H cell below along a reads E_e(cell) with a plus sign
-      int ii = i, jj = j, kk = k;
-      if (neighbour(g, a, -1, ii, jj, kk)) {
-        const T wn = -sg * dt * p.H[h][cell_index(g, ii, jj, kk)];
-        eb[e] += dbar(g, p, 1, h, a, ii, jj, kk, wn) * idx;
-      }
+      const T wn = nb.ok[a] ? -sg * dt * hn[a][h] : T(0);
+      const int ii = a == 0 ? nb.q[0] : i, jj = a == 1 ? nb.q[1] : j, kk = a == 2 ? nb.q[2] : k;
+      eb[e] += dbar(g, p, nb.lay[a], 1, h, a, nb.q[a], ii, jj, kk, wn) * idx;
     }
 #pragma unroll
-  for (int c = 0; c < 3; ++c) p.E[c][t] += eb[c];
+  for (int c = 0; c < 3; ++c) p.E[c][id] = ev[c] + eb[c];
 }
 
 // Flux detector: part 0 adds dt dF/dE^{n+1} and dt dF/dH^{n+1/2}, part 1 adds
@@ -361,14 +402,14 @@ static hipError_t launch_adj_sweep(const AdjSweep<T>& a, const Geom& g, hipStrea
   }
   p.epsinv = a.epsinv;
   p.tab = a.tab;
-  const size_t ncell = (size_t)g.n[0] * g.n[1] * g.n[2];
-  const unsigned blocks = (unsigned)((ncell + 255) / 256);
+  if (g.n[2] > 65535) return hipErrorInvalidValue;  // one grid row per z plane
+  const dim3 grid((g.n[0] + 63) / 64, (g.n[1] + 3) / 4, g.n[2]), block(64, 4, 1);
   p.psi_in = a.psi[0];
   p.psi_out = a.psi[1];
-  hipLaunchKernelGGL(k_adj_E<T>, dim3(blocks), dim3(256), 0, st, p, g);
+  hipLaunchKernelGGL(k_adj_E<T>, grid, block, 0, st, p, g);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_adj_H<T>, dim3(blocks), dim3(256), 0, st, p, g);
+  hipLaunchKernelGGL(k_adj_H<T>, grid, block, 0, st, p, g);
   return hipGetLastError();
 }
 
