@@ -258,8 +258,9 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
     T hx = nH[0], hy = nH[1], hz = nH[2];
     const T ce = dt * nEps;
     const T hxh_y = nHx[0], hxh_z = nHx[1], hyh_x = nHy[0], hyh_z = nHy[1];
-    // prefetch the next plane while this one is computed
-    {
+    // prefetch the next plane while this one is computed (the last plane of the
+    // chunk needs neither E(k+2) nor H(k+1))
+    if (k + 1 < k1) {
       const Col pl2 = plane(g, k + 2);
       nEov = load3(a, ocol, pl2, nEo);
       nErv = load3(a, rcol, pl2, nEr);
