@@ -7,19 +7,25 @@ namespace mlk {
 
 // Value one cell up along an axis (stride s) from linear index id at axis
 // coordinate q: wraps on a periodic axis, otherwise the virtual wall plane
-// q = n, where the tangential E of the metallic wall is zero.
+// q = n, where the tangential E of the metallic wall is zero.  The load is
+// unconditional (beyond a wall it reads the cell itself and discards it), so a
+// thread's neighbour loads are all in flight together.
 template <typename T>
 __device__ __forceinline__ T fwd(const T* a, size_t id, int q, int n, int periodic, size_t s) {
-  if (q + 1 < n) return a[id + s];
-  return periodic ? a[id - (size_t)(n - 1) * s] : T(0);
+  const bool in = q + 1 < n;
+  const size_t nid = in ? id + s : (periodic ? id - (size_t)(n - 1) * s : id);
+  const T v = a[nid];
+  return (in || periodic) ? v : T(0);
 }
 
-// Value one cell down: wraps on a periodic axis; below index 0 of a wall
-// axis the value is never used (those E components are held at zero).
+// Value one cell down: wraps on a periodic axis; below index 0 of a wall axis
+// the value is never used (those E components are held at zero).
 template <typename T>
 __device__ __forceinline__ T bwd(const T* a, size_t id, int q, int n, int periodic, size_t s) {
-  if (q > 0) return a[id - s];
-  return periodic ? a[id + (size_t)(n - 1) * s] : T(0);
+  const bool in = q > 0;
+  const size_t nid = in ? id - s : (periodic ? id + (size_t)(n - 1) * s : id);
+  const T v = a[nid];
+  return (in || periodic) ? v : T(0);
 }
 
 // Convolutional PML stretching of a derivative d taken along axis a, at the

@@ -64,12 +64,13 @@ __device__ __forceinline__ void update_e_cell(const FieldPtrs<T>& in, const Fiel
   dHy_dx = stretch(g, in.tab, in.psi, out.psi, 0, 2, 0, i, j, k, dHy_dx);
   dHx_dy = stretch(g, in.tab, in.psi, out.psi, 0, 2, 1, i, j, k, dHx_dy);
   const T ce = (T)g.dt * in.epsinv[id];
+  const T e0 = in.E[0][id], e1 = in.E[1][id], e2 = in.E[2][id];
   const T cx = dHz_dy - dHy_dz;
   const T cy = dHx_dz - dHz_dx;
   const T cz = dHy_dx - dHx_dy;
-  out.E[0][id] = tangential_wall(g, 0, i, j, k) ? T(0) : in.E[0][id] + ce * cx;
-  out.E[1][id] = tangential_wall(g, 1, i, j, k) ? T(0) : in.E[1][id] + ce * cy;
-  out.E[2][id] = tangential_wall(g, 2, i, j, k) ? T(0) : in.E[2][id] + ce * cz;
+  out.E[0][id] = tangential_wall(g, 0, i, j, k) ? T(0) : e0 + ce * cx;
+  out.E[1][id] = tangential_wall(g, 1, i, j, k) ? T(0) : e1 + ce * cy;
+  out.E[2][id] = tangential_wall(g, 2, i, j, k) ? T(0) : e2 + ce * cz;
 }
 
 template <typename T, bool H>
