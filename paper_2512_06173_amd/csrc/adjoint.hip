@@ -26,6 +26,8 @@
 // where w is the adjoint of the stretched derivative; neighbours read the old
 // psib, so it is double-buffered.
 #include "mlk_internal.h"
+#include "launch.h"
+#include "yee_common.h"
 
 namespace mlk {
 
@@ -103,19 +105,19 @@ constexpr int kOt[3][2] = {{2, 1}, {0, 2}, {1, 0}};
 
 }  // namespace
 
-// One thread per cell, 64 x 4 cells per workgroup over (x, y), one z plane per
-// grid row; neighbour values come through the caches.  Every field load of a
-// thread is issued up front, unconditionally (a missing neighbour reads the
-// cell itself and its term is zeroed afterwards), so the loads are in flight
-// together; only the CPML terms load inside branches.
+// Cell updates of the transposed step.  Every field load of a thread is issued
+// up front, unconditionally (a missing neighbour reads the cell itself and its
+// term is zeroed afterwards), so the loads are in flight together; only the
+// CPML terms load inside branches.  In place (OOP = false), p holds Eb and Hb;
+// out of place, Eb and Hb are read from p and written to o.
 
-// Transposed E update.  Eb holds the adjoint of E^{n+1} and leaves holding that
-// of E^n (identity part, zero on the walls, stored only where a wall zeroes it);
-// Hb gains the curl part.
-template <typename T>
-__global__ __launch_bounds__(256) void k_adj_E(AdjPtrs<T> p, Geom g) {
-  const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
-  if (i >= g.n[0] || j >= g.n[1]) return;
+// Transposed E update.  Eb holds the adjoint of E^{n+1}; Hb gains the curl
+// part.  In place, Eb leaves holding that of E^n (identity part, zero on the
+// walls, stored only where a wall zeroes it); out of place the H pass applies
+// the mask.
+template <typename T, bool OOP>
+__device__ __forceinline__ void adj_e_cell(const AdjPtrs<T>& p, const AdjPtrs<T>& o,
+                                           const Geom& g, int i, int j, int k) {
   const size_t id = (size_t)i + (size_t)g.n[0] * ((size_t)j + (size_t)g.n[1] * (size_t)k);
   const T dt = (T)g.dt, idx = (T)g.inv_dx;
   const int qo[3] = {i, j, k};
@@ -163,33 +165,41 @@ __global__ __launch_bounds__(256) void k_adj_E(AdjPtrs<T> p, Geom g) {
       const int ii = a == 0 ? nb.q[0] : i, jj = a == 1 ? nb.q[1] : j, kk = a == 2 ? nb.q[2] : k;
       hb[h] -= dbar(g, p, nb.lay[a], 0, c, a, nb.q[a], ii, jj, kk, wn) * idx;
     }
-  if (w0 || w1 || w2) {
+  if (!OOP && (w0 || w1 || w2)) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) p.E[c][id] = u[c];
   }
+  const AdjPtrs<T>& d = OOP ? o : p;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) p.H[c][id] = hv[c] + hb[c];
+  for (int c = 0; c < 3; ++c) d.H[c][id] = hv[c] + hb[c];
 }
 
 // Transposed H update.  Hb holds the adjoint of H^{n+1/2} (unchanged: identity
-// part); Eb gains the curl part.
-template <typename T>
-__global__ __launch_bounds__(256) void k_adj_H(AdjPtrs<T> p, Geom g) {
-  const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
-  if (i >= g.n[0] || j >= g.n[1]) return;
+// part); Eb gains the curl part.  Out of place, Hb is read from o (the E pass
+// wrote it there) and Eb from p, masked on the walls.
+template <typename T, bool OOP>
+__device__ __forceinline__ void adj_h_cell(const AdjPtrs<T>& p, const AdjPtrs<T>& o,
+                                           const Geom& g, int i, int j, int k) {
   const size_t id = (size_t)i + (size_t)g.n[0] * ((size_t)j + (size_t)g.n[1] * (size_t)k);
   const T dt = (T)g.dt, idx = (T)g.inv_dx;
   const int qo[3] = {i, j, k};
   const Nbrs nb = neighbours(g, i, j, k, id, -1);
+  const AdjPtrs<T>& hs = OOP ? o : p;
   T hv[3], hn[3][3], ev[3];
 #pragma unroll
-  for (int h = 0; h < 3; ++h) hv[h] = p.H[h][id];
+  for (int h = 0; h < 3; ++h) hv[h] = hs.H[h][id];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int h = 0; h < 3; ++h) hn[a][h] = h != a ? p.H[h][nb.id[a]] : T(0);
+    for (int h = 0; h < 3; ++h) hn[a][h] = h != a ? hs.H[h][nb.id[a]] : T(0);
 #pragma unroll
   for (int c = 0; c < 3; ++c) ev[c] = p.E[c][id];
+  if (OOP) {
+    const bool w0 = g.wall[0] && i == 0, w1 = g.wall[1] && j == 0, w2 = g.wall[2] && k == 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if ((c != 0 && w0) || (c != 1 && w1) || (c != 2 && w2)) ev[c] = T(0);
+  }
   T eb[3] = {T(0), T(0), T(0)};
 #pragma unroll
   for (int h = 0; h < 3; ++h)
@@ -207,8 +217,38 @@ __global__ __launch_bounds__(256) void k_adj_H(AdjPtrs<T> p, Geom g) {
       const int ii = a == 0 ? nb.q[0] : i, jj = a == 1 ? nb.q[1] : j, kk = a == 2 ? nb.q[2] : k;
       eb[e] += dbar(g, p, nb.lay[a], 1, h, a, nb.q[a], ii, jj, kk, wn) * idx;
     }
+  const AdjPtrs<T>& d = OOP ? o : p;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) p.E[c][id] = ev[c] + eb[c];
+  for (int c = 0; c < 3; ++c) d.E[c][id] = ev[c] + eb[c];
+}
+
+// Whole-grid transposed sweep in place: one thread per cell, 64 x 4 cells per
+// workgroup over (x, y), one z plane per grid row.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_E(AdjPtrs<T> p, Geom g) {
+  const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
+  if (i >= g.n[0] || j >= g.n[1]) return;
+  adj_e_cell<T, false>(p, p, g, i, j, k);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_H(AdjPtrs<T> p, Geom g) {
+  const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
+  if (i >= g.n[0] || j >= g.n[1]) return;
+  adj_h_cell<T, false>(p, p, g, i, j, k);
+}
+
+// The cells outside the fused transposed sweep's box (compact enumeration),
+// out of place: the E pass (E_PASS) writes o.H, then the H pass writes o.E.
+template <typename T, bool E_PASS>
+__global__ __launch_bounds__(256) void k_adj_shell(AdjPtrs<T> p, AdjPtrs<T> o, Geom g,
+                                                   ShellMap m) {
+  const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+  if ((long long)t >= m.total) return;
+  int i, j, k;
+  shell_cell(g, m, t, i, j, k);
+  if (E_PASS) adj_e_cell<T, true>(p, o, g, i, j, k);
+  else adj_h_cell<T, true>(p, o, g, i, j, k);
 }
 
 // Flux detector: part 0 adds dt dF/dE^{n+1} and dt dF/dH^{n+1/2}, part 1 adds
@@ -402,10 +442,32 @@ static hipError_t launch_adj_sweep(const AdjSweep<T>& a, const Geom& g, hipStrea
   }
   p.epsinv = a.epsinv;
   p.tab = a.tab;
-  if (g.n[2] > 65535) return hipErrorInvalidValue;  // one grid row per z plane
-  const dim3 grid((g.n[0] + 63) / 64, (g.n[1] + 3) / 4, g.n[2]), block(64, 4, 1);
   p.psi_in = a.psi[0];
   p.psi_out = a.psi[1];
+  if (a.Eo[0]) {
+    // fused transposed sweep on its box, then the shell cells, out of place
+    const Box box = adj_interior_box(g);
+    hipError_t e;
+    if constexpr (sizeof(T) == 4) e = adj_fused_f32(a, g, box, st);
+    else e = adj_fused_f64(a, g, box, st);
+    if (e != hipSuccess) return e;
+    const ShellMap m = shell_map(g, box);
+    if (m.total == 0) return hipSuccess;
+    if (m.total >= 0x7fffff00LL) return hipErrorInvalidValue;  // 32-bit cell index
+    AdjPtrs<T> o = p;
+    for (int c = 0; c < 3; ++c) {
+      o.E[c] = a.Eo[c];
+      o.H[c] = a.Ho[c];
+    }
+    const unsigned blocks = (unsigned)((m.total + 255) / 256);
+    hipLaunchKernelGGL((k_adj_shell<T, true>), dim3(blocks), dim3(256), 0, st, p, o, g, m);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_adj_shell<T, false>), dim3(blocks), dim3(256), 0, st, p, o, g, m);
+    return hipGetLastError();
+  }
+  if (g.n[2] > 65535) return hipErrorInvalidValue;  // one grid row per z plane
+  const dim3 grid((g.n[0] + 63) / 64, (g.n[1] + 3) / 4, g.n[2]), block(64, 4, 1);
   hipLaunchKernelGGL(k_adj_E<T>, grid, block, 0, st, p, g);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -1,0 +1,305 @@
+// Fused transposed sweep: the reverse of one Yee step (see adjoint.hip) in one
+// pass over a box of cells clear of every CPML layer.
+//
+// With u = Eb masked on the metallic walls (the adjoint of E^{n+1}), the
+// transposed E update followed by the transposed H update is, away from the
+// layers,
+//   W    = dt eps^-1 u                       (per cell and component)
+//   Hb' = Hb + curl_f W / dx                 (forward differences, as H^{n+1/2})
+//   Eb' = u - dt curl_b Hb' / dx             (backward differences, as E^{n+1})
+// the same leapfrog shape as the forward step, so this kernel marches z-chunks
+// of 64 x TY tiles like the forward fused sweep: W of plane k+1 is staged in
+// LDS with a one-cell ring, Hb' of plane k is computed on the tile plus the
+// low-x / low-y halo that the backward curl needs (recomputed, not read), and
+// Eb' of plane k follows in the same pass.  Eb and Hb are read from one pair of
+// buffers and written to the other.
+//
+// The stretching of a CPML layer acts, in the reverse step, at the cell whose
+// forward update used the derivative: the transposed E update needs the psi
+// adjoint at the +1 neighbours as well.  The box therefore keeps a one-cell
+// margin above the low layers (the recomputed halo) and one below the high
+// layers (the staged +1 neighbours); the cells outside it are updated by the
+// shell passes in adjoint.hip.
+#include "mlk_internal.h"
+#include "yee_common.h"
+
+namespace mlk {
+
+template <typename T>
+struct AdjFused {
+  const T* E[3];  // adjoint of E^{n+1}
+  const T* H[3];  // adjoint of H^{n+1/2}
+  T* Eo[3];       // adjoint of E^n
+  T* Ho[3];       // adjoint of H^{n+1/2} after the transposed E update
+  const T* epsinv;
+};
+
+namespace {
+
+// Loads of one staged slot (Eb and 1/eps), unconditional from a safe address.
+template <typename T>
+__device__ __forceinline__ bool load4(const AdjFused<T>& p, Col col, Col pl, T v[3], T& ei) {
+  const bool ok = col.valid && pl.valid;
+  const size_t id = ok ? col.off + pl.off : 0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) v[c] = p.E[c][id];
+  ei = p.epsinv[id];
+  return ok;
+}
+
+// Wall mask of cell (x, y, z): component c is zero on the wall planes (index 0
+// of a metallic axis other than c) through the cell.
+__device__ __forceinline__ bool wall_masked(const Geom& g, int c, int x, int y, int z) {
+  return (c != 0 && g.wall[0] && x == 0) || (c != 1 && g.wall[1] && y == 0) ||
+         (c != 2 && g.wall[2] && z == 0);
+}
+
+}  // namespace
+
+template <typename T, int TY>
+__global__ __launch_bounds__(64 * TY) void k_adj_fused(AdjFused<T> p, Geom g, Box box, int kz,
+                                                       int ntx, int nty, int nblocks) {
+  constexpr int EW = 66, EH = TY + 2;   // W plane in LDS: x in [-1, 64], y in [-1, TY]
+  constexpr int HW = 65, HH = TY + 1;   // Hb' plane in LDS: x in [-1, 63], y in [-1, TY-1]
+  constexpr int NHALO = 2 * EW + 2 * TY;
+  static_assert(64 * TY >= NHALO, "one thread per ring slot of the staged plane");
+  __shared__ T wL[2][3][EH * EW];
+  __shared__ T hL[3][HH * HW];
+
+  const int bid = xcd_block(blockIdx.x, nblocks);
+  const int tile_x = bid % ntx, tile_y = (bid / ntx) % nty, chunk = bid / (ntx * nty);
+  // x tiles start on a 128-byte boundary at or below the box; cells below
+  // box.lo[0] are computed too and overwritten by the shell passes
+  const int x0 = (box.lo[0] & ~31) + tile_x * 64, y0 = box.lo[1] + tile_y * TY;
+  const int k0 = box.lo[2] + chunk * kz, k1 = min(k0 + kz, box.hi[2]);
+
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6, tid = threadIdx.x;
+  const int i = x0 + tx, j = y0 + ty;
+  const bool own = i < box.hi[0] && j < box.hi[1];
+  const T dt = (T)g.dt, idx = (T)g.inv_dx;
+  const size_t plane_sz = (size_t)g.n[0] * g.n[1];
+
+  const Col ocol = column(g, i, j);
+  const int oslot = (ty + 1) * EW + tx + 1;
+  int rslot = 0, rx = 0, ry = 0;
+  Col rcol{0, false};
+  if (tid < NHALO) {
+    int xs, ys;
+    if (tid < EW) {
+      xs = tid - 1;
+      ys = -1;
+    } else if (tid < 2 * EW) {
+      xs = tid - EW - 1;
+      ys = TY;
+    } else {
+      const int c2 = tid - 2 * EW;
+      ys = c2 >> 1;
+      xs = (c2 & 1) ? 64 : -1;
+    }
+    rslot = (ys + 1) * EW + xs + 1;
+    rx = x0 + xs;
+    ry = y0 + ys;
+    rcol = column(g, rx, ry);
+  }
+  const bool hx_on = tx == 0 && j < box.hi[1] && (x0 > 0 || g.periodic[0]);
+  const int ih = x0 > 0 ? x0 - 1 : g.n[0] - 1;
+  const bool hy_on = ty == 0 && i < box.hi[0] && (y0 > 0 || g.periodic[1]);
+  const int jh = y0 > 0 ? y0 - 1 : g.n[1] - 1;
+  const size_t own_off = own ? (size_t)i + (size_t)g.n[0] * j : 0;
+  const size_t hx_off = hx_on ? (size_t)ih + (size_t)g.n[0] * j : 0;
+  const size_t hy_off = hy_on ? (size_t)i + (size_t)g.n[0] * jh : 0;
+
+  auto W_at = [&](int q, int c, int xs, int ys) -> T { return wL[q][c][(ys + 1) * EW + xs + 1]; };
+  // W = dt eps^-1 u of a staged slot (zero outside the closure); the own slot's
+  // u is returned in u
+  auto put = [&](int q, int z, const T o[3], T oe, bool ov, T u[3], T w[3], const T r[3], T re,
+                 bool rv) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      u[c] = (ov && !wall_masked(g, c, i, j, z)) ? o[c] : T(0);
+      w[c] = dt * oe * u[c];
+      wL[q][c][oslot] = w[c];
+    }
+    if (tid < NHALO) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        wL[q][c][rslot] = (rv && !wall_masked(g, c, rx, ry, z)) ? dt * re * r[c] : T(0);
+    }
+  };
+
+  T wk[3], wk1[3], uk[3], uk1[3], hpx = T(0), hpy = T(0);
+  T nEo[3], nEr[3] = {T(0), T(0), T(0)}, nEoe = T(0), nEre = T(0);
+  bool nEov = false, nErv = false;
+
+  // prologue: Hb' of plane k0-1 on the own column (x and y components)
+  {
+    const int km = k0 - 1;
+    const int pm = (km + 2) & 1, p0 = k0 & 1;
+    T em[3], emr[3], ek[3], ekr[3], eme, emre, eke, ekre, um[3], wm[3];
+    const Col plm = plane(g, km), pl0 = plane(g, k0);
+    const bool emv = load4(p, ocol, plm, em, eme), ekv = load4(p, ocol, pl0, ek, eke);
+    const bool emrv = load4(p, rcol, plm, emr, emre), ekrv = load4(p, rcol, pl0, ekr, ekre);
+    const int kmw = km < 0 ? km + g.n[2] : km;
+    put(pm, kmw, em, eme, emv, um, wm, emr, emre, emrv);
+    put(p0, k0, ek, eke, ekv, uk, wk, ekr, ekre, ekrv);
+    lds_barrier();
+    if (own && plm.valid) {
+      const size_t id = own_off + plm.off;
+      const T dWz_dy = W_at(pm, 2, tx, ty + 1) - wm[2];
+      const T dWy_dz = wk[1] - wm[1];
+      const T dWx_dz = wk[0] - wm[0];
+      const T dWz_dx = W_at(pm, 2, tx + 1, ty) - wm[2];
+      hpx = p.H[0][id] + idx * (dWz_dy - dWy_dz);
+      hpy = p.H[1][id] + idx * (dWx_dz - dWz_dx);
+    }
+    const Col pl1 = plane(g, k0 + 1);
+    nEov = load4(p, ocol, pl1, nEo, nEoe);
+    nErv = load4(p, rcol, pl1, nEr, nEre);
+    lds_barrier();
+  }
+
+  // prefetched Hb of plane k (own) and of the low-x / low-y halo cells
+  T nH[3] = {T(0), T(0), T(0)}, nHx[2] = {T(0), T(0)}, nHy[2] = {T(0), T(0)};
+  auto prefetch_h = [&](int k) {
+    const size_t po = (size_t)min(k, g.n[2] - 1) * plane_sz;
+    nH[0] = p.H[0][own_off + po];
+    nH[1] = p.H[1][own_off + po];
+    nH[2] = p.H[2][own_off + po];
+    nHx[0] = p.H[1][hx_off + po];
+    nHx[1] = p.H[2][hx_off + po];
+    nHy[0] = p.H[0][hy_off + po];
+    nHy[1] = p.H[2][hy_off + po];
+  };
+  prefetch_h(k0);
+
+  for (int k = k0; k < k1; ++k) {
+    const int p0 = k & 1, p1 = (k + 1) & 1;
+    const int kn = k + 1 < g.n[2] ? k + 1 : k + 1 - g.n[2];
+    put(p1, kn, nEo, nEoe, nEov, uk1, wk1, nEr, nEre, nErv);
+    T hx = nH[0], hy = nH[1], hz = nH[2];
+    const T hxh_y = nHx[0], hxh_z = nHx[1], hyh_x = nHy[0], hyh_z = nHy[1];
+    if (k + 1 < k1) {  // the chunk's last plane needs neither W(k+2) nor Hb(k+1)
+      const Col pl2 = plane(g, k + 2);
+      nEov = load4(p, ocol, pl2, nEo, nEoe);
+      nErv = load4(p, rcol, pl2, nEr, nEre);
+      prefetch_h(k + 1);
+    }
+    lds_barrier();
+
+    const size_t id = own_off + (size_t)k * plane_sz;
+    // Hb' of plane k on the own cell: Hb + curl_f W / dx
+    if (own) {
+      const T dWz_dy = W_at(p0, 2, tx, ty + 1) - wk[2];
+      const T dWy_dz = wk1[1] - wk[1];
+      const T dWx_dz = wk1[0] - wk[0];
+      const T dWz_dx = W_at(p0, 2, tx + 1, ty) - wk[2];
+      const T dWy_dx = W_at(p0, 1, tx + 1, ty) - wk[1];
+      const T dWx_dy = W_at(p0, 0, tx, ty + 1) - wk[0];
+      hx += idx * (dWz_dy - dWy_dz);
+      hy += idx * (dWx_dz - dWz_dx);
+      hz += idx * (dWy_dx - dWx_dy);
+      p.Ho[0][id] = hx;
+      p.Ho[1][id] = hy;
+      p.Ho[2][id] = hz;
+    }
+    hL[0][(ty + 1) * HW + tx + 1] = hx;
+    hL[1][(ty + 1) * HW + tx + 1] = hy;
+    hL[2][(ty + 1) * HW + tx + 1] = hz;
+    // halo Hb' at x0-1 (y and z components) for the own row, by lane 0 of each wave
+    if (tx == 0) {
+      T hyh = T(0), hzh = T(0);
+      if (hx_on) {
+        const T dWx_dz = W_at(p1, 0, -1, ty) - W_at(p0, 0, -1, ty);
+        const T dWz_dx = W_at(p0, 2, 0, ty) - W_at(p0, 2, -1, ty);
+        const T dWy_dx = W_at(p0, 1, 0, ty) - W_at(p0, 1, -1, ty);
+        const T dWx_dy = W_at(p0, 0, -1, ty + 1) - W_at(p0, 0, -1, ty);
+        hyh = hxh_y + idx * (dWx_dz - dWz_dx);
+        hzh = hxh_z + idx * (dWy_dx - dWx_dy);
+      }
+      hL[1][(ty + 1) * HW] = hyh;
+      hL[2][(ty + 1) * HW] = hzh;
+    }
+    // halo Hb' at y0-1 (x and z components) for the own column, by the first wave
+    if (ty == 0) {
+      T hxh = T(0), hzh = T(0);
+      if (hy_on) {
+        const T dWz_dy = W_at(p0, 2, tx, 0) - W_at(p0, 2, tx, -1);
+        const T dWy_dz = W_at(p1, 1, tx, -1) - W_at(p0, 1, tx, -1);
+        const T dWy_dx = W_at(p0, 1, tx + 1, -1) - W_at(p0, 1, tx, -1);
+        const T dWx_dy = W_at(p0, 0, tx, 0) - W_at(p0, 0, tx, -1);
+        hxh = hyh_x + idx * (dWz_dy - dWy_dz);
+        hzh = hyh_z + idx * (dWy_dx - dWx_dy);
+      }
+      hL[0][tx + 1] = hxh;
+      hL[2][tx + 1] = hzh;
+    }
+    lds_barrier();
+
+    // Eb' of plane k on the own cell: u - dt curl_b Hb' / dx
+    if (own) {
+      const T dHz_dy = hz - hL[2][ty * HW + tx + 1];
+      const T dHy_dz = hy - hpy;
+      const T dHx_dz = hx - hpx;
+      const T dHz_dx = hz - hL[2][(ty + 1) * HW + tx];
+      const T dHy_dx = hy - hL[1][(ty + 1) * HW + tx];
+      const T dHx_dy = hx - hL[0][ty * HW + tx + 1];
+      const T cf = -dt * idx;
+      p.Eo[0][id] = uk[0] + cf * (dHz_dy - dHy_dz);
+      p.Eo[1][id] = uk[1] + cf * (dHx_dz - dHz_dx);
+      p.Eo[2][id] = uk[2] + cf * (dHy_dx - dHx_dy);
+    }
+    hpx = hx;
+    hpy = hy;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      wk[c] = wk1[c];
+      uk[c] = uk1[c];
+    }
+  }
+}
+
+// Box of the fused transposed sweep: per axis, one cell of margin above the low
+// CPML layers and one below the high layers (none on an axis without layers on
+// that side).
+Box adj_interior_box(const Geom& g) {
+  Box b{};
+  for (int a = 0; a < 3; ++a) {
+    b.lo[a] = g.nlo[a] > 0 ? g.nlo[a] + 1 : 0;
+    b.hi[a] = g.nhi[a] > 0 ? g.n[a] - g.nhi[a] - 1 : g.n[a];
+    if (b.hi[a] < b.lo[a]) b.hi[a] = b.lo[a];
+  }
+  return b;
+}
+
+template <typename T>
+static hipError_t launch_adj_fused(const AdjSweep<T>& a, const Geom& g, const Box& box,
+                                   hipStream_t st) {
+  constexpr int TY = 4;
+  const int kz = a.kz > 0 ? a.kz : 16;
+  const int ex = box.hi[0] - box.lo[0], ey = box.hi[1] - box.lo[1], ez = box.hi[2] - box.lo[2];
+  if (ex <= 0 || ey <= 0 || ez <= 0) return hipSuccess;
+  AdjFused<T> p{};
+  for (int c = 0; c < 3; ++c) {
+    p.E[c] = a.E[c];
+    p.H[c] = a.H[c];
+    p.Eo[c] = a.Eo[c];
+    p.Ho[c] = a.Ho[c];
+  }
+  p.epsinv = a.epsinv;
+  const int ntx = (box.hi[0] - (box.lo[0] & ~31) + 63) / 64, nty = (ey + TY - 1) / TY;
+  const int nblocks = ntx * nty * ((ez + kz - 1) / kz);
+  hipLaunchKernelGGL((k_adj_fused<T, TY>), dim3(nblocks), dim3(64 * TY), 0, st, p, g, box, kz,
+                     ntx, nty, nblocks);
+  return hipGetLastError();
+}
+
+hipError_t adj_fused_f32(const AdjSweep<float>& a, const Geom& g, const Box& box,
+                         hipStream_t st) {
+  return launch_adj_fused<float>(a, g, box, st);
+}
+hipError_t adj_fused_f64(const AdjSweep<double>& a, const Geom& g, const Box& box,
+                         hipStream_t st) {
+  return launch_adj_fused<double>(a, g, box, st);
+}
+
+}  // namespace mlk

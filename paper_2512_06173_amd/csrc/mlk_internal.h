@@ -358,6 +358,11 @@ struct AdjSweep {
   const T* epsinv;
   const T* tab;
   T* psi[2];
+  // out of place (fused transposed sweep plus shell passes): the updated
+  // adjoint fields go here; null: whole-grid update in place
+  T* Eo[3];
+  T* Ho[3];
+  int kz;  // z planes per workgroup of the fused transposed sweep
 };
 
 }  // namespace mlk

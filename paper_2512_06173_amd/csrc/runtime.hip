@@ -1497,14 +1497,17 @@ mlk_status adjoint_run(mlk_sim* s, int kind, const double* weights, int64_t T_st
   }
   *value = J;
 
-  // adjoint state
-  DevBuf<T> Eb[3], Hb[3], psib[2];
-  for (int c = 0; c < 3; ++c) {
-    HIPCHK(Eb[c].alloc(nc));
-    HIPCHK(Hb[c].alloc(nc));
-    HIPCHK(hipMemsetAsync(Eb[c].p, 0, nc * sizeof(T), st));
-    HIPCHK(hipMemsetAsync(Hb[c].p, 0, nc * sizeof(T), st));
-  }
+  // adjoint state; a fused-sweep sim takes the transposed sweep out of place
+  // (fused box plus shell), with two sets of adjoint fields used in turn
+  const bool oop = s->desc.sweep == MLK_SWEEP_FUSED;
+  DevBuf<T> Eb[2][3], Hb[2][3], psib[2];
+  for (int q = 0; q < (oop ? 2 : 1); ++q)
+    for (int c = 0; c < 3; ++c) {
+      HIPCHK(Eb[q][c].alloc(nc));
+      HIPCHK(Hb[q][c].alloc(nc));
+      HIPCHK(hipMemsetAsync(Eb[q][c].p, 0, nc * sizeof(T), st));
+      HIPCHK(hipMemsetAsync(Hb[q][c].p, 0, nc * sizeof(T), st));
+    }
   const size_t npsi = psi_total(s->g);
   for (int q = 0; q < 2; ++q) {
     HIPCHK(psib[q].alloc(npsi));
@@ -1537,16 +1540,23 @@ mlk_status adjoint_run(mlk_sim* s, int kind, const double* weights, int64_t T_st
   const BinPtrs bins = bin_ptrs(s);
   const TlsPtrs tls = tls_ptrs(s);
   AdjSweep<T> adj{};
-  for (int c = 0; c < 3; ++c) {
-    adj.E[c] = Eb[c].p;
-    adj.H[c] = Hb[c].p;
-  }
+  FieldPtrs<T> fb{};  // the adjoint of E as a field, for the gather and the scatter
+  int cur = 0;        // the set holding the current adjoint fields
+  auto bind = [&]() {
+    for (int c = 0; c < 3; ++c) {
+      adj.E[c] = Eb[cur][c].p;
+      adj.H[c] = Hb[cur][c].p;
+      adj.Eo[c] = oop ? Eb[cur ^ 1][c].p : nullptr;
+      adj.Ho[c] = oop ? Hb[cur ^ 1][c].p : nullptr;
+      fb.E[c] = Eb[cur][c].p;
+    }
+  };
+  bind();
   adj.epsinv = (const T*)s->epsinv;
   adj.tab = (const T*)s->tab;
   adj.psi[0] = psib[0].p;
   adj.psi[1] = psib[1].p;
-  FieldPtrs<T> fb{};  // the adjoint of E as a field, for the gather and the scatter
-  for (int c = 0; c < 3; ++c) fb.E[c] = Eb[c].p;
+  adj.kz = 16;
   fb.epsinv = (T*)s->epsinv;
   const double mub_scale = -s->g.dt * s->g.inv_dx * s->g.inv_dx * s->g.inv_dx;
   const FluxPlane* fpp = s->fp.on ? &s->fp : nullptr;
@@ -1591,6 +1601,10 @@ mlk_status adjoint_run(mlk_sim* s, int kind, const double* weights, int64_t T_st
       if constexpr (f32) HIPCHK(adj_sweep_f32(adj, s->g, st));
       else HIPCHK(adj_sweep_f64(adj, s->g, st));
       std::swap(adj.psi[0], adj.psi[1]);
+      if (oop) {
+        cur ^= 1;
+        bind();
+      }
       if (nt) {
         HIPCHK(adj_tls(tls, s->g.dt, mub_scale, ts.p + (size_t)3 * nt * q,
                        tg.p + (size_t)3 * M * q, mub.p, sb.p, gd.p, etb.p, st));

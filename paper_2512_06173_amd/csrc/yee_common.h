@@ -61,4 +61,86 @@ __device__ __forceinline__ double pulse_value(const Source& s, double t) {
   return s.amp * cos(s.omega * u) * exp(-u * u / (2.0 * s.tau * s.tau));
 }
 
+// Column (x, y) of the grid seen through the closure rules: periodic axes
+// wrap, beyond a metallic wall the value is zero (valid = false).
+struct Col {
+  size_t off;  // x + nx*y of the (wrapped) column
+  bool valid;
+};
+
+__device__ __forceinline__ int wrap_mod(int q, int n) {
+  const int r = q % n;
+  return r < 0 ? r + n : r;
+}
+
+__device__ __forceinline__ Col column(const Geom& g, int x, int y) {
+  bool ok = true;
+  if (x < 0 || x >= g.n[0]) {
+    ok = ok && g.periodic[0];
+    x = wrap_mod(x, g.n[0]);
+  }
+  if (y < 0 || y >= g.n[1]) {
+    ok = ok && g.periodic[1];
+    y = wrap_mod(y, g.n[1]);
+  }
+  Col c;
+  c.valid = ok;
+  c.off = ok ? (size_t)x + (size_t)g.n[0] * (size_t)y : 0;
+  return c;
+}
+
+// Offset of plane z with the closure rule along z (valid = false: zero plane).
+__device__ __forceinline__ Col plane(const Geom& g, int z) {
+  Col c;
+  c.valid = true;
+  if (z < 0 || z >= g.n[2]) {
+    c.valid = g.periodic[2] != 0;
+    z = wrap_mod(z, g.n[2]);
+  }
+  c.off = c.valid ? (size_t)z * (size_t)g.n[0] * (size_t)g.n[1] : 0;
+  return c;
+}
+
+// Loads of one staged slot are issued without any branch or select on the
+// loaded value (an invalid slot reads index 0, a safe address, and is zeroed
+// when it is written to LDS), so prefetched loads stay in flight until used.
+template <typename T>
+__device__ __forceinline__ bool load3(const FieldPtrs<T>& f, Col col, Col pl, T v[3]) {
+  const bool ok = col.valid && pl.valid;
+  const size_t id = ok ? col.off + pl.off : 0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) v[c] = f.E[c][id];
+  return ok;
+}
+
+// Cell (i, j, k) of entry t of the compact CPML-shell enumeration (see ShellMap).
+__device__ __forceinline__ void shell_cell(const Geom& g, const ShellMap& m, unsigned t, int& i,
+                                           int& j, int& k) {
+  const unsigned nx = (unsigned)g.n[0];
+  if ((long long)t < m.nslab) {
+    const unsigned plane = nx * (unsigned)g.n[1];
+    const unsigned p = div_by(t, plane, m.inv_plane);
+    const unsigned r = t - p * plane;
+    k = (int)p < m.nzlo ? (int)p : m.in.hi[2] + ((int)p - m.nzlo);
+    j = (int)div_by(r, nx, m.inv_nx);
+    i = (int)(r - (unsigned)j * nx);
+    return;
+  }
+  const unsigned u = t - (unsigned)m.nslab;
+  const unsigned p = div_by(u, (unsigned)m.per_plane, m.inv_per_plane);
+  unsigned r = u - p * (unsigned)m.per_plane;
+  k = m.in.lo[2] + (int)p;
+  if ((int)r < m.full_cells) {
+    const int row = (int)div_by(r, nx, m.inv_nx);
+    i = (int)(r - (unsigned)row * nx);
+    j = row < m.ylo_rows ? row : m.in.hi[1] + (row - m.ylo_rows);
+    return;
+  }
+  r -= (unsigned)m.full_cells;
+  const int row = (int)div_by(r, (unsigned)m.strip, m.inv_strip);
+  const int c = (int)r - row * m.strip;
+  j = m.in.lo[1] + row;
+  i = c < m.in.lo[0] ? c : m.in.hi[0] + (c - m.in.lo[0]);
+}
+
 }  // namespace mlk

@@ -30,62 +30,6 @@
 
 namespace mlk {
 
-namespace {
-
-}  // namespace
-
-// Column (x, y) of the grid seen through the closure rules: periodic axes
-// wrap, beyond a metallic wall the value is zero (valid = false).
-struct Col {
-  size_t off;  // x + nx*y of the (wrapped) column
-  bool valid;
-};
-
-__device__ __forceinline__ int wrap_mod(int q, int n) {
-  const int r = q % n;
-  return r < 0 ? r + n : r;
-}
-
-__device__ __forceinline__ Col column(const Geom& g, int x, int y) {
-  bool ok = true;
-  if (x < 0 || x >= g.n[0]) {
-    ok = ok && g.periodic[0];
-    x = wrap_mod(x, g.n[0]);
-  }
-  if (y < 0 || y >= g.n[1]) {
-    ok = ok && g.periodic[1];
-    y = wrap_mod(y, g.n[1]);
-  }
-  Col c;
-  c.valid = ok;
-  c.off = ok ? (size_t)x + (size_t)g.n[0] * (size_t)y : 0;
-  return c;
-}
-
-// Offset of plane z with the closure rule along z (valid = false: zero plane).
-__device__ __forceinline__ Col plane(const Geom& g, int z) {
-  Col c;
-  c.valid = true;
-  if (z < 0 || z >= g.n[2]) {
-    c.valid = g.periodic[2] != 0;
-    z = wrap_mod(z, g.n[2]);
-  }
-  c.off = c.valid ? (size_t)z * (size_t)g.n[0] * (size_t)g.n[1] : 0;
-  return c;
-}
-
-// Loads of one staged slot are issued without any branch or select on the
-// loaded value (an invalid slot reads index 0, a safe address, and is zeroed
-// when it is written to LDS), so prefetched loads stay in flight until used.
-template <typename T>
-__device__ __forceinline__ bool load3(const FieldPtrs<T>& f, Col col, Col pl, T v[3]) {
-  const bool ok = col.valid && pl.valid;
-  const size_t id = ok ? col.off + pl.off : 0;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) v[c] = f.E[c][id];
-  return ok;
-}
-
 template <typename T, int TY>
 __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtrs<T>& b,
                                            const Geom& g, const Box& box, int kz, int ntx,

@@ -84,35 +84,6 @@ __global__ __launch_bounds__(256) void k_update_box(FieldPtrs<T> in, FieldPtrs<T
   else update_e_cell(in, out, g, i, j, k);
 }
 
-__device__ __forceinline__ void shell_cell(const Geom& g, const ShellMap& m, unsigned t, int& i,
-                                           int& j, int& k) {
-  const unsigned nx = (unsigned)g.n[0];
-  if ((long long)t < m.nslab) {
-    const unsigned plane = nx * (unsigned)g.n[1];
-    const unsigned p = div_by(t, plane, m.inv_plane);
-    const unsigned r = t - p * plane;
-    k = (int)p < m.nzlo ? (int)p : m.in.hi[2] + ((int)p - m.nzlo);
-    j = (int)div_by(r, nx, m.inv_nx);
-    i = (int)(r - (unsigned)j * nx);
-    return;
-  }
-  const unsigned u = t - (unsigned)m.nslab;
-  const unsigned p = div_by(u, (unsigned)m.per_plane, m.inv_per_plane);
-  unsigned r = u - p * (unsigned)m.per_plane;
-  k = m.in.lo[2] + (int)p;
-  if ((int)r < m.full_cells) {
-    const int row = (int)div_by(r, nx, m.inv_nx);
-    i = (int)(r - (unsigned)row * nx);
-    j = row < m.ylo_rows ? row : m.in.hi[1] + (row - m.ylo_rows);
-    return;
-  }
-  r -= (unsigned)m.full_cells;
-  const int row = (int)div_by(r, (unsigned)m.strip, m.inv_strip);
-  const int c = (int)r - row * m.strip;
-  j = m.in.lo[1] + row;
-  i = c < m.in.lo[0] ? c : m.in.hi[0] + (c - m.in.lo[0]);
-}
-
 template <typename T, bool H>
 __global__ __launch_bounds__(256) void k_update_shell(FieldPtrs<T> in, FieldPtrs<T> out, Geom g,
                                                       ShellMap m) {

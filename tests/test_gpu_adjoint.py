@@ -55,6 +55,39 @@ def test_adjoint_matches_oracle_fp64(objective, sweep):
     assert rel(ggd, ogd) <= 1e-10
 
 
+@pytest.mark.parametrize("bc, cpml", [
+    (("periodic", "periodic", "pec", "pec", "cpml", "cpml"), (0, 0, 0, 0, 5, 6)),
+    (("periodic",) * 6, (0,) * 6),
+    (("cpml", "pec", "pec", "cpml", "cpml", "cpml"), (7, 0, 0, 6, 5, 4)),
+])
+@pytest.mark.parametrize("sweep", ["fused", "plain"])
+def test_adjoint_closures_tiles_and_chunks_fp64(bc, cpml, sweep):
+    """70 x 26 x 40 (two x tiles, one ragged; several z chunks) with periodic, metallic
+    and uneven CPML faces: the fused transposed sweep (box plus shell passes) and the
+    whole-grid one against the oracle adjoint, flux objective."""
+    rng = np.random.default_rng(11)
+    shape = (70, 26, 40)
+    M = 5
+    pos = np.column_stack([rng.uniform(30, 40, M), rng.uniform(11, 15, M),
+                           rng.uniform(17, 23, M)])
+    tls = W.TLSSet(pos=pos, sigma=np.full(M, 0.8), gamma=np.ones(M),
+                   omega0=rng.uniform(0.45, 0.55, M), dipole=0.6 * rng.standard_normal((M, 3)),
+                   rho0=np.tile([0.5, 0.5, 0.0], (M, 1)))
+    eps = rng.uniform(1.0, 2.0, (shape[2], shape[1], shape[0]))
+    w = W.Workload(name="adj_closures", shape=shape, bc=bc, cpml=cpml, eps=eps, tls=tls,
+                   point_sources=[W.PointSource(1, (33, 12, 19), 1.0, 0.5, 2.0, 6.0)],
+                   flux=(2, 29), steps=40, precision="fp64")
+    box = ((30, 10, 17), (37, 16, 24))
+    ov, oge, ogd = build_oracle(w).adjoint("flux", w.steps, box)
+    sim = mlk().from_workload(w, sweep=sweep)
+    gv, gge, ggd = sim.adjoint("flux", w.steps, box, checkpoint_every=15)
+    say(f"[adjoint closures] {bc} {sweep}: value {abs(gv - ov) / abs(ov):.2e}, "
+        f"eps {rel(gge, oge):.2e}, dipole {rel(ggd, ogd):.2e}")
+    assert abs(gv - ov) <= 1e-12 * abs(ov)
+    assert rel(gge, oge) <= 1e-10
+    assert rel(ggd, ogd) <= 1e-10
+
+
 @pytest.mark.parametrize("objective", ["flux", "population"])
 def test_adjoint_fp32_fields(objective):
     w = problem("fp32")
