@@ -59,6 +59,20 @@ def parse():
     return p.parse_args()
 
 
+def box_memberships(lo, hi, shape, cpml):
+    """Sum over axes of the cells of the box [lo, hi) lying in that axis's CPML layers."""
+    tot = 0
+    for a in range(3):
+        n, nlo, nhi = shape[a], cpml[2 * a], cpml[2 * a + 1]
+        in_layers = sum(1 for q in range(lo[a], hi[a]) if q < nlo or q >= n - nhi)
+        other = 1
+        for b in range(3):
+            if b != a:
+                other *= hi[b] - lo[b]
+        tot += in_layers * other
+    return tot
+
+
 def layer_memberships(shape, cpml):
     """Sum over axes of the cells lying in that axis's CPML layers."""
     nx, ny, nz = shape
@@ -260,9 +274,9 @@ def main():
     sweep_ms, sweep_n = phases["sweep"]
     lo, hi = box
     launch_cells = (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2])
-    # cells of the launch inside the x CPML layers also read and write 8 psi words
-    xlayer_cells = (w.cpml[0] + w.cpml[1]) * (hi[1] - lo[1]) * (hi[2] - lo[2])
-    launch_bytes = launch_cells * CELL_WORDS * esz + xlayer_cells * PSI_WORDS * esz
+    # a cell of the launch also reads and writes 8 psi words per CPML layer it lies in
+    launch_memb = box_memberships(lo, hi, w.shape, w.cpml)
+    launch_bytes = launch_cells * CELL_WORDS * esz + launch_memb * PSI_WORDS * esz
     t_launch = sweep_ms / sweep_n * 1e-3
     achieved = launch_bytes / t_launch / 1e9
     traffic = traffic_from_profile(launch_cells)

@@ -621,27 +621,29 @@ hipError_t collect_marks(mlk_sim* s) {
   return hipSuccess;
 }
 
-// Interior box of the fused sweep: the y and z positions whose own update and
-// recomputed halo avoid the CPML layers of those axes (one cell of margin
-// above the low layers), and every x column, the fused kernel stretching x
-// derivatives itself, provided the low-x halo column of each 64-wide tile
-// (x = 64t - 1, t >= 1) lies outside the x layers and the x psi arrays index
-// in 32 bits; otherwise x is limited like y and z.  The cells outside the box
-// form the CPML shell.
-Box interior_box(const Geom& g) {
+// Box of the fused sweep.  With FP32 fields (layers): the whole grid, the
+// kernel stretching the derivatives of cells in the CPML layers itself; with
+// FP64 fields the y and z extent stops one cell of margin above the low layers
+// and at the high layers (the FP64 kernel carries the x layers only, keeping
+// its registers within occupancy), the plain passes updating the rest.  In both
+// the x extent is every column provided the low-x halo column of each 64-wide
+// tile (x = 64t - 1, t >= 1) lies outside the x layers and the x psi arrays
+// index in 32 bits; otherwise x is limited like y and z.  The y and z psi
+// arrays must index in 32 bits too for a full y and z extent.  The cells
+// outside the box form the CPML shell.
+Box interior_box(const Geom& g, bool layers) {
   Box inner{};
   const int n = g.n[0], ntx = (n + 63) / 64;
+  const double plane = (double)g.n[0] * g.n[1] * g.n[2];
   const bool x_full = !has_cpml(g, 0) ||
                       (g.nlo[0] <= 63 && 64 * (ntx - 1) <= n - g.nhi[0] &&
                        (double)(g.nlo[0] + g.nhi[0]) * g.n[1] * g.n[2] < 4294967296.0);
-  for (int a = x_full ? 1 : 0; a < 3; ++a) {
-    inner.lo[a] = g.nlo[a] > 0 ? g.nlo[a] + 1 : 0;
-    inner.hi[a] = g.n[a] - g.nhi[a];
-    if (inner.hi[a] < inner.lo[a]) inner.hi[a] = inner.lo[a];
-  }
-  if (x_full) {
-    inner.lo[0] = 0;
-    inner.hi[0] = n;
+  const bool yz_full = layers && 4.0 * plane * (g.nlo[1] + g.nhi[1]) / g.n[1] < 4294967296.0 &&
+                       4.0 * plane * (g.nlo[2] + g.nhi[2]) / g.n[2] < 4294967296.0;
+  for (int a = 0; a < 3; ++a) {
+    const bool full = a == 0 ? x_full : yz_full;
+    inner.lo[a] = full ? 0 : (g.nlo[a] > 0 ? g.nlo[a] + 1 : 0);
+    inner.hi[a] = full ? g.n[a] : std::max(inner.lo[a], g.n[a] - g.nhi[a]);
   }
   return inner;
 }
@@ -652,7 +654,7 @@ mlk_status sweep(mlk_sim* s) {
   const FieldPtrs<T> f = field_ptrs<T>(s);
   if (s->desc.sweep == MLK_SWEEP_FUSED) {
     const FieldPtrs<T> nf = spare_ptrs<T>(s);
-    const Box inner = interior_box(s->g);
+    const Box inner = interior_box(s->g, s->fp32);
     int t0 = mark_begin(s, MLK_PHASE_SWEEP);
     if constexpr (f32) HIPCHK(sweep_fused_f32(f, nf, s->g, inner, s->kz, s->ty, s->stream));
     else HIPCHK(sweep_fused_f64(f, nf, s->g, inner, s->kz, s->ty, s->stream));
@@ -1242,7 +1244,7 @@ mlk_status mlk_get_phase_time(mlk_sim* s, int32_t phase, double* total_ms, int64
 
 mlk_status mlk_get_interior_box(mlk_sim* s, int32_t box[6]) {
   if (!s || !box) return fail(MLK_EINVAL, "null argument");
-  const Box b = interior_box(s->g);
+  const Box b = interior_box(s->g, s->fp32);
   for (int a = 0; a < 3; ++a) {
     box[a] = b.lo[a];
     box[3 + a] = b.hi[a];
@@ -1865,7 +1867,7 @@ mlk_status build_tables(mlk_batch* b, BatchTables<T> (&tab)[2]) {
       }
       Box inner{};
       if (b->fused) {
-        inner = interior_box(s->g);
+        inner = interior_box(s->g, s->fp32);
         FusedJob<T> J{};
         J.a = cur;
         J.b = nxt;
@@ -2187,7 +2189,7 @@ mlk_status mlk_batch_destroy(mlk_batch* b) {
 namespace {
 
 std::string tune_key(const mlk_sim* s) {
-  const Box b = interior_box(s->g);
+  const Box b = interior_box(s->g, s->fp32);
   char k[160];
   std::snprintf(k, sizeof k, "%s %d %d %d %d %d %d %d %d %d", s->fp32 ? "fp32" : "fp64",
                 s->g.n[0], s->g.n[1], s->g.n[2], b.lo[0], b.lo[1], b.lo[2], b.hi[0], b.hi[1],
@@ -2233,7 +2235,7 @@ bool write_cache(const char* path, const std::vector<TuneEntry>& v) {
 template <typename T>
 mlk_status time_fused(mlk_sim* s, int ty, int kz, double* us) {
   const FieldPtrs<T> a = field_ptrs<T>(s), b = spare_ptrs<T>(s);
-  const Box inner = interior_box(s->g);
+  const Box inner = interior_box(s->g, s->fp32);
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
@@ -2298,7 +2300,7 @@ mlk_status mlk_autotune(mlk_sim* s, const char* cache_path) {
     }
   HIPCHK(hipSetDevice(s->desc.device));
   STCHK(sync_sim(s));
-  const Box inner = interior_box(s->g);
+  const Box inner = interior_box(s->g, s->fp32);
   const int ez = inner.hi[2] - inner.lo[2];
   if (ez <= 0) return MLK_OK;
   struct Cand {

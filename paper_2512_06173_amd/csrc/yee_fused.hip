@@ -3,15 +3,23 @@
 //   H^{n+1/2} = H^{n-1/2} - dt curl E^n
 //   E^{n+1}   = E^n + (dt/eps_r) curl H^{n+1/2}
 // (eq. Maxwell with D = eps_r E and B = H) with metallic or periodic closure.
-// This kernel covers a box of cells whose y and z positions keep their own
-// update and recomputed halo outside the y and z CPML layers (those layers
-// plus a one-cell margin are updated by the plain passes, whole rows of the
-// grid).  Along x the box normally spans every column and cells in the x
-// layers stretch their x derivatives here: they are a few lanes at the two
-// ends of each row, which the plain passes would otherwise handle as short,
-// badly coalesced strips.  The host chooses that box only when no tile's
-// low-x halo column lies in an x layer, so halo recomputations never need
-// psi.  Source and molecular currents are added by their own passes.
+// This kernel normally covers the whole grid, CPML layers included: a cell in
+// the layers of an axis stretches its derivatives along that axis here.
+//  * x layers are a few lanes at the two ends of each row, in half the tiles:
+//    their coefficients sit in LDS and their psi is prefetched a plane ahead.
+//    The host takes a full x extent only when no tile's low-x halo column lies
+//    in an x layer (else x is limited to the cells clear of the layers plus a
+//    margin, and the plain passes update the rest).
+//  * y layers are whole rows (one wavefront each) and z layers whole planes:
+//    the coefficients of the tile's rows sit in LDS, those of a plane are
+//    uniform loads, and psi (own cell and the halo cells of the curl) is
+//    prefetched a plane ahead in branches uniform across a wavefront or the
+//    workgroup.  The recomputed halo H (low-y row, low-x column, the plane
+//    below the chunk) reads psi without storing it.
+// A psi value used in the iteration that loads it would make the wavefront
+// wait for every load issued before it, the next plane's prefetch included
+// (vector memory counters retire in order).
+// Source and molecular currents are added by their own passes.
 //
 // A workgroup owns a tile of 64 x TY columns and marches over a chunk of z
 // planes.  For plane k it stages E^n(k+1) (with a one-cell halo ring) in LDS,
@@ -34,6 +42,10 @@ template <typename T, int TY>
 __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtrs<T>& b,
                                            const Geom& g, const Box& box, int kz, int ntx,
                                            int nty, int nblocks, int bid_in) {
+  // A cell's H is computed by the tile that owns it and recomputed as halo by its
+  // neighbours (CPML stretching included); both must round alike, so no product
+  // is contracted into a fused multiply-add here, whatever the code around it.
+#pragma clang fp contract(off)
   constexpr int EW = 66, EH = TY + 2;   // E plane in LDS: x in [-1, 64], y in [-1, TY]
   constexpr int HW = 65, HH = TY + 1;   // H plane in LDS: x in [-1, 63], y in [-1, TY-1]
   constexpr int NHALO = 2 * EW + 2 * TY;  // ring of the E plane
@@ -41,6 +53,7 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
   __shared__ T eL[2][3][EH * EW];
   __shared__ T hL[3][HH * HW];
   __shared__ T xc[2][3][64];  // x CPML b, c, 1/kappa of the tile's columns (E, H positions)
+  __shared__ T yc[2][3][TY + 1];  // y CPML b, c, 1/kappa of rows y0-1 .. y0+TY-1
 
   // XCD-aware tile order: consecutive blocks go to different XCDs; map the
   // blocks one XCD receives onto a contiguous range of tiles.
@@ -98,6 +111,47 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
   const size_t P = (size_t)nlny * (unsigned)g.n[2];  // psi values per component array
   const unsigned li = xl ? (unsigned)layer_index(g, 0, i) : 0u;
   const unsigned pb = li + nl * (unsigned)j, pby = li + nl * (unsigned)jh;
+  // y layers (own row and low-y halo row, uniform across a wavefront) and z
+  // layers (per plane, uniform across the workgroup).  The psi arrays of an
+  // axis are addressed from one base pointer with 32-bit indices (slot x array
+  // size + cell; range checked on the host), and the coefficients of a row or
+  // plane are uniform loads.
+  // (FP32 only: the FP64 kernel's box keeps clear of the y and z layers)
+  constexpr bool YZ = sizeof(T) == 4;
+  const bool yl = YZ && has_cpml(g, 1) && j < g.n[1] && in_layer(g, 1, j);
+  const bool yhl = YZ && has_cpml(g, 1) && in_layer(g, 1, jh);
+  auto zlay = [&](int k) { return YZ && has_cpml(g, 2) && in_layer(g, 2, k); };
+  const unsigned unx = (unsigned)g.n[0], uny = (unsigned)g.n[1];
+  const unsigned nly = (unsigned)(g.nlo[1] + g.nhi[1]);
+  const unsigned Py = has_cpml(g, 1) ? unx * nly * (unsigned)g.n[2] : 0u;
+  const unsigned Pz = has_cpml(g, 2) ? unx * uny * (unsigned)(g.nlo[2] + g.nhi[2]) : 0u;
+  const size_t oy = has_cpml(g, 1) ? psi_offset(g, 0, 0, 1) : 0;
+  const size_t oz = has_cpml(g, 2) ? psi_offset(g, 0, 0, 2) : 0;
+  const T* ty_tab = a.tab + (has_cpml(g, 1) ? tab_offset(g, 1) : 0);
+  const T* tz_tab = a.tab + (has_cpml(g, 2) ? tab_offset(g, 2) : 0);
+  const unsigned lyo = yl ? (unsigned)layer_index(g, 1, j) : 0u;
+  const unsigned lyh = yhl ? (unsigned)layer_index(g, 1, jh) : 0u;
+  // psi <- b psi + c d, d <- d / kappa + psi for the y derivative at row q (layer
+  // index lq) and column x of plane k; slot: 0 E x, 1 E z, 2 H x, 3 H z
+  auto sty = [&](int slot, int q, unsigned lq, int x, int k, T d, bool store) -> T {
+    const int field = slot >> 1;
+    const T* t = ty_tab + field * g.n[1] + q;
+    const unsigned id = (unsigned)slot * Py + (unsigned)x + unx * (lq + nly * (unsigned)k);
+    const T p = t[0] * a.psi[oy + id] + t[2 * g.n[1]] * d;
+    if (store) b.psi[oy + id] = p;
+    return t[4 * g.n[1]] * d + p;
+  };
+  // the same for a z derivative at cell (x, y) of plane k; slot: 0 E x, 1 E y,
+  // 2 H x, 3 H y
+  auto stz = [&](int slot, int x, int y, int k, T d, bool store) -> T {
+    const int field = slot >> 1;
+    const T* t = tz_tab + field * g.n[2] + k;
+    const unsigned lz = (unsigned)layer_index(g, 2, k);
+    const unsigned id = (unsigned)slot * Pz + (unsigned)x + unx * ((unsigned)y + uny * lz);
+    const T p = t[0] * a.psi[oz + id] + t[2 * g.n[2]] * d;
+    if (store) b.psi[oz + id] = p;
+    return t[4 * g.n[2]] * d + p;
+  };
   // psi arrays of axis x: E of y, E of z, H of y, H of z
   auto psi_at = [&](const FieldPtrs<T>& f, int slot, unsigned id) -> T& {
     return f.psi[(size_t)slot * P + id];
@@ -110,6 +164,14 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
       xc[fld][0][tx] = t[fld * n + i];
       xc[fld][1][tx] = t[2 * n + fld * n + i];
       xc[fld][2][tx] = t[4 * n + fld * n + i];
+    }
+  }
+  if (YZ && has_cpml(g, 1)) {
+    for (int t = tid; t < 2 * 3 * (TY + 1); t += 64 * TY) {
+      const int fld = t / (3 * (TY + 1)), w = (t / (TY + 1)) % 3, r = t % (TY + 1);
+      const int q = y0 - 1 + r;
+      yc[fld][w][r] = (q >= 0 && q < g.n[1] && in_layer(g, 1, q))
+                          ? ty_tab[w * 2 * g.n[1] + fld * g.n[1] + q] : T(0);
     }
   }
   const size_t hx_off = hx_on ? (size_t)ih + (size_t)g.n[0] * j : 0;
@@ -151,10 +213,15 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
       T dEy_dz = (ek[1] - em[1]) * idx;
       T dEx_dz = (ek[0] - em[0]) * idx;
       T dEz_dx = (E_at(pm, 2, tx + 1, ty) - em[2]) * idx;
+      const int kmw = km < 0 ? km + g.n[2] : km;
       if (xl) {
-        const unsigned kmw = (unsigned)(km < 0 ? km + g.n[2] : km);
-        const T q = xc[1][0][tx] * psi_at(a, 2, pb + nlny * kmw) + xc[1][1][tx] * dEz_dx;
+        const T q = xc[1][0][tx] * psi_at(a, 2, pb + nlny * (unsigned)kmw) + xc[1][1][tx] * dEz_dx;
         dEz_dx = xc[1][2][tx] * dEz_dx + q;
+      }
+      if (yl) dEz_dy = sty(2, j, lyo, i, kmw, dEz_dy, false);
+      if (zlay(kmw)) {
+        dEy_dz = stz(2, i, j, kmw, dEy_dz, false);
+        dEx_dz = stz(3, i, j, kmw, dEx_dz, false);
       }
       hpx = a.H[0][id] - dt * (dEz_dy - dEy_dz);
       hpy = a.H[1][id] - dt * (dEx_dz - dEz_dx);
@@ -184,18 +251,59 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
   // psi of plane k for the x-layer cells, read one iteration ahead after the
   // plane's field prefetch: own E y/z and H y/z, and H z of the low-y halo cell
   T nP[4] = {T(0), T(0), T(0), T(0)}, nPy = T(0);
+  // y and z layers, by psi slot: own y (E x, E z, H x, H z), own z (E x, E y,
+  // H x, H y); low-x halo cell: z H y, y H z; low-y halo cell: y H x, y H z, z H x
+  T nYo[4] = {T(0), T(0), T(0), T(0)}, nZo[4] = {T(0), T(0), T(0), T(0)};
+  T nXh[2] = {T(0), T(0)}, nYh[3] = {T(0), T(0), T(0)};
+  auto iy = [&](int slot, int x, unsigned lq, int k) -> unsigned {
+    return (unsigned)slot * Py + (unsigned)x + unx * (lq + nly * (unsigned)k);
+  };
+  auto iz = [&](int slot, int x, int y, int k) -> unsigned {
+    return (unsigned)slot * Pz + (unsigned)x +
+           unx * ((unsigned)y + uny * (unsigned)layer_index(g, 2, k));
+  };
   auto prefetch_psi = [&](int k) {
-    if (xl && k < k1) {
+    if (k >= k1) return;
+    if (xl) {
       const unsigned pk = pb + nlny * (unsigned)k;
 #pragma unroll
       for (int q = 0; q < 4; ++q) nP[q] = psi_at(a, q, pk);
       if (hy_on) nPy = psi_at(a, 3, pby + nlny * (unsigned)k);
     }
+    if (own && yl) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) nYo[q] = a.psi[oy + iy(q, i, lyo, k)];
+    }
+    if (hx_on && yl) nXh[1] = a.psi[oy + iy(3, ih, lyo, k)];
+    if (hy_on && yhl) {
+      nYh[0] = a.psi[oy + iy(2, i, lyh, k)];
+      nYh[1] = a.psi[oy + iy(3, i, lyh, k)];
+    }
+    if (zlay(k)) {
+      if (own) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) nZo[q] = a.psi[oz + iz(q, i, j, k)];
+      }
+      if (hx_on) nXh[0] = a.psi[oz + iz(3, ih, j, k)];
+      if (hy_on) nYh[2] = a.psi[oz + iz(2, i, jh, k)];
+    }
+  };
+  // stretched derivative from a prefetched psi (the new psi in pn): y at LDS row
+  // r, z at plane k
+  auto fy = [&](int field, int r, T ps, T d, T& pn) -> T {
+    pn = yc[field][0][r] * ps + yc[field][1][r] * d;
+    return yc[field][2][r] * d + pn;
+  };
+  auto fz = [&](int field, int k, T ps, T d, T& pn) -> T {
+    const T* t = tz_tab + field * g.n[2] + k;
+    pn = t[0] * ps + t[2 * g.n[2]] * d;
+    return t[4 * g.n[2]] * d + pn;
   };
   prefetch_psi(k0);
 
   for (int k = k0; k < k1; ++k) {
     const int p0 = k & 1, p1 = (k + 1) & 1;
+    const bool zl = zlay(k);  // plane k in a z layer (uniform across the workgroup)
     put(p1, nEo, nEov, nEr, nErv);
 #pragma unroll
     for (int c = 0; c < 3; ++c) ek1[c] = nEo[c];
@@ -231,6 +339,19 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
         dEz_dx = kh * dEz_dx + qy;
         dEy_dx = kh * dEy_dx + qz;
       }
+      T pn;
+      if (yl) {
+        dEz_dy = fy(1, ty + 1, nYo[2], dEz_dy, pn);
+        b.psi[oy + iy(2, i, lyo, k)] = pn;
+        dEx_dy = fy(1, ty + 1, nYo[3], dEx_dy, pn);
+        b.psi[oy + iy(3, i, lyo, k)] = pn;
+      }
+      if (zl) {
+        dEy_dz = fz(1, k, nZo[2], dEy_dz, pn);
+        b.psi[oz + iz(2, i, j, k)] = pn;
+        dEx_dz = fz(1, k, nZo[3], dEx_dz, pn);
+        b.psi[oz + iz(3, i, j, k)] = pn;
+      }
       hx -= dt * (dEz_dy - dEy_dz);
       hy -= dt * (dEx_dz - dEz_dx);
       hz -= dt * (dEy_dx - dEx_dy);
@@ -249,6 +370,9 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
         T dEz_dx = (E_at(p0, 2, 0, ty) - E_at(p0, 2, -1, ty)) * idx;
         T dEy_dx = (E_at(p0, 1, 0, ty) - E_at(p0, 1, -1, ty)) * idx;
         T dEx_dy = (E_at(p0, 0, -1, ty + 1) - E_at(p0, 0, -1, ty)) * idx;
+        T pn;
+        if (zl) dEx_dz = fz(1, k, nXh[0], dEx_dz, pn);
+        if (yl) dEx_dy = fy(1, ty + 1, nXh[1], dEx_dy, pn);
         hyh = hxh_y - dt * (dEx_dz - dEz_dx);
         hzh = hxh_z - dt * (dEy_dx - dEx_dy);
       }
@@ -264,6 +388,12 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
         T dEy_dx = (E_at(p0, 1, tx + 1, -1) - E_at(p0, 1, tx, -1)) * idx;
         T dEx_dy = (E_at(p0, 0, tx, 0) - E_at(p0, 0, tx, -1)) * idx;
         if (xl) dEy_dx = xc[1][2][tx] * dEy_dx + (xc[1][0][tx] * nPy + xc[1][1][tx] * dEy_dx);
+        T pn;
+        if (yhl) {
+          dEz_dy = fy(1, 0, nYh[0], dEz_dy, pn);
+          dEx_dy = fy(1, 0, nYh[1], dEx_dy, pn);
+        }
+        if (zl) dEy_dz = fz(1, k, nYh[2], dEy_dz, pn);
         hxh = hyh_x - dt * (dEz_dy - dEy_dz);
         hzh = hyh_z - dt * (dEy_dx - dEx_dy);
       }
@@ -290,6 +420,19 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
         dHz_dx = ke * dHz_dx + qy;
         dHy_dx = ke * dHy_dx + qz;
       }
+      T pn;
+      if (yl) {
+        dHz_dy = fy(0, ty + 1, nYo[0], dHz_dy, pn);
+        b.psi[oy + iy(0, i, lyo, k)] = pn;
+        dHx_dy = fy(0, ty + 1, nYo[1], dHx_dy, pn);
+        b.psi[oy + iy(1, i, lyo, k)] = pn;
+      }
+      if (zl) {
+        dHy_dz = fz(0, k, nZo[0], dHy_dz, pn);
+        b.psi[oz + iz(0, i, j, k)] = pn;
+        dHx_dz = fz(0, k, nZo[1], dHx_dz, pn);
+        b.psi[oz + iz(1, i, j, k)] = pn;
+      }
       const T cx = dHz_dy - dHy_dz;
       const T cy = dHx_dz - dHz_dx;
       const T cz = dHy_dx - dHx_dy;
@@ -306,7 +449,7 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
 }
 
 template <typename T, int TY>
-__global__ __launch_bounds__(64 * TY) void k_fused(FieldPtrs<T> a, FieldPtrs<T> b, Geom g,
+__global__ __launch_bounds__(64 * TY, 4) void k_fused(FieldPtrs<T> a, FieldPtrs<T> b, Geom g,
                                                    Box box, int kz, int ntx, int nty,
                                                    int nblocks) {
   fused_body<T, TY>(a, b, g, box, kz, ntx, nty, nblocks, blockIdx.x);
@@ -314,7 +457,7 @@ __global__ __launch_bounds__(64 * TY) void k_fused(FieldPtrs<T> a, FieldPtrs<T> 
 
 // One launch over the jobs of a batch of domains (see BatchJobs).
 template <typename T, int TY>
-__global__ __launch_bounds__(64 * TY) void k_fused_batch(const FusedJob<T>* jobs,
+__global__ __launch_bounds__(64 * TY, 4) void k_fused_batch(const FusedJob<T>* jobs,
                                                          const int* start, int njobs) {
   const int j = find_job(start, njobs, blockIdx.x);
   const FusedJob<T>& J = jobs[j];

@@ -131,17 +131,21 @@ def test_fused_sweep_many_tiles_and_chunks_fp64():
     check(sim, ora, w)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("nx, full", [(72, True), (70, False)])
-def test_fused_x_layers_and_fallback_box_fp64(nx, full):
-    """The fused sweep spans every x column and stretches x derivatives in the x CPML
-    layers, unless the low-x halo column of a 64-wide tile falls into a layer (nx = 70
-    with 8 layers: the second tile's halo column x = 63 is a layer cell); then the x
-    layers go to the plain passes.  Both boxes against the oracle."""
-    w = _sources_workload((nx, 30, 36), ("cpml",) * 6, (8, 8, 6, 7, 8, 6), "fp64", 150)
+def test_fused_box_layers_and_fallback(nx, full, precision):
+    """With FP32 fields the fused sweep covers the whole grid and stretches the
+    derivatives of the CPML cells itself; the FP64 kernel carries the x layers only (its
+    y and z extent stops at the layers, with a margin).  The x layers go to the plain
+    passes when the low-x halo column of a 64-wide tile falls into one (nx = 70 with 8
+    layers: the second tile's halo column x = 63 is a layer cell).  All four boxes
+    against the oracle."""
+    w = _sources_workload((nx, 30, 36), ("cpml",) * 6, (8, 8, 6, 7, 8, 6), precision, 150)
     sim, ora = run_both(w, sweep="fused")
     lo, hi = sim.interior_box()
     assert (lo[0], hi[0]) == ((0, nx) if full else (9, nx - 8))
-    assert (lo[1], hi[1], lo[2], hi[2]) == (7, 23, 9, 30)
+    yz = (0, 30, 0, 36) if precision == "fp32" else (7, 23, 9, 30)
+    assert (lo[1], hi[1], lo[2], hi[2]) == yz
     check(sim, ora, w)
 
 
