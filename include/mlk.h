@@ -284,17 +284,30 @@ mlk_status mlk_batch_sync(mlk_batch* b);
 mlk_status mlk_batch_destroy(mlk_batch* b);
 
 /* Tile shape of the fused sweep: rows per workgroup ty (4, 8 or 16) and z planes
- * per workgroup kz.  mlk_autotune times every pair on the sim's own grid, each
- * as the fused launch plus the two CPML shell passes of a step, in three
- * interleaved rounds (the state is left untouched; each pair keeps its best
- * round) and keeps the fastest; with cache_path (NULL: no
- * cache) results are read from and added to a JSON file keyed by precision,
- * grid and interior box.  The result does not depend on the tile shape (each
+ * per workgroup kz.  mlk_autotune times every pair (and, with FP32 fields, both
+ * layer modes, see mlk_set_sweep_layers) on the sim's own grid, each as the
+ * fused launch plus the two CPML shell passes of a step, in three interleaved
+ * rounds (the state is left untouched; each candidate keeps its best round) and
+ * keeps the fastest; with cache_path (NULL: no cache) results are read from and
+ * added to a JSON file keyed by precision, grid, CPML thicknesses and periodic
+ * axes.  The result does not depend on the tile shape (each
  * cell's arithmetic is the same), only the speed does.  Plain-sweep sims have
  * nothing to tune. */
 mlk_status mlk_autotune(mlk_sim* s, const char* cache_path);
 mlk_status mlk_set_tuning(mlk_sim* s, int32_t ty, int32_t kz);
 mlk_status mlk_get_tuning(mlk_sim* s, int32_t* ty, int32_t* kz);
+
+/* Layer mode of the fused sweep (FP32 fields): on, the fused kernel updates the
+ * whole grid and stretches the derivatives of the y and z CPML cells itself;
+ * off, the cells of the y and z layers (plus a one-cell margin above the low
+ * layers) are updated by the plain shell passes.  The default is on when the y
+ * and z layers are a small part of the grid ((nlo + nhi) / n summed over y and z
+ * at most 1/4); mlk_autotune times both modes and keeps the faster (and caches
+ * it).  Like the tile shape, the mode changes speed, not results.  FP64 fields:
+ * always off (MLK_EUNSUPPORTED for on).  MLK_ESTATE while the sim belongs to a
+ * batch. */
+mlk_status mlk_set_sweep_layers(mlk_sim* s, int32_t on);
+mlk_status mlk_get_sweep_layers(mlk_sim* s, int32_t* on);
 
 #ifdef __cplusplus
 }

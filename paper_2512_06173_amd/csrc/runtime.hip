@@ -88,6 +88,7 @@ struct mlk_sim {
   void* psi2 = nullptr;
   int kz = 0;       // z planes per workgroup of the fused sweep
   int ty = 4;       // y rows per workgroup of the fused sweep (4, 8 or 16)
+  bool layers = false;  // FP32 fused sweep carries the y and z CPML layers itself
   hipStream_t batch_stream = nullptr;  // stream of the batch this sim belongs to
   bool in_batch = false;
   double adj_forward_ms = 0.0, adj_reverse_ms = 0.0;  // phases of the last adjoint call
@@ -648,13 +649,15 @@ Box interior_box(const Geom& g, bool layers) {
   return inner;
 }
 
+Box sweep_box(const mlk_sim* s) { return interior_box(s->g, s->fp32 && s->layers); }
+
 template <typename T>
 mlk_status sweep(mlk_sim* s) {
   constexpr bool f32 = sizeof(T) == 4;
   const FieldPtrs<T> f = field_ptrs<T>(s);
   if (s->desc.sweep == MLK_SWEEP_FUSED) {
     const FieldPtrs<T> nf = spare_ptrs<T>(s);
-    const Box inner = interior_box(s->g, s->fp32);
+    const Box inner = sweep_box(s);
     int t0 = mark_begin(s, MLK_PHASE_SWEEP);
     if constexpr (f32) HIPCHK(sweep_fused_f32(f, nf, s->g, inner, s->kz, s->ty, s->stream));
     else HIPCHK(sweep_fused_f64(f, nf, s->g, inner, s->kz, s->ty, s->stream));
@@ -927,6 +930,11 @@ mlk_status mlk_create(const mlk_grid_desc* gd, mlk_sim** out) {
     int kz = (int)(((long long)n[2] * ntile + 2047) / 2048);
     s->kz = std::max(8, std::min(kz, n[2]));
   }
+  // FP32: the fused sweep takes the y and z layers when they are a small part of
+  // the grid (on small, layer-heavy grids the plain shell passes are faster);
+  // mlk_autotune measures both
+  s->layers = s->fp32 && (double)(s->g.nlo[1] + s->g.nhi[1]) / n[1] +
+                                 (double)(s->g.nlo[2] + s->g.nhi[2]) / n[2] <= 0.25;
   if (dalloc(&s->epsinv, s->ncell * s->esz) != hipSuccess)
     return bail(fail(MLK_ENOMEM, "eps allocation failed"));
   {
@@ -1244,7 +1252,7 @@ mlk_status mlk_get_phase_time(mlk_sim* s, int32_t phase, double* total_ms, int64
 
 mlk_status mlk_get_interior_box(mlk_sim* s, int32_t box[6]) {
   if (!s || !box) return fail(MLK_EINVAL, "null argument");
-  const Box b = interior_box(s->g, s->fp32);
+  const Box b = sweep_box(s);
   for (int a = 0; a < 3; ++a) {
     box[a] = b.lo[a];
     box[3 + a] = b.hi[a];
@@ -1867,7 +1875,7 @@ mlk_status build_tables(mlk_batch* b, BatchTables<T> (&tab)[2]) {
       }
       Box inner{};
       if (b->fused) {
-        inner = interior_box(s->g, s->fp32);
+        inner = sweep_box(s);
         FusedJob<T> J{};
         J.a = cur;
         J.b = nxt;
@@ -2189,17 +2197,17 @@ mlk_status mlk_batch_destroy(mlk_batch* b) {
 namespace {
 
 std::string tune_key(const mlk_sim* s) {
-  const Box b = interior_box(s->g, s->fp32);
-  char k[160];
-  std::snprintf(k, sizeof k, "%s %d %d %d %d %d %d %d %d %d", s->fp32 ? "fp32" : "fp64",
-                s->g.n[0], s->g.n[1], s->g.n[2], b.lo[0], b.lo[1], b.lo[2], b.hi[0], b.hi[1],
-                b.hi[2]);
+  const Geom& g = s->g;
+  char k[200];
+  std::snprintf(k, sizeof k, "%s %d %d %d cpml %d %d %d %d %d %d periodic %d %d %d",
+                s->fp32 ? "fp32" : "fp64", g.n[0], g.n[1], g.n[2], g.nlo[0], g.nhi[0], g.nlo[1],
+                g.nhi[1], g.nlo[2], g.nhi[2], g.periodic[0], g.periodic[1], g.periodic[2]);
   return k;
 }
 
 struct TuneEntry {
   std::string key;
-  int ty, kz;
+  int ty, kz, layers;
   double us;
 };
 
@@ -2211,8 +2219,8 @@ std::vector<TuneEntry> read_cache(const char* path) {
   while (std::fgets(line, sizeof line, f)) {
     char key[200];
     TuneEntry e{};
-    if (std::sscanf(line, " \"%199[^\"]\": {\"ty\": %d, \"kz\": %d, \"us\": %lf", key, &e.ty, &e.kz,
-                    &e.us) == 4) {
+    if (std::sscanf(line, " \"%199[^\"]\": {\"ty\": %d, \"kz\": %d, \"layers\": %d, \"us\": %lf",
+                    key, &e.ty, &e.kz, &e.layers, &e.us) == 5) {
       e.key = key;
       v.push_back(e);
     }
@@ -2226,8 +2234,9 @@ bool write_cache(const char* path, const std::vector<TuneEntry>& v) {
   if (!f) return false;
   std::fprintf(f, "{\n");
   for (size_t q = 0; q < v.size(); ++q)
-    std::fprintf(f, "\"%s\": {\"ty\": %d, \"kz\": %d, \"us\": %.3f}%s\n", v[q].key.c_str(),
-                 v[q].ty, v[q].kz, v[q].us, q + 1 < v.size() ? "," : "");
+    std::fprintf(f, "\"%s\": {\"ty\": %d, \"kz\": %d, \"layers\": %d, \"us\": %.3f}%s\n",
+                 v[q].key.c_str(), v[q].ty, v[q].kz, v[q].layers, v[q].us,
+                 q + 1 < v.size() ? "," : "");
   std::fprintf(f, "}\n");
   return std::fclose(f) == 0;
 }
@@ -2235,7 +2244,7 @@ bool write_cache(const char* path, const std::vector<TuneEntry>& v) {
 template <typename T>
 mlk_status time_fused(mlk_sim* s, int ty, int kz, double* us) {
   const FieldPtrs<T> a = field_ptrs<T>(s), b = spare_ptrs<T>(s);
-  const Box inner = interior_box(s->g, s->fp32);
+  const Box inner = sweep_box(s);
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
@@ -2286,6 +2295,22 @@ mlk_status mlk_get_tuning(mlk_sim* s, int32_t* ty, int32_t* kz) {
   return MLK_OK;
 }
 
+mlk_status mlk_set_sweep_layers(mlk_sim* s, int32_t on) {
+  if (!s) return fail(MLK_EINVAL, "null argument");
+  if (s->in_batch) return fail(MLK_ESTATE, "tune members before forming the batch");
+  if (on && !s->fp32)
+    return fail(MLK_EUNSUPPORTED, "the FP64 fused sweep leaves the y and z layers to the shell");
+  STCHK(sync_sim(s));
+  s->layers = on != 0;
+  return MLK_OK;
+}
+
+mlk_status mlk_get_sweep_layers(mlk_sim* s, int32_t* on) {
+  if (!s || !on) return fail(MLK_EINVAL, "null argument");
+  *on = s->layers ? 1 : 0;
+  return MLK_OK;
+}
+
 mlk_status mlk_autotune(mlk_sim* s, const char* cache_path) {
   if (!s) return fail(MLK_EINVAL, "null argument");
   if (s->in_batch) return fail(MLK_ESTATE, "tune members before forming the batch");
@@ -2296,40 +2321,49 @@ mlk_status mlk_autotune(mlk_sim* s, const char* cache_path) {
     if (e.key == key && (e.ty == 4 || e.ty == 8 || e.ty == 16) && e.kz > 0) {
       s->ty = e.ty;
       s->kz = e.kz;
+      s->layers = s->fp32 && e.layers != 0;
       return MLK_OK;
     }
   HIPCHK(hipSetDevice(s->desc.device));
   STCHK(sync_sim(s));
-  const Box inner = interior_box(s->g, s->fp32);
-  const int ez = inner.hi[2] - inner.lo[2];
-  if (ez <= 0) return MLK_OK;
+  // candidates: layer mode (FP32: with or without the y and z layers in the
+  // fused kernel) x rows per workgroup x planes per workgroup
   struct Cand {
-    int ty, kz;
+    int layers, ty, kz;
     double us;
   };
   std::vector<Cand> cands;
-  for (int ty : {4, 8, 16})
-    for (int kz : {4, 8, 16, 32, 64, 128})
-      if (kz <= std::max(4, ez)) cands.push_back({ty, kz, 1e300});
+  for (int lay = 0; lay <= (s->fp32 ? 1 : 0); ++lay) {
+    s->layers = lay != 0;
+    const Box inner = sweep_box(s);
+    const int ez = inner.hi[2] - inner.lo[2];
+    if (ez <= 0) continue;
+    for (int ty : {4, 8, 16})
+      for (int kz : {4, 8, 16, 32, 64, 128})
+        if (kz <= std::max(4, ez)) cands.push_back({lay, ty, kz, 1e300});
+  }
   for (int round = 0; round < 3; ++round)
     for (Cand& c : cands) {
       double us = 0.0;
+      s->layers = c.layers != 0;
       STCHK(s->fp32 ? time_fused<float>(s, c.ty, c.kz, &us)
                     : time_fused<double>(s, c.ty, c.kz, &us));
       c.us = std::min(c.us, us);
     }
   double best = 1e300;
-  int bty = s->ty, bkz = s->kz;
+  int blay = 0, bty = s->ty, bkz = s->kz;
   for (const Cand& c : cands)
     if (c.us < best) {
       best = c.us;
+      blay = c.layers;
       bty = c.ty;
       bkz = c.kz;
     }
+  s->layers = blay != 0;
   s->ty = bty;
   s->kz = bkz;
   if (cache_path) {
-    cache.push_back({key, bty, bkz, best});
+    cache.push_back({key, bty, bkz, blay, best});
     if (!write_cache(cache_path, cache))
       return fail(MLK_EINVAL, "cannot write the tuning cache %s", cache_path);
   }

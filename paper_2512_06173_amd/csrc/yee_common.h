@@ -37,6 +37,7 @@ __device__ __forceinline__ T bwd(const T* a, size_t id, int q, int n, int period
 template <typename T>
 __device__ __forceinline__ T stretch(const Geom& g, const T* tab, const T* in, T* out, int field,
                                      int c, int a, int i, int j, int k, T d) {
+#pragma clang fp contract(off)  // see the cell updates
   if (!has_cpml(g, a)) return d;
   const int q = a == 0 ? i : (a == 1 ? j : k);
   if (!in_layer(g, a, q)) return d;

@@ -20,6 +20,9 @@ namespace mlk {
 template <typename T>
 __device__ __forceinline__ void update_h_cell(const FieldPtrs<T>& in, const FieldPtrs<T>& out,
                                               const Geom& g, int i, int j, int k) {
+  // products are not contracted into fused multiply-adds, as in the fused sweep,
+  // so that every way of splitting the grid between the two rounds alike
+#pragma clang fp contract(off)
   const size_t sx = 1, sy = (size_t)g.n[0], sz = (size_t)g.n[0] * g.n[1];
   const size_t id = cell_index(g, i, j, k);
   const T idx = (T)g.inv_dx;
@@ -47,6 +50,9 @@ __device__ __forceinline__ void update_h_cell(const FieldPtrs<T>& in, const Fiel
 template <typename T>
 __device__ __forceinline__ void update_e_cell(const FieldPtrs<T>& in, const FieldPtrs<T>& out,
                                               const Geom& g, int i, int j, int k) {
+  // products are not contracted into fused multiply-adds, as in the fused sweep,
+  // so that every way of splitting the grid between the two rounds alike
+#pragma clang fp contract(off)
   const size_t sx = 1, sy = (size_t)g.n[0], sz = (size_t)g.n[0] * g.n[1];
   const size_t id = cell_index(g, i, j, k);
   const T idx = (T)g.inv_dx;

@@ -124,6 +124,8 @@ def lib():
         "mlk_autotune": (st, [sim, C.c_char_p]),
         "mlk_set_tuning": (st, [sim, C.c_int32, C.c_int32]),
         "mlk_get_tuning": (st, [sim, _ip, _ip]),
+        "mlk_set_sweep_layers": (st, [sim, C.c_int32]),
+        "mlk_get_sweep_layers": (st, [sim, _ip]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(L, name)
@@ -144,7 +146,7 @@ def exported_symbols():
             "mlk_checkpoint_load", "mlk_set_timing", "mlk_get_phase_time",
             "mlk_get_interior_box", "mlk_batch_create", "mlk_batch_step", "mlk_batch_capture",
             "mlk_batch_replay", "mlk_batch_sync", "mlk_batch_destroy", "mlk_autotune",
-            "mlk_set_tuning", "mlk_get_tuning", "mlk_adjoint", "mlk_set_eps_box",
+            "mlk_set_tuning", "mlk_get_tuning", "mlk_set_sweep_layers", "mlk_get_sweep_layers", "mlk_adjoint", "mlk_set_eps_box",
             "mlk_set_tls_dipoles", "mlk_get_adjoint_times"]
 
 
@@ -458,6 +460,15 @@ class Simulation:
 
     def set_tuning(self, ty, kz):
         _check(lib().mlk_set_tuning(self._h, int(ty), int(kz)))
+
+    def sweep_layers(self):
+        """Whether the fused sweep updates the y and z CPML layers itself (FP32)."""
+        on = C.c_int32()
+        _check(lib().mlk_get_sweep_layers(self._h, C.byref(on)))
+        return bool(on.value)
+
+    def set_sweep_layers(self, on):
+        _check(lib().mlk_set_sweep_layers(self._h, 1 if on else 0))
 
 
 class Batch:

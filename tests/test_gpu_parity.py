@@ -134,19 +134,49 @@ def test_fused_sweep_many_tiles_and_chunks_fp64():
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("nx, full", [(72, True), (70, False)])
 def test_fused_box_layers_and_fallback(nx, full, precision):
-    """With FP32 fields the fused sweep covers the whole grid and stretches the
-    derivatives of the CPML cells itself; the FP64 kernel carries the x layers only (its
-    y and z extent stops at the layers, with a margin).  The x layers go to the plain
-    passes when the low-x halo column of a 64-wide tile falls into one (nx = 70 with 8
-    layers: the second tile's halo column x = 63 is a layer cell).  All four boxes
-    against the oracle."""
+    """With FP32 fields and the layer mode on, the fused sweep covers the whole grid and
+    stretches the derivatives of the CPML cells itself; the FP64 kernel carries the x
+    layers only (its y and z extent stops at the layers, with a margin).  The x layers go
+    to the plain passes when the low-x halo column of a 64-wide tile falls into one
+    (nx = 70 with 8 layers: the second tile's halo column x = 63 is a layer cell).  All
+    four boxes against the oracle."""
     w = _sources_workload((nx, 30, 36), ("cpml",) * 6, (8, 8, 6, 7, 8, 6), precision, 150)
-    sim, ora = run_both(w, sweep="fused")
+    say(f"[parity] {w.name} precision={precision} layers in the fused sweep")
+    sim = mlk().from_workload(w, sweep="fused")
+    if precision == "fp32":
+        sim.set_sweep_layers(True)
     lo, hi = sim.interior_box()
     assert (lo[0], hi[0]) == ((0, nx) if full else (9, nx - 8))
     yz = (0, 30, 0, 36) if precision == "fp32" else (7, 23, 9, 30)
     assert (lo[1], hi[1], lo[2], hi[2]) == yz
+    ora = build_oracle(w)
+    sim.step(w.steps)
+    ora.step(w.steps)
     check(sim, ora, w)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_sweep_decompositions_agree_bitwise(precision):
+    """The plain sweep, the fused sweep with the CPML shell, and (FP32) the fused sweep
+    carrying every layer give the same fields bit for bit: each cell's arithmetic is the
+    same expression, rounded alike, whichever kernel evaluates it."""
+    w = W.radiating_cube(n=72, n_emit=60, steps=0, cpml=8, precision=precision)
+    runs = []
+    for sweep, layers in (("plain", None), ("fused", False), ("fused", True)):
+        if layers and precision == "fp64":
+            continue
+        sim = mlk().from_workload(w, sweep=sweep)
+        if layers is not None:
+            sim.set_sweep_layers(layers)
+        say(f"[decomposition] {precision} {sweep} layers={layers} box={sim.interior_box()}")
+        sim.step(40)
+        runs.append(sim.fields())
+    for other in runs[1:]:
+        for x, y in zip(runs[0], other):
+            assert np.array_equal(x, y)
+    if precision == "fp64":
+        with pytest.raises(mlk().MlkError):
+            mlk().from_workload(w, sweep="fused").set_sweep_layers(True)
 
 
 def test_ragged_mixed_boundaries_fp64():
