@@ -16,10 +16,16 @@
 //
 // The stretching of a CPML layer acts, in the reverse step, at the cell whose
 // forward update used the derivative: the transposed E update needs the psi
-// adjoint at the +1 neighbours as well.  The box therefore keeps a one-cell
-// margin above the low layers (the recomputed halo) and one below the high
-// layers (the staged +1 neighbours); the cells outside it are updated by the
-// shell passes in adjoint.hip.
+// adjoint at the +1 neighbours as well.  Along y and z the box therefore keeps
+// a one-cell margin above the low layers (the recomputed halo) and one below
+// the high layers (the staged +1 neighbours); the cells outside it are updated
+// by the shell passes in adjoint.hip.  Along x the box normally spans every
+// column and the x layers are handled here: each cell turns its own x-derivative
+// terms into their stretched adjoints, D = dbar(+-W) for the transposed E update
+// and G = dbar(-+dt Hb') for the transposed H update (psi adjoint prefetched a
+// plane ahead), and its neighbours read them from LDS.  The host takes that box
+// only when no tile's low-x halo column or high-x ring column lies in an x
+// layer, so those stay plain.
 #include "mlk_internal.h"
 #include "yee_common.h"
 
@@ -32,6 +38,9 @@ struct AdjFused {
   T* Eo[3];       // adjoint of E^n
   T* Ho[3];       // adjoint of H^{n+1/2} after the transposed E update
   const T* epsinv;
+  const T* tab;      // CPML tables of the forward sweep
+  const T* psi_in;   // psi adjoint (E and H), read
+  T* psi_out;        // psi adjoint, written
 };
 
 namespace {
@@ -65,6 +74,9 @@ __global__ __launch_bounds__(64 * TY) void k_adj_fused(AdjFused<T> p, Geom g, Bo
   static_assert(64 * TY >= NHALO, "one thread per ring slot of the staged plane");
   __shared__ T wL[2][3][EH * EW];
   __shared__ T hL[3][HH * HW];
+  __shared__ T dL[2][HH * EW];  // D of the y and z x-terms, plane k, rows -1..TY-1
+  __shared__ T gL[2][HH * HW];  // G of the y and z x-terms, rows -1..TY-1
+  __shared__ T xc[2][3][64];    // x CPML b, c, 1/kappa + c of the tile's columns
 
   const int bid = xcd_block(blockIdx.x, nblocks);
   const int tile_x = bid % ntx, tile_y = (bid / ntx) % nty, chunk = bid / (ntx * nty);
@@ -109,7 +121,38 @@ __global__ __launch_bounds__(64 * TY) void k_adj_fused(AdjFused<T> p, Geom g, Bo
   const size_t hx_off = hx_on ? (size_t)ih + (size_t)g.n[0] * j : 0;
   const size_t hy_off = hy_on ? (size_t)i + (size_t)g.n[0] * jh : 0;
 
+  // x layers: own cells and low-y halo cells in them; psi adjoint (x compressed to
+  // the layers; slots E y, E z, H y, H z) through 32-bit indices (checked on the host)
+  const bool lay_i = has_cpml(g, 0) && i < g.n[0] && in_layer(g, 0, i);
+  const bool xl = lay_i && i >= box.lo[0] && own;
+  const bool xhl = lay_i && hy_on;
+  const unsigned nl = (unsigned)(g.nlo[0] + g.nhi[0]);
+  const unsigned nlny = nl * (unsigned)g.n[1];
+  const size_t P = (size_t)nlny * (unsigned)g.n[2];
+  const unsigned li = lay_i ? (unsigned)layer_index(g, 0, i) : 0u;
+  const unsigned pb = li + nl * (unsigned)j, pby = li + nl * (unsigned)jh;
+  if (ty == 0 && lay_i) {
+    const T* t = p.tab + tab_offset(g, 0);
+    const int n = g.n[0];
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      const T c = t[2 * n + f * n + i];
+      xc[f][0][tx] = t[f * n + i];
+      xc[f][1][tx] = c;
+      xc[f][2][tx] = t[4 * n + f * n + i] + c;
+    }
+  }
+  lds_barrier();  // the prologue uses the coefficients
+  // adjoint of a stretched derivative from w: (1/kappa + c) w + c psi_in
+  auto dbar = [&](int f, T w, T ps) -> T { return xc[f][2][tx] * w + xc[f][1][tx] * ps; };
+
   auto W_at = [&](int q, int c, int xs, int ys) -> T { return wL[q][c][(ys + 1) * EW + xs + 1]; };
+  // D of the x-term of the E component y (c = 0: -W_y) or z (c = 1: +W_z) at slot
+  // (xs, ys) of plane q; the ring columns lie outside the x layers (host check)
+  auto D_at = [&](int q, int c, int xs, int ys) -> T {
+    if (xs == 64 || xs == -1) return c == 0 ? -W_at(q, 1, xs, ys) : W_at(q, 2, xs, ys);
+    return dL[c][(ys + 1) * EW + xs + 1];
+  };
   // W = dt eps^-1 u of a staged slot (zero outside the closure); the own slot's
   // u is returned in u
   auto put = [&](int q, int z, const T o[3], T oe, bool ov, T u[3], T w[3], const T r[3], T re,
@@ -142,15 +185,17 @@ __global__ __launch_bounds__(64 * TY) void k_adj_fused(AdjFused<T> p, Geom g, Bo
     const int kmw = km < 0 ? km + g.n[2] : km;
     put(pm, kmw, em, eme, emv, um, wm, emr, emre, emrv);
     put(p0, k0, ek, eke, ekv, uk, wk, ekr, ekre, ekrv);
+    // D of plane km (z component) for the own cell, read-only psi
+    dL[1][oslot] = (xl && plm.valid)
+                       ? dbar(0, wm[2], p.psi_in[P + pb + nlny * (unsigned)kmw]) : wm[2];
     lds_barrier();
     if (own && plm.valid) {
       const size_t id = own_off + plm.off;
       const T dWz_dy = W_at(pm, 2, tx, ty + 1) - wm[2];
       const T dWy_dz = wk[1] - wm[1];
       const T dWx_dz = wk[0] - wm[0];
-      const T dWz_dx = W_at(pm, 2, tx + 1, ty) - wm[2];
       hpx = p.H[0][id] + idx * (dWz_dy - dWy_dz);
-      hpy = p.H[1][id] + idx * (dWx_dz - dWz_dx);
+      hpy = p.H[1][id] + idx * (dWx_dz + (dL[1][oslot] - D_at(pm, 1, tx + 1, ty)));
     }
     const Col pl1 = plane(g, k0 + 1);
     nEov = load4(p, ocol, pl1, nEo, nEoe);
@@ -171,11 +216,42 @@ __global__ __launch_bounds__(64 * TY) void k_adj_fused(AdjFused<T> p, Geom g, Bo
     nHy[1] = p.H[2][hy_off + po];
   };
   prefetch_h(k0);
+  // psi adjoint of plane k for the x-layer cells, read one iteration ahead:
+  // own E y, E z, H y, H z, and E y of the low-y halo cell
+  T nP[4] = {T(0), T(0), T(0), T(0)}, nPy = T(0);
+  auto prefetch_psi = [&](int k) {
+    if (k >= k1) return;
+    if (xl) {
+      const unsigned pk = pb + nlny * (unsigned)k;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) nP[q] = p.psi_in[(size_t)q * P + pk];
+    }
+    if (xhl) nPy = p.psi_in[pby + nlny * (unsigned)k];
+  };
+  prefetch_psi(k0);
 
   for (int k = k0; k < k1; ++k) {
     const int p0 = k & 1, p1 = (k + 1) & 1;
     const int kn = k + 1 < g.n[2] ? k + 1 : k + 1 - g.n[2];
     put(p1, kn, nEo, nEoe, nEov, uk1, wk1, nEr, nEre, nErv);
+    // D of plane k: own cell (psi adjoint updated: psi <- b (w + psi)) and low-y halo
+    {
+      const T wy = -wk[1], wz = wk[2];
+      T dy = wy, dz = wz;
+      if (xl) {
+        const unsigned pk = pb + nlny * (unsigned)k;
+        dy = dbar(0, wy, nP[0]);
+        dz = dbar(0, wz, nP[1]);
+        p.psi_out[pk] = xc[0][0][tx] * (wy + nP[0]);
+        p.psi_out[P + pk] = xc[0][0][tx] * (wz + nP[1]);
+      }
+      dL[0][oslot] = dy;
+      dL[1][oslot] = dz;
+      if (ty == 0) {
+        const T why = -W_at(p0, 1, tx, -1);
+        dL[0][tx + 1] = xhl ? dbar(0, why, nPy) : why;
+      }
+    }
     T hx = nH[0], hy = nH[1], hz = nH[2];
     const T hxh_y = nHx[0], hxh_z = nHx[1], hyh_x = nHy[0], hyh_z = nHy[1];
     if (k + 1 < k1) {  // the chunk's last plane needs neither W(k+2) nor Hb(k+1)
@@ -192,15 +268,28 @@ __global__ __launch_bounds__(64 * TY) void k_adj_fused(AdjFused<T> p, Geom g, Bo
       const T dWz_dy = W_at(p0, 2, tx, ty + 1) - wk[2];
       const T dWy_dz = wk1[1] - wk[1];
       const T dWx_dz = wk1[0] - wk[0];
-      const T dWz_dx = W_at(p0, 2, tx + 1, ty) - wk[2];
-      const T dWy_dx = W_at(p0, 1, tx + 1, ty) - wk[1];
       const T dWx_dy = W_at(p0, 0, tx, ty + 1) - wk[0];
+      // x-terms: D(cell) - D(cell + x), D = +W_z (y component), -W_y (z component)
       hx += idx * (dWz_dy - dWy_dz);
-      hy += idx * (dWx_dz - dWz_dx);
-      hz += idx * (dWy_dx - dWx_dy);
+      hy += idx * (dWx_dz + (dL[1][oslot] - D_at(p0, 1, tx + 1, ty)));
+      hz += idx * ((dL[0][oslot] - D_at(p0, 0, tx + 1, ty)) - dWx_dy);
       p.Ho[0][id] = hx;
       p.Ho[1][id] = hy;
       p.Ho[2][id] = hz;
+    }
+    // G of the own cell: x-terms of the transposed H update (psi adjoint updated)
+    {
+      const T wy = dt * hy, wz = -dt * hz;
+      T gy = wy, gz = wz;
+      if (xl) {
+        const unsigned pk = pb + nlny * (unsigned)k;
+        gy = dbar(1, wy, nP[2]);
+        gz = dbar(1, wz, nP[3]);
+        p.psi_out[2 * P + pk] = xc[1][0][tx] * (wy + nP[2]);
+        p.psi_out[3 * P + pk] = xc[1][0][tx] * (wz + nP[3]);
+      }
+      gL[0][(ty + 1) * HW + tx + 1] = gy;
+      gL[1][(ty + 1) * HW + tx + 1] = gz;
     }
     hL[0][(ty + 1) * HW + tx + 1] = hx;
     hL[1][(ty + 1) * HW + tx + 1] = hy;
@@ -210,14 +299,14 @@ __global__ __launch_bounds__(64 * TY) void k_adj_fused(AdjFused<T> p, Geom g, Bo
       T hyh = T(0), hzh = T(0);
       if (hx_on) {
         const T dWx_dz = W_at(p1, 0, -1, ty) - W_at(p0, 0, -1, ty);
-        const T dWz_dx = W_at(p0, 2, 0, ty) - W_at(p0, 2, -1, ty);
-        const T dWy_dx = W_at(p0, 1, 0, ty) - W_at(p0, 1, -1, ty);
         const T dWx_dy = W_at(p0, 0, -1, ty + 1) - W_at(p0, 0, -1, ty);
-        hyh = hxh_y + idx * (dWx_dz - dWz_dx);
-        hzh = hxh_z + idx * (dWy_dx - dWx_dy);
+        hyh = hxh_y + idx * (dWx_dz + (D_at(p0, 1, -1, ty) - D_at(p0, 1, 0, ty)));
+        hzh = hxh_z + idx * ((D_at(p0, 0, -1, ty) - D_at(p0, 0, 0, ty)) - dWx_dy);
       }
       hL[1][(ty + 1) * HW] = hyh;
       hL[2][(ty + 1) * HW] = hzh;
+      gL[0][(ty + 1) * HW] = dt * hyh;   // the halo column lies outside the x layers
+      gL[1][(ty + 1) * HW] = -dt * hzh;
     }
     // halo Hb' at y0-1 (x and z components) for the own column, by the first wave
     if (ty == 0) {
@@ -225,10 +314,9 @@ __global__ __launch_bounds__(64 * TY) void k_adj_fused(AdjFused<T> p, Geom g, Bo
       if (hy_on) {
         const T dWz_dy = W_at(p0, 2, tx, 0) - W_at(p0, 2, tx, -1);
         const T dWy_dz = W_at(p1, 1, tx, -1) - W_at(p0, 1, tx, -1);
-        const T dWy_dx = W_at(p0, 1, tx + 1, -1) - W_at(p0, 1, tx, -1);
         const T dWx_dy = W_at(p0, 0, tx, 0) - W_at(p0, 0, tx, -1);
         hxh = hyh_x + idx * (dWz_dy - dWy_dz);
-        hzh = hyh_z + idx * (dWy_dx - dWx_dy);
+        hzh = hyh_z + idx * ((D_at(p0, 0, tx, -1) - D_at(p0, 0, tx + 1, -1)) - dWx_dy);
       }
       hL[0][tx + 1] = hxh;
       hL[2][tx + 1] = hzh;
@@ -240,13 +328,13 @@ __global__ __launch_bounds__(64 * TY) void k_adj_fused(AdjFused<T> p, Geom g, Bo
       const T dHz_dy = hz - hL[2][ty * HW + tx + 1];
       const T dHy_dz = hy - hpy;
       const T dHx_dz = hx - hpx;
-      const T dHz_dx = hz - hL[2][(ty + 1) * HW + tx];
-      const T dHy_dx = hy - hL[1][(ty + 1) * HW + tx];
       const T dHx_dy = hx - hL[0][ty * HW + tx + 1];
       const T cf = -dt * idx;
+      // x-terms: G(cell - x) - G(cell), G = dt Hb'_y (z component), -dt Hb'_z (y)
+      const int sw = (ty + 1) * HW + tx;
       p.Eo[0][id] = uk[0] + cf * (dHz_dy - dHy_dz);
-      p.Eo[1][id] = uk[1] + cf * (dHx_dz - dHz_dx);
-      p.Eo[2][id] = uk[2] + cf * (dHy_dx - dHx_dy);
+      p.Eo[1][id] = uk[1] + (cf * dHx_dz + idx * (gL[1][sw] - gL[1][sw + 1]));
+      p.Eo[2][id] = uk[2] + (idx * (gL[0][sw] - gL[0][sw + 1]) - cf * dHx_dy);
     }
     hpx = hx;
     hpy = hy;
@@ -255,18 +343,28 @@ __global__ __launch_bounds__(64 * TY) void k_adj_fused(AdjFused<T> p, Geom g, Bo
       wk[c] = wk1[c];
       uk[c] = uk1[c];
     }
+    prefetch_psi(k + 1);
   }
 }
 
 // Box of the fused transposed sweep: per axis, one cell of margin above the low
 // CPML layers and one below the high layers (none on an axis without layers on
 // that side).
+// Along x every column when the low-x halo column (x = 64t - 1, t >= 1) and the
+// high-x ring column (x = 64t, t < number of tiles) of every tile lie outside the
+// x layers and the x psi arrays index in 32 bits.
 Box adj_interior_box(const Geom& g) {
   Box b{};
   for (int a = 0; a < 3; ++a) {
     b.lo[a] = g.nlo[a] > 0 ? g.nlo[a] + 1 : 0;
     b.hi[a] = g.nhi[a] > 0 ? g.n[a] - g.nhi[a] - 1 : g.n[a];
     if (b.hi[a] < b.lo[a]) b.hi[a] = b.lo[a];
+  }
+  const int n = g.n[0], ntx = (n + 63) / 64;
+  if (has_cpml(g, 0) && g.nlo[0] <= 63 && 64 * (ntx - 1) < n - g.nhi[0] &&
+      (double)(g.nlo[0] + g.nhi[0]) * g.n[1] * g.n[2] < 4294967296.0) {
+    b.lo[0] = 0;
+    b.hi[0] = n;
   }
   return b;
 }
@@ -286,6 +384,9 @@ static hipError_t launch_adj_fused(const AdjSweep<T>& a, const Geom& g, const Bo
     p.Ho[c] = a.Ho[c];
   }
   p.epsinv = a.epsinv;
+  p.tab = a.tab;
+  p.psi_in = a.psi[0];
+  p.psi_out = a.psi[1];
   const int ntx = (box.hi[0] - (box.lo[0] & ~31) + 63) / 64, nty = (ey + TY - 1) / TY;
   const int nblocks = ntx * nty * ((ez + kz - 1) / kz);
   hipLaunchKernelGGL((k_adj_fused<T, TY>), dim3(nblocks), dim3(64 * TY), 0, st, p, g, box, kz,
