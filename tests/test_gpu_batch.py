@@ -150,7 +150,8 @@ def test_tile_shape_changes_speed_not_results(tmp_path):
     say(f"  autotuned (ty, kz) = {t}")
     assert t[0] in (4, 8, 16) and t[1] >= 1
     d = mlk().from_workload(w)
-    assert d.autotune(cache) == t  # read back from the cache
+    assert d.autotune(cache) == t  # read back from the cache, layer mode included
+    assert d.sweep_layers() == a.sweep_layers()
     import json
     entries = json.load(open(cache))
     assert len(entries) == 1
