@@ -58,12 +58,6 @@ constexpr int kLanesPerEmitter = 8;  // = kMaxWin: one lane per window x offset
 constexpr int kThreads = 512;
 constexpr int kGroups = kThreads / kLanesPerEmitter;  // emitters in flight per workgroup
 
-__device__ __forceinline__ int wrap_once(int q, int n) {
-  q += q < 0 ? n : 0;
-  q -= q >= n ? n : 0;
-  return q;
-}
-
 __device__ __forceinline__ double wave_sum64(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -299,6 +293,11 @@ struct Acc<double> {
 // E_c(p) -= [eps_r^-1(p) if EPS] amp0 gamma a^c w^c_p over the windows, with
 // a = mudot (the forward current: amp0 = dt / dx^3, EPS) or any other per-emitter
 // amplitude (the adjoint step: amp0 = -1, no EPS).
+//
+// A pair (emitter, bin) comes with its window's runs inside the bin, one per
+// axis, set up on the host (see PairDesc): window offsets d0 .. d0+c-1 on the
+// bin-local cells l0 .. l0+c-1.  A window that wraps inside one bin (a periodic
+// axis no longer than the bin) is split into several pairs.
 template <typename T, bool EPS = true>
 __device__ __forceinline__ void scatter_body(const FieldPtrs<T>& f, const Geom& g,
                                              const BinPtrs& bins, const WindowPtrs<T>& win,
@@ -309,12 +308,14 @@ __device__ __forceinline__ void scatter_body(const FieldPtrs<T>& f, const Geom& 
   constexpr int NW = kThreads / 64;
   constexpr int R4 = sizeof(WinRec<T>) / sizeof(int4);       // 16-byte pieces of a record
   constexpr int NP = (kGroups * R4 + kThreads - 1) / kThreads;  // pieces per thread and chunk
-  // pair ids of a bin kept in LDS (beyond: read from HBM); sized so that two
-  // workgroups still fit one CU's LDS
+  static_assert(BX <= 16 && BY <= 16 && BZ <= 16, "bin-local run starts take four bits");
+  // emitter ids of a bin's pairs kept in LDS (beyond: read from HBM); sized so
+  // that two workgroups still fit one CU's LDS
   constexpr int kIdCap = sizeof(T) == 4 ? 4096 : 1024;
   __shared__ typename A::U sJ[3][CELLS];
   __shared__ WinRec<T> sW[kGroups];
   __shared__ T sAmp[kGroups][3];
+  __shared__ unsigned sRun[kGroups];
   __shared__ int sId[kIdCap];
   __shared__ double sRed[NW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -330,10 +331,10 @@ __device__ __forceinline__ void scatter_body(const FieldPtrs<T>& f, const Geom& 
   }
   double bound = 0.0;
   for (int q = q0 + tid; q < q1; q += kThreads) {
-    const int e = bins.sbin_em[q];
-    if (q - q0 < kIdCap) sId[q - q0] = e;
-    const double ge = fabs(amp0 * win.gamma[e]) * (double)win.rec[e].wmax;
-    bound += ge * (fabs(mudot[3 * e]) + fabs(mudot[3 * e + 1]) + fabs(mudot[3 * e + 2]));
+    const int4 pd = bins.sbin_pair[q];
+    if (q - q0 < kIdCap) sId[q - q0] = pd.x;
+    bound += (double)__int_as_float(pd.z) *
+             (fabs(mudot[3 * pd.x]) + fabs(mudot[3 * pd.x + 1]) + fabs(mudot[3 * pd.x + 2]));
   }
   bound = wave_sum64(bound);
   if (lane == 0) sRed[wave] = bound;
@@ -341,6 +342,7 @@ __device__ __forceinline__ void scatter_body(const FieldPtrs<T>& f, const Geom& 
   bound = 0.0;
 #pragma unroll
   for (int w = 0; w < NW; ++w) bound += sRed[w];
+  bound *= fabs(amp0);
   if (!(bound > 0.0)) return;  // nothing to add in this bin (uniform across the block)
   // scale = 2^(BITS - e) with bound < 2^e: every partial sum stays below 2^BITS
   const int ebits = ilogb(bound) + 1;
@@ -348,7 +350,7 @@ __device__ __forceinline__ void scatter_body(const FieldPtrs<T>& f, const Geom& 
   const double inv_scale = ldexp(1.0, ebits - A::BITS);
 
   // The pairs are taken in chunks of kGroups.  With FP32 fields the next
-  // chunk's window records and amplitudes (gamma, mu_dot) are loaded into
+  // chunk's window records, runs and amplitudes (gamma, mu_dot) are loaded into
   // registers while the current chunk is summed, and moved to LDS behind an
   // LDS-only barrier, so their HBM latency overlaps the atomics instead of
   // stalling every chunk.  FP64 records are twice as large: holding them across
@@ -358,31 +360,31 @@ __device__ __forceinline__ void scatter_body(const FieldPtrs<T>& f, const Geom& 
   typedef int piece_t __attribute__((ext_vector_type(4)));  // kept in registers
   piece_t piece[NP];
   double pg = 0.0, pm0 = 0.0, pm1 = 0.0, pm2 = 0.0;
-  // Eight lanes per (emitter, bin) pair, lane i on window x offset i.  The
-  // window rows (y) and planes (z) inside the bin are given as bit masks over
-  // the window offsets; the group walks exactly its cj x ck of them (the r-th
-  // set bit first moved, with its weights and LDS offset, into register r), so
-  // a wavefront runs its eight groups' loops side by side for as many steps as
-  // its longest group, and the host orders the pairs of a bin by (ck, cj) so
-  // that neighbouring groups have equal counts.
+  unsigned prun = 0;
+  // Eight lanes per pair, lane i on the i-th window x offset of the pair's x run;
+  // the group walks the cy x cz rows and planes of its y and z runs, so a
+  // wavefront runs its eight groups' loops side by side for as many steps as its
+  // longest group; the host orders the pairs of a bin by (cz, cy) so that
+  // neighbouring groups have equal counts.
   const int grp = tid / kLanesPerEmitter, i = tid % kLanesPerEmitter;
   // loads of the chunk at c: pieces (clamped to the chunk's last record) and, for
-  // tid < the chunk size, the amplitude inputs of pair tid
+  // tid < the chunk size, the runs and amplitude inputs of pair tid
 #define MLK_STAGE_LOAD(c)                                                             \
   {                                                                                  \
     const int cl = min(kGroups, q1 - (c)) - 1;                                       \
     _Pragma("unroll") for (int p = 0; p < NP; ++p) {                                 \
       const int idx = tid + p * kThreads, sl = min(idx / R4, cl);                    \
       const int q = (c) + sl;                                                        \
-      const int em = q - q0 < kIdCap ? sId[q - q0] : bins.sbin_em[q];                \
+      const int em = q - q0 < kIdCap ? sId[q - q0] : bins.sbin_pair[q].x;            \
       piece[p] = reinterpret_cast<const piece_t*>(win.rec + em)[idx % R4];           \
     }                                                                                \
     const int q = (c) + min(tid, cl);                                                \
-    const int em = q - q0 < kIdCap ? sId[q - q0] : bins.sbin_em[q];                  \
-    pg = win.gamma[em];                                                              \
-    pm0 = mudot[3 * em];                                                             \
-    pm1 = mudot[3 * em + 1];                                                         \
-    pm2 = mudot[3 * em + 2];                                                         \
+    const int4 pd = bins.sbin_pair[q];                                               \
+    prun = (unsigned)pd.y;                                                           \
+    pg = win.gamma[pd.x];                                                            \
+    pm0 = mudot[3 * pd.x];                                                           \
+    pm1 = mudot[3 * pd.x + 1];                                                       \
+    pm2 = mudot[3 * pd.x + 2];                                                       \
   }
   if (kPipe) MLK_STAGE_LOAD(q0)
   for (int c0 = q0; c0 < q1; c0 += kGroups) {
@@ -399,51 +401,41 @@ __device__ __forceinline__ void scatter_body(const FieldPtrs<T>& f, const Geom& 
       sAmp[tid][0] = (T)(ge * pm0);
       sAmp[tid][1] = (T)(ge * pm1);
       sAmp[tid][2] = (T)(ge * pm2);
+      sRun[tid] = prun;
     }
     lds_barrier();
     if (kPipe && c0 + kGroups < q1) MLK_STAGE_LOAD(c0 + kGroups)
     if (grp >= cn) continue;
+    const unsigned run = sRun[grp];
+    const int nx = ((run >> 7) & 7) + 1;
+    if (i >= nx) continue;
     const WinRec<T>& w = sW[grp];
-    unsigned jm = 0, km = 0;
-#pragma unroll
-    for (int d = 0; d < kMaxWin; ++d) {
-      const int lj = wrap_once(w.org[1] + d, g.n[1]) - y0;
-      const int lk = wrap_once(w.org[2] + d, g.n[2]) - z0;
-      jm |= (d < w.n[1] && lj >= 0 && lj < ey) ? 1u << d : 0u;
-      km |= (d < w.n[2] && lk >= 0 && lk < ez) ? 1u << d : 0u;
-    }
-    const int li = wrap_once(w.org[0] + i, g.n[0]) - x0;
-    if (!(i < w.n[0] && li >= 0 && li < ex) || jm == 0 || km == 0) continue;
-    const int cj = __builtin_popcount(jm), ck = __builtin_popcount(km);
-    int rowoff[kMaxWin], planeoff[kMaxWin];
+    const int li = (run & 15) + i, dxi = ((run >> 4) & 7) + i;
+    const int ly0 = (run >> 10) & 15, dy0 = (run >> 14) & 7, cj = ((run >> 17) & 7) + 1;
+    const int lz0 = (run >> 20) & 15, dz0 = (run >> 24) & 7, ck = ((run >> 27) & 7) + 1;
     T wy0[kMaxWin], wy1[kMaxWin], wz0[kMaxWin], wz1[kMaxWin];
-    unsigned mj = jm, mk = km;
 #pragma unroll
     for (int r = 0; r < kMaxWin; ++r) {
-      // offset of the r-th set bit (the last offset once the mask is spent)
-      const int ry = mj ? __builtin_ctz(mj) : kMaxWin - 1;
-      const int rz = mk ? __builtin_ctz(mk) : kMaxWin - 1;
-      mj &= mj - 1u;
-      mk &= mk - 1u;
-      rowoff[r] = BX * (wrap_once(w.org[1] + ry, g.n[1]) - y0);
-      planeoff[r] = BX * BY * (wrap_once(w.org[2] + rz, g.n[2]) - z0);
-      wy0[r] = w.wr[1][0][ry];
-      wy1[r] = w.wr[1][1][ry];
-      wz0[r] = w.wr[2][0][rz];
-      wz1[r] = w.wr[2][1][rz];
+      // offsets past the run are clamped into the record and never used
+      const int dy = min(dy0 + r, kMaxWin - 1), dz = min(dz0 + r, kMaxWin - 1);
+      wy0[r] = w.wr[1][0][dy];
+      wy1[r] = w.wr[1][1][dy];
+      wz0[r] = w.wr[2][0][dz];
+      wz1[r] = w.wr[2][1][dz];
     }
-    const T cx = sAmp[grp][0] * w.wr[0][1][i];
-    const T cy = sAmp[grp][1] * w.wr[0][0][i];
-    const T cz = sAmp[grp][2] * w.wr[0][0][i];
+    const T cx = sAmp[grp][0] * w.wr[0][1][dxi];
+    const T cy = sAmp[grp][1] * w.wr[0][0][dxi];
+    const T cz = sAmp[grp][2] * w.wr[0][0][dxi];
+    const int base = BX * (ly0 + BY * lz0) + li;
 #pragma unroll
     for (int k = 0; k < kMaxWin; ++k) {
       if (k >= ck) break;
       const T cxk = cx * wz0[k], cyk = cy * wz0[k], czk = cz * wz1[k];
-      const int pk = planeoff[k] + li;
+      const int pk = base + BX * BY * k;
 #pragma unroll
       for (int j = 0; j < kMaxWin; ++j) {
         if (j >= cj) break;
-        const int s = pk + rowoff[j];
+        const int s = pk + BX * j;
         atomicAdd(&sJ[0][s], (typename A::U)A::round(cxk * wy0[j]));
         atomicAdd(&sJ[1][s], (typename A::U)A::round(cyk * wy1[j]));
         atomicAdd(&sJ[2][s], (typename A::U)A::round(czk * wy0[j]));

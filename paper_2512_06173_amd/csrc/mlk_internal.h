@@ -226,9 +226,24 @@ struct BinPtrs {
   const int* gbin_em;       // emitter ids
   int nscatter;             // scatter bins touched by at least one window
   const int* sbin_id;       // [nscatter]
-  const int* sbin_start;    // [nscatter+1] CSR into sbin_em
-  const int* sbin_em;       // emitter id of each pair
+  const int* sbin_start;    // [nscatter+1] CSR into sbin_pair
+  const int4* sbin_pair;    // one PairDesc per (emitter, bin) pair
 };
+
+// A scatter pair: emitter e and, per axis a, the run of its union window inside
+// the bin: window offsets d0 .. d0+c-1 on the bin-local cells l0 .. l0+c-1, packed
+// as l0 | d0 << 4 | (c-1) << 7 at bit 10a of runs.  gw = |gamma| times the
+// record's wmax, rounded up to FP32 (the per-bin bound of the fixed-point grid).
+struct PairDesc {
+  int e;
+  unsigned runs;
+  float gw;
+  int pad;
+};
+static_assert(sizeof(PairDesc) == 16, "a pair is loaded as one int4");
+inline unsigned pack_run(int l0, int d0, int c) {
+  return (unsigned)l0 | (unsigned)d0 << 4 | (unsigned)(c - 1) << 7;
+}
 
 // ---------------------------------------------------------------- batches
 // A batched launch covers the jobs of several domains: job j owns blocks

@@ -138,7 +138,7 @@ struct mlk_sim {
   int* d_gbin_em = nullptr;
   int* d_sbin_id = nullptr;
   int* d_sbin_start = nullptr;
-  int* d_sbin_em = nullptr;
+  PairDesc* d_sbin_pair = nullptr;
   int* d_tls_slot = nullptr;
 
   SourceSet src{};
@@ -296,8 +296,27 @@ BinPtrs bin_ptrs(const mlk_sim* s) {
   b.nscatter = s->nscatter;
   b.sbin_id = s->d_sbin_id;
   b.sbin_start = s->d_sbin_start;
-  b.sbin_em = s->d_sbin_em;
+  b.sbin_pair = reinterpret_cast<const int4*>(s->d_sbin_pair);
   return b;
+}
+
+// Union windows of the emitters as the binned kernels see them: origin and
+// length per axis and the largest 3-D weight, read back from the records.
+template <typename T>
+mlk_status read_unions(const mlk_sim* s, std::vector<int>& org, std::vector<int>& n,
+                       std::vector<double>& wmax) {
+  std::vector<WinRec<T>> rec(s->nem);
+  if (s->nem > 0)
+    HIPCHK(hipMemcpy(rec.data(), s->d_rec, rec.size() * sizeof(WinRec<T>),
+                     hipMemcpyDeviceToHost));
+  for (int e = 0; e < s->nem; ++e) {
+    for (int a = 0; a < 3; ++a) {
+      org[3 * e + a] = rec[e].org[a];
+      n[3 * e + a] = rec[e].n[a];
+    }
+    wmax[e] = rec[e].wmax;
+  }
+  return MLK_OK;
 }
 
 // Emitter bins (index bookkeeping only).  Gather bins group emitters by the
@@ -313,9 +332,6 @@ mlk_status build_bins(mlk_sim* s) {
   s->nby = nb[1];
   s->nbz = nb[2];
   const int M = s->nem;
-  std::vector<int> lo((size_t)M * 6), len((size_t)M * 6);
-  HIPCHK(hipMemcpy(lo.data(), s->d_wlo, lo.size() * sizeof(int), hipMemcpyDeviceToHost));
-  HIPCHK(hipMemcpy(len.data(), s->d_wlen, len.size() * sizeof(int), hipMemcpyDeviceToHost));
 
   // gather: key = bin of the (unwrapped) centre cell
   struct Key {
@@ -347,31 +363,62 @@ mlk_status build_bins(mlk_sim* s) {
   gstart.push_back(M);
   s->ngather = (int)gstart.size() - 1;
 
-  // scatter: bins touched by the union of each emitter's windows
-  const size_t nball = (size_t)nb[0] * nb[1] * nb[2];
-  std::vector<std::vector<int>> per_em(M);
-  for (int e = 0; e < M; ++e) {
-    std::vector<int> ax[3];
-    for (int a = 0; a < 3; ++a) {
-      const int s0 = win_slot(e, a, 0), s1 = win_slot(e, a, 1);
-      const int u0 = std::min(lo[s0], lo[s1]);
-      const int u1 = std::max(lo[s0] + len[s0], lo[s1] + len[s1]);
-      for (int q = u0; q < u1; ++q) {
-        int w = q % g.n[a];
-        if (w < 0) w += g.n[a];
-        const int bq = w / B[a];
-        if (std::find(ax[a].begin(), ax[a].end(), bq) == ax[a].end()) ax[a].push_back(bq);
+  // scatter: the union window of each emitter (org, n per axis, as in its
+  // record) split, per axis, into runs inside one bin: consecutive window
+  // offsets on consecutive cells.  A pair is one run per axis; a window wraps
+  // inside a bin only on a periodic axis no longer than the bin, where it gives
+  // two runs.
+  std::vector<int> worg((size_t)M * 3), wn((size_t)M * 3);
+  std::vector<double> wmax(M);
+  if (s->fp32)
+    STCHK(read_unions<float>(s, worg, wn, wmax));
+  else
+    STCHK(read_unions<double>(s, worg, wn, wmax));
+  struct Run {
+    int bin, l0, d0, c;
+  };
+  auto runs_of = [&](int e, int a, std::vector<Run>& out) {
+    out.clear();
+    for (int d = 0; d < wn[3 * e + a]; ++d) {
+      int w = (worg[3 * e + a] + d) % g.n[a];
+      if (w < 0) w += g.n[a];
+      const int bq = w / B[a], l = w - bq * B[a];
+      if (!out.empty()) {
+        Run& r = out.back();
+        if (r.bin == bq && r.d0 + r.c == d && r.l0 + r.c == l) {
+          ++r.c;
+          continue;
+        }
       }
+      out.push_back({bq, l, d, 1});
     }
-    for (int bz : ax[2])
-      for (int by : ax[1])
-        for (int bx : ax[0]) per_em[e].push_back(bx + nb[0] * (by + nb[1] * bz));
+  };
+  const size_t nball = (size_t)nb[0] * nb[1] * nb[2];
+  std::vector<std::vector<std::pair<int, PairDesc>>> per_em(M);  // (bin, pair)
+  std::vector<Run> rx, ry, rz;
+  for (int e = 0; e < M; ++e) {
+    runs_of(e, 0, rx);
+    runs_of(e, 1, ry);
+    runs_of(e, 2, rz);
+    float gw = (float)(std::fabs(s->gamma[e]) * wmax[e]);
+    if ((double)gw < std::fabs(s->gamma[e]) * wmax[e]) gw = std::nextafter(gw, INFINITY);
+    for (const Run& z : rz)
+      for (const Run& y : ry)
+        for (const Run& x : rx) {
+          PairDesc pd;
+          pd.e = e;
+          pd.runs = pack_run(x.l0, x.d0, x.c) | pack_run(y.l0, y.d0, y.c) << 10 |
+                    pack_run(z.l0, z.d0, z.c) << 20;
+          pd.gw = gw;
+          pd.pad = 0;
+          per_em[e].push_back({x.bin + nb[0] * (y.bin + nb[1] * z.bin), pd});
+        }
   }
   std::vector<int> count(nball, 0);
   size_t npairs = 0;
   for (int e = 0; e < M; ++e)
-    for (int b : per_em[e]) {
-      ++count[b];
+    for (const auto& bp : per_em[e]) {
+      ++count[bp.first];
       ++npairs;
     }
   if (npairs > (size_t)INT32_MAX) return fail(MLK_EUNSUPPORTED, "too many emitter-bin pairs");
@@ -382,45 +429,21 @@ mlk_status build_bins(mlk_sim* s) {
       sid.push_back((int)b);
       sstart.push_back(sstart.back() + count[b]);
     }
-  std::vector<int> fill(sstart.begin(), sstart.end() - 1), sem(npairs);
+  std::vector<int> fill(sstart.begin(), sstart.end() - 1);
+  std::vector<PairDesc> spair(npairs);
   // emitters in gather order, so neighbouring pairs touch neighbouring windows
-  for (int q = 0; q < M; ++q) {
-    const int e = gem[q];
-    for (int b : per_em[e]) sem[fill[slot_of[b]]++] = e;
-  }
-  // within a bin, pairs by decreasing numbers of window planes (z), then rows
-  // (y), inside it: the workgroup runs eight pairs per wavefront side by side,
-  // each looping over its own planes and rows, so equal counts keep its lanes
-  // busy (stable: ties stay in gather order)
-  {
-    auto overlap = [&](int e, int a, int bq) {
-      const int s0 = win_slot(e, a, 0), s1 = win_slot(e, a, 1);
-      const int u0 = std::min(lo[s0], lo[s1]);
-      const int u1 = std::max(lo[s0] + len[s0], lo[s1] + len[s1]);
-      int c = 0;
-      for (int q = u0; q < u1; ++q) {
-        int w = q % g.n[a];
-        if (w < 0) w += g.n[a];
-        c += (w / B[a]) == bq;
-      }
-      return c;
+  for (int q = 0; q < M; ++q)
+    for (const auto& bp : per_em[gem[q]]) spair[fill[slot_of[bp.first]]++] = bp.second;
+  // within a bin, pairs by decreasing numbers of planes (z), then rows (y): the
+  // workgroup runs eight pairs per wavefront side by side, each looping over its
+  // own planes and rows, so equal counts keep its lanes busy (stable: ties stay
+  // in gather order)
+  for (size_t sl = 0; sl < sid.size(); ++sl) {
+    auto rows = [](const PairDesc& p) {
+      return 16 * (int)((p.runs >> 27) & 7) + (int)((p.runs >> 17) & 7);
     };
-    std::vector<std::pair<int, int>> tmp;
-    for (size_t sl = 0; sl < sid.size(); ++sl) {
-      const int b = sid[sl];
-      const int bx = b % nb[0], by = (b / nb[0]) % nb[1], bz = b / (nb[0] * nb[1]);
-      tmp.clear();
-      for (int q = sstart[sl]; q < sstart[sl + 1]; ++q) {
-        const int e = sem[q];
-        const int rows = overlap(e, 0, bx) > 0 ? 16 * overlap(e, 2, bz) + overlap(e, 1, by) : 0;
-        tmp.push_back({-rows, e});
-      }
-      std::stable_sort(tmp.begin(), tmp.end(),
-                       [](const std::pair<int, int>& x, const std::pair<int, int>& y) {
-                         return x.first < y.first;
-                       });
-      for (size_t q = 0; q < tmp.size(); ++q) sem[sstart[sl] + q] = tmp[q].second;
-    }
+    std::stable_sort(spair.begin() + sstart[sl], spair.begin() + sstart[sl + 1],
+                     [&](const PairDesc& x, const PairDesc& y) { return rows(x) > rows(y); });
   }
   s->nscatter = (int)sid.size();
   STCHK(upload(&s->d_gbin_org, gorg));
@@ -428,7 +451,7 @@ mlk_status build_bins(mlk_sim* s) {
   STCHK(upload(&s->d_gbin_em, gem));
   STCHK(upload(&s->d_sbin_id, sid));
   STCHK(upload(&s->d_sbin_start, sstart));
-  STCHK(upload(&s->d_sbin_em, sem));
+  STCHK(upload(&s->d_sbin_pair, spair));
   STCHK(upload(&s->d_tls_slot, s->tls_slot));
   return MLK_OK;
 }
@@ -783,7 +806,7 @@ void release(mlk_sim* s) {
   dfree(s->d_gbin_em);
   dfree(s->d_sbin_id);
   dfree(s->d_sbin_start);
-  dfree(s->d_sbin_em);
+  dfree(s->d_sbin_pair);
   dfree(s->d_tls_slot);
   dfree(s->d_probe);
   dfree(s->d_flux_series);
