@@ -3,11 +3,11 @@
 // gather (eq. E_regu_Emi): the emitters are grouped by the bin of their
 // centre cell.  The workgroup of a bin stages E over the bin plus a halo of
 // kHalo cells in LDS, which holds every window of its emitters.  Eight lanes
-// serve one emitter, lane i taking the x offset i of its window: a lane sums
-// the window rows along y in the field precision, weights them along z into
-// FP64, and the eight lanes of the emitter add up their sums (FP64).  Bins are
-// handed out XCD by XCD so that neighbouring bins, whose halos overlap, share
-// one L2.
+// (FP32 fields) or sixteen (FP64) serve one emitter, lane (i, h) taking the x
+// offset i of its window and the h-th share of its rows: a lane sums its rows
+// along y in the field precision, weights them along z into FP64, and the
+// lanes of the emitter add up their sums (FP64).  Bins are handed out XCD by XCD so that neighbouring bins, whose
+// halos overlap, share one L2.
 //
 // step (eq. von-Neumann-tls, eq. dipole_derivative): one thread per two-level
 // emitter advances its state with the exact propagator and writes mu_dot.
@@ -57,6 +57,20 @@ namespace {
 constexpr int kLanesPerEmitter = 8;  // = kMaxWin: one lane per window x offset
 constexpr int kThreads = 512;
 constexpr int kGroups = kThreads / kLanesPerEmitter;  // emitters in flight per workgroup
+// Gather launch shape.  The tile fill is latency-bound, so FP32 (small register
+// footprint) runs sixteen wavefronts per bin, two workgroups per CU (LDS and
+// registers: at most 64 VGPRs, eight wavefronts per SIMD).  An emitter takes
+// `lanes` lanes: lane (i, h) on window x offset i and rows h*rows ..
+// h*rows+rows-1.  FP64 splits the rows over sixteen lanes, which halves the
+// chain of each lane's sums and its registers; measured, FP32 is faster with
+// eight.
+template <typename T>
+struct GatherCfg {
+  static constexpr int threads = sizeof(T) == 4 ? 1024 : 512;
+  static constexpr int waves_per_simd = sizeof(T) == 4 ? 8 : 1;
+  static constexpr int lanes = sizeof(T) == 4 ? 8 : 16;
+  static constexpr int rows = kMaxWin * kLanesPerEmitter / lanes;
+};
 
 __device__ __forceinline__ double wave_sum64(double v) {
 #pragma unroll
@@ -64,25 +78,26 @@ __device__ __forceinline__ double wave_sum64(double v) {
   return v;
 }
 
-__device__ __forceinline__ double group_sum8(double v) {
-  v += __shfl_xor(v, 4, kLanesPerEmitter);
-  v += __shfl_xor(v, 2, kLanesPerEmitter);
-  v += __shfl_xor(v, 1, kLanesPerEmitter);
+// sum over the L consecutive lanes of one gather emitter
+template <int L>
+__device__ __forceinline__ double gather_lane_sum(double v) {
+#pragma unroll
+  for (int off = L / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, L);
   return v;
 }
 
-// The part of an emitter's window record that one of its eight lanes needs,
-// in registers: the union window, the lane's own x weights and every y and z
-// weight (the eight lanes read the same record, one cache line at a time).
+// The part of an emitter's window record that one gather lane needs, in
+// registers: the union window, the lane's own x weights, the y weights of its
+// rows and every z weight (the lanes of an emitter read the same record).
 template <typename T>
 struct LaneWin {
   int org[3], n[3];
   T wx0, wx1;
-  T wy[2][kMaxWin], wz[2][kMaxWin];
+  T wy[2][GatherCfg<T>::rows], wz[2][kMaxWin];
 };
 
 template <typename T>
-__device__ __forceinline__ void load_lane_win(const WinRec<T>& r, int i, LaneWin<T>& w) {
+__device__ __forceinline__ void load_lane_win(const WinRec<T>& r, int i, int j0, LaneWin<T>& w) {
   const int4 o = *reinterpret_cast<const int4*>(&r.org[0]);  // org[0..2], n[0]
   const int2 nn = *reinterpret_cast<const int2*>(&r.n[1]);
   w.org[0] = o.x;
@@ -94,12 +109,12 @@ __device__ __forceinline__ void load_lane_win(const WinRec<T>& r, int i, LaneWin
   w.wx0 = r.wr[0][0][i];
   w.wx1 = r.wr[0][1][i];
 #pragma unroll
-  for (int v = 0; v < 2; ++v)
+  for (int v = 0; v < 2; ++v) {
 #pragma unroll
-    for (int d = 0; d < kMaxWin; ++d) {
-      w.wy[v][d] = r.wr[1][v][d];
-      w.wz[v][d] = r.wr[2][v][d];
-    }
+    for (int d = 0; d < GatherCfg<T>::rows; ++d) w.wy[v][d] = r.wr[1][v][j0 + d];
+#pragma unroll
+    for (int d = 0; d < kMaxWin; ++d) w.wz[v][d] = r.wr[2][v][d];
+  }
 }
 
 }  // namespace
@@ -111,6 +126,8 @@ __device__ __forceinline__ void gather_body(const FieldPtrs<T>& f, const Geom& g
                                             const BinPtrs& bins, const WindowPtrs<T>& win,
                                             double* Et, int bid) {
   constexpr int BX = BinCfg<T>::GX, BY = BinCfg<T>::GY, BZ = BinCfg<T>::GZ;
+  constexpr int NT = GatherCfg<T>::threads, LG = GatherCfg<T>::lanes, NG = NT / LG;
+  constexpr int RG = GatherCfg<T>::rows;
   constexpr int TX = BX + 2 * kHalo, TY = BY + 2 * kHalo, TZ = BZ + 2 * kHalo;
   __shared__ T sE[3][TX * TY * TZ];
   const int tid = threadIdx.x;
@@ -124,12 +141,12 @@ __device__ __forceinline__ void gather_body(const FieldPtrs<T>& f, const Geom& g
   // store, so they are in flight together (unconditional loads from a safe
   // index; cells beyond a non-periodic face read as zero)
   constexpr int NTILE = TX * TY * TZ;
-  static_assert(NTILE % kThreads == 0, "the tile is a whole number of workgroup passes");
-  constexpr int RF = NTILE / kThreads;
+  static_assert(NTILE % NT == 0, "the tile is a whole number of workgroup passes");
+  constexpr int RF = NTILE / NT;
   T v[RF][3];
 #pragma unroll
   for (int r = 0; r < RF; ++r) {
-    const int t = tid + r * kThreads;
+    const int t = tid + r * NT;
     const int li = t % TX, lj = (t / TX) % TY, lk = t / (TX * TY);
     int q[3] = {x0 + li, y0 + lj, z0 + lk};
     bool ok = true;
@@ -156,7 +173,7 @@ __device__ __forceinline__ void gather_body(const FieldPtrs<T>& f, const Geom& g
   }
 #pragma unroll
   for (int r = 0; r < RF; ++r) {
-    const int t = tid + r * kThreads;
+    const int t = tid + r * NT;
     sE[0][t] = v[r][0];
     sE[1][t] = v[r][1];
     sE[2][t] = v[r][2];
@@ -164,22 +181,23 @@ __device__ __forceinline__ void gather_body(const FieldPtrs<T>& f, const Geom& g
 
   __syncthreads();
 
-  const int grp = tid / kLanesPerEmitter, i = tid % kLanesPerEmitter;
+  const int grp = tid / LG, i = tid % kLanesPerEmitter;
+  const int j0 = (tid / kLanesPerEmitter) % (LG / kLanesPerEmitter) * RG;
   const int q0 = bins.gbin_start[bin], q1 = bins.gbin_start[bin + 1];
-  for (int q = q0 + grp; q < q1; q += kGroups) {  // uniform across the eight lanes of a group
+  for (int q = q0 + grp; q < q1; q += NG) {  // uniform across the lanes of an emitter
     const int e = bins.gbin_em[q];
     LaneWin<T> w;
-    load_lane_win(win.rec[e], i, w);
+    load_lane_win(win.rec[e], i, j0, w);
     double ax = 0.0, ay = 0.0, az = 0.0;
     if (i < w.n[0]) {
-      const int ny = w.n[1], nz = w.n[2];
-      int s = (w.org[0] + i - x0) + TX * (w.org[1] - y0) + TX * TY * (w.org[2] - z0);
+      const int ny = w.n[1] - j0, nz = w.n[2];
+      int s = (w.org[0] + i - x0) + TX * (w.org[1] + j0 - y0) + TX * TY * (w.org[2] - z0);
 #pragma unroll
       for (int k = 0; k < kMaxWin; ++k, s += TX * TY) {
         if (k < nz) {
           T sx = T(0), sy = T(0), sz = T(0);
 #pragma unroll
-          for (int j = 0; j < kMaxWin; ++j) {
+          for (int j = 0; j < RG; ++j) {
             if (j < ny) {
               const int p = s + TX * j;
               sx += w.wy[0][j] * sE[0][p];
@@ -197,9 +215,9 @@ __device__ __forceinline__ void gather_body(const FieldPtrs<T>& f, const Geom& g
       ay *= (double)w.wx0;
       az *= (double)w.wx0;
     }
-    ax = group_sum8(ax);
-    ay = group_sum8(ay);
-    az = group_sum8(az);
+    ax = gather_lane_sum<LG>(ax);
+    ay = gather_lane_sum<LG>(ay);
+    az = gather_lane_sum<LG>(az);
     if (i == 0) {
       const double gm = win.gamma[e];
       Et[3 * e] = gm * ax;
@@ -210,13 +228,13 @@ __device__ __forceinline__ void gather_body(const FieldPtrs<T>& f, const Geom& g
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_gather_bins(FieldPtrs<T> f, Geom g, BinPtrs bins,
+__global__ __launch_bounds__(GatherCfg<T>::threads, GatherCfg<T>::waves_per_simd) void k_gather_bins(FieldPtrs<T> f, Geom g, BinPtrs bins,
                                                           WindowPtrs<T> win, double* Et) {
   gather_body(f, g, bins, win, Et, blockIdx.x);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_gather_batch(const GatherJob<T>* jobs,
+__global__ __launch_bounds__(GatherCfg<T>::threads, GatherCfg<T>::waves_per_simd) void k_gather_batch(const GatherJob<T>* jobs,
                                                            const int* start, int njobs) {
   const int j = find_job(start, njobs, blockIdx.x);
   const GatherJob<T>& J = jobs[j];
@@ -494,7 +512,7 @@ static hipError_t launch_gather_step(const FieldPtrs<T>& f, const Geom& g, const
                                      double* Et, double* mudot, const int64_t* pop_off,
                                      const Series& ser, const int64_t* step, hipStream_t st) {
   if (b.ngather <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather_bins<T>, dim3(b.ngather), dim3(kThreads), 0, st, f, g, b, win, Et);
+  hipLaunchKernelGGL(k_gather_bins<T>, dim3(b.ngather), dim3(GatherCfg<T>::threads), 0, st, f, g, b, win, Et);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || tls.count == 0) return e;
   hipLaunchKernelGGL(k_tls_step, dim3((tls.count + 255) / 256), dim3(256), 0, st, tls, g.dt, Et,
@@ -536,7 +554,7 @@ template <typename T>
 static hipError_t launch_gather_batch(const GatherJob<T>* jobs, const int* start, int njobs,
                                       int nblocks, hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather_batch<T>, dim3(nblocks), dim3(kThreads), 0, st, jobs, start, njobs);
+  hipLaunchKernelGGL(k_gather_batch<T>, dim3(nblocks), dim3(GatherCfg<T>::threads), 0, st, jobs, start, njobs);
   return hipGetLastError();
 }
 template <typename T>
@@ -571,7 +589,7 @@ hipError_t tls_batch(const TlsJob* jobs, const int* start, int njobs, int nblock
 
 // ---- adjoint-step variants
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_gather_epsw(FieldPtrs<T> f, Geom g, BinPtrs bins,
+__global__ __launch_bounds__(GatherCfg<T>::threads, GatherCfg<T>::waves_per_simd) void k_gather_epsw(FieldPtrs<T> f, Geom g, BinPtrs bins,
                                                           WindowPtrs<T> win, double* out) {
   gather_body<T, true>(f, g, bins, win, out, blockIdx.x);
 }
@@ -585,7 +603,7 @@ template <typename T>
 static hipError_t launch_gather_epsw(const FieldPtrs<T>& f, const Geom& g, const BinPtrs& b,
                                      const WindowPtrs<T>& win, double* out, hipStream_t st) {
   if (b.ngather <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather_epsw<T>, dim3(b.ngather), dim3(kThreads), 0, st, f, g, b, win, out);
+  hipLaunchKernelGGL(k_gather_epsw<T>, dim3(b.ngather), dim3(GatherCfg<T>::threads), 0, st, f, g, b, win, out);
   return hipGetLastError();
 }
 template <typename T>
