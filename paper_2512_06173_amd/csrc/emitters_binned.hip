@@ -463,7 +463,9 @@ __device__ __forceinline__ void scatter_body(const FieldPtrs<T>& f, const Geom& 
 #undef MLK_STAGE_LOAD
   __syncthreads();
   // owner write: E -= [eps^-1] J on the cells of this bin; the loads of a thread's
-  // cells are issued together (unconditional, from a safe index), then the stores
+  // cells are issued together (unconditional, from a safe index: cell 0 for a
+  // cell that no window reaches, so only touched cells cost HBM reads), then the
+  // stores
   static_assert(CELLS % kThreads == 0, "the bin is a whole number of workgroup passes");
   constexpr int RW = CELLS / kThreads;
   typename A::S jv[RW][3];
@@ -476,7 +478,8 @@ __device__ __forceinline__ void scatter_body(const FieldPtrs<T>& f, const Geom& 
     const bool in = li < ex && lj < ey && lk < ez;
 #pragma unroll
     for (int c = 0; c < 3; ++c) jv[r][c] = in ? (typename A::S)sJ[c][t] : 0;
-    idw[r] = in ? cell_index(g, x0 + li, y0 + lj, z0 + lk) : 0;
+    const bool hit = in && (jv[r][0] | jv[r][1] | jv[r][2]) != 0;
+    idw[r] = hit ? cell_index(g, x0 + li, y0 + lj, z0 + lk) : 0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) ev[r][c] = f.E[c][idw[r]];
     eiv[r] = EPS ? f.epsinv[idw[r]] : T(1);

@@ -89,6 +89,7 @@ struct mlk_sim {
   int kz = 0;       // z planes per workgroup of the fused sweep
   int ty = 4;       // y rows per workgroup of the fused sweep (4, 8 or 16)
   bool layers = false;  // FP32 fused sweep carries the y and z CPML layers itself
+  bool vacuum = true;   // eps_r = 1 in every cell: the fused sweep reads no 1/eps_r
   hipStream_t batch_stream = nullptr;  // stream of the batch this sim belongs to
   bool in_batch = false;
   double adj_forward_ms = 0.0, adj_reverse_ms = 0.0;  // phases of the last adjoint call
@@ -674,16 +675,24 @@ Box interior_box(const Geom& g, bool layers) {
 
 Box sweep_box(const mlk_sim* s) { return interior_box(s->g, s->fp32 && s->layers); }
 
+// The fields as the fused sweep reads them: no 1/eps_r array in vacuum.
+template <typename T>
+FieldPtrs<T> sweep_reads(const mlk_sim* s) {
+  FieldPtrs<T> f = field_ptrs<T>(s);
+  if (s->vacuum) f.epsinv = nullptr;
+  return f;
+}
+
 template <typename T>
 mlk_status sweep(mlk_sim* s) {
   constexpr bool f32 = sizeof(T) == 4;
   const FieldPtrs<T> f = field_ptrs<T>(s);
   if (s->desc.sweep == MLK_SWEEP_FUSED) {
-    const FieldPtrs<T> nf = spare_ptrs<T>(s);
+    const FieldPtrs<T> nf = spare_ptrs<T>(s), fr = sweep_reads<T>(s);
     const Box inner = sweep_box(s);
     int t0 = mark_begin(s, MLK_PHASE_SWEEP);
-    if constexpr (f32) HIPCHK(sweep_fused_f32(f, nf, s->g, inner, s->kz, s->ty, s->stream));
-    else HIPCHK(sweep_fused_f64(f, nf, s->g, inner, s->kz, s->ty, s->stream));
+    if constexpr (f32) HIPCHK(sweep_fused_f32(fr, nf, s->g, inner, s->kz, s->ty, s->stream));
+    else HIPCHK(sweep_fused_f64(fr, nf, s->g, inner, s->kz, s->ty, s->stream));
     mark_end(s, MLK_PHASE_SWEEP, t0);
     t0 = mark_begin(s, MLK_PHASE_SHELL);
     if constexpr (f32) {
@@ -1017,9 +1026,12 @@ mlk_status mlk_set_eps(mlk_sim* s, const double* eps, int32_t mem_kind) {
   } else if (mem_kind != MLK_MEM_HOST) {
     return fail(MLK_EINVAL, "bad mem_kind");
   }
-  for (size_t q = 0; q < s->ncell; ++q)
+  bool vac = true;
+  for (size_t q = 0; q < s->ncell; ++q) {
     if (!(src[q] >= 1.0) || !std::isfinite(src[q]))
       return fail(MLK_EINVAL, "eps_r[%zu] = %g must be finite and >= 1", q, src[q]);
+    vac = vac && src[q] == 1.0;
+  }
   double* d = nullptr;
   HIPCHK(dalloc(&d, s->ncell * sizeof(double)));
   hipError_t e = hipMemcpy(d, src, s->ncell * sizeof(double), hipMemcpyHostToDevice);
@@ -1028,6 +1040,7 @@ mlk_status mlk_set_eps(mlk_sim* s, const double* eps, int32_t mem_kind) {
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   dfree(d);
   if (e != hipSuccess) return fail(MLK_EDEVICE, "set_eps: %s", hipGetErrorString(e));
+  s->vacuum = vac;
   return MLK_OK;
 }
 
@@ -1732,8 +1745,11 @@ mlk_status mlk_set_eps_box(mlk_sim* s, const int32_t box[6], const double* eps, 
   } else {
     std::memcpy(h.data(), eps, nb * sizeof(double));
   }
-  for (double v : h)
+  bool vac = true;
+  for (double v : h) {
     if (!(v >= 1.0) || !std::isfinite(v)) return fail(MLK_EINVAL, "eps_r must be finite and >= 1");
+    vac = vac && v == 1.0;
+  }
   STCHK(sync_sim(s));
   double* d = nullptr;
   HIPCHK(dalloc(&d, nb * sizeof(double)));
@@ -1744,6 +1760,7 @@ mlk_status mlk_set_eps_box(mlk_sim* s, const int32_t box[6], const double* eps, 
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   dfree(d);
   HIPCHK(e);
+  s->vacuum = s->vacuum && vac;
   return MLK_OK;
 }
 
@@ -1901,6 +1918,7 @@ mlk_status build_tables(mlk_batch* b, BatchTables<T> (&tab)[2]) {
         inner = sweep_box(s);
         FusedJob<T> J{};
         J.a = cur;
+        if (s->vacuum) J.a.epsinv = nullptr;
         J.b = nxt;
         J.g = s->g;
         J.box = inner;
@@ -2266,7 +2284,7 @@ bool write_cache(const char* path, const std::vector<TuneEntry>& v) {
 
 template <typename T>
 mlk_status time_fused(mlk_sim* s, int ty, int kz, double* us) {
-  const FieldPtrs<T> a = field_ptrs<T>(s), b = spare_ptrs<T>(s);
+  const FieldPtrs<T> a = field_ptrs<T>(s), b = spare_ptrs<T>(s), ar = sweep_reads<T>(s);
   const Box inner = sweep_box(s);
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
@@ -2276,11 +2294,11 @@ mlk_status time_fused(mlk_sim* s, int ty, int kz, double* us) {
   for (int r = -1; r < kReps && err == hipSuccess; ++r) {
     if (r == 0) err = hipEventRecord(e0, s->stream);
     if constexpr (sizeof(T) == 4) {
-      if (err == hipSuccess) err = sweep_fused_f32(a, b, s->g, inner, kz, ty, s->stream);
+      if (err == hipSuccess) err = sweep_fused_f32(ar, b, s->g, inner, kz, ty, s->stream);
       if (err == hipSuccess) err = sweep_shell_f32(a, b, s->g, inner, true, s->stream);
       if (err == hipSuccess) err = sweep_shell_f32(a, b, s->g, inner, false, s->stream);
     } else {
-      if (err == hipSuccess) err = sweep_fused_f64(a, b, s->g, inner, kz, ty, s->stream);
+      if (err == hipSuccess) err = sweep_fused_f64(ar, b, s->g, inner, kz, ty, s->stream);
       if (err == hipSuccess) err = sweep_shell_f64(a, b, s->g, inner, true, s->stream);
       if (err == hipSuccess) err = sweep_shell_f64(a, b, s->g, inner, false, s->stream);
     }

@@ -241,7 +241,7 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
     nH[0] = a.H[0][own_off + po];
     nH[1] = a.H[1][own_off + po];
     nH[2] = a.H[2][own_off + po];
-    nEps = a.epsinv[own_off + po];
+    nEps = a.epsinv ? a.epsinv[own_off + po] : T(1);  // null: eps_r = 1 everywhere
     nHx[0] = a.H[1][hx_off + po];
     nHx[1] = a.H[2][hx_off + po];
     nHy[0] = a.H[0][hy_off + po];

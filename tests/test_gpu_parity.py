@@ -159,16 +159,25 @@ def test_fused_box_layers_and_fallback(nx, full, precision):
 def test_sweep_decompositions_agree_bitwise(precision):
     """The plain sweep, the fused sweep with the CPML shell, and (FP32) the fused sweep
     carrying every layer give the same fields bit for bit: each cell's arithmetic is the
-    same expression, rounded alike, whichever kernel evaluates it."""
+    same expression, rounded alike, whichever kernel evaluates it.  In vacuum the fused
+    sweep reads no 1/eps_r array; with the array (all ones) it agrees bit for bit."""
     w = W.radiating_cube(n=72, n_emit=60, steps=0, cpml=8, precision=precision)
     runs = []
-    for sweep, layers in (("plain", None), ("fused", False), ("fused", True)):
+    for sweep, layers, eps_array in (("plain", None, True), ("fused", False, False),
+                                     ("fused", True, False), ("fused", False, True)):
         if layers and precision == "fp64":
             continue
         sim = mlk().from_workload(w, sweep=sweep)
         if layers is not None:
             sim.set_sweep_layers(layers)
-        say(f"[decomposition] {precision} {sweep} layers={layers} box={sim.interior_box()}")
+        if eps_array:
+            # a box set to 2 and back to 1: the grid is vacuum again, but no longer
+            # known to be, so the fused sweep reads the 1/eps_r array
+            box = ((20, 20, 20), (30, 30, 30))
+            sim.set_eps_box(box, np.full((10, 10, 10), 2.0))
+            sim.set_eps_box(box, np.ones((10, 10, 10)))
+        say(f"[decomposition] {precision} {sweep} layers={layers} eps_array={eps_array} "
+            f"box={sim.interior_box()}")
         sim.step(40)
         runs.append(sim.fields())
     for other in runs[1:]:
