@@ -52,7 +52,7 @@ __device__ __forceinline__ bool load4(const AdjFused<T>& p, Col col, Col pl, T v
   const size_t id = ok ? col.off + pl.off : 0;
 #pragma unroll
   for (int c = 0; c < 3; ++c) v[c] = p.E[c][id];
-  ei = p.epsinv[id];
+  ei = p.epsinv ? p.epsinv[id] : T(1);  // null: eps_r = 1 everywhere
   return ok;
 }
 
@@ -383,7 +383,7 @@ static hipError_t launch_adj_fused(const AdjSweep<T>& a, const Geom& g, const Bo
     p.Eo[c] = a.Eo[c];
     p.Ho[c] = a.Ho[c];
   }
-  p.epsinv = a.epsinv;
+  p.epsinv = a.vacuum ? nullptr : a.epsinv;
   p.tab = a.tab;
   p.psi_in = a.psi[0];
   p.psi_out = a.psi[1];

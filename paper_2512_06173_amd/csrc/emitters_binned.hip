@@ -161,7 +161,7 @@ __device__ __forceinline__ void gather_body(const FieldPtrs<T>& f, const Geom& g
     }
     const size_t id = ok ? cell_index(g, q[0], q[1], q[2]) : 0;
     T e0 = f.E[0][id], e1 = f.E[1][id], e2 = f.E[2][id];
-    if (WEPS) {
+    if (WEPS && f.epsinv) {  // null: eps_r = 1 everywhere
       const T ei = f.epsinv[id];
       e0 *= ei;
       e1 *= ei;

@@ -378,6 +378,7 @@ struct AdjSweep {
   T* Eo[3];
   T* Ho[3];
   int kz;  // z planes per workgroup of the fused transposed sweep
+  int vacuum;  // eps_r = 1 everywhere: the fused transposed sweep reads no 1/eps_r
 };
 
 }  // namespace mlk

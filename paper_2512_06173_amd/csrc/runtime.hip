@@ -1603,7 +1603,9 @@ mlk_status adjoint_run(mlk_sim* s, int kind, const double* weights, int64_t T_st
   adj.psi[0] = psib[0].p;
   adj.psi[1] = psib[1].p;
   adj.kz = 16;
-  fb.epsinv = (T*)s->epsinv;
+  adj.vacuum = s->vacuum;
+  // in vacuum the adjoint gather reads no 1/eps_r (the scatter never does)
+  fb.epsinv = s->vacuum ? nullptr : (T*)s->epsinv;
   const double mub_scale = -s->g.dt * s->g.inv_dx * s->g.inv_dx * s->g.inv_dx;
   const FluxPlane* fpp = s->fp.on ? &s->fp : nullptr;
 
