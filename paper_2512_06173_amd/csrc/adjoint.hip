@@ -446,7 +446,7 @@ static hipError_t launch_adj_sweep(const AdjSweep<T>& a, const Geom& g, hipStrea
   p.psi_out = a.psi[1];
   if (a.Eo[0]) {
     // fused transposed sweep on its box, then the shell cells, out of place
-    const Box box = adj_interior_box(g);
+    const Box box = adj_interior_box(g, sizeof(T) == 4);
     hipError_t e;
     if constexpr (sizeof(T) == 4) e = adj_fused_f32(a, g, box, st);
     else e = adj_fused_f64(a, g, box, st);

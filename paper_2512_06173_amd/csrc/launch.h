@@ -117,7 +117,7 @@ hipError_t scatter_plain_f64(const FieldPtrs<double>& f, const Geom& g, const Bi
 hipError_t scatter_plain_f32(const FieldPtrs<float>& f, const Geom& g, const BinPtrs& b,
                              const WindowPtrs<float>& win, const double* amp, double amp0,
                              hipStream_t st);
-Box adj_interior_box(const Geom& g);
+Box adj_interior_box(const Geom& g, bool zl);
 hipError_t adj_fused_f64(const AdjSweep<double>& a, const Geom& g, const Box& box,
                          hipStream_t st);
 hipError_t adj_fused_f32(const AdjSweep<float>& a, const Geom& g, const Box& box,

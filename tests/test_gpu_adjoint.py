@@ -88,6 +88,43 @@ def test_adjoint_closures_tiles_and_chunks_fp64(bc, cpml, sweep):
     assert rel(ggd, ogd) <= 1e-10
 
 
+@pytest.mark.parametrize("bc, cpml", [
+    (("periodic", "periodic", "pec", "pec", "cpml", "cpml"), (0, 0, 0, 0, 5, 6)),
+    (("cpml", "pec", "pec", "cpml", "cpml", "cpml"), (7, 0, 0, 6, 5, 4)),
+])
+def test_fused_transposed_sweep_fp32_matches_plain(bc, cpml):
+    """FP32 fields: the fused transposed sweep carries the z layers itself (every z
+    plane in its box); against the whole-grid transposed sweep in FP32 and against the
+    FP64 oracle, on the closures problem of 70 x 26 x 40 cells."""
+    rng = np.random.default_rng(12)
+    shape = (70, 26, 40)
+    M = 5
+    pos = np.column_stack([rng.uniform(30, 40, M), rng.uniform(11, 15, M),
+                           rng.uniform(17, 23, M)])
+    tls = W.TLSSet(pos=pos, sigma=np.full(M, 0.8), gamma=np.ones(M),
+                   omega0=rng.uniform(0.45, 0.55, M), dipole=0.6 * rng.standard_normal((M, 3)),
+                   rho0=np.tile([0.5, 0.5, 0.0], (M, 1)))
+    eps = rng.uniform(1.0, 2.0, (shape[2], shape[1], shape[0]))
+    w = W.Workload(name="adj_fp32_z", shape=shape, bc=bc, cpml=cpml, eps=eps, tls=tls,
+                   point_sources=[W.PointSource(1, (33, 12, 3), 1.0, 0.5, 2.0, 6.0)],
+                   flux=(2, 37), steps=40, precision="fp32")
+    box = ((30, 10, 2), (37, 16, 9))
+    res = {}
+    for sweep in ("fused", "plain"):
+        sim = mlk().from_workload(w, sweep=sweep)
+        res[sweep] = sim.adjoint("flux", w.steps, box, checkpoint_every=15)
+    ov, oge, ogd = build_oracle(w).adjoint("flux", w.steps, box)
+    (fv, fge, fgd), (pv, pge, pgd) = res["fused"], res["plain"]
+    say(f"[adjoint fp32 z] {bc}: fused/plain value {abs(fv - pv) / abs(pv):.2e}, "
+        f"eps {rel(fge, pge):.2e}, dipole {rel(fgd, pgd):.2e}; fused/oracle eps "
+        f"{rel(fge, oge):.2e}")
+    assert abs(fv - pv) <= 1e-5 * abs(pv)
+    assert rel(fge, pge) <= 2e-5
+    assert rel(fgd, pgd) <= 2e-5
+    assert rel(fge, oge) <= 1e-3
+    assert rel(fgd, ogd) <= 1e-3
+
+
 @pytest.mark.parametrize("objective", ["flux", "population"])
 def test_adjoint_fp32_fields(objective):
     w = problem("fp32")
