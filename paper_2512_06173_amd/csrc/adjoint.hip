@@ -37,7 +37,7 @@ template <typename T>
 struct AdjPtrs {
   T* E[3];           // adjoint of E
   T* H[3];           // adjoint of H
-  const T* epsinv;
+  const T* epsinv;   // null in vacuum (eps_r = 1) for the transposed sweep
   const T* tab;      // CPML tables (b, c, 1/kappa) of the forward sweep
   const T* psi_in;   // adjoint of psi (both fields), read
   T* psi_out;        // adjoint of psi, written
@@ -125,10 +125,10 @@ __device__ __forceinline__ void adj_e_cell(const AdjPtrs<T>& p, const AdjPtrs<T>
   T eo[3], hv[3], en[3][3], epn[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) eo[c] = p.E[c][id];
-  const T ei = p.epsinv[id];
+  const T ei = p.epsinv ? p.epsinv[id] : T(1);  // null: eps_r = 1 everywhere
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    epn[a] = p.epsinv[nb.id[a]];
+    epn[a] = p.epsinv ? p.epsinv[nb.id[a]] : T(1);
 #pragma unroll
     for (int c = 0; c < 3; ++c) en[a][c] = c != a ? p.E[c][nb.id[a]] : T(0);
   }
@@ -440,7 +440,7 @@ static hipError_t launch_adj_sweep(const AdjSweep<T>& a, const Geom& g, hipStrea
     p.E[c] = a.E[c];
     p.H[c] = a.H[c];
   }
-  p.epsinv = a.epsinv;
+  p.epsinv = a.vacuum ? nullptr : a.epsinv;  // null: eps_r = 1 everywhere
   p.tab = a.tab;
   p.psi_in = a.psi[0];
   p.psi_out = a.psi[1];
