@@ -11,27 +11,6 @@
 
 namespace mlk {
 
-__device__ __forceinline__ size_t plane_cell(const Geom& g, int a, int index, int iu, int iv) {
-  const int u = (a + 1) % 3, v = (a + 2) % 3;
-  int q[3];
-  q[a] = index;
-  q[u] = iu;
-  q[v] = iv;
-  return cell_index(g, q[0], q[1], q[2]);
-}
-
-template <typename T>
-__device__ __forceinline__ void flux_save_body(const FieldPtrs<T>& f, const Geom& g,
-                                               const FluxPlane& fp, int t) {
-  const int a = fp.axis, u = (a + 1) % 3, v = (a + 2) % 3;
-  const int nu = g.n[u], nv = g.n[v];
-  if (t >= nu * nv) return;
-  const int iu = t % nu, iv = t / nu;
-  const size_t id = plane_cell(g, a, fp.index, iu, iv);
-  fp.Eu0[t] = (double)f.E[u][id];
-  fp.Ev0[t] = (double)f.E[v][id];
-}
-
 // Partial flux of block b of nb (grid-stride over the plane).
 template <typename T>
 __device__ __forceinline__ void flux_partial_body(const FieldPtrs<T>& f, const Geom& g,

@@ -227,9 +227,16 @@ __device__ __forceinline__ void gather_body(const FieldPtrs<T>& f, const Geom& g
   }
 }
 
+// The blocks past the gather bins, if any, save the flux plane's E^n (one
+// launch fewer per step; both read E^n only).
 template <typename T>
-__global__ __launch_bounds__(GatherCfg<T>::threads, GatherCfg<T>::waves_per_simd) void k_gather_bins(FieldPtrs<T> f, Geom g, BinPtrs bins,
-                                                          WindowPtrs<T> win, double* Et) {
+__global__ __launch_bounds__(GatherCfg<T>::threads, GatherCfg<T>::waves_per_simd) void k_gather_bins(
+    FieldPtrs<T> f, Geom g, BinPtrs bins, WindowPtrs<T> win, double* Et, FluxPlane fp) {
+  if ((int)blockIdx.x >= bins.ngather) {  // uniform across the block
+    flux_save_body(f, g, fp, ((int)blockIdx.x - bins.ngather) * GatherCfg<T>::threads +
+                                 (int)threadIdx.x);
+    return;
+  }
   gather_body(f, g, bins, win, Et, blockIdx.x);
 }
 
@@ -513,9 +520,18 @@ template <typename T>
 static hipError_t launch_gather_step(const FieldPtrs<T>& f, const Geom& g, const BinPtrs& b,
                                      const WindowPtrs<T>& win, const TlsPtrs& tls,
                                      double* Et, double* mudot, const int64_t* pop_off,
-                                     const Series& ser, const int64_t* step, hipStream_t st) {
-  if (b.ngather <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather_bins<T>, dim3(b.ngather), dim3(GatherCfg<T>::threads), 0, st, f, g, b, win, Et);
+                                     const Series& ser, const int64_t* step,
+                                     const FluxPlane* fp, hipStream_t st) {
+  if (b.ngather <= 0) return fp ? hipErrorInvalidValue : hipSuccess;
+  int nflux = 0;
+  FluxPlane fpv{};
+  if (fp) {
+    const int a = fp->axis, u = (a + 1) % 3, v = (a + 2) % 3;
+    nflux = (g.n[u] * g.n[v] + GatherCfg<T>::threads - 1) / GatherCfg<T>::threads;
+    fpv = *fp;
+  }
+  hipLaunchKernelGGL(k_gather_bins<T>, dim3(b.ngather + nflux), dim3(GatherCfg<T>::threads), 0,
+                     st, f, g, b, win, Et, fpv);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || tls.count == 0) return e;
   hipLaunchKernelGGL(k_tls_step, dim3((tls.count + 255) / 256), dim3(256), 0, st, tls, g.dt, Et,
@@ -535,14 +551,14 @@ static hipError_t launch_scatter(const FieldPtrs<T>& f, const Geom& g, const Bin
 hipError_t bin_gather_step_f64(const FieldPtrs<double>& f, const Geom& g, const BinPtrs& b,
                                const WindowPtrs<double>& win, const TlsPtrs& tls, double* Et,
                                double* mudot, const int64_t* pop_off, const Series& ser,
-                               const int64_t* step, hipStream_t st) {
-  return launch_gather_step<double>(f, g, b, win, tls, Et, mudot, pop_off, ser, step, st);
+                               const int64_t* step, const FluxPlane* fp, hipStream_t st) {
+  return launch_gather_step<double>(f, g, b, win, tls, Et, mudot, pop_off, ser, step, fp, st);
 }
 hipError_t bin_gather_step_f32(const FieldPtrs<float>& f, const Geom& g, const BinPtrs& b,
                                const WindowPtrs<float>& win, const TlsPtrs& tls, double* Et,
                                double* mudot, const int64_t* pop_off, const Series& ser,
-                               const int64_t* step, hipStream_t st) {
-  return launch_gather_step<float>(f, g, b, win, tls, Et, mudot, pop_off, ser, step, st);
+                               const int64_t* step, const FluxPlane* fp, hipStream_t st) {
+  return launch_gather_step<float>(f, g, b, win, tls, Et, mudot, pop_off, ser, step, fp, st);
 }
 hipError_t bin_scatter_f64(const FieldPtrs<double>& f, const Geom& g, const BinPtrs& b,
                            const WindowPtrs<double>& win, const double* mudot, hipStream_t st) {

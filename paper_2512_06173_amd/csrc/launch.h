@@ -57,14 +57,15 @@ hipError_t finish_f64(const FieldPtrs<double>& f, const Geom& g, const FluxPlane
 hipError_t finish_f32(const FieldPtrs<float>& f, const Geom& g, const FluxPlane& fp,
                       const Series& ser, int64_t* step, hipStream_t st);
 
+// fp: when given, the same launch saves the flux plane's E^n (needs ngather > 0)
 hipError_t bin_gather_step_f64(const FieldPtrs<double>& f, const Geom& g, const BinPtrs& b,
                                const WindowPtrs<double>& win, const TlsPtrs& tls, double* Et,
                                double* mudot, const int64_t* pop_off, const Series& ser,
-                               const int64_t* step, hipStream_t st);
+                               const int64_t* step, const FluxPlane* fp, hipStream_t st);
 hipError_t bin_gather_step_f32(const FieldPtrs<float>& f, const Geom& g, const BinPtrs& b,
                                const WindowPtrs<float>& win, const TlsPtrs& tls, double* Et,
                                double* mudot, const int64_t* pop_off, const Series& ser,
-                               const int64_t* step, hipStream_t st);
+                               const int64_t* step, const FluxPlane* fp, hipStream_t st);
 hipError_t bin_scatter_f64(const FieldPtrs<double>& f, const Geom& g, const BinPtrs& b,
                            const WindowPtrs<double>& win, const double* mudot, hipStream_t st);
 hipError_t bin_scatter_f32(const FieldPtrs<float>& f, const Geom& g, const BinPtrs& b,

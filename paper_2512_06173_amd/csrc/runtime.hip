@@ -734,9 +734,12 @@ mlk_status enqueue_steps(mlk_sim* s, int64_t nsteps) {
   const bool binned = s->desc.scatter == MLK_SCATTER_OWNER && s->nem > 0;
   const BinPtrs bins = bin_ptrs(s);
   const MlDev ml = ml_dev(s);
+  // the gather launch saves the flux plane too when it runs
+  const bool fold_save = s->fp.on && s->nem > 0 && s->ngather > 0;
+  const FluxPlane* fsave = fold_save ? &s->fp : nullptr;
   for (int64_t q = 0; q < nsteps; ++q) {
     FieldPtrs<T> f = field_ptrs<T>(s);
-    if (s->fp.on) {
+    if (s->fp.on && !fold_save) {
       const int t0 = mark_begin(s, MLK_PHASE_DETECTORS);
       if constexpr (f32) HIPCHK(flux_save_f32(f, s->g, s->fp, s->stream));
       else HIPCHK(flux_save_f64(f, s->g, s->fp, s->stream));
@@ -747,10 +750,10 @@ mlk_status enqueue_steps(mlk_sim* s, int64_t nsteps) {
       // gather of every emitter, then the two-level and the multilevel steps
       if constexpr (f32)
         HIPCHK(bin_gather_step_f32(f, s->g, bins, win, tls, s->d_Et, s->d_mudot, s->d_popoff,
-                                   ser, s->d_step, s->stream));
+                                   ser, s->d_step, fsave, s->stream));
       else
         HIPCHK(bin_gather_step_f64(f, s->g, bins, win, tls, s->d_Et, s->d_mudot, s->d_popoff,
-                                   ser, s->d_step, s->stream));
+                                   ser, s->d_step, fsave, s->stream));
       if (ml.count > 0)
         HIPCHK(ml_step(ml, s->ml_range, s->g.dt, s->d_Et, s->d_mudot, s->d_popoff, ser,
                        s->d_step, s->stream));
