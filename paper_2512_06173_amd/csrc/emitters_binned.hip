@@ -57,16 +57,16 @@ namespace {
 constexpr int kLanesPerEmitter = 8;  // = kMaxWin: one lane per window x offset
 constexpr int kThreads = 512;
 constexpr int kGroups = kThreads / kLanesPerEmitter;  // emitters in flight per workgroup
-// Gather launch shape.  The tile fill is latency-bound, so FP32 (small register
-// footprint) runs sixteen wavefronts per bin, two workgroups per CU (LDS and
-// registers: at most 64 VGPRs, eight wavefronts per SIMD).  An emitter takes
-// `lanes` lanes: lane (i, h) on window x offset i and rows h*rows ..
+// Gather launch shape.  The tile fill is latency-bound, so a bin runs sixteen
+// wavefronts: in FP32 two workgroups share a CU (LDS and registers: at most 64
+// VGPRs, eight wavefronts per SIMD), in FP64 one (98 KB of tile).  An emitter
+// takes `lanes` lanes: lane (i, h) on window x offset i and rows h*rows ..
 // h*rows+rows-1.  FP64 splits the rows over sixteen lanes, which halves the
-// chain of each lane's sums and its registers; measured, FP32 is faster with
-// eight.
+// chain of each lane's sums and its registers (122, within the 128 that 1024
+// threads allow); measured, FP32 is faster with eight.
 template <typename T>
 struct GatherCfg {
-  static constexpr int threads = sizeof(T) == 4 ? 1024 : 512;
+  static constexpr int threads = 1024;
   static constexpr int waves_per_simd = sizeof(T) == 4 ? 8 : 1;
   static constexpr int lanes = sizeof(T) == 4 ? 8 : 16;
   static constexpr int rows = kMaxWin * kLanesPerEmitter / lanes;
