@@ -33,11 +33,10 @@ FUSED_SRC = os.path.join(ROOT, "paper_2512_06173_amd", "csrc", "yee_fused.hip")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_fused_f32_radiating_cube_256_traffic.md")
 # Algorithmic bytes, per unit (see the roofline section of the design notes):
 #   cell-step: read + write of the 6 field components and one read of 1/eps_r
-#   (none in vacuum, where eps_r = 1 needs no array)
+#   (credited also in vacuum, where the fused sweep skips that read)
 #   CPML layer membership: read + write of the 4 psi values of that axis
 #   two-level emitter step: state, parameters, E~ and mu_dot
 CELL_WORDS = 13
-CELL_WORDS_VACUUM = 12
 PSI_WORDS = 8
 TLS_STEP_BYTES = 100
 
@@ -271,8 +270,7 @@ def main():
     nem = len(w.tls.pos)
     esz = 4
     memb = layer_memberships(w.shape, w.cpml)
-    cell_words = CELL_WORDS_VACUUM if w.eps is None else CELL_WORDS
-    step_bytes = cells * cell_words * esz + memb * PSI_WORDS * esz + nem * TLS_STEP_BYTES
+    step_bytes = cells * CELL_WORDS * esz + memb * PSI_WORDS * esz + nem * TLS_STEP_BYTES
 
     # timed region: events around the fused sweep launch only
     dt, phases, box, tuning = run_gpu(w, "fp32", "fused", args.steps, args.warmup, ["sweep"],
@@ -290,7 +288,7 @@ def main():
     launch_cells = (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2])
     # a cell of the launch also reads and writes 8 psi words per CPML layer it lies in
     launch_memb = box_memberships(lo, hi, w.shape, w.cpml)
-    launch_bytes = launch_cells * cell_words * esz + launch_memb * PSI_WORDS * esz
+    launch_bytes = launch_cells * CELL_WORDS * esz + launch_memb * PSI_WORDS * esz
     t_launch = sweep_ms / sweep_n * 1e-3
     achieved = launch_bytes / t_launch / 1e9
     traffic = traffic_from_profile(launch_cells)
