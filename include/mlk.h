@@ -105,7 +105,10 @@ mlk_status mlk_destroy(mlk_sim* s);
 
 /* Relative permittivity per cell, nx*ny*nz doubles, x fastest; every E
  * component with index (i,j,k) uses eps_r(i,j,k) (staircase, eq. Dromega with
- * a static eps_r).  EINVAL if any value is < 1 or not finite. */
+ * a static eps_r).  EINVAL if any value is < 1 or not finite.  While the grid
+ * is known to be vacuum (eps_r never set, set to all ones here, or set to ones
+ * only by mlk_set_eps_box) the fused sweeps skip the 1/eps_r array; results
+ * are the same bit for bit. */
 mlk_status mlk_set_eps(mlk_sim* s, const double* eps, int32_t mem_kind);
 
 /* Overwrite one field component (0..2 = Ex..Ez at E^n, 3..5 = Hx..Hz at
