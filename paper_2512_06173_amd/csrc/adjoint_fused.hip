@@ -399,9 +399,10 @@ __global__ __launch_bounds__(64 * TY) void k_adj_fused(AdjFused<T> p, Geom g, Bo
         hy += idx * (dWx_dz + (dL[1][oslot] - D_at(p0, 1, tx + 1, ty)));
       }
       hz += idx * ((dL[0][oslot] - D_at(p0, 0, tx + 1, ty)) - dWx_dy);
-      p.Ho[0][id] = hx;
-      p.Ho[1][id] = hy;
-      p.Ho[2][id] = hz;
+      // streaming stores, as in the forward sweep
+      __builtin_nontemporal_store(hx, &p.Ho[0][id]);
+      __builtin_nontemporal_store(hy, &p.Ho[1][id]);
+      __builtin_nontemporal_store(hz, &p.Ho[2][id]);
     }
     // G of the own cell: x-terms of the transposed H update (psi adjoint updated)
     {
@@ -475,16 +476,20 @@ __global__ __launch_bounds__(64 * TY) void k_adj_fused(AdjFused<T> p, Geom g, Bo
       // z-terms: G(k-1) - G(k), G = -dt Hb'_y (x component), dt Hb'_x (y)
       // x-terms: G(cell - x) - G(cell), G = dt Hb'_y (z component), -dt Hb'_z (y)
       const int sw = (ty + 1) * HW + tx;
+      T e0, e1;
       if constexpr (ZL) {
-        p.Eo[0][id] = uk[0] + (cf * dHz_dy + idx * (gzy - gzy1));
-        p.Eo[1][id] = uk[1] + (idx * (gzx - gzx1) + idx * (gL[1][sw] - gL[1][sw + 1]));
+        e0 = uk[0] + (cf * dHz_dy + idx * (gzy - gzy1));
+        e1 = uk[1] + (idx * (gzx - gzx1) + idx * (gL[1][sw] - gL[1][sw + 1]));
       } else {
         const T dHy_dz = hy - hpy;
         const T dHx_dz = hx - hpx;
-        p.Eo[0][id] = uk[0] + cf * (dHz_dy - dHy_dz);
-        p.Eo[1][id] = uk[1] + (cf * dHx_dz + idx * (gL[1][sw] - gL[1][sw + 1]));
+        e0 = uk[0] + cf * (dHz_dy - dHy_dz);
+        e1 = uk[1] + (cf * dHx_dz + idx * (gL[1][sw] - gL[1][sw + 1]));
       }
-      p.Eo[2][id] = uk[2] + (idx * (gL[0][sw] - gL[0][sw + 1]) - cf * dHx_dy);
+      const T e2 = uk[2] + (idx * (gL[0][sw] - gL[0][sw + 1]) - cf * dHx_dy);
+      __builtin_nontemporal_store(e0, &p.Eo[0][id]);
+      __builtin_nontemporal_store(e1, &p.Eo[1][id]);
+      __builtin_nontemporal_store(e2, &p.Eo[2][id]);
     }
     hpx = hx;
     hpy = hy;

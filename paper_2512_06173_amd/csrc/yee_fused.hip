@@ -355,9 +355,11 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
       hx -= dt * (dEz_dy - dEy_dz);
       hy -= dt * (dEx_dz - dEz_dx);
       hz -= dt * (dEy_dx - dEx_dy);
-      b.H[0][id] = hx;
-      b.H[1][id] = hy;
-      b.H[2][id] = hz;
+      // streaming stores: the new fields are read again only in the next step,
+      // long after this sweep has passed through the caches
+      __builtin_nontemporal_store(hx, &b.H[0][id]);
+      __builtin_nontemporal_store(hy, &b.H[1][id]);
+      __builtin_nontemporal_store(hz, &b.H[2][id]);
     }
     hL[0][(ty + 1) * HW + tx + 1] = hx;
     hL[1][(ty + 1) * HW + tx + 1] = hy;
@@ -436,9 +438,12 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
       const T cx = dHz_dy - dHy_dz;
       const T cy = dHx_dz - dHz_dx;
       const T cz = dHy_dx - dHx_dy;
-      b.E[0][id] = tangential_wall(g, 0, i, j, k) ? T(0) : ek[0] + ce * cx;
-      b.E[1][id] = tangential_wall(g, 1, i, j, k) ? T(0) : ek[1] + ce * cy;
-      b.E[2][id] = tangential_wall(g, 2, i, j, k) ? T(0) : ek[2] + ce * cz;
+      const T e0 = tangential_wall(g, 0, i, j, k) ? T(0) : ek[0] + ce * cx;
+      const T e1 = tangential_wall(g, 1, i, j, k) ? T(0) : ek[1] + ce * cy;
+      const T e2 = tangential_wall(g, 2, i, j, k) ? T(0) : ek[2] + ce * cz;
+      __builtin_nontemporal_store(e0, &b.E[0][id]);
+      __builtin_nontemporal_store(e1, &b.E[1][id]);
+      __builtin_nontemporal_store(e2, &b.E[2][id]);
     }
     hpx = hx;
     hpy = hy;
