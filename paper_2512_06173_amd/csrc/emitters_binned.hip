@@ -337,7 +337,7 @@ __device__ __forceinline__ void scatter_body(const FieldPtrs<T>& f, const Geom& 
   // emitter ids of a bin's pairs kept in LDS (beyond: read from HBM); sized so
   // that two workgroups still fit one CU's LDS
   constexpr int kIdCap = sizeof(T) == 4 ? 4096 : 1024;
-  __shared__ typename A::U sJ[3][CELLS];
+  __shared__ alignas(16) typename A::U sJ[3][CELLS];
   __shared__ WinRec<T> sW[kGroups];
   __shared__ T sAmp[kGroups][3];
   __shared__ unsigned sRun[kGroups];
@@ -349,10 +349,12 @@ __device__ __forceinline__ void scatter_body(const FieldPtrs<T>& f, const Geom& 
   const int x0 = bx * BX, y0 = by * BY, z0 = bz * BZ;
   const int ex = min(BX, g.n[0] - x0), ey = min(BY, g.n[1] - y0), ez = min(BZ, g.n[2] - z0);
   const int q0 = bins.sbin_start[bid], q1 = bins.sbin_start[bid + 1];
-  for (int t = tid; t < CELLS; t += kThreads) {
-    sJ[0][t] = 0;
-    sJ[1][t] = 0;
-    sJ[2][t] = 0;
+  {
+    // cleared 16 bytes at a time (the three accumulator arrays are contiguous)
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    u4* z = reinterpret_cast<u4*>(&sJ[0][0]);
+    constexpr int NZ = 3 * CELLS * (int)sizeof(typename A::U) / 16;
+    for (int t = tid; t < NZ; t += kThreads) z[t] = u4{0u, 0u, 0u, 0u};
   }
   double bound = 0.0;
   for (int q = q0 + tid; q < q1; q += kThreads) {
@@ -489,7 +491,7 @@ __device__ __forceinline__ void scatter_body(const FieldPtrs<T>& f, const Geom& 
     idw[r] = hit ? cell_index(g, x0 + li, y0 + lj, z0 + lk) : 0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) ev[r][c] = f.E[c][idw[r]];
-    eiv[r] = EPS ? f.epsinv[idw[r]] : T(1);
+    eiv[r] = (EPS && f.epsinv) ? f.epsinv[idw[r]] : T(1);  // null: eps_r = 1 everywhere
   }
 #pragma unroll
   for (int r = 0; r < RW; ++r)

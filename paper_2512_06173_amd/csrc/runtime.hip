@@ -763,8 +763,11 @@ mlk_status enqueue_steps(mlk_sim* s, int64_t nsteps) {
     f = field_ptrs<T>(s);
     t0 = mark_begin(s, MLK_PHASE_SCATTER);
     if (binned) {
-      if constexpr (f32) HIPCHK(bin_scatter_f32(f, s->g, bins, win, s->d_mudot, s->stream));
-      else HIPCHK(bin_scatter_f64(f, s->g, bins, win, s->d_mudot, s->stream));
+      // in vacuum the owner write reads no 1/eps_r
+      FieldPtrs<T> fs = f;
+      if (s->vacuum) fs.epsinv = nullptr;
+      if constexpr (f32) HIPCHK(bin_scatter_f32(fs, s->g, bins, win, s->d_mudot, s->stream));
+      else HIPCHK(bin_scatter_f64(fs, s->g, bins, win, s->d_mudot, s->stream));
     } else if (s->nem > 0) {
       if constexpr (f32)
         HIPCHK(scatter_atomic_f32(f, s->g, win, s->nem, s->d_mudot, s->stream));
