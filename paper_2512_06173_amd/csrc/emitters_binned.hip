@@ -136,6 +136,11 @@ __device__ __forceinline__ void gather_body(const FieldPtrs<T>& f, const Geom& g
   const int x0 = bins.gbin_org[3 * bin] - kHalo;
   const int y0 = bins.gbin_org[3 * bin + 1] - kHalo;
   const int z0 = bins.gbin_org[3 * bin + 2] - kHalo;
+  // the bin's emitter range and each group's first emitter id, loaded with the
+  // tile so that the sums start right after the barrier
+  const int grp = tid / LG, i = tid % kLanesPerEmitter;
+  const int q0 = bins.gbin_start[bin], q1 = bins.gbin_start[bin + 1];
+  int e_next = q0 + grp < q1 ? bins.gbin_em[q0 + grp] : 0;
 
   // stage the tile: every load of a thread is issued before the first LDS
   // store, so they are in flight together (unconditional loads from a safe
@@ -181,11 +186,10 @@ __device__ __forceinline__ void gather_body(const FieldPtrs<T>& f, const Geom& g
 
   __syncthreads();
 
-  const int grp = tid / LG, i = tid % kLanesPerEmitter;
   const int j0 = (tid / kLanesPerEmitter) % (LG / kLanesPerEmitter) * RG;
-  const int q0 = bins.gbin_start[bin], q1 = bins.gbin_start[bin + 1];
   for (int q = q0 + grp; q < q1; q += NG) {  // uniform across the lanes of an emitter
-    const int e = bins.gbin_em[q];
+    const int e = e_next;
+    if (q + NG < q1) e_next = bins.gbin_em[q + NG];
     LaneWin<T> w;
     load_lane_win(win.rec[e], i, j0, w);
     double ax = 0.0, ay = 0.0, az = 0.0;
