@@ -145,9 +145,10 @@ def batch_leg(steps, spr=20, tune=False):
     """64 independent domains (edges 32..96, CPML 8, 1..256 TLS each, FP32 fields):
     batched (one launch per phase, replayed from a captured hipGraph) against the same
     domains stepped one after another on the same stream, and (context) against each
-    domain stepping on a stream of its own, so that their launches overlap.  The members
-    keep their default tiles: the autotuner times a sim on its own, where a small domain
-    favours the fewest launches, while a batch wants throughput."""
+    domain stepping on a stream of its own, so that their launches overlap.  The batch
+    tuner picks one tile shape and layer mode for all members by timing the batch's
+    sweep; the one-by-one leg keeps that choice.  tune=True instead tunes every member
+    on its own first (each small domain then favours its own latency)."""
     import torch
     from paper_2512_06173_amd import mlk, workloads as W
     ws = W.batch(n_domains=64, steps=0)
@@ -172,6 +173,7 @@ def batch_leg(steps, spr=20, tune=False):
         for s in sims:
             s.autotune()
     b = mlk.Batch(sims)
+    tuned = None if tune else b.autotune()
     b.step(2)
     b.capture(spr)
     b.replay(1)
@@ -199,6 +201,8 @@ def batch_leg(steps, spr=20, tune=False):
     return {"workload": f"{len(ws)} cubic domains, edges 32..96 (8 x U{{4..12}}), CPML 8, "
                         f"eps per 8^3 block, {nem} TLS in all; FP32 fields",
             "cells": cells, "emitters": nem, "steps": nsteps,
+            "batch_tuning": None if tuned is None else
+            {"ty": tuned[0], "kz": tuned[1], "layers": bool(tuned[2])},
             "batched_graph": rate(tb), "one_by_one": rate(tu),
             "speedup": round(tu / tb, 2),
             "own_streams": rate(tc), "speedup_vs_own_streams": round(tc / tb, 2)}

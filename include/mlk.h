@@ -286,6 +286,18 @@ mlk_status mlk_batch_replay(mlk_batch* b, int64_t nreplays);
 mlk_status mlk_batch_sync(mlk_batch* b);
 mlk_status mlk_batch_destroy(mlk_batch* b);
 
+/* Tile shape and layer mode for the batch as a whole: every member gets the same
+ * (ty, kz, layer mode), chosen by timing the batch's sweep phase (the fused
+ * launches and the two shell passes of one batched step, best of three runs;
+ * the members' state is untouched) for every candidate, three interleaved
+ * rounds.  A member tuned alone minimises its own latency; a batch wants
+ * throughput over all of them.  With cache_path (NULL: no cache) the choice is
+ * read from and added to the JSON file of mlk_autotune, keyed by precision,
+ * member count and a hash of the members' grids.  Drops a captured graph (the
+ * next mlk_batch_replay captures again).  Speed only: results do not change.
+ * Plain-sweep batches have nothing to tune. */
+mlk_status mlk_batch_autotune(mlk_batch* b, const char* cache_path);
+
 /* Tile shape of the fused sweep: rows per workgroup ty (4, 8 or 16) and z planes
  * per workgroup kz.  mlk_autotune times every pair (and, with FP32 fields, both
  * layer modes, see mlk_set_sweep_layers) on the sim's own grid, each as the

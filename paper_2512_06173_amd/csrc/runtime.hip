@@ -2184,7 +2184,7 @@ mlk_status mlk_batch_capture(mlk_batch* b, int64_t steps_per_replay) {
 
 mlk_status mlk_batch_replay(mlk_batch* b, int64_t nreplays) {
   if (!b) return fail(MLK_EINVAL, "null argument");
-  if (!b->exec) return fail(MLK_ESTATE, "nothing captured");
+  if (!b->exec && b->replay_steps <= 0) return fail(MLK_ESTATE, "nothing captured");
   if (nreplays < 0) return fail(MLK_EINVAL, "negative replay count");
   HIPCHK(hipSetDevice(b->sims[0]->desc.device));
   for (mlk_sim* s : b->sims)
@@ -2192,8 +2192,9 @@ mlk_status mlk_batch_replay(mlk_batch* b, int64_t nreplays) {
   const int64_t spr = b->replay_steps;
   STCHK(batch_reserve(b, nreplays * spr));
   if (!b->exec || b->capture_parity != b->parity) {
-    // a series had to grow (the captured pointers are stale), or odd eager steps
-    // since the capture left the fused buffers the other way round: capture again
+    // a series had to grow (the captured pointers are stale), the tables were
+    // rebuilt (tuning), or odd eager steps since the capture left the fused
+    // buffers the other way round: capture again
     STCHK(mlk_batch_capture(b, spr));
   }
   for (int64_t r = 0; r < nreplays; ++r) {
@@ -2413,6 +2414,129 @@ mlk_status mlk_autotune(mlk_sim* s, const char* cache_path) {
   s->kz = bkz;
   if (cache_path) {
     cache.push_back({key, bty, bkz, blay, best});
+    if (!write_cache(cache_path, cache))
+      return fail(MLK_EINVAL, "cannot write the tuning cache %s", cache_path);
+  }
+  return MLK_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Device time of the sweep phase of one batched step (every fused launch plus
+// the two shell passes) on the tables of the current parity, best of kReps; the
+// members' state is untouched (both write the spare buffers).
+template <typename T>
+mlk_status time_batch_sweep(mlk_batch* b, const BatchTables<T>& t, double* us) {
+  constexpr bool f32 = sizeof(T) == 4;
+  hipStream_t st = b->stream;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  hipError_t err = hipSuccess;
+  const int tys[3] = {4, 8, 16};
+  auto once = [&]() {
+    for (int k = 0; k < 3 && err == hipSuccess; ++k) {
+      const DevTable<FusedJob<T>>& f = t.fused[k];
+      if constexpr (f32) err = sweep_fused_batch_f32(f.jobs, f.start, f.njobs, f.nblocks, tys[k], st);
+      else err = sweep_fused_batch_f64(f.jobs, f.start, f.njobs, f.nblocks, tys[k], st);
+    }
+    for (int h = 1; h >= 0 && err == hipSuccess; --h) {
+      if constexpr (f32)
+        err = shell_batch_f32(t.shell.jobs, t.shell.start, t.shell.njobs, t.shell.nblocks, h == 1, st);
+      else
+        err = shell_batch_f64(t.shell.jobs, t.shell.start, t.shell.njobs, t.shell.nblocks, h == 1, st);
+    }
+  };
+  constexpr int kReps = 3;
+  once();  // warm-up
+  double best = 1e300;
+  for (int r = 0; r < kReps && err == hipSuccess; ++r) {
+    err = hipEventRecord(e0, st);
+    once();
+    if (err == hipSuccess) err = hipEventRecord(e1, st);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    best = std::min(best, 1e3 * (double)ms);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIPCHK(err);
+  *us = best;
+  return MLK_OK;
+}
+
+// Cache key of a batch: precision, member count and an FNV-1a hash of the
+// members' grid keys in order.
+std::string batch_key(const mlk_batch* b) {
+  uint64_t h = 1469598103934665603ull;
+  for (const mlk_sim* s : b->sims)
+    for (char c : tune_key(s) + ";") {
+      h ^= (unsigned char)c;
+      h *= 1099511628211ull;
+    }
+  char k[96];
+  std::snprintf(k, sizeof k, "batch %s %zu %016llx", b->fp32 ? "fp32" : "fp64", b->sims.size(),
+                (unsigned long long)h);
+  return k;
+}
+
+void set_members(mlk_batch* b, int layers, int ty, int kz) {
+  for (mlk_sim* s : b->sims) {
+    s->layers = b->fp32 && layers != 0;
+    s->ty = ty;
+    s->kz = kz;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+mlk_status mlk_batch_autotune(mlk_batch* b, const char* cache_path) {
+  if (!b) return fail(MLK_EINVAL, "null argument");
+  if (!b->fused) return MLK_OK;  // nothing to tune
+  HIPCHK(hipSetDevice(b->sims[0]->desc.device));
+  // the captured graph refers to the tables about to be rebuilt; the next replay
+  // captures the same step count again
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  HIPCHK(hipStreamSynchronize(b->stream));
+  const std::string key = batch_key(b);
+  std::vector<TuneEntry> cache = read_cache(cache_path);
+  for (const TuneEntry& e : cache)
+    if (e.key == key && (e.ty == 4 || e.ty == 8 || e.ty == 16) && e.kz > 0) {
+      set_members(b, e.layers, e.ty, e.kz);
+      return rebuild_tables(b);
+    }
+  struct Cand {
+    int layers, ty, kz;
+    double us;
+  };
+  std::vector<Cand> cands;
+  for (int lay = 0; lay <= (b->fp32 ? 1 : 0); ++lay)
+    for (int ty : {4, 8, 16})
+      for (int kz : {4, 8, 16, 32}) cands.push_back({lay, ty, kz, 1e300});
+  for (int round = 0; round < 3; ++round)
+    for (Cand& c : cands) {
+      set_members(b, c.layers, c.ty, c.kz);
+      STCHK(rebuild_tables(b));
+      double us = 0.0;
+      STCHK(b->fp32 ? time_batch_sweep<float>(b, b->t32[0], &us)
+                    : time_batch_sweep<double>(b, b->t64[0], &us));
+      c.us = std::min(c.us, us);
+    }
+  const Cand* best = &cands[0];
+  for (const Cand& c : cands)
+    if (c.us < best->us) best = &c;
+  set_members(b, best->layers, best->ty, best->kz);
+  STCHK(rebuild_tables(b));
+  if (cache_path) {
+    cache.push_back({key, best->ty, best->kz, best->layers, best->us});
     if (!write_cache(cache_path, cache))
       return fail(MLK_EINVAL, "cannot write the tuning cache %s", cache_path);
   }

@@ -116,6 +116,7 @@ def lib():
         "mlk_batch_replay": (st, [C.c_void_p, C.c_int64]),
         "mlk_batch_sync": (st, [C.c_void_p]),
         "mlk_batch_destroy": (st, [C.c_void_p]),
+        "mlk_batch_autotune": (st, [C.c_void_p, C.c_char_p]),
         "mlk_adjoint": (st, [sim, C.POINTER(Objective), C.c_int64, C.c_int32, _ip, C.c_void_p,
                              C.c_void_p, C.POINTER(C.c_double)]),
         "mlk_set_eps_box": (st, [sim, _ip, _dp, C.c_int32]),
@@ -145,7 +146,8 @@ def exported_symbols():
             "mlk_get_flux_total", "mlk_checkpoint_size", "mlk_checkpoint_save",
             "mlk_checkpoint_load", "mlk_set_timing", "mlk_get_phase_time",
             "mlk_get_interior_box", "mlk_batch_create", "mlk_batch_step", "mlk_batch_capture",
-            "mlk_batch_replay", "mlk_batch_sync", "mlk_batch_destroy", "mlk_autotune",
+            "mlk_batch_replay", "mlk_batch_sync", "mlk_batch_destroy", "mlk_batch_autotune",
+            "mlk_autotune",
             "mlk_set_tuning", "mlk_get_tuning", "mlk_set_sweep_layers", "mlk_get_sweep_layers", "mlk_adjoint", "mlk_set_eps_box",
             "mlk_set_tls_dipoles", "mlk_get_adjoint_times"]
 
@@ -493,6 +495,13 @@ class Batch:
 
     def sync(self):
         _check(lib().mlk_batch_sync(self._h))
+
+    def autotune(self, cache_path=None):
+        """One tile shape and layer mode for every member, chosen by timing the batch's
+        sweep phase (optionally cached in JSON); returns (ty, kz, layers)."""
+        _check(lib().mlk_batch_autotune(self._h, cache_path.encode() if cache_path else None))
+        ty, kz = self.sims[0].tuning()
+        return ty, kz, self.sims[0].sweep_layers()
 
     def close(self):
         if getattr(self, "_h", None):

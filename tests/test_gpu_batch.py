@@ -115,6 +115,37 @@ def test_graph_replay_equals_eager_steps():
             compare(s, m, w)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batch_autotune_changes_speed_not_results(precision, tmp_path):
+    """The batch tuner gives every member one tile shape and layer mode; stepping goes
+    on bit for bit as for the members alone (before and after an odd step count and a
+    capture that the tuning drops), and the choice is read back from the cache."""
+    ws = domains(precision, seed=9)
+    solo = [mlk().from_workload(w) for w in ws]
+    mem = [mlk().from_workload(w) for w in ws]
+    cache = str(tmp_path / "tune.json")
+    with mlk().Batch(mem) as b:
+        b.step(5)  # odd: the members' buffers are swapped when the tuner runs
+        b.capture(4)
+        t = b.autotune(cache)
+        say(f"  batch tuned (ty, kz, layers) = {t}")
+        assert t[0] in (4, 8, 16) and t[1] in (4, 8, 16, 32)
+        assert all(m.tuning() == t[:2] and m.sweep_layers() == t[2] for m in mem)
+        assert precision == "fp32" or not t[2]
+        b.step(7)
+        b.replay(2)  # captures again on the new tables
+        b.sync()
+    for s in solo:
+        s.step(20)
+    for s, m, w in zip(solo, mem, ws):
+        compare(s, m, w)
+    again = [mlk().from_workload(w) for w in ws]
+    with mlk().Batch(again) as b2:
+        assert b2.autotune(cache) == t
+    import json
+    assert len(json.load(open(cache))) == 1
+
+
 def test_capture_needs_even_steps_in_fused_mode():
     ws = domains("fp32")
     mem = [mlk().from_workload(w) for w in ws[:2]]
