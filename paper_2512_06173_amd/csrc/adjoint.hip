@@ -171,7 +171,7 @@ __device__ __forceinline__ void adj_e_cell(const AdjPtrs<T>& p, const AdjPtrs<T>
   }
   const AdjPtrs<T>& d = OOP ? o : p;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) d.H[c][id] = hv[c] + hb[c];
+  for (int c = 0; c < 3; ++c) __builtin_nontemporal_store(hv[c] + hb[c], &d.H[c][id]);
 }
 
 // Transposed H update.  Hb holds the adjoint of H^{n+1/2} (unchanged: identity
@@ -219,7 +219,7 @@ __device__ __forceinline__ void adj_h_cell(const AdjPtrs<T>& p, const AdjPtrs<T>
     }
   const AdjPtrs<T>& d = OOP ? o : p;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) d.E[c][id] = ev[c] + eb[c];
+  for (int c = 0; c < 3; ++c) __builtin_nontemporal_store(ev[c] + eb[c], &d.E[c][id]);
 }
 
 // Whole-grid transposed sweep in place: one thread per cell, 64 x 4 cells per

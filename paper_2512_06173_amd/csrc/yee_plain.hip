@@ -40,9 +40,13 @@ __device__ __forceinline__ void update_h_cell(const FieldPtrs<T>& in, const Fiel
   dEy_dx = stretch(g, in.tab, in.psi, out.psi, 1, 2, 0, i, j, k, dEy_dx);
   dEx_dy = stretch(g, in.tab, in.psi, out.psi, 1, 2, 1, i, j, k, dEx_dy);
   const T dt = (T)g.dt;
-  out.H[0][id] = in.H[0][id] - dt * (dEz_dy - dEy_dz);
-  out.H[1][id] = in.H[1][id] - dt * (dEx_dz - dEz_dx);
-  out.H[2][id] = in.H[2][id] - dt * (dEy_dx - dEx_dy);
+  const T h0 = in.H[0][id] - dt * (dEz_dy - dEy_dz);
+  const T h1 = in.H[1][id] - dt * (dEx_dz - dEz_dx);
+  const T h2 = in.H[2][id] - dt * (dEy_dx - dEx_dy);
+  // streaming stores (as in the fused sweep)
+  __builtin_nontemporal_store(h0, &out.H[0][id]);
+  __builtin_nontemporal_store(h1, &out.H[1][id]);
+  __builtin_nontemporal_store(h2, &out.H[2][id]);
 }
 
 // E^{n+1} at cell (i,j,k); H^{n+1/2} is read from `out` (already advanced
@@ -74,9 +78,12 @@ __device__ __forceinline__ void update_e_cell(const FieldPtrs<T>& in, const Fiel
   const T cx = dHz_dy - dHy_dz;
   const T cy = dHx_dz - dHz_dx;
   const T cz = dHy_dx - dHx_dy;
-  out.E[0][id] = tangential_wall(g, 0, i, j, k) ? T(0) : e0 + ce * cx;
-  out.E[1][id] = tangential_wall(g, 1, i, j, k) ? T(0) : e1 + ce * cy;
-  out.E[2][id] = tangential_wall(g, 2, i, j, k) ? T(0) : e2 + ce * cz;
+  const T n0 = tangential_wall(g, 0, i, j, k) ? T(0) : e0 + ce * cx;
+  const T n1 = tangential_wall(g, 1, i, j, k) ? T(0) : e1 + ce * cy;
+  const T n2 = tangential_wall(g, 2, i, j, k) ? T(0) : e2 + ce * cz;
+  __builtin_nontemporal_store(n0, &out.E[0][id]);
+  __builtin_nontemporal_store(n1, &out.E[1][id]);
+  __builtin_nontemporal_store(n2, &out.E[2][id]);
 }
 
 template <typename T, bool H>
