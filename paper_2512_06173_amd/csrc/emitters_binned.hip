@@ -6,22 +6,25 @@
 // (FP32 fields) or sixteen (FP64) serve one emitter, lane (i, h) taking the x
 // offset i of its window and the h-th share of its rows: a lane sums its rows
 // along y in the field precision, weights them along z into FP64, and the
-// lanes of the emitter add up their sums (FP64).  Bins are handed out XCD by XCD so that neighbouring bins, whose
-// halos overlap, share one L2.
+// lanes of the emitter add up their sums (FP64).  The weights come from the
+// emitter's record into registers.  Bins are handed out XCD by XCD so that
+// neighbouring bins, whose halos overlap, share one L2.  Extra workgroups of
+// the same launch save the flux plane's E^n.
 //
 // step (eq. von-Neumann-tls, eq. dipole_derivative): one thread per two-level
 // emitter advances its state with the exact propagator and writes mu_dot.
 //
 // scatter (eqs. J_mol, Polarization_mol):  E_c(p) -= (dt/eps_r(p)) gamma mu_dot^c
-// w^c_{m,p} / dx^3.  A workgroup owns a bin of cells and takes every emitter
-// whose window touches the bin, again eight lanes per emitter; contributions
-// are summed in LDS (as fixed-point integers, see k_scatter_bins) and each
-// cell is written once by its owner (no global atomics).
+// w^c_{m,p} / dx^3.  A workgroup owns a bin of cells and takes every (emitter,
+// bin) pair whose window touches the bin, eight lanes per pair; the pair
+// carries its window's runs inside the bin, set up on the host.  Contributions
+// are summed in LDS (as fixed-point integers, see scatter_body) and each cell
+// is written once by its owner (no global atomics).  The pairs' records are
+// copied into LDS with 16-byte loads, so the inner loops touch LDS only.
 //
 // Window weights are the separable factors wx wy wz set up by k_windows, kept
 // per emitter as a union-window record (WinRec); a component uses the
-// half-integer variant on its own axis.  Records are copied into LDS with
-// 16-byte loads, so the inner loops touch LDS only.
+// half-integer variant on its own axis.
 #include "mlk_internal.h"
 #include "tls_math.h"
 
