@@ -170,6 +170,23 @@ mlk_status mlk_record_populations(mlk_sim* s, int32_t every);
 
 /* Advance nsteps full coupled steps (asynchronous). */
 mlk_status mlk_step(mlk_sim* s, int64_t nsteps);
+
+/* Classical-path stepping (eq. E_analytical; the prescribed-field solver of the
+ * paper's table of EM solvers): nsteps steps of dt of every emitter under a
+ * given field, with no grid and no back-action.  Et holds nsteps x M x 3
+ * doubles, step-major and in emitter-id order: the field each emitter sees, as
+ * the gather would give it (gamma times the smeared E), in host or device
+ * memory (mem_kind; the caller keeps ownership).  Each step advances the
+ * two-level and multilevel states exactly as the coupled step does and forms
+ * mu_dot; the fields, the step counter and the series do not change.  tls_out
+ * (nullable, same memory kind) receives after every step the states (rho11,
+ * Re rho01, Im rho01) of the two-level emitters in id order: nsteps x ntls x 3
+ * doubles.  mlk_get_rho and mlk_get_tls_state read the final states,
+ * mlk_get_emitter_io the last step's E~ and mu_dot.  Returns when host buffers
+ * are done with; with device buffers it is asynchronous on the sim's stream.
+ * EINVAL: negative nsteps, bad mem_kind, null Et (with emitters, nsteps > 0). */
+mlk_status mlk_step_prescribed(mlk_sim* s, int64_t nsteps, const double* Et, int32_t mem_kind,
+                               double* tls_out);
 mlk_status mlk_sync(mlk_sim* s);
 mlk_status mlk_step_count(mlk_sim* s, int64_t* n);
 

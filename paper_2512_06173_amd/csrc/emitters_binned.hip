@@ -548,6 +548,16 @@ static hipError_t launch_gather_step(const FieldPtrs<T>& f, const Geom& g, const
   return hipGetLastError();
 }
 
+// Two-level step of every two-level emitter under a given E~ (emitter-id order).
+hipError_t tls_step(const TlsPtrs& tls, double dt, const double* Et, double* mudot,
+                    const int64_t* pop_off, const Series& ser, const int64_t* step,
+                    hipStream_t st) {
+  if (tls.count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tls_step, dim3((tls.count + 255) / 256), dim3(256), 0, st, tls, dt, Et,
+                     mudot, pop_off, ser, step);
+  return hipGetLastError();
+}
+
 template <typename T>
 static hipError_t launch_scatter(const FieldPtrs<T>& f, const Geom& g, const BinPtrs& b,
                                  const WindowPtrs<T>& win, const double* mudot, hipStream_t st) {

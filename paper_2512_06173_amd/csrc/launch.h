@@ -20,6 +20,10 @@ hipError_t sweep_shell_f64(const FieldPtrs<double>& in, const FieldPtrs<double>&
                            const Geom& g, const Box& inner, bool h_pass, hipStream_t st);
 hipError_t sweep_shell_f32(const FieldPtrs<float>& in, const FieldPtrs<float>& out, const Geom& g,
                            const Box& inner, bool h_pass, hipStream_t st);
+// Two-level step of every two-level emitter under E~ (M x 3, emitter-id order).
+hipError_t tls_step(const TlsPtrs& tls, double dt, const double* Et, double* mudot,
+                    const int64_t* pop_off, const Series& ser, const int64_t* step,
+                    hipStream_t st);
 // Multilevel step of every slot; range[n]..range[n+1] are the slots with n levels.
 hipError_t ml_step(const MlDev& ml, const int* range, double dt, const double* Et, double* mudot,
                    const int64_t* pop_off, const Series& ser, const int64_t* step,

@@ -63,6 +63,18 @@ void dfree(P*& p) {
   p = nullptr;
 }
 
+// Device buffer owned by a scope.
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  ~DevBuf() { dfree(p); }
+  hipError_t alloc(size_t n) {
+    dfree(p);
+    if (n == 0) return hipSuccess;
+    return dalloc(&p, n * sizeof(T));
+  }
+};
+
 }  // namespace
 
 struct mlk_sim {
@@ -1269,6 +1281,59 @@ mlk_status mlk_step(mlk_sim* s, int64_t nsteps) {
   return st;
 }
 
+mlk_status mlk_step_prescribed(mlk_sim* s, int64_t nsteps, const double* Et, int32_t mem_kind,
+                               double* tls_out) {
+  if (!s) return fail(MLK_EINVAL, "null argument");
+  if (nsteps < 0) return fail(MLK_EINVAL, "negative step count");
+  if (mem_kind != MLK_MEM_HOST && mem_kind != MLK_MEM_DEVICE) return fail(MLK_EINVAL, "bad mem_kind");
+  if (nsteps == 0 || s->nem == 0) return MLK_OK;
+  if (!Et) return fail(MLK_EINVAL, "null field");
+  HIPCHK(hipSetDevice(s->desc.device));
+  if (s->batch_stream) HIPCHK(hipStreamSynchronize(s->batch_stream));
+  const size_t per = 3 * (size_t)s->nem, nt = s->tls_gid.size();
+  const TlsPtrs tls = tls_ptrs(s);
+  const MlDev ml = ml_dev(s);
+  Series ser = series_of(s);
+  ser.pop_every = 0;  // no series: the step counter does not move
+  const bool host = mem_kind == MLK_MEM_HOST;
+  // host data goes through device staging in chunks of at most about 64 MB
+  const int64_t K = host ? std::max<int64_t>(1, std::min<int64_t>(nsteps, (int64_t)((64u << 20) /
+                                                                                   (8 * per))))
+                         : nsteps;
+  DevBuf<double> dE, dO;
+  if (host) {
+    HIPCHK(dE.alloc((size_t)K * per));
+    if (tls_out && nt) HIPCHK(dO.alloc((size_t)K * 3 * nt));
+  }
+  for (int64_t c0 = 0; c0 < nsteps; c0 += K) {
+    const int64_t kc = std::min(K, nsteps - c0);
+    const double* e = host ? dE.p : Et + (size_t)c0 * per;
+    double* o = tls_out && nt ? (host ? dO.p : tls_out + (size_t)c0 * 3 * nt) : nullptr;
+    if (host)
+      HIPCHK(hipMemcpyAsync(dE.p, Et + (size_t)c0 * per, (size_t)kc * per * sizeof(double),
+                            hipMemcpyHostToDevice, s->stream));
+    for (int64_t q = 0; q < kc; ++q) {
+      const double* eq = e + (size_t)q * per;
+      HIPCHK(tls_step(tls, s->g.dt, eq, s->d_mudot, s->d_popoff, ser, s->d_step, s->stream));
+      if (ml.count > 0)
+        HIPCHK(ml_step(ml, s->ml_range, s->g.dt, eq, s->d_mudot, s->d_popoff, ser, s->d_step,
+                       s->stream));
+      if (o)
+        HIPCHK(hipMemcpyAsync(o + (size_t)q * 3 * nt, s->d_tls_rho, 3 * nt * sizeof(double),
+                              hipMemcpyDeviceToDevice, s->stream));
+    }
+    // E~ of the last step, as mlk_get_emitter_io reports it
+    if (c0 + kc == nsteps)
+      HIPCHK(hipMemcpyAsync(s->d_Et, e + (size_t)(kc - 1) * per, per * sizeof(double),
+                            hipMemcpyDeviceToDevice, s->stream));
+    if (host && o)
+      HIPCHK(hipMemcpyAsync(tls_out + (size_t)c0 * 3 * nt, dO.p, (size_t)kc * 3 * nt * sizeof(double),
+                            hipMemcpyDeviceToHost, s->stream));
+    if (host) HIPCHK(hipStreamSynchronize(s->stream));  // staging is reused
+  }
+  return MLK_OK;
+}
+
 mlk_status mlk_set_timing(mlk_sim* s, int32_t on) {
   if (!s) return fail(MLK_EINVAL, "null argument");
   STCHK(sync_sim(s));
@@ -1487,17 +1552,6 @@ mlk_status mlk_checkpoint_load(mlk_sim* s, const void* src, int32_t mem_kind) {
 // it was before the call.
 
 namespace {
-
-template <typename T>
-struct DevBuf {
-  T* p = nullptr;
-  ~DevBuf() { dfree(p); }
-  hipError_t alloc(size_t n) {
-    dfree(p);
-    if (n == 0) return hipSuccess;
-    return dalloc(&p, n * sizeof(T));
-  }
-};
 
 template <typename T>
 mlk_status adjoint_run(mlk_sim* s, int kind, const double* weights, int64_t T_steps, int K,

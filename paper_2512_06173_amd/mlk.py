@@ -117,6 +117,7 @@ def lib():
         "mlk_batch_sync": (st, [C.c_void_p]),
         "mlk_batch_destroy": (st, [C.c_void_p]),
         "mlk_batch_autotune": (st, [C.c_void_p, C.c_char_p]),
+        "mlk_step_prescribed": (st, [sim, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p]),
         "mlk_adjoint": (st, [sim, C.POINTER(Objective), C.c_int64, C.c_int32, _ip, C.c_void_p,
                              C.c_void_p, C.POINTER(C.c_double)]),
         "mlk_set_eps_box": (st, [sim, _ip, _dp, C.c_int32]),
@@ -141,7 +142,7 @@ def exported_symbols():
     return ["mlk_grid_desc_init", "mlk_last_error", "mlk_version", "mlk_create", "mlk_destroy",
             "mlk_set_eps", "mlk_set_field", "mlk_add_tls", "mlk_add_multilevel",
             "mlk_add_plane_source", "mlk_add_point_source", "mlk_add_probe", "mlk_add_flux_plane",
-            "mlk_record_populations", "mlk_step", "mlk_sync", "mlk_step_count", "mlk_get_field",
+            "mlk_record_populations", "mlk_step", "mlk_step_prescribed", "mlk_sync", "mlk_step_count", "mlk_get_field",
             "mlk_get_rho", "mlk_get_tls_state", "mlk_get_emitter_io", "mlk_get_series",
             "mlk_get_flux_total", "mlk_checkpoint_size", "mlk_checkpoint_save",
             "mlk_checkpoint_load", "mlk_set_timing", "mlk_get_phase_time",
@@ -208,6 +209,7 @@ class Simulation:
         self.precision = precision
         self.dt = courant * dx
         self.nlev = []
+        self.n_tls = 0  # two-level emitters (mlk_add_tls), in id order
         self.nprobe = 0
 
     def close(self):
@@ -252,6 +254,7 @@ class Simulation:
         first = C.c_int32()
         _check(lib().mlk_add_tls(self._h, n, *[k[1] for k in keep], C.byref(first)))
         self.nlev += [2] * n
+        self.n_tls += n
         return first.value
 
     def add_multilevel(self, nlev, energies, mop, dipole, gphi, rho0, pos, sigma, gamma):
@@ -303,6 +306,19 @@ class Simulation:
 
     def sync(self):
         _check(lib().mlk_sync(self._h))
+
+    def step_prescribed(self, Et, record=False):
+        """Classical-path steps: every emitter advanced under the given field (no grid,
+        no back-action).  Et: (nsteps, M, 3) or (M, 3), gamma times the smeared field per
+        emitter.  With record, returns the two-level states after every step,
+        (nsteps, ntls, 3) as (rho11, Re rho01, Im rho01)."""
+        M = len(self.nlev)
+        E = np.ascontiguousarray(np.asarray(Et, dtype=np.float64).reshape(-1, M, 3))
+        out = np.zeros((E.shape[0], self.n_tls, 3)) if record else None
+        _check(lib().mlk_step_prescribed(self._h, E.shape[0], E.ctypes.data_as(C.c_void_p),
+                                         MEM_HOST, out.ctypes.data_as(C.c_void_p)
+                                         if record and self.n_tls else None))
+        return out
 
     @property
     def step_count(self):

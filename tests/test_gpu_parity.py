@@ -435,3 +435,30 @@ def test_mixed_tls_and_multilevel_fp64():
                      rho0=np.tile([0.5, 0.5, 0.0], (Mt, 1)))
     sim, ora = run_both(w)
     check(sim, ora, w)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_superradiance_2d_rate_on_the_gpu(precision):
+    """The paper's 2-D validation on the GPU path: z-invariant vacuum grid, TLS in the
+    weak-excitation state; P_e decays as exp(-N gamma t) with gamma = mu^2 w^2 / 2 times
+    the Gaussian kernel's form factor exp(-(w sigma)^2), for N = 1 and N = 4 collocated
+    emitters (the rate law pinned on the oracle)."""
+    n, d, steps, w0, mu = 128, 16, 4000, 0.25, 0.1
+    gamma = mu ** 2 * w0 ** 2 / 2 * np.exp(-w0 ** 2)
+    for N in (1, 4):
+        w = W.Workload(name="2d_rate", shape=(n, n, 1),
+                       bc=("cpml",) * 4 + ("periodic",) * 2, cpml=(d, d, d, d, 0, 0),
+                       steps=steps, precision=precision, pop_every=1,
+                       tls=W.TLSSet(pos=np.tile([n / 2, n / 2, 0.5], (N, 1)), sigma=np.ones(N),
+                                    gamma=np.ones(N), omega0=np.full(N, w0),
+                                    dipole=np.tile([0.0, 0.0, mu], (N, 1)),
+                                    rho0=np.tile([1e-4, np.sqrt(0.9999) * 0.01, 0.0], (N, 1))))
+        sim = mlk().from_workload(w)
+        sim.step(steps)
+        P = sim.populations()
+        t = (np.arange(P.shape[0]) + 0.5) * sim.dt
+        sel = t > 200.0
+        for q in range(N):
+            rate = -np.polyfit(t[sel], np.log(P[sel, q]), 1)[0]
+            say(f"  {precision} N={N} emitter {q}: rate / (N gamma) = {rate / (N * gamma):.4f}")
+            assert abs(rate / (N * gamma) - 1) < 0.02
