@@ -104,6 +104,11 @@ typedef struct ora_sim {
   ora_series pop_series;
   int energy_on;
   ora_series energy_series;
+  /* single-mode cavity (no grid): frequency, effective volume, coupling, and the
+   * mode coordinates q (integer steps), p = dq/dt (half steps) and the total
+   * dipole d (integer steps), for the x and y polarisations */
+  int cav_on;
+  double cav_w, cav_V, cav_eps, cav_q[2], cav_p[2], cav_d[2];
 } ora_sim;
 
 static void series_push(ora_series* s, double v) {
@@ -852,6 +857,85 @@ static void emitter_advance(const ora_sim* s, ora_emitter* e) {
   dipole_rate(e);
 }
 
+/* Expectation value of the dipole operator, <mu^c> = d^c Tr(rho M). */
+static void dipole_expect(const ora_emitter* e, double out[3]) {
+  int n = e->n;
+  double tr = 0.0;
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) tr += creal(e->rho[a * n + b]) * e->M[b * n + a];
+  for (int c = 0; c < 3; ++c) out[c] = tr * e->d[c];
+}
+
+/* Single-mode cavity (Sec. II.A.2: eqs. H_F_normalmode, eom_cavmd,
+ * varepsilon_cavmd, dklambda_def, E_normalmode in the single-mode limit): one
+ * photonic mode of frequency w, polarised along x and along y, with mode function
+ * e_l / sqrt(V); with eps0 = 1 the coupling is eps = w / sqrt(V).  Every emitter
+ * feels the same field E~ = -sum_l (eps q_l + d_l / V) e_l and the mode obeys
+ * q_l'' = -w^2 q_l - eps d_l, d_l = sum_m <mu_l^(m)>.  Discretised as the grid
+ * scheme is: q at integer steps, p = q' at half steps (leapfrog), emitters at
+ * half steps, and the total dipole advanced by the same mu_dot that the grid
+ * turns into a current: d^{n+1} = d^n + dt sum_m mu_dot^{n+1/2}, from d^0 =
+ * sum_m <mu> of the initial states.  Step n -> n+1:
+ *   E~^n from q^n and d^n; rho^{n-1/2} -> rho^{n+1/2}, mu_dot^{n+1/2};
+ *   p^{n+1/2} = p^{n-1/2} - dt (w^2 q^n + eps d^n);  q^{n+1} = q^n + dt p^{n+1/2};
+ *   d^{n+1} = d^n + dt sum_m mu_dot^{n+1/2}  (emitters summed in index order).
+ * The grid is left alone.  Call after the emitters are added and before the
+ * first step. */
+int ora_set_cavity(ora_sim* s, double w, double V, const double q0[2], const double p0[2]) {
+  if (!(w > 0.0) || !(V > 0.0) || s->step != 0) return -1;
+  s->cav_on = 1;
+  s->cav_w = w;
+  s->cav_V = V;
+  s->cav_eps = w / sqrt(V);
+  s->cav_d[0] = s->cav_d[1] = 0.0;
+  for (int m = 0; m < s->nem; ++m) {
+    double mu[3];
+    dipole_expect(&s->em[m], mu);
+    s->cav_d[0] += mu[0];
+    s->cav_d[1] += mu[1];
+  }
+  for (int l = 0; l < 2; ++l) {
+    s->cav_q[l] = q0[l];
+    s->cav_p[l] = p0[l];
+  }
+  return 0;
+}
+
+/* q_x, q_y, p_x, p_y, d_x, d_y at the current step (p at the half step before). */
+void ora_get_cavity(const ora_sim* s, double out[6]) {
+  for (int l = 0; l < 2; ++l) {
+    out[l] = s->cav_q[l];
+    out[2 + l] = s->cav_p[l];
+    out[4 + l] = s->cav_d[l];
+  }
+}
+
+static void cavity_step(ora_sim* s) {
+  const double dt = s->dt, w2 = s->cav_w * s->cav_w, eps = s->cav_eps;
+  double Et[3] = {-(eps * s->cav_q[0] + s->cav_d[0] / s->cav_V),
+                  -(eps * s->cav_q[1] + s->cav_d[1] / s->cav_V), 0.0};
+#pragma omp parallel for schedule(static)
+  for (int m = 0; m < s->nem; ++m) {
+    memcpy(s->em[m].Et, Et, 3 * sizeof(double));
+    emitter_advance(s, &s->em[m]);
+  }
+  double sum[2] = {0.0, 0.0};
+  for (int m = 0; m < s->nem; ++m) {
+    sum[0] += s->em[m].mudot[0];
+    sum[1] += s->em[m].mudot[1];
+  }
+  for (int l = 0; l < 2; ++l) {
+    s->cav_p[l] -= dt * (w2 * s->cav_q[l] + eps * s->cav_d[l]);
+    s->cav_q[l] += dt * s->cav_p[l];
+    s->cav_d[l] += dt * sum[l];
+  }
+  if (s->pop_every > 0 && s->step % s->pop_every == 0)
+    for (int m = 0; m < s->nem; ++m)
+      for (int k = 1; k < s->em[m].n; ++k)
+        series_push(&s->pop_series, creal(s->em[m].rho[k * s->em[m].n + k]));
+  s->step++;
+}
+
 /* Advance every emitter by one step under a prescribed field E~ (M x 3),
  * without any grid: the classical-path mode of eq. E_analytical. */
 void ora_emitters_step_prescribed(ora_sim* s, const double* Et) {
@@ -1010,7 +1094,10 @@ static void step_once(ora_sim* s) {
 }
 
 void ora_step(ora_sim* s, int64_t nsteps) {
-  for (int64_t q = 0; q < nsteps; ++q) step_once(s);
+  for (int64_t q = 0; q < nsteps; ++q) {
+    if (s->cav_on) cavity_step(s);
+    else step_once(s);
+  }
 }
 
 int ora_threads(void) {

@@ -81,6 +81,9 @@ def lib():
     L.ora_step.argtypes = [C.c_void_p, C.c_int64]
     L.ora_jacobi_eig.argtypes = [C.c_int, _dp, _dp, _dp]
     L.ora_emitters_step_prescribed.argtypes = [C.c_void_p, _dp]
+    L.ora_set_cavity.argtypes = [C.c_void_p, C.c_double, C.c_double, _dp, _dp]
+    L.ora_set_cavity.restype = C.c_int
+    L.ora_get_cavity.argtypes = [C.c_void_p, _dp]
     L.ora_gather.argtypes = [C.c_void_p, _dp]
     L.ora_scatter.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
     L.ora_dipole_rate_trace.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
@@ -348,6 +351,21 @@ class Oracle:
         J = [np.zeros(self.ncell) for _ in range(3)]
         lib().ora_scatter(self._h, _f64(mudot, (M, 3)).ravel(), J[0], J[1], J[2])
         return [j.reshape(nz, ny, nx) for j in J]
+
+    def set_cavity(self, omega, volume, q0=(0.0, 0.0), p0=(0.0, 0.0)):
+        """Single-mode cavity instead of the grid (x and y polarisations); call after
+        adding the emitters, before stepping."""
+        st = lib().ora_set_cavity(self._h, float(omega), float(volume),
+                                  _f64(q0, (2,)), _f64(p0, (2,)))
+        if st != 0:
+            raise ValueError("oracle: bad cavity")
+
+    def cavity(self):
+        """(q_x, q_y, p_x, p_y, d_x, d_y): q and d at the current step, p half a step
+        before."""
+        out = np.zeros(6)
+        lib().ora_get_cavity(self._h, out)
+        return out
 
     def emitters_step_prescribed(self, Et):
         M = len(self.nlev)

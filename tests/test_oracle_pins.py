@@ -649,3 +649,93 @@ def test_flux_is_the_energy_flow_through_the_plane():
     assert np.max(np.abs(0.5 * (dA + dB) - dt * F[:steps])) <= 1e-12 * scale
     # a wrong half-plane (only one side of the average) is caught
     assert np.max(np.abs(dA - dt * F[:steps])) > 1e-6 * scale
+
+
+# --------------------------------------------------------------- single-mode cavity
+def _cavity_run(o, steps):
+    out = np.empty((steps + 1, 6))
+    out[0] = o.cavity()
+    for n in range(steps):
+        o.step(1)
+        out[n + 1] = o.cavity()
+    return out
+
+
+def test_cavity_free_mode_is_the_leapfrog_oscillator():
+    """No emitters: the mode is a leapfrog oscillator, q^n = cos(n theta) for x and
+    0.5 sin(n theta) for y exactly, sin(theta/2) = w dt / 2, given the matching p^{-1/2}."""
+    o = Oracle((1, 1, 1), bc=("periodic",) * 6)
+    w, dt = 0.3, o.dt
+    th = 2.0 * np.arcsin(w * dt / 2.0)
+    # q^1 = q^0 + dt (p^{-1/2} - dt w^2 q^0) must equal cos(theta), resp. 0.5 sin(theta)
+    p0 = ((np.cos(th) - 1.0) / dt + dt * w * w, 0.5 * np.sin(th) / dt)
+    o.set_cavity(w, 7.0, q0=(1.0, 0.0), p0=p0)
+    tr = _cavity_run(o, 500)
+    n = np.arange(501)
+    assert np.max(np.abs(tr[:, 0] - np.cos(n * th))) < 1e-12
+    assert np.max(np.abs(tr[:, 1] - 0.5 * np.sin(n * th))) < 1e-12
+    assert np.all(tr[:, 4:] == 0.0)
+    with pytest.raises(ValueError):
+        Oracle((1, 1, 1), bc=("periodic",) * 6).set_cavity(0.0, 1.0)
+
+
+def _polariton_trace(n_emit, d, w, w0, V, A, T, courant=0.05):
+    o = Oracle((1, 1, 1), bc=("periodic",) * 6, courant=courant)
+    o.add_tls(np.tile([0.5, 0.5, 0.5], (n_emit, 1)), np.ones(n_emit), np.ones(n_emit),
+              np.full(n_emit, w0), np.tile([d, 0.0, 0.0], (n_emit, 1)),
+              np.zeros((n_emit, 3)))
+    th = 2.0 * np.arcsin(w * o.dt / 2.0)
+    o.set_cavity(w, V, q0=(A, 0.5), p0=(0.0, (np.cos(th) - 1.0) / o.dt * 0.5 + o.dt * w * w * 0.5))
+    steps = int(round(T / o.dt))
+    return o.dt, th, _cavity_run(o, steps)
+
+
+def _fit_residual(t, y, freqs):
+    B = np.concatenate([np.stack([np.cos(f * t), np.sin(f * t)], 1) for f in freqs], 1)
+    c, *_ = np.linalg.lstsq(B, y, rcond=None)
+    return np.linalg.norm(B @ c - y) / np.linalg.norm(y)
+
+
+def test_cavity_vacuum_rabi_splitting_linear_response():
+    """Weakly driven TLS in the mode (Sec. II.A.2 coupling with the dipole self-energy):
+    the linearised pair q'' = -w^2 q - eps mu, mu'' = -w0^2 mu - 2 w0 d^2 (eps q + mu / V)
+    (a TLS ground state has polarisability 2 d^2 / w0) oscillates at the two normal-mode
+    frequencies.  q_x must be a sum of exactly those two; dropping the self-energy or
+    flipping the sign of the dipole's force on the mode gives other frequencies, which the
+    fit then misses."""
+    w = w0 = 0.25
+    d, V, A, T = 0.05, 1.0, 0.01, 1200.0
+    dt, th, tr = _polariton_trace(1, d, w, w0, V, A, T)
+    t = np.arange(tr.shape[0]) * dt
+    eps = w / np.sqrt(V)
+
+    def normal_modes(self_term=1.0, back_action=1.0):
+        K = np.array([[w * w, back_action * eps],
+                      [2 * w0 * d * d * eps, w0 * w0 + self_term * 2 * w0 * d * d / V]])
+        return np.sqrt(np.linalg.eigvals(K).real)
+
+    ref = normal_modes()
+    split = abs(ref[1] - ref[0])
+    assert split > 0.02  # well resolved within T
+    assert _fit_residual(t, tr[:, 0], ref) < 5e-3
+    assert _fit_residual(t, tr[:, 0], normal_modes(self_term=0.0)) > 0.1
+    assert _fit_residual(t, tr[:, 0], normal_modes(back_action=-1.0)) > 0.1
+    assert _fit_residual(t, tr[:, 0], [w]) > 0.1
+    # the y polarisation does not see an x dipole: it stays the free leapfrog oscillator
+    n = np.arange(tr.shape[0])
+    assert np.max(np.abs(tr[:, 1] - 0.5 * np.cos(n * th))) < 1e-12
+    assert np.all(tr[:, 5] == 0.0)
+
+
+def test_cavity_collective_coupling_sums_the_dipoles():
+    """N identical emitters of dipole d / sqrt(N) have the polarisability of one of dipole
+    d, so in linear response the mode cannot tell them apart (the total dipole sums over
+    emitters); they differ only at second order in the excitation."""
+    w, w0, d, V, A, T = 0.25, 0.25, 0.05, 1.0, 0.01, 300.0
+    _, _, one = _polariton_trace(1, d, w, w0, V, A, T)
+    _, _, four = _polariton_trace(4, d / 2.0, w, w0, V, A, T)
+    _, _, four_full = _polariton_trace(4, d, w, w0, V, A, T)
+    scale = np.max(np.abs(one[:, 0]))
+    assert np.max(np.abs(four[:, 0] - one[:, 0])) < 1e-3 * scale
+    assert np.max(np.abs(four[:, 4] - one[:, 4])) < 1e-3 * np.max(np.abs(one[:, 4]))
+    assert np.max(np.abs(four_full[:, 0] - one[:, 0])) > 0.1 * scale
