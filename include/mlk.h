@@ -190,6 +190,33 @@ mlk_status mlk_step_prescribed(mlk_sim* s, int64_t nsteps, const double* Et, int
 mlk_status mlk_sync(mlk_sim* s);
 mlk_status mlk_step_count(mlk_sim* s, int64_t* n);
 
+/* Single-mode cavity in place of the grid (Sec. II.A.2: the normal-mode field
+ * Hamiltonian with the dipole self-energy and its equations of motion, in the
+ * single-mode limit; eps0 = 1).  One mode of frequency omega > 0 and effective
+ * volume V > 0 with an x and a y polarisation; the coupling is
+ * eps = omega / sqrt(V).  Every emitter then sees the same field
+ * E~ = -sum_l (eps q_l + d_l / V) e_l (gamma, positions and widths are not
+ * used), where d = sum_m <mu^(m)>, and the mode obeys
+ * q_l'' = -omega^2 q_l - eps d_l.  Per step: E~ from q^n and d^n, the emitter
+ * steps (as the coupled step does them), then
+ *   p^{n+1/2} = p^{n-1/2} - dt (omega^2 q^n + eps d^n),  q^{n+1} = q^n + dt p^{n+1/2},
+ *   d^{n+1} = d^n + dt sum_m mu_dot^{n+1/2},
+ * with d^0 the sum of the current states' expectation values.  q0 and p0 are
+ * (x, y): q at step 0 and p half a step before.  mlk_step then advances the
+ * emitters and the mode and leaves the grid alone; populations are recorded as
+ * usual and checkpoints carry the mode state.  Call after every emitter is
+ * added and before the first step.  EINVAL: null pointers, omega or V not
+ * positive and finite, non-finite q0/p0.  ESTATE: after stepping, in a batch.
+ * EUNSUPPORTED: with sources, probes or a flux plane.  Afterwards adding
+ * emitters (ESTATE), sources, probes or a flux plane, batching, the adjoint
+ * (EUNSUPPORTED) and mlk_step_prescribed (ESTATE) are refused. */
+mlk_status mlk_set_cavity(mlk_sim* s, double omega, double volume, const double q0[2],
+                          const double p0[2]);
+/* Mode state (q_x, q_y, p_x, p_y, d_x, d_y) into out[6] (host): q and d at the
+ * current step, p half a step before.  Synchronises.  ESTATE: no cavity. */
+mlk_status mlk_get_cavity(mlk_sim* s, double out[6]);
+
+
 /* Read a field component (0..5) as nx*ny*nz doubles. */
 mlk_status mlk_get_field(mlk_sim* s, int32_t comp, double* dst, int32_t mem_kind);
 /* Density matrix of emitter id as n*n complex (re/im interleaved); *nlev gets n.

@@ -144,6 +144,12 @@ hipError_t pack_tape_f64(const FieldPtrs<double>& f, const Geom& g, const Box& b
                          double* box_out, const FluxPlane* fp, double* flux_out, hipStream_t st);
 hipError_t pack_tape_f32(const FieldPtrs<float>& f, const Geom& g, const Box& box, float* box_out,
                          const FluxPlane* fp, double* flux_out, hipStream_t st);
+// Single-mode cavity: E~ of every emitter from the mode state, then the
+// sum of mu_dot over the emitters, the (p, q, d) update and the step counter.
+int cavity_blocks(int M);
+hipError_t cavity_field(const CavityDev& c, double* Et, int M, hipStream_t st);
+hipError_t cavity_update(const CavityDev& c, const double* mudot, int M, double dt, int64_t* step,
+                         hipStream_t st);
 hipError_t eps_box_f64(const double* eps, const Geom& g, const Box& box, double* epsinv,
                        hipStream_t st);
 hipError_t eps_box_f32(const double* eps, const Geom& g, const Box& box, float* epsinv,

@@ -214,6 +214,13 @@ struct FluxPlane {
   double* total;    // running dt * sum F
 };
 
+// Single-mode cavity that replaces the grid: mode state and coupling.
+struct CavityDev {
+  double* st;       // q_x, q_y, p_x, p_y, d_x, d_y (FP64)
+  double* partial;  // per-block partial sums of mu_dot_x, mu_dot_y
+  double w, V, eps; // mode frequency, effective volume, eps = w / sqrt(V)
+};
+
 // Cell (index along axis a; iu, iv along the two others in cyclic order) of a plane.
 __device__ __forceinline__ size_t plane_cell(const Geom& g, int a, int index, int iu, int iv) {
   const int u = (a + 1) % 3, v = (a + 2) % 3;

@@ -171,6 +171,10 @@ struct mlk_sim {
 
   int64_t* d_step = nullptr;
   int64_t host_step = 0;
+
+  // single-mode cavity in place of the grid (off unless mlk_set_cavity was called)
+  bool cav_on = false;
+  CavityDev cav{};
 };
 
 namespace {
@@ -795,6 +799,27 @@ mlk_status enqueue_steps(mlk_sim* s, int64_t nsteps) {
   return MLK_OK;
 }
 
+// Cavity steps: E~ from the mode, the emitter steps, then the mode update
+// (which also moves the step counter on).  The grid is left alone.
+mlk_status enqueue_cavity_steps(mlk_sim* s, int64_t nsteps) {
+  const Series ser = series_of(s);
+  const TlsPtrs tls = tls_ptrs(s);
+  const MlDev ml = ml_dev(s);
+  for (int64_t q = 0; q < nsteps; ++q) {
+    const int t0 = mark_begin(s, MLK_PHASE_EMITTERS);
+    if (s->nem > 0) {
+      HIPCHK(cavity_field(s->cav, s->d_Et, s->nem, s->stream));
+      HIPCHK(tls_step(tls, s->g.dt, s->d_Et, s->d_mudot, s->d_popoff, ser, s->d_step, s->stream));
+      if (ml.count > 0)
+        HIPCHK(ml_step(ml, s->ml_range, s->g.dt, s->d_Et, s->d_mudot, s->d_popoff, ser,
+                       s->d_step, s->stream));
+    }
+    HIPCHK(cavity_update(s->cav, s->d_mudot, s->nem, s->g.dt, s->d_step, s->stream));
+    mark_end(s, MLK_PHASE_EMITTERS, t0);
+  }
+  return MLK_OK;
+}
+
 void release(mlk_sim* s) {
   for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
   s->events.clear();
@@ -843,6 +868,8 @@ void release(mlk_sim* s) {
   dfree(s->fp.total);
   dfree(s->d_pop);
   dfree(s->d_step);
+  dfree(s->cav.st);
+  dfree(s->cav.partial);
   if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
   s->stream = nullptr;
 }
@@ -867,6 +894,7 @@ std::vector<Piece> state_pieces(mlk_sim* s) {
   }
   v.push_back({s->d_step, sizeof(int64_t)});
   if (s->fp.on) v.push_back({s->fp.total, sizeof(double)});
+  if (s->cav_on) v.push_back({s->cav.st, 6 * sizeof(double)});
   return v;
 }
 
@@ -1086,6 +1114,7 @@ mlk_status mlk_add_tls(mlk_sim* s, int32_t n, const double* pos, const double* s
     return fail(MLK_EINVAL, "null argument");
   if (n < 0) return fail(MLK_EINVAL, "negative count");
   if (s->host_step > 0) return fail(MLK_ESTATE, "emitters must be added before stepping");
+  if (s->cav_on) return fail(MLK_ESTATE, "emitters must be added before the cavity is set");
   for (int q = 0; q < n; ++q) {
     STCHK(check_emitter_geometry(s, pos + 3 * q, sigma[q]));
     const double p = rho0[3 * q], re = rho0[3 * q + 1], im = rho0[3 * q + 2];
@@ -1122,6 +1151,7 @@ mlk_status mlk_add_multilevel(mlk_sim* s, int32_t n, const int32_t* nlev, const 
     return fail(MLK_EINVAL, "null argument");
   if (n < 0) return fail(MLK_EINVAL, "negative count");
   if (s->host_step > 0) return fail(MLK_ESTATE, "emitters must be added before stepping");
+  if (s->cav_on) return fail(MLK_ESTATE, "emitters must be added before the cavity is set");
   for (int q = 0; q < n; ++q) {
     const int L = nlev[q];
     if (L < 2 || L > kMaxLevels)
@@ -1179,6 +1209,7 @@ mlk_status mlk_add_multilevel(mlk_sim* s, int32_t n, const int32_t* nlev, const 
 }
 
 static mlk_status add_source(mlk_sim* s, const Source& src) {
+  if (s->cav_on) return fail(MLK_EUNSUPPORTED, "the cavity replaces the grid: no sources");
   if (s->src.count >= kMaxSources) return fail(MLK_EINVAL, "at most %d sources", kMaxSources);
   if (!(src.tau > 0.0) || !std::isfinite(src.amp) || !std::isfinite(src.omega) ||
       !std::isfinite(src.t0))
@@ -1224,6 +1255,7 @@ mlk_status mlk_add_point_source(mlk_sim* s, int32_t comp, const int32_t ijk[3], 
 mlk_status mlk_add_probe(mlk_sim* s, int32_t comp, const int32_t ijk[3], int32_t* id) {
   if (!s || !ijk) return fail(MLK_EINVAL, "null argument");
   if (s->host_step > 0) return fail(MLK_ESTATE, "probes must be added before stepping");
+  if (s->cav_on) return fail(MLK_EUNSUPPORTED, "the cavity replaces the grid: no probes");
   if (s->nprobe >= 16) return fail(MLK_EINVAL, "at most 16 probes");
   if (comp < 0 || comp > 5) return fail(MLK_EINVAL, "bad component");
   for (int a = 0; a < 3; ++a)
@@ -1241,6 +1273,7 @@ mlk_status mlk_add_flux_plane(mlk_sim* s, int32_t axis, int32_t index) {
   if (!s) return fail(MLK_EINVAL, "null argument");
   if (s->host_step > 0) return fail(MLK_ESTATE, "detectors must be added before stepping");
   if (s->fp.on) return fail(MLK_EINVAL, "one flux plane per simulation");
+  if (s->cav_on) return fail(MLK_EUNSUPPORTED, "the cavity replaces the grid: no flux plane");
   if (axis < 0 || axis > 2 || index < 1 || index >= s->g.n[axis])
     return fail(MLK_EINVAL, "flux plane index must be 1..n-1");
   const int u = (axis + 1) % 3, v = (axis + 2) % 3;
@@ -1276,7 +1309,9 @@ mlk_status mlk_step(mlk_sim* s, int64_t nsteps) {
   HIPCHK(hipSetDevice(s->desc.device));
   if (s->batch_stream) HIPCHK(hipStreamSynchronize(s->batch_stream));
   STCHK(reserve_series(s, nsteps));
-  mlk_status st = s->fp32 ? enqueue_steps<float>(s, nsteps) : enqueue_steps<double>(s, nsteps);
+  mlk_status st = s->cav_on ? enqueue_cavity_steps(s, nsteps)
+                  : s->fp32 ? enqueue_steps<float>(s, nsteps)
+                            : enqueue_steps<double>(s, nsteps);
   if (st == MLK_OK) s->host_step += nsteps;
   return st;
 }
@@ -1286,6 +1321,7 @@ mlk_status mlk_step_prescribed(mlk_sim* s, int64_t nsteps, const double* Et, int
   if (!s) return fail(MLK_EINVAL, "null argument");
   if (nsteps < 0) return fail(MLK_EINVAL, "negative step count");
   if (mem_kind != MLK_MEM_HOST && mem_kind != MLK_MEM_DEVICE) return fail(MLK_EINVAL, "bad mem_kind");
+  if (s->cav_on) return fail(MLK_ESTATE, "the cavity sets the field");
   if (nsteps == 0 || s->nem == 0) return MLK_OK;
   if (!Et) return fail(MLK_EINVAL, "null field");
   HIPCHK(hipSetDevice(s->desc.device));
@@ -1331,6 +1367,65 @@ mlk_status mlk_step_prescribed(mlk_sim* s, int64_t nsteps, const double* Et, int
                             hipMemcpyDeviceToHost, s->stream));
     if (host) HIPCHK(hipStreamSynchronize(s->stream));  // staging is reused
   }
+  return MLK_OK;
+}
+
+mlk_status mlk_set_cavity(mlk_sim* s, double omega, double volume, const double q0[2],
+                          const double p0[2]) {
+  if (!s || !q0 || !p0) return fail(MLK_EINVAL, "null argument");
+  if (!(omega > 0.0) || !(volume > 0.0) || !std::isfinite(omega) || !std::isfinite(volume))
+    return fail(MLK_EINVAL, "cavity frequency and volume must be positive");
+  for (int l = 0; l < 2; ++l)
+    if (!std::isfinite(q0[l]) || !std::isfinite(p0[l])) return fail(MLK_EINVAL, "bad mode state");
+  if (s->host_step > 0) return fail(MLK_ESTATE, "the cavity must be set before stepping");
+  if (s->in_batch) return fail(MLK_ESTATE, "the sim belongs to a batch");
+  if (s->src.count > 0 || s->nprobe > 0 || s->fp.on)
+    return fail(MLK_EUNSUPPORTED, "the cavity replaces the grid: no sources, probes or flux plane");
+  HIPCHK(hipSetDevice(s->desc.device));
+  STCHK(sync_sim(s));
+  // d^0 = sum over emitters (id order) of d Tr(rho M) of the current states
+  const size_t nt = s->tls_gid.size(), nml = s->ml_gid.size();
+  constexpr int F = kMaxLevels;
+  std::vector<double> trho(3 * nt), mrho(2 * F * F * nml), mM(F * F * nml), mdip(3 * nml);
+  if (nt) HIPCHK(hipMemcpy(trho.data(), s->d_tls_rho, trho.size() * 8, hipMemcpyDeviceToHost));
+  if (nml) {
+    HIPCHK(hipMemcpy(mrho.data(), s->d_ml_rho, mrho.size() * 8, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(mM.data(), s->d_ml_M, mM.size() * 8, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(mdip.data(), s->d_ml_dip, mdip.size() * 8, hipMemcpyDeviceToHost));
+  }
+  double st[6] = {q0[0], q0[1], p0[0], p0[1], 0.0, 0.0};
+  for (int e = 0; e < s->nem; ++e) {
+    const int k = s->tls_slot[e];
+    double mu[2];
+    if (k >= 0) {
+      const double tr = trho[3 * (size_t)k + 1] + trho[3 * (size_t)k + 1];  // Tr(rho sigma_x)
+      for (int c = 0; c < 2; ++c) mu[c] = tr * s->tls_dip[3 * (size_t)k + c];
+    } else {
+      const size_t m = (size_t)s->ml_slot[e];
+      double tr = 0.0;
+      for (int a = 0; a < F; ++a)
+        for (int b = 0; b < F; ++b)
+          tr += mrho[(size_t)(2 * (a * F + b)) * nml + m] * mM[(size_t)(b * F + a) * nml + m];
+      for (int c = 0; c < 2; ++c) mu[c] = tr * mdip[(size_t)c * nml + m];
+    }
+    st[4] += mu[0];
+    st[5] += mu[1];
+  }
+  if (!s->cav.st) HIPCHK(dalloc(&s->cav.st, 6 * sizeof(double)));
+  if (!s->cav.partial) HIPCHK(dalloc(&s->cav.partial, 2 * 256 * sizeof(double)));
+  HIPCHK(hipMemcpy(s->cav.st, st, sizeof(st), hipMemcpyHostToDevice));
+  s->cav.w = omega;
+  s->cav.V = volume;
+  s->cav.eps = omega / std::sqrt(volume);
+  s->cav_on = true;
+  return MLK_OK;
+}
+
+mlk_status mlk_get_cavity(mlk_sim* s, double out[6]) {
+  if (!s || !out) return fail(MLK_EINVAL, "null argument");
+  if (!s->cav_on) return fail(MLK_ESTATE, "no cavity");
+  STCHK(sync_sim(s));
+  HIPCHK(hipMemcpy(out, s->cav.st, 6 * sizeof(double), hipMemcpyDeviceToHost));
   return MLK_OK;
 }
 
@@ -1756,6 +1851,7 @@ mlk_status mlk_adjoint(mlk_sim* s, const mlk_objective* obj, int64_t nsteps, int
                        double* value) {
   if (!s || !obj || !box || !value) return fail(MLK_EINVAL, "null argument");
   if (s->in_batch) return fail(MLK_ESTATE, "the sim belongs to a batch");
+  if (s->cav_on) return fail(MLK_EUNSUPPORTED, "the adjoint covers the grid, not the cavity");
   if (nsteps <= 0 || ckpt_every <= 0) return fail(MLK_EINVAL, "steps and checkpoint interval must be positive");
   if (!s->ml_gid.empty()) return fail(MLK_EUNSUPPORTED, "the adjoint covers two-level emitters only");
   if (obj->kind == MLK_OBJ_FLUX) {
@@ -2144,6 +2240,10 @@ mlk_status mlk_batch_create(mlk_sim* const* sims, int32_t n, mlk_batch** out) {
         delete b;
         return fail(MLK_EINVAL, "member %d appears twice", q);
       }
+    if (s->cav_on) {
+      delete b;
+      return fail(MLK_EUNSUPPORTED, "member %d steps a cavity, not a grid", q);
+    }
     const mlk_sim* s0 = sims[0];
     if (s->fp32 != s0->fp32 || s->desc.sweep != s0->desc.sweep || s->host_step != s0->host_step ||
         s->desc.device != s0->desc.device) {

@@ -118,6 +118,8 @@ def lib():
         "mlk_batch_destroy": (st, [C.c_void_p]),
         "mlk_batch_autotune": (st, [C.c_void_p, C.c_char_p]),
         "mlk_step_prescribed": (st, [sim, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p]),
+        "mlk_set_cavity": (st, [sim, C.c_double, C.c_double, _dp, _dp]),
+        "mlk_get_cavity": (st, [sim, _dp]),
         "mlk_adjoint": (st, [sim, C.POINTER(Objective), C.c_int64, C.c_int32, _ip, C.c_void_p,
                              C.c_void_p, C.POINTER(C.c_double)]),
         "mlk_set_eps_box": (st, [sim, _ip, _dp, C.c_int32]),
@@ -142,7 +144,8 @@ def exported_symbols():
     return ["mlk_grid_desc_init", "mlk_last_error", "mlk_version", "mlk_create", "mlk_destroy",
             "mlk_set_eps", "mlk_set_field", "mlk_add_tls", "mlk_add_multilevel",
             "mlk_add_plane_source", "mlk_add_point_source", "mlk_add_probe", "mlk_add_flux_plane",
-            "mlk_record_populations", "mlk_step", "mlk_step_prescribed", "mlk_sync", "mlk_step_count", "mlk_get_field",
+            "mlk_record_populations", "mlk_step", "mlk_step_prescribed",
+            "mlk_set_cavity", "mlk_get_cavity", "mlk_sync", "mlk_step_count", "mlk_get_field",
             "mlk_get_rho", "mlk_get_tls_state", "mlk_get_emitter_io", "mlk_get_series",
             "mlk_get_flux_total", "mlk_checkpoint_size", "mlk_checkpoint_save",
             "mlk_checkpoint_load", "mlk_set_timing", "mlk_get_phase_time",
@@ -318,6 +321,21 @@ class Simulation:
         _check(lib().mlk_step_prescribed(self._h, E.shape[0], E.ctypes.data_as(C.c_void_p),
                                          MEM_HOST, out.ctypes.data_as(C.c_void_p)
                                          if record and self.n_tls else None))
+        return out
+
+    def set_cavity(self, omega, volume, q0=(0.0, 0.0), p0=(0.0, 0.0)):
+        """Single-mode cavity in place of the grid (x and y polarisations); call after
+        adding the emitters, before stepping."""
+        q = np.ascontiguousarray(np.asarray(q0, dtype=np.float64).reshape(2))
+        p = np.ascontiguousarray(np.asarray(p0, dtype=np.float64).reshape(2))
+        _check(lib().mlk_set_cavity(self._h, float(omega), float(volume),
+                                    q.ctypes.data_as(_dp), p.ctypes.data_as(_dp)))
+
+    def cavity(self):
+        """(q_x, q_y, p_x, p_y, d_x, d_y): q and d at the current step, p half a step
+        before."""
+        out = np.zeros(6)
+        _check(lib().mlk_get_cavity(self._h, out.ctypes.data_as(_dp)))
         return out
 
     @property

@@ -1,0 +1,170 @@
+"""Single-mode cavity in place of the grid (Sec. II.A.2: normal-mode field equations
+with the dipole self-energy, single-mode limit): the mode state, the emitter states and
+the population series against the oracle's cavity mode; the vacuum Rabi splitting of a
+weakly driven emitter; checkpoints; refused combinations."""
+import numpy as np
+import pytest
+
+from oracle.feed import build_oracle
+from paper_2512_06173_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def mlk():
+    from paper_2512_06173_amd import mlk as m
+    return m
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def ensemble(precision, seed=8):
+    """Two-level emitters with coherent initial states (ids first), then 2-6 level
+    Lindblad emitters, on a small grid that the cavity leaves alone."""
+    w = W.bragg(nx=16, ny=16, nz=112, n_emit=10, steps=0, pairs_per_mirror=3,
+                precision=precision, seed=seed)
+    w.plane_sources, w.point_sources, w.probes, w.flux = [], [], [], None
+    ml = w.multilevel
+    ml.dipole = ml.dipole * 20.0
+    ml.gphi = np.full(len(ml), 2e-3)
+    rng = np.random.default_rng(seed)
+    zc = ml.pos[:, 2].mean()
+    Mt = 9
+    pos = np.column_stack([rng.uniform(0, 16, Mt), rng.uniform(0, 16, Mt),
+                           rng.uniform(zc - 5, zc + 5, Mt)])
+    th = rng.uniform(0.2, 1.2, Mt)
+    rho0 = np.column_stack([np.sin(th / 2) ** 2, 0.5 * np.sin(th) * np.cos(th),
+                            0.5 * np.sin(th) * np.sin(th)])
+    w.tls = W.TLSSet(pos=pos, sigma=np.ones(Mt), gamma=np.ones(Mt),
+                     omega0=rng.uniform(0.24, 0.26, Mt), dipole=0.3 * rng.standard_normal((Mt, 3)),
+                     rho0=rho0)
+    w.pop_every = 1
+    return w, Mt
+
+
+def _rel(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_cavity_matches_the_oracle(precision):
+    """300 steps of a mixed ensemble in one mode: q, p and d every 50 steps, every
+    emitter's final state, the last E~ and mu_dot and the population series against the
+    oracle's cavity mode (FP64 in both field precisions: the grid is not used)."""
+    w, Mt = ensemble(precision)
+    sim = mlk().from_workload(w)
+    ora = build_oracle(w)
+    q0, p0 = (0.3, -0.1), (0.01, 0.02)
+    sim.set_cavity(0.25, 20.0, q0, p0)
+    ora.set_cavity(0.25, 20.0, q0, p0)
+    M = len(sim.nlev)
+    e0 = _rel(sim.cavity(), ora.cavity())
+    assert e0 <= 1e-14 and abs(ora.cavity()[4]) > 1e-3  # d^0 from the coherent states
+    worst = 0.0
+    for _ in range(6):
+        sim.step(50)
+        ora.step(50)
+        c, r = sim.cavity(), ora.cavity()
+        for part in (slice(0, 2), slice(2, 4), slice(4, 6)):
+            worst = max(worst, _rel(c[part], r[part]))
+    e_tls = np.max(np.abs(sim.tls_state(0, Mt) - ora.tls_state()[:Mt]))
+    e_ml = max(np.max(np.abs(sim.rho(m) - ora.rho(m))) for m in range(Mt, M))
+    et_g, md_g = sim.emitter_io()
+    et_o, md_o = ora.emitter_io()
+    e_io = max(_rel(et_g, et_o), _rel(md_g, md_o))
+    e_pop = np.max(np.abs(sim.populations() - ora.populations()))
+    say(f"[cavity] {precision}: mode {worst:.2e}, tls {e_tls:.2e}, multilevel {e_ml:.2e}, "
+        f"io {e_io:.2e}, populations {e_pop:.2e}")
+    assert sim.step_count == 300 and sim.populations().shape[0] == 300
+    assert worst <= 1e-12 and e_tls <= 1e-12 and e_ml <= 1e-12 and e_io <= 1e-12
+    assert e_pop <= 1e-12
+    assert np.all(et_g[:, 2] == 0.0) and np.all(et_g == et_g[0])
+    assert all(np.count_nonzero(f) == 0 for f in sim.fields())
+
+
+def test_cavity_vacuum_rabi_splitting():
+    """One weakly excited emitter at resonance: q_x is a sum of the two normal modes of
+    the linearised pair q'' = -w^2 q - eps mu, mu'' = -w0^2 mu - 2 w0 d^2 (eps q + mu / V),
+    and the final mode state agrees with the oracle after 24000 steps."""
+    w0 = om = 0.25
+    d, V, A = 0.05, 1.0, 0.01
+    wl = W.Workload(name="polariton", shape=(8, 8, 8), bc=("periodic",) * 6, courant=0.05,
+                    steps=0, precision="fp64",
+                    tls=W.TLSSet(pos=np.array([[4.0, 4.0, 4.0]]), sigma=np.ones(1),
+                                 gamma=np.ones(1), omega0=np.array([w0]),
+                                 dipole=np.array([[d, 0.0, 0.0]]), rho0=np.zeros((1, 3))))
+    sim = mlk().from_workload(wl)
+    sim.set_cavity(om, V, (A, 0.0), (0.0, 0.0))
+    steps, chunk = 24000, 100
+    dt = sim.dt
+    q = np.empty(steps // chunk + 1)
+    q[0] = sim.cavity()[0]
+    for k in range(steps // chunk):
+        sim.step(chunk)
+        q[k + 1] = sim.cavity()[0]
+    t = np.arange(q.size) * chunk * dt
+    eps = om / np.sqrt(V)
+    K = np.array([[om * om, eps], [2 * w0 * d * d * eps, w0 * w0 + 2 * w0 * d * d / V]])
+    f = np.sqrt(np.linalg.eigvals(K).real)
+    B = np.concatenate([np.stack([np.cos(x * t), np.sin(x * t)], 1) for x in f], 1)
+    c, *_ = np.linalg.lstsq(B, q, rcond=None)
+    res = np.linalg.norm(B @ c - q) / np.linalg.norm(q)
+    ora = build_oracle(wl)
+    ora.set_cavity(om, V, (A, 0.0), (0.0, 0.0))
+    ora.step(steps)
+    e = _rel(sim.cavity(), ora.cavity())
+    say(f"[cavity] splitting {abs(f[1] - f[0]):.4f}: fit residual {res:.2e}, vs oracle {e:.2e}")
+    assert res < 5e-3
+    assert e <= 1e-10
+
+
+def test_cavity_checkpoint_round_trip():
+    """A checkpoint taken mid-run carries the mode state: reloading it and stepping again
+    reproduces the same mode and emitter states bit for bit."""
+    w, Mt = ensemble("fp64", seed=9)
+    w.pop_every = 0
+    sim = mlk().from_workload(w)
+    sim.set_cavity(0.3, 12.0, (0.1, 0.2), (0.0, -0.01))
+    sim.step(40)
+    ck = sim.checkpoint_save()
+    sim.step(60)
+    c1, s1 = sim.cavity(), sim.tls_state(0, Mt)
+    sim.checkpoint_load(ck)
+    assert sim.step_count == 40
+    sim.step(60)
+    assert np.array_equal(sim.cavity(), c1)
+    assert np.array_equal(sim.tls_state(0, Mt), s1)
+
+
+def test_cavity_refusals():
+    """The cavity replaces the grid: sources, probes, flux planes, the adjoint, batches and
+    prescribed stepping are refused, as are a late cavity, late emitters and bad modes."""
+    m = mlk()
+    w, _ = ensemble("fp64", seed=10)
+    w.pop_every = 0
+
+    def status(fn, *a):
+        with pytest.raises(m.MlkError) as ex:
+            fn(*a)
+        return ex.value.status
+
+    sim = m.from_workload(w)
+    assert status(sim.set_cavity, 0.0, 1.0) == m.MLK_EINVAL
+    assert status(sim.set_cavity, 0.2, -1.0) == m.MLK_EINVAL
+    sim.set_cavity(0.2, 3.0)
+    tls = w.tls
+    assert status(sim.add_tls, tls.pos[:1], tls.sigma[:1], tls.gamma[:1], tls.omega0[:1],
+                  tls.dipole[:1], tls.rho0[:1]) == m.MLK_ESTATE
+    assert status(sim.add_point_source, 2, (8, 8, 50), 1.0, 0.2, 5.0, 10.0) == m.MLK_EUNSUPPORTED
+    assert status(sim.add_probe, 0, (8, 8, 50)) == m.MLK_EUNSUPPORTED
+    assert status(sim.add_flux_plane, 2, 50) == m.MLK_EUNSUPPORTED
+    assert status(sim.step_prescribed, np.zeros((1, len(sim.nlev), 3))) == m.MLK_ESTATE
+    assert status(m.Batch, [sim]) == m.MLK_EUNSUPPORTED
+    sim.step(3)
+    assert status(sim.set_cavity, 0.2, 3.0) == m.MLK_ESTATE
+    plain = m.from_workload(w)
+    plain.add_probe(0, (8, 8, 50))
+    assert status(plain.set_cavity, 0.2, 3.0) == m.MLK_EUNSUPPORTED
+    assert status(plain.cavity) == m.MLK_ESTATE
