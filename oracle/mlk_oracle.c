@@ -12,7 +12,10 @@
  *   - Maxwell's curl equations with the molecular current (Sec. II.A.1,
  *     eq. Maxwell), constitutive relation D = eps_r E with a static
  *     per-cell eps_r and mu = mu0 (eq. Dromega and the text after it),
- *     discretised on Yee's staggered grid;
+ *     discretised on Yee's staggered grid; optional Lorentz and Drude
+ *     poles (the dielectric functions of eq. Dromega) as polarisation
+ *     oscillators advanced by central differences;
+ *   - a single-mode cavity in place of the grid (Sec. II.A.2);
  *   - textbook convolutional PML backed by a perfect conductor, periodic
  *     and metallic walls (the boundary conditions of Sec. III);
  *   - Gaussian kernel normalised to unit integral, the regularised field
@@ -76,6 +79,18 @@ typedef struct {
   int64_t len, cap;
 } ora_series;
 
+/* One Lorentz or Drude pole of a dispersive block (Sec. II.A.1, eq. Dromega):
+ * chi(w) = sigma w0^2 / (kappa w0^2 - w^2 - i w gamma), kappa = 1 (Lorentz) or
+ * 0 (Drude), over the half-open cell box [lo, hi).  Its polarisation obeys
+ * P'' + gamma P' + kappa w0^2 P = sigma w0^2 E for every E component stored
+ * in the box; P at integer steps, current and previous. */
+typedef struct {
+  int lo[3], hi[3];
+  double w0, gamma, sigma;
+  int drude;
+  double *P[3], *Pm[3];
+} ora_pole;
+
 typedef struct ora_sim {
   int N[3];
   double dx, dt, courant;
@@ -109,6 +124,9 @@ typedef struct ora_sim {
    * dipole d (integer steps), for the x and y polarisations */
   int cav_on;
   double cav_w, cav_V, cav_eps, cav_q[2], cav_p[2], cav_d[2];
+  /* dispersive blocks; eps holds eps_infinity in their cells */
+  ora_pole pole[8];
+  int npole;
 } ora_sim;
 
 static void series_push(ora_series* s, double v) {
@@ -247,6 +265,8 @@ void ora_destroy(ora_sim* s) {
     }
   }
   free(s->eps);
+  for (int k = 0; k < s->npole; ++k)
+    for (int c = 0; c < 3; ++c) { free(s->pole[k].P[c]); free(s->pole[k].Pm[c]); }
   for (int m = 0; m < s->nem; ++m)
     for (int c = 0; c < 3; ++c) free(s->em[m].w[c]);
   free(s->em);
@@ -617,7 +637,40 @@ static void update_H(ora_sim* s) {
 
 /* E^{n+1} = E^n + (dt/eps_r) (curl H^{n+1/2} - J^{n+1/2})  (eq. Maxwell,
  * first line, D = eps_r E), then the tangential E on metallic walls is 0. */
+/* Polarisation of every pole from P^n, P^{n-1} and E^n by central differences
+ * of its oscillator equation (the standard auxiliary-equation form):
+ *   (P^{n+1} - 2 P^n + P^{n-1}) / dt^2 + gamma (P^{n+1} - P^{n-1}) / (2 dt)
+ *     + kappa w0^2 P^n = sigma w0^2 E^n.
+ * Writes P^{n+1} into out[k][c]. */
+static void poles_advance(const ora_sim* s, double* out[8][3]) {
+  const double dt = s->dt;
+  for (int k = 0; k < s->npole; ++k) {
+    const ora_pole* p = &s->pole[k];
+    const double g = 0.5 * p->gamma * dt, w2 = p->w0 * p->w0;
+    const double kappa = p->drude ? 0.0 : 1.0;
+    const int bx = p->hi[0] - p->lo[0], by = p->hi[1] - p->lo[1], bz = p->hi[2] - p->lo[2];
+    for (int c = 0; c < 3; ++c)
+      for (int kk = 0; kk < bz; ++kk)
+        for (int j = 0; j < by; ++j)
+          for (int i = 0; i < bx; ++i) {
+            size_t b = (size_t)i + (size_t)bx * (j + (size_t)by * kk);
+            double e = s->E[c][IDX(s, p->lo[0] + i, p->lo[1] + j, p->lo[2] + kk)];
+            out[k][c][b] = ((2.0 - kappa * w2 * dt * dt) * p->P[c][b] -
+                            (1.0 - g) * p->Pm[c][b] + p->sigma * w2 * dt * dt * e) / (1.0 + g);
+          }
+  }
+}
+
 static void update_E(ora_sim* s) {
+  /* D = eps_inf E + sum_k P_k advances by dt (curl H - J): the poles move first,
+   * from E^n, and E^{n+1} = E^n + (dt (curl H - J) - sum_k (P_k^{n+1} - P_k^n)) / eps_inf */
+  double* Pn[8][3] = {{0}};
+  for (int k = 0; k < s->npole; ++k) {
+    const ora_pole* p = &s->pole[k];
+    size_t nb = (size_t)(p->hi[0] - p->lo[0]) * (p->hi[1] - p->lo[1]) * (p->hi[2] - p->lo[2]);
+    for (int c = 0; c < 3; ++c) Pn[k][c] = (double*)malloc(nb * sizeof(double));
+  }
+  poles_advance(s, Pn);
   const int nx = s->N[0], ny = s->N[1], nz = s->N[2];
   const double dt = s->dt, idx = 1.0 / s->dx;
   double *Ex = s->E[0], *Ey = s->E[1], *Ez = s->E[2];
@@ -646,6 +699,22 @@ static void update_E(ora_sim* s) {
         Ey[id] += ce * (cy - Jy[id]);
         Ez[id] += ce * (cz - Jz[id]);
       }
+  for (int k = 0; k < s->npole; ++k) {
+    ora_pole* p = &s->pole[k];
+    const int bx = p->hi[0] - p->lo[0], by = p->hi[1] - p->lo[1], bz = p->hi[2] - p->lo[2];
+    for (int c = 0; c < 3; ++c) {
+      for (int kk = 0; kk < bz; ++kk)
+        for (int j = 0; j < by; ++j)
+          for (int i = 0; i < bx; ++i) {
+            size_t b = (size_t)i + (size_t)bx * (j + (size_t)by * kk);
+            size_t id = IDX(s, p->lo[0] + i, p->lo[1] + j, p->lo[2] + kk);
+            s->E[c][id] -= (Pn[k][c][b] - p->P[c][b]) / s->eps[id];
+          }
+      free(p->Pm[c]);
+      p->Pm[c] = p->P[c];
+      p->P[c] = Pn[k][c];
+    }
+  }
   /* metallic walls (also behind each PML): E tangential to the wall plane
    * at index 0 of that axis is held at zero */
   for (int ax = 0; ax < 3; ++ax) {
@@ -882,7 +951,7 @@ static void dipole_expect(const ora_emitter* e, double out[3]) {
  * The grid is left alone.  Call after the emitters are added and before the
  * first step. */
 int ora_set_cavity(ora_sim* s, double w, double V, const double q0[2], const double p0[2]) {
-  if (!(w > 0.0) || !(V > 0.0) || s->step != 0) return -1;
+  if (!(w > 0.0) || !(V > 0.0) || s->step != 0 || s->npole > 0) return -1;
   s->cav_on = 1;
   s->cav_w = w;
   s->cav_V = V;
@@ -908,6 +977,39 @@ void ora_get_cavity(const ora_sim* s, double out[6]) {
     out[2 + l] = s->cav_p[l];
     out[4 + l] = s->cav_d[l];
   }
+}
+
+/* A Lorentz (drude = 0) or Drude (drude = 1) pole over the half-open box
+ * (x0, y0, z0, x1, y1, z1), P = 0 initially.  The box keeps clear of the CPML
+ * layers and of the index-0 wall plane of every non-periodic axis.  eps of the
+ * box cells is taken as eps_infinity.  Before the first step; at most 8. */
+int ora_add_susceptibility(ora_sim* s, const int box[6], double w0, double gamma, double sigma,
+                           int drude) {
+  if (s->step != 0 || s->npole >= 8 || s->cav_on) return -1;
+  if (!(w0 > 0.0) || !(gamma >= 0.0) || !isfinite(sigma) || !isfinite(gamma)) return -1;
+  ora_pole* p = &s->pole[s->npole];
+  for (int a = 0; a < 3; ++a) {
+    int lo = box[a], hi = box[3 + a];
+    int lmin = 0, hmax = s->N[a];
+    if (s->bc[2 * a] != ORA_PERIODIC) {
+      lmin = s->npml[2 * a] > 1 ? s->npml[2 * a] : 1;
+      hmax = s->N[a] - s->npml[2 * a + 1];
+    }
+    if (lo < lmin || hi > hmax || lo >= hi) return -1;
+    p->lo[a] = lo;
+    p->hi[a] = hi;
+  }
+  p->w0 = w0;
+  p->gamma = gamma;
+  p->sigma = sigma;
+  p->drude = drude ? 1 : 0;
+  size_t nb = (size_t)(p->hi[0] - p->lo[0]) * (p->hi[1] - p->lo[1]) * (p->hi[2] - p->lo[2]);
+  for (int c = 0; c < 3; ++c) {
+    p->P[c] = (double*)calloc(nb, sizeof(double));
+    p->Pm[c] = (double*)calloc(nb, sizeof(double));
+  }
+  s->npole++;
+  return 0;
 }
 
 static void cavity_step(ora_sim* s) {
@@ -1264,7 +1366,7 @@ static void tls_map_dg(double w0, double dt, double g, const double in[3], doubl
 
 int ora_adjoint(ora_sim* s, int kind, const double* weights, int64_t T, const int* box,
                 double* grad_eps, double* grad_dip, double* value) {
-  if (T <= 0) return ORA_EINVAL;
+  if (T <= 0 || s->npole > 0) return ORA_EINVAL;
   if (kind == 0 && !s->flux_on) return ORA_EINVAL;
   if (kind == 1 && !weights) return ORA_EINVAL;
   for (int m = 0; m < s->nem; ++m)

@@ -84,6 +84,9 @@ def lib():
     L.ora_set_cavity.argtypes = [C.c_void_p, C.c_double, C.c_double, _dp, _dp]
     L.ora_set_cavity.restype = C.c_int
     L.ora_get_cavity.argtypes = [C.c_void_p, _dp]
+    L.ora_add_susceptibility.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.c_double, C.c_double,
+                                         C.c_double, C.c_int]
+    L.ora_add_susceptibility.restype = C.c_int
     L.ora_gather.argtypes = [C.c_void_p, _dp]
     L.ora_scatter.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
     L.ora_dipole_rate_trace.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
@@ -359,6 +362,15 @@ class Oracle:
                                   _f64(q0, (2,)), _f64(p0, (2,)))
         if st != 0:
             raise ValueError("oracle: bad cavity")
+
+    def add_susceptibility(self, box, omega0, gamma, sigma, drude=False):
+        """Lorentz (or Drude) pole chi = sigma w0^2 / (kappa w0^2 - w^2 - i w gamma) over
+        the half-open cell box (x0, y0, z0, x1, y1, z1); eps of its cells is eps_inf."""
+        b = (C.c_int * 6)(*[int(v) for v in box])
+        st = lib().ora_add_susceptibility(self._h, b, float(omega0), float(gamma), float(sigma),
+                                          1 if drude else 0)
+        if st != 0:
+            raise ValueError("oracle: bad susceptibility")
 
     def cavity(self):
         """(q_x, q_y, p_x, p_y, d_x, d_y): q and d at the current step, p half a step

@@ -739,3 +739,79 @@ def test_cavity_collective_coupling_sums_the_dipoles():
     assert np.max(np.abs(four[:, 0] - one[:, 0])) < 1e-3 * scale
     assert np.max(np.abs(four[:, 4] - one[:, 4])) < 1e-3 * np.max(np.abs(one[:, 4]))
     assert np.max(np.abs(four_full[:, 0] - one[:, 0])) > 0.1 * scale
+
+
+# --------------------------------------------------------------- dispersive poles
+def _uniform_pole_run(drude, w0, gamma, sigma, einf, steps):
+    o = Oracle((2, 2, 2), bc=("periodic",) * 6)
+    o.set_eps(np.full((2, 2, 2), einf))
+    o.add_susceptibility((0, 0, 0, 2, 2, 2), w0, gamma, sigma, drude=drude)
+    E0 = np.array([0.7, -0.3, 1.1])
+    for c in range(3):
+        o.set_field(c, np.full((2, 2, 2), E0[c]))
+    tr = np.empty((steps + 1, 3))
+    tr[0] = E0
+    for n in range(steps):
+        o.step(1)
+        tr[n + 1] = [o.get_field(c)[1, 0, 1] for c in range(3)]
+    return o.dt, E0, tr
+
+
+@pytest.mark.parametrize("drude,gamma", [(False, 0.0), (False, 0.05), (True, 0.0), (True, 0.08)])
+def test_pole_uniform_field_closed_form(drude, gamma):
+    """Uniform field, no curl: D = eps_inf E + P is conserved, so E relaxes to the static
+    value D / eps(0) (eps(0) = eps_inf + sigma for a Lorentz pole, infinite for Drude:
+    E -> 0) through the two roots r of (1 + g) r^2 - (2 - (kappa + sigma / eps_inf) w0^2
+    dt^2) r + (1 - g) = 0, g = gamma dt / 2 -- the plasma / longitudinal oscillation."""
+    w0, sigma, einf, steps = 0.4, 1.5, 2.0, 400
+    dt, E0, tr = _uniform_pole_run(drude, w0, gamma, sigma, einf, steps)
+    kappa = 0.0 if drude else 1.0
+    g = gamma * dt / 2
+    r = np.roots([1 + g, -(2 - (kappa + sigma / einf) * w0 ** 2 * dt ** 2), 1 - g])
+    Einf = np.zeros(3) if drude else E0 * einf / (einf + sigma)
+    n = np.arange(steps + 1)
+    B = np.stack([r[0] ** n, r[1] ** n], 1)
+    for c in range(3):
+        y = tr[:, c] - Einf[c]
+        coef, *_ = np.linalg.lstsq(B, y.astype(complex), rcond=None)
+        assert np.max(np.abs(B @ coef - y)) < 1e-12 * np.max(np.abs(y))
+    if gamma > 0:
+        # loss: the transient dies at the rate |r|^2 = (1 - g) / (1 + g) per step
+        assert np.allclose(np.abs(r) ** 2, (1 - g) / (1 + g), rtol=1e-12)
+        assert np.max(np.abs(tr[-1] - Einf)) < 0.05 * np.max(np.abs(E0))
+
+
+def test_pole_plane_wave_discrete_dispersion():
+    """A lossless Lorentz medium filling a periodic box: a standing wave of wavenumber k
+    oscillates at exactly the two polariton branches of the discrete dispersion relation
+    u (eps_inf + sigma w0^2 / (w0^2 - u)) = (4 / dx^2) sum sin^2(k_a dx / 2),
+    u = (4 / dt^2) sin^2(w dt / 2); a 1% error in w0 misses them."""
+    n, w0, sigma, einf = 16, 0.5, 2.0, 1.5
+    o = Oracle((n, 2, 2), bc=("periodic",) * 6)
+    o.set_eps(np.full((2, 2, n), einf))
+    o.add_susceptibility((0, 0, 0, n, 2, 2), w0, 0.0, sigma)
+    kx = 2 * np.pi * 3 / n
+    x = np.arange(n)
+    o.set_field(2, np.broadcast_to(np.cos(kx * x), (2, 2, n)).copy())  # Ez at integer x
+    steps = 1500
+    y = np.empty(steps + 1)
+    y[0] = 1.0
+    for q in range(steps):
+        o.step(1)
+        y[q + 1] = o.get_field(2)[0, 0, 0]
+    dt = o.dt
+    K = 4 * np.sin(kx / 2) ** 2
+
+    def branches(w):
+        u = np.roots([-einf, einf * w * w + sigma * w * w + K, -K * w * w]).real
+        return 2 / dt * np.arcsin(dt * np.sqrt(u) / 2)
+
+    t = np.arange(steps + 1) * dt
+
+    def resid(freqs):
+        B = np.concatenate([np.stack([np.cos(f * t), np.sin(f * t)], 1) for f in freqs], 1)
+        c, *_ = np.linalg.lstsq(B, y, rcond=None)
+        return np.linalg.norm(B @ c - y) / np.linalg.norm(y)
+
+    assert resid(branches(w0)) < 1e-10
+    assert resid(branches(1.01 * w0)) > 1e-3
