@@ -212,6 +212,23 @@ mlk_status mlk_step_count(mlk_sim* s, int64_t* n);
  * (EUNSUPPORTED) and mlk_step_prescribed (ESTATE) are refused. */
 mlk_status mlk_set_cavity(mlk_sim* s, double omega, double volume, const double q0[2],
                           const double p0[2]);
+/* Dispersive block (eq. Dromega: a dielectric function made of Lorentz and Drude
+ * oscillators): one pole chi(w) = sigma w0^2 / (kappa w0^2 - w^2 - i w gamma),
+ * kappa = 1 (drude = 0, Lorentz) or 0 (drude = 1, Drude), over the half-open
+ * cell box {x0, y0, z0, x1, y1, z1}.  eps_r of the box cells (mlk_set_eps) is
+ * eps_infinity.  Its polarisation P (zero at the start, one value per E
+ * component per box cell, held by the library in the field precision) obeys
+ * P'' + gamma P' + kappa w0^2 P = sigma w0^2 E, advanced by central
+ * differences from P^n, P^{n-1} and E^n, and the E update becomes
+ * E^{n+1} = E^n + (dt (curl H - J) - sum_poles (P^{n+1} - P^n)) / eps_inf.
+ * Poles may overlap (their P add).  On a non-periodic axis the box stays clear
+ * of the CPML layers and of the index-0 wall plane.  Before the first step; at
+ * most 8 poles; checkpoints carry P.  EINVAL: box outside those limits or
+ * empty, omega0 <= 0, gamma < 0, non-finite values, a ninth pole.  ESTATE:
+ * after stepping, in a batch.  EUNSUPPORTED: with a cavity.  Batches and the
+ * adjoint refuse a sim with poles (EUNSUPPORTED). */
+mlk_status mlk_add_susceptibility(mlk_sim* s, const int32_t box[6], double omega0, double gamma,
+                                  double sigma, int32_t drude);
 /* Mode state (q_x, q_y, p_x, p_y, d_x, d_y) into out[6] (host): q and d at the
  * current step, p half a step before.  Synchronises.  ESTATE: no cavity. */
 mlk_status mlk_get_cavity(mlk_sim* s, double out[6]);

@@ -144,6 +144,14 @@ hipError_t pack_tape_f64(const FieldPtrs<double>& f, const Geom& g, const Box& b
                          double* box_out, const FluxPlane* fp, double* flux_out, hipStream_t st);
 hipError_t pack_tape_f32(const FieldPtrs<float>& f, const Geom& g, const Box& box, float* box_out,
                          const FluxPlane* fp, double* flux_out, hipStream_t st);
+// Dispersive poles: before the sweep, Q <- P^{n+1} - P^n from P, Q and E^n; after
+// the sweep, the scatter and the sources, E -= (1/eps_inf) Q and P += Q.
+hipError_t pole_pre_f64(const PoleDev& p, const FieldPtrs<double>& f, const Geom& g, hipStream_t st);
+hipError_t pole_pre_f32(const PoleDev& p, const FieldPtrs<float>& f, const Geom& g, hipStream_t st);
+hipError_t pole_post_f64(const PoleDev& p, const FieldPtrs<double>& f, const Geom& g,
+                         const double* epsinv, hipStream_t st);
+hipError_t pole_post_f32(const PoleDev& p, const FieldPtrs<float>& f, const Geom& g,
+                         const float* epsinv, hipStream_t st);
 // Single-mode cavity: E~ of every emitter from the mode state, then the
 // sum of mu_dot over the emitters, the (p, q, d) update and the step counter.
 int cavity_blocks(int M);

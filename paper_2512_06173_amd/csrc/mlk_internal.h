@@ -214,6 +214,14 @@ struct FluxPlane {
   double* total;    // running dt * sum F
 };
 
+// One Lorentz or Drude pole over a cell box: P^{n+1} (1 + g) = a P^n - b P^{n-1} + c E^n.
+struct PoleDev {
+  int lo[3], n[3];    // box origin and extent (cells)
+  double a, b, c, g1; // 2 - kappa w0^2 dt^2, 1 - g, sigma w0^2 dt^2, 1 + g (g = gamma dt / 2)
+  void* P;            // P^n, 3 x box cells of the field type, component-major, x fastest
+  void* Q;            // P^n - P^{n-1}; after the pre-sweep pass P^{n+1} - P^n
+};
+
 // Single-mode cavity that replaces the grid: mode state and coupling.
 struct CavityDev {
   double* st;       // q_x, q_y, p_x, p_y, d_x, d_y (FP64)

@@ -175,6 +175,10 @@ struct mlk_sim {
   // single-mode cavity in place of the grid (off unless mlk_set_cavity was called)
   bool cav_on = false;
   CavityDev cav{};
+
+  // dispersive poles (Lorentz / Drude over cell boxes), in add order
+  int npole = 0;
+  PoleDev pole[8] = {};
 };
 
 namespace {
@@ -775,6 +779,10 @@ mlk_status enqueue_steps(mlk_sim* s, int64_t nsteps) {
                        s->d_step, s->stream));
     }
     mark_end(s, MLK_PHASE_EMITTERS, t0);
+    for (int k = 0; k < s->npole; ++k) {
+      if constexpr (f32) HIPCHK(pole_pre_f32(s->pole[k], f, s->g, s->stream));
+      else HIPCHK(pole_pre_f64(s->pole[k], f, s->g, s->stream));
+    }
     STCHK(sweep<T>(s));
     f = field_ptrs<T>(s);
     t0 = mark_begin(s, MLK_PHASE_SCATTER);
@@ -791,6 +799,10 @@ mlk_status enqueue_steps(mlk_sim* s, int64_t nsteps) {
         HIPCHK(scatter_atomic_f64(f, s->g, win, s->nem, s->d_mudot, s->stream));
     }
     mark_end(s, MLK_PHASE_SCATTER, t0);
+    for (int k = 0; k < s->npole; ++k) {
+      if constexpr (f32) HIPCHK(pole_post_f32(s->pole[k], f, s->g, (const float*)s->epsinv, s->stream));
+      else HIPCHK(pole_post_f64(s->pole[k], f, s->g, (const double*)s->epsinv, s->stream));
+    }
     t0 = mark_begin(s, MLK_PHASE_DETECTORS);
     if constexpr (f32) HIPCHK(finish_f32(f, s->g, s->fp, ser, s->d_step, s->stream));
     else HIPCHK(finish_f64(f, s->g, s->fp, ser, s->d_step, s->stream));
@@ -870,6 +882,10 @@ void release(mlk_sim* s) {
   dfree(s->d_step);
   dfree(s->cav.st);
   dfree(s->cav.partial);
+  for (int k = 0; k < s->npole; ++k) {
+    dfree(s->pole[k].P);
+    dfree(s->pole[k].Q);
+  }
   if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
   s->stream = nullptr;
 }
@@ -895,6 +911,11 @@ std::vector<Piece> state_pieces(mlk_sim* s) {
   v.push_back({s->d_step, sizeof(int64_t)});
   if (s->fp.on) v.push_back({s->fp.total, sizeof(double)});
   if (s->cav_on) v.push_back({s->cav.st, 6 * sizeof(double)});
+  for (int k = 0; k < s->npole; ++k) {
+    const size_t nb = 3 * (size_t)s->pole[k].n[0] * s->pole[k].n[1] * s->pole[k].n[2];
+    v.push_back({s->pole[k].P, nb * s->esz});
+    v.push_back({s->pole[k].Q, nb * s->esz});
+  }
   return v;
 }
 
@@ -1379,8 +1400,9 @@ mlk_status mlk_set_cavity(mlk_sim* s, double omega, double volume, const double 
     if (!std::isfinite(q0[l]) || !std::isfinite(p0[l])) return fail(MLK_EINVAL, "bad mode state");
   if (s->host_step > 0) return fail(MLK_ESTATE, "the cavity must be set before stepping");
   if (s->in_batch) return fail(MLK_ESTATE, "the sim belongs to a batch");
-  if (s->src.count > 0 || s->nprobe > 0 || s->fp.on)
-    return fail(MLK_EUNSUPPORTED, "the cavity replaces the grid: no sources, probes or flux plane");
+  if (s->src.count > 0 || s->nprobe > 0 || s->fp.on || s->npole > 0)
+    return fail(MLK_EUNSUPPORTED,
+                "the cavity replaces the grid: no sources, probes, flux plane or poles");
   HIPCHK(hipSetDevice(s->desc.device));
   STCHK(sync_sim(s));
   // d^0 = sum over emitters (id order) of d Tr(rho M) of the current states
@@ -1418,6 +1440,48 @@ mlk_status mlk_set_cavity(mlk_sim* s, double omega, double volume, const double 
   s->cav.V = volume;
   s->cav.eps = omega / std::sqrt(volume);
   s->cav_on = true;
+  return MLK_OK;
+}
+
+mlk_status mlk_add_susceptibility(mlk_sim* s, const int32_t box[6], double omega0, double gamma,
+                                  double sigma, int32_t drude) {
+  if (!s || !box) return fail(MLK_EINVAL, "null argument");
+  if (s->host_step > 0) return fail(MLK_ESTATE, "poles must be added before stepping");
+  if (s->in_batch) return fail(MLK_ESTATE, "the sim belongs to a batch");
+  if (s->cav_on) return fail(MLK_EUNSUPPORTED, "the cavity replaces the grid: no poles");
+  if (s->npole >= 8) return fail(MLK_EINVAL, "at most 8 poles");
+  if (!(omega0 > 0.0) || !(gamma >= 0.0) || !std::isfinite(omega0) || !std::isfinite(gamma) ||
+      !std::isfinite(sigma))
+    return fail(MLK_EINVAL, "pole needs omega0 > 0, gamma >= 0, finite sigma");
+  PoleDev p{};
+  for (int a = 0; a < 3; ++a) {
+    const int lo = box[a], hi = box[3 + a];
+    int lmin = 0, hmax = s->g.n[a];
+    if (!s->g.periodic[a]) {
+      lmin = std::max(s->g.nlo[a], 1);  // clear of the CPML and of the index-0 wall plane
+      hmax = s->g.n[a] - s->g.nhi[a];
+    }
+    if (lo < lmin || hi > hmax || lo >= hi)
+      return fail(MLK_EINVAL, "pole box axis %d: [%d, %d) outside [%d, %d)", a, lo, hi, lmin, hmax);
+    p.lo[a] = lo;
+    p.n[a] = hi - lo;
+  }
+  const double dt = s->g.dt, g = 0.5 * gamma * dt, w2 = omega0 * omega0;
+  p.a = 2.0 - (drude ? 0.0 : w2 * dt * dt);
+  p.b = 1.0 - g;
+  p.c = sigma * w2 * dt * dt;
+  p.g1 = 1.0 + g;
+  const size_t bytes = 3 * (size_t)p.n[0] * p.n[1] * p.n[2] * s->esz;
+  HIPCHK(hipSetDevice(s->desc.device));
+  STCHK(sync_sim(s));
+  HIPCHK(dalloc(&p.P, bytes));
+  if (dalloc(&p.Q, bytes) != hipSuccess) {
+    dfree(p.P);
+    return fail(MLK_ENOMEM, "pole state");
+  }
+  HIPCHK(hipMemset(p.P, 0, bytes));
+  HIPCHK(hipMemset(p.Q, 0, bytes));
+  s->pole[s->npole++] = p;
   return MLK_OK;
 }
 
@@ -1852,6 +1916,7 @@ mlk_status mlk_adjoint(mlk_sim* s, const mlk_objective* obj, int64_t nsteps, int
   if (!s || !obj || !box || !value) return fail(MLK_EINVAL, "null argument");
   if (s->in_batch) return fail(MLK_ESTATE, "the sim belongs to a batch");
   if (s->cav_on) return fail(MLK_EUNSUPPORTED, "the adjoint covers the grid, not the cavity");
+  if (s->npole > 0) return fail(MLK_EUNSUPPORTED, "the adjoint covers non-dispersive media only");
   if (nsteps <= 0 || ckpt_every <= 0) return fail(MLK_EINVAL, "steps and checkpoint interval must be positive");
   if (!s->ml_gid.empty()) return fail(MLK_EUNSUPPORTED, "the adjoint covers two-level emitters only");
   if (obj->kind == MLK_OBJ_FLUX) {
@@ -2240,9 +2305,9 @@ mlk_status mlk_batch_create(mlk_sim* const* sims, int32_t n, mlk_batch** out) {
         delete b;
         return fail(MLK_EINVAL, "member %d appears twice", q);
       }
-    if (s->cav_on) {
+    if (s->cav_on || s->npole > 0) {
       delete b;
-      return fail(MLK_EUNSUPPORTED, "member %d steps a cavity, not a grid", q);
+      return fail(MLK_EUNSUPPORTED, "member %d steps a cavity or dispersive media", q);
     }
     const mlk_sim* s0 = sims[0];
     if (s->fp32 != s0->fp32 || s->desc.sweep != s0->desc.sweep || s->host_step != s0->host_step ||

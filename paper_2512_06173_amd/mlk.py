@@ -120,6 +120,7 @@ def lib():
         "mlk_step_prescribed": (st, [sim, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p]),
         "mlk_set_cavity": (st, [sim, C.c_double, C.c_double, _dp, _dp]),
         "mlk_get_cavity": (st, [sim, _dp]),
+        "mlk_add_susceptibility": (st, [sim, _ip, C.c_double, C.c_double, C.c_double, C.c_int32]),
         "mlk_adjoint": (st, [sim, C.POINTER(Objective), C.c_int64, C.c_int32, _ip, C.c_void_p,
                              C.c_void_p, C.POINTER(C.c_double)]),
         "mlk_set_eps_box": (st, [sim, _ip, _dp, C.c_int32]),
@@ -145,7 +146,7 @@ def exported_symbols():
             "mlk_set_eps", "mlk_set_field", "mlk_add_tls", "mlk_add_multilevel",
             "mlk_add_plane_source", "mlk_add_point_source", "mlk_add_probe", "mlk_add_flux_plane",
             "mlk_record_populations", "mlk_step", "mlk_step_prescribed",
-            "mlk_set_cavity", "mlk_get_cavity", "mlk_sync", "mlk_step_count", "mlk_get_field",
+            "mlk_set_cavity", "mlk_get_cavity", "mlk_add_susceptibility", "mlk_sync", "mlk_step_count", "mlk_get_field",
             "mlk_get_rho", "mlk_get_tls_state", "mlk_get_emitter_io", "mlk_get_series",
             "mlk_get_flux_total", "mlk_checkpoint_size", "mlk_checkpoint_save",
             "mlk_checkpoint_load", "mlk_set_timing", "mlk_get_phase_time",
@@ -322,6 +323,13 @@ class Simulation:
                                          MEM_HOST, out.ctypes.data_as(C.c_void_p)
                                          if record and self.n_tls else None))
         return out
+
+    def add_susceptibility(self, box, omega0, gamma, sigma, drude=False):
+        """Lorentz (or Drude) pole chi = sigma w0^2 / (kappa w0^2 - w^2 - i w gamma) over the
+        half-open cell box (x0, y0, z0, x1, y1, z1); eps of its cells is eps_inf."""
+        b = np.ascontiguousarray(np.asarray(box, dtype=np.int32).reshape(6))
+        _check(lib().mlk_add_susceptibility(self._h, b.ctypes.data_as(_ip), float(omega0),
+                                            float(gamma), float(sigma), 1 if drude else 0))
 
     def set_cavity(self, omega, volume, q0=(0.0, 0.0), p0=(0.0, 0.0)):
         """Single-mode cavity in place of the grid (x and y polarisations); call after
