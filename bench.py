@@ -55,6 +55,8 @@ def parse():
     p.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
     p.add_argument("--adjoint-steps", type=int, default=4000)
     p.add_argument("--copy-calib", action="store_true")
+    p.add_argument("--dispersive-only", action="store_true",
+                   help="only the leg with a Lorentz pole block (profiling runs; needs --tile)")
     p.add_argument("--tile", type=lambda v: tuple(int(x) for x in v.split(",")), default=None,
                    help="fused tile TY,KZ instead of autotuning (profiling runs)")
     return p.parse_args()
@@ -111,11 +113,13 @@ def traffic_from_profile(launch_cells):
     return float(t.group(1))
 
 
-def run_gpu(w, precision, sweep, steps, warmup, timing, tile=None):
+def run_gpu(w, precision, sweep, steps, warmup, timing, tile=None, poles=()):
     import torch
     from paper_2512_06173_amd import mlk
     sim = mlk.from_workload(w, precision=precision, sweep=sweep, scatter="owner",
                             stream=mlk.current_stream_handle())
+    for box, w0, gamma, sigma, drude in poles:
+        sim.add_susceptibility(box, w0, gamma, sigma, drude=drude)
     if tile:
         sim.set_tuning(*tile)
     else:
@@ -208,6 +212,30 @@ def batch_leg(steps, spr=20, tune=False):
             "own_streams": rate(tc), "speedup_vs_own_streams": round(tc / tb, 2)}
 
 
+# Algorithmic bytes per pole cell and step (FP32): the pre-sweep pass reads E, P, Q and
+# writes Q (4 words per component), the post pass reads E, Q, P and writes E, P (5 per
+# component), and 1/eps_inf is read once per cell.
+POLE_BYTES_PER_CELL = 3 * 9 * 4 + 4
+
+
+def dispersive_leg(w, steps, tuning, ms_plain):
+    """The same workload with a Lorentz pole over the central eighth of the domain."""
+    n = w.shape[0]
+    lo, hi = n // 4, 3 * n // 4
+    poles = [((lo, lo, lo, hi, hi, hi), 0.3, 0.01, 1.5, False)]
+    d, ph, _, _ = run_gpu(w, "fp32", "fused", steps, 5, ["poles"], tuning, poles)
+    ms, nl = ph["poles"]
+    cells = (hi - lo) ** 3
+    t_pair = ms / (nl / 2) * 1e-3  # pre + post per step
+    achieved = cells * POLE_BYTES_PER_CELL / t_pair / 1e9
+    return {"pole_cells": cells, "ms_per_step": round(d * 1e3 / steps, 4),
+            "extra_ms_per_step": round(d * 1e3 / steps - ms_plain, 4),
+            "pole_passes_us_per_step": round(t_pair * 1e6, 2),
+            "bytes_per_pole_cell": POLE_BYTES_PER_CELL,
+            "pole_passes_GBs": round(achieved, 1),
+            "frac_of_hbm_peak": round(achieved / HBM_PEAK_GBS, 4), "steps": steps}
+
+
 def adjoint_leg(w, steps, ms_forward, ckpt=200):
     """Gradients of the time-integrated flux through the z = 200 plane over `steps`
     steps with respect to eps_r in the design box [96,160)^3 and every emitter's dipole,
@@ -269,6 +297,9 @@ def main():
     mlk.lib()
 
     w = W.radiating_cube(n=args.n, n_emit=args.emitters)
+    if args.dispersive_only:
+        print(json.dumps({"dispersive": dispersive_leg(w, args.steps, args.tile, 0.0)}), flush=True)
+        return
     nx, ny, nz = w.shape
     cells = nx * ny * nz
     nem = len(w.tls.pos)
@@ -343,6 +374,8 @@ def main():
         out["adjoint_forward_ratio"] = adj["adjoint_forward_ratio"]
     if not args.no_batch:
         out["batch"] = batch_leg(max(20, args.steps // 5))
+    if not args.no_compare:
+        out["dispersive"] = dispersive_leg(w, max(20, args.steps // 5), tuning, ms_step)
     out["cpu_baseline"] = None if args.no_cpu else cpu_baseline(w, args.cpu_steps)
     print(json.dumps(out), flush=True)
 

@@ -277,7 +277,8 @@ enum {
   MLK_PHASE_SOURCES = 3,
   MLK_PHASE_SCATTER = 4,
   MLK_PHASE_DETECTORS = 5,
-  MLK_PHASE_COUNT = 6,
+  MLK_PHASE_POLES = 6, /* the two passes of the dispersive poles */
+  MLK_PHASE_COUNT = 7,
   MLK_TIMING_ALL = (1 << 6) - 1
 };
 mlk_status mlk_set_timing(mlk_sim* s, int32_t on);

@@ -9,7 +9,8 @@
 // Q = P^n - P^{n-1} in place (two arrays, no host-side rotation):
 //   pre  (E = E^n):   Q <- P^{n+1} - P^n,  P^{n+1} = (a P^n - b (P^n - Q) + c E^n) / (1 + g)
 //   post (E = E^{n+1} without the poles):  E -= Q / eps_inf,  P += Q.
-// One thread per (component, box cell), x fastest: coalesced along rows.
+// One thread per box cell for all three components (one 1/eps_inf read and one
+// index computation per cell), x fastest: coalesced along rows.
 #include "launch.h"
 
 namespace mlk {
@@ -30,31 +31,38 @@ __device__ __forceinline__ size_t pole_cell(const PoleDev& p, const Geom& g, siz
 template <typename T>
 __global__ __launch_bounds__(kPoleThreads) void k_pole_pre(PoleDev p, FieldPtrs<T> f, Geom g,
                                                            size_t nb) {
-  const size_t t = (size_t)blockIdx.x * kPoleThreads + threadIdx.x;
-  if (t >= 3 * nb) return;
-  const int c = (int)(t / nb);
-  const size_t b = t - (size_t)c * nb;
-  T* P = (T*)p.P;
+  const size_t b = (size_t)blockIdx.x * kPoleThreads + threadIdx.x;
+  if (b >= nb) return;
+  const size_t id = pole_cell(p, g, b);
+  const T* P = (const T*)p.P;
   T* Q = (T*)p.Q;
-  const double e = (double)f.E[c][pole_cell(p, g, b)];
-  const double pn = (double)P[t], pm = pn - (double)Q[t];
-  const double pnew = (p.a * pn - p.b * pm + p.c * e) / p.g1;
-  Q[t] = (T)(pnew - pn);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const size_t t = (size_t)c * nb + b;
+    const double e = (double)f.E[c][id];
+    const double pn = (double)P[t], pm = pn - (double)Q[t];
+    const double pnew = (p.a * pn - p.b * pm + p.c * e) / p.g1;
+    Q[t] = (T)(pnew - pn);
+  }
 }
 
 template <typename T>
 __global__ __launch_bounds__(kPoleThreads) void k_pole_post(PoleDev p, FieldPtrs<T> f, Geom g,
                                                             const T* __restrict__ epsinv,
                                                             size_t nb) {
-  const size_t t = (size_t)blockIdx.x * kPoleThreads + threadIdx.x;
-  if (t >= 3 * nb) return;
-  const int c = (int)(t / nb);
-  const size_t b = t - (size_t)c * nb;
-  T* P = (T*)p.P;
-  const T q = ((const T*)p.Q)[t];
+  const size_t b = (size_t)blockIdx.x * kPoleThreads + threadIdx.x;
+  if (b >= nb) return;
   const size_t id = pole_cell(p, g, b);
-  f.E[c][id] -= epsinv[id] * q;
-  P[t] += q;
+  const T ei = epsinv[id];
+  T* P = (T*)p.P;
+  const T* Q = (const T*)p.Q;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const size_t t = (size_t)c * nb + b;
+    const T q = Q[t];
+    f.E[c][id] -= ei * q;
+    P[t] += q;
+  }
 }
 
 size_t pole_cells(const PoleDev& p) { return (size_t)p.n[0] * p.n[1] * p.n[2]; }
@@ -63,7 +71,7 @@ template <typename T>
 hipError_t pole_pre(const PoleDev& p, const FieldPtrs<T>& f, const Geom& g, hipStream_t st) {
   const size_t nb = pole_cells(p);
   if (nb == 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((3 * nb + kPoleThreads - 1) / kPoleThreads);
+  const unsigned blocks = (unsigned)((nb + kPoleThreads - 1) / kPoleThreads);
   hipLaunchKernelGGL(k_pole_pre<T>, dim3(blocks), dim3(kPoleThreads), 0, st, p, f, g, nb);
   return hipGetLastError();
 }
@@ -73,7 +81,7 @@ hipError_t pole_post(const PoleDev& p, const FieldPtrs<T>& f, const Geom& g, con
                      hipStream_t st) {
   const size_t nb = pole_cells(p);
   if (nb == 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((3 * nb + kPoleThreads - 1) / kPoleThreads);
+  const unsigned blocks = (unsigned)((nb + kPoleThreads - 1) / kPoleThreads);
   hipLaunchKernelGGL(k_pole_post<T>, dim3(blocks), dim3(kPoleThreads), 0, st, p, f, g, epsinv,
                      nb);
   return hipGetLastError();

@@ -779,10 +779,12 @@ mlk_status enqueue_steps(mlk_sim* s, int64_t nsteps) {
                        s->d_step, s->stream));
     }
     mark_end(s, MLK_PHASE_EMITTERS, t0);
+    t0 = s->npole ? mark_begin(s, MLK_PHASE_POLES) : -1;
     for (int k = 0; k < s->npole; ++k) {
       if constexpr (f32) HIPCHK(pole_pre_f32(s->pole[k], f, s->g, s->stream));
       else HIPCHK(pole_pre_f64(s->pole[k], f, s->g, s->stream));
     }
+    mark_end(s, MLK_PHASE_POLES, t0);
     STCHK(sweep<T>(s));
     f = field_ptrs<T>(s);
     t0 = mark_begin(s, MLK_PHASE_SCATTER);
@@ -799,10 +801,12 @@ mlk_status enqueue_steps(mlk_sim* s, int64_t nsteps) {
         HIPCHK(scatter_atomic_f64(f, s->g, win, s->nem, s->d_mudot, s->stream));
     }
     mark_end(s, MLK_PHASE_SCATTER, t0);
+    t0 = s->npole ? mark_begin(s, MLK_PHASE_POLES) : -1;
     for (int k = 0; k < s->npole; ++k) {
       if constexpr (f32) HIPCHK(pole_post_f32(s->pole[k], f, s->g, (const float*)s->epsinv, s->stream));
       else HIPCHK(pole_post_f64(s->pole[k], f, s->g, (const double*)s->epsinv, s->stream));
     }
+    mark_end(s, MLK_PHASE_POLES, t0);
     t0 = mark_begin(s, MLK_PHASE_DETECTORS);
     if constexpr (f32) HIPCHK(finish_f32(f, s->g, s->fp, ser, s->d_step, s->stream));
     else HIPCHK(finish_f64(f, s->g, s->fp, ser, s->d_step, s->stream));

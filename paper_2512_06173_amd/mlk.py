@@ -589,7 +589,8 @@ def coupled_objective(sim, eps_box, dipoles, objective, nsteps, box, weights=Non
     return _Fn.apply(eps_box, dipoles)
 
 
-PHASES = {"emitters": 0, "sweep": 1, "shell": 2, "sources": 3, "scatter": 4, "detectors": 5}
+PHASES = {"emitters": 0, "sweep": 1, "shell": 2, "sources": 3, "scatter": 4, "detectors": 5,
+          "poles": 6}
 
 
 def from_workload(w, pop_every=None, **kw):
