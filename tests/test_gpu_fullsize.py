@@ -74,6 +74,48 @@ def test_radiating_cube_256(precision):
     compare(sim, ora, w, precision == "fp64")
 
 
+def test_radiating_cube_256_with_lorentz_block():
+    """The benchmark's dispersive leg: the radiating cube with a Lorentz pole over the
+    central 128^3 cells, FP32 fields, autotuned fused sweep."""
+    w = W.radiating_cube(precision="fp32")
+    w.pop_every = 1
+    n = w.shape[0]
+    box = (n // 4,) * 3 + (3 * n // 4,) * 3
+    t0 = time.time()
+    sim = mlk().from_workload(w, stream=mlk().current_stream_handle())
+    sim.autotune()
+    sim.add_susceptibility(box, 0.3, 0.01, 1.5)
+    sim.step(14)
+    sim.sync()
+    t1 = time.time()
+    ora = build_oracle(w)
+    ora.add_susceptibility(box, 0.3, 0.01, 1.5)
+    ora.step(14)
+    say(f"[fullsize] {w.name} + Lorentz block: gpu {t1 - t0:.1f} s, oracle {time.time() - t1:.1f} s")
+    compare(sim, ora, w, False)
+
+
+def test_cavity_with_100k_emitters():
+    """The benchmark's 100,000 two-level emitters in one cavity mode (no grid): mode state,
+    every emitter state and the population series after 60 steps."""
+    w = W.radiating_cube(precision="fp64")
+    w.flux, w.probes, w.pop_every = None, [], 1
+    sim = mlk().from_workload(w)
+    ora = build_oracle(w)
+    for o in (sim, ora):
+        o.set_cavity(0.25, 2.0e4, (0.05, -0.02), (0.0, 0.001))
+    sim.step(60)
+    ora.step(60)
+    c, r = sim.cavity(), ora.cavity()
+    e_mode = max(np.max(np.abs(c[k:k + 2] - r[k:k + 2])) / np.max(np.abs(r[k:k + 2]))
+                 for k in (0, 2, 4))
+    e_tls = np.max(np.abs(sim.tls_state(0, len(w.tls)) - ora.tls_state()))
+    e_pop = np.max(np.abs(sim.populations() - ora.populations()))
+    say(f"[fullsize] cavity, {len(w.tls)} emitters: mode {e_mode:.2e}, tls {e_tls:.2e}, "
+        f"populations {e_pop:.2e}")
+    assert abs(r[4]) > 0 and e_mode <= FP64_TOL and e_tls <= FP64_TOL and e_pop <= FP64_TOL
+
+
 def test_slab_128_with_source():
     w = W.slab()
     w.pop_every = 10
