@@ -18,6 +18,7 @@ on a bounded sample of the same workload.
     python bench.py --copy-calib     # plain copy kernel of known size (counter scaling)
 """
 import argparse
+import copy
 import hashlib
 import json
 import os
@@ -57,6 +58,8 @@ def parse():
     p.add_argument("--copy-calib", action="store_true")
     p.add_argument("--dispersive-only", action="store_true",
                    help="only the leg with a Lorentz pole block (profiling runs; needs --tile)")
+    p.add_argument("--cavity-only", action="store_true",
+                   help="only the leg with the emitters in one cavity mode (profiling runs)")
     p.add_argument("--tile", type=lambda v: tuple(int(x) for x in v.split(",")), default=None,
                    help="fused tile TY,KZ instead of autotuning (profiling runs)")
     return p.parse_args()
@@ -236,6 +239,27 @@ def dispersive_leg(w, steps, tuning, ms_plain):
             "frac_of_hbm_peak": round(achieved / HBM_PEAK_GBS, 4), "steps": steps}
 
 
+def cavity_leg(w, steps):
+    """The workload's emitters in one cavity mode instead of the grid (FP64 states)."""
+    import torch
+    from paper_2512_06173_amd import mlk
+    w = copy.copy(w)
+    w.flux, w.probes, w.pop_every = None, [], 0
+    sim = mlk.from_workload(w, stream=mlk.current_stream_handle())
+    sim.set_cavity(0.25, 2.0e4, (0.05, 0.0), (0.0, 0.0))
+    sim.step(10)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    dt = time.perf_counter() - t0
+    nem = len(w.tls.pos)
+    sim.close()
+    return {"emitters": nem, "steps": steps, "ms_per_step": round(dt * 1e3 / steps, 4),
+            "emitter_steps_per_s": round(nem * steps / dt, 1)}
+
+
 def adjoint_leg(w, steps, ms_forward, ckpt=200):
     """Gradients of the time-integrated flux through the z = 200 plane over `steps`
     steps with respect to eps_r in the design box [96,160)^3 and every emitter's dipole,
@@ -297,6 +321,9 @@ def main():
     mlk.lib()
 
     w = W.radiating_cube(n=args.n, n_emit=args.emitters)
+    if args.cavity_only:
+        print(json.dumps({"cavity": cavity_leg(w, args.steps)}), flush=True)
+        return
     if args.dispersive_only:
         print(json.dumps({"dispersive": dispersive_leg(w, args.steps, args.tile, 0.0)}), flush=True)
         return
@@ -376,6 +403,7 @@ def main():
         out["batch"] = batch_leg(max(20, args.steps // 5))
     if not args.no_compare:
         out["dispersive"] = dispersive_leg(w, max(20, args.steps // 5), tuning, ms_step)
+        out["cavity"] = cavity_leg(w, max(20, args.steps // 5))
     out["cpu_baseline"] = None if args.no_cpu else cpu_baseline(w, args.cpu_steps)
     print(json.dumps(out), flush=True)
 
