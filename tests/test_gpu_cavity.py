@@ -168,3 +168,21 @@ def test_cavity_refusals():
     plain.add_probe(0, (8, 8, 50))
     assert status(plain.set_cavity, 0.2, 3.0) == m.MLK_EUNSUPPORTED
     assert status(plain.cavity) == m.MLK_ESTATE
+
+
+def test_cavity_without_emitters_is_the_leapfrog_oscillator():
+    """No emitters: q^n = cos(n theta) (x) and 0.5 sin(n theta) (y) exactly, with
+    sin(theta/2) = w dt / 2 and the matching p^{-1/2}; d stays zero."""
+    sim = mlk().Simulation((8, 8, 8), bc=("periodic",) * 6)
+    w, dt = 0.3, sim.dt
+    th = 2.0 * np.arcsin(w * dt / 2.0)
+    sim.set_cavity(w, 7.0, (1.0, 0.0), ((np.cos(th) - 1.0) / dt + dt * w * w, 0.5 * np.sin(th) / dt))
+    q = [sim.cavity()]
+    for _ in range(5):
+        sim.step(100)
+        q.append(sim.cavity())
+    q = np.array(q)
+    n = np.arange(6) * 100
+    assert np.max(np.abs(q[:, 0] - np.cos(n * th))) < 1e-12
+    assert np.max(np.abs(q[:, 1] - 0.5 * np.sin(n * th))) < 1e-12
+    assert np.all(q[:, 4:] == 0.0) and sim.step_count == 500

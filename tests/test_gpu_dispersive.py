@@ -150,3 +150,24 @@ def test_dispersive_refusals():
                   weights=np.ones(2)) == m.MLK_EUNSUPPORTED
     sim.step(2)
     assert status(sim.add_susceptibility, (7, 6, 9, 10, 16, 21), 0.4, 0.0, 1.0) == m.MLK_ESTATE
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_single_cell_poles_at_the_box_limits(precision):
+    """Degenerate boxes: one cell next to the CPML on the low side and one touching the
+    CPML on the high side of every axis, a Drude and a Lorentz pole, against the oracle."""
+    w = dispersive_block(precision, seed=7)
+    nx, ny, nz = w.shape
+    poles = [((5, 5, 5, 6, 6, 6), 0.5, 0.05, 2.0, True),
+             ((nx - 6, ny - 6, nz - 6, nx - 5, ny - 5, nz - 5), 0.4, 0.0, 1.0, False),
+             ((5, 10, 12, nx - 5, 11, 13), 0.35, 0.02, 1.5, False)]
+    sim = mlk().from_workload(w)
+    ora = build_oracle(w)
+    for o in (sim, ora):
+        for box, w0, g, s, drude in poles:
+            o.add_susceptibility(box, w0, g, s, drude=drude)
+    sim.step(120)
+    ora.step(120)
+    e = rel_l2(sim.fields(), ora.fields())
+    say(f"[dispersive] single-cell boxes {precision}: fields {e:.2e}")
+    assert e <= (1e-12 if precision == "fp64" else 1e-4)
