@@ -10,11 +10,14 @@
 // half steps, and the total dipole advanced with the same dipole rate that the
 // grid would receive as current, d^{n+1} = d^n + dt sum_m mu_dot^{n+1/2}.
 //
-// Per step: one launch writes E~ for every emitter, the emitter kernels
-// advance the states and leave mu_dot, a grid of blocks sums mu_dot_x,y in
-// FP64 into per-block partials, and one block adds the partials in a fixed
-// order, advances (p, q, d) and moves the step counter on.  The mode state is
-// six doubles in device memory: q_x, q_y, p_x, p_y, d_x, d_y.
+// Per step, general case: one launch writes E~ for every emitter, the emitter
+// kernels advance the states and leave mu_dot, a grid of blocks sums
+// mu_dot_x,y in FP64 into per-block partials, and one block adds the partials
+// in a fixed order, advances (p, q, d) and moves the step counter on.  With
+// two-level emitters only, one launch forms E~, steps the emitters and leaves
+// the per-block partials itself (the step is launch-bound, so two launches
+// instead of four).  The mode state is six doubles in device memory: q_x, q_y,
+// p_x, p_y, d_x, d_y.
 #include "launch.h"
 
 namespace mlk {
@@ -75,8 +78,11 @@ __global__ __launch_bounds__(kCavThreads) void k_cavity_update(double* __restric
                                                                double eps,
                                                                int64_t* __restrict__ step) {
   const int t = threadIdx.x;
-  double sx = t < nb ? partial[2 * t + 0] : 0.0;
-  double sy = t < nb ? partial[2 * t + 1] : 0.0;
+  double sx = 0.0, sy = 0.0;
+  for (int q = t; q < nb; q += kCavThreads) {
+    sx += partial[2 * q + 0];
+    sy += partial[2 * q + 1];
+  }
   block_sum2(sx, sy);
   if (t == 0) {
     const double sum[2] = {sx, sy};
@@ -106,6 +112,13 @@ hipError_t cavity_field(const CavityDev& c, double* Et, int M, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t cavity_advance(const CavityDev& c, int npartial, double dt, int64_t* step,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_cavity_update, dim3(1), dim3(kCavThreads), 0, st, c.st, c.partial,
+                     npartial, dt, c.w, c.eps, step);
+  return hipGetLastError();
+}
+
 hipError_t cavity_update(const CavityDev& c, const double* mudot, int M, double dt, int64_t* step,
                          hipStream_t st) {
   const int nb = cavity_blocks(M);
@@ -114,9 +127,7 @@ hipError_t cavity_update(const CavityDev& c, const double* mudot, int M, double 
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_cavity_update, dim3(1), dim3(kCavThreads), 0, st, c.st, c.partial,
-                     M > 0 ? nb : 0, dt, c.w, c.eps, step);
-  return hipGetLastError();
+  return cavity_advance(c, M > 0 ? nb : 0, dt, step, st);
 }
 
 }  // namespace mlk

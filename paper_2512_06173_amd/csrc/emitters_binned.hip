@@ -286,6 +286,41 @@ __global__ __launch_bounds__(256) void k_tls_step(TlsPtrs tls, double dt, const 
   tls_body(tls, dt, Et, mudot, pop_off, ser, step, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+// Cavity mode with two-level emitters only: each thread forms the mode's common
+// field E~ = -(eps q_l + d_l / V) e_l for its emitter, steps it, and the block
+// sums mu_dot_x and mu_dot_y in a fixed tree order into c.partial[block].
+__global__ __launch_bounds__(kTlsThreads) void k_cavity_tls(TlsPtrs tls, double dt, CavityDev c,
+                                                            double* Et, double* mudot,
+                                                            const int64_t* pop_off, Series ser,
+                                                            const int64_t* step) {
+  __shared__ double rx[kTlsThreads], ry[kTlsThreads];
+  const int t = threadIdx.x, m = blockIdx.x * kTlsThreads + t;
+  double sx = 0.0, sy = 0.0;
+  if (m < tls.count) {
+    const int e = tls.gid[m];
+    Et[3 * e + 0] = -(c.eps * c.st[0] + c.st[4] / c.V);
+    Et[3 * e + 1] = -(c.eps * c.st[1] + c.st[5] / c.V);
+    Et[3 * e + 2] = 0.0;
+    tls_body(tls, dt, Et, mudot, pop_off, ser, step, m);
+    sx = mudot[3 * e + 0];
+    sy = mudot[3 * e + 1];
+  }
+  rx[t] = sx;
+  ry[t] = sy;
+  __syncthreads();
+  for (int w = kTlsThreads / 2; w > 0; w >>= 1) {
+    if (t < w) {
+      rx[t] += rx[t + w];
+      ry[t] += ry[t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    c.partial[2 * blockIdx.x + 0] = rx[0];
+    c.partial[2 * blockIdx.x + 1] = ry[0];
+  }
+}
+
 __global__ __launch_bounds__(256) void k_tls_batch(const TlsJob* jobs, const int* start,
                                                    int njobs) {
   const int j = find_job(start, njobs, blockIdx.x);
@@ -549,6 +584,15 @@ static hipError_t launch_gather_step(const FieldPtrs<T>& f, const Geom& g, const
 }
 
 // Two-level step of every two-level emitter under a given E~ (emitter-id order).
+hipError_t cavity_tls_step(const TlsPtrs& tls, double dt, const CavityDev& c, double* Et,
+                           double* mudot, const int64_t* pop_off, const Series& ser,
+                           const int64_t* step, hipStream_t st) {
+  if (tls.count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cavity_tls, dim3(cavity_tls_blocks(tls.count)), dim3(kTlsThreads), 0, st,
+                     tls, dt, c, Et, mudot, pop_off, ser, step);
+  return hipGetLastError();
+}
+
 hipError_t tls_step(const TlsPtrs& tls, double dt, const double* Et, double* mudot,
                     const int64_t* pop_off, const Series& ser, const int64_t* step,
                     hipStream_t st) {

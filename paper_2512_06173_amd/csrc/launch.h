@@ -158,6 +158,14 @@ int cavity_blocks(int M);
 hipError_t cavity_field(const CavityDev& c, double* Et, int M, hipStream_t st);
 hipError_t cavity_update(const CavityDev& c, const double* mudot, int M, double dt, int64_t* step,
                          hipStream_t st);
+// The (p, q, d) update from npartial per-block partial sums already in c.partial.
+hipError_t cavity_advance(const CavityDev& c, int npartial, double dt, int64_t* step,
+                          hipStream_t st);
+// Two-level emitters only: E~ from the mode, the two-level step, and the partial sums
+// of mu_dot_x,y of each block of kTlsThreads slots into c.partial; returns the count.
+hipError_t cavity_tls_step(const TlsPtrs& tls, double dt, const CavityDev& c, double* Et,
+                           double* mudot, const int64_t* pop_off, const Series& ser,
+                           const int64_t* step, hipStream_t st);
 hipError_t eps_box_f64(const double* eps, const Geom& g, const Box& box, double* epsinv,
                        hipStream_t st);
 hipError_t eps_box_f32(const double* eps, const Geom& g, const Box& box, float* epsinv,

@@ -228,6 +228,9 @@ struct CavityDev {
   double* partial;  // per-block partial sums of mu_dot_x, mu_dot_y
   double w, V, eps; // mode frequency, effective volume, eps = w / sqrt(V)
 };
+// Two-level-only cavity step: one block of kTlsThreads slots per partial sum.
+constexpr int kTlsThreads = 256;
+inline int cavity_tls_blocks(int ntls) { return (ntls + kTlsThreads - 1) / kTlsThreads; }
 
 // Cell (index along axis a; iu, iv along the two others in cyclic order) of a plane.
 __device__ __forceinline__ size_t plane_cell(const Geom& g, int a, int index, int iu, int iv) {

@@ -821,8 +821,17 @@ mlk_status enqueue_cavity_steps(mlk_sim* s, int64_t nsteps) {
   const Series ser = series_of(s);
   const TlsPtrs tls = tls_ptrs(s);
   const MlDev ml = ml_dev(s);
+  const int ntls = (int)s->tls_gid.size();
   for (int64_t q = 0; q < nsteps; ++q) {
     const int t0 = mark_begin(s, MLK_PHASE_EMITTERS);
+    if (ml.count == 0 && ntls > 0) {
+      // two-level emitters only: field, step and partial sums in one launch
+      HIPCHK(cavity_tls_step(tls, s->g.dt, s->cav, s->d_Et, s->d_mudot, s->d_popoff, ser,
+                             s->d_step, s->stream));
+      HIPCHK(cavity_advance(s->cav, cavity_tls_blocks(ntls), s->g.dt, s->d_step, s->stream));
+      mark_end(s, MLK_PHASE_EMITTERS, t0);
+      continue;
+    }
     if (s->nem > 0) {
       HIPCHK(cavity_field(s->cav, s->d_Et, s->nem, s->stream));
       HIPCHK(tls_step(tls, s->g.dt, s->d_Et, s->d_mudot, s->d_popoff, ser, s->d_step, s->stream));
@@ -1438,7 +1447,11 @@ mlk_status mlk_set_cavity(mlk_sim* s, double omega, double volume, const double 
     st[5] += mu[1];
   }
   if (!s->cav.st) HIPCHK(dalloc(&s->cav.st, 6 * sizeof(double)));
-  if (!s->cav.partial) HIPCHK(dalloc(&s->cav.partial, 2 * 256 * sizeof(double)));
+  // partial sums: at most 256 blocks in the general path, one per 256 two-level
+  // emitters in the two-level path
+  const size_t npart = std::max<size_t>(256, (nt + 255) / 256);
+  dfree(s->cav.partial);
+  HIPCHK(dalloc(&s->cav.partial, 2 * npart * sizeof(double)));
   HIPCHK(hipMemcpy(s->cav.st, st, sizeof(st), hipMemcpyHostToDevice));
   s->cav.w = omega;
   s->cav.V = volume;
