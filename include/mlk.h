@@ -196,12 +196,16 @@ mlk_status mlk_step_count(mlk_sim* s, int64_t* n);
  * volume V > 0 with an x and a y polarisation; the coupling is
  * eps = omega / sqrt(V).  Every emitter then sees the same field
  * E~ = -sum_l (eps q_l + d_l / V) e_l (gamma, positions and widths are not
- * used), where d = sum_m <mu^(m)>, and the mode obeys
- * q_l'' = -omega^2 q_l - eps d_l.  Per step: E~ from q^n and d^n, the emitter
- * steps (as the coupled step does them), then
+ * used), where d = sum_m <mu^(m)> (eq. dklambda_def), and the mode obeys
+ * q_l'' = -omega^2 q_l - eps d_l.  The total dipole at the integer time t_n is
+ * formed from the latest states rho^{n-1/2}, carried half a step forward by
+ * their rate (eq. dipole_derivative; second order):
+ *   d^n = sum_m [ <mu^(m)>(rho^{n-1/2}) + (dt/2) mu_dot^(m)(rho^{n-1/2}) ].
+ * Per step: E~ from q^n and d^n, the emitter steps (as the coupled step does
+ * them), then
  *   p^{n+1/2} = p^{n-1/2} - dt (omega^2 q^n + eps d^n),  q^{n+1} = q^n + dt p^{n+1/2},
- *   d^{n+1} = d^n + dt sum_m mu_dot^{n+1/2},
- * with d^0 the sum of the current states' expectation values.  q0 and p0 are
+ * and d^{n+1} from the new states; d^0 comes from the states at the call, and
+ * mlk_set_tls_dipoles forms it again from the new dipoles.  q0 and p0 are
  * (x, y): q at step 0 and p half a step before.  mlk_step then advances the
  * emitters and the mode and leaves the grid alone; populations are recorded as
  * usual and checkpoints carry the mode state.  Call after every emitter is

@@ -940,29 +940,41 @@ static void dipole_expect(const ora_emitter* e, double out[3]) {
  * photonic mode of frequency w, polarised along x and along y, with mode function
  * e_l / sqrt(V); with eps0 = 1 the coupling is eps = w / sqrt(V).  Every emitter
  * feels the same field E~ = -sum_l (eps q_l + d_l / V) e_l and the mode obeys
- * q_l'' = -w^2 q_l - eps d_l, d_l = sum_m <mu_l^(m)>.  Discretised as the grid
- * scheme is: q at integer steps, p = q' at half steps (leapfrog), emitters at
- * half steps, and the total dipole advanced by the same mu_dot that the grid
- * turns into a current: d^{n+1} = d^n + dt sum_m mu_dot^{n+1/2}, from d^0 =
- * sum_m <mu> of the initial states.  Step n -> n+1:
+ * q_l'' = -w^2 q_l - eps d_l, where d_l = sum_m <mu_l^(m)> is the total dipole
+ * (eq. dklambda_def with f = e_l / sqrt(V)).  Discretised as the grid scheme is:
+ * q at integer steps, p = q' at half steps (leapfrog), emitters at half steps.
+ * The total dipole at the integer time t_n is formed from the expectation values
+ * of the latest states, rho^{n-1/2}, carried half a step forward by their own
+ * rate (eq. dipole_derivative):
+ *   d^n = sum_m [ <mu^(m)>(rho_m^{n-1/2}) + (dt/2) mu_dot_m(rho_m^{n-1/2}) ],
+ * second-order accurate like the rest of the scheme (a bare <mu> at t_{n-1/2}
+ * would lag by half a step).  mu_dot is a function of the state alone (the field
+ * term of Tr(rho_dot mu) vanishes because mu commutes with itself), so d^0 comes
+ * from the initial states.  Step n -> n+1:
  *   E~^n from q^n and d^n; rho^{n-1/2} -> rho^{n+1/2}, mu_dot^{n+1/2};
  *   p^{n+1/2} = p^{n-1/2} - dt (w^2 q^n + eps d^n);  q^{n+1} = q^n + dt p^{n+1/2};
- *   d^{n+1} = d^n + dt sum_m mu_dot^{n+1/2}  (emitters summed in index order).
+ *   d^{n+1} from the new states (emitters summed in index order).
  * The grid is left alone.  Call after the emitters are added and before the
  * first step. */
+static void cavity_dipole(ora_sim* s, double out[2]) {
+  out[0] = out[1] = 0.0;
+  for (int m = 0; m < s->nem; ++m) {
+    double mu[3];
+    dipole_expect(&s->em[m], mu);
+    out[0] += mu[0] + 0.5 * s->dt * s->em[m].mudot[0];
+    out[1] += mu[1] + 0.5 * s->dt * s->em[m].mudot[1];
+  }
+}
+
 int ora_set_cavity(ora_sim* s, double w, double V, const double q0[2], const double p0[2]) {
   if (!(w > 0.0) || !(V > 0.0) || s->step != 0 || s->npole > 0) return -1;
   s->cav_on = 1;
   s->cav_w = w;
   s->cav_V = V;
   s->cav_eps = w / sqrt(V);
-  s->cav_d[0] = s->cav_d[1] = 0.0;
-  for (int m = 0; m < s->nem; ++m) {
-    double mu[3];
-    dipole_expect(&s->em[m], mu);
-    s->cav_d[0] += mu[0];
-    s->cav_d[1] += mu[1];
-  }
+  /* the rates of the initial states (no field has acted yet) */
+  for (int m = 0; m < s->nem; ++m) dipole_rate(&s->em[m]);
+  cavity_dipole(s, s->cav_d);
   for (int l = 0; l < 2; ++l) {
     s->cav_q[l] = q0[l];
     s->cav_p[l] = p0[l];
@@ -1021,15 +1033,12 @@ static void cavity_step(ora_sim* s) {
     memcpy(s->em[m].Et, Et, 3 * sizeof(double));
     emitter_advance(s, &s->em[m]);
   }
-  double sum[2] = {0.0, 0.0};
-  for (int m = 0; m < s->nem; ++m) {
-    sum[0] += s->em[m].mudot[0];
-    sum[1] += s->em[m].mudot[1];
-  }
+  double dnew[2];
+  cavity_dipole(s, dnew);
   for (int l = 0; l < 2; ++l) {
     s->cav_p[l] -= dt * (w2 * s->cav_q[l] + eps * s->cav_d[l]);
     s->cav_q[l] += dt * s->cav_p[l];
-    s->cav_d[l] += dt * sum[l];
+    s->cav_d[l] = dnew[l];
   }
   if (s->pop_every > 0 && s->step % s->pop_every == 0)
     for (int m = 0; m < s->nem; ++m)
@@ -1654,5 +1663,10 @@ void ora_linear_step_adjoint(ora_sim* s, double* y) {
 int ora_set_tls_dipole(ora_sim* s, int m, const double* d) {
   if (m < 0 || m >= s->nem) return ORA_EINVAL;
   memcpy(s->em[m].d, d, 3 * sizeof(double));
+  if (s->cav_on) {
+    /* the mode's total dipole follows the new dipole vector */
+    dipole_rate(&s->em[m]);
+    cavity_dipole(s, s->cav_d);
+  }
   return ORA_OK;
 }

@@ -30,10 +30,14 @@ _lp = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
 
 def build(verbose: bool = False) -> str:
     """Compile liboracle.so with gcc (portable -O3, OpenMP)."""
-    cmd = ["gcc", "-O3", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-o", _LIB, _SRC, "-lm"]
+    # built beside the library and renamed over it, so a process that has the old
+    # library loaded keeps its copy intact
+    tmp = f"{_LIB}.{os.getpid()}.tmp"
+    cmd = ["gcc", "-O3", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
+    os.replace(tmp, _LIB)
     return _LIB
 
 

@@ -288,7 +288,9 @@ __global__ __launch_bounds__(256) void k_tls_step(TlsPtrs tls, double dt, const 
 
 // Cavity mode with two-level emitters only: each thread forms the mode's common
 // field E~ = -(eps q_l + d_l / V) e_l for its emitter, steps it, and the block
-// sums mu_dot_x and mu_dot_y in a fixed tree order into c.partial[block].
+// sums <mu> + (dt/2) mu_dot of the new state, x and y (the emitter's share of
+// the mode's total dipole at the next integer time), in a fixed tree order into
+// c.partial[block].  <mu> = 2 Re rho01 d.
 __global__ __launch_bounds__(kTlsThreads) void k_cavity_tls(TlsPtrs tls, double dt, CavityDev c,
                                                             double* Et, double* mudot,
                                                             const int64_t* pop_off, Series ser,
@@ -302,8 +304,9 @@ __global__ __launch_bounds__(kTlsThreads) void k_cavity_tls(TlsPtrs tls, double 
     Et[3 * e + 1] = -(c.eps * c.st[1] + c.st[5] / c.V);
     Et[3 * e + 2] = 0.0;
     tls_body(tls, dt, Et, mudot, pop_off, ser, step, m);
-    sx = mudot[3 * e + 0];
-    sy = mudot[3 * e + 1];
+    const double mu = 2.0 * tls.rho[3 * m + 1];
+    sx = mu * tls.dip[3 * m + 0] + 0.5 * dt * mudot[3 * e + 0];
+    sy = mu * tls.dip[3 * m + 1] + 0.5 * dt * mudot[3 * e + 1];
   }
   rx[t] = sx;
   ry[t] = sy;

@@ -156,13 +156,19 @@ hipError_t pole_post_f32(const PoleDev& p, const FieldPtrs<float>& f, const Geom
 // sum of mu_dot over the emitters, the (p, q, d) update and the step counter.
 int cavity_blocks(int M);
 hipError_t cavity_field(const CavityDev& c, double* Et, int M, hipStream_t st);
-hipError_t cavity_update(const CavityDev& c, const double* mudot, int M, double dt, int64_t* step,
-                         hipStream_t st);
+// Partial sums of <mu> + (dt/2) mu_dot over the states, then the (p, q) leapfrog
+// with the old d, the new d and the step counter.
+hipError_t cavity_update(const CavityDev& c, const TlsPtrs& tls, const MlDev& ml, double dt,
+                         int64_t* step, hipStream_t st);
+// The same sums, stored as d without advancing the mode (set-up, new dipoles).
+hipError_t cavity_set_dipole(const CavityDev& c, const TlsPtrs& tls, const MlDev& ml, double dt,
+                             hipStream_t st);
 // The (p, q, d) update from npartial per-block partial sums already in c.partial.
 hipError_t cavity_advance(const CavityDev& c, int npartial, double dt, int64_t* step,
                           hipStream_t st);
 // Two-level emitters only: E~ from the mode, the two-level step, and the partial sums
-// of mu_dot_x,y of each block of kTlsThreads slots into c.partial; returns the count.
+// of <mu> + (dt/2) mu_dot (x, y) of each block of kTlsThreads slots of the new states
+// into c.partial.
 hipError_t cavity_tls_step(const TlsPtrs& tls, double dt, const CavityDev& c, double* Et,
                            double* mudot, const int64_t* pop_off, const Series& ser,
                            const int64_t* step, hipStream_t st);

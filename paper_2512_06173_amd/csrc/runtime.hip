@@ -839,7 +839,7 @@ mlk_status enqueue_cavity_steps(mlk_sim* s, int64_t nsteps) {
         HIPCHK(ml_step(ml, s->ml_range, s->g.dt, s->d_Et, s->d_mudot, s->d_popoff, ser,
                        s->d_step, s->stream));
     }
-    HIPCHK(cavity_update(s->cav, s->d_mudot, s->nem, s->g.dt, s->d_step, s->stream));
+    HIPCHK(cavity_update(s->cav, tls, ml, s->g.dt, s->d_step, s->stream));
     mark_end(s, MLK_PHASE_EMITTERS, t0);
   }
   return MLK_OK;
@@ -1418,34 +1418,8 @@ mlk_status mlk_set_cavity(mlk_sim* s, double omega, double volume, const double 
                 "the cavity replaces the grid: no sources, probes, flux plane or poles");
   HIPCHK(hipSetDevice(s->desc.device));
   STCHK(sync_sim(s));
-  // d^0 = sum over emitters (id order) of d Tr(rho M) of the current states
-  const size_t nt = s->tls_gid.size(), nml = s->ml_gid.size();
-  constexpr int F = kMaxLevels;
-  std::vector<double> trho(3 * nt), mrho(2 * F * F * nml), mM(F * F * nml), mdip(3 * nml);
-  if (nt) HIPCHK(hipMemcpy(trho.data(), s->d_tls_rho, trho.size() * 8, hipMemcpyDeviceToHost));
-  if (nml) {
-    HIPCHK(hipMemcpy(mrho.data(), s->d_ml_rho, mrho.size() * 8, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(mM.data(), s->d_ml_M, mM.size() * 8, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(mdip.data(), s->d_ml_dip, mdip.size() * 8, hipMemcpyDeviceToHost));
-  }
+  const size_t nt = s->tls_gid.size();
   double st[6] = {q0[0], q0[1], p0[0], p0[1], 0.0, 0.0};
-  for (int e = 0; e < s->nem; ++e) {
-    const int k = s->tls_slot[e];
-    double mu[2];
-    if (k >= 0) {
-      const double tr = trho[3 * (size_t)k + 1] + trho[3 * (size_t)k + 1];  // Tr(rho sigma_x)
-      for (int c = 0; c < 2; ++c) mu[c] = tr * s->tls_dip[3 * (size_t)k + c];
-    } else {
-      const size_t m = (size_t)s->ml_slot[e];
-      double tr = 0.0;
-      for (int a = 0; a < F; ++a)
-        for (int b = 0; b < F; ++b)
-          tr += mrho[(size_t)(2 * (a * F + b)) * nml + m] * mM[(size_t)(b * F + a) * nml + m];
-      for (int c = 0; c < 2; ++c) mu[c] = tr * mdip[(size_t)c * nml + m];
-    }
-    st[4] += mu[0];
-    st[5] += mu[1];
-  }
   if (!s->cav.st) HIPCHK(dalloc(&s->cav.st, 6 * sizeof(double)));
   // partial sums: at most 256 blocks in the general path, one per 256 two-level
   // emitters in the two-level path
@@ -1456,6 +1430,9 @@ mlk_status mlk_set_cavity(mlk_sim* s, double omega, double volume, const double 
   s->cav.w = omega;
   s->cav.V = volume;
   s->cav.eps = omega / std::sqrt(volume);
+  // d^0 from the initial states: sum of <mu> + (dt/2) mu_dot
+  HIPCHK(cavity_set_dipole(s->cav, tls_ptrs(s), ml_dev(s), s->g.dt, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
   s->cav_on = true;
   return MLK_OK;
 }
@@ -2018,6 +1995,11 @@ mlk_status mlk_set_tls_dipoles(mlk_sim* s, int32_t first, int32_t count, const d
   }
   HIPCHK(hipMemcpy(s->d_tls_dip, s->tls_dip.data(), s->tls_dip.size() * sizeof(double),
                    hipMemcpyHostToDevice));
+  if (s->cav_on) {
+    // the mode's total dipole is a sum over the states with these dipoles
+    HIPCHK(cavity_set_dipole(s->cav, tls_ptrs(s), ml_dev(s), s->g.dt, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+  }
   return MLK_OK;
 }
 
