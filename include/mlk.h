@@ -158,14 +158,20 @@ mlk_status mlk_add_plane_source(mlk_sim* s, int32_t axis, int32_t index, int32_t
 mlk_status mlk_add_point_source(mlk_sim* s, int32_t comp, const int32_t ijk[3], double amp,
                                 double omega, double tau, double t0);
 
-/* Probe of field component comp (0..5) at ijk, sampled after each step. */
+/* Probe of field component comp (0..5) at ijk: the field at its Yee point after
+ * each step's E update, E^{n+1} (or H^{n+1/2}), one value per step (the time series
+ * of the local field that the examples of Sec. IV read). */
 mlk_status mlk_add_probe(mlk_sim* s, int32_t comp, const int32_t ijk[3], int32_t* id);
 /* Poynting flux through plane `index` (1 .. n-1) of `axis`, one value per step:
  * F^{n+1/2} = dx^2 sum (E_u H_v - E_v H_u) with E averaged over n, n+1 and H over
  * the two half cells across the plane, (axis,u,v) cyclic; the running
- * integral dt * sum F is kept as well.  One flux plane per simulation. */
+ * integral dt * sum F is kept as well (the energy that the plane-wave pulse of
+ * App. B carries through a plane, from eq. Maxwell).  One flux plane per
+ * simulation. */
 mlk_status mlk_add_flux_plane(mlk_sim* s, int32_t axis, int32_t index);
-/* Record Re rho_kk, k >= 1, of every emitter on steps with n % every == 0. */
+/* Record Re rho_kk, k >= 1, of every emitter on steps with n % every == 0, right
+ * after the emitter step (the populations at t_{n+1/2}; the excited-state
+ * population of eq. population_decay_superradiance, Sec. IV.A). */
 mlk_status mlk_record_populations(mlk_sim* s, int32_t every);
 
 /* Advance nsteps full coupled steps (asynchronous). */
@@ -187,6 +193,14 @@ mlk_status mlk_step(mlk_sim* s, int64_t nsteps);
  * EINVAL: negative nsteps, bad mem_kind, null Et (with emitters, nsteps > 0). */
 mlk_status mlk_step_prescribed(mlk_sim* s, int64_t nsteps, const double* Et, int32_t mem_kind,
                                double* tls_out);
+/* Wait for the sim's work.  Also the non-finite watchdog (robustness, Sec. III item
+ * (v)): every emitter step checks its new state and dipole rate, and the detectors
+ * check each probe sample and flux value; the first step at which one is not finite
+ * is kept on the device, and mlk_sync (and mlk_batch_sync for every member) then
+ * returns MLK_ENUMERIC naming it, on every call until mlk_checkpoint_load restores a
+ * state.  A non-finite field reaches the watchdog through the emitters whose window
+ * it touches and through the probes and the flux plane.  Stepping goes on regardless
+ * (the values stay what the arithmetic gives). */
 mlk_status mlk_sync(mlk_sim* s);
 mlk_status mlk_step_count(mlk_sim* s, int64_t* n);
 
@@ -253,9 +267,15 @@ mlk_status mlk_get_series(mlk_sim* s, int32_t kind, int32_t id, double* dst, int
                           int64_t* len);
 mlk_status mlk_get_flux_total(mlk_sim* s, double* total);
 
-/* Checkpoint of the whole evolving state (fields, psi, emitter states, step
- * counter, flux integral); restoring gives an identical continuation.
- * Recorded series are not part of it. */
+/* Checkpoint of the whole evolving state (restart after a failure, Sec. III
+ * item (v)); restoring gives an identical continuation, bit for bit.  Recorded
+ * series are not part of it.  Layout, in order: Ex, Ey, Ez, Hx, Hy, Hz (nx*ny*nz
+ * values each in the field precision, x fastest); the CPML state (with a CPML
+ * face); the two-level states (rho11, Re rho01, Im rho01 per two-level emitter, in
+ * id order); the multilevel states; E~ and mu_dot (3 doubles per emitter); the step
+ * counter (int64); the flux integral (with a flux plane); the cavity mode (6
+ * doubles); the dispersive poles.  mlk_checkpoint_load also clears the non-finite
+ * watchdog (see mlk_sync). */
 mlk_status mlk_checkpoint_size(mlk_sim* s, size_t* bytes);
 mlk_status mlk_checkpoint_save(mlk_sim* s, void* dst, int32_t mem_kind);
 mlk_status mlk_checkpoint_load(mlk_sim* s, const void* src, int32_t mem_kind);
@@ -309,7 +329,9 @@ mlk_status mlk_get_interior_box(mlk_sim* s, int32_t box[6]);
  * memory, written): grad_eps (design-box cells, x fastest; may be NULL),
  * grad_dipole (3 per emitter id; may be NULL), value (the objective).  The sim
  * is left in the state it had before the call.  Multilevel emitters: the call
- * returns MLK_EUNSUPPORTED. */
+ * returns MLK_EUNSUPPORTED.  MLK_ENUMERIC when a run inside the call met a
+ * non-finite value (the watchdog of mlk_sync is left as it was) or the objective is
+ * not finite. */
 enum { MLK_OBJ_FLUX = 0, MLK_OBJ_POPULATION = 1 };
 typedef struct mlk_objective {
   int32_t kind;

@@ -49,7 +49,9 @@ __device__ __forceinline__ void finish_body(const FieldPtrs<T>& f, const Geom& g
   if (t < ser.nprobe) {
     const int comp = ser.probe_comp[t];
     const T* a = comp < 3 ? f.E[comp] : f.H[comp - 3];
-    ser.probe[(size_t)t * ser.cap + n] = (double)a[ser.probe_idx[t]];
+    const double v = (double)a[ser.probe_idx[t]];
+    ser.probe[(size_t)t * ser.cap + n] = v;
+    if (!isfinite(v)) flag_nonfinite(ser, n);
   }
   if (fp.on) {
     double s = 0.0;
@@ -64,6 +66,7 @@ __device__ __forceinline__ void finish_body(const FieldPtrs<T>& f, const Geom& g
       const double F = red[0] * g.dx * g.dx;
       fp.series[n] = F;
       *fp.total += g.dt * F;
+      if (!isfinite(F)) flag_nonfinite(ser, n);
     }
   }
   __syncthreads();

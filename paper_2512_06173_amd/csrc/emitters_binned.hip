@@ -268,6 +268,7 @@ __device__ __forceinline__ void tls_body(const TlsPtrs& tls, double dt, const do
   double st[3] = {tls.rho[3 * m], tls.rho[3 * m + 1], tls.rho[3 * m + 2]};
   double md[3];
   tls_advance(tls.omega0[m], d, et, dt, st, md);
+  if (!isfinite(st[0] + st[1] + st[2] + md[0] + md[1] + md[2])) flag_nonfinite(ser, *step);
   tls.rho[3 * m] = st[0];
   tls.rho[3 * m + 1] = st[1];
   tls.rho[3 * m + 2] = st[2];

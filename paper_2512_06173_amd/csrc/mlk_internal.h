@@ -201,7 +201,16 @@ struct Series {
   int pop_every;
   int64_t npop;
   int64_t pop_cap;     // records
+  // non-finite watchdog: 0 while every checked value is finite, else 1 + the first
+  // step at which an emitter state, dipole rate, probe sample or flux value was not
+  unsigned long long* numeric;
 };
+
+// Record step n as the first non-finite one (the earliest record wins the race only
+// within a launch; launches run in step order, so the first launch to set it wins).
+__device__ __forceinline__ void flag_nonfinite(const Series& ser, int64_t n) {
+  if (ser.numeric) atomicCAS(ser.numeric, 0ull, (unsigned long long)n + 1ull);
+}
 
 struct FluxPlane {
   int on;

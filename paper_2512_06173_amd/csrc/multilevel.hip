@@ -141,7 +141,7 @@ __device__ __forceinline__ void ml_body(const MlDev& ml, int first, int count, d
 
   // rho' = U rho U^+ row by row: T = U rho (row a), rho'_ab = (T U^+)_ab for b >= a;
   // the second half dephasing, the store, the population and the trace follow
-  double tr = 0.0;
+  double tr = 0.0, diag = 0.0;
   const int64_t n = *step;
   const bool rec = ser.pop_every > 0 && n % ser.pop_every == 0;
 #pragma unroll
@@ -172,6 +172,7 @@ __device__ __forceinline__ void ml_body(const MlDev& ml, int first, int count, d
       }
       const size_t q = (size_t)(a * kMaxLevels + b);
       if (a == b) {
+        diag += re;
         ml.rho[(2 * q) * st + m] = re;
         ml.rho[(2 * q + 1) * st + m] = 0.0;
         if (rec && a > 0)
@@ -190,6 +191,7 @@ __device__ __forceinline__ void ml_body(const MlDev& ml, int first, int count, d
     }
   }
   tr *= -2.0;
+  if (!isfinite(tr + diag)) flag_nonfinite(ser, n);
   mudot[3 * e] = tr * ml.dip[m];
   mudot[3 * e + 1] = tr * ml.dip[st + m];
   mudot[3 * e + 2] = tr * ml.dip[2 * st + m];

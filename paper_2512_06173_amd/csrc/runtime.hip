@@ -171,6 +171,8 @@ struct mlk_sim {
 
   int64_t* d_step = nullptr;
   int64_t host_step = 0;
+  // non-finite watchdog (see Series::numeric)
+  unsigned long long* d_numeric = nullptr;
 
   // single-mode cavity in place of the grid (off unless mlk_set_cavity was called)
   bool cav_on = false;
@@ -261,7 +263,26 @@ Series series_of(const mlk_sim* s) {
   ser.pop_every = s->pop_every;
   ser.npop = s->npop;
   ser.pop_cap = s->pop_cap;
+  ser.numeric = s->d_numeric;
   return ser;
+}
+
+// The watchdog's record after the sim's work is done (0: every checked value finite).
+mlk_status read_numeric(mlk_sim* s, unsigned long long* v) {
+  STCHK(sync_sim(s));
+  HIPCHK(hipMemcpy(v, s->d_numeric, sizeof(*v), hipMemcpyDeviceToHost));
+  return MLK_OK;
+}
+
+mlk_status check_numeric(mlk_sim* s) {
+  unsigned long long v = 0;
+  STCHK(read_numeric(s, &v));
+  if (v)
+    return fail(MLK_ENUMERIC,
+                "non-finite state: an emitter state, dipole rate, probe sample or flux value "
+                "was not finite at step %llu",
+                v - 1);
+  return MLK_OK;
 }
 
 bool in_range_face(const mlk_sim* s, int a, double x, double reach) {
@@ -893,6 +914,7 @@ void release(mlk_sim* s) {
   dfree(s->fp.total);
   dfree(s->d_pop);
   dfree(s->d_step);
+  dfree(s->d_numeric);
   dfree(s->cav.st);
   dfree(s->cav.partial);
   for (int k = 0; k < s->npole; ++k) {
@@ -930,6 +952,23 @@ std::vector<Piece> state_pieces(mlk_sim* s) {
     v.push_back({s->pole[k].Q, nb * s->esz});
   }
   return v;
+}
+
+// Restore the evolving state from a checkpoint (the watchdog is left alone).
+mlk_status load_state(mlk_sim* s, const void* src, int32_t mem_kind) {
+  STCHK(sync_sim(s));
+  const char* o = (const char*)src;
+  const hipMemcpyKind kind =
+      mem_kind == MLK_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  for (const Piece& p : state_pieces(s)) {
+    HIPCHK(hipMemcpy(p.p, o, p.bytes, kind));
+    o += p.bytes;
+  }
+  int64_t step = 0;
+  HIPCHK(hipMemcpy(&step, s->d_step, sizeof(int64_t), hipMemcpyDeviceToHost));
+  if (step > s->host_step) STCHK(reserve_series(s, step - s->host_step));
+  s->host_step = step;
+  return MLK_OK;
 }
 
 }  // namespace
@@ -1077,9 +1116,11 @@ mlk_status mlk_create(const mlk_grid_desc* gd, mlk_sim** out) {
         return bail(fail(MLK_EDEVICE, "CPML table kernel failed"));
     }
   }
-  if (dalloc(&s->d_step, sizeof(int64_t)) != hipSuccess)
+  if (dalloc(&s->d_step, sizeof(int64_t)) != hipSuccess ||
+      dalloc(&s->d_numeric, sizeof(unsigned long long)) != hipSuccess)
     return bail(fail(MLK_ENOMEM, "step counter allocation failed"));
   if (hipMemsetAsync(s->d_step, 0, sizeof(int64_t), s->stream) != hipSuccess ||
+      hipMemsetAsync(s->d_numeric, 0, sizeof(unsigned long long), s->stream) != hipSuccess ||
       hipStreamSynchronize(s->stream) != hipSuccess)
     return bail(fail(MLK_EDEVICE, "initialisation failed"));
   *out = s;
@@ -1522,8 +1563,7 @@ mlk_status mlk_get_interior_box(mlk_sim* s, int32_t box[6]) {
 
 mlk_status mlk_sync(mlk_sim* s) {
   if (!s) return fail(MLK_EINVAL, "null argument");
-  STCHK(sync_sim(s));
-  return MLK_OK;
+  return check_numeric(s);
 }
 
 mlk_status mlk_step_count(mlk_sim* s, int64_t* n) {
@@ -1677,18 +1717,10 @@ mlk_status mlk_checkpoint_save(mlk_sim* s, void* dst, int32_t mem_kind) {
 
 mlk_status mlk_checkpoint_load(mlk_sim* s, const void* src, int32_t mem_kind) {
   if (!s || !src) return fail(MLK_EINVAL, "null argument");
-  STCHK(sync_sim(s));
-  const char* o = (const char*)src;
-  const hipMemcpyKind kind =
-      mem_kind == MLK_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-  for (const Piece& p : state_pieces(s)) {
-    HIPCHK(hipMemcpy(p.p, o, p.bytes, kind));
-    o += p.bytes;
-  }
-  int64_t step = 0;
-  HIPCHK(hipMemcpy(&step, s->d_step, sizeof(int64_t), hipMemcpyDeviceToHost));
-  if (step > s->host_step) STCHK(reserve_series(s, step - s->host_step));
-  s->host_step = step;
+  STCHK(load_state(s, src, mem_kind));
+  // a new state: the watchdog starts afresh
+  const unsigned long long zero = 0;
+  HIPCHK(hipMemcpy(s->d_numeric, &zero, sizeof(zero), hipMemcpyHostToDevice));
   return MLK_OK;
 }
 
@@ -1823,7 +1855,7 @@ mlk_status adjoint_run(mlk_sim* s, int kind, const double* weights, int64_t T_st
   const FluxPlane* fpp = s->fp.on ? &s->fp : nullptr;
 
   for (int seg = nseg - 1; seg >= 0; --seg) {
-    STCHK(mlk_checkpoint_load(s, ckpt.p + ck * (size_t)seg, MLK_MEM_DEVICE));
+    STCHK(load_state(s, ckpt.p + ck * (size_t)seg, MLK_MEM_DEVICE));
     const int64_t ns = std::min<int64_t>(K, T_steps - (int64_t)seg * K);
     // recompute the segment, recording the tape
     if (nb) {
@@ -1886,7 +1918,7 @@ mlk_status adjoint_run(mlk_sim* s, int kind, const double* weights, int64_t T_st
   s->adj_forward_ms = f_ms;
   s->adj_reverse_ms = r_ms;
   // back to the state before the call
-  STCHK(mlk_checkpoint_load(s, ckpt.p, MLK_MEM_DEVICE));
+  STCHK(load_state(s, ckpt.p, MLK_MEM_DEVICE));
   s->host_step = step0;
   STCHK(sync_sim(s));
   if (nb && grad_eps) HIPCHK(hipMemcpy(grad_eps, geps.p, nb * sizeof(double), hipMemcpyDeviceToHost));
@@ -1930,10 +1962,21 @@ mlk_status mlk_adjoint(mlk_sim* s, const mlk_objective* obj, int64_t nsteps, int
   HIPCHK(hipSetDevice(s->desc.device));
   STCHK(sync_sim(s));
   const int K = (int)std::min<int64_t>(ckpt_every, nsteps);
-  return s->fp32 ? adjoint_run<float>(s, obj->kind, obj->weights, nsteps, K, b, grad_eps,
-                                      grad_dipole, value)
-                 : adjoint_run<double>(s, obj->kind, obj->weights, nsteps, K, b, grad_eps,
-                                       grad_dipole, value);
+  unsigned long long before = 0, after = 0;
+  STCHK(read_numeric(s, &before));
+  STCHK(s->fp32 ? adjoint_run<float>(s, obj->kind, obj->weights, nsteps, K, b, grad_eps,
+                                     grad_dipole, value)
+                : adjoint_run<double>(s, obj->kind, obj->weights, nsteps, K, b, grad_eps,
+                                      grad_dipole, value));
+  // the runs inside the call leave the watchdog as they found it, and report
+  STCHK(read_numeric(s, &after));
+  if (after != before) {
+    HIPCHK(hipMemcpy(s->d_numeric, &before, sizeof(before), hipMemcpyHostToDevice));
+    return fail(MLK_ENUMERIC, "non-finite state in the adjoint's forward runs at step %llu",
+                after - 1);
+  }
+  if (!std::isfinite(*value)) return fail(MLK_ENUMERIC, "non-finite objective");
+  return MLK_OK;
 }
 
 mlk_status mlk_get_adjoint_times(mlk_sim* s, double* forward_ms, double* reverse_ms) {
@@ -2425,6 +2468,10 @@ mlk_status mlk_batch_replay(mlk_batch* b, int64_t nreplays) {
 mlk_status mlk_batch_sync(mlk_batch* b) {
   if (!b) return fail(MLK_EINVAL, "null argument");
   HIPCHK(hipStreamSynchronize(b->stream));
+  for (mlk_sim* s : b->sims) {
+    const mlk_status st = check_numeric(s);
+    if (st != MLK_OK) return st;
+  }
   return MLK_OK;
 }
 

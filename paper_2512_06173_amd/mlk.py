@@ -316,12 +316,14 @@ class Simulation:
         no back-action).  Et: (nsteps, M, 3) or (M, 3), gamma times the smeared field per
         emitter.  With record, returns the two-level states after every step,
         (nsteps, ntls, 3) as (rho11, Re rho01, Im rho01)."""
+        return self._prescribed(lib().mlk_step_prescribed, Et, record)
+
+    def _prescribed(self, fn, Et, record):
         M = len(self.nlev)
         E = np.ascontiguousarray(np.asarray(Et, dtype=np.float64).reshape(-1, M, 3))
         out = np.zeros((E.shape[0], self.n_tls, 3)) if record else None
-        _check(lib().mlk_step_prescribed(self._h, E.shape[0], E.ctypes.data_as(C.c_void_p),
-                                         MEM_HOST, out.ctypes.data_as(C.c_void_p)
-                                         if record and self.n_tls else None))
+        _check(fn(self._h, E.shape[0], E.ctypes.data_as(C.c_void_p), MEM_HOST,
+                  out.ctypes.data_as(C.c_void_p) if record and self.n_tls else None))
         return out
 
     def add_susceptibility(self, box, omega0, gamma, sigma, drude=False):
