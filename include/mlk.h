@@ -193,6 +193,20 @@ mlk_status mlk_step(mlk_sim* s, int64_t nsteps);
  * EINVAL: negative nsteps, bad mem_kind, null Et (with emitters, nsteps > 0). */
 mlk_status mlk_step_prescribed(mlk_sim* s, int64_t nsteps, const double* Et, int32_t mem_kind,
                                double* tls_out);
+/* The same classical-path steps for callers that cannot allocate device memory
+ * (tight driver loops, code that forbids hipMalloc): with host buffers the field
+ * and the recorded states pass through a fixed 16 MiB staging array on each device
+ * (2,097,152 doubles, allocated when the library is loaded and held until the
+ * process ends) instead of staging allocated per call; with device buffers nothing
+ * is staged.  No hipMalloc, hipFree or other allocating call is made.  Results are
+ * those of mlk_step_prescribed, bit for bit.  A step needs 3 M doubles of staging
+ * (M emitters) plus 3 ntls with tls_out; EINVAL when that exceeds the array (about
+ * 700,000 emitters, 350,000 two-level ones with tls_out); otherwise as many steps
+ * as fit go through the array at a time.  All calls on one GPU share its array:
+ * calls that overlap in time on one GPU (from several host threads) race and are
+ * not allowed.  Returns when the host buffers are done with. */
+mlk_status mlk_step_prescribed_noalloc(mlk_sim* s, int64_t nsteps, const double* Et,
+                                       int32_t mem_kind, double* tls_out);
 /* Wait for the sim's work.  Also the non-finite watchdog (robustness, Sec. III item
  * (v)): every emitter step checks its new state and dipole rate, and the detectors
  * check each probe sample and flux value; the first step at which one is not finite

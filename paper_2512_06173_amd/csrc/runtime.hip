@@ -16,6 +16,7 @@
 #include <string>
 #include <array>
 #include <vector>
+#include <mutex>
 
 #include "launch.h"
 #include "mlk.h"
@@ -1391,37 +1392,30 @@ mlk_status mlk_step(mlk_sim* s, int64_t nsteps) {
   return st;
 }
 
-mlk_status mlk_step_prescribed(mlk_sim* s, int64_t nsteps, const double* Et, int32_t mem_kind,
-                               double* tls_out) {
-  if (!s) return fail(MLK_EINVAL, "null argument");
-  if (nsteps < 0) return fail(MLK_EINVAL, "negative step count");
-  if (mem_kind != MLK_MEM_HOST && mem_kind != MLK_MEM_DEVICE) return fail(MLK_EINVAL, "bad mem_kind");
-  if (s->cav_on) return fail(MLK_ESTATE, "the cavity sets the field");
-  if (nsteps == 0 || s->nem == 0) return MLK_OK;
-  if (!Et) return fail(MLK_EINVAL, "null field");
-  HIPCHK(hipSetDevice(s->desc.device));
-  if (s->batch_stream) HIPCHK(hipStreamSynchronize(s->batch_stream));
+}  // extern "C"
+
+namespace {
+
+// Classical-path steps shared by the two entry points.  With host buffers the field
+// and the recorded states pass through device staging of `cap` doubles at stage,
+// K steps at a time (K >= 1, checked by the caller); with device buffers stage is
+// not used.
+mlk_status prescribed_steps(mlk_sim* s, int64_t nsteps, const double* Et, bool host,
+                            double* tls_out, double* stage, int64_t K) {
   const size_t per = 3 * (size_t)s->nem, nt = s->tls_gid.size();
   const TlsPtrs tls = tls_ptrs(s);
   const MlDev ml = ml_dev(s);
   Series ser = series_of(s);
   ser.pop_every = 0;  // no series: the step counter does not move
-  const bool host = mem_kind == MLK_MEM_HOST;
-  // host data goes through device staging in chunks of at most about 64 MB
-  const int64_t K = host ? std::max<int64_t>(1, std::min<int64_t>(nsteps, (int64_t)((64u << 20) /
-                                                                                   (8 * per))))
-                         : nsteps;
-  DevBuf<double> dE, dO;
-  if (host) {
-    HIPCHK(dE.alloc((size_t)K * per));
-    if (tls_out && nt) HIPCHK(dO.alloc((size_t)K * 3 * nt));
-  }
+  double* dE = host ? stage : nullptr;
+  double* dO = host ? stage + (size_t)K * per : nullptr;
+  if (!host) K = nsteps;
   for (int64_t c0 = 0; c0 < nsteps; c0 += K) {
     const int64_t kc = std::min(K, nsteps - c0);
-    const double* e = host ? dE.p : Et + (size_t)c0 * per;
-    double* o = tls_out && nt ? (host ? dO.p : tls_out + (size_t)c0 * 3 * nt) : nullptr;
+    const double* e = host ? dE : Et + (size_t)c0 * per;
+    double* o = tls_out && nt ? (host ? dO : tls_out + (size_t)c0 * 3 * nt) : nullptr;
     if (host)
-      HIPCHK(hipMemcpyAsync(dE.p, Et + (size_t)c0 * per, (size_t)kc * per * sizeof(double),
+      HIPCHK(hipMemcpyAsync(dE, Et + (size_t)c0 * per, (size_t)kc * per * sizeof(double),
                             hipMemcpyHostToDevice, s->stream));
     for (int64_t q = 0; q < kc; ++q) {
       const double* eq = e + (size_t)q * per;
@@ -1438,11 +1432,102 @@ mlk_status mlk_step_prescribed(mlk_sim* s, int64_t nsteps, const double* Et, int
       HIPCHK(hipMemcpyAsync(s->d_Et, e + (size_t)(kc - 1) * per, per * sizeof(double),
                             hipMemcpyDeviceToDevice, s->stream));
     if (host && o)
-      HIPCHK(hipMemcpyAsync(tls_out + (size_t)c0 * 3 * nt, dO.p, (size_t)kc * 3 * nt * sizeof(double),
+      HIPCHK(hipMemcpyAsync(tls_out + (size_t)c0 * 3 * nt, dO, (size_t)kc * 3 * nt * sizeof(double),
                             hipMemcpyDeviceToHost, s->stream));
     if (host) HIPCHK(hipStreamSynchronize(s->stream));  // staging is reused
   }
   return MLK_OK;
+}
+
+// Argument checks shared by the two entry points; *go is false when there is
+// nothing to do.
+mlk_status prescribed_args(mlk_sim* s, int64_t nsteps, const double* Et, int32_t mem_kind,
+                           bool* go) {
+  *go = false;
+  if (!s) return fail(MLK_EINVAL, "null argument");
+  if (nsteps < 0) return fail(MLK_EINVAL, "negative step count");
+  if (mem_kind != MLK_MEM_HOST && mem_kind != MLK_MEM_DEVICE) return fail(MLK_EINVAL, "bad mem_kind");
+  if (s->cav_on) return fail(MLK_ESTATE, "the cavity sets the field");
+  if (nsteps == 0 || s->nem == 0) return MLK_OK;
+  if (!Et) return fail(MLK_EINVAL, "null field");
+  HIPCHK(hipSetDevice(s->desc.device));
+  if (s->batch_stream) HIPCHK(hipStreamSynchronize(s->batch_stream));
+  *go = true;
+  return MLK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mlk_status mlk_step_prescribed(mlk_sim* s, int64_t nsteps, const double* Et, int32_t mem_kind,
+                               double* tls_out) {
+  bool go = false;
+  STCHK(prescribed_args(s, nsteps, Et, mem_kind, &go));
+  if (!go) return MLK_OK;
+  const bool host = mem_kind == MLK_MEM_HOST;
+  const size_t per = 3 * (size_t)s->nem, nt = s->tls_gid.size();
+  // host data goes through device staging in chunks of at most about 64 MB
+  const int64_t K = host ? std::max<int64_t>(1, std::min<int64_t>(nsteps, (int64_t)((64u << 20) /
+                                                                                   (8 * per))))
+                         : nsteps;
+  DevBuf<double> stage;
+  if (host) HIPCHK(stage.alloc((size_t)K * (per + (tls_out ? 3 * nt : 0))));
+  return prescribed_steps(s, nsteps, Et, host, tls_out, stage.p, K);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Staging of mlk_step_prescribed_noalloc: a fixed device array, one copy on each
+// GPU the library runs on, held until the process ends.  In host code its name
+// only stands for the symbol: the device address comes from hipGetSymbolAddress,
+// taken once per device with that device current, and only that address is
+// handed to copies and kernels.
+constexpr size_t kScratchDoubles = (size_t)(16u << 20) / sizeof(double);  // 16 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kScratchDevices] = {};
+
+// Device address of the staging array on device dev (current on entry).
+mlk_status scratch_address(int dev, double** out) {
+  if (dev < 0 || dev >= kScratchDevices)
+    return fail(MLK_EUNSUPPORTED, "device %d: the fixed staging covers devices 0..%d", dev,
+                kScratchDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return MLK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mlk_status mlk_step_prescribed_noalloc(mlk_sim* s, int64_t nsteps, const double* Et,
+                                       int32_t mem_kind, double* tls_out) {
+  bool go = false;
+  STCHK(prescribed_args(s, nsteps, Et, mem_kind, &go));
+  if (!go) return MLK_OK;
+  if (mem_kind == MLK_MEM_DEVICE)  // device buffers need no staging
+    return prescribed_steps(s, nsteps, Et, false, tls_out, nullptr, nsteps);
+  const size_t per = 3 * (size_t)s->nem, nt = s->tls_gid.size();
+  const size_t need = per + (tls_out ? 3 * nt : 0);  // staging doubles per step
+  if (need > kScratchDoubles)
+    return fail(MLK_EINVAL,
+                "one step of %d emitters needs %zu doubles of staging, more than the %zu of "
+                "the fixed staging array",
+                s->nem, need, kScratchDoubles);
+  const int64_t K = std::min<int64_t>(nsteps, (int64_t)(kScratchDoubles / need));
+  double* ptr = nullptr;
+  STCHK(scratch_address(s->desc.device, &ptr));
+  return prescribed_steps(s, nsteps, Et, true, tls_out, ptr, K);
 }
 
 mlk_status mlk_set_cavity(mlk_sim* s, double omega, double volume, const double q0[2],

@@ -118,6 +118,8 @@ def lib():
         "mlk_batch_destroy": (st, [C.c_void_p]),
         "mlk_batch_autotune": (st, [C.c_void_p, C.c_char_p]),
         "mlk_step_prescribed": (st, [sim, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p]),
+        "mlk_step_prescribed_noalloc": (st, [sim, C.c_int64, C.c_void_p, C.c_int32,
+                                             C.c_void_p]),
         "mlk_set_cavity": (st, [sim, C.c_double, C.c_double, _dp, _dp]),
         "mlk_get_cavity": (st, [sim, _dp]),
         "mlk_add_susceptibility": (st, [sim, _ip, C.c_double, C.c_double, C.c_double, C.c_int32]),
@@ -146,6 +148,7 @@ def exported_symbols():
             "mlk_set_eps", "mlk_set_field", "mlk_add_tls", "mlk_add_multilevel",
             "mlk_add_plane_source", "mlk_add_point_source", "mlk_add_probe", "mlk_add_flux_plane",
             "mlk_record_populations", "mlk_step", "mlk_step_prescribed",
+            "mlk_step_prescribed_noalloc",
             "mlk_set_cavity", "mlk_get_cavity", "mlk_add_susceptibility", "mlk_sync", "mlk_step_count", "mlk_get_field",
             "mlk_get_rho", "mlk_get_tls_state", "mlk_get_emitter_io", "mlk_get_series",
             "mlk_get_flux_total", "mlk_checkpoint_size", "mlk_checkpoint_save",
@@ -317,6 +320,11 @@ class Simulation:
         emitter.  With record, returns the two-level states after every step,
         (nsteps, ntls, 3) as (rho11, Re rho01, Im rho01)."""
         return self._prescribed(lib().mlk_step_prescribed, Et, record)
+
+    def step_prescribed_noalloc(self, Et, record=False):
+        """As step_prescribed, through the library's fixed staging array: the call
+        allocates no device memory."""
+        return self._prescribed(lib().mlk_step_prescribed_noalloc, Et, record)
 
     def _prescribed(self, fn, Et, record):
         M = len(self.nlev)
