@@ -68,7 +68,7 @@ enum { MLK_SWEEP_FUSED = 0, MLK_SWEEP_PLAIN = 1 };
 /* Current scatter variant: deterministic owner-computes (default) or atomics. */
 enum { MLK_SCATTER_OWNER = 0, MLK_SCATTER_ATOMIC = 1 };
 /* Series kinds for mlk_get_series. */
-enum { MLK_SERIES_PROBE = 0, MLK_SERIES_FLUX = 1, MLK_SERIES_POPULATION = 2 };
+enum { MLK_SERIES_PROBE = 0, MLK_SERIES_FLUX = 1, MLK_SERIES_POPULATION = 2, MLK_SERIES_ENERGY = 3 };
 
 typedef struct mlk_sim mlk_sim;
 
@@ -173,6 +173,16 @@ mlk_status mlk_add_flux_plane(mlk_sim* s, int32_t axis, int32_t index);
  * after the emitter step (the populations at t_{n+1/2}; the excited-state
  * population of eq. population_decay_superradiance, Sec. IV.A). */
 mlk_status mlk_record_populations(mlk_sim* s, int32_t every);
+/* Record the discrete field energy (Poynting's theorem for eq. Maxwell on the Yee
+ * grid) on steps with n % every == 0 (0: off):
+ *   W^n = dx^3 [ 1/2 sum eps_r |E^n|^2 + 1/2 sum H^{n+1/2} . H^{n-1/2} ],
+ * summed in FP64 in a fixed order.  It is exactly invariant without currents,
+ * sources and CPML; with them it changes by the work done on the currents and
+ * the loss in the layers.  Read with mlk_get_series(MLK_SERIES_ENERGY).  Before the
+ * first step.  EUNSUPPORTED in the plain sweep (the detector reads both field
+ * buffers of the fused sweep) and with a cavity; batches refuse a member that
+ * records it. */
+mlk_status mlk_record_energy(mlk_sim* s, int32_t every);
 
 /* Advance nsteps full coupled steps (asynchronous). */
 mlk_status mlk_step(mlk_sim* s, int64_t nsteps);

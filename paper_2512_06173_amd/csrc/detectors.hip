@@ -100,6 +100,73 @@ __global__ __launch_bounds__(256) void k_detect_batch(const FluxJob<T>* jobs, co
   else finish_body(J.f, J.g, J.fp, J.ser, J.step);
 }
 
+// Discrete field energy (Poynting's theorem on the Yee grid; invariant without
+// currents, sources or absorbing layers):
+//   W^n = dx^3 [ 1/2 sum eps_r |E^n|^2 + 1/2 sum H^{n+1/2} . H^{n-1/2} ].
+// The fused sweep leaves E^n and H^{n-1/2} in the spare buffers (`old`) and
+// H^{n+1/2} in the current ones, so W^n is formed right after the sweep; FP64
+// partial sums per block, then one block adds them in a fixed order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_energy_partial(FieldPtrs<T> old, FieldPtrs<T> cur,
+                                                        size_t ncell, EnergyRec er,
+                                                        const int64_t* step) {
+  __shared__ double red[256];
+  if (*step % er.every != 0) return;  // uniform across the grid
+  double s = 0.0;
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < ncell;
+       q += (size_t)gridDim.x * blockDim.x) {
+    const double ex = old.E[0][q], ey = old.E[1][q], ez = old.E[2][q];
+    const double eps = old.epsinv ? 1.0 / (double)old.epsinv[q] : 1.0;
+    const double hh = (double)cur.H[0][q] * (double)old.H[0][q] +
+                      (double)cur.H[1][q] * (double)old.H[1][q] +
+                      (double)cur.H[2][q] * (double)old.H[2][q];
+    s += 0.5 * eps * (ex * ex + ey * ey + ez * ez) + 0.5 * hh;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) er.partial[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_energy_finish(EnergyRec er, const int64_t* step) {
+  __shared__ double red[256];
+  const int64_t n = *step;
+  if (n % er.every != 0) return;
+  const int t = threadIdx.x;
+  double s = 0.0;
+  for (int q = t; q < er.nblocks; q += blockDim.x) s += er.partial[q];
+  red[t] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) red[t] += red[t + w];
+    __syncthreads();
+  }
+  if (t == 0) er.series[n / er.every] = red[0] * er.dv;
+}
+
+template <typename T>
+static hipError_t launch_energy(const FieldPtrs<T>& old, const FieldPtrs<T>& cur, size_t ncell,
+                                const EnergyRec& er, const int64_t* step, hipStream_t st) {
+  hipLaunchKernelGGL(k_energy_partial<T>, dim3(er.nblocks), dim3(256), 0, st, old, cur, ncell, er,
+                     step);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_energy_finish, dim3(1), dim3(256), 0, st, er, step);
+  return hipGetLastError();
+}
+
+hipError_t energy_f64(const FieldPtrs<double>& old, const FieldPtrs<double>& cur, size_t ncell,
+                      const EnergyRec& er, const int64_t* step, hipStream_t st) {
+  return launch_energy<double>(old, cur, ncell, er, step, st);
+}
+hipError_t energy_f32(const FieldPtrs<float>& old, const FieldPtrs<float>& cur, size_t ncell,
+                      const EnergyRec& er, const int64_t* step, hipStream_t st) {
+  return launch_energy<float>(old, cur, ncell, er, step, st);
+}
+
 template <typename T>
 static hipError_t launch_flux_save(const FieldPtrs<T>& f, const Geom& g, const FluxPlane& fp,
                                    hipStream_t st) {

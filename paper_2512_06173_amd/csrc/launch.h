@@ -56,6 +56,12 @@ hipError_t flux_save_f64(const FieldPtrs<double>& f, const Geom& g, const FluxPl
                          hipStream_t st);
 hipError_t flux_save_f32(const FieldPtrs<float>& f, const Geom& g, const FluxPlane& fp,
                          hipStream_t st);
+// W^n from the spare (E^n, H^{n-1/2}) and current (H^{n+1/2}) buffers of the fused
+// sweep, into er.series on steps with n % er.every == 0.
+hipError_t energy_f64(const FieldPtrs<double>& old, const FieldPtrs<double>& cur, size_t ncell,
+                      const EnergyRec& er, const int64_t* step, hipStream_t st);
+hipError_t energy_f32(const FieldPtrs<float>& old, const FieldPtrs<float>& cur, size_t ncell,
+                      const EnergyRec& er, const int64_t* step, hipStream_t st);
 hipError_t finish_f64(const FieldPtrs<double>& f, const Geom& g, const FluxPlane& fp,
                       const Series& ser, int64_t* step, hipStream_t st);
 hipError_t finish_f32(const FieldPtrs<float>& f, const Geom& g, const FluxPlane& fp,

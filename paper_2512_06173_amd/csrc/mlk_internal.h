@@ -223,6 +223,15 @@ struct FluxPlane {
   double* total;    // running dt * sum F
 };
 
+// Discrete field energy W^n, recorded every `every` steps (0: off).
+struct EnergyRec {
+  int every;
+  double* partial;  // per-block partial sums (FP64)
+  int nblocks;
+  double* series;   // [records]
+  double dv;        // cell volume dx^3
+};
+
 // One Lorentz or Drude pole over a cell box: P^{n+1} (1 + g) = a P^n - b P^{n-1} + c E^n.
 struct PoleDev {
   int lo[3], n[3];    // box origin and extent (cells)

@@ -170,6 +170,9 @@ struct mlk_sim {
   double* d_pop = nullptr;
   int64_t pop_cap = 0;
 
+  EnergyRec er{};          // discrete field energy detector (off: er.every == 0)
+  int64_t energy_cap = 0;  // records
+
   int64_t* d_step = nullptr;
   int64_t host_step = 0;
   // non-finite watchdog (see Series::numeric)
@@ -625,6 +628,23 @@ mlk_status reserve_series(mlk_sim* s, int64_t nsteps) {
     }
     s->series_cap = cap;
   }
+  if (s->er.every > 0) {
+    const int64_t rec = (need + s->er.every - 1) / s->er.every;
+    if (rec > s->energy_cap) {
+      STCHK(sync_sim(s));
+      int64_t cap = s->energy_cap ? 2 * s->energy_cap : 64;
+      while (cap < rec) cap *= 2;
+      double* ne = nullptr;
+      HIPCHK(dalloc(&ne, (size_t)cap * sizeof(double)));
+      const int64_t have = s->host_step > 0 ? (s->host_step - 1) / s->er.every + 1 : 0;
+      if (s->er.series && have > 0)
+        HIPCHK(hipMemcpy(ne, s->er.series, (size_t)have * sizeof(double),
+                         hipMemcpyDeviceToDevice));
+      dfree(s->er.series);
+      s->er.series = ne;
+      s->energy_cap = cap;
+    }
+  }
   if (s->pop_every > 0 && s->npop > 0) {
     const int64_t rec = (need + s->pop_every - 1) / s->pop_every;
     if (rec > s->pop_cap) {
@@ -809,6 +829,13 @@ mlk_status enqueue_steps(mlk_sim* s, int64_t nsteps) {
     mark_end(s, MLK_PHASE_POLES, t0);
     STCHK(sweep<T>(s));
     f = field_ptrs<T>(s);
+    if (s->er.every > 0) {
+      // W^n: E^n and H^{n-1/2} are in the spare buffers now, H^{n+1/2} in the current
+      t0 = mark_begin(s, MLK_PHASE_DETECTORS);
+      if constexpr (f32) HIPCHK(energy_f32(spare_ptrs<T>(s), f, s->ncell, s->er, s->d_step, s->stream));
+      else HIPCHK(energy_f64(spare_ptrs<T>(s), f, s->ncell, s->er, s->d_step, s->stream));
+      mark_end(s, MLK_PHASE_DETECTORS, t0);
+    }
     t0 = mark_begin(s, MLK_PHASE_SCATTER);
     if (binned) {
       // in vacuum the owner write reads no 1/eps_r
@@ -916,6 +943,8 @@ void release(mlk_sim* s) {
   dfree(s->d_pop);
   dfree(s->d_step);
   dfree(s->d_numeric);
+  dfree(s->er.partial);
+  dfree(s->er.series);
   dfree(s->cav.st);
   dfree(s->cav.partial);
   for (int k = 0; k < s->npole; ++k) {
@@ -1368,6 +1397,26 @@ mlk_status mlk_add_flux_plane(mlk_sim* s, int32_t axis, int32_t index) {
   return MLK_OK;
 }
 
+mlk_status mlk_record_energy(mlk_sim* s, int32_t every) {
+  if (!s) return fail(MLK_EINVAL, "null argument");
+  if (s->host_step > 0) return fail(MLK_ESTATE, "detectors must be set before stepping");
+  if (s->in_batch) return fail(MLK_ESTATE, "the sim belongs to a batch");
+  if (every < 0) return fail(MLK_EINVAL, "every must be >= 0");
+  if (every > 0 && s->desc.sweep != MLK_SWEEP_FUSED)
+    return fail(MLK_EUNSUPPORTED, "the energy detector reads both field buffers of the fused sweep");
+  if (s->cav_on) return fail(MLK_EUNSUPPORTED, "the cavity replaces the grid: no field energy");
+  HIPCHK(hipSetDevice(s->desc.device));
+  dfree(s->er.series);
+  dfree(s->er.partial);
+  s->energy_cap = 0;
+  s->er.every = every;
+  if (every == 0) return MLK_OK;
+  s->er.nblocks = (int)std::max<size_t>(1, std::min<size_t>((s->ncell + 255) / 256, 1024));
+  s->er.dv = s->g.dx * s->g.dx * s->g.dx;
+  HIPCHK(dalloc(&s->er.partial, (size_t)s->er.nblocks * sizeof(double)));
+  return MLK_OK;
+}
+
 mlk_status mlk_record_populations(mlk_sim* s, int32_t every) {
   if (!s) return fail(MLK_EINVAL, "null argument");
   if (s->host_step > 0) return fail(MLK_ESTATE, "detectors must be set before stepping");
@@ -1760,6 +1809,10 @@ mlk_status mlk_get_series(mlk_sim* s, int32_t kind, int32_t id, double* dst, int
         (s->pop_every > 0 && s->host_step > 0) ? (s->host_step - 1) / s->pop_every + 1 : 0;
     n = rec * s->npop;
     src = s->d_pop;
+  } else if (kind == MLK_SERIES_ENERGY) {
+    if (s->er.every <= 0) return fail(MLK_EINVAL, "no energy record");
+    n = s->host_step > 0 ? (s->host_step - 1) / s->er.every + 1 : 0;
+    src = s->er.series;
   } else {
     return fail(MLK_EINVAL, "bad series kind");
   }
@@ -2432,6 +2485,9 @@ mlk_status mlk_batch_create(mlk_sim* const* sims, int32_t n, mlk_batch** out) {
         delete b;
         return fail(MLK_EINVAL, "member %d appears twice", q);
       }
+    if (s->er.every > 0) {
+      return fail(MLK_EUNSUPPORTED, "member %d records the field energy", q);
+    }
     if (s->cav_on || s->npole > 0) {
       delete b;
       return fail(MLK_EUNSUPPORTED, "member %d steps a cavity or dispersive media", q);

@@ -23,7 +23,7 @@ BC = {"pec": 0, "periodic": 1, "cpml": 2}
 MEM_HOST, MEM_DEVICE = 0, 1
 SWEEP = {"fused": 0, "plain": 1}
 SCATTER = {"owner": 0, "atomic": 1}
-SERIES_PROBE, SERIES_FLUX, SERIES_POPULATION = 0, 1, 2
+SERIES_PROBE, SERIES_FLUX, SERIES_POPULATION, SERIES_ENERGY = 0, 1, 2, 3
 
 _STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "EUNSUPPORTED", 6: "ENUMERIC"}
 
@@ -95,6 +95,7 @@ def lib():
         "mlk_add_probe": (st, [sim, C.c_int32, _ip, _ip]),
         "mlk_add_flux_plane": (st, [sim, C.c_int32, C.c_int32]),
         "mlk_record_populations": (st, [sim, C.c_int32]),
+        "mlk_record_energy": (st, [sim, C.c_int32]),
         "mlk_step": (st, [sim, C.c_int64]),
         "mlk_sync": (st, [sim]),
         "mlk_step_count": (st, [sim, _lp]),
@@ -147,7 +148,7 @@ def exported_symbols():
     return ["mlk_grid_desc_init", "mlk_last_error", "mlk_version", "mlk_create", "mlk_destroy",
             "mlk_set_eps", "mlk_set_field", "mlk_add_tls", "mlk_add_multilevel",
             "mlk_add_plane_source", "mlk_add_point_source", "mlk_add_probe", "mlk_add_flux_plane",
-            "mlk_record_populations", "mlk_step", "mlk_step_prescribed",
+            "mlk_record_populations", "mlk_record_energy", "mlk_step", "mlk_step_prescribed",
             "mlk_step_prescribed_noalloc",
             "mlk_set_cavity", "mlk_get_cavity", "mlk_add_susceptibility", "mlk_sync", "mlk_step_count", "mlk_get_field",
             "mlk_get_rho", "mlk_get_tls_state", "mlk_get_emitter_io", "mlk_get_series",
@@ -307,6 +308,9 @@ class Simulation:
     def record_populations(self, every=1):
         _check(lib().mlk_record_populations(self._h, int(every)))
 
+    def record_energy(self, every=1):
+        _check(lib().mlk_record_energy(self._h, int(every)))
+
     # ------------------------------------------------------------ stepping
     def step(self, n=1):
         _check(lib().mlk_step(self._h, int(n)))
@@ -411,6 +415,10 @@ class Simulation:
         v = C.c_double()
         _check(lib().mlk_get_flux_total(self._h, C.byref(v)))
         return v.value
+
+    def energy_series(self):
+        """W^n on the recorded steps (mlk_record_energy)."""
+        return self._series(SERIES_ENERGY)
 
     def populations(self):
         v = self._series(SERIES_POPULATION)

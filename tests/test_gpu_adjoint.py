@@ -50,9 +50,9 @@ def test_adjoint_matches_oracle_fp64(objective, sweep):
     gv, gge, ggd = sim.adjoint(objective, w.steps, BOX, weights=weights, checkpoint_every=25)
     say(f"[adjoint] {objective} {sweep}: value {abs(gv - ov) / abs(ov):.2e}, "
         f"eps {rel(gge, oge):.2e}, dipole {rel(ggd, ogd):.2e}")
-    assert abs(gv - ov) <= 1e-12 * abs(ov)
-    assert rel(gge, oge) <= 1e-10
-    assert rel(ggd, ogd) <= 1e-10
+    assert abs(gv - ov) <= 1e-14 * abs(ov)
+    assert rel(gge, oge) <= 1e-13
+    assert rel(ggd, ogd) <= 1e-13
 
 
 @pytest.mark.parametrize("bc, cpml", [
@@ -83,9 +83,9 @@ def test_adjoint_closures_tiles_and_chunks_fp64(bc, cpml, sweep):
     gv, gge, ggd = sim.adjoint("flux", w.steps, box, checkpoint_every=15)
     say(f"[adjoint closures] {bc} {sweep}: value {abs(gv - ov) / abs(ov):.2e}, "
         f"eps {rel(gge, oge):.2e}, dipole {rel(ggd, ogd):.2e}")
-    assert abs(gv - ov) <= 1e-12 * abs(ov)
-    assert rel(gge, oge) <= 1e-10
-    assert rel(ggd, ogd) <= 1e-10
+    assert abs(gv - ov) <= 1e-14 * abs(ov)
+    assert rel(gge, oge) <= 1e-13
+    assert rel(ggd, ogd) <= 1e-13
 
 
 @pytest.mark.parametrize("bc, cpml", [
@@ -121,8 +121,8 @@ def test_fused_transposed_sweep_fp32_matches_plain(bc, cpml):
     assert abs(fv - pv) <= 1e-5 * abs(pv)
     assert rel(fge, pge) <= 2e-5
     assert rel(fgd, pgd) <= 2e-5
-    assert rel(fge, oge) <= 1e-3
-    assert rel(fgd, ogd) <= 1e-3
+    assert rel(fge, oge) <= 1e-5
+    assert rel(fgd, ogd) <= 1e-5
 
 
 @pytest.mark.parametrize("objective", ["flux", "population"])
@@ -134,9 +134,9 @@ def test_adjoint_fp32_fields(objective):
     gv, gge, ggd = sim.adjoint(objective, w.steps, BOX, weights=weights, checkpoint_every=25)
     say(f"[adjoint fp32] {objective}: value {abs(gv - ov) / abs(ov):.2e}, "
         f"eps {rel(gge, oge):.2e}, dipole {rel(ggd, ogd):.2e}")
-    assert abs(gv - ov) <= 1e-4 * abs(ov)
-    assert rel(gge, oge) <= 1e-3
-    assert rel(ggd, ogd) <= 1e-3
+    assert abs(gv - ov) <= 1e-6 * abs(ov)
+    assert rel(gge, oge) <= 1e-5
+    assert rel(ggd, ogd) <= 1e-5
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -162,9 +162,9 @@ def test_adjoint_in_vacuum_matches_the_eps_array_path(precision):
         ov, oge, ogd = build_oracle(w).adjoint("flux", w.steps, BOX)
         say(f"[adjoint vacuum] value {abs(v - ov) / abs(ov):.2e}, eps {rel(ge, oge):.2e}, "
             f"dipole {rel(gd, ogd):.2e}")
-        assert abs(v - ov) <= 1e-12 * abs(ov)
-        assert rel(ge, oge) <= 1e-10
-        assert rel(gd, ogd) <= 1e-10
+        assert abs(v - ov) <= 1e-14 * abs(ov)
+        assert rel(ge, oge) <= 1e-13
+        assert rel(gd, ogd) <= 1e-13
 
 
 def test_checkpoint_interval_does_not_change_the_result():
