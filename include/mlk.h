@@ -103,6 +103,35 @@ const char* mlk_version(void);
 mlk_status mlk_create(const mlk_grid_desc* g, mlk_sim** out);
 mlk_status mlk_destroy(mlk_sim* s);
 
+/* Caller-owned device memory for the evolving state (e.g. tensors of the caller's
+ * framework), in place of the library's own allocations.  field[q][c] is component
+ * c (Ex, Ey, Ez, Hx, Hy, Hz) of field set q, bytes[0] bytes each (nx*ny*nz values
+ * of the field precision, x fastest); set 1 exists in the fused sweep only, whose two
+ * sets swap roles every step (mlk_get_field_set says which holds E^n and
+ * H^{n-1/2} now).  psi[q]: the CPML state of set q (bytes[1], layout of the
+ * checkpoint), only with CPML faces.  tls_state: (rho11, Re rho01, Im rho01) per
+ * two-level emitter in id order (bytes[2]); ml_state: the multilevel states
+ * (bytes[3], as the checkpoint holds them).  NULL entries keep the library's
+ * buffer.  Each buffer given takes over the current contents of the one it
+ * replaces, which is freed; from then on the library reads and writes the
+ * caller's memory and never frees it.  The caller keeps ownership and keeps every
+ * bound buffer alive and unmoved until mlk_destroy.  Pointers must be device memory
+ * on the sim's GPU, 16-byte aligned (256 recommended).  Emitter states can be bound
+ * once every emitter is added (adding emitters afterwards: ESTATE).  EINVAL: a set-1
+ * or psi buffer the sim does not have, misalignment; ESTATE: in a batch. */
+typedef struct {
+  void* field[2][6];
+  void* psi[2];
+  double* tls_state;
+  double* ml_state;
+} mlk_buffers;
+/* Sizes in bytes of one field array, one psi set, the two-level and the multilevel
+ * states, into bytes[4]. */
+mlk_status mlk_buffer_bytes(mlk_sim* s, size_t bytes[4]);
+mlk_status mlk_bind_device_buffers(mlk_sim* s, const mlk_buffers* b);
+/* Which field set (0 or 1) holds the current fields (always 0 in the plain sweep). */
+mlk_status mlk_get_field_set(mlk_sim* s, int32_t* set);
+
 /* Relative permittivity per cell, nx*ny*nz doubles, x fastest; every E
  * component with index (i,j,k) uses eps_r(i,j,k) (staircase, eq. Dromega with
  * a static eps_r).  EINVAL if any value is < 1 or not finite.  While the grid
@@ -424,17 +453,32 @@ mlk_status mlk_autotune(mlk_sim* s, const char* cache_path);
 mlk_status mlk_set_tuning(mlk_sim* s, int32_t ty, int32_t kz);
 mlk_status mlk_get_tuning(mlk_sim* s, int32_t* ty, int32_t* kz);
 
-/* Layer mode of the fused sweep (FP32 fields): on, the fused kernel updates the
- * whole grid and stretches the derivatives of the y and z CPML cells itself;
- * off, the cells of the y and z layers (plus a one-cell margin above the low
- * layers) are updated by the plain shell passes.  The default is on when the y
- * and z layers are a small part of the grid ((nlo + nhi) / n summed over y and z
- * at most 1/4); mlk_autotune times both modes and keeps the faster (and caches
- * it).  Like the tile shape, the mode changes speed, not results.  FP64 fields:
- * always off (MLK_EUNSUPPORTED for on).  MLK_ESTATE while the sim belongs to a
- * batch. */
+/* Layer mode of the fused sweep (FP32 fields): where the cells of the y and z CPML
+ * layers are updated.  0: by the plain shell passes (the fused box stops one cell
+ * above the low layers and at the high ones); 1: by the fused kernel itself, which
+ * then covers the whole grid and stretches their derivatives; 2: the box of mode 0
+ * by the lean fused kernel (no y/z layer code, fewer registers, more waves per
+ * SIMD), then the layer frame around it (the z slabs and the y slabs) in one launch
+ * of the full kernel (needs y or z layers and a box spanning every x column).  The
+ * default is 1 when the y and z layers are a small part of the grid ((nlo + nhi) / n
+ * summed over y and z at most 1/4), else 0; mlk_autotune times every mode and keeps
+ * the fastest (and caches it).  Like the tile shape, the mode changes speed, not
+ * results.  FP64 fields: always 0 (MLK_EUNSUPPORTED for 1 or 2).  MLK_ESTATE while
+ * the sim belongs to a batch (a batch runs modes 0 and 1; a member in mode 2 runs as
+ * in mode 0). */
 mlk_status mlk_set_sweep_layers(mlk_sim* s, int32_t on);
 mlk_status mlk_get_sweep_layers(mlk_sim* s, int32_t* on);
+
+/* ------------------------------------------------------------ calibration
+ * Streaming copy of `bytes` (a multiple of 16) from src to dst, both device memory,
+ * enqueued on `stream` (a hipStream_t; NULL = the null stream) with `blocks`
+ * workgroups of 256 threads, each thread moving 8 x 16 bytes per pass with every load
+ * issued before the first store.  variant: 0 ordinary loads and stores, 1 streaming
+ * (nontemporal) stores, 2 streaming loads, 3 both.  Not part of the method: the
+ * yardstick against which the sweep kernels' bandwidth is read.  EINVAL on bad
+ * arguments, EDEVICE when the launch fails. */
+mlk_status mlk_stream_copy(const void* src, void* dst, size_t bytes, int32_t variant,
+                           int32_t blocks, void* stream);
 
 #ifdef __cplusplus
 }

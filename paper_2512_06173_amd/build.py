@@ -12,7 +12,7 @@ LIB = os.path.join(HERE, "libmlk.so")
 SOURCES = ["runtime.hip", "setup.hip", "yee_plain.hip", "yee_fused.hip", "emitters.hip",
            "emitters_binned.hip", "multilevel.hip", "detectors.hip",
            "adjoint.hip", "adjoint_fused.hip", "cavity.hip",
-           "dispersive.hip"]
+           "dispersive.hip", "calib.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -32,6 +32,12 @@ hipError_t sources_f64(const FieldPtrs<double>& f, const Geom& g, const SourceSe
                        const int64_t* step, hipStream_t st);
 hipError_t sources_f32(const FieldPtrs<float>& f, const Geom& g, const SourceSet& src,
                        const int64_t* step, hipStream_t st);
+// The frame of y and z CPML layers around an interior box (which the fused sweep
+// covers with its lean kernel), by the full fused kernel in one launch.
+hipError_t sweep_frame_f64(const FieldPtrs<double>& a, const FieldPtrs<double>& b, const Geom& g,
+                           const Box& inner, int kz, hipStream_t st);
+hipError_t sweep_frame_f32(const FieldPtrs<float>& a, const FieldPtrs<float>& b, const Geom& g,
+                           const Box& inner, int kz, hipStream_t st);
 hipError_t sweep_fused_f64(const FieldPtrs<double>& a, const FieldPtrs<double>& b, const Geom& g,
                            const Box& box, int kz, int ty, hipStream_t st);
 hipError_t sweep_fused_f32(const FieldPtrs<float>& a, const FieldPtrs<float>& b, const Geom& g,

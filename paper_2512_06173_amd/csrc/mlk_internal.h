@@ -327,6 +327,15 @@ struct FusedJob {
   int kz, ty, ntx, nty, nblocks;
 };
 
+// Up to four boxes of one sim swept by one launch of the full fused kernel (the
+// layer frame around an interior box), passed by value.
+template <typename T>
+struct FrameJobs {
+  FusedJob<T> job[4];
+  int start[5];
+  int njobs;
+};
+
 // The cells of the grid outside an interior box, enumerated in memory order:
 // the whole planes below and above the box in z, then, plane by plane inside
 // it, the whole rows below and above it in y followed by the two x strips of

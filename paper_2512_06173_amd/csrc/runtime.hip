@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <climits>
+#include <cstdint>
 #include <algorithm>
 #include <string>
 #include <array>
@@ -99,9 +100,15 @@ struct mlk_sim {
   void* E2[3] = {};  // second buffers of the fused sweep (swapped every step)
   void* H2[3] = {};
   void* psi2 = nullptr;
+  // the two field sets of the fused sweep have swapped an odd number of times: the
+  // current fields are in set 1 (set 0 is the one E[] held at creation)
+  bool swapped = false;
+  // device buffers the caller owns (mlk_bind_device_buffers): never freed here
+  std::vector<const void*> borrowed;
+  bool states_bound = false;
   int kz = 0;       // z planes per workgroup of the fused sweep
   int ty = 4;       // y rows per workgroup of the fused sweep (4, 8 or 16)
-  bool layers = false;  // FP32 fused sweep carries the y and z CPML layers itself
+  int layer_mode = 0;  // y/z CPML layers: 0 shell passes, 1 in the fused kernel, 2 frame launch
   bool vacuum = true;   // eps_r = 1 in every cell: the fused sweep reads no 1/eps_r
   hipStream_t batch_stream = nullptr;  // stream of the batch this sim belongs to
   bool in_batch = false;
@@ -218,6 +225,7 @@ void swap_buffers(mlk_sim* s) {
     std::swap(s->H[c], s->H2[c]);
   }
   std::swap(s->psi, s->psi2);
+  s->swapped = !s->swapped;
 }
 
 template <typename T>
@@ -718,6 +726,9 @@ hipError_t collect_marks(mlk_sim* s) {
 // index in 32 bits; otherwise x is limited like y and z.  The y and z psi
 // arrays must index in 32 bits too for a full y and z extent.  The cells
 // outside the box form the CPML shell.
+// z planes per chunk of the frame launch's y slabs
+constexpr int kFrameKz = 8;
+
 Box interior_box(const Geom& g, bool layers) {
   Box inner{};
   const int n = g.n[0], ntx = (n + 63) / 64;
@@ -735,7 +746,36 @@ Box interior_box(const Geom& g, bool layers) {
   return inner;
 }
 
-Box sweep_box(const mlk_sim* s) { return interior_box(s->g, s->fp32 && s->layers); }
+Box sweep_box(const mlk_sim* s) { return interior_box(s->g, s->fp32 && s->layer_mode == 1); }
+
+// The frame launch can take the y/z layers when the fused box of the other modes
+// spans every x column (the x layers then stay in the box's own kernel) and some
+// y or z face has layers.  FP32 only (the FP64 kernel carries the x layers alone).
+bool split_ok(const mlk_sim* s) {
+  if (!s->fp32 || (!has_cpml(s->g, 1) && !has_cpml(s->g, 2))) return false;
+  const Box b = interior_box(s->g, false);
+  return b.lo[0] == 0 && b.hi[0] == s->g.n[0];
+}
+
+// The fused launch over the sim's box and the passes for the cells outside it:
+// the frame launch (layer mode 2) or the two plain shell passes.
+template <typename T>
+hipError_t sweep_passes(const mlk_sim* s, const FieldPtrs<T>& a, const FieldPtrs<T>& ar,
+                        const FieldPtrs<T>& b, const Box& inner, int kz, int ty) {
+  hipError_t e = hipSuccess;
+  if constexpr (sizeof(T) == 4) {
+    e = sweep_fused_f32(ar, b, s->g, inner, kz, ty, s->stream);
+    if (e == hipSuccess && s->layer_mode == 2 && split_ok(s))
+      return sweep_frame_f32(ar, b, s->g, inner, kFrameKz, s->stream);
+    if (e == hipSuccess) e = sweep_shell_f32(a, b, s->g, inner, true, s->stream);
+    if (e == hipSuccess) e = sweep_shell_f32(a, b, s->g, inner, false, s->stream);
+  } else {
+    e = sweep_fused_f64(ar, b, s->g, inner, kz, ty, s->stream);
+    if (e == hipSuccess) e = sweep_shell_f64(a, b, s->g, inner, true, s->stream);
+    if (e == hipSuccess) e = sweep_shell_f64(a, b, s->g, inner, false, s->stream);
+  }
+  return e;
+}
 
 // The fields as the fused sweep reads them: no 1/eps_r array in vacuum.
 template <typename T>
@@ -752,19 +792,29 @@ mlk_status sweep(mlk_sim* s) {
   if (s->desc.sweep == MLK_SWEEP_FUSED) {
     const FieldPtrs<T> nf = spare_ptrs<T>(s), fr = sweep_reads<T>(s);
     const Box inner = sweep_box(s);
-    int t0 = mark_begin(s, MLK_PHASE_SWEEP);
-    if constexpr (f32) HIPCHK(sweep_fused_f32(fr, nf, s->g, inner, s->kz, s->ty, s->stream));
-    else HIPCHK(sweep_fused_f64(fr, nf, s->g, inner, s->kz, s->ty, s->stream));
-    mark_end(s, MLK_PHASE_SWEEP, t0);
-    t0 = mark_begin(s, MLK_PHASE_SHELL);
-    if constexpr (f32) {
-      HIPCHK(sweep_shell_f32(f, nf, s->g, inner, true, s->stream));
-      HIPCHK(sweep_shell_f32(f, nf, s->g, inner, false, s->stream));
+    if (f32 && s->layer_mode == 2 && split_ok(s)) {
+      // the lean interior, then the layer frame in one launch of the full kernel
+      int t0 = mark_begin(s, MLK_PHASE_SWEEP);
+      if constexpr (f32) HIPCHK(sweep_fused_f32(fr, nf, s->g, inner, s->kz, s->ty, s->stream));
+      mark_end(s, MLK_PHASE_SWEEP, t0);
+      t0 = mark_begin(s, MLK_PHASE_SHELL);
+      if constexpr (f32) HIPCHK(sweep_frame_f32(fr, nf, s->g, inner, kFrameKz, s->stream));
+      mark_end(s, MLK_PHASE_SHELL, t0);
     } else {
-      HIPCHK(sweep_shell_f64(f, nf, s->g, inner, true, s->stream));
-      HIPCHK(sweep_shell_f64(f, nf, s->g, inner, false, s->stream));
+      int t0 = mark_begin(s, MLK_PHASE_SWEEP);
+      if constexpr (f32) HIPCHK(sweep_fused_f32(fr, nf, s->g, inner, s->kz, s->ty, s->stream));
+      else HIPCHK(sweep_fused_f64(fr, nf, s->g, inner, s->kz, s->ty, s->stream));
+      mark_end(s, MLK_PHASE_SWEEP, t0);
+      t0 = mark_begin(s, MLK_PHASE_SHELL);
+      if constexpr (f32) {
+        HIPCHK(sweep_shell_f32(f, nf, s->g, inner, true, s->stream));
+        HIPCHK(sweep_shell_f32(f, nf, s->g, inner, false, s->stream));
+      } else {
+        HIPCHK(sweep_shell_f64(f, nf, s->g, inner, true, s->stream));
+        HIPCHK(sweep_shell_f64(f, nf, s->g, inner, false, s->stream));
+      }
+      mark_end(s, MLK_PHASE_SHELL, t0);
     }
-    mark_end(s, MLK_PHASE_SHELL, t0);
     swap_buffers(s);
   } else {
     Box all{};
@@ -897,6 +947,27 @@ mlk_status enqueue_cavity_steps(mlk_sim* s, int64_t nsteps) {
 void release(mlk_sim* s) {
   for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
   s->events.clear();
+  // caller-owned buffers are dropped, not freed
+  auto drop = [&](void*& p) {
+    if (p && std::find(s->borrowed.begin(), s->borrowed.end(), p) != s->borrowed.end())
+      p = nullptr;
+  };
+  for (int c = 0; c < 3; ++c) {
+    drop(s->E[c]);
+    drop(s->H[c]);
+    drop(s->E2[c]);
+    drop(s->H2[c]);
+  }
+  drop(s->psi);
+  drop(s->psi2);
+  {
+    void* t = s->d_tls_rho;
+    drop(t);
+    if (!t) s->d_tls_rho = nullptr;
+    void* m = s->d_ml_rho;
+    drop(m);
+    if (!m) s->d_ml_rho = nullptr;
+  }
   for (int c = 0; c < 3; ++c) {
     dfree(s->E[c]);
     dfree(s->H[c]);
@@ -1114,8 +1185,11 @@ mlk_status mlk_create(const mlk_grid_desc* gd, mlk_sim** out) {
   // FP32: the fused sweep takes the y and z layers when they are a small part of
   // the grid (on small, layer-heavy grids the plain shell passes are faster);
   // mlk_autotune measures both
-  s->layers = s->fp32 && (double)(s->g.nlo[1] + s->g.nhi[1]) / n[1] +
-                                 (double)(s->g.nlo[2] + s->g.nhi[2]) / n[2] <= 0.25;
+  {
+    const bool thin = (double)(s->g.nlo[1] + s->g.nhi[1]) / n[1] +
+                          (double)(s->g.nlo[2] + s->g.nhi[2]) / n[2] <= 0.25;
+    s->layer_mode = s->fp32 && thin ? 1 : 0;
+  }
   if (dalloc(&s->epsinv, s->ncell * s->esz) != hipSuccess)
     return bail(fail(MLK_ENOMEM, "eps allocation failed"));
   {
@@ -1220,6 +1294,8 @@ mlk_status mlk_add_tls(mlk_sim* s, int32_t n, const double* pos, const double* s
   if (n < 0) return fail(MLK_EINVAL, "negative count");
   if (s->host_step > 0) return fail(MLK_ESTATE, "emitters must be added before stepping");
   if (s->cav_on) return fail(MLK_ESTATE, "emitters must be added before the cavity is set");
+  if (s->states_bound)
+    return fail(MLK_ESTATE, "emitters must be added before their states are bound");
   for (int q = 0; q < n; ++q) {
     STCHK(check_emitter_geometry(s, pos + 3 * q, sigma[q]));
     const double p = rho0[3 * q], re = rho0[3 * q + 1], im = rho0[3 * q + 2];
@@ -1257,6 +1333,8 @@ mlk_status mlk_add_multilevel(mlk_sim* s, int32_t n, const int32_t* nlev, const 
   if (n < 0) return fail(MLK_EINVAL, "negative count");
   if (s->host_step > 0) return fail(MLK_ESTATE, "emitters must be added before stepping");
   if (s->cav_on) return fail(MLK_ESTATE, "emitters must be added before the cavity is set");
+  if (s->states_bound)
+    return fail(MLK_ESTATE, "emitters must be added before their states are bound");
   for (int q = 0; q < n; ++q) {
     const int L = nlev[q];
     if (L < 2 || L > kMaxLevels)
@@ -1394,6 +1472,74 @@ mlk_status mlk_add_flux_plane(mlk_sim* s, int32_t axis, int32_t index) {
   s->fp.on = 1;
   dfree(s->d_probe);
   s->series_cap = 0;
+  return MLK_OK;
+}
+
+mlk_status mlk_buffer_bytes(mlk_sim* s, size_t bytes[4]) {
+  if (!s || !bytes) return fail(MLK_EINVAL, "null argument");
+  bytes[0] = s->ncell * s->esz;
+  bytes[1] = psi_total(s->g) * s->esz;
+  bytes[2] = s->tls_gid.size() * 3 * sizeof(double);
+  bytes[3] = s->ml_gid.size() * 2 * kMaxLevels * kMaxLevels * sizeof(double);
+  return MLK_OK;
+}
+
+mlk_status mlk_get_field_set(mlk_sim* s, int32_t* set) {
+  if (!s || !set) return fail(MLK_EINVAL, "null argument");
+  *set = s->swapped ? 1 : 0;
+  return MLK_OK;
+}
+
+mlk_status mlk_bind_device_buffers(mlk_sim* s, const mlk_buffers* b) {
+  if (!s || !b) return fail(MLK_EINVAL, "null argument");
+  if (s->in_batch) return fail(MLK_ESTATE, "the sim belongs to a batch");
+  const bool fused = s->desc.sweep == MLK_SWEEP_FUSED;
+  const size_t fbytes = s->ncell * s->esz, pbytes = psi_total(s->g) * s->esz;
+  const size_t tbytes = s->tls_gid.size() * 3 * sizeof(double);
+  const size_t mbytes = s->ml_gid.size() * 2 * kMaxLevels * kMaxLevels * sizeof(double);
+  auto aligned = [](const void* p) { return ((uintptr_t)p & 15u) == 0; };
+  for (int q = 0; q < 2; ++q) {
+    for (int c = 0; c < 6; ++c)
+      if (b->field[q][c] && (!aligned(b->field[q][c]) || (q == 1 && !fused)))
+        return fail(MLK_EINVAL, "field set %d component %d: %s", q, c,
+                    q == 1 && !fused ? "the plain sweep has one field set" : "not 16-byte aligned");
+    if (b->psi[q] && (!aligned(b->psi[q]) || pbytes == 0 || (q == 1 && !fused)))
+      return fail(MLK_EINVAL, "psi set %d: no such buffer, or not 16-byte aligned", q);
+  }
+  if ((b->tls_state && (tbytes == 0 || !aligned(b->tls_state))) ||
+      (b->ml_state && (mbytes == 0 || !aligned(b->ml_state))))
+    return fail(MLK_EINVAL, "emitter state buffer without emitters, or not 16-byte aligned");
+  HIPCHK(hipSetDevice(s->desc.device));
+  STCHK(sync_sim(s));
+  // move the contents into the caller's buffer, free the library's, use the caller's
+  auto adopt = [&](void*& slot, void* dst, size_t bytes) -> mlk_status {
+    if (!dst || dst == slot) return MLK_OK;
+    if (slot && bytes) HIPCHK(hipMemcpy(dst, slot, bytes, hipMemcpyDeviceToDevice));
+    if (std::find(s->borrowed.begin(), s->borrowed.end(), slot) == s->borrowed.end()) dfree(slot);
+    slot = dst;
+    s->borrowed.push_back(dst);
+    return MLK_OK;
+  };
+  const int cur = s->swapped ? 1 : 0;
+  for (int q = 0; q < 2; ++q) {
+    const bool here = q == cur;  // set q is the one the sim reads now
+    for (int c = 0; c < 3; ++c) {
+      STCHK(adopt(here ? s->E[c] : s->E2[c], b->field[q][c], fbytes));
+      STCHK(adopt(here ? s->H[c] : s->H2[c], b->field[q][3 + c], fbytes));
+    }
+    STCHK(adopt(here ? s->psi : s->psi2, b->psi[q], pbytes));
+  }
+  if (b->tls_state) {
+    void* p = s->d_tls_rho;
+    STCHK(adopt(p, b->tls_state, tbytes));
+    s->d_tls_rho = (double*)p;
+  }
+  if (b->ml_state) {
+    void* p = s->d_ml_rho;
+    STCHK(adopt(p, b->ml_state, mbytes));
+    s->d_ml_rho = (double*)p;
+  }
+  if (b->tls_state || b->ml_state) s->states_bound = true;
   return MLK_OK;
 }
 
@@ -2708,15 +2854,7 @@ mlk_status time_fused(mlk_sim* s, int ty, int kz, double* us) {
   constexpr int kReps = 4;
   for (int r = -1; r < kReps && err == hipSuccess; ++r) {
     if (r == 0) err = hipEventRecord(e0, s->stream);
-    if constexpr (sizeof(T) == 4) {
-      if (err == hipSuccess) err = sweep_fused_f32(ar, b, s->g, inner, kz, ty, s->stream);
-      if (err == hipSuccess) err = sweep_shell_f32(a, b, s->g, inner, true, s->stream);
-      if (err == hipSuccess) err = sweep_shell_f32(a, b, s->g, inner, false, s->stream);
-    } else {
-      if (err == hipSuccess) err = sweep_fused_f64(ar, b, s->g, inner, kz, ty, s->stream);
-      if (err == hipSuccess) err = sweep_shell_f64(a, b, s->g, inner, true, s->stream);
-      if (err == hipSuccess) err = sweep_shell_f64(a, b, s->g, inner, false, s->stream);
-    }
+    if (err == hipSuccess) err = sweep_passes<T>(s, a, ar, b, inner, kz, ty);
   }
   if (err == hipSuccess) err = hipEventRecord(e1, s->stream);
   if (err == hipSuccess) err = hipEventSynchronize(e1);
@@ -2754,16 +2892,20 @@ mlk_status mlk_get_tuning(mlk_sim* s, int32_t* ty, int32_t* kz) {
 mlk_status mlk_set_sweep_layers(mlk_sim* s, int32_t on) {
   if (!s) return fail(MLK_EINVAL, "null argument");
   if (s->in_batch) return fail(MLK_ESTATE, "tune members before forming the batch");
+  if (on < 0 || on > 2) return fail(MLK_EINVAL, "layer mode %d: 0, 1 or 2", on);
   if (on && !s->fp32)
     return fail(MLK_EUNSUPPORTED, "the FP64 fused sweep leaves the y and z layers to the shell");
+  if (on == 2 && !split_ok(s))
+    return fail(MLK_EUNSUPPORTED, "the frame launch needs y or z layers and a fused box "
+                                  "spanning every x column");
   STCHK(sync_sim(s));
-  s->layers = on != 0;
+  s->layer_mode = on;
   return MLK_OK;
 }
 
 mlk_status mlk_get_sweep_layers(mlk_sim* s, int32_t* on) {
   if (!s || !on) return fail(MLK_EINVAL, "null argument");
-  *on = s->layers ? 1 : 0;
+  *on = s->layer_mode;
   return MLK_OK;
 }
 
@@ -2777,7 +2919,7 @@ mlk_status mlk_autotune(mlk_sim* s, const char* cache_path) {
     if (e.key == key && (e.ty == 4 || e.ty == 8 || e.ty == 16) && e.kz > 0) {
       s->ty = e.ty;
       s->kz = e.kz;
-      s->layers = s->fp32 && e.layers != 0;
+      s->layer_mode = !s->fp32 ? 0 : (e.layers == 2 && !split_ok(s) ? 1 : e.layers);
       return MLK_OK;
     }
   HIPCHK(hipSetDevice(s->desc.device));
@@ -2789,8 +2931,9 @@ mlk_status mlk_autotune(mlk_sim* s, const char* cache_path) {
     double us;
   };
   std::vector<Cand> cands;
-  for (int lay = 0; lay <= (s->fp32 ? 1 : 0); ++lay) {
-    s->layers = lay != 0;
+  for (int lay = 0; lay <= (s->fp32 ? 2 : 0); ++lay) {
+    if (lay == 2 && !split_ok(s)) continue;
+    s->layer_mode = lay;
     const Box inner = sweep_box(s);
     const int ez = inner.hi[2] - inner.lo[2];
     if (ez <= 0) continue;
@@ -2801,7 +2944,7 @@ mlk_status mlk_autotune(mlk_sim* s, const char* cache_path) {
   for (int round = 0; round < 3; ++round)
     for (Cand& c : cands) {
       double us = 0.0;
-      s->layers = c.layers != 0;
+      s->layer_mode = c.layers;
       STCHK(s->fp32 ? time_fused<float>(s, c.ty, c.kz, &us)
                     : time_fused<double>(s, c.ty, c.kz, &us));
       c.us = std::min(c.us, us);
@@ -2815,7 +2958,7 @@ mlk_status mlk_autotune(mlk_sim* s, const char* cache_path) {
       bty = c.ty;
       bkz = c.kz;
     }
-  s->layers = blay != 0;
+  s->layer_mode = blay;
   s->ty = bty;
   s->kz = bkz;
   if (cache_path) {
@@ -2891,7 +3034,7 @@ std::string batch_key(const mlk_batch* b) {
 
 void set_members(mlk_batch* b, int layers, int ty, int kz) {
   for (mlk_sim* s : b->sims) {
-    s->layers = b->fp32 && layers != 0;
+    s->layer_mode = b->fp32 && layers != 0 ? 1 : 0;
     s->ty = ty;
     s->kz = kz;
   }

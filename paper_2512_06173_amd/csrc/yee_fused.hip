@@ -38,7 +38,10 @@
 
 namespace mlk {
 
-template <typename T, int TY>
+// CPM: the CPML code compiled in: 0 none, 1 the x layers, 2 every axis (FP32; the
+// FP64 kernel carries the x layers only).  Fewer layers, fewer registers: about 71
+// VGPRs without any in FP32, against 118 with all of them.
+template <typename T, int TY, int CPM = 2>
 __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtrs<T>& b,
                                            const Geom& g, const Box& box, int kz, int ntx,
                                            int nty, int nblocks, int bid_in) {
@@ -55,12 +58,29 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
   __shared__ T xc[2][3][64];  // x CPML b, c, 1/kappa of the tile's columns (E, H positions)
   __shared__ T yc[2][3][TY + 1];  // y CPML b, c, 1/kappa of rows y0-1 .. y0+TY-1
 
-  // XCD-aware tile order: consecutive blocks go to different XCDs; map the
-  // blocks one XCD receives onto a contiguous range of tiles.
-  int bid = bid_in;
-  const int q8 = nblocks / 8;
-  if (bid < 8 * q8) bid = (bid % 8) * q8 + bid / 8;
-  const int tile_x = bid % ntx, tile_y = (bid / ntx) % nty, chunk = bid / (ntx * nty);
+  int tile_x, tile_y, chunk;
+  if (CPM == 2 && sizeof(T) == 4 && (has_cpml(g, 1) || has_cpml(g, 2))) {
+    // Heaviest first: the workgroups whose rows or planes lie in the y or z layers
+    // carry the psi traffic and arithmetic and take longest.  Dispatched first (y
+    // tiles from the two edges inwards, then within each the z chunks likewise), the
+    // lighter ones fill in behind them instead of the launch waiting on a few heavy
+    // workgroups at its end.
+    auto fold = [](int q, int n) { return (q & 1) ? n - 1 - (q >> 1) : (q >> 1); };
+    const int nch = nblocks / (ntx * nty);
+    tile_x = bid_in % ntx;
+    const int r = bid_in / ntx;
+    chunk = fold(r % nch, nch);
+    tile_y = fold(r / nch, nty);
+  } else {
+    // XCD-aware tile order: consecutive blocks go to different XCDs; map the
+    // blocks one XCD receives onto a contiguous range of tiles.
+    int bid = bid_in;
+    const int q8 = nblocks / 8;
+    if (bid < 8 * q8) bid = (bid % 8) * q8 + bid / 8;
+    tile_x = bid % ntx;
+    tile_y = (bid / ntx) % nty;
+    chunk = bid / (ntx * nty);
+  }
   // x tiles start on a 128-byte boundary at or below the box; the extra cells
   // below box.lo[0] are updated too (they belong to the CPML shell, whose own
   // pass overwrites them)
@@ -104,8 +124,8 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
   // + c d, d <- d / kappa + psi.  The coefficients of the tile's columns sit in
   // LDS; psi (one array per field component, x compressed to the layers) is
   // read at plane k through a 32-bit index (32-bit range checked on the host).
-  const bool xl = has_cpml(g, 0) && i >= box.lo[0] && i < box.hi[0] && j < box.hi[1] &&
-                  in_layer(g, 0, i);
+  const bool xl = CPM >= 1 && has_cpml(g, 0) && i >= box.lo[0] && i < box.hi[0] &&
+                  j < box.hi[1] && in_layer(g, 0, i);
   const unsigned nl = (unsigned)(g.nlo[0] + g.nhi[0]);
   const unsigned nlny = nl * (unsigned)g.n[1];
   const size_t P = (size_t)nlny * (unsigned)g.n[2];  // psi values per component array
@@ -117,7 +137,7 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
   // size + cell; range checked on the host), and the coefficients of a row or
   // plane are uniform loads.
   // (FP32 only: the FP64 kernel's box keeps clear of the y and z layers)
-  constexpr bool YZ = sizeof(T) == 4;
+  constexpr bool YZ = CPM == 2 && sizeof(T) == 4;
   const bool yl = YZ && has_cpml(g, 1) && j < g.n[1] && in_layer(g, 1, j);
   const bool yhl = YZ && has_cpml(g, 1) && in_layer(g, 1, jh);
   auto zlay = [&](int k) { return YZ && has_cpml(g, 2) && in_layer(g, 2, k); };
@@ -460,6 +480,26 @@ __global__ __launch_bounds__(64 * TY, 4) void k_fused(FieldPtrs<T> a, FieldPtrs<
   fused_body<T, TY>(a, b, g, box, kz, ntx, nty, nblocks, blockIdx.x);
 }
 
+// Boxes where no y or z layer needs stretching (x layers at most): the same body
+// without the y/z layer code, built for more waves per SIMD.
+template <typename T, int TY, int CPM, int W>
+__global__ __launch_bounds__(64 * TY, W) void k_fused_lean(FieldPtrs<T> a, FieldPtrs<T> b, Geom g,
+                                                        Box box, int kz, int ntx, int nty,
+                                                        int nblocks) {
+  fused_body<T, TY, CPM>(a, b, g, box, kz, ntx, nty, nblocks, blockIdx.x);
+}
+
+// The frame of y and z layers around such a box, up to four boxes in one launch
+// (full kernel, TY = 4): block b belongs to the job whose start range holds it.
+template <typename T>
+__global__ __launch_bounds__(256, 4) void k_fused_frame(FrameJobs<T> fj) {
+  int j = 0;
+  while (j + 1 < fj.njobs && (int)blockIdx.x >= fj.start[j + 1]) ++j;
+  const FusedJob<T>& J = fj.job[j];
+  fused_body<T, 4>(J.a, J.b, J.g, J.box, J.kz, J.ntx, J.nty, J.nblocks,
+                   (int)blockIdx.x - fj.start[j]);
+}
+
 // One launch over the jobs of a batch of domains (see BatchJobs).
 template <typename T, int TY>
 __global__ __launch_bounds__(64 * TY, 4) void k_fused_batch(const FusedJob<T>* jobs,
@@ -471,16 +511,36 @@ __global__ __launch_bounds__(64 * TY, 4) void k_fused_batch(const FusedJob<T>* j
   fused_body<T, TY>(J.a, J.b, J.g, J.box, J.kz, J.ntx, J.nty, J.nblocks, bid);
 }
 
+// Waves per SIMD the lean kernel is built for (registers permitting): with no CPML
+// code it needs about 71 VGPRs in FP32, so blocks of 256 or 512 threads run six or
+// more waves per SIMD against four for the full kernel.
+// Waves per SIMD the lean kernels are built for: FP32 without layer code needs about
+// 71 VGPRs (six waves), with the x layers 87 (five); FP64 and 1024-thread blocks four.
+template <typename T, int TY, int CPM>
+struct LeanWaves {
+  static constexpr int value = (sizeof(T) == 4 && TY < 16) ? (CPM == 0 ? 6 : 5) : 4;
+};
+
+// cpm: 0 no layer code (no CPML face), 1 x layers only (the box keeps clear of the y
+// and z layers), 2 the full kernel
 template <typename T, int TY>
 static hipError_t launch_fused(const FieldPtrs<T>& a, const FieldPtrs<T>& b, const Geom& g,
-                               const Box& box, int kz, hipStream_t st) {
+                               const Box& box, int kz, int cpm, hipStream_t st) {
   const int ex = box.hi[0] - box.lo[0], ey = box.hi[1] - box.lo[1], ez = box.hi[2] - box.lo[2];
   if (ex <= 0 || ey <= 0 || ez <= 0) return hipSuccess;
   const int ntx = (box.hi[0] - (box.lo[0] & ~31) + 63) / 64, nty = (ey + TY - 1) / TY;
   const int nch = (ez + kz - 1) / kz;
   const int nblocks = ntx * nty * nch;
-  hipLaunchKernelGGL((k_fused<T, TY>), dim3(nblocks), dim3(64 * TY), 0, st, a, b, g, box, kz, ntx,
-                     nty, nblocks);
+  constexpr int W0 = LeanWaves<T, TY, 0>::value, W1 = LeanWaves<T, TY, 1>::value;
+  if (cpm == 0)
+    hipLaunchKernelGGL((k_fused_lean<T, TY, 0, W0>), dim3(nblocks), dim3(64 * TY), 0, st, a, b,
+                       g, box, kz, ntx, nty, nblocks);
+  else if (cpm == 1)
+    hipLaunchKernelGGL((k_fused_lean<T, TY, 1, W1>), dim3(nblocks), dim3(64 * TY), 0, st, a, b,
+                       g, box, kz, ntx, nty, nblocks);
+  else
+    hipLaunchKernelGGL((k_fused<T, TY>), dim3(nblocks), dim3(64 * TY), 0, st, a, b, g, box, kz,
+                       ntx, nty, nblocks);
   return hipGetLastError();
 }
 
@@ -501,12 +561,70 @@ void fused_job_shape(FusedJob<T>& J) {
 template void fused_job_shape<float>(FusedJob<float>&);
 template void fused_job_shape<double>(FusedJob<double>&);
 
+// The leanest kernel that covers the box: none of the layer code when no CPML
+// layer reaches it (a halo cell included), the x layers alone when the y and z
+// layers stay clear, else everything.
+template <typename T>
+int fused_cpm(const Geom& g, const Box& box) {
+  auto clear = [&](int a) {
+    if (!has_cpml(g, a)) return true;
+    const int lo = g.nlo[a] > 0 ? g.nlo[a] + 1 : 0, hi = g.n[a] - g.nhi[a];
+    return box.lo[a] >= lo && box.hi[a] <= hi;
+  };
+  if (!clear(1) || !clear(2)) return 2;
+  return has_cpml(g, 0) ? 1 : 0;
+}
+
 template <typename T>
 static hipError_t launch_fused_any(const FieldPtrs<T>& a, const FieldPtrs<T>& b, const Geom& g,
                                    const Box& box, int kz, int ty, hipStream_t st) {
-  if (ty == 16) return launch_fused<T, 16>(a, b, g, box, kz, st);
-  if (ty == 8) return launch_fused<T, 8>(a, b, g, box, kz, st);
-  return launch_fused<T, 4>(a, b, g, box, kz, st);
+  const int cpm = fused_cpm<T>(g, box);
+  if (ty == 16) return launch_fused<T, 16>(a, b, g, box, kz, cpm, st);
+  if (ty == 8) return launch_fused<T, 8>(a, b, g, box, kz, cpm, st);
+  return launch_fused<T, 4>(a, b, g, box, kz, cpm, st);
+}
+
+// The y/z layer frame around an interior box: up to four boxes (the z slabs over
+// the whole x-y plane, the y slabs over the box's z range), one launch of the full
+// kernel with TY = 4.  The slabs are thin, so their chunks are short to give the
+// launch enough workgroups: kz planes in the y slabs, four in the z slabs.
+template <typename T>
+static hipError_t launch_frame(const FieldPtrs<T>& a, const FieldPtrs<T>& b, const Geom& g,
+                               const Box& inner, int kz, hipStream_t st) {
+  FrameJobs<T> fj{};
+  Box boxes[4];
+  int nb = 0;
+  auto add = [&](int x0, int y0, int z0, int x1, int y1, int z1) {
+    if (x1 <= x0 || y1 <= y0 || z1 <= z0) return;
+    Box& bx = boxes[nb++];
+    bx.lo[0] = x0; bx.lo[1] = y0; bx.lo[2] = z0;
+    bx.hi[0] = x1; bx.hi[1] = y1; bx.hi[2] = z1;
+  };
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  add(0, 0, 0, nx, ny, inner.lo[2]);
+  add(0, 0, inner.hi[2], nx, ny, nz);
+  add(0, 0, inner.lo[2], nx, inner.lo[1], inner.hi[2]);
+  add(0, inner.hi[1], inner.lo[2], nx, ny, inner.hi[2]);
+  int total = 0;
+  for (int q = 0; q < nb; ++q) {
+    FusedJob<T>& J = fj.job[fj.njobs];
+    J.a = a;
+    J.b = b;
+    J.g = g;
+    J.box = boxes[q];
+    J.ty = 4;
+    const int ez = boxes[q].hi[2] - boxes[q].lo[2];
+    J.kz = std::max(1, std::min(q < 2 ? 4 : kz, ez));
+    fused_job_shape(J);
+    if (J.nblocks <= 0) continue;
+    fj.start[fj.njobs] = total;
+    total += J.nblocks;
+    ++fj.njobs;
+  }
+  fj.start[fj.njobs] = total;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fused_frame<T>, dim3(total), dim3(256), 0, st, fj);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -529,6 +647,14 @@ hipError_t sweep_fused_f64(const FieldPtrs<double>& a, const FieldPtrs<double>& 
 hipError_t sweep_fused_f32(const FieldPtrs<float>& a, const FieldPtrs<float>& b, const Geom& g,
                            const Box& box, int kz, int ty, hipStream_t st) {
   return launch_fused_any<float>(a, b, g, box, kz, ty, st);
+}
+hipError_t sweep_frame_f64(const FieldPtrs<double>& a, const FieldPtrs<double>& b, const Geom& g,
+                           const Box& inner, int kz, hipStream_t st) {
+  return launch_frame<double>(a, b, g, inner, kz, st);
+}
+hipError_t sweep_frame_f32(const FieldPtrs<float>& a, const FieldPtrs<float>& b, const Geom& g,
+                           const Box& inner, int kz, hipStream_t st) {
+  return launch_frame<float>(a, b, g, inner, kz, st);
 }
 hipError_t sweep_fused_batch_f64(const FusedJob<double>* jobs, const int* start, int njobs,
                                  int nblocks, int ty, hipStream_t st) {

@@ -57,6 +57,12 @@ _ip = C.POINTER(C.c_int32)
 _lp = C.POINTER(C.c_int64)
 
 
+class Buffers(C.Structure):
+    """mlk_buffers: caller-owned device memory for the evolving state."""
+    _fields_ = [("field", (C.c_void_p * 6) * 2), ("psi", C.c_void_p * 2),
+                ("tls_state", C.c_void_p), ("ml_state", C.c_void_p)]
+
+
 class Objective(C.Structure):
     _fields_ = [("kind", C.c_int32), ("weights", C.c_void_p)]
 
@@ -134,6 +140,11 @@ def lib():
         "mlk_get_tuning": (st, [sim, _ip, _ip]),
         "mlk_set_sweep_layers": (st, [sim, C.c_int32]),
         "mlk_get_sweep_layers": (st, [sim, _ip]),
+        "mlk_stream_copy": (st, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32, C.c_int32,
+                                 C.c_void_p]),
+        "mlk_buffer_bytes": (st, [sim, C.POINTER(C.c_size_t)]),
+        "mlk_bind_device_buffers": (st, [sim, C.POINTER(Buffers)]),
+        "mlk_get_field_set": (st, [sim, _ip]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(L, name)
@@ -158,7 +169,8 @@ def exported_symbols():
             "mlk_batch_replay", "mlk_batch_sync", "mlk_batch_destroy", "mlk_batch_autotune",
             "mlk_autotune",
             "mlk_set_tuning", "mlk_get_tuning", "mlk_set_sweep_layers", "mlk_get_sweep_layers", "mlk_adjoint", "mlk_set_eps_box",
-            "mlk_set_tls_dipoles", "mlk_get_adjoint_times"]
+            "mlk_set_tls_dipoles", "mlk_get_adjoint_times", "mlk_stream_copy",
+            "mlk_buffer_bytes", "mlk_bind_device_buffers", "mlk_get_field_set"]
 
 
 def _check(st):
@@ -185,6 +197,15 @@ def current_stream_handle():
     """HIP stream of torch's current stream on the current device (ROCm build)."""
     import torch
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def stream_copy(src, dst, variant=1, blocks=4096):
+    """Calibration copy of the bytes of torch tensor src into dst (same size, device
+    memory) on torch's current stream (mlk_stream_copy)."""
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    _check(lib().mlk_stream_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes,
+                                 int(variant), int(blocks), current_stream_handle()))
 
 
 class Simulation:
@@ -215,6 +236,8 @@ class Simulation:
         self._h = h
         self.shape = (d.nx, d.ny, d.nz)
         self.precision = precision
+        self.fused = d.sweep == SWEEP["fused"]
+        self._bound = None
         self.dt = courant * dx
         self.nlev = []
         self.n_tls = 0  # two-level emitters (mlk_add_tls), in id order
@@ -244,6 +267,58 @@ class Simulation:
         return nx * ny * nz
 
     # ------------------------------------------------------------ set-up
+    # ------------------------------------------------------------ caller memory
+    def buffer_bytes(self):
+        """Bytes of one field array, one psi set, the two-level and multilevel states."""
+        v = (C.c_size_t * 4)()
+        _check(lib().mlk_buffer_bytes(self._h, v))
+        return tuple(int(x) for x in v)
+
+    def bind_torch(self, fields=True, psi=True, states=True):
+        """Back the evolving state with torch tensors on the sim's device (allocated
+        here, kept referenced by the sim): field sets, CPML state and emitter states
+        (mlk_bind_device_buffers).  Bind the emitter states after the last emitter is
+        added.  Returns the dict of tensors."""
+        import torch
+        fb, pb, tb, mb = self.buffer_bytes()
+        dt = torch.float32 if self.precision == "fp32" else torch.float64
+        esz = 4 if self.precision == "fp32" else 8
+        b = Buffers()
+        out = {"field": [[None] * 6 for _ in range(2)], "psi": [None, None], "tls": None,
+               "ml": None}
+        sets = 2 if self.fused else 1
+        for q in range(sets):
+            if fields:
+                for c in range(6):
+                    t = torch.empty(fb // esz, dtype=dt, device="cuda")
+                    out["field"][q][c] = t
+                    b.field[q][c] = t.data_ptr()
+            if psi and pb:
+                t = torch.empty(pb // esz, dtype=dt, device="cuda")
+                out["psi"][q] = t
+                b.psi[q] = t.data_ptr()
+        if states and tb:
+            out["tls"] = torch.empty(tb // 8, dtype=torch.float64, device="cuda")
+            b.tls_state = out["tls"].data_ptr()
+        if states and mb:
+            out["ml"] = torch.empty(mb // 8, dtype=torch.float64, device="cuda")
+            b.ml_state = out["ml"].data_ptr()
+        torch.cuda.synchronize()
+        _check(lib().mlk_bind_device_buffers(self._h, C.byref(b)))
+        self._bound = out
+        return out
+
+    def field_set(self):
+        v = np.zeros(1, dtype=np.int32)
+        _check(lib().mlk_get_field_set(self._h, v.ctypes.data_as(_ip)))
+        return int(v[0])
+
+    def field_tensor(self, comp):
+        """The bound torch tensor holding the current values of component comp (0..5),
+        shaped (nz, ny, nx)."""
+        nx, ny, nz = self.shape
+        return self._bound["field"][self.field_set()][comp].view(nz, ny, nx)
+
     def set_eps(self, eps):
         a, p = _d(np.asarray(eps, dtype=np.float64).ravel())
         _check(lib().mlk_set_eps(self._h, p, MEM_HOST))
@@ -524,13 +599,15 @@ class Simulation:
         _check(lib().mlk_set_tuning(self._h, int(ty), int(kz)))
 
     def sweep_layers(self):
-        """Whether the fused sweep updates the y and z CPML layers itself (FP32)."""
+        """Where the fused sweep updates the y and z CPML layers (FP32): 0 the plain shell
+        passes, 1 the fused kernel itself, 2 one launch of the full kernel over the layer
+        frame around a box that the lean kernel sweeps."""
         on = C.c_int32()
         _check(lib().mlk_get_sweep_layers(self._h, C.byref(on)))
-        return bool(on.value)
+        return on.value
 
-    def set_sweep_layers(self, on):
-        _check(lib().mlk_set_sweep_layers(self._h, 1 if on else 0))
+    def set_sweep_layers(self, mode):
+        _check(lib().mlk_set_sweep_layers(self._h, int(mode)))
 
 
 class Batch:
