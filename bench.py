@@ -60,6 +60,8 @@ def parse():
                    help="only the leg with a Lorentz pole block (profiling runs; needs --tile)")
     p.add_argument("--cavity-only", action="store_true",
                    help="only the leg with the emitters in one cavity mode (profiling runs)")
+    p.add_argument("--batch-only", action="store_true",
+                   help="only the 64-domain batch leg (profiling runs)")
     p.add_argument("--tile", type=lambda v: tuple(int(x) for x in v.split(",")), default=None,
                    help="fused tile TY,KZ instead of autotuning (profiling runs)")
     return p.parse_args()
@@ -350,6 +352,9 @@ def main():
     mlk.lib()
 
     w = W.radiating_cube(n=args.n, n_emit=args.emitters)
+    if args.batch_only:
+        print(json.dumps({"batch": batch_leg(max(100, args.steps))}), flush=True)
+        return
     if args.cavity_only:
         print(json.dumps({"cavity": cavity_leg(w, args.steps)}), flush=True)
         return

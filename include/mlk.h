@@ -232,6 +232,19 @@ mlk_status mlk_step(mlk_sim* s, int64_t nsteps);
  * EINVAL: negative nsteps, bad mem_kind, null Et (with emitters, nsteps > 0). */
 mlk_status mlk_step_prescribed(mlk_sim* s, int64_t nsteps, const double* Et, int32_t mem_kind,
                                double* tls_out);
+/* Classical-path steps under a travelling pulse evaluated on the device (eq.
+ * E_analytical: a waveform of z - ct, propagating along +z, c = 1): over the q-th
+ * step (q = 0 .. nsteps-1), centred at t = t_start + q dt, emitter m at height z_m
+ * (its centre, cell units) sees
+ *   E~_m = gamma_m amp f(t - (z_m - z0)) pol,
+ *   f(u) = cos(omega (u - t0)) exp(-(u - t0)^2 / (2 tau^2))   (the pulse of App. B),
+ * with no grid and no back-action; the states advance exactly as in
+ * mlk_step_prescribed.  tls_out (host, nullable): the two-level states after every
+ * step, nsteps x ntls x 3 doubles.  EINVAL: non-finite parameters, tau <= 0.
+ * Returns when tls_out is filled; otherwise asynchronous. */
+mlk_status mlk_step_prescribed_wave(mlk_sim* s, int64_t nsteps, const double pol[3], double amp,
+                                    double omega, double tau, double t0, double z0,
+                                    double t_start, double* tls_out);
 /* The same classical-path steps for callers that cannot allocate device memory
  * (tight driver loops, code that forbids hipMalloc): with host buffers the field
  * and the recorded states pass through a fixed 16 MiB staging array on each device

@@ -1057,6 +1057,22 @@ void ora_emitters_step_prescribed(ora_sim* s, const double* Et) {
   }
 }
 
+/* Classical-path step under a travelling pulse (eq. E_analytical, propagation along
+ * +z at c = 1): emitter m at height z_m sees, over the step centred at time t,
+ * E~_m = gamma_m amp f(t - (z_m - z0)) pol with the Gaussian pulse of App. B,
+ * f(u) = cos(omega (u - t0)) exp(-(u - t0)^2 / (2 tau^2)). */
+void ora_emitters_step_wave(ora_sim* s, const double* pol, double amp, double omega, double tau,
+                            double t0, double z0, double t) {
+#pragma omp parallel for schedule(static)
+  for (int m = 0; m < s->nem; ++m) {
+    ora_emitter* e = &s->em[m];
+    double u = t - (e->pos[2] - z0) - t0;
+    double f = amp * cos(omega * u) * exp(-u * u / (2.0 * tau * tau));
+    for (int c = 0; c < 3; ++c) e->Et[c] = e->gamma * f * pol[c];
+    emitter_advance(s, e);
+  }
+}
+
 /* Gather of the current E into E~ (M x 3). */
 void ora_gather(ora_sim* s, double* Et) {
 #pragma omp parallel for schedule(static)

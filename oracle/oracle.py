@@ -85,6 +85,8 @@ def lib():
     L.ora_step.argtypes = [C.c_void_p, C.c_int64]
     L.ora_jacobi_eig.argtypes = [C.c_int, _dp, _dp, _dp]
     L.ora_emitters_step_prescribed.argtypes = [C.c_void_p, _dp]
+    L.ora_emitters_step_wave.argtypes = [C.c_void_p, _dp, C.c_double, C.c_double, C.c_double,
+                                         C.c_double, C.c_double, C.c_double]
     L.ora_set_cavity.argtypes = [C.c_void_p, C.c_double, C.c_double, _dp, _dp]
     L.ora_set_cavity.restype = C.c_int
     L.ora_get_cavity.argtypes = [C.c_void_p, _dp]
@@ -387,6 +389,11 @@ class Oracle:
         M = len(self.nlev)
         lib().ora_emitters_step_prescribed(self._h, _f64(Et, (M, 3)).ravel())
 
+
+    def emitters_step_wave(self, pol, amp, omega, tau, t0, z0, t):
+        """One classical-path step of every emitter under the travelling pulse
+        amp f(t - (z_m - z0)) pol (eq. E_analytical), the step centred at time t."""
+        lib().ora_emitters_step_wave(self._h, _f64(pol, (3,)), amp, omega, tau, t0, z0, t)
     def dipole_rate_trace(self, m, Et):
         out = np.zeros(3)
         lib().ora_dipole_rate_trace(self._h, m, _f64(Et, (3,)), out)

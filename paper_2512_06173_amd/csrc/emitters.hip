@@ -203,4 +203,27 @@ hipError_t scatter_atomic_f32(const FieldPtrs<float>& f, const Geom& g,
   return launch_scatter_atomic<float>(f, g, win, count, mudot, st);
 }
 
+// Classical-path field of a travelling pulse (eq. E_analytical, +z at c = 1): the
+// emitter at height z sees gamma amp f(t - (z - z0)) pol over the step centred at
+// t, with the Gaussian pulse of App. B, f(u) = cos(omega (u - t0)) exp(-(u - t0)^2 /
+// (2 tau^2)).  One thread per emitter (id order).
+__global__ void k_wave_field(int M, const double* pos, const double* gamma, WaveDesc w, double t,
+                             double* Et) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M) return;
+  const double u = t - (pos[3 * (size_t)e + 2] - w.z0) - w.t0;
+  const double f = gamma[e] * w.amp * cos(w.omega * u) * exp(-u * u / (2.0 * w.tau * w.tau));
+  Et[3 * (size_t)e] = f * w.pol[0];
+  Et[3 * (size_t)e + 1] = f * w.pol[1];
+  Et[3 * (size_t)e + 2] = f * w.pol[2];
+}
+
+hipError_t wave_field(int M, const double* pos, const double* gamma, const WaveDesc& w, double t,
+                      double* Et, hipStream_t st) {
+  if (M <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_wave_field, dim3((M + 255) / 256), dim3(256), 0, st, M, pos, gamma, w, t,
+                     Et);
+  return hipGetLastError();
+}
+
 }  // namespace mlk

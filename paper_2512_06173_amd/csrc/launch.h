@@ -21,6 +21,9 @@ hipError_t sweep_shell_f64(const FieldPtrs<double>& in, const FieldPtrs<double>&
 hipError_t sweep_shell_f32(const FieldPtrs<float>& in, const FieldPtrs<float>& out, const Geom& g,
                            const Box& inner, bool h_pass, hipStream_t st);
 // Two-level step of every two-level emitter under E~ (M x 3, emitter-id order).
+// E~ of every emitter (id order) under the travelling pulse at time t.
+hipError_t wave_field(int M, const double* pos, const double* gamma, const WaveDesc& w, double t,
+                      double* Et, hipStream_t st);
 hipError_t tls_step(const TlsPtrs& tls, double dt, const double* Et, double* mudot,
                     const int64_t* pop_off, const Series& ser, const int64_t* step,
                     hipStream_t st);

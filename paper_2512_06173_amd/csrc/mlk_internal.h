@@ -223,6 +223,12 @@ struct FluxPlane {
   double* total;    // running dt * sum F
 };
 
+// Travelling pulse of the classical-path mode: amp f(t - (z - z0)) pol.
+struct WaveDesc {
+  double pol[3];
+  double amp, omega, tau, t0, z0;
+};
+
 // Discrete field energy W^n, recorded every `every` steps (0: off).
 struct EnergyRec {
   int every;

@@ -1655,6 +1655,57 @@ mlk_status prescribed_args(mlk_sim* s, int64_t nsteps, const double* Et, int32_t
 
 extern "C" {
 
+mlk_status mlk_step_prescribed_wave(mlk_sim* s, int64_t nsteps, const double pol[3], double amp,
+                                    double omega, double tau, double t0, double z0,
+                                    double t_start, double* tls_out) {
+  if (!pol) return fail(MLK_EINVAL, "null polarisation");
+  for (double v : {pol[0], pol[1], pol[2], amp, omega, t0, z0, t_start})
+    if (!std::isfinite(v)) return fail(MLK_EINVAL, "non-finite pulse parameter");
+  if (!(tau > 0.0) || !std::isfinite(tau)) return fail(MLK_EINVAL, "tau must be > 0");
+  bool go = false;
+  STCHK(prescribed_args(s, nsteps, pol, MLK_MEM_HOST, &go));
+  if (!go) return MLK_OK;
+  const size_t nt = s->tls_gid.size();
+  const TlsPtrs tls = tls_ptrs(s);
+  const MlDev ml = ml_dev(s);
+  Series ser = series_of(s);
+  ser.pop_every = 0;  // no series: the step counter does not move
+  WaveDesc w{};
+  for (int c = 0; c < 3; ++c) w.pol[c] = pol[c];
+  w.amp = amp;
+  w.omega = omega;
+  w.tau = tau;
+  w.t0 = t0;
+  w.z0 = z0;
+  // recorded states go through device staging of at most about 64 MB at a time
+  const int64_t K = tls_out && nt ? std::max<int64_t>(1, std::min<int64_t>(
+                                        nsteps, (int64_t)((64u << 20) / (24 * nt))))
+                                  : nsteps;
+  DevBuf<double> stage;
+  if (tls_out && nt) HIPCHK(stage.alloc((size_t)K * 3 * nt));
+  for (int64_t c0 = 0; c0 < nsteps; c0 += K) {
+    const int64_t kc = std::min(K, nsteps - c0);
+    for (int64_t q = 0; q < kc; ++q) {
+      const double t = t_start + (double)(c0 + q) * s->g.dt;
+      HIPCHK(wave_field(s->nem, s->d_pos, s->d_gamma, w, t, s->d_Et, s->stream));
+      HIPCHK(tls_step(tls, s->g.dt, s->d_Et, s->d_mudot, s->d_popoff, ser, s->d_step, s->stream));
+      if (ml.count > 0)
+        HIPCHK(ml_step(ml, s->ml_range, s->g.dt, s->d_Et, s->d_mudot, s->d_popoff, ser,
+                       s->d_step, s->stream));
+      if (stage.p)
+        HIPCHK(hipMemcpyAsync(stage.p + (size_t)q * 3 * nt, s->d_tls_rho, 3 * nt * sizeof(double),
+                              hipMemcpyDeviceToDevice, s->stream));
+    }
+    if (stage.p) {
+      HIPCHK(hipMemcpyAsync(tls_out + (size_t)c0 * 3 * nt, stage.p,
+                            (size_t)kc * 3 * nt * sizeof(double), hipMemcpyDeviceToHost,
+                            s->stream));
+      HIPCHK(hipStreamSynchronize(s->stream));
+    }
+  }
+  return MLK_OK;
+}
+
 mlk_status mlk_step_prescribed(mlk_sim* s, int64_t nsteps, const double* Et, int32_t mem_kind,
                                double* tls_out) {
   bool go = false;

@@ -127,6 +127,9 @@ def lib():
         "mlk_step_prescribed": (st, [sim, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p]),
         "mlk_step_prescribed_noalloc": (st, [sim, C.c_int64, C.c_void_p, C.c_int32,
                                              C.c_void_p]),
+        "mlk_step_prescribed_wave": (st, [sim, C.c_int64, _dp, C.c_double, C.c_double,
+                                          C.c_double, C.c_double, C.c_double, C.c_double,
+                                          C.c_void_p]),
         "mlk_set_cavity": (st, [sim, C.c_double, C.c_double, _dp, _dp]),
         "mlk_get_cavity": (st, [sim, _dp]),
         "mlk_add_susceptibility": (st, [sim, _ip, C.c_double, C.c_double, C.c_double, C.c_int32]),
@@ -160,7 +163,7 @@ def exported_symbols():
             "mlk_set_eps", "mlk_set_field", "mlk_add_tls", "mlk_add_multilevel",
             "mlk_add_plane_source", "mlk_add_point_source", "mlk_add_probe", "mlk_add_flux_plane",
             "mlk_record_populations", "mlk_record_energy", "mlk_step", "mlk_step_prescribed",
-            "mlk_step_prescribed_noalloc",
+            "mlk_step_prescribed_noalloc", "mlk_step_prescribed_wave",
             "mlk_set_cavity", "mlk_get_cavity", "mlk_add_susceptibility", "mlk_sync", "mlk_step_count", "mlk_get_field",
             "mlk_get_rho", "mlk_get_tls_state", "mlk_get_emitter_io", "mlk_get_series",
             "mlk_get_flux_total", "mlk_checkpoint_size", "mlk_checkpoint_save",
@@ -405,6 +408,18 @@ class Simulation:
         allocates no device memory."""
         return self._prescribed(lib().mlk_step_prescribed_noalloc, Et, record)
 
+    def step_wave(self, nsteps, pol, amp, omega, tau, t0, z0=0.0, t_start=0.0, record=False):
+        """Classical-path steps under the travelling pulse amp f(t - (z - z0)) pol of eq.
+        E_analytical, evaluated on the device; returns the recorded two-level states
+        (nsteps, ntls, 3) with record."""
+        p = np.ascontiguousarray(np.asarray(pol, dtype=np.float64).reshape(3))
+        out = np.zeros((int(nsteps), self.n_tls, 3)) if record else None
+        _check(lib().mlk_step_prescribed_wave(
+            self._h, int(nsteps), p.ctypes.data_as(_dp), float(amp), float(omega), float(tau),
+            float(t0), float(z0), float(t_start),
+            out.ctypes.data_as(C.c_void_p) if record and self.n_tls else None))
+        return out
+
     def _prescribed(self, fn, Et, record):
         M = len(self.nlev)
         E = np.ascontiguousarray(np.asarray(Et, dtype=np.float64).reshape(-1, M, 3))
@@ -510,6 +525,35 @@ class Simulation:
         buf = np.zeros(self.checkpoint_size(), dtype=np.uint8)
         _check(lib().mlk_checkpoint_save(self._h, buf.ctypes.data_as(C.c_void_p), MEM_HOST))
         return buf
+
+    def checkpoint_save_device(self):
+        """The checkpoint in a torch uint8 tensor on the GPU (no host copy)."""
+        import torch
+        t = torch.empty(self.checkpoint_size(), dtype=torch.uint8, device="cuda")
+        _check(lib().mlk_checkpoint_save(self._h, C.c_void_p(t.data_ptr()), MEM_DEVICE))
+        return t
+
+    def checkpoint_load_device(self, t):
+        _check(lib().mlk_checkpoint_load(self._h, C.c_void_p(t.data_ptr()), MEM_DEVICE))
+
+    def objective_value(self, objective, nsteps, weights=None):
+        """The adjoint's objective over the next nsteps steps, by one plain run from a
+        device checkpoint of the current state, which is then restored: "flux" (dt sum F
+        over the steps) or "population" (sum_m weights[m] rho11_m after the last
+        step, two-level emitters)."""
+        blob = self.checkpoint_save_device()
+        f0 = self.flux_total() if objective == "flux" else 0.0
+        self.step(nsteps)
+        if objective == "flux":
+            val = self.flux_total() - f0
+        else:
+            w = np.broadcast_to(np.asarray(weights, dtype=np.float64), (len(self.nlev),))
+            st = self.tls_state(0, self.n_tls)
+            val = 0.0
+            for m in range(self.n_tls):
+                val += float(w[m]) * float(st[m, 0])
+        self.checkpoint_load_device(blob)
+        return val
 
     def checkpoint_load(self, buf):
         buf = np.ascontiguousarray(buf, dtype=np.uint8)
@@ -662,24 +706,32 @@ def coupled_objective(sim, eps_box, dipoles, objective, nsteps, box, weights=Non
                       checkpoint_every=200):
     """Differentiable objective of a run: eps_box (z, y, x) sets eps_r in the design box
     and dipoles (M, 3) the two-level emitters' dipoles, then nsteps coupled steps run
-    from the sim's current state (which is left unchanged).  The hand-written adjoint
-    computes the gradient together with the value (the forward pass of the adjoint
-    runs the steps anyway), and backward returns it."""
+    from the sim's current state (which is left unchanged).  forward runs the steps
+    once from a device checkpoint and reads the objective (flux through the sim's flux
+    plane integrated over the steps, or sum_m weights[m] rho11_m at the end); backward
+    calls the checkpointed adjoint (mlk_adjoint) for the gradients.  A forward-only
+    evaluation therefore costs one plain run."""
     import torch
 
     class _Fn(torch.autograd.Function):
         @staticmethod
         def forward(ctx, e, d):
-            sim.set_eps_box(box, e.detach().cpu().double().numpy())
-            sim.set_tls_dipoles(0, d.detach().cpu().double().numpy())
-            val, ge, gd = sim.adjoint(objective, nsteps, box, weights, checkpoint_every)
-            ctx.save_for_backward(torch.from_numpy(ge).to(e), torch.from_numpy(gd).to(d))
+            en = e.detach().cpu().double().numpy()
+            dn = d.detach().cpu().double().numpy()
+            sim.set_eps_box(box, en)
+            sim.set_tls_dipoles(0, dn)
+            val = sim.objective_value(objective, nsteps, weights)
+            ctx.params = (en, dn)
             return torch.tensor(val, dtype=e.dtype, device=e.device)
 
         @staticmethod
         def backward(ctx, gout):
-            ge, gd = ctx.saved_tensors
-            return gout * ge, gout * gd
+            en, dn = ctx.params
+            sim.set_eps_box(box, en)
+            sim.set_tls_dipoles(0, dn)
+            _, ge, gd = sim.adjoint(objective, nsteps, box, weights, checkpoint_every)
+            return (gout * torch.from_numpy(ge).to(gout.device, gout.dtype),
+                    gout * torch.from_numpy(gd).to(gout.device, gout.dtype))
 
     return _Fn.apply(eps_box, dipoles)
 

@@ -201,7 +201,10 @@ def test_torch_autograd_wrapper():
     e = torch.tensor(w.eps[z0:z1, y0:y1, x0:x1], dtype=torch.float64, requires_grad=True)
     d = torch.tensor(w.tls.dipole, dtype=torch.float64, requires_grad=True)
     J = mlk().coupled_objective(sim, e, d, "flux", w.steps, BOX, checkpoint_every=20)
+    # the forward pass is one plain run: no adjoint has run yet
+    assert sim.adjoint_times() == (0.0, 0.0)
     J.backward()
+    assert sim.adjoint_times()[1] > 0.0
     v, ge, gd = mlk().from_workload(w).adjoint("flux", w.steps, BOX, checkpoint_every=20)
     assert float(J) == v
     assert np.array_equal(e.grad.numpy(), ge) and np.array_equal(d.grad.numpy(), gd)
@@ -213,3 +216,25 @@ def test_adjoint_refuses_multilevel_emitters():
     sim = mlk().from_workload(w)
     with pytest.raises(mlk().MlkError):
         sim.adjoint("flux", 10, ((2, 2, 40), (6, 6, 44)))
+
+
+def test_torch_autograd_population_objective():
+    """The population objective through the autograd wrapper: forward is one plain run,
+    backward the adjoint; both agree with a direct adjoint call, and a second forward
+    from the restored state gives the same value."""
+    import torch
+    w = problem()
+    weights = np.linspace(1.0, 2.0, len(w.tls))
+    sim = mlk().from_workload(w)
+    (x0, y0, z0), (x1, y1, z1) = BOX
+    e = torch.tensor(w.eps[z0:z1, y0:y1, x0:x1], dtype=torch.float64, requires_grad=True)
+    d = torch.tensor(w.tls.dipole, dtype=torch.float64, requires_grad=True)
+    J = mlk().coupled_objective(sim, e, d, "population", w.steps, BOX, weights=weights,
+                                checkpoint_every=20)
+    J2 = mlk().coupled_objective(sim, e, d, "population", w.steps, BOX, weights=weights)
+    assert float(J) == float(J2)
+    J.backward()
+    v, ge, gd = mlk().from_workload(w).adjoint("population", w.steps, BOX, weights=weights,
+                                                checkpoint_every=20)
+    assert abs(float(J) - v) <= 1e-15 * abs(v)
+    assert np.array_equal(e.grad.numpy(), ge) and np.array_equal(d.grad.numpy(), gd)

@@ -119,3 +119,36 @@ def test_prescribed_from_device_memory_and_errors():
         mlk()._check(L.mlk_step_prescribed(a._h, 3, None, mlk().MEM_HOST, None))
     with pytest.raises(mlk().MlkError):
         mlk()._check(L.mlk_step_prescribed(a._h, 1, C.c_void_p(dev.data_ptr()), 7, None))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_travelling_pulse_on_the_device_matches_the_oracle(precision):
+    """eq. E_analytical evaluated on the device for two-level and multilevel emitters at
+    different heights: every recorded two-level state and the final multilevel states
+    against the oracle's pulse step (the emitter states are FP64 in both modes)."""
+    from oracle.oracle import Oracle
+    from paper_2512_06173_amd import workloads as W
+    rng = np.random.default_rng(17)
+    n_tls, n_ml = 40, 12
+    pos_t = np.column_stack([rng.uniform(0, 16, n_tls), rng.uniform(0, 16, n_tls),
+                             rng.uniform(0, 16, n_tls)])
+    tls = W.tls_ensemble(rng, n_tls, 0.0, 16.0, "superposition")
+    tls.pos = pos_t
+    ml = W.random_multilevel(rng, n_ml, rng.uniform(0.0, 16.0, (n_ml, 3)), dmag=0.05)
+    sim = mlk().Simulation((16, 16, 16), bc=("periodic",) * 6, precision=precision)
+    ora = Oracle((16, 16, 16), bc=("periodic",) * 6)
+    for o in (sim, ora):
+        o.add_tls(tls.pos, tls.sigma, tls.gamma, tls.omega0, tls.dipole, tls.rho0)
+        o.add_multilevel(ml.nlev, ml.energies, ml.mop, ml.dipole, ml.gphi, ml.rho0, ml.pos,
+                         ml.sigma, ml.gamma)
+    pulse = dict(pol=[0.3, -0.2, 0.9], amp=2.0, omega=0.25, tau=20.0, t0=60.0, z0=2.0)
+    steps = 300
+    rec = sim.step_wave(steps, t_start=1.5, record=True, **pulse)
+    worst = 0.0
+    for q in range(steps):
+        ora.emitters_step_wave(t=1.5 + q * ora.dt, **pulse)
+        worst = max(worst, np.max(np.abs(rec[q] - ora.tls_state()[:n_tls])))
+    wml = max(np.max(np.abs(sim.rho(m) - ora.rho(m))) for m in range(n_tls, n_tls + n_ml))
+    print(f"[wave] {precision}: two-level {worst:.2e}, multilevel {wml:.2e}", flush=True)
+    assert np.max(rec[:, :, 0]) > 1e-6
+    assert worst <= 1e-12 and wml <= 1e-12

@@ -1014,3 +1014,47 @@ def test_pole_plane_wave_discrete_dispersion():
 
     assert resid(branches(w0)) < 1e-10
     assert resid(branches(1.01 * w0)) > 1e-3
+
+
+# ------------------------------------------------------ classical path, travelling pulse
+
+def _wave_tls(zs, courant=0.5):
+    o = Oracle((1, 1, 1), bc=("periodic",) * 6, courant=courant)
+    n = len(zs)
+    pos = np.column_stack([np.full(n, 0.5), np.full(n, 0.5), zs])
+    o.add_tls(pos, np.ones(n), np.linspace(0.8, 1.2, n), np.full(n, 0.25),
+              np.tile([0.03, -0.02, 0.08], (n, 1)), np.tile([0.0, 0.0, 0.0], (n, 1)))
+    return o
+
+
+def test_travelling_pulse_depends_on_z_minus_ct():
+    """eq. E_analytical: the field is a function of z - ct.  An emitter L cells further
+    along z that starts L time units later goes through exactly the same states."""
+    pulse = dict(pol=[0.2, 0.3, 0.9], amp=0.8, omega=0.25, tau=40.0, t0=150.0, z0=1.0)
+    a, b = _wave_tls([3.0]), _wave_tls([10.0])
+    L = 7.0
+    for q in range(500):
+        t = q * a.dt
+        a.emitters_step_wave(t=t, **pulse)
+        b.emitters_step_wave(t=t + L, **pulse)
+        if q % 50 == 0:
+            assert np.array_equal(a.tls_state(), b.tls_state())
+    assert np.max(a.tls_state()[:, 0]) > 1e-4  # the pulse did drive the emitter
+
+
+def test_travelling_pulse_is_the_prescribed_field_it_names():
+    """The pulse step equals the generic prescribed-field step fed with the field written
+    out here: gamma amp cos(omega (u - t0)) exp(-(u - t0)^2 / 2 tau^2) pol at
+    u = t - (z - z0) (the Gaussian pulse of App. B moving along +z)."""
+    zs = np.array([2.0, 5.5, 9.25])
+    gam = np.linspace(0.8, 1.2, 3)
+    pol = np.array([0.2, 0.3, 0.9])
+    amp, om, tau, t0, z0 = 0.8, 0.25, 40.0, 150.0, 1.0
+    a, b = _wave_tls(zs), _wave_tls(zs)
+    for q in range(300):
+        t = q * a.dt
+        a.emitters_step_wave(pol, amp, om, tau, t0, z0, t)
+        u = t - (zs - z0) - t0
+        f = gam * amp * np.cos(om * u) * np.exp(-u ** 2 / (2 * tau ** 2))
+        b.emitters_step_prescribed(f[:, None] * pol[None, :])
+    assert np.max(np.abs(a.tls_state() - b.tls_state())) < 1e-15
