@@ -499,6 +499,38 @@ mlk_status build_bins(mlk_sim* s) {
     std::stable_sort(spair.begin() + sstart[sl], spair.begin() + sstart[sl + 1],
                      [&](const PairDesc& x, const PairDesc& y) { return rows(x) > rows(y); });
   }
+  // bins heaviest first: a workgroup per bin, two per CU, and the bins along the
+  // emitter region's faces hold few pairs; started first, the heavy bins run side by
+  // side and the light ones fill in behind them instead of sharing rounds with them.
+  // Work of a bin: its pairs' row loops (eight pairs per wavefront) plus the clear
+  // and the owner write, which cost every bin the same.
+  {
+    const size_t nsl = sid.size();
+    std::vector<double> work(nsl, 0.0);
+    for (size_t sl = 0; sl < nsl; ++sl) {
+      double w = 256.0;  // clear, bound and owner write, in row-loop units
+      for (int q = sstart[sl]; q < sstart[sl + 1]; ++q) {
+        const unsigned ru = spair[q].runs;
+        w += (double)((((ru >> 17) & 7) + 1) * (((ru >> 27) & 7) + 1)) / 8.0 + 1.0;
+      }
+      work[sl] = w;
+    }
+    std::vector<int> order(nsl);
+    for (size_t q = 0; q < nsl; ++q) order[q] = (int)q;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return work[x] > work[y]; });
+    std::vector<int> sid2, sstart2(1, 0);
+    std::vector<PairDesc> spair2;
+    spair2.reserve(spair.size());
+    for (int sl : order) {
+      sid2.push_back(sid[sl]);
+      spair2.insert(spair2.end(), spair.begin() + sstart[sl], spair.begin() + sstart[sl + 1]);
+      sstart2.push_back((int)spair2.size());
+    }
+    sid.swap(sid2);
+    sstart.swap(sstart2);
+    spair.swap(spair2);
+  }
   s->nscatter = (int)sid.size();
   STCHK(upload(&s->d_gbin_org, gorg));
   STCHK(upload(&s->d_gbin_start, gstart));
