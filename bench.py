@@ -28,6 +28,8 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# the CPU baseline's threads stay on neighbouring cores (read when OpenMP starts)
+os.environ.setdefault("OMP_PROC_BIND", "close")
 
 HBM_PEAK_GBS = 8000.0
 FUSED_SRC = os.path.join(ROOT, "paper_2512_06173_amd", "csrc", "yee_fused.hip")
@@ -179,14 +181,13 @@ def run_gpu(w, precision, sweep, steps, warmup, timing, tile=None, poles=()):
     return dt, phases, box, tuning
 
 
-def batch_leg(steps, spr=20, tune=False):
-    """64 independent domains (edges 32..96, CPML 8, 1..256 TLS each, FP32 fields):
-    batched (one launch per phase, replayed from a captured hipGraph) against the same
-    domains stepped one after another on the same stream, and (context) against each
-    domain stepping on a stream of its own, so that their launches overlap.  The batch
-    tuner picks one tile shape and layer mode for all members by timing the batch's
-    sweep; the one-by-one leg keeps that choice.  tune=True instead tunes every member
-    on its own first (each small domain then favours its own latency)."""
+def batch_leg(steps, spr=20):
+    """64 independent domains (edges 32..96, CPML 8, 1..256 TLS each, FP32 fields),
+    batched (one launch per phase, replayed from a captured hipGraph), with both sweeps:
+    the fused sweep (one tile shape and layer mode for all members, chosen by the batch
+    tuner) and the plain one; the faster is the leg's headline.  Against it: the same
+    domains stepped one after another on one stream, and (context) each domain on a
+    stream of its own, so that their launches overlap."""
     import torch
     from paper_2512_06173_amd import mlk, workloads as W
     ws = W.batch(n_domains=64, steps=0)
@@ -206,44 +207,54 @@ def batch_leg(steps, spr=20, tune=False):
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
-    sims = [mlk.from_workload(w, stream=h) for w in ws]
-    if tune:
+    rate = lambda t: {"gcell_updates_per_s": round(cells * nsteps / t / 1e9, 3),
+                      "ms_per_step": round(t * 1e3 / nsteps, 4)}
+    legs, tuned = {}, None
+    for sweep in ("fused", "plain"):
+        sims = [mlk.from_workload(w, stream=h, sweep=sweep) for w in ws]
+        b = mlk.Batch(sims)
+        if sweep == "fused":
+            tuned = b.autotune()
+        b.step(2)
+        b.capture(spr)
+        b.replay(1)
+        b.sync()
+        legs[sweep] = timed(lambda: (b.replay(reps), b.sync()))
+        b.close()
         for s in sims:
-            s.autotune()
-    b = mlk.Batch(sims)
-    tuned = None if tune else b.autotune()
-    b.step(2)
-    b.capture(spr)
-    b.replay(1)
-    b.sync()
-    tb = timed(lambda: (b.replay(reps), b.sync()))
-    b.close()
+            s.close()
+    best = min(legs, key=legs.get)
 
-    def one_by_one():
+    def one_by_one(sims):
         for s in sims:
             s.step(nsteps)
         for s in sims:
             s.sync()
 
-    tu = timed(one_by_one)  # the same sims, continuing, on the shared stream
-    for s in sims:
-        s.close()
-    sims = [mlk.from_workload(w) for w in ws]  # library-owned stream each
+    sims = [mlk.from_workload(w, stream=h, sweep=best) for w in ws]
+    if best == "fused":
+        for s in sims:
+            s.set_tuning(tuned[0], tuned[1])
+            s.set_sweep_layers(tuned[2])
     for s in sims:
         s.step(2)
-    tc = timed(one_by_one)
+    tu = timed(lambda: one_by_one(sims))
     for s in sims:
         s.close()
-    rate = lambda t: {"gcell_updates_per_s": round(cells * nsteps / t / 1e9, 3),
-                      "ms_per_step": round(t * 1e3 / nsteps, 4)}
+    sims = [mlk.from_workload(w, sweep=best) for w in ws]  # library-owned stream each
+    for s in sims:
+        s.step(2)
+    tc = timed(lambda: one_by_one(sims))
+    for s in sims:
+        s.close()
     return {"workload": f"{len(ws)} cubic domains, edges 32..96 (8 x U{{4..12}}), CPML 8, "
                         f"eps per 8^3 block, {nem} TLS in all; FP32 fields",
-            "cells": cells, "emitters": nem, "steps": nsteps,
-            "batch_tuning": None if tuned is None else
-            {"ty": tuned[0], "kz": tuned[1], "layers": bool(tuned[2])},
-            "batched_graph": rate(tb), "one_by_one": rate(tu),
-            "speedup": round(tu / tb, 2),
-            "own_streams": rate(tc), "speedup_vs_own_streams": round(tc / tb, 2)}
+            "cells": cells, "emitters": nem, "steps": nsteps, "sweep": best,
+            "batch_tuning": {"ty": tuned[0], "kz": tuned[1], "layers": int(tuned[2])},
+            "batched_graph": rate(legs[best]),
+            "batched_graph_by_sweep": {k: rate(v) for k, v in legs.items()},
+            "one_by_one": rate(tu), "speedup": round(tu / legs[best], 2),
+            "own_streams": rate(tc), "speedup_vs_own_streams": round(tc / legs[best], 2)}
 
 
 # Algorithmic bytes per pole cell and step (FP32): the pre-sweep pass reads E, P, Q and
@@ -315,22 +326,51 @@ def adjoint_leg(w, steps, ms_forward, ckpt=200):
             "total_forward_ratio": round((f_ms + r_ms) / plain, 3)}
 
 
-def cpu_baseline(w, steps):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(w, steps, slab_steps=6):
+    """The FP64 oracle on the host cores: a bounded sample of the benchmark workload with
+    every thread, and the 128^3 slab workload (1000 emitters and the plane-wave source)
+    with one thread."""
     from oracle import oracle
     from oracle.feed import build_oracle
+    from paper_2512_06173_amd import workloads as W
     oracle.build()
+    threads = oracle.threads()
     ora = build_oracle(w)
     ora.step(1)  # first touch of the arrays
     t0 = time.perf_counter()
     ora.step(steps)
     dt = time.perf_counter() - t0
+    del ora
     cells = w.shape[0] * w.shape[1] * w.shape[2]
+    sl = W.slab()
+    oracle.set_threads(1)
+    o1 = build_oracle(sl)
+    o1.step(1)
+    t1 = time.perf_counter()
+    o1.step(slab_steps)
+    d1 = time.perf_counter() - t1
+    oracle.set_threads(threads)
     return {"value": cells * steps / dt / 1e9, "unit": "Gcell-updates/s",
-            "cores": oracle.threads(), "kind": "oracle",
+            "cores": threads, "kind": "oracle",
             "sample": f"{steps} steps of the same {w.shape[0]}x{w.shape[1]}x{w.shape[2]} "
                       f"workload with all {len(w.tls.pos)} emitters (FP64, after 1 untimed "
                       f"step); {dt:.1f} s",
-            "emitter_steps_per_s": len(w.tls.pos) * steps / dt}
+            "emitter_steps_per_s": len(w.tls.pos) * steps / dt,
+            "cpu_model": cpu_model(), "omp_proc_bind": os.environ.get("OMP_PROC_BIND"),
+            "one_thread_slab_128": {
+                "gcell_updates_per_s": sl.ncell * slab_steps / d1 / 1e9,
+                "sample": f"{slab_steps} steps of the 128^3 slab workload (1000 emitters, "
+                          f"plane-wave source), one thread; {d1:.1f} s"}}
 
 
 def main():
@@ -418,7 +458,7 @@ def main():
     }
     if not args.no_compare:
         cmp = {}
-        ksteps = max(1, args.steps // 5)
+        ksteps = max(100, args.steps // 5)
         for prec, sweep in (("fp32", "plain"), ("fp64", "fused"), ("fp64", "plain")):
             d, _, _, _ = run_gpu(w, prec, sweep, ksteps, max(1, args.warmup // 2), False)
             cmp[f"{sweep}_{prec}"] = {"gcell_updates_per_s": round(cells * ksteps / d / 1e9, 3),
@@ -434,7 +474,7 @@ def main():
         out["adjoint"] = adj
         out["adjoint_forward_ratio"] = adj["adjoint_forward_ratio"]
     if not args.no_batch:
-        out["batch"] = batch_leg(max(20, args.steps // 5))
+        out["batch"] = batch_leg(max(100, args.steps // 5))
     if not args.no_compare:
         out["dispersive"] = dispersive_leg(w, max(20, args.steps // 5), tuning, ms_step)
         out["cavity"] = cavity_leg(w, max(20, args.steps // 5))

@@ -98,9 +98,12 @@ void fused_job_shape(FusedJob<T>& J);
 ShellMap shell_map(const Geom& g, const Box& inner);
 int source_blocks_of(const Geom& g, const SourceSet& src);
 hipError_t sweep_fused_batch_f64(const FusedJob<double>* jobs, const int* start, int njobs,
-                                 int nblocks, int ty, hipStream_t st);
+                                 int nblocks, int ty, bool lean, hipStream_t st);
 hipError_t sweep_fused_batch_f32(const FusedJob<float>* jobs, const int* start, int njobs,
-                                 int nblocks, int ty, hipStream_t st);
+                                 int nblocks, int ty, bool lean, hipStream_t st);
+// CPML code a fused launch over the box needs: 0 none, 1 x layers only (the box keeps
+// clear of the y and z layers), 2 every layer.
+int fused_cpm(const Geom& g, const Box& box);
 hipError_t shell_batch_f64(const ShellJob<double>* jobs, const int* start, int njobs, int nblocks,
                            bool h_pass, hipStream_t st);
 hipError_t shell_batch_f32(const ShellJob<float>* jobs, const int* start, int njobs, int nblocks,

@@ -2470,6 +2470,7 @@ struct BatchTables {
   DevTable<FluxJob<T>> fsave, fpart, finish;
   DevTable<GatherJob<T>> gather;
   DevTable<FusedJob<T>> fused[3];  // by TY: 4, 8, 16
+  bool fused_lean[3] = {false, false, false};  // no job's box reaches a y or z layer
   DevTable<ShellJob<T>> shell;
   DevTable<SourceJob<T>> sources;
   DevTable<ScatterJob<T>> scatter;
@@ -2584,7 +2585,12 @@ mlk_status build_tables(mlk_batch* b, BatchTables<T> (&tab)[2]) {
     STCHK(make_table(t.fpart, fpj));
     STCHK(make_table(t.finish, fin));
     STCHK(make_table(t.gather, ga));
-    for (int k = 0; k < 3; ++k) STCHK(make_table(t.fused[k], fu[k]));
+    for (int k = 0; k < 3; ++k) {
+      STCHK(make_table(t.fused[k], fu[k]));
+      bool lean = true;
+      for (const FusedJob<T>& J : fu[k]) lean = lean && fused_cpm(J.g, J.box) <= 1;
+      t.fused_lean[k] = lean;
+    }
     STCHK(make_table(t.shell, sh));
     STCHK(make_table(t.sources, so));
     STCHK(make_table(t.scatter, sc));
@@ -2640,8 +2646,10 @@ mlk_status enqueue_batch_step(mlk_batch* b, const BatchTables<T>& t) {
   const int tys[3] = {4, 8, 16};
   for (int k = 0; k < 3; ++k) {
     const DevTable<FusedJob<T>>& f = t.fused[k];
-    if constexpr (f32) HIPCHK(sweep_fused_batch_f32(f.jobs, f.start, f.njobs, f.nblocks, tys[k], st));
-    else HIPCHK(sweep_fused_batch_f64(f.jobs, f.start, f.njobs, f.nblocks, tys[k], st));
+    if constexpr (f32)
+      HIPCHK(sweep_fused_batch_f32(f.jobs, f.start, f.njobs, f.nblocks, tys[k], t.fused_lean[k], st));
+    else
+      HIPCHK(sweep_fused_batch_f64(f.jobs, f.start, f.njobs, f.nblocks, tys[k], t.fused_lean[k], st));
   }
   for (int h = 1; h >= 0; --h) {
     if constexpr (f32) HIPCHK(shell_batch_f32(t.shell.jobs, t.shell.start, t.shell.njobs,
@@ -3071,8 +3079,10 @@ mlk_status time_batch_sweep(mlk_batch* b, const BatchTables<T>& t, double* us) {
   auto once = [&]() {
     for (int k = 0; k < 3 && err == hipSuccess; ++k) {
       const DevTable<FusedJob<T>>& f = t.fused[k];
-      if constexpr (f32) err = sweep_fused_batch_f32(f.jobs, f.start, f.njobs, f.nblocks, tys[k], st);
-      else err = sweep_fused_batch_f64(f.jobs, f.start, f.njobs, f.nblocks, tys[k], st);
+      if constexpr (f32)
+        err = sweep_fused_batch_f32(f.jobs, f.start, f.njobs, f.nblocks, tys[k], t.fused_lean[k], st);
+      else
+        err = sweep_fused_batch_f64(f.jobs, f.start, f.njobs, f.nblocks, tys[k], t.fused_lean[k], st);
     }
     for (int h = 1; h >= 0 && err == hipSuccess; --h) {
       if constexpr (f32)

@@ -500,15 +500,16 @@ __global__ __launch_bounds__(256, 4) void k_fused_frame(FrameJobs<T> fj) {
                    (int)blockIdx.x - fj.start[j]);
 }
 
-// One launch over the jobs of a batch of domains (see BatchJobs).
-template <typename T, int TY>
-__global__ __launch_bounds__(64 * TY, 4) void k_fused_batch(const FusedJob<T>* jobs,
+// One launch over the jobs of a batch of domains (see BatchJobs); CPM and W as for
+// the single-domain kernels (the lean form when no job's box reaches a y or z layer).
+template <typename T, int TY, int CPM, int W>
+__global__ __launch_bounds__(64 * TY, W) void k_fused_batch(const FusedJob<T>* jobs,
                                                          const int* start, int njobs) {
   const int j = find_job(start, njobs, blockIdx.x);
   const FusedJob<T>& J = jobs[j];
   const int bid = blockIdx.x - start[j];
   if (J.ty != TY || bid >= J.nblocks) return;
-  fused_body<T, TY>(J.a, J.b, J.g, J.box, J.kz, J.ntx, J.nty, J.nblocks, bid);
+  fused_body<T, TY, CPM>(J.a, J.b, J.g, J.box, J.kz, J.ntx, J.nty, J.nblocks, bid);
 }
 
 // Waves per SIMD the lean kernel is built for (registers permitting): with no CPML
@@ -564,7 +565,6 @@ template void fused_job_shape<double>(FusedJob<double>&);
 // The leanest kernel that covers the box: none of the layer code when no CPML
 // layer reaches it (a halo cell included), the x layers alone when the y and z
 // layers stay clear, else everything.
-template <typename T>
 int fused_cpm(const Geom& g, const Box& box) {
   auto clear = [&](int a) {
     if (!has_cpml(g, a)) return true;
@@ -578,7 +578,7 @@ int fused_cpm(const Geom& g, const Box& box) {
 template <typename T>
 static hipError_t launch_fused_any(const FieldPtrs<T>& a, const FieldPtrs<T>& b, const Geom& g,
                                    const Box& box, int kz, int ty, hipStream_t st) {
-  const int cpm = fused_cpm<T>(g, box);
+  const int cpm = fused_cpm(g, box);
   if (ty == 16) return launch_fused<T, 16>(a, b, g, box, kz, cpm, st);
   if (ty == 8) return launch_fused<T, 8>(a, b, g, box, kz, cpm, st);
   return launch_fused<T, 4>(a, b, g, box, kz, cpm, st);
@@ -627,16 +627,24 @@ static hipError_t launch_frame(const FieldPtrs<T>& a, const FieldPtrs<T>& b, con
   return hipGetLastError();
 }
 
+template <typename T, int TY>
+static void launch_fused_batch_ty(const FusedJob<T>* jobs, const int* start, int njobs,
+                                  int nblocks, bool lean, hipStream_t st) {
+  if (lean)
+    hipLaunchKernelGGL((k_fused_batch<T, TY, 1, LeanWaves<T, TY, 1>::value>), dim3(nblocks),
+                       dim3(64 * TY), 0, st, jobs, start, njobs);
+  else
+    hipLaunchKernelGGL((k_fused_batch<T, TY, 2, 4>), dim3(nblocks), dim3(64 * TY), 0, st, jobs,
+                       start, njobs);
+}
+
 template <typename T>
 static hipError_t launch_fused_batch(const FusedJob<T>* jobs, const int* start, int njobs,
-                                     int nblocks, int ty, hipStream_t st) {
+                                     int nblocks, int ty, bool lean, hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
-  if (ty == 16)
-    hipLaunchKernelGGL((k_fused_batch<T, 16>), dim3(nblocks), dim3(1024), 0, st, jobs, start, njobs);
-  else if (ty == 8)
-    hipLaunchKernelGGL((k_fused_batch<T, 8>), dim3(nblocks), dim3(512), 0, st, jobs, start, njobs);
-  else
-    hipLaunchKernelGGL((k_fused_batch<T, 4>), dim3(nblocks), dim3(256), 0, st, jobs, start, njobs);
+  if (ty == 16) launch_fused_batch_ty<T, 16>(jobs, start, njobs, nblocks, lean, st);
+  else if (ty == 8) launch_fused_batch_ty<T, 8>(jobs, start, njobs, nblocks, lean, st);
+  else launch_fused_batch_ty<T, 4>(jobs, start, njobs, nblocks, lean, st);
   return hipGetLastError();
 }
 
@@ -657,12 +665,12 @@ hipError_t sweep_frame_f32(const FieldPtrs<float>& a, const FieldPtrs<float>& b,
   return launch_frame<float>(a, b, g, inner, kz, st);
 }
 hipError_t sweep_fused_batch_f64(const FusedJob<double>* jobs, const int* start, int njobs,
-                                 int nblocks, int ty, hipStream_t st) {
-  return launch_fused_batch<double>(jobs, start, njobs, nblocks, ty, st);
+                                 int nblocks, int ty, bool lean, hipStream_t st) {
+  return launch_fused_batch<double>(jobs, start, njobs, nblocks, ty, lean, st);
 }
 hipError_t sweep_fused_batch_f32(const FusedJob<float>* jobs, const int* start, int njobs,
-                                 int nblocks, int ty, hipStream_t st) {
-  return launch_fused_batch<float>(jobs, start, njobs, nblocks, ty, st);
+                                 int nblocks, int ty, bool lean, hipStream_t st) {
+  return launch_fused_batch<float>(jobs, start, njobs, nblocks, ty, lean, st);
 }
 
 }  // namespace mlk
