@@ -45,6 +45,10 @@ struct BinCfg<double> {
   static constexpr int SX = 16, SY = 16, SZ = 8;
 };
 
+// A gather bin of at most this many emitters is light: it stages only the cells
+// that its windows cover (7^3 per window against the 24 x 16 x 16 tile).
+int gather_light_max() { return 4; }
+
 void bin_shape(bool fp32, int G[3], int S[3]) {
   if (fp32) {
     G[0] = BinCfg<float>::GX; G[1] = BinCfg<float>::GY; G[2] = BinCfg<float>::GZ;
@@ -134,7 +138,8 @@ __device__ __forceinline__ void gather_body(const FieldPtrs<T>& f, const Geom& g
   constexpr int TX = BX + 2 * kHalo, TY = BY + 2 * kHalo, TZ = BZ + 2 * kHalo;
   __shared__ T sE[3][TX * TY * TZ];
   const int tid = threadIdx.x;
-  const int bin = xcd_block(bid, bins.ngather);
+  const bool light = bid >= bins.gdense;  // uniform across the block
+  const int bin = light ? bid : xcd_block(bid, bins.gdense);
   // tile origin in the unwrapped frame of the emitters' window indices
   const int x0 = bins.gbin_org[3 * bin] - kHalo;
   const int y0 = bins.gbin_org[3 * bin + 1] - kHalo;
@@ -145,17 +150,9 @@ __device__ __forceinline__ void gather_body(const FieldPtrs<T>& f, const Geom& g
   const int q0 = bins.gbin_start[bin], q1 = bins.gbin_start[bin + 1];
   int e_next = q0 + grp < q1 ? bins.gbin_em[q0 + grp] : 0;
 
-  // stage the tile: every load of a thread is issued before the first LDS
-  // store, so they are in flight together (unconditional loads from a safe
-  // index; cells beyond a non-periodic face read as zero)
-  constexpr int NTILE = TX * TY * TZ;
-  static_assert(NTILE % NT == 0, "the tile is a whole number of workgroup passes");
-  constexpr int RF = NTILE / NT;
-  T v[RF][3];
-#pragma unroll
-  for (int r = 0; r < RF; ++r) {
-    const int t = tid + r * NT;
-    const int li = t % TX, lj = (t / TX) % TY, lk = t / (TX * TY);
+  // E (times 1/eps_r with WEPS) of tile cell (li, lj, lk), from a safe index:
+  // zero beyond a non-periodic face
+  auto tile_cell = [&](int li, int lj, int lk, T& e0, T& e1, T& e2) {
     int q[3] = {x0 + li, y0 + lj, z0 + lk};
     bool ok = true;
 #pragma unroll
@@ -168,23 +165,64 @@ __device__ __forceinline__ void gather_body(const FieldPtrs<T>& f, const Geom& g
       }
     }
     const size_t id = ok ? cell_index(g, q[0], q[1], q[2]) : 0;
-    T e0 = f.E[0][id], e1 = f.E[1][id], e2 = f.E[2][id];
+    e0 = f.E[0][id];
+    e1 = f.E[1][id];
+    e2 = f.E[2][id];
     if (WEPS && f.epsinv) {  // null: eps_r = 1 everywhere
       const T ei = f.epsinv[id];
       e0 *= ei;
       e1 *= ei;
       e2 *= ei;
     }
-    v[r][0] = ok ? e0 : T(0);
-    v[r][1] = ok ? e1 : T(0);
-    v[r][2] = ok ? e2 : T(0);
-  }
+    e0 = ok ? e0 : T(0);
+    e1 = ok ? e1 : T(0);
+    e2 = ok ? e2 : T(0);
+  };
+  if (light) {
+    // A light bin stages only the box that its few windows cover (the union of
+    // [org, org + n) per axis): the same values at the cells its sums read.
+    int lo[3] = {TX, TY, TZ}, hi[3] = {0, 0, 0};
+    for (int q = q0; q < q1; ++q) {
+      const WinRec<T>& r = win.rec[bins.gbin_em[q]];
+      const int4 o = *reinterpret_cast<const int4*>(&r.org[0]);  // org[0..2], n[0]
+      const int2 nn = *reinterpret_cast<const int2*>(&r.n[1]);
+      lo[0] = min(lo[0], o.x - x0);
+      lo[1] = min(lo[1], o.y - y0);
+      lo[2] = min(lo[2], o.z - z0);
+      hi[0] = max(hi[0], o.x - x0 + o.w);
+      hi[1] = max(hi[1], o.y - y0 + nn.x);
+      hi[2] = max(hi[2], o.z - z0 + nn.y);
+    }
+    const int nx = hi[0] - lo[0], ny = hi[1] - lo[1], nxy = nx * (hi[1] - lo[1]);
+    const int cells = nxy * (hi[2] - lo[2]);
+    for (int t = tid; t < cells; t += NT) {
+      const int li = lo[0] + t % nx, lj = lo[1] + (t / nx) % ny, lk = lo[2] + t / nxy;
+      T e0, e1, e2;
+      tile_cell(li, lj, lk, e0, e1, e2);
+      const int s = li + TX * (lj + TY * lk);
+      sE[0][s] = e0;
+      sE[1][s] = e1;
+      sE[2][s] = e2;
+    }
+  } else {
+    // stage the tile: every load of a thread is issued before the first LDS
+    // store, so they are in flight together
+    constexpr int NTILE = TX * TY * TZ;
+    static_assert(NTILE % NT == 0, "the tile is a whole number of workgroup passes");
+    constexpr int RF = NTILE / NT;
+    T v[RF][3];
 #pragma unroll
-  for (int r = 0; r < RF; ++r) {
-    const int t = tid + r * NT;
-    sE[0][t] = v[r][0];
-    sE[1][t] = v[r][1];
-    sE[2][t] = v[r][2];
+    for (int r = 0; r < RF; ++r) {
+      const int t = tid + r * NT;
+      tile_cell(t % TX, (t / TX) % TY, t / (TX * TY), v[r][0], v[r][1], v[r][2]);
+    }
+#pragma unroll
+    for (int r = 0; r < RF; ++r) {
+      const int t = tid + r * NT;
+      sE[0][t] = v[r][0];
+      sE[1][t] = v[r][1];
+      sE[2][t] = v[r][2];
+    }
   }
 
   __syncthreads();
@@ -249,11 +287,19 @@ __global__ __launch_bounds__(GatherCfg<T>::threads, GatherCfg<T>::waves_per_simd
 
 template <typename T>
 __global__ __launch_bounds__(GatherCfg<T>::threads, GatherCfg<T>::waves_per_simd) void k_gather_batch(const GatherJob<T>* jobs,
-                                                           const int* start, int njobs) {
-  const int j = find_job(start, njobs, blockIdx.x);
+                                                           const int* start, int njobs,
+                                                           const int2* order) {
+  int j, bid;
+  if (order) {  // (job, bin) of the block, heaviest first across the jobs
+    const int2 o = order[blockIdx.x];
+    j = o.x;
+    bid = o.y;
+  } else {
+    j = find_job(start, njobs, blockIdx.x);
+    bid = blockIdx.x - start[j];
+    if (bid >= jobs[j].nblocks) return;
+  }
   const GatherJob<T>& J = jobs[j];
-  const int bid = blockIdx.x - start[j];
-  if (bid >= J.nblocks) return;
   gather_body(J.f, J.g, J.bins, J.win, J.Et, bid);
 }
 
@@ -555,11 +601,19 @@ __global__ __launch_bounds__(kThreads, 4) void k_scatter_bins(FieldPtrs<T> f, Ge
 
 template <typename T>
 __global__ __launch_bounds__(kThreads, 4) void k_scatter_batch(const ScatterJob<T>* jobs,
-                                                            const int* start, int njobs) {
-  const int j = find_job(start, njobs, blockIdx.x);
+                                                            const int* start, int njobs,
+                                                            const int2* order) {
+  int j, bid;
+  if (order) {  // (job, bin) of the block, heaviest first across the jobs
+    const int2 o = order[blockIdx.x];
+    j = o.x;
+    bid = o.y;
+  } else {
+    j = find_job(start, njobs, blockIdx.x);
+    bid = blockIdx.x - start[j];
+    if (bid >= jobs[j].nblocks) return;
+  }
   const ScatterJob<T>& J = jobs[j];
-  const int bid = blockIdx.x - start[j];
-  if (bid >= J.nblocks) return;
   scatter_body(J.f, J.g, J.bins, J.win, J.mudot, J.g.dt * J.g.inv_dx * J.g.inv_dx * J.g.inv_dx,
                bid);
 }
@@ -638,33 +692,36 @@ hipError_t bin_scatter_f32(const FieldPtrs<float>& f, const Geom& g, const BinPt
 
 template <typename T>
 static hipError_t launch_gather_batch(const GatherJob<T>* jobs, const int* start, int njobs,
-                                      int nblocks, hipStream_t st) {
+                                      const int2* order, int nblocks, hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather_batch<T>, dim3(nblocks), dim3(GatherCfg<T>::threads), 0, st, jobs, start, njobs);
+  hipLaunchKernelGGL(k_gather_batch<T>, dim3(nblocks), dim3(GatherCfg<T>::threads), 0, st, jobs,
+                     start, njobs, order);
   return hipGetLastError();
 }
 template <typename T>
 static hipError_t launch_scatter_batch(const ScatterJob<T>* jobs, const int* start, int njobs,
-                                       int nblocks, hipStream_t st) {
+                                       const int2* order, int nblocks, hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scatter_batch<T>, dim3(nblocks), dim3(kThreads), 0, st, jobs, start, njobs);
+  hipLaunchKernelGGL(k_scatter_batch<T>, dim3(nblocks), dim3(kThreads), 0, st, jobs, start, njobs,
+                     order);
   return hipGetLastError();
 }
+
 hipError_t gather_batch_f64(const GatherJob<double>* jobs, const int* start, int njobs,
-                            int nblocks, hipStream_t st) {
-  return launch_gather_batch<double>(jobs, start, njobs, nblocks, st);
+                            const int2* order, int nblocks, hipStream_t st) {
+  return launch_gather_batch<double>(jobs, start, njobs, order, nblocks, st);
 }
 hipError_t gather_batch_f32(const GatherJob<float>* jobs, const int* start, int njobs,
-                            int nblocks, hipStream_t st) {
-  return launch_gather_batch<float>(jobs, start, njobs, nblocks, st);
+                            const int2* order, int nblocks, hipStream_t st) {
+  return launch_gather_batch<float>(jobs, start, njobs, order, nblocks, st);
 }
 hipError_t scatter_batch_f64(const ScatterJob<double>* jobs, const int* start, int njobs,
-                             int nblocks, hipStream_t st) {
-  return launch_scatter_batch<double>(jobs, start, njobs, nblocks, st);
+                             const int2* order, int nblocks, hipStream_t st) {
+  return launch_scatter_batch<double>(jobs, start, njobs, order, nblocks, st);
 }
 hipError_t scatter_batch_f32(const ScatterJob<float>* jobs, const int* start, int njobs,
-                             int nblocks, hipStream_t st) {
-  return launch_scatter_batch<float>(jobs, start, njobs, nblocks, st);
+                             const int2* order, int nblocks, hipStream_t st) {
+  return launch_scatter_batch<float>(jobs, start, njobs, order, nblocks, st);
 }
 hipError_t tls_batch(const TlsJob* jobs, const int* start, int njobs, int nblocks,
                      hipStream_t st) {

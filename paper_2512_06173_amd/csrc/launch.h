@@ -91,6 +91,8 @@ hipError_t bin_scatter_f32(const FieldPtrs<float>& f, const Geom& g, const BinPt
                            const WindowPtrs<float>& win, const double* mudot, hipStream_t st);
 // bin edge lengths (cells) of the gather (G) and scatter (S) bins for a field precision
 void bin_shape(bool fp32, int G[3], int S[3]);
+// Gather bins of at most this many emitters are light (stage only their windows).
+int gather_light_max();
 
 // ---- batched launches (one launch per phase over the jobs of many domains)
 template <typename T>
@@ -113,17 +115,17 @@ hipError_t sources_batch_f64(const SourceJob<double>* jobs, const int* start, in
 hipError_t sources_batch_f32(const SourceJob<float>* jobs, const int* start, int njobs,
                              int nblocks, hipStream_t st);
 hipError_t gather_batch_f64(const GatherJob<double>* jobs, const int* start, int njobs,
-                            int nblocks, hipStream_t st);
+                            const int2* order, int nblocks, hipStream_t st);
 hipError_t gather_batch_f32(const GatherJob<float>* jobs, const int* start, int njobs,
-                            int nblocks, hipStream_t st);
+                            const int2* order, int nblocks, hipStream_t st);
 hipError_t tls_batch(const TlsJob* jobs, const int* start, int njobs, int nblocks,
                      hipStream_t st);
 hipError_t ml_batch(const MlJob* jobs, const int* start, int njobs, int nblocks, int nl,
                     hipStream_t st);
 hipError_t scatter_batch_f64(const ScatterJob<double>* jobs, const int* start, int njobs,
-                             int nblocks, hipStream_t st);
+                             const int2* order, int nblocks, hipStream_t st);
 hipError_t scatter_batch_f32(const ScatterJob<float>* jobs, const int* start, int njobs,
-                             int nblocks, hipStream_t st);
+                             const int2* order, int nblocks, hipStream_t st);
 hipError_t detect_batch_f64(const FluxJob<double>* jobs, const int* start, int njobs, int nblocks,
                             int kind, hipStream_t st);
 hipError_t detect_batch_f32(const FluxJob<float>* jobs, const int* start, int njobs, int nblocks,

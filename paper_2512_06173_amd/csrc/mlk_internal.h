@@ -284,9 +284,12 @@ __device__ __forceinline__ void flux_save_body(const FieldPtrs<T>& f, const Geom
 // Gather bins: every emitter belongs to the bin of its centre cell; the
 // workgroup of a bin stages the bin plus a halo of kHalo cells.
 // Scatter bins: every (bin, emitter) pair whose window touches the bin.
+// Gather bins of at most a few emitters ("light" bins) come after the others and
+// stage only the part of their tile that their windows cover.
 struct BinPtrs {
   int nbx, nby, nbz;        // scatter bins per axis
   int ngather;              // gather bins holding at least one centre
+  int gdense;               // bins [0, gdense) stage the whole tile, the rest are light
   const int* gbin_org;      // [3*ngather] bin origin in unwrapped cells (centre-cell frame)
   const int* gbin_start;    // [ngather+1] CSR into gbin_em
   const int* gbin_em;       // emitter ids

@@ -153,7 +153,9 @@ struct mlk_sim {
   double* d_tls_rho = nullptr;
   // binned emitter phase
   int nbx = 0, nby = 0, nbz = 0;
-  int ngather = 0, nscatter = 0;
+  int ngather = 0, nscatter = 0, gdense = 0;
+  // estimated work of each gather / scatter launch block (host; orders a batch's blocks)
+  std::vector<float> gwork, swork;
   int* d_gbin_org = nullptr;
   int* d_gbin_start = nullptr;
   int* d_gbin_em = nullptr;
@@ -344,6 +346,7 @@ BinPtrs bin_ptrs(const mlk_sim* s) {
   b.nby = s->nby;
   b.nbz = s->nbz;
   b.ngather = s->ngather;
+  b.gdense = s->gdense;
   b.gbin_org = s->d_gbin_org;
   b.gbin_start = s->d_gbin_start;
   b.gbin_em = s->d_gbin_em;
@@ -415,7 +418,36 @@ mlk_status build_bins(mlk_sim* s) {
     gem.push_back(keys[q].e);
   }
   gstart.push_back(M);
-  s->ngather = (int)gstart.size() - 1;
+  {
+    // light bins (at most gather_light_max() emitters) after the others, keeping the
+    // order within each kind: the heavier bins are dispatched first
+    const int light_max = gather_light_max();
+    const int nbin = (int)gstart.size() - 1;
+    std::vector<int> org2, start2, em2;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int b = 0; b < nbin; ++b) {
+        const bool light = gstart[b + 1] - gstart[b] <= light_max;
+        if (light != (pass == 1)) continue;
+        start2.push_back((int)em2.size());
+        for (int a = 0; a < 3; ++a) org2.push_back(gorg[3 * b + a]);
+        for (int q = gstart[b]; q < gstart[b + 1]; ++q) em2.push_back(gem[q]);
+      }
+      if (pass == 0) s->gdense = (int)start2.size();
+    }
+    start2.push_back((int)em2.size());
+    gorg.swap(org2);
+    gstart.swap(start2);
+    gem.swap(em2);
+    s->ngather = nbin;
+    // work of launch block q: the staged bins (taken through the kernel's XCD
+    // order) before the light ones, each kind by its emitter count
+    s->gwork.assign(nbin, 0.f);
+    const int nd = s->gdense, q8 = nd / 8;
+    for (int q = 0; q < nbin; ++q) {
+      const int bin = q < nd && q < 8 * q8 ? (q % 8) * q8 + q / 8 : q;
+      s->gwork[q] = (float)(gstart[bin + 1] - gstart[bin]) + (q < nd ? 1e6f : 0.f);
+    }
+  }
 
   // scatter: the union window of each emitter (org, n per axis, as in its
   // record) split, per axis, into runs inside one bin: consecutive window
@@ -522,7 +554,9 @@ mlk_status build_bins(mlk_sim* s) {
     std::vector<int> sid2, sstart2(1, 0);
     std::vector<PairDesc> spair2;
     spair2.reserve(spair.size());
+    s->swork.clear();
     for (int sl : order) {
+      s->swork.push_back((float)work[sl]);
       sid2.push_back(sid[sl]);
       spair2.insert(spair2.end(), spair.begin() + sstart[sl], spair.begin() + sstart[sl + 1]);
       sstart2.push_back((int)spair2.size());
@@ -2433,13 +2467,38 @@ struct DevTable {
   int* start = nullptr;
   int njobs = 0;
   int nblocks = 0;
+  int2* order = nullptr;  // optional: (job, block) of each launch block
+  int norder = 0;
 };
 
 template <typename J>
 void free_table(DevTable<J>& t) {
   dfree(t.jobs);
   dfree(t.start);
+  dfree(t.order);
   t = DevTable<J>{};
+}
+
+// One launch order for a table's blocks across its jobs, heaviest first by the
+// given estimated work of each job's blocks (the jobs as uploaded): the kernel
+// reads its (job, block) from it instead of searching the job starts, so that
+// the heavy blocks of every job start first and the light ones fill in behind.
+template <typename J>
+mlk_status make_order(DevTable<J>& t, const std::vector<const std::vector<float>*>& work) {
+  if ((int)work.size() != t.njobs) return fail(MLK_EINVAL, "block work does not match the jobs");
+  std::vector<std::pair<float, int2>> all;
+  for (int j = 0; j < t.njobs; ++j)
+    for (int q = 0; q < (int)work[j]->size(); ++q) all.push_back({(*work[j])[q], make_int2(j, q)});
+  std::stable_sort(all.begin(), all.end(),
+                   [](const std::pair<float, int2>& x, const std::pair<float, int2>& y) {
+                     return x.first > y.first;
+                   });
+  std::vector<int2> ord(all.size());
+  for (size_t k = 0; k < all.size(); ++k) ord[k] = all[k].second;
+  if (ord.empty()) return MLK_OK;
+  STCHK(upload(&t.order, ord));
+  t.norder = (int)ord.size();
+  return MLK_OK;
 }
 
 // Upload the non-empty jobs; job starts are padded to multiples of 8 blocks.
@@ -2530,6 +2589,7 @@ mlk_status build_tables(mlk_batch* b, BatchTables<T> (&tab)[2]) {
     std::vector<ShellJob<T>> sh;
     std::vector<SourceJob<T>> so;
     std::vector<ScatterJob<T>> sc;
+    std::vector<const std::vector<float>*> gw, sw;  // block work of the non-empty jobs
     for (mlk_sim* s : b->sims) {
       if (q == 1 && b->fused) swap_buffers(s);
       const FieldPtrs<T> cur = field_ptrs<T>(s);
@@ -2545,6 +2605,8 @@ mlk_status build_tables(mlk_batch* b, BatchTables<T> (&tab)[2]) {
       if (s->nem > 0) {
         ga.push_back({cur, s->g, bin_ptrs(s), window_ptrs<T>(s), s->d_Et, s->ngather});
         sc.push_back({nxt, s->g, bin_ptrs(s), window_ptrs<T>(s), s->d_mudot, s->nscatter});
+        if (s->ngather > 0) gw.push_back(&s->gwork);
+        if (s->nscatter > 0) sw.push_back(&s->swork);
       }
       Box inner{};
       if (b->fused) {
@@ -2585,6 +2647,7 @@ mlk_status build_tables(mlk_batch* b, BatchTables<T> (&tab)[2]) {
     STCHK(make_table(t.fpart, fpj));
     STCHK(make_table(t.finish, fin));
     STCHK(make_table(t.gather, ga));
+    STCHK(make_order(t.gather, gw));
     for (int k = 0; k < 3; ++k) {
       STCHK(make_table(t.fused[k], fu[k]));
       bool lean = true;
@@ -2594,6 +2657,7 @@ mlk_status build_tables(mlk_batch* b, BatchTables<T> (&tab)[2]) {
     STCHK(make_table(t.shell, sh));
     STCHK(make_table(t.sources, so));
     STCHK(make_table(t.scatter, sc));
+    STCHK(make_order(t.scatter, sw));
   }
   std::vector<TlsJob> tj;
   std::vector<MlJob> mj[kMaxLevels + 1];
@@ -2637,9 +2701,9 @@ mlk_status enqueue_batch_step(mlk_batch* b, const BatchTables<T>& t) {
   };
   HIPCHK(detect(t.fsave, 0));
   if constexpr (f32) HIPCHK(gather_batch_f32(t.gather.jobs, t.gather.start, t.gather.njobs,
-                                             t.gather.nblocks, st));
-  else HIPCHK(gather_batch_f64(t.gather.jobs, t.gather.start, t.gather.njobs, t.gather.nblocks,
-                               st));
+                                             t.gather.order, t.gather.norder, st));
+  else HIPCHK(gather_batch_f64(t.gather.jobs, t.gather.start, t.gather.njobs, t.gather.order,
+                               t.gather.norder, st));
   HIPCHK(tls_batch(b->tls.jobs, b->tls.start, b->tls.njobs, b->tls.nblocks, st));
   for (int n = 2; n <= kMaxLevels; ++n)
     HIPCHK(ml_batch(b->ml[n].jobs, b->ml[n].start, b->ml[n].njobs, b->ml[n].nblocks, n, st));
@@ -2662,9 +2726,9 @@ mlk_status enqueue_batch_step(mlk_batch* b, const BatchTables<T>& t) {
   else HIPCHK(sources_batch_f64(t.sources.jobs, t.sources.start, t.sources.njobs,
                                 t.sources.nblocks, st));
   if constexpr (f32) HIPCHK(scatter_batch_f32(t.scatter.jobs, t.scatter.start, t.scatter.njobs,
-                                              t.scatter.nblocks, st));
+                                              t.scatter.order, t.scatter.norder, st));
   else HIPCHK(scatter_batch_f64(t.scatter.jobs, t.scatter.start, t.scatter.njobs,
-                                t.scatter.nblocks, st));
+                                t.scatter.order, t.scatter.norder, st));
   HIPCHK(detect(t.fpart, 1));
   HIPCHK(detect(t.finish, 2));
   return MLK_OK;
