@@ -92,7 +92,7 @@ template <typename T, int KIND>
 __global__ __launch_bounds__(256) void k_detect_batch(const FluxJob<T>* jobs, const int* start,
                                                       int njobs) {
   const int j = find_job(start, njobs, blockIdx.x);
-  const FluxJob<T>& J = jobs[j];
+  const FluxJob<T>& J = jobs[j];  // (a copy would put its probe arrays in scratch)
   const int lb = blockIdx.x - start[j];
   if (lb >= J.nblocks) return;
   if (KIND == 0) flux_save_body(J.f, J.g, J.fp, lb * blockDim.x + threadIdx.x);

@@ -299,7 +299,7 @@ __global__ __launch_bounds__(GatherCfg<T>::threads, GatherCfg<T>::waves_per_simd
     bid = blockIdx.x - start[j];
     if (bid >= jobs[j].nblocks) return;
   }
-  const GatherJob<T>& J = jobs[j];
+  const GatherJob<T> J = load_job(jobs, j);
   gather_body(J.f, J.g, J.bins, J.win, J.Et, bid);
 }
 
@@ -374,7 +374,7 @@ __global__ __launch_bounds__(kTlsThreads) void k_cavity_tls(TlsPtrs tls, double 
 __global__ __launch_bounds__(256) void k_tls_batch(const TlsJob* jobs, const int* start,
                                                    int njobs) {
   const int j = find_job(start, njobs, blockIdx.x);
-  const TlsJob& J = jobs[j];
+  const TlsJob J = load_job(jobs, j);
   const int lb = blockIdx.x - start[j];
   if (lb >= J.nblocks) return;
   tls_body(J.tls, J.dt, J.Et, J.mudot, J.pop_off, J.ser, J.step, lb * blockDim.x + threadIdx.x);
@@ -613,7 +613,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_scatter_batch(const ScatterJob<
     bid = blockIdx.x - start[j];
     if (bid >= jobs[j].nblocks) return;
   }
-  const ScatterJob<T>& J = jobs[j];
+  const ScatterJob<T> J = load_job(jobs, j);
   scatter_body(J.f, J.g, J.bins, J.win, J.mudot, J.g.dt * J.g.inv_dx * J.g.inv_dx * J.g.inv_dx,
                bid);
 }

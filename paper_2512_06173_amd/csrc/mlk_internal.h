@@ -299,6 +299,22 @@ struct BinPtrs {
   const int4* sbin_pair;    // one PairDesc per (emitter, bin) pair
 };
 
+// A batch kernel's job, read from its table through the constant address space.
+// The tables are written before the launch and only read by kernels, and pointers
+// read from constant memory are known to point to global memory, so the kernel
+// reaches the fields through global instructions.  Read from an ordinary pointer,
+// the job's pointers would be generic: the compiler would emit flat instructions,
+// which also count against the LDS and scalar wait counter.  (The host pass only
+// parses kernels; it reads the table directly.)
+template <typename J>
+__device__ __forceinline__ J load_job(const J* jobs, int j) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return ((__attribute__((address_space(4))) const J*)jobs)[j];
+#else
+  return jobs[j];
+#endif
+}
+
 // A scatter pair: emitter e and, per axis a, the run of its union window inside
 // the bin: window offsets d0 .. d0+c-1 on the bin-local cells l0 .. l0+c-1, packed
 // as l0 | d0 << 4 | (c-1) << 7 at bit 10a of runs.  gw = |gamma| times the

@@ -209,7 +209,7 @@ __global__ __launch_bounds__(64) void k_ml_step(MlDev ml, int first, int count, 
 template <int N>
 __global__ __launch_bounds__(64) void k_ml_batch(const MlJob* jobs, const int* start, int njobs) {
   const int j = find_job(start, njobs, blockIdx.x);
-  const MlJob& J = jobs[j];
+  const MlJob J = load_job(jobs, j);
   const int lb = blockIdx.x - start[j];
   if (lb >= J.nblocks) return;
   ml_body<N>(J.ml, J.first, J.count, J.dt, J.Et, J.mudot, J.pop_off, J.ser, J.step,

@@ -61,14 +61,25 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
   int tile_x, tile_y, chunk;
   if (CPM == 2 && sizeof(T) == 4 && (has_cpml(g, 1) || has_cpml(g, 2))) {
     // Heaviest first: the workgroups whose rows or planes lie in the y or z layers
-    // carry the psi traffic and arithmetic and take longest.  Dispatched first (y
-    // tiles from the two edges inwards, then within each the z chunks likewise), the
-    // lighter ones fill in behind them instead of the launch waiting on a few heavy
-    // workgroups at its end.
+    // carry the psi traffic and arithmetic and take longest.  Rows of tiles (a y tile
+    // of one z chunk) are taken from the two y edges inwards, and within each the z
+    // chunks likewise, so the lighter ones fill in behind the heavy ones instead of
+    // the launch waiting on a few heavy workgroups at its end.  Consecutive rows go
+    // to consecutive XCDs (workgroups are dealt to the 8 XCDs in turn), which spreads
+    // the heavy ones evenly, and the x tiles of one row run one after another on the
+    // same XCD: the cache lines that neighbouring x tiles share (the E ring's x = -1
+    // and x = 64 columns, the halo H column) are then read once into that XCD's L2.
     auto fold = [](int q, int n) { return (q & 1) ? n - 1 - (q >> 1) : (q >> 1); };
     const int nch = nblocks / (ntx * nty);
-    tile_x = bid_in % ntx;
-    const int r = bid_in / ntx;
+    int r;
+    if ((nty * nch) % 8 == 0) {
+      const int xcd = bid_in % 8, m = bid_in / 8;
+      tile_x = m % ntx;
+      r = (m / ntx) * 8 + xcd;
+    } else {
+      tile_x = bid_in % ntx;
+      r = bid_in / ntx;
+    }
     chunk = fold(r % nch, nch);
     tile_y = fold(r / nch, nty);
   } else {
@@ -506,7 +517,7 @@ template <typename T, int TY, int CPM, int W>
 __global__ __launch_bounds__(64 * TY, W) void k_fused_batch(const FusedJob<T>* jobs,
                                                          const int* start, int njobs) {
   const int j = find_job(start, njobs, blockIdx.x);
-  const FusedJob<T>& J = jobs[j];
+  const FusedJob<T> J = load_job(jobs, j);
   const int bid = blockIdx.x - start[j];
   if (J.ty != TY || bid >= J.nblocks) return;
   fused_body<T, TY, CPM>(J.a, J.b, J.g, J.box, J.kz, J.ntx, J.nty, J.nblocks, bid);

@@ -112,7 +112,7 @@ template <typename T, bool H>
 __global__ __launch_bounds__(256) void k_update_shell_batch(const ShellJob<T>* jobs,
                                                             const int* start, int njobs) {
   const int jb = find_job(start, njobs, blockIdx.x);
-  const ShellJob<T>& J = jobs[jb];
+  const ShellJob<T> J = load_job(jobs, jb);
   const unsigned t = (blockIdx.x - start[jb]) * blockDim.x + threadIdx.x;
   if ((long long)t >= J.m.total) return;
   int i, j, k;
@@ -165,7 +165,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_sources_batch(const SourceJob<T>* jobs, const int* start,
                                                        int njobs) {
   const int jb = find_job(start, njobs, blockIdx.x);
-  const SourceJob<T>& J = jobs[jb];
+  const SourceJob<T>& J = jobs[jb];  // (a copy would put its source array in scratch)
   const int lb = blockIdx.x - start[jb];
   if (lb >= J.nblocks) return;
   const int q = lb / J.bx;
