@@ -62,6 +62,7 @@ void bin_shape(bool fp32, int G[3], int S[3]) {
 namespace {
 
 constexpr int kLanesPerEmitter = 8;  // = kMaxWin: one lane per window x offset
+constexpr int kLightThreads = 256;   // threads per block of the light-emitter gather
 constexpr int kThreads = 512;
 constexpr int kGroups = kThreads / kLanesPerEmitter;  // emitters in flight per workgroup
 // Gather launch shape.  The tile fill is latency-bound, so a bin runs sixteen
@@ -272,13 +273,138 @@ __device__ __forceinline__ void gather_body(const FieldPtrs<T>& f, const Geom& g
   }
 }
 
-// The blocks past the gather bins, if any, save the flux plane's E^n (one
-// launch fewer per step; both read E^n only).
+// The emitters of the light bins, without a tile: a group of lanes per emitter
+// (the lane layout of gather_body), each lane reading its window cells from global
+// memory, all loads of a window plane issued before its sums.  The values and the
+// order of every operation are those of the tiled gather, so E~ is the same bit
+// for bit.  em: the emitter ids, count of them.
+template <typename T>
+__device__ __forceinline__ void light_body(const FieldPtrs<T>& f, const Geom& g, const int* em,
+                                           int count, const WindowPtrs<T>& win, double* Et,
+                                           int bid) {
+  constexpr int LG = GatherCfg<T>::lanes, RG = GatherCfg<T>::rows;
+  constexpr int NG = kLightThreads / LG;
+  const int tid = threadIdx.x;
+  const int grp = tid / LG, i = tid % kLanesPerEmitter;
+  const int j0 = (tid / kLanesPerEmitter) % (LG / kLanesPerEmitter) * RG;
+  const int q = bid * NG + grp;
+  if (q >= count) return;  // uniform across the lanes of an emitter
+  const int e = em[q];
+  const WinRec<T>& r = win.rec[e];
+  const int4 o = *reinterpret_cast<const int4*>(&r.org[0]);  // org[0..2], n[0]
+  const int2 nn = *reinterpret_cast<const int2*>(&r.n[1]);
+  double ax = 0.0, ay = 0.0, az = 0.0;
+  if (i < o.w) {
+    const T wx0 = r.wr[0][0][i], wx1 = r.wr[0][1][i];
+    T wy0[RG], wy1[RG];
+#pragma unroll
+    for (int d = 0; d < RG; ++d) {
+      wy0[d] = r.wr[1][0][j0 + d];
+      wy1[d] = r.wr[1][1][j0 + d];
+    }
+    const int ny = nn.x - j0, nz = nn.y;
+    // window cells in the grid: wrapped on a periodic axis; beyond a wall the tile
+    // holds zero, and so does this path
+    int cx = o.x + i;
+    bool okx = true;
+    if (g.periodic[0]) {
+      cx %= g.n[0];
+      cx = cx < 0 ? cx + g.n[0] : cx;
+    } else {
+      okx = cx >= 0 && cx < g.n[0];
+    }
+    int cyv[RG];
+    unsigned okym = 0u;
+#pragma unroll
+    for (int j = 0; j < RG; ++j) {
+      int cy = o.y + j0 + j;
+      bool ok = j < ny;
+      if (g.periodic[1]) {
+        cy %= g.n[1];
+        cy = cy < 0 ? cy + g.n[1] : cy;
+      } else {
+        ok = ok && cy >= 0 && cy < g.n[1];
+      }
+      cyv[j] = cy;
+      okym |= ok ? (1u << j) : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxWin; ++k) {
+      if (k < nz) {
+        int cz = o.z + k;
+        bool okz = okx;
+        if (g.periodic[2]) {
+          cz %= g.n[2];
+          cz = cz < 0 ? cz + g.n[2] : cz;
+        } else {
+          okz = okz && cz >= 0 && cz < g.n[2];
+        }
+        const unsigned okm = okz ? okym : 0u;
+        T v[RG][3];
+#pragma unroll
+        for (int j = 0; j < RG; ++j) {
+          const size_t id = ((okm >> j) & 1u) ? cell_index(g, cx, cyv[j], cz) : 0;
+          v[j][0] = f.E[0][id];
+          v[j][1] = f.E[1][id];
+          v[j][2] = f.E[2][id];
+        }
+        const T wz0 = r.wr[2][0][k], wz1 = r.wr[2][1][k];
+        T sx = T(0), sy = T(0), sz = T(0);
+#pragma unroll
+        for (int j = 0; j < RG; ++j) {
+          if (j < ny) {
+            const bool ok = (okm >> j) & 1u;
+            sx += wy0[j] * (ok ? v[j][0] : T(0));
+            sy += wy1[j] * (ok ? v[j][1] : T(0));
+            sz += wy0[j] * (ok ? v[j][2] : T(0));
+          }
+        }
+        ax += (double)(wz0 * sx);
+        ay += (double)(wz0 * sy);
+        az += (double)(wz1 * sz);
+      }
+    }
+    // Ex sits at half-integer x (variant 1); Ey, Ez at integer x
+    ax *= (double)wx1;
+    ay *= (double)wx0;
+    az *= (double)wx0;
+  }
+  ax = gather_lane_sum<LG>(ax);
+  ay = gather_lane_sum<LG>(ay);
+  az = gather_lane_sum<LG>(az);
+  if (i == 0 && j0 == 0) {
+    const double gm = win.gamma[e];
+    Et[3 * e] = gm * ax;
+    Et[3 * e + 1] = gm * ay;
+    Et[3 * e + 2] = gm * az;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kLightThreads) void k_gather_light(FieldPtrs<T> f, Geom g,
+                                                                const int* em, int count,
+                                                                WindowPtrs<T> win, double* Et) {
+  light_body(f, g, em, count, win, Et, blockIdx.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kLightThreads) void k_gather_light_batch(const LightJob<T>* jobs,
+                                                                      const int* start,
+                                                                      int njobs) {
+  const int j = find_job(start, njobs, blockIdx.x);
+  const LightJob<T> J = load_job(jobs, j);
+  const int bid = blockIdx.x - start[j];
+  if (bid >= J.nblocks) return;
+  light_body(J.f, J.g, J.em, J.count, J.win, J.Et, bid);
+}
+
+// The staged bins (the light ones have a kernel of their own); the blocks past them,
+// if any, save the flux plane's E^n (one launch fewer per step; both read E^n only).
 template <typename T>
 __global__ __launch_bounds__(GatherCfg<T>::threads, GatherCfg<T>::waves_per_simd) void k_gather_bins(
     FieldPtrs<T> f, Geom g, BinPtrs bins, WindowPtrs<T> win, double* Et, FluxPlane fp) {
-  if ((int)blockIdx.x >= bins.ngather) {  // uniform across the block
-    flux_save_body(f, g, fp, ((int)blockIdx.x - bins.ngather) * GatherCfg<T>::threads +
+  if ((int)blockIdx.x >= bins.gdense) {  // uniform across the block
+    flux_save_body(f, g, fp, ((int)blockIdx.x - bins.gdense) * GatherCfg<T>::threads +
                                  (int)threadIdx.x);
     return;
   }
@@ -632,9 +758,16 @@ static hipError_t launch_gather_step(const FieldPtrs<T>& f, const Geom& g, const
     nflux = (g.n[u] * g.n[v] + GatherCfg<T>::threads - 1) / GatherCfg<T>::threads;
     fpv = *fp;
   }
-  hipLaunchKernelGGL(k_gather_bins<T>, dim3(b.ngather + nflux), dim3(GatherCfg<T>::threads), 0,
-                     st, f, g, b, win, Et, fpv);
+  if (b.gdense + nflux > 0)
+    hipLaunchKernelGGL(k_gather_bins<T>, dim3(b.gdense + nflux), dim3(GatherCfg<T>::threads), 0,
+                       st, f, g, b, win, Et, fpv);
   hipError_t e = hipGetLastError();
+  if (e == hipSuccess && b.nlight > 0) {
+    constexpr int NG = kLightThreads / GatherCfg<T>::lanes;
+    hipLaunchKernelGGL(k_gather_light<T>, dim3((b.nlight + NG - 1) / NG), dim3(kLightThreads),
+                       0, st, f, g, b.gbin_em + b.glight0, b.nlight, win, Et);
+    e = hipGetLastError();
+  }
   if (e != hipSuccess || tls.count == 0) return e;
   hipLaunchKernelGGL(k_tls_step, dim3((tls.count + 255) / 256), dim3(256), 0, st, tls, g.dt, Et,
                      mudot, pop_off, ser, step);
@@ -714,6 +847,25 @@ hipError_t gather_batch_f64(const GatherJob<double>* jobs, const int* start, int
 hipError_t gather_batch_f32(const GatherJob<float>* jobs, const int* start, int njobs,
                             const int2* order, int nblocks, hipStream_t st) {
   return launch_gather_batch<float>(jobs, start, njobs, order, nblocks, st);
+}
+template <typename T>
+static hipError_t launch_light_batch(const LightJob<T>* jobs, const int* start, int njobs,
+                                     int nblocks, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_light_batch<T>, dim3(nblocks), dim3(kLightThreads), 0, st, jobs,
+                     start, njobs);
+  return hipGetLastError();
+}
+hipError_t light_batch_f64(const LightJob<double>* jobs, const int* start, int njobs,
+                           int nblocks, hipStream_t st) {
+  return launch_light_batch<double>(jobs, start, njobs, nblocks, st);
+}
+hipError_t light_batch_f32(const LightJob<float>* jobs, const int* start, int njobs, int nblocks,
+                           hipStream_t st) {
+  return launch_light_batch<float>(jobs, start, njobs, nblocks, st);
+}
+int light_per_block(bool fp32) {
+  return fp32 ? kLightThreads / GatherCfg<float>::lanes : kLightThreads / GatherCfg<double>::lanes;
 }
 hipError_t scatter_batch_f64(const ScatterJob<double>* jobs, const int* start, int njobs,
                              const int2* order, int nblocks, hipStream_t st) {

@@ -122,6 +122,12 @@ hipError_t tls_batch(const TlsJob* jobs, const int* start, int njobs, int nblock
                      hipStream_t st);
 hipError_t ml_batch(const MlJob* jobs, const int* start, int njobs, int nblocks, int nl,
                     hipStream_t st);
+// The light bins' emitters of a batch (no tile); light_per_block: emitters per block.
+hipError_t light_batch_f64(const LightJob<double>* jobs, const int* start, int njobs,
+                           int nblocks, hipStream_t st);
+hipError_t light_batch_f32(const LightJob<float>* jobs, const int* start, int njobs, int nblocks,
+                           hipStream_t st);
+int light_per_block(bool fp32);
 hipError_t scatter_batch_f64(const ScatterJob<double>* jobs, const int* start, int njobs,
                              const int2* order, int nblocks, hipStream_t st);
 hipError_t scatter_batch_f32(const ScatterJob<float>* jobs, const int* start, int njobs,

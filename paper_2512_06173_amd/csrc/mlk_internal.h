@@ -290,6 +290,7 @@ struct BinPtrs {
   int nbx, nby, nbz;        // scatter bins per axis
   int ngather;              // gather bins holding at least one centre
   int gdense;               // bins [0, gdense) stage the whole tile, the rest are light
+  int glight0, nlight;      // gbin_em[glight0 .. glight0 + nlight): the light bins' emitters
   const int* gbin_org;      // [3*ngather] bin origin in unwrapped cells (centre-cell frame)
   const int* gbin_start;    // [ngather+1] CSR into gbin_em
   const int* gbin_em;       // emitter ids
@@ -405,6 +406,18 @@ struct SourceJob {
   int nblocks;  // bx * src.count
 };
 
+// The light bins' emitters of one domain, gathered without a tile.
+template <typename T>
+struct LightJob {
+  FieldPtrs<T> f;
+  Geom g;
+  const int* em;
+  int count;
+  WindowPtrs<T> win;
+  double* Et;
+  int nblocks;
+};
+
 template <typename T>
 struct GatherJob {
   FieldPtrs<T> f;
@@ -412,7 +425,7 @@ struct GatherJob {
   BinPtrs bins;
   WindowPtrs<T> win;
   double* Et;
-  int nblocks;  // bins.ngather
+  int nblocks;  // bins.gdense (the light bins go to LightJob)
 };
 
 struct TlsJob {

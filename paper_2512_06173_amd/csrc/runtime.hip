@@ -153,7 +153,7 @@ struct mlk_sim {
   double* d_tls_rho = nullptr;
   // binned emitter phase
   int nbx = 0, nby = 0, nbz = 0;
-  int ngather = 0, nscatter = 0, gdense = 0;
+  int ngather = 0, nscatter = 0, gdense = 0, glight0 = 0, nlight = 0;
   // estimated work of each gather / scatter launch block (host; orders a batch's blocks)
   std::vector<float> gwork, swork;
   int* d_gbin_org = nullptr;
@@ -347,6 +347,8 @@ BinPtrs bin_ptrs(const mlk_sim* s) {
   b.nbz = s->nbz;
   b.ngather = s->ngather;
   b.gdense = s->gdense;
+  b.glight0 = s->glight0;
+  b.nlight = s->nlight;
   b.gbin_org = s->d_gbin_org;
   b.gbin_start = s->d_gbin_start;
   b.gbin_em = s->d_gbin_em;
@@ -439,13 +441,17 @@ mlk_status build_bins(mlk_sim* s) {
     gstart.swap(start2);
     gem.swap(em2);
     s->ngather = nbin;
-    // work of launch block q: the staged bins (taken through the kernel's XCD
-    // order) before the light ones, each kind by its emitter count
-    s->gwork.assign(nbin, 0.f);
+    // the light bins' emitters, one run of gem (the forward gather serves them
+    // without a tile)
+    s->glight0 = gstart[s->gdense];
+    s->nlight = M - s->glight0;
+    // work of launch block q of the staged bins (taken through the kernel's XCD
+    // order): its emitter count
     const int nd = s->gdense, q8 = nd / 8;
-    for (int q = 0; q < nbin; ++q) {
-      const int bin = q < nd && q < 8 * q8 ? (q % 8) * q8 + q / 8 : q;
-      s->gwork[q] = (float)(gstart[bin + 1] - gstart[bin]) + (q < nd ? 1e6f : 0.f);
+    s->gwork.assign(nd, 0.f);
+    for (int q = 0; q < nd; ++q) {
+      const int bin = q < 8 * q8 ? (q % 8) * q8 + q / 8 : q;
+      s->gwork[q] = (float)(gstart[bin + 1] - gstart[bin]);
     }
   }
 
@@ -2528,6 +2534,7 @@ template <typename T>
 struct BatchTables {
   DevTable<FluxJob<T>> fsave, fpart, finish;
   DevTable<GatherJob<T>> gather;
+  DevTable<LightJob<T>> light;  // the light bins' emitters
   DevTable<FusedJob<T>> fused[3];  // by TY: 4, 8, 16
   bool fused_lean[3] = {false, false, false};  // no job's box reaches a y or z layer
   DevTable<ShellJob<T>> shell;
@@ -2538,6 +2545,7 @@ struct BatchTables {
     free_table(fpart);
     free_table(finish);
     free_table(gather);
+    free_table(light);
     for (auto& f : fused) free_table(f);
     free_table(shell);
     free_table(sources);
@@ -2590,6 +2598,7 @@ mlk_status build_tables(mlk_batch* b, BatchTables<T> (&tab)[2]) {
     std::vector<SourceJob<T>> so;
     std::vector<ScatterJob<T>> sc;
     std::vector<const std::vector<float>*> gw, sw;  // block work of the non-empty jobs
+    std::vector<LightJob<T>> li;
     for (mlk_sim* s : b->sims) {
       if (q == 1 && b->fused) swap_buffers(s);
       const FieldPtrs<T> cur = field_ptrs<T>(s);
@@ -2603,9 +2612,14 @@ mlk_status build_tables(mlk_batch* b, BatchTables<T> (&tab)[2]) {
       }
       fin.push_back({nxt, s->g, s->fp, ser, s->d_step, 1});
       if (s->nem > 0) {
-        ga.push_back({cur, s->g, bin_ptrs(s), window_ptrs<T>(s), s->d_Et, s->ngather});
+        ga.push_back({cur, s->g, bin_ptrs(s), window_ptrs<T>(s), s->d_Et, s->gdense});
         sc.push_back({nxt, s->g, bin_ptrs(s), window_ptrs<T>(s), s->d_mudot, s->nscatter});
-        if (s->ngather > 0) gw.push_back(&s->gwork);
+        if (s->gdense > 0) gw.push_back(&s->gwork);
+        if (s->nlight > 0) {
+          const int per = light_per_block(s->fp32);
+          li.push_back({cur, s->g, s->d_gbin_em + s->glight0, s->nlight, window_ptrs<T>(s),
+                        s->d_Et, (s->nlight + per - 1) / per});
+        }
         if (s->nscatter > 0) sw.push_back(&s->swork);
       }
       Box inner{};
@@ -2648,6 +2662,7 @@ mlk_status build_tables(mlk_batch* b, BatchTables<T> (&tab)[2]) {
     STCHK(make_table(t.finish, fin));
     STCHK(make_table(t.gather, ga));
     STCHK(make_order(t.gather, gw));
+    STCHK(make_table(t.light, li));
     for (int k = 0; k < 3; ++k) {
       STCHK(make_table(t.fused[k], fu[k]));
       bool lean = true;
@@ -2704,6 +2719,9 @@ mlk_status enqueue_batch_step(mlk_batch* b, const BatchTables<T>& t) {
                                              t.gather.order, t.gather.norder, st));
   else HIPCHK(gather_batch_f64(t.gather.jobs, t.gather.start, t.gather.njobs, t.gather.order,
                                t.gather.norder, st));
+  if constexpr (f32) HIPCHK(light_batch_f32(t.light.jobs, t.light.start, t.light.njobs,
+                                            t.light.nblocks, st));
+  else HIPCHK(light_batch_f64(t.light.jobs, t.light.start, t.light.njobs, t.light.nblocks, st));
   HIPCHK(tls_batch(b->tls.jobs, b->tls.start, b->tls.njobs, b->tls.nblocks, st));
   for (int n = 2; n <= kMaxLevels; ++n)
     HIPCHK(ml_batch(b->ml[n].jobs, b->ml[n].start, b->ml[n].njobs, b->ml[n].nblocks, n, st));
