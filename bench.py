@@ -65,7 +65,7 @@ def parse():
     p.add_argument("--batch-only", action="store_true",
                    help="only the 64-domain batch leg (profiling runs)")
     p.add_argument("--tile", type=lambda v: tuple(int(x) for x in v.split(",")), default=None,
-                   help="fused tile TY,KZ instead of autotuning (profiling runs)")
+                   help="fused tile TY,KZ[,TX] instead of autotuning (profiling runs)")
     return p.parse_args()
 
 
@@ -134,9 +134,10 @@ def copy_calibration():
     print(json.dumps(out), flush=True)
 
 
-def traffic_from_profile(launch_cells):
+def traffic_from_profile(launch_cells, tile):
     """HBM bytes per launch of the fused kernel from the committed counter summary,
-    or None when it is absent or was taken on a different kernel source."""
+    or None when it is absent or was taken on a different kernel source, box or tile
+    (tx, ty, kz)."""
     if not os.path.exists(TRAFFIC_SUMMARY):
         return None
     txt = open(TRAFFIC_SUMMARY).read()
@@ -144,7 +145,10 @@ def traffic_from_profile(launch_cells):
     m = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", txt)
     t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
     c = re.search(r"cells_per_launch:\s*(\d+)", txt)
-    if not (m and t and c) or m.group(1) != want or int(c.group(1)) != launch_cells:
+    k = re.search(r"tile_tx_ty_kz:\s*(\d+)\s+(\d+)\s+(\d+)", txt)
+    if not (m and t and c and k) or m.group(1) != want or int(c.group(1)) != launch_cells:
+        return None
+    if tuple(int(v) for v in k.groups()) != tuple(tile):
         return None
     return float(t.group(1))
 
@@ -157,7 +161,9 @@ def run_gpu(w, precision, sweep, steps, warmup, timing, tile=None, poles=()):
     for box, w0, gamma, sigma, drude in poles:
         sim.add_susceptibility(box, w0, gamma, sigma, drude=drude)
     if tile:
-        sim.set_tuning(*tile)
+        sim.set_tuning(*tile[:2])
+        if len(tile) > 2:
+            sim.set_tile_width(tile[2])
     else:
         sim.autotune()  # tile shape of the fused sweep (untimed; plain sweeps have none)
     sim.step(warmup)
@@ -176,7 +182,7 @@ def run_gpu(w, precision, sweep, steps, warmup, timing, tile=None, poles=()):
             if n:
                 phases[name] = (ms, n)
     box = sim.interior_box()
-    tuning = sim.tuning()
+    tuning = sim.tuning() + (sim.tile_width(),)
     sim.close()
     return dt, phases, box, tuning
 
@@ -236,6 +242,7 @@ def batch_leg(steps, spr=20):
         for s in sims:
             s.set_tuning(tuned[0], tuned[1])
             s.set_sweep_layers(tuned[2])
+            s.set_tile_width(tuned[3])
     for s in sims:
         s.step(2)
     tu = timed(lambda: one_by_one(sims))
@@ -250,7 +257,8 @@ def batch_leg(steps, spr=20):
     return {"workload": f"{len(ws)} cubic domains, edges 32..96 (8 x U{{4..12}}), CPML 8, "
                         f"eps per 8^3 block, {nem} TLS in all; FP32 fields",
             "cells": cells, "emitters": nem, "steps": nsteps, "sweep": best,
-            "batch_tuning": {"ty": tuned[0], "kz": tuned[1], "layers": int(tuned[2])},
+            "batch_tuning": {"tx": tuned[3], "ty": tuned[0], "kz": tuned[1],
+                             "layers": int(tuned[2])},
             "batched_graph": rate(legs[best]),
             "batched_graph_by_sweep": {k: rate(v) for k, v in legs.items()},
             "one_by_one": rate(tu), "speedup": round(tu / legs[best], 2),
@@ -427,11 +435,11 @@ def main():
     launch_bytes = launch_cells * CELL_WORDS * esz + launch_memb * PSI_WORDS * esz
     t_launch = sweep_ms / sweep_n * 1e-3
     achieved = launch_bytes / t_launch / 1e9
-    traffic = traffic_from_profile(launch_cells)
+    traffic = traffic_from_profile(launch_cells, (tuning[2], tuning[0], tuning[1]))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": f"k_fused<float, {tuning[0]}>",
-                "tile": {"ty": tuning[0], "kz": tuning[1]},
+                "traffic": traffic, "kernel": f"k_fused<float, {tuning[2]}, {tuning[0]}>",
+                "tile": {"tx": tuning[2], "ty": tuning[0], "kz": tuning[1]},
                 "cells_per_launch": launch_cells, "bytes_per_launch": launch_bytes,
                 "avg_launch_us": round(t_launch * 1e6, 2)}
     emitter_ms = sum(breakdown[p][0] / breakdown[p][1] for p in ("emitters", "scatter")

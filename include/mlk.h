@@ -441,7 +441,7 @@ mlk_status mlk_batch_sync(mlk_batch* b);
 mlk_status mlk_batch_destroy(mlk_batch* b);
 
 /* Tile shape and layer mode for the batch as a whole: every member gets the same
- * (ty, kz, layer mode), chosen by timing the batch's sweep phase (the fused
+ * (tile width, ty, kz, layer mode), chosen by timing the batch's sweep phase (the fused
  * launches and the two shell passes of one batched step, best of three runs;
  * the members' state is untouched) for every candidate, three interleaved
  * rounds.  A member tuned alone minimises its own latency; a batch wants
@@ -453,8 +453,12 @@ mlk_status mlk_batch_destroy(mlk_batch* b);
 mlk_status mlk_batch_autotune(mlk_batch* b, const char* cache_path);
 
 /* Tile shape of the fused sweep: rows per workgroup ty (4, 8 or 16) and z planes
- * per workgroup kz.  mlk_autotune times every pair (and, with FP32 fields, both
- * layer modes, see mlk_set_sweep_layers) on the sim's own grid, each as the
+ * per workgroup kz (mlk_set_tuning), and the tile width, 64 (the default) or 32 x
+ * cells per workgroup (mlk_set_tile_width: narrower tiles give small grids more
+ * workgroups; EINVAL for other widths, EUNSUPPORTED when the sim is in layer mode 2
+ * and the width leaves no fused box over every x column).  All MLK_ESTATE while the
+ * sim belongs to a batch.  mlk_autotune times every combination (and, with FP32
+ * fields, every layer mode, see mlk_set_sweep_layers) on the sim's own grid, each as the
  * fused launch plus the two CPML shell passes of a step, in three interleaved
  * rounds (the state is left untouched; each candidate keeps its best round) and
  * keeps the fastest; with cache_path (NULL: no cache) results are read from and
@@ -465,6 +469,8 @@ mlk_status mlk_batch_autotune(mlk_batch* b, const char* cache_path);
 mlk_status mlk_autotune(mlk_sim* s, const char* cache_path);
 mlk_status mlk_set_tuning(mlk_sim* s, int32_t ty, int32_t kz);
 mlk_status mlk_get_tuning(mlk_sim* s, int32_t* ty, int32_t* kz);
+mlk_status mlk_set_tile_width(mlk_sim* s, int32_t tx);
+mlk_status mlk_get_tile_width(mlk_sim* s, int32_t* tx);
 
 /* Layer mode of the fused sweep (FP32 fields): where the cells of the y and z CPML
  * layers are updated.  0: by the plain shell passes (the fused box stops one cell

@@ -42,9 +42,9 @@ hipError_t sweep_frame_f64(const FieldPtrs<double>& a, const FieldPtrs<double>& 
 hipError_t sweep_frame_f32(const FieldPtrs<float>& a, const FieldPtrs<float>& b, const Geom& g,
                            const Box& inner, int kz, hipStream_t st);
 hipError_t sweep_fused_f64(const FieldPtrs<double>& a, const FieldPtrs<double>& b, const Geom& g,
-                           const Box& box, int kz, int ty, hipStream_t st);
+                           const Box& box, int kz, int tx, int ty, hipStream_t st);
 hipError_t sweep_fused_f32(const FieldPtrs<float>& a, const FieldPtrs<float>& b, const Geom& g,
-                           const Box& box, int kz, int ty, hipStream_t st);
+                           const Box& box, int kz, int tx, int ty, hipStream_t st);
 
 hipError_t windows_f64(int count, const double* pos, const double* sigma, double R, const Geom& g,
                        int* lo, int* len, double* w, hipStream_t st);
@@ -100,9 +100,9 @@ void fused_job_shape(FusedJob<T>& J);
 ShellMap shell_map(const Geom& g, const Box& inner);
 int source_blocks_of(const Geom& g, const SourceSet& src);
 hipError_t sweep_fused_batch_f64(const FusedJob<double>* jobs, const int* start, int njobs,
-                                 int nblocks, int ty, bool lean, hipStream_t st);
+                                 int nblocks, int tx, int ty, bool lean, hipStream_t st);
 hipError_t sweep_fused_batch_f32(const FusedJob<float>* jobs, const int* start, int njobs,
-                                 int nblocks, int ty, bool lean, hipStream_t st);
+                                 int nblocks, int tx, int ty, bool lean, hipStream_t st);
 // CPML code a fused launch over the box needs: 0 none, 1 x layers only (the box keeps
 // clear of the y and z layers), 2 every layer.
 int fused_cpm(const Geom& g, const Box& box);

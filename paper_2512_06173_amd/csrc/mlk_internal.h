@@ -350,7 +350,7 @@ struct FusedJob {
   FieldPtrs<T> a, b;
   Geom g;
   Box box;
-  int kz, ty, ntx, nty, nblocks;
+  int kz, tx, ty, ntx, nty, nblocks;  // planes per chunk, tile width and rows, tile grid
 };
 
 // Up to four boxes of one sim swept by one launch of the full fused kernel (the

@@ -108,6 +108,7 @@ struct mlk_sim {
   bool states_bound = false;
   int kz = 0;       // z planes per workgroup of the fused sweep
   int ty = 4;       // y rows per workgroup of the fused sweep (4, 8 or 16)
+  int tx = 64;      // x cells per workgroup of the fused sweep (64 or 32)
   int layer_mode = 0;  // y/z CPML layers: 0 shell passes, 1 in the fused kernel, 2 frame launch
   bool vacuum = true;   // eps_r = 1 in every cell: the fused sweep reads no 1/eps_r
   hipStream_t batch_stream = nullptr;  // stream of the batch this sim belongs to
@@ -793,20 +794,20 @@ hipError_t collect_marks(mlk_sim* s) {
 // FP64 fields the y and z extent stops one cell of margin above the low layers
 // and at the high layers (the FP64 kernel carries the x layers only, keeping
 // its registers within occupancy), the plain passes updating the rest.  In both
-// the x extent is every column provided the low-x halo column of each 64-wide
-// tile (x = 64t - 1, t >= 1) lies outside the x layers and the x psi arrays
+// the x extent is every column provided the low-x halo column of each tx-wide
+// tile (x = tx t - 1, t >= 1) lies outside the x layers and the x psi arrays
 // index in 32 bits; otherwise x is limited like y and z.  The y and z psi
 // arrays must index in 32 bits too for a full y and z extent.  The cells
 // outside the box form the CPML shell.
 // z planes per chunk of the frame launch's y slabs
 constexpr int kFrameKz = 8;
 
-Box interior_box(const Geom& g, bool layers) {
+Box interior_box(const Geom& g, bool layers, int tx) {
   Box inner{};
-  const int n = g.n[0], ntx = (n + 63) / 64;
+  const int n = g.n[0], ntx = (n + tx - 1) / tx;
   const double plane = (double)g.n[0] * g.n[1] * g.n[2];
   const bool x_full = !has_cpml(g, 0) ||
-                      (g.nlo[0] <= 63 && 64 * (ntx - 1) <= n - g.nhi[0] &&
+                      (g.nlo[0] <= tx - 1 && tx * (ntx - 1) <= n - g.nhi[0] &&
                        (double)(g.nlo[0] + g.nhi[0]) * g.n[1] * g.n[2] < 4294967296.0);
   const bool yz_full = layers && 4.0 * plane * (g.nlo[1] + g.nhi[1]) / g.n[1] < 4294967296.0 &&
                        4.0 * plane * (g.nlo[2] + g.nhi[2]) / g.n[2] < 4294967296.0;
@@ -818,14 +819,16 @@ Box interior_box(const Geom& g, bool layers) {
   return inner;
 }
 
-Box sweep_box(const mlk_sim* s) { return interior_box(s->g, s->fp32 && s->layer_mode == 1); }
+Box sweep_box(const mlk_sim* s) {
+  return interior_box(s->g, s->fp32 && s->layer_mode == 1, s->tx);
+}
 
 // The frame launch can take the y/z layers when the fused box of the other modes
 // spans every x column (the x layers then stay in the box's own kernel) and some
 // y or z face has layers.  FP32 only (the FP64 kernel carries the x layers alone).
 bool split_ok(const mlk_sim* s) {
   if (!s->fp32 || (!has_cpml(s->g, 1) && !has_cpml(s->g, 2))) return false;
-  const Box b = interior_box(s->g, false);
+  const Box b = interior_box(s->g, false, s->tx);
   return b.lo[0] == 0 && b.hi[0] == s->g.n[0];
 }
 
@@ -833,16 +836,16 @@ bool split_ok(const mlk_sim* s) {
 // the frame launch (layer mode 2) or the two plain shell passes.
 template <typename T>
 hipError_t sweep_passes(const mlk_sim* s, const FieldPtrs<T>& a, const FieldPtrs<T>& ar,
-                        const FieldPtrs<T>& b, const Box& inner, int kz, int ty) {
+                        const FieldPtrs<T>& b, const Box& inner, int kz, int tx, int ty) {
   hipError_t e = hipSuccess;
   if constexpr (sizeof(T) == 4) {
-    e = sweep_fused_f32(ar, b, s->g, inner, kz, ty, s->stream);
+    e = sweep_fused_f32(ar, b, s->g, inner, kz, tx, ty, s->stream);
     if (e == hipSuccess && s->layer_mode == 2 && split_ok(s))
       return sweep_frame_f32(ar, b, s->g, inner, kFrameKz, s->stream);
     if (e == hipSuccess) e = sweep_shell_f32(a, b, s->g, inner, true, s->stream);
     if (e == hipSuccess) e = sweep_shell_f32(a, b, s->g, inner, false, s->stream);
   } else {
-    e = sweep_fused_f64(ar, b, s->g, inner, kz, ty, s->stream);
+    e = sweep_fused_f64(ar, b, s->g, inner, kz, tx, ty, s->stream);
     if (e == hipSuccess) e = sweep_shell_f64(a, b, s->g, inner, true, s->stream);
     if (e == hipSuccess) e = sweep_shell_f64(a, b, s->g, inner, false, s->stream);
   }
@@ -867,15 +870,15 @@ mlk_status sweep(mlk_sim* s) {
     if (f32 && s->layer_mode == 2 && split_ok(s)) {
       // the lean interior, then the layer frame in one launch of the full kernel
       int t0 = mark_begin(s, MLK_PHASE_SWEEP);
-      if constexpr (f32) HIPCHK(sweep_fused_f32(fr, nf, s->g, inner, s->kz, s->ty, s->stream));
+      if constexpr (f32) HIPCHK(sweep_fused_f32(fr, nf, s->g, inner, s->kz, s->tx, s->ty, s->stream));
       mark_end(s, MLK_PHASE_SWEEP, t0);
       t0 = mark_begin(s, MLK_PHASE_SHELL);
       if constexpr (f32) HIPCHK(sweep_frame_f32(fr, nf, s->g, inner, kFrameKz, s->stream));
       mark_end(s, MLK_PHASE_SHELL, t0);
     } else {
       int t0 = mark_begin(s, MLK_PHASE_SWEEP);
-      if constexpr (f32) HIPCHK(sweep_fused_f32(fr, nf, s->g, inner, s->kz, s->ty, s->stream));
-      else HIPCHK(sweep_fused_f64(fr, nf, s->g, inner, s->kz, s->ty, s->stream));
+      if constexpr (f32) HIPCHK(sweep_fused_f32(fr, nf, s->g, inner, s->kz, s->tx, s->ty, s->stream));
+      else HIPCHK(sweep_fused_f64(fr, nf, s->g, inner, s->kz, s->tx, s->ty, s->stream));
       mark_end(s, MLK_PHASE_SWEEP, t0);
       t0 = mark_begin(s, MLK_PHASE_SHELL);
       if constexpr (f32) {
@@ -2467,6 +2470,8 @@ mlk_status mlk_set_tls_dipoles(mlk_sim* s, int32_t first, int32_t count, const d
 
 namespace {
 
+constexpr int kTileSlots = 6;  // fused tile shapes a batch launches, see tile_slot
+
 template <typename J>
 struct DevTable {
   J* jobs = nullptr;
@@ -2535,8 +2540,8 @@ struct BatchTables {
   DevTable<FluxJob<T>> fsave, fpart, finish;
   DevTable<GatherJob<T>> gather;
   DevTable<LightJob<T>> light;  // the light bins' emitters
-  DevTable<FusedJob<T>> fused[3];  // by TY: 4, 8, 16
-  bool fused_lean[3] = {false, false, false};  // no job's box reaches a y or z layer
+  DevTable<FusedJob<T>> fused[kTileSlots];  // by tile shape, see tile_slot
+  bool fused_lean[kTileSlots] = {};  // no job's box reaches a y or z layer
   DevTable<ShellJob<T>> shell;
   DevTable<SourceJob<T>> sources;
   DevTable<ScatterJob<T>> scatter;
@@ -2553,7 +2558,10 @@ struct BatchTables {
   }
 };
 
-int ty_slot(int ty) { return ty == 16 ? 2 : (ty == 8 ? 1 : 0); }
+// Fused tile shapes (TX, TY): 64 x {4, 8, 16}, then 32 x {4, 8, 16}.
+int tile_slot(int tx, int ty) { return (tx == 32 ? 3 : 0) + (ty == 16 ? 2 : (ty == 8 ? 1 : 0)); }
+int slot_tx(int k) { return k < 3 ? 64 : 32; }
+int slot_ty(int k) { return 4 << (k % 3); }
 
 }  // namespace
 
@@ -2593,7 +2601,7 @@ mlk_status build_tables(mlk_batch* b, BatchTables<T> (&tab)[2]) {
   for (int q = 0; q < 2; ++q) {
     std::vector<FluxJob<T>> fs, fpj, fin;
     std::vector<GatherJob<T>> ga;
-    std::vector<FusedJob<T>> fu[3];
+    std::vector<FusedJob<T>> fu[kTileSlots];
     std::vector<ShellJob<T>> sh;
     std::vector<SourceJob<T>> so;
     std::vector<ScatterJob<T>> sc;
@@ -2632,9 +2640,10 @@ mlk_status build_tables(mlk_batch* b, BatchTables<T> (&tab)[2]) {
         J.g = s->g;
         J.box = inner;
         J.kz = s->kz;
+        J.tx = s->tx;
         J.ty = s->ty;
         fused_job_shape(J);
-        fu[ty_slot(s->ty)].push_back(J);
+        fu[tile_slot(s->tx, s->ty)].push_back(J);
       }
       ShellJob<T> S{};
       S.in = cur;
@@ -2663,7 +2672,7 @@ mlk_status build_tables(mlk_batch* b, BatchTables<T> (&tab)[2]) {
     STCHK(make_table(t.gather, ga));
     STCHK(make_order(t.gather, gw));
     STCHK(make_table(t.light, li));
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < kTileSlots; ++k) {
       STCHK(make_table(t.fused[k], fu[k]));
       bool lean = true;
       for (const FusedJob<T>& J : fu[k]) lean = lean && fused_cpm(J.g, J.box) <= 1;
@@ -2725,13 +2734,14 @@ mlk_status enqueue_batch_step(mlk_batch* b, const BatchTables<T>& t) {
   HIPCHK(tls_batch(b->tls.jobs, b->tls.start, b->tls.njobs, b->tls.nblocks, st));
   for (int n = 2; n <= kMaxLevels; ++n)
     HIPCHK(ml_batch(b->ml[n].jobs, b->ml[n].start, b->ml[n].njobs, b->ml[n].nblocks, n, st));
-  const int tys[3] = {4, 8, 16};
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < kTileSlots; ++k) {
     const DevTable<FusedJob<T>>& f = t.fused[k];
     if constexpr (f32)
-      HIPCHK(sweep_fused_batch_f32(f.jobs, f.start, f.njobs, f.nblocks, tys[k], t.fused_lean[k], st));
+      HIPCHK(sweep_fused_batch_f32(f.jobs, f.start, f.njobs, f.nblocks, slot_tx(k), slot_ty(k),
+                                   t.fused_lean[k], st));
     else
-      HIPCHK(sweep_fused_batch_f64(f.jobs, f.start, f.njobs, f.nblocks, tys[k], t.fused_lean[k], st));
+      HIPCHK(sweep_fused_batch_f64(f.jobs, f.start, f.njobs, f.nblocks, slot_tx(k), slot_ty(k),
+                                   t.fused_lean[k], st));
   }
   for (int h = 1; h >= 0; --h) {
     if constexpr (f32) HIPCHK(shell_batch_f32(t.shell.jobs, t.shell.start, t.shell.njobs,
@@ -2984,7 +2994,12 @@ struct TuneEntry {
   std::string key;
   int ty, kz, layers;
   double us;
+  int tx;
 };
+
+bool valid_entry(const TuneEntry& e) {
+  return (e.tx == 64 || e.tx == 32) && (e.ty == 4 || e.ty == 8 || e.ty == 16) && e.kz > 0;
+}
 
 std::vector<TuneEntry> read_cache(const char* path) {
   std::vector<TuneEntry> v;
@@ -2994,8 +3009,10 @@ std::vector<TuneEntry> read_cache(const char* path) {
   while (std::fgets(line, sizeof line, f)) {
     char key[200];
     TuneEntry e{};
-    if (std::sscanf(line, " \"%199[^\"]\": {\"ty\": %d, \"kz\": %d, \"layers\": %d, \"us\": %lf",
-                    key, &e.ty, &e.kz, &e.layers, &e.us) == 5) {
+    e.tx = 64;  // entries written before the tile width was tuned
+    if (std::sscanf(line,
+                    " \"%199[^\"]\": {\"ty\": %d, \"kz\": %d, \"layers\": %d, \"us\": %lf, \"tx\": %d",
+                    key, &e.ty, &e.kz, &e.layers, &e.us, &e.tx) >= 5) {
       e.key = key;
       v.push_back(e);
     }
@@ -3009,15 +3026,15 @@ bool write_cache(const char* path, const std::vector<TuneEntry>& v) {
   if (!f) return false;
   std::fprintf(f, "{\n");
   for (size_t q = 0; q < v.size(); ++q)
-    std::fprintf(f, "\"%s\": {\"ty\": %d, \"kz\": %d, \"layers\": %d, \"us\": %.3f}%s\n",
-                 v[q].key.c_str(), v[q].ty, v[q].kz, v[q].layers, v[q].us,
+    std::fprintf(f, "\"%s\": {\"ty\": %d, \"kz\": %d, \"layers\": %d, \"us\": %.3f, \"tx\": %d}%s\n",
+                 v[q].key.c_str(), v[q].ty, v[q].kz, v[q].layers, v[q].us, v[q].tx,
                  q + 1 < v.size() ? "," : "");
   std::fprintf(f, "}\n");
   return std::fclose(f) == 0;
 }
 
 template <typename T>
-mlk_status time_fused(mlk_sim* s, int ty, int kz, double* us) {
+mlk_status time_fused(mlk_sim* s, int tx, int ty, int kz, double* us) {
   const FieldPtrs<T> a = field_ptrs<T>(s), b = spare_ptrs<T>(s), ar = sweep_reads<T>(s);
   const Box inner = sweep_box(s);
   hipEvent_t e0, e1;
@@ -3027,7 +3044,7 @@ mlk_status time_fused(mlk_sim* s, int ty, int kz, double* us) {
   constexpr int kReps = 4;
   for (int r = -1; r < kReps && err == hipSuccess; ++r) {
     if (r == 0) err = hipEventRecord(e0, s->stream);
-    if (err == hipSuccess) err = sweep_passes<T>(s, a, ar, b, inner, kz, ty);
+    if (err == hipSuccess) err = sweep_passes<T>(s, a, ar, b, inner, kz, tx, ty);
   }
   if (err == hipSuccess) err = hipEventRecord(e1, s->stream);
   if (err == hipSuccess) err = hipEventSynchronize(e1);
@@ -3062,6 +3079,28 @@ mlk_status mlk_get_tuning(mlk_sim* s, int32_t* ty, int32_t* kz) {
   return MLK_OK;
 }
 
+mlk_status mlk_set_tile_width(mlk_sim* s, int32_t tx) {
+  if (!s) return fail(MLK_EINVAL, "null argument");
+  if (tx != 64 && tx != 32) return fail(MLK_EINVAL, "tile width %d: 64 or 32", tx);
+  if (s->in_batch) return fail(MLK_ESTATE, "tune members before forming the batch");
+  STCHK(sync_sim(s));
+  const int old = s->tx;
+  s->tx = tx;
+  // the frame launch needs a fused box over every x column, which depends on the width
+  if (s->layer_mode == 2 && !split_ok(s)) {
+    s->tx = old;
+    return fail(MLK_EUNSUPPORTED, "the frame launch needs a fused box spanning every x "
+                                  "column, which %d-wide tiles do not give here", tx);
+  }
+  return MLK_OK;
+}
+
+mlk_status mlk_get_tile_width(mlk_sim* s, int32_t* tx) {
+  if (!s || !tx) return fail(MLK_EINVAL, "null argument");
+  *tx = s->tx;
+  return MLK_OK;
+}
+
 mlk_status mlk_set_sweep_layers(mlk_sim* s, int32_t on) {
   if (!s) return fail(MLK_EINVAL, "null argument");
   if (s->in_batch) return fail(MLK_ESTATE, "tune members before forming the batch");
@@ -3089,7 +3128,8 @@ mlk_status mlk_autotune(mlk_sim* s, const char* cache_path) {
   const std::string key = tune_key(s);
   std::vector<TuneEntry> cache = read_cache(cache_path);
   for (const TuneEntry& e : cache)
-    if (e.key == key && (e.ty == 4 || e.ty == 8 || e.ty == 16) && e.kz > 0) {
+    if (e.key == key && valid_entry(e)) {
+      s->tx = e.tx;
       s->ty = e.ty;
       s->kz = e.kz;
       s->layer_mode = !s->fp32 ? 0 : (e.layers == 2 && !split_ok(s) ? 1 : e.layers);
@@ -3098,44 +3138,50 @@ mlk_status mlk_autotune(mlk_sim* s, const char* cache_path) {
   HIPCHK(hipSetDevice(s->desc.device));
   STCHK(sync_sim(s));
   // candidates: layer mode (FP32: with or without the y and z layers in the
-  // fused kernel) x rows per workgroup x planes per workgroup
+  // fused kernel, or in the frame launch) x tile width x rows per workgroup x
+  // planes per workgroup
   struct Cand {
-    int layers, ty, kz;
+    int layers, tx, ty, kz;
     double us;
   };
   std::vector<Cand> cands;
-  for (int lay = 0; lay <= (s->fp32 ? 2 : 0); ++lay) {
-    if (lay == 2 && !split_ok(s)) continue;
-    s->layer_mode = lay;
-    const Box inner = sweep_box(s);
-    const int ez = inner.hi[2] - inner.lo[2];
-    if (ez <= 0) continue;
-    for (int ty : {4, 8, 16})
-      for (int kz : {4, 8, 16, 32, 64, 128})
-        if (kz <= std::max(4, ez)) cands.push_back({lay, ty, kz, 1e300});
-  }
+  for (int lay = 0; lay <= (s->fp32 ? 2 : 0); ++lay)
+    for (int tx : {64, 32}) {
+      s->layer_mode = lay;
+      s->tx = tx;
+      if (lay == 2 && !split_ok(s)) continue;
+      const Box inner = sweep_box(s);
+      const int ez = inner.hi[2] - inner.lo[2];
+      if (ez <= 0) continue;
+      for (int ty : {4, 8, 16})
+        for (int kz : {4, 8, 16, 32, 64, 128})
+          if (kz <= std::max(4, ez)) cands.push_back({lay, tx, ty, kz, 1e300});
+    }
   for (int round = 0; round < 3; ++round)
     for (Cand& c : cands) {
       double us = 0.0;
       s->layer_mode = c.layers;
-      STCHK(s->fp32 ? time_fused<float>(s, c.ty, c.kz, &us)
-                    : time_fused<double>(s, c.ty, c.kz, &us));
+      s->tx = c.tx;
+      STCHK(s->fp32 ? time_fused<float>(s, c.tx, c.ty, c.kz, &us)
+                    : time_fused<double>(s, c.tx, c.ty, c.kz, &us));
       c.us = std::min(c.us, us);
     }
   double best = 1e300;
-  int blay = 0, bty = s->ty, bkz = s->kz;
+  int blay = 0, btx = 64, bty = s->ty, bkz = s->kz;
   for (const Cand& c : cands)
     if (c.us < best) {
       best = c.us;
       blay = c.layers;
+      btx = c.tx;
       bty = c.ty;
       bkz = c.kz;
     }
   s->layer_mode = blay;
+  s->tx = btx;
   s->ty = bty;
   s->kz = bkz;
   if (cache_path) {
-    cache.push_back({key, bty, bkz, blay, best});
+    cache.push_back({key, bty, bkz, blay, best, btx});
     if (!write_cache(cache_path, cache))
       return fail(MLK_EINVAL, "cannot write the tuning cache %s", cache_path);
   }
@@ -3157,14 +3203,15 @@ mlk_status time_batch_sweep(mlk_batch* b, const BatchTables<T>& t, double* us) {
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   hipError_t err = hipSuccess;
-  const int tys[3] = {4, 8, 16};
   auto once = [&]() {
-    for (int k = 0; k < 3 && err == hipSuccess; ++k) {
+    for (int k = 0; k < kTileSlots && err == hipSuccess; ++k) {
       const DevTable<FusedJob<T>>& f = t.fused[k];
       if constexpr (f32)
-        err = sweep_fused_batch_f32(f.jobs, f.start, f.njobs, f.nblocks, tys[k], t.fused_lean[k], st);
+        err = sweep_fused_batch_f32(f.jobs, f.start, f.njobs, f.nblocks, slot_tx(k), slot_ty(k),
+                                    t.fused_lean[k], st);
       else
-        err = sweep_fused_batch_f64(f.jobs, f.start, f.njobs, f.nblocks, tys[k], t.fused_lean[k], st);
+        err = sweep_fused_batch_f64(f.jobs, f.start, f.njobs, f.nblocks, slot_tx(k), slot_ty(k),
+                                    t.fused_lean[k], st);
     }
     for (int h = 1; h >= 0 && err == hipSuccess; --h) {
       if constexpr (f32)
@@ -3207,9 +3254,10 @@ std::string batch_key(const mlk_batch* b) {
   return k;
 }
 
-void set_members(mlk_batch* b, int layers, int ty, int kz) {
+void set_members(mlk_batch* b, int layers, int tx, int ty, int kz) {
   for (mlk_sim* s : b->sims) {
     s->layer_mode = b->fp32 && layers != 0 ? 1 : 0;
+    s->tx = tx;
     s->ty = ty;
     s->kz = kz;
   }
@@ -3233,21 +3281,22 @@ mlk_status mlk_batch_autotune(mlk_batch* b, const char* cache_path) {
   const std::string key = batch_key(b);
   std::vector<TuneEntry> cache = read_cache(cache_path);
   for (const TuneEntry& e : cache)
-    if (e.key == key && (e.ty == 4 || e.ty == 8 || e.ty == 16) && e.kz > 0) {
-      set_members(b, e.layers, e.ty, e.kz);
+    if (e.key == key && valid_entry(e)) {
+      set_members(b, e.layers, e.tx, e.ty, e.kz);
       return rebuild_tables(b);
     }
   struct Cand {
-    int layers, ty, kz;
+    int layers, tx, ty, kz;
     double us;
   };
   std::vector<Cand> cands;
   for (int lay = 0; lay <= (b->fp32 ? 1 : 0); ++lay)
-    for (int ty : {4, 8, 16})
-      for (int kz : {4, 8, 16, 32}) cands.push_back({lay, ty, kz, 1e300});
+    for (int tx : {64, 32})
+      for (int ty : {4, 8, 16})
+        for (int kz : {4, 8, 16, 32}) cands.push_back({lay, tx, ty, kz, 1e300});
   for (int round = 0; round < 3; ++round)
     for (Cand& c : cands) {
-      set_members(b, c.layers, c.ty, c.kz);
+      set_members(b, c.layers, c.tx, c.ty, c.kz);
       STCHK(rebuild_tables(b));
       double us = 0.0;
       STCHK(b->fp32 ? time_batch_sweep<float>(b, b->t32[0], &us)
@@ -3257,10 +3306,10 @@ mlk_status mlk_batch_autotune(mlk_batch* b, const char* cache_path) {
   const Cand* best = &cands[0];
   for (const Cand& c : cands)
     if (c.us < best->us) best = &c;
-  set_members(b, best->layers, best->ty, best->kz);
+  set_members(b, best->layers, best->tx, best->ty, best->kz);
   STCHK(rebuild_tables(b));
   if (cache_path) {
-    cache.push_back({key, best->ty, best->kz, best->layers, best->us});
+    cache.push_back({key, best->ty, best->kz, best->layers, best->us, best->tx});
     if (!write_cache(cache_path, cache))
       return fail(MLK_EINVAL, "cannot write the tuning cache %s", cache_path);
   }

@@ -10,7 +10,8 @@
 //    The host takes a full x extent only when no tile's low-x halo column lies
 //    in an x layer (else x is limited to the cells clear of the layers plus a
 //    margin, and the plain passes update the rest).
-//  * y layers are whole rows (one wavefront each) and z layers whole planes:
+//  * y layers are whole rows (a wavefront each in 64-wide tiles, half of one in
+//    32-wide tiles) and z layers whole planes:
 //    the coefficients of the tile's rows sit in LDS, those of a plane are
 //    uniform loads, and psi (own cell and the halo cells of the curl) is
 //    prefetched a plane ahead in branches uniform across a wavefront or the
@@ -21,7 +22,7 @@
 // (vector memory counters retire in order).
 // Source and molecular currents are added by their own passes.
 //
-// A workgroup owns a tile of 64 x TY columns and marches over a chunk of z
+// A workgroup owns a tile of TX x TY columns (TX = 64 or 32) and marches over a chunk of z
 // planes.  For plane k it stages E^n(k+1) (with a one-cell halo ring) in LDS,
 // computes H^{n+1/2}(k) on the tile plus the low-x / low-y halo that the curl
 // of H needs (the halo H is recomputed here rather than read from a
@@ -40,8 +41,10 @@ namespace mlk {
 
 // CPM: the CPML code compiled in: 0 none, 1 the x layers, 2 every axis (FP32; the
 // FP64 kernel carries the x layers only).  Fewer layers, fewer registers: about 71
-// VGPRs without any in FP32, against 118 with all of them.
-template <typename T, int TY, int CPM = 2>
+// VGPRs without any in FP32, against 118 with all of them.  TX, the tile width, is
+// 64 (a row per wavefront) or 32 (two rows per wavefront: narrower tiles, more of
+// them, for domains too small to give 64-wide tiles enough workgroups).
+template <typename T, int TX, int TY, int CPM = 2>
 __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtrs<T>& b,
                                            const Geom& g, const Box& box, int kz, int ntx,
                                            int nty, int nblocks, int bid_in) {
@@ -49,13 +52,14 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
   // neighbours (CPML stretching included); both must round alike, so no product
   // is contracted into a fused multiply-add here, whatever the code around it.
 #pragma clang fp contract(off)
-  constexpr int EW = 66, EH = TY + 2;   // E plane in LDS: x in [-1, 64], y in [-1, TY]
-  constexpr int HW = 65, HH = TY + 1;   // H plane in LDS: x in [-1, 63], y in [-1, TY-1]
+  static_assert(TX == 64 || TX == 32, "tiles are 64 or 32 cells wide");
+  constexpr int EW = TX + 2, EH = TY + 2;  // E plane in LDS: x in [-1, TX], y in [-1, TY]
+  constexpr int HW = TX + 1, HH = TY + 1;  // H plane in LDS: x in [-1, TX-1], y in [-1, TY-1]
   constexpr int NHALO = 2 * EW + 2 * TY;  // ring of the E plane
-  static_assert(64 * TY >= NHALO, "one thread per ring slot of the staged E plane");
+  static_assert(TX * TY >= NHALO, "one thread per ring slot of the staged E plane");
   __shared__ T eL[2][3][EH * EW];
   __shared__ T hL[3][HH * HW];
-  __shared__ T xc[2][3][64];  // x CPML b, c, 1/kappa of the tile's columns (E, H positions)
+  __shared__ T xc[2][3][TX];  // x CPML b, c, 1/kappa of the tile's columns (E, H positions)
   __shared__ T yc[2][3][TY + 1];  // y CPML b, c, 1/kappa of rows y0-1 .. y0+TY-1
 
   int tile_x, tile_y, chunk;
@@ -68,7 +72,7 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
     // to consecutive XCDs (workgroups are dealt to the 8 XCDs in turn), which spreads
     // the heavy ones evenly, and the x tiles of one row run one after another on the
     // same XCD: the cache lines that neighbouring x tiles share (the E ring's x = -1
-    // and x = 64 columns, the halo H column) are then read once into that XCD's L2.
+    // and x = TX columns, the halo H column) are then read once into that XCD's L2.
     auto fold = [](int q, int n) { return (q & 1) ? n - 1 - (q >> 1) : (q >> 1); };
     const int nch = nblocks / (ntx * nty);
     int r;
@@ -95,10 +99,10 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
   // x tiles start on a 128-byte boundary at or below the box; the extra cells
   // below box.lo[0] are updated too (they belong to the CPML shell, whose own
   // pass overwrites them)
-  const int x0 = (box.lo[0] & ~31) + tile_x * 64, y0 = box.lo[1] + tile_y * TY;
+  const int x0 = (box.lo[0] & ~31) + tile_x * TX, y0 = box.lo[1] + tile_y * TY;
   const int k0 = box.lo[2] + chunk * kz, k1 = min(k0 + kz, box.hi[2]);
 
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6, tid = threadIdx.x;
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX, tid = threadIdx.x;
   const int i = x0 + tx, j = y0 + ty;
   const bool own = i < box.hi[0] && j < box.hi[1];
   const T dt = (T)g.dt, idx = (T)g.inv_dx;
@@ -120,12 +124,12 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
     } else {
       const int c2 = tid - 2 * EW;
       ys = c2 >> 1;
-      xs = (c2 & 1) ? 64 : -1;
+      xs = (c2 & 1) ? TX : -1;
     }
     rslot = (ys + 1) * EW + xs + 1;
     rcol = column(g, x0 + xs, y0 + ys);
   }
-  // halo H columns: x0-1 (lane 0 of every wave), y0-1 (first wave)
+  // halo H columns: x0-1 (first lane of every row), y0-1 (first row)
   const bool hx_on = tx == 0 && j < box.hi[1] && (x0 > 0 || g.periodic[0]);
   const int ih = x0 > 0 ? x0 - 1 : g.n[0] - 1;
   const bool hy_on = ty == 0 && i < box.hi[0] && (y0 > 0 || g.periodic[1]);
@@ -198,7 +202,7 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
     }
   }
   if (YZ && has_cpml(g, 1)) {
-    for (int t = tid; t < 2 * 3 * (TY + 1); t += 64 * TY) {
+    for (int t = tid; t < 2 * 3 * (TY + 1); t += TX * TY) {
       const int fld = t / (3 * (TY + 1)), w = (t / (TY + 1)) % 3, r = t % (TY + 1);
       const int q = y0 - 1 + r;
       yc[fld][w][r] = (q >= 0 && q < g.n[1] && in_layer(g, 1, q))
@@ -395,7 +399,7 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
     hL[0][(ty + 1) * HW + tx + 1] = hx;
     hL[1][(ty + 1) * HW + tx + 1] = hy;
     hL[2][(ty + 1) * HW + tx + 1] = hz;
-    // halo H at x0-1 (Hy, Hz) for the own row, by lane 0 of each wave
+    // halo H at x0-1 (Hy, Hz) for the own row, by its first lane
     if (tx == 0) {
       T hyh = T(0), hzh = T(0);
       if (hx_on) {
@@ -412,7 +416,7 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
       hL[1][(ty + 1) * HW] = hyh;
       hL[2][(ty + 1) * HW] = hzh;
     }
-    // halo H at y0-1 (Hx, Hz) for the own column, by the first wave
+    // halo H at y0-1 (Hx, Hz) for the own column, by the first row
     if (ty == 0) {
       T hxh = T(0), hzh = T(0);
       if (hy_on) {
@@ -484,80 +488,77 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
   }
 }
 
-template <typename T, int TY>
-__global__ __launch_bounds__(64 * TY, 4) void k_fused(FieldPtrs<T> a, FieldPtrs<T> b, Geom g,
+template <typename T, int TX, int TY>
+__global__ __launch_bounds__(TX * TY, 4) void k_fused(FieldPtrs<T> a, FieldPtrs<T> b, Geom g,
                                                    Box box, int kz, int ntx, int nty,
                                                    int nblocks) {
-  fused_body<T, TY>(a, b, g, box, kz, ntx, nty, nblocks, blockIdx.x);
+  fused_body<T, TX, TY>(a, b, g, box, kz, ntx, nty, nblocks, blockIdx.x);
 }
 
 // Boxes where no y or z layer needs stretching (x layers at most): the same body
 // without the y/z layer code, built for more waves per SIMD.
-template <typename T, int TY, int CPM, int W>
-__global__ __launch_bounds__(64 * TY, W) void k_fused_lean(FieldPtrs<T> a, FieldPtrs<T> b, Geom g,
+template <typename T, int TX, int TY, int CPM, int W>
+__global__ __launch_bounds__(TX * TY, W) void k_fused_lean(FieldPtrs<T> a, FieldPtrs<T> b, Geom g,
                                                         Box box, int kz, int ntx, int nty,
                                                         int nblocks) {
-  fused_body<T, TY, CPM>(a, b, g, box, kz, ntx, nty, nblocks, blockIdx.x);
+  fused_body<T, TX, TY, CPM>(a, b, g, box, kz, ntx, nty, nblocks, blockIdx.x);
 }
 
 // The frame of y and z layers around such a box, up to four boxes in one launch
-// (full kernel, TY = 4): block b belongs to the job whose start range holds it.
+// (full kernel, 64 x 4 tiles): block b belongs to the job whose start range holds it.
 template <typename T>
 __global__ __launch_bounds__(256, 4) void k_fused_frame(FrameJobs<T> fj) {
   int j = 0;
   while (j + 1 < fj.njobs && (int)blockIdx.x >= fj.start[j + 1]) ++j;
   const FusedJob<T>& J = fj.job[j];
-  fused_body<T, 4>(J.a, J.b, J.g, J.box, J.kz, J.ntx, J.nty, J.nblocks,
+  fused_body<T, 64, 4>(J.a, J.b, J.g, J.box, J.kz, J.ntx, J.nty, J.nblocks,
                    (int)blockIdx.x - fj.start[j]);
 }
 
 // One launch over the jobs of a batch of domains (see BatchJobs); CPM and W as for
 // the single-domain kernels (the lean form when no job's box reaches a y or z layer).
-template <typename T, int TY, int CPM, int W>
-__global__ __launch_bounds__(64 * TY, W) void k_fused_batch(const FusedJob<T>* jobs,
+template <typename T, int TX, int TY, int CPM, int W>
+__global__ __launch_bounds__(TX * TY, W) void k_fused_batch(const FusedJob<T>* jobs,
                                                          const int* start, int njobs) {
   const int j = find_job(start, njobs, blockIdx.x);
   const FusedJob<T> J = load_job(jobs, j);
   const int bid = blockIdx.x - start[j];
-  if (J.ty != TY || bid >= J.nblocks) return;
-  fused_body<T, TY, CPM>(J.a, J.b, J.g, J.box, J.kz, J.ntx, J.nty, J.nblocks, bid);
+  if (J.tx != TX || J.ty != TY || bid >= J.nblocks) return;
+  fused_body<T, TX, TY, CPM>(J.a, J.b, J.g, J.box, J.kz, J.ntx, J.nty, J.nblocks, bid);
 }
 
-// Waves per SIMD the lean kernel is built for (registers permitting): with no CPML
-// code it needs about 71 VGPRs in FP32, so blocks of 256 or 512 threads run six or
-// more waves per SIMD against four for the full kernel.
 // Waves per SIMD the lean kernels are built for: FP32 without layer code needs about
 // 71 VGPRs (six waves), with the x layers 87 (five); FP64 and 1024-thread blocks four.
-template <typename T, int TY, int CPM>
+template <typename T, int TX, int TY, int CPM>
 struct LeanWaves {
-  static constexpr int value = (sizeof(T) == 4 && TY < 16) ? (CPM == 0 ? 6 : 5) : 4;
+  static constexpr int value = (sizeof(T) == 4 && TX * TY < 1024) ? (CPM == 0 ? 6 : 5) : 4;
 };
 
 // cpm: 0 no layer code (no CPML face), 1 x layers only (the box keeps clear of the y
 // and z layers), 2 the full kernel
-template <typename T, int TY>
+template <typename T, int TX, int TY>
 static hipError_t launch_fused(const FieldPtrs<T>& a, const FieldPtrs<T>& b, const Geom& g,
                                const Box& box, int kz, int cpm, hipStream_t st) {
   const int ex = box.hi[0] - box.lo[0], ey = box.hi[1] - box.lo[1], ez = box.hi[2] - box.lo[2];
   if (ex <= 0 || ey <= 0 || ez <= 0) return hipSuccess;
-  const int ntx = (box.hi[0] - (box.lo[0] & ~31) + 63) / 64, nty = (ey + TY - 1) / TY;
+  const int ntx = (box.hi[0] - (box.lo[0] & ~31) + TX - 1) / TX, nty = (ey + TY - 1) / TY;
   const int nch = (ez + kz - 1) / kz;
   const int nblocks = ntx * nty * nch;
-  constexpr int W0 = LeanWaves<T, TY, 0>::value, W1 = LeanWaves<T, TY, 1>::value;
+  constexpr int W0 = LeanWaves<T, TX, TY, 0>::value, W1 = LeanWaves<T, TX, TY, 1>::value;
   if (cpm == 0)
-    hipLaunchKernelGGL((k_fused_lean<T, TY, 0, W0>), dim3(nblocks), dim3(64 * TY), 0, st, a, b,
-                       g, box, kz, ntx, nty, nblocks);
+    hipLaunchKernelGGL((k_fused_lean<T, TX, TY, 0, W0>), dim3(nblocks), dim3(TX * TY), 0, st, a,
+                       b, g, box, kz, ntx, nty, nblocks);
   else if (cpm == 1)
-    hipLaunchKernelGGL((k_fused_lean<T, TY, 1, W1>), dim3(nblocks), dim3(64 * TY), 0, st, a, b,
-                       g, box, kz, ntx, nty, nblocks);
+    hipLaunchKernelGGL((k_fused_lean<T, TX, TY, 1, W1>), dim3(nblocks), dim3(TX * TY), 0, st, a,
+                       b, g, box, kz, ntx, nty, nblocks);
   else
-    hipLaunchKernelGGL((k_fused<T, TY>), dim3(nblocks), dim3(64 * TY), 0, st, a, b, g, box, kz,
-                       ntx, nty, nblocks);
+    hipLaunchKernelGGL((k_fused<T, TX, TY>), dim3(nblocks), dim3(TX * TY), 0, st, a, b, g, box,
+                       kz, ntx, nty, nblocks);
   return hipGetLastError();
 }
 
-// Tile grid of the fused kernel over a box: x tiles of 64 from the 128-byte
-// boundary at or below box.lo, y tiles of TY, z chunks of kz planes.
+// Tile grid of the fused kernel over a box: x tiles of J.tx from the 128-byte
+// boundary at or below box.lo, y tiles of J.ty, z chunks of J.kz planes.
 template <typename T>
 void fused_job_shape(FusedJob<T>& J) {
   const Box& box = J.box;
@@ -566,7 +567,7 @@ void fused_job_shape(FusedJob<T>& J) {
     J.ntx = J.nty = J.nblocks = 0;
     return;
   }
-  J.ntx = (box.hi[0] - (box.lo[0] & ~31) + 63) / 64;
+  J.ntx = (box.hi[0] - (box.lo[0] & ~31) + J.tx - 1) / J.tx;
   J.nty = (ey + J.ty - 1) / J.ty;
   J.nblocks = J.ntx * J.nty * ((ez + J.kz - 1) / J.kz);
 }
@@ -586,18 +587,25 @@ int fused_cpm(const Geom& g, const Box& box) {
   return has_cpml(g, 0) ? 1 : 0;
 }
 
+template <typename T, int TX>
+static hipError_t launch_fused_tx(const FieldPtrs<T>& a, const FieldPtrs<T>& b, const Geom& g,
+                                  const Box& box, int kz, int ty, int cpm, hipStream_t st) {
+  if (ty == 16) return launch_fused<T, TX, 16>(a, b, g, box, kz, cpm, st);
+  if (ty == 8) return launch_fused<T, TX, 8>(a, b, g, box, kz, cpm, st);
+  return launch_fused<T, TX, 4>(a, b, g, box, kz, cpm, st);
+}
+
 template <typename T>
 static hipError_t launch_fused_any(const FieldPtrs<T>& a, const FieldPtrs<T>& b, const Geom& g,
-                                   const Box& box, int kz, int ty, hipStream_t st) {
+                                   const Box& box, int kz, int tx, int ty, hipStream_t st) {
   const int cpm = fused_cpm(g, box);
-  if (ty == 16) return launch_fused<T, 16>(a, b, g, box, kz, cpm, st);
-  if (ty == 8) return launch_fused<T, 8>(a, b, g, box, kz, cpm, st);
-  return launch_fused<T, 4>(a, b, g, box, kz, cpm, st);
+  if (tx == 32) return launch_fused_tx<T, 32>(a, b, g, box, kz, ty, cpm, st);
+  return launch_fused_tx<T, 64>(a, b, g, box, kz, ty, cpm, st);
 }
 
 // The y/z layer frame around an interior box: up to four boxes (the z slabs over
 // the whole x-y plane, the y slabs over the box's z range), one launch of the full
-// kernel with TY = 4.  The slabs are thin, so their chunks are short to give the
+// kernel with 64 x 4 tiles.  The slabs are thin, so their chunks are short to give the
 // launch enough workgroups: kz planes in the y slabs, four in the z slabs.
 template <typename T>
 static hipError_t launch_frame(const FieldPtrs<T>& a, const FieldPtrs<T>& b, const Geom& g,
@@ -623,6 +631,7 @@ static hipError_t launch_frame(const FieldPtrs<T>& a, const FieldPtrs<T>& b, con
     J.b = b;
     J.g = g;
     J.box = boxes[q];
+    J.tx = 64;
     J.ty = 4;
     const int ez = boxes[q].hi[2] - boxes[q].lo[2];
     J.kz = std::max(1, std::min(q < 2 ? 4 : kz, ez));
@@ -638,34 +647,41 @@ static hipError_t launch_frame(const FieldPtrs<T>& a, const FieldPtrs<T>& b, con
   return hipGetLastError();
 }
 
-template <typename T, int TY>
-static void launch_fused_batch_ty(const FusedJob<T>* jobs, const int* start, int njobs,
-                                  int nblocks, bool lean, hipStream_t st) {
+template <typename T, int TX, int TY>
+static void launch_fused_batch_t(const FusedJob<T>* jobs, const int* start, int njobs,
+                                 int nblocks, bool lean, hipStream_t st) {
   if (lean)
-    hipLaunchKernelGGL((k_fused_batch<T, TY, 1, LeanWaves<T, TY, 1>::value>), dim3(nblocks),
-                       dim3(64 * TY), 0, st, jobs, start, njobs);
+    hipLaunchKernelGGL((k_fused_batch<T, TX, TY, 1, LeanWaves<T, TX, TY, 1>::value>),
+                       dim3(nblocks), dim3(TX * TY), 0, st, jobs, start, njobs);
   else
-    hipLaunchKernelGGL((k_fused_batch<T, TY, 2, 4>), dim3(nblocks), dim3(64 * TY), 0, st, jobs,
-                       start, njobs);
+    hipLaunchKernelGGL((k_fused_batch<T, TX, TY, 2, 4>), dim3(nblocks), dim3(TX * TY), 0, st,
+                       jobs, start, njobs);
+}
+
+template <typename T, int TX>
+static void launch_fused_batch_tx(const FusedJob<T>* jobs, const int* start, int njobs,
+                                  int nblocks, int ty, bool lean, hipStream_t st) {
+  if (ty == 16) launch_fused_batch_t<T, TX, 16>(jobs, start, njobs, nblocks, lean, st);
+  else if (ty == 8) launch_fused_batch_t<T, TX, 8>(jobs, start, njobs, nblocks, lean, st);
+  else launch_fused_batch_t<T, TX, 4>(jobs, start, njobs, nblocks, lean, st);
 }
 
 template <typename T>
 static hipError_t launch_fused_batch(const FusedJob<T>* jobs, const int* start, int njobs,
-                                     int nblocks, int ty, bool lean, hipStream_t st) {
+                                     int nblocks, int tx, int ty, bool lean, hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
-  if (ty == 16) launch_fused_batch_ty<T, 16>(jobs, start, njobs, nblocks, lean, st);
-  else if (ty == 8) launch_fused_batch_ty<T, 8>(jobs, start, njobs, nblocks, lean, st);
-  else launch_fused_batch_ty<T, 4>(jobs, start, njobs, nblocks, lean, st);
+  if (tx == 32) launch_fused_batch_tx<T, 32>(jobs, start, njobs, nblocks, ty, lean, st);
+  else launch_fused_batch_tx<T, 64>(jobs, start, njobs, nblocks, ty, lean, st);
   return hipGetLastError();
 }
 
 hipError_t sweep_fused_f64(const FieldPtrs<double>& a, const FieldPtrs<double>& b, const Geom& g,
-                           const Box& box, int kz, int ty, hipStream_t st) {
-  return launch_fused_any<double>(a, b, g, box, kz, ty, st);
+                           const Box& box, int kz, int tx, int ty, hipStream_t st) {
+  return launch_fused_any<double>(a, b, g, box, kz, tx, ty, st);
 }
 hipError_t sweep_fused_f32(const FieldPtrs<float>& a, const FieldPtrs<float>& b, const Geom& g,
-                           const Box& box, int kz, int ty, hipStream_t st) {
-  return launch_fused_any<float>(a, b, g, box, kz, ty, st);
+                           const Box& box, int kz, int tx, int ty, hipStream_t st) {
+  return launch_fused_any<float>(a, b, g, box, kz, tx, ty, st);
 }
 hipError_t sweep_frame_f64(const FieldPtrs<double>& a, const FieldPtrs<double>& b, const Geom& g,
                            const Box& inner, int kz, hipStream_t st) {
@@ -676,12 +692,12 @@ hipError_t sweep_frame_f32(const FieldPtrs<float>& a, const FieldPtrs<float>& b,
   return launch_frame<float>(a, b, g, inner, kz, st);
 }
 hipError_t sweep_fused_batch_f64(const FusedJob<double>* jobs, const int* start, int njobs,
-                                 int nblocks, int ty, bool lean, hipStream_t st) {
-  return launch_fused_batch<double>(jobs, start, njobs, nblocks, ty, lean, st);
+                                 int nblocks, int tx, int ty, bool lean, hipStream_t st) {
+  return launch_fused_batch<double>(jobs, start, njobs, nblocks, tx, ty, lean, st);
 }
 hipError_t sweep_fused_batch_f32(const FusedJob<float>* jobs, const int* start, int njobs,
-                                 int nblocks, int ty, bool lean, hipStream_t st) {
-  return launch_fused_batch<float>(jobs, start, njobs, nblocks, ty, lean, st);
+                                 int nblocks, int tx, int ty, bool lean, hipStream_t st) {
+  return launch_fused_batch<float>(jobs, start, njobs, nblocks, tx, ty, lean, st);
 }
 
 }  // namespace mlk

@@ -141,6 +141,8 @@ def lib():
         "mlk_autotune": (st, [sim, C.c_char_p]),
         "mlk_set_tuning": (st, [sim, C.c_int32, C.c_int32]),
         "mlk_get_tuning": (st, [sim, _ip, _ip]),
+        "mlk_set_tile_width": (st, [sim, C.c_int32]),
+        "mlk_get_tile_width": (st, [sim, _ip]),
         "mlk_set_sweep_layers": (st, [sim, C.c_int32]),
         "mlk_get_sweep_layers": (st, [sim, _ip]),
         "mlk_stream_copy": (st, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32, C.c_int32,
@@ -171,7 +173,8 @@ def exported_symbols():
             "mlk_get_interior_box", "mlk_batch_create", "mlk_batch_step", "mlk_batch_capture",
             "mlk_batch_replay", "mlk_batch_sync", "mlk_batch_destroy", "mlk_batch_autotune",
             "mlk_autotune",
-            "mlk_set_tuning", "mlk_get_tuning", "mlk_set_sweep_layers", "mlk_get_sweep_layers", "mlk_adjoint", "mlk_set_eps_box",
+            "mlk_set_tuning", "mlk_get_tuning", "mlk_set_tile_width", "mlk_get_tile_width",
+            "mlk_set_sweep_layers", "mlk_get_sweep_layers", "mlk_adjoint", "mlk_set_eps_box",
             "mlk_set_tls_dipoles", "mlk_get_adjoint_times", "mlk_stream_copy",
             "mlk_buffer_bytes", "mlk_bind_device_buffers", "mlk_get_field_set"]
 
@@ -630,9 +633,10 @@ class Simulation:
 
     # ------------------------------------------------------------ tuning
     def autotune(self, cache_path=None):
-        """Pick the fused sweep's tile shape by timing (optionally cached in JSON)."""
+        """Pick the fused sweep's tile shape by timing (optionally cached in JSON);
+        returns (ty, kz, tile width)."""
         _check(lib().mlk_autotune(self._h, cache_path.encode() if cache_path else None))
-        return self.tuning()
+        return self.tuning() + (self.tile_width(),)
 
     def tuning(self):
         ty, kz = C.c_int32(), C.c_int32()
@@ -641,6 +645,15 @@ class Simulation:
 
     def set_tuning(self, ty, kz):
         _check(lib().mlk_set_tuning(self._h, int(ty), int(kz)))
+
+    def tile_width(self):
+        """x cells per workgroup of the fused sweep: 64 or 32."""
+        tx = C.c_int32()
+        _check(lib().mlk_get_tile_width(self._h, C.byref(tx)))
+        return tx.value
+
+    def set_tile_width(self, tx):
+        _check(lib().mlk_set_tile_width(self._h, int(tx)))
 
     def sweep_layers(self):
         """Where the fused sweep updates the y and z CPML layers (FP32): 0 the plain shell
@@ -679,10 +692,10 @@ class Batch:
 
     def autotune(self, cache_path=None):
         """One tile shape and layer mode for every member, chosen by timing the batch's
-        sweep phase (optionally cached in JSON); returns (ty, kz, layers)."""
+        sweep phase (optionally cached in JSON); returns (ty, kz, layers, tile width)."""
         _check(lib().mlk_batch_autotune(self._h, cache_path.encode() if cache_path else None))
         ty, kz = self.sims[0].tuning()
-        return ty, kz, self.sims[0].sweep_layers()
+        return ty, kz, self.sims[0].sweep_layers(), self.sims[0].tile_width()
 
     def close(self):
         if getattr(self, "_h", None):

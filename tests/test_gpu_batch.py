@@ -128,9 +128,10 @@ def test_batch_autotune_changes_speed_not_results(precision, tmp_path):
         b.step(5)  # odd: the members' buffers are swapped when the tuner runs
         b.capture(4)
         t = b.autotune(cache)
-        say(f"  batch tuned (ty, kz, layers) = {t}")
-        assert t[0] in (4, 8, 16) and t[1] in (4, 8, 16, 32)
-        assert all(m.tuning() == t[:2] and m.sweep_layers() == t[2] for m in mem)
+        say(f"  batch tuned (ty, kz, layers, tx) = {t}")
+        assert t[0] in (4, 8, 16) and t[1] in (4, 8, 16, 32) and t[3] in (64, 32)
+        assert all(m.tuning() == t[:2] and m.sweep_layers() == t[2] and m.tile_width() == t[3]
+                   for m in mem)
         assert precision == "fp32" or not t[2]
         b.step(7)
         b.replay(2)  # captures again on the new tables
@@ -164,6 +165,32 @@ def test_member_cannot_be_destroyed_while_batched():
     mem[0].close()
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batch_mixed_tile_shapes(precision):
+    """Members tuned alone to different tile shapes (64 or 32 wide, 4, 8 or 16 rows) go
+    to different fused launches of the batch; each still steps as it does alone."""
+    ws = domains(precision, seed=11)
+    shapes = [(64, 8, 8), (32, 4, 16), (32, 16, 5), (64, 4, 32)]
+    solo = [mlk().from_workload(w) for w in ws]
+    mem = [mlk().from_workload(w) for w in ws]
+    for s, m, (tx, ty, kz) in zip(solo, mem, shapes):
+        for x in (s, m):
+            x.set_tile_width(tx)
+            x.set_tuning(ty, kz)
+    say(f"[batch] {precision} mixed tiles {shapes}")
+    with mlk().Batch(mem) as b:
+        b.step(6)
+        b.capture(4)
+        b.replay(2)
+        b.sync()
+        with pytest.raises(mlk().MlkError):
+            mem[0].set_tile_width(32)  # members are tuned before the batch forms
+    for s in solo:
+        s.step(14)
+    for s, m, w in zip(solo, mem, ws):
+        compare(s, m, w)
+
+
 def test_tile_shape_changes_speed_not_results(tmp_path):
     w = W.radiating_cube(n=72, n_emit=300, steps=0, cpml=10, precision="fp32")
     a = mlk().from_workload(w)
@@ -171,15 +198,26 @@ def test_tile_shape_changes_speed_not_results(tmp_path):
     b.set_tuning(16, 5)
     c = mlk().from_workload(w)
     c.set_tuning(8, 64)
-    for s in (a, b, c):
+    e = mlk().from_workload(w)
+    e.set_tile_width(32)
+    e.set_tuning(8, 16)
+    f = mlk().from_workload(w)
+    f.set_tile_width(32)
+    f.set_tuning(16, 3)
+    assert a.tile_width() == 64 and e.tile_width() == 32
+    for s in (a, b, c, e, f):
         s.step(25)
-    assert same(a.fields(), b.fields()) and same(a.fields(), c.fields())
+    for s in (b, c, e, f):
+        assert same(a.fields(), s.fields())
     with pytest.raises(mlk().MlkError):
         c.set_tuning(2, 8)  # a 64 x 2 workgroup cannot stage the halo ring
+    for bad in (16, 48, 128):
+        with pytest.raises(mlk().MlkError):
+            c.set_tile_width(bad)
     cache = str(tmp_path / "tune.json")
     t = a.autotune(cache)
-    say(f"  autotuned (ty, kz) = {t}")
-    assert t[0] in (4, 8, 16) and t[1] >= 1
+    say(f"  autotuned (ty, kz, tx) = {t}")
+    assert t[0] in (4, 8, 16) and t[1] >= 1 and t[2] in (64, 32)
     d = mlk().from_workload(w)
     assert d.autotune(cache) == t  # read back from the cache, layer mode included
     assert d.sweep_layers() == a.sweep_layers()

@@ -132,17 +132,20 @@ def test_fused_sweep_many_tiles_and_chunks_fp64():
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
-@pytest.mark.parametrize("nx, full", [(72, True), (70, False)])
-def test_fused_box_layers_and_fallback(nx, full, precision):
+@pytest.mark.parametrize("nx, tx, full", [(72, 64, True), (70, 64, False), (72, 32, True),
+                                          (36, 64, True), (36, 32, False)])
+def test_fused_box_layers_and_fallback(nx, tx, full, precision):
     """With FP32 fields and the layer mode on, the fused sweep covers the whole grid and
     stretches the derivatives of the CPML cells itself; the FP64 kernel carries the x
     layers only (its y and z extent stops at the layers, with a margin).  The x layers go
-    to the plain passes when the low-x halo column of a 64-wide tile falls into one
-    (nx = 70 with 8 layers: the second tile's halo column x = 63 is a layer cell).  All
-    four boxes against the oracle."""
+    to the plain passes when the low-x halo column of a tile falls into one (nx = 70
+    with 8 layers: the second 64-wide tile's halo column x = 63 is a layer cell; nx = 36:
+    one 64-wide tile, but the second 32-wide tile's halo column x = 31 is).  Every box
+    against the oracle."""
     w = _sources_workload((nx, 30, 36), ("cpml",) * 6, (8, 8, 6, 7, 8, 6), precision, 150)
-    say(f"[parity] {w.name} precision={precision} layers in the fused sweep")
+    say(f"[parity] {w.name} precision={precision} tile width {tx} layers in the fused sweep")
     sim = mlk().from_workload(w, sweep="fused")
+    sim.set_tile_width(tx)
     if precision == "fp32":
         sim.set_sweep_layers(True)
     lo, hi = sim.interior_box()
@@ -159,18 +162,23 @@ def test_fused_box_layers_and_fallback(nx, full, precision):
 def test_sweep_decompositions_agree_bitwise(precision):
     """The plain sweep, the fused sweep with the CPML shell, and (FP32) the fused sweep
     carrying every layer, or its lean kernel on the interior with the layer frame in one
-    launch of the full kernel, give the same fields bit for bit: each cell's arithmetic
-    is the same expression, rounded alike, whichever kernel evaluates it.  In vacuum the
+    launch of the full kernel, in 64- or 32-wide tiles, give the same fields bit for bit:
+    each cell's arithmetic is the same expression, rounded alike, whichever kernel (and
+    tile) evaluates it.  In vacuum the
     fused sweep reads no 1/eps_r array; with the array (all ones) it agrees bit for
     bit."""
     w = W.radiating_cube(n=72, n_emit=60, steps=0, cpml=8, precision=precision)
     runs = []
-    for sweep, layers, eps_array in (("plain", None, True), ("fused", 0, False),
-                                     ("fused", 1, False), ("fused", 2, False),
-                                     ("fused", 2, True), ("fused", 0, True)):
+    for sweep, layers, eps_array, tx in (("plain", None, True, 64), ("fused", 0, False, 64),
+                                         ("fused", 1, False, 64), ("fused", 2, False, 64),
+                                         ("fused", 2, True, 64), ("fused", 0, True, 64),
+                                         ("fused", 0, False, 32), ("fused", 1, False, 32),
+                                         ("fused", 2, False, 32)):
         if layers and precision == "fp64":
             continue
         sim = mlk().from_workload(w, sweep=sweep)
+        if sweep == "fused":
+            sim.set_tile_width(tx)
         if layers is not None:
             sim.set_sweep_layers(layers)
         if eps_array:
@@ -180,7 +188,7 @@ def test_sweep_decompositions_agree_bitwise(precision):
             sim.set_eps_box(box, np.full((10, 10, 10), 2.0))
             sim.set_eps_box(box, np.ones((10, 10, 10)))
         say(f"[decomposition] {precision} {sweep} layers={layers} eps_array={eps_array} "
-            f"box={sim.interior_box()}")
+            f"tx={tx} box={sim.interior_box()}")
         sim.step(40)
         runs.append(sim.fields())
     for other in runs[1:]:
