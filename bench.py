@@ -65,7 +65,7 @@ def parse():
     p.add_argument("--batch-only", action="store_true",
                    help="only the 64-domain batch leg (profiling runs)")
     p.add_argument("--tile", type=lambda v: tuple(int(x) for x in v.split(",")), default=None,
-                   help="fused tile TY,KZ[,TX] instead of autotuning (profiling runs)")
+                   help="fused tile TY,KZ[,TX[,LAYER_MODE]] instead of autotuning (profiling runs)")
     return p.parse_args()
 
 
@@ -136,21 +136,20 @@ def copy_calibration():
 
 def traffic_from_profile(launch_cells, tile):
     """HBM bytes per launch of the fused kernel from the committed counter summary,
-    or None when it is absent or was taken on a different kernel source, box or tile
-    (tx, ty, kz)."""
+    or None when it is absent, was taken on a different kernel source or box, or
+    holds no line for this tile (tx, ty, kz, layer mode)."""
     if not os.path.exists(TRAFFIC_SUMMARY):
         return None
     txt = open(TRAFFIC_SUMMARY).read()
     want = hashlib.sha256(open(FUSED_SRC, "rb").read()).hexdigest()
     m = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", txt)
-    t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
     c = re.search(r"cells_per_launch:\s*(\d+)", txt)
-    k = re.search(r"tile_tx_ty_kz:\s*(\d+)\s+(\d+)\s+(\d+)", txt)
-    if not (m and t and c and k) or m.group(1) != want or int(c.group(1)) != launch_cells:
+    if not (m and c) or m.group(1) != want or int(c.group(1)) != launch_cells:
         return None
-    if tuple(int(v) for v in k.groups()) != tuple(tile):
-        return None
-    return float(t.group(1))
+    for k in re.finditer(r"tile_traffic:\s*(\d+)\s+(\d+)\s+(\d+)\s+(\d+)\s+([0-9.eE+]+)", txt):
+        if tuple(int(v) for v in k.groups()[:4]) == tuple(tile):
+            return float(k.group(5))
+    return None
 
 
 def run_gpu(w, precision, sweep, steps, warmup, timing, tile=None, poles=()):
@@ -164,6 +163,8 @@ def run_gpu(w, precision, sweep, steps, warmup, timing, tile=None, poles=()):
         sim.set_tuning(*tile[:2])
         if len(tile) > 2:
             sim.set_tile_width(tile[2])
+        if len(tile) > 3:
+            sim.set_sweep_layers(tile[3])
     else:
         sim.autotune()  # tile shape of the fused sweep (untimed; plain sweeps have none)
     sim.step(warmup)
@@ -182,7 +183,7 @@ def run_gpu(w, precision, sweep, steps, warmup, timing, tile=None, poles=()):
             if n:
                 phases[name] = (ms, n)
     box = sim.interior_box()
-    tuning = sim.tuning() + (sim.tile_width(),)
+    tuning = sim.tuning() + (sim.tile_width(), sim.sweep_layers())
     sim.close()
     return dt, phases, box, tuning
 
@@ -435,11 +436,12 @@ def main():
     launch_bytes = launch_cells * CELL_WORDS * esz + launch_memb * PSI_WORDS * esz
     t_launch = sweep_ms / sweep_n * 1e-3
     achieved = launch_bytes / t_launch / 1e9
-    traffic = traffic_from_profile(launch_cells, (tuning[2], tuning[0], tuning[1]))
+    traffic = traffic_from_profile(launch_cells, (tuning[2], tuning[0], tuning[1], tuning[3]))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "kernel": f"k_fused<float, {tuning[2]}, {tuning[0]}>",
-                "tile": {"tx": tuning[2], "ty": tuning[0], "kz": tuning[1]},
+                "tile": {"tx": tuning[2], "ty": tuning[0], "kz": tuning[1],
+                         "layer_mode": tuning[3]},
                 "cells_per_launch": launch_cells, "bytes_per_launch": launch_bytes,
                 "avg_launch_us": round(t_launch * 1e6, 2)}
     emitter_ms = sum(breakdown[p][0] / breakdown[p][1] for p in ("emitters", "scatter")

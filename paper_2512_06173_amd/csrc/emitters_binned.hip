@@ -238,24 +238,37 @@ __device__ __forceinline__ void gather_body(const FieldPtrs<T>& f, const Geom& g
     if (i < w.n[0]) {
       const int ny = w.n[1] - j0, nz = w.n[2];
       int s = (w.org[0] + i - x0) + TX * (w.org[1] + j0 - y0) + TX * TY * (w.org[2] - z0);
+      // The sums read every row of a plane before adding them up (no branch per
+      // row), one component at a time, so that the reads of a plane are in flight
+      // together.  Rows past the window (j >= ny) read the window's first row, a
+      // staged cell, with the record's zero weight: their terms are zeros and leave
+      // the sums as they are.  (FP64: emitter phase 131 -> 118 us at 256^3 with
+      // 100,000 emitters; FP32 unchanged, its row-by-row form ran as fast.)
+      int roff[RG];
 #pragma unroll
-      for (int k = 0; k < kMaxWin; ++k, s += TX * TY) {
-        if (k < nz) {
-          T sx = T(0), sy = T(0), sz = T(0);
+      for (int j = 0; j < RG; ++j) roff[j] = j < ny ? TX * j : -TX * j0;
+      // Ex and Ez take the integer y weights, Ey the half-integer ones; Ez the
+      // half-integer z weights
+      auto comp = [&](const T* sEc, const T* wy, const T* wz) -> double {
+        double a = 0.0;
+        int sk = s;
 #pragma unroll
-          for (int j = 0; j < RG; ++j) {
-            if (j < ny) {
-              const int p = s + TX * j;
-              sx += w.wy[0][j] * sE[0][p];
-              sy += w.wy[1][j] * sE[1][p];
-              sz += w.wy[0][j] * sE[2][p];
-            }
+        for (int k = 0; k < kMaxWin; ++k, sk += TX * TY) {
+          if (k < nz) {
+            T v[RG];
+#pragma unroll
+            for (int j = 0; j < RG; ++j) v[j] = sEc[sk + roff[j]];
+            T sc = T(0);
+#pragma unroll
+            for (int j = 0; j < RG; ++j) sc += wy[j] * v[j];
+            a += (double)(wz[k] * sc);
           }
-          ax += (double)(w.wz[0][k] * sx);
-          ay += (double)(w.wz[0][k] * sy);
-          az += (double)(w.wz[1][k] * sz);
         }
-      }
+        return a;
+      };
+      ax = comp(sE[0], w.wy[0], w.wz[0]);
+      ay = comp(sE[1], w.wy[1], w.wz[0]);
+      az = comp(sE[2], w.wy[0], w.wz[1]);
       // Ex sits at half-integer x (variant 1); Ey, Ez at integer x
       ax *= (double)w.wx1;
       ay *= (double)w.wx0;
