@@ -94,6 +94,16 @@ __device__ __forceinline__ double gather_lane_sum(double v) {
   return v;
 }
 
+// One plane's term of an emitter's z sum, a + wz s, rounded alike by every gather
+// path: in FP64 as one fused multiply-add, in FP32 with the product rounded in FP32
+// and the sum in FP64.
+__device__ __forceinline__ double zterm(double a, double wz, double s) {
+  return __builtin_fma(wz, s, a);
+}
+__device__ __forceinline__ double zterm(double a, float wz, float s) {
+  return a + (double)(wz * s);
+}
+
 // The part of an emitter's window record that one gather lane needs, in
 // registers: the union window, the lane's own x weights, the y weights of its
 // rows and every z weight (the lanes of an emitter read the same record).
@@ -261,7 +271,7 @@ __device__ __forceinline__ void gather_body(const FieldPtrs<T>& f, const Geom& g
             T sc = T(0);
 #pragma unroll
             for (int j = 0; j < RG; ++j) sc += wy[j] * v[j];
-            a += (double)(wz[k] * sc);
+            a = zterm(a, wz[k], sc);
           }
         }
         return a;
@@ -286,106 +296,132 @@ __device__ __forceinline__ void gather_body(const FieldPtrs<T>& f, const Geom& g
   }
 }
 
-// The emitters of the light bins, without a tile: a group of lanes per emitter
-// (the lane layout of gather_body), each lane reading its window cells from global
-// memory, all loads of a window plane issued before its sums.  The values and the
-// order of every operation are those of the tiled gather, so E~ is the same bit
-// for bit.  em: the emitter ids, count of them.
+// The emitters of the light bins, without a tile: a wavefront per emitter, lane
+// (i, k) on window x offset i and plane k, reading its window cells from global
+// memory (every row of its plane, for each of the row groups h that the tiled
+// gather gives separate lanes).  A lane forms the tiled gather's row sums
+// sum_j wy E for its plane; the plane-0 lanes then take the z sums in plane order,
+// scale by the x weight, join the row groups and sum over x as the tiled gather's
+// lanes do, so E~ is the same bit for bit.  All planes' loads are
+// in flight together (a lane per plane), where a lane walking the planes one after
+// another would wait on each.  em: the emitter ids, count of them.
 template <typename T>
 __device__ __forceinline__ void light_body(const FieldPtrs<T>& f, const Geom& g, const int* em,
                                            int count, const WindowPtrs<T>& win, double* Et,
                                            int bid) {
-  constexpr int LG = GatherCfg<T>::lanes, RG = GatherCfg<T>::rows;
-  constexpr int NG = kLightThreads / LG;
-  const int tid = threadIdx.x;
-  const int grp = tid / LG, i = tid % kLanesPerEmitter;
-  const int j0 = (tid / kLanesPerEmitter) % (LG / kLanesPerEmitter) * RG;
-  const int q = bid * NG + grp;
-  if (q >= count) return;  // uniform across the lanes of an emitter
+  constexpr int RG = GatherCfg<T>::rows, H = GatherCfg<T>::lanes / kLanesPerEmitter;
+  constexpr int NG = kLightThreads / 64;
+  static_assert(kLanesPerEmitter * kMaxWin == 64, "one lane per (x offset, plane)");
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int i = lane % kLanesPerEmitter, k = lane / kLanesPerEmitter;
+  const int q = bid * NG + tid / 64;
+  if (q >= count) return;  // uniform across the wavefront
   const int e = em[q];
   const WinRec<T>& r = win.rec[e];
   const int4 o = *reinterpret_cast<const int4*>(&r.org[0]);  // org[0..2], n[0]
   const int2 nn = *reinterpret_cast<const int2*>(&r.n[1]);
-  double ax = 0.0, ay = 0.0, az = 0.0;
-  if (i < o.w) {
-    const T wx0 = r.wr[0][0][i], wx1 = r.wr[0][1][i];
-    T wy0[RG], wy1[RG];
+  const int nz = nn.y;
+  T t[H][3];  // the lane's row sums of its plane, per row group and component
 #pragma unroll
-    for (int d = 0; d < RG; ++d) {
-      wy0[d] = r.wr[1][0][j0 + d];
-      wy1[d] = r.wr[1][1][j0 + d];
-    }
-    const int ny = nn.x - j0, nz = nn.y;
+  for (int h = 0; h < H; ++h) t[h][0] = t[h][1] = t[h][2] = T(0);
+  if (i < o.w && k < nz) {
     // window cells in the grid: wrapped on a periodic axis; beyond a wall the tile
     // holds zero, and so does this path
-    int cx = o.x + i;
-    bool okx = true;
+    int cx = o.x + i, cz = o.z + k;
+    bool ok0 = true;
     if (g.periodic[0]) {
       cx %= g.n[0];
       cx = cx < 0 ? cx + g.n[0] : cx;
     } else {
-      okx = cx >= 0 && cx < g.n[0];
+      ok0 = cx >= 0 && cx < g.n[0];
     }
-    int cyv[RG];
-    unsigned okym = 0u;
-#pragma unroll
-    for (int j = 0; j < RG; ++j) {
-      int cy = o.y + j0 + j;
-      bool ok = j < ny;
-      if (g.periodic[1]) {
-        cy %= g.n[1];
-        cy = cy < 0 ? cy + g.n[1] : cy;
-      } else {
-        ok = ok && cy >= 0 && cy < g.n[1];
-      }
-      cyv[j] = cy;
-      okym |= ok ? (1u << j) : 0u;
+    if (g.periodic[2]) {
+      cz %= g.n[2];
+      cz = cz < 0 ? cz + g.n[2] : cz;
+    } else {
+      ok0 = ok0 && cz >= 0 && cz < g.n[2];
     }
+    T v[H][RG][3];
+    unsigned okm[H];
 #pragma unroll
-    for (int k = 0; k < kMaxWin; ++k) {
-      if (k < nz) {
-        int cz = o.z + k;
-        bool okz = okx;
-        if (g.periodic[2]) {
-          cz %= g.n[2];
-          cz = cz < 0 ? cz + g.n[2] : cz;
+    for (int h = 0; h < H; ++h) {
+      const int ny = nn.x - h * RG;
+      okm[h] = 0u;
+#pragma unroll
+      for (int j = 0; j < RG; ++j) {
+        int cy = o.y + h * RG + j;
+        bool ok = ok0 && j < ny;
+        if (g.periodic[1]) {
+          cy %= g.n[1];
+          cy = cy < 0 ? cy + g.n[1] : cy;
         } else {
-          okz = okz && cz >= 0 && cz < g.n[2];
+          ok = ok && cy >= 0 && cy < g.n[1];
         }
-        const unsigned okm = okz ? okym : 0u;
-        T v[RG][3];
-#pragma unroll
-        for (int j = 0; j < RG; ++j) {
-          const size_t id = ((okm >> j) & 1u) ? cell_index(g, cx, cyv[j], cz) : 0;
-          v[j][0] = f.E[0][id];
-          v[j][1] = f.E[1][id];
-          v[j][2] = f.E[2][id];
-        }
-        const T wz0 = r.wr[2][0][k], wz1 = r.wr[2][1][k];
-        T sx = T(0), sy = T(0), sz = T(0);
-#pragma unroll
-        for (int j = 0; j < RG; ++j) {
-          if (j < ny) {
-            const bool ok = (okm >> j) & 1u;
-            sx += wy0[j] * (ok ? v[j][0] : T(0));
-            sy += wy1[j] * (ok ? v[j][1] : T(0));
-            sz += wy0[j] * (ok ? v[j][2] : T(0));
-          }
-        }
-        ax += (double)(wz0 * sx);
-        ay += (double)(wz0 * sy);
-        az += (double)(wz1 * sz);
+        okm[h] |= ok ? (1u << j) : 0u;
+        const size_t id = ok ? cell_index(g, cx, cy, cz) : 0;
+        v[h][j][0] = f.E[0][id];
+        v[h][j][1] = f.E[1][id];
+        v[h][j][2] = f.E[2][id];
       }
     }
-    // Ex sits at half-integer x (variant 1); Ey, Ez at integer x
-    ax *= (double)wx1;
-    ay *= (double)wx0;
-    az *= (double)wx0;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      const int ny = nn.x - h * RG;
+      T sx = T(0), sy = T(0), sz = T(0);
+#pragma unroll
+      for (int j = 0; j < RG; ++j) {
+        if (j < ny) {
+          const bool ok = (okm[h] >> j) & 1u;
+          const T wy0 = r.wr[1][0][h * RG + j], wy1 = r.wr[1][1][h * RG + j];
+          sx += wy0 * (ok ? v[h][j][0] : T(0));
+          sy += wy1 * (ok ? v[h][j][1] : T(0));
+          sz += wy0 * (ok ? v[h][j][2] : T(0));
+        }
+      }
+      t[h][0] = sx;
+      t[h][1] = sy;
+      t[h][2] = sz;
+    }
   }
-  ax = gather_lane_sum<LG>(ax);
-  ay = gather_lane_sum<LG>(ay);
-  az = gather_lane_sum<LG>(az);
-  if (i == 0 && j0 == 0) {
+  // the z sums in plane order (every lane takes part in the shuffles; the plane-0
+  // lanes keep the sums); Ez takes the half-integer z weights
+  double a[H][3];
+#pragma unroll
+  for (int h = 0; h < H; ++h) a[h][0] = a[h][1] = a[h][2] = 0.0;
+#pragma unroll
+  for (int kk = 0; kk < kMaxWin; ++kk) {
+    if (kk < nz) {  // uniform across the wavefront
+      const T wz0 = r.wr[2][0][kk], wz1 = r.wr[2][1][kk];
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        const int src = i + kLanesPerEmitter * kk;
+        a[h][0] = zterm(a[h][0], wz0, __shfl(t[h][0], src, 64));
+        a[h][1] = zterm(a[h][1], wz0, __shfl(t[h][1], src, 64));
+        a[h][2] = zterm(a[h][2], wz1, __shfl(t[h][2], src, 64));
+      }
+    }
+  }
+  if (i < o.w) {
+    // Ex sits at half-integer x (variant 1); Ey, Ez at integer x
+    const double wx0 = (double)r.wr[0][0][i], wx1 = (double)r.wr[0][1][i];
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      a[h][0] *= wx1;
+      a[h][1] *= wx0;
+      a[h][2] *= wx0;
+    }
+  }
+  // the row groups of one x offset, then the x offsets: the tiled gather's lane sum
+  double ax = a[0][0], ay = a[0][1], az = a[0][2];
+  if (H == 2) {
+    ax += a[H - 1][0];
+    ay += a[H - 1][1];
+    az += a[H - 1][2];
+  }
+  ax = gather_lane_sum<kLanesPerEmitter>(ax);
+  ay = gather_lane_sum<kLanesPerEmitter>(ay);
+  az = gather_lane_sum<kLanesPerEmitter>(az);
+  if (lane == 0) {
     const double gm = win.gamma[e];
     Et[3 * e] = gm * ax;
     Et[3 * e + 1] = gm * ay;
@@ -776,7 +812,7 @@ static hipError_t launch_gather_step(const FieldPtrs<T>& f, const Geom& g, const
                        st, f, g, b, win, Et, fpv);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && b.nlight > 0) {
-    constexpr int NG = kLightThreads / GatherCfg<T>::lanes;
+    constexpr int NG = kLightThreads / 64;  // a wavefront per emitter
     hipLaunchKernelGGL(k_gather_light<T>, dim3((b.nlight + NG - 1) / NG), dim3(kLightThreads),
                        0, st, f, g, b.gbin_em + b.glight0, b.nlight, win, Et);
     e = hipGetLastError();
@@ -877,8 +913,8 @@ hipError_t light_batch_f32(const LightJob<float>* jobs, const int* start, int nj
                            hipStream_t st) {
   return launch_light_batch<float>(jobs, start, njobs, nblocks, st);
 }
-int light_per_block(bool fp32) {
-  return fp32 ? kLightThreads / GatherCfg<float>::lanes : kLightThreads / GatherCfg<double>::lanes;
+int light_per_block(bool) {
+  return kLightThreads / 64;  // a wavefront per emitter
 }
 hipError_t scatter_batch_f64(const ScatterJob<double>* jobs, const int* start, int njobs,
                              const int2* order, int nblocks, hipStream_t st) {

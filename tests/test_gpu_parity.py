@@ -199,6 +199,36 @@ def test_sweep_decompositions_agree_bitwise(precision):
             mlk().from_workload(w, sweep="fused").set_sweep_layers(True)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("bc, lo", [("periodic", 40.2), ("pec", 8.2)])
+def test_light_and_tiled_gather_agree_bitwise(precision, bc, lo):
+    """An emitter alone in its gather bin is gathered without a tile (a light bin); with
+    nine more emitters of zero dipole in the same bin, the bin stages its tile.  The
+    extra emitters add nothing to the field, so both runs give the same fields, state
+    and gathered field bit for bit.  On the periodic grid the bin sits at the corner
+    where the windows wrap."""
+    rng = np.random.default_rng(17)
+    n = 48
+    pos = rng.uniform(lo, lo + 7.6, size=(10, 3))  # one bin in both precisions' binnings
+    dip = np.zeros((10, 3))
+    dip[0] = (0.3, -0.2, 0.25)
+    fields = [1e-2 * rng.standard_normal((n, n, n)) for _ in range(6)]
+    runs = []
+    for m in (1, 10):
+        sim = mlk().Simulation((n, n, n), precision=precision, bc=(bc,) * 6)
+        for c in range(6):
+            sim.set_field(c, fields[c])
+        sim.add_tls(pos[:m], np.ones(m), np.ones(m), 0.25, dip[:m],
+                    np.tile([0.5, 0.5, 0.0], (m, 1)))
+        say(f"[gather] {precision} {bc} {m} emitter(s) in the bin")
+        sim.step(25)
+        runs.append((sim.fields(), sim.tls_state(0, 1), sim.emitter_io()[0][0]))
+    (fa, ta, ea), (fb, tb, eb) = runs
+    assert all(np.array_equal(x, y) for x, y in zip(fa, fb))
+    assert np.array_equal(ta, tb) and np.array_equal(ea, eb)
+    assert np.any(ea != 0.0)
+
+
 def test_ragged_mixed_boundaries_fp64():
     """x periodic with a ragged tail (nx not a multiple of 64), y metallic, z CPML; emitters
     whose windows wrap across the periodic axis."""
