@@ -63,7 +63,11 @@ typedef enum {
 enum { MLK_FP64 = 0, MLK_FP32_FIELDS = 1 };
 enum { MLK_BC_PEC = 0, MLK_BC_PERIODIC = 1, MLK_BC_CPML = 2 };
 enum { MLK_MEM_HOST = 0, MLK_MEM_DEVICE = 1 };
-/* Yee sweep variant: one fused H+E pass (default) or separate H and E passes. */
+/* Yee sweep variant: one fused H+E pass (default) or separate H and E passes.  The
+ * fused sweep addresses each field array and the CPML psi buffer with 32-bit byte
+ * offsets: mlk_create refuses it (MLK_EUNSUPPORTED) when a field array or the psi
+ * buffer would reach 4 GiB (about 1024^3 cells in FP32); the plain sweep has no such
+ * limit. */
 enum { MLK_SWEEP_FUSED = 0, MLK_SWEEP_PLAIN = 1 };
 /* Current scatter variant: deterministic owner-computes (default) or atomics. */
 enum { MLK_SCATTER_OWNER = 0, MLK_SCATTER_ATOMIC = 1 };

@@ -1244,6 +1244,11 @@ mlk_status mlk_create(const mlk_grid_desc* gd, mlk_sim** out) {
     return hipMemsetAsync(*p, 0, bytes, s->stream) == hipSuccess;
   };
   const bool fused = gd->sweep == MLK_SWEEP_FUSED;
+  // the fused kernels address a field array and the psi buffer by 32-bit byte offsets
+  if (fused && (s->ncell * s->esz >= ((size_t)1 << 32) || psi_total(g) * s->esz >= ((size_t)1 << 32)))
+    return bail(fail(MLK_EUNSUPPORTED, "the fused sweep needs field arrays and psi buffer "
+                                       "under 4 GiB (%zu and %zu bytes): use the plain sweep",
+                     s->ncell * s->esz, psi_total(g) * s->esz));
   for (int c = 0; c < 3; ++c) {
     if (!alloc_zero(&s->E[c], s->ncell * s->esz) || !alloc_zero(&s->H[c], s->ncell * s->esz))
       return bail(fail(MLK_ENOMEM, "field allocation of %zu bytes failed", s->ncell * s->esz));

@@ -39,6 +39,45 @@
 
 namespace mlk {
 
+// Element access by a 32-bit index: each field array, and the psi buffer, holds less
+// than 4 GiB (checked on the host), so an element's byte offset fits 32 bits and a
+// load takes the array's base from scalar registers plus one 32-bit offset register,
+// which the arrays read at the same cell share.
+template <typename T>
+__device__ __forceinline__ T ld32(const T* base, unsigned i) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void st32(T* base, unsigned i, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (unsigned)sizeof(T)) = v;
+}
+template <typename T>
+__device__ __forceinline__ void st32nt(T* base, unsigned i, T v) {
+  __builtin_nontemporal_store(v, reinterpret_cast<T*>(reinterpret_cast<char*>(base) +
+                                                      i * (unsigned)sizeof(T)));
+}
+// column / plane offsets as 32-bit element indices (valid = false: a zero cell)
+struct Col32 {
+  unsigned off;
+  bool valid;
+};
+__device__ __forceinline__ Col32 column32(const Geom& g, int x, int y) {
+  const Col c = column(g, x, y);
+  return Col32{(unsigned)c.off, c.valid};
+}
+__device__ __forceinline__ Col32 plane32(const Geom& g, int z) {
+  const Col c = plane(g, z);
+  return Col32{(unsigned)c.off, c.valid};
+}
+template <typename T>
+__device__ __forceinline__ bool load3_32(const FieldPtrs<T>& f, Col32 col, Col32 pl, T v[3]) {
+  const bool ok = col.valid && pl.valid;
+  const unsigned id = ok ? col.off + pl.off : 0u;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) v[c] = ld32(f.E[c], id);
+  return ok;
+}
+
 // CPM: the CPML code compiled in: 0 none, 1 the x layers, 2 every axis (FP32; the
 // FP64 kernel carries the x layers only).  Fewer layers, fewer registers: about 71
 // VGPRs without any in FP32, against 118 with all of them.  TX, the tile width, is
@@ -106,13 +145,13 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
   const int i = x0 + tx, j = y0 + ty;
   const bool own = i < box.hi[0] && j < box.hi[1];
   const T dt = (T)g.dt, idx = (T)g.inv_dx;
-  const size_t plane_sz = (size_t)g.n[0] * g.n[1];
+  const unsigned plane_sz = (unsigned)g.n[0] * (unsigned)g.n[1];
 
   // the columns this thread stages: its own slot and (for tid < NHALO) one ring slot
-  const Col ocol = column(g, i, j);
+  const Col32 ocol = column32(g, i, j);
   const int oslot = (ty + 1) * EW + tx + 1;
   int rslot = 0;
-  Col rcol{0, false};
+  Col32 rcol{0u, false};
   if (tid < NHALO) {
     int xs, ys;
     if (tid < EW) {
@@ -127,14 +166,14 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
       xs = (c2 & 1) ? TX : -1;
     }
     rslot = (ys + 1) * EW + xs + 1;
-    rcol = column(g, x0 + xs, y0 + ys);
+    rcol = column32(g, x0 + xs, y0 + ys);
   }
   // halo H columns: x0-1 (first lane of every row), y0-1 (first row)
   const bool hx_on = tx == 0 && j < box.hi[1] && (x0 > 0 || g.periodic[0]);
   const int ih = x0 > 0 ? x0 - 1 : g.n[0] - 1;
   const bool hy_on = ty == 0 && i < box.hi[0] && (y0 > 0 || g.periodic[1]);
   const int jh = y0 > 0 ? y0 - 1 : g.n[1] - 1;
-  const size_t own_off = own ? (size_t)i + (size_t)g.n[0] * j : 0;
+  const unsigned own_off = own ? (unsigned)i + (unsigned)g.n[0] * (unsigned)j : 0u;
   // x CPML: own cells in the x layers stretch their x derivatives, psi <- b psi
   // + c d, d <- d / kappa + psi.  The coefficients of the tile's columns sit in
   // LDS; psi (one array per field component, x compressed to the layers) is
@@ -143,7 +182,7 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
                   j < box.hi[1] && in_layer(g, 0, i);
   const unsigned nl = (unsigned)(g.nlo[0] + g.nhi[0]);
   const unsigned nlny = nl * (unsigned)g.n[1];
-  const size_t P = (size_t)nlny * (unsigned)g.n[2];  // psi values per component array
+  const unsigned P = nlny * (unsigned)g.n[2];  // psi values per component array
   const unsigned li = xl ? (unsigned)layer_index(g, 0, i) : 0u;
   const unsigned pb = li + nl * (unsigned)j, pby = li + nl * (unsigned)jh;
   // y layers (own row and low-y halo row, uniform across a wavefront) and z
@@ -160,8 +199,8 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
   const unsigned nly = (unsigned)(g.nlo[1] + g.nhi[1]);
   const unsigned Py = has_cpml(g, 1) ? unx * nly * (unsigned)g.n[2] : 0u;
   const unsigned Pz = has_cpml(g, 2) ? unx * uny * (unsigned)(g.nlo[2] + g.nhi[2]) : 0u;
-  const size_t oy = has_cpml(g, 1) ? psi_offset(g, 0, 0, 1) : 0;
-  const size_t oz = has_cpml(g, 2) ? psi_offset(g, 0, 0, 2) : 0;
+  const unsigned oy = has_cpml(g, 1) ? (unsigned)psi_offset(g, 0, 0, 1) : 0u;
+  const unsigned oz = has_cpml(g, 2) ? (unsigned)psi_offset(g, 0, 0, 2) : 0u;
   const T* ty_tab = a.tab + (has_cpml(g, 1) ? tab_offset(g, 1) : 0);
   const T* tz_tab = a.tab + (has_cpml(g, 2) ? tab_offset(g, 2) : 0);
   const unsigned lyo = yl ? (unsigned)layer_index(g, 1, j) : 0u;
@@ -172,8 +211,8 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
     const int field = slot >> 1;
     const T* t = ty_tab + field * g.n[1] + q;
     const unsigned id = (unsigned)slot * Py + (unsigned)x + unx * (lq + nly * (unsigned)k);
-    const T p = t[0] * a.psi[oy + id] + t[2 * g.n[1]] * d;
-    if (store) b.psi[oy + id] = p;
+    const T p = t[0] * ld32(a.psi, oy + id) + t[2 * g.n[1]] * d;
+    if (store) st32(b.psi, oy + id, p);
     return t[4 * g.n[1]] * d + p;
   };
   // the same for a z derivative at cell (x, y) of plane k; slot: 0 E x, 1 E y,
@@ -183,14 +222,13 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
     const T* t = tz_tab + field * g.n[2] + k;
     const unsigned lz = (unsigned)layer_index(g, 2, k);
     const unsigned id = (unsigned)slot * Pz + (unsigned)x + unx * ((unsigned)y + uny * lz);
-    const T p = t[0] * a.psi[oz + id] + t[2 * g.n[2]] * d;
-    if (store) b.psi[oz + id] = p;
+    const T p = t[0] * ld32(a.psi, oz + id) + t[2 * g.n[2]] * d;
+    if (store) st32(b.psi, oz + id, p);
     return t[4 * g.n[2]] * d + p;
   };
   // psi arrays of axis x: E of y, E of z, H of y, H of z
-  auto psi_at = [&](const FieldPtrs<T>& f, int slot, unsigned id) -> T& {
-    return f.psi[(size_t)slot * P + id];
-  };
+  auto psi_ld = [&](int slot, unsigned id) -> T { return ld32(a.psi, (unsigned)slot * P + id); };
+  auto psi_st = [&](int slot, unsigned id, T v) { st32(b.psi, (unsigned)slot * P + id, v); };
   if (ty == 0 && xl) {
     const T* t = a.tab + tab_offset(g, 0);
     const int n = g.n[0];
@@ -209,8 +247,8 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
                           ? ty_tab[w * 2 * g.n[1] + fld * g.n[1] + q] : T(0);
     }
   }
-  const size_t hx_off = hx_on ? (size_t)ih + (size_t)g.n[0] * j : 0;
-  const size_t hy_off = hy_on ? (size_t)i + (size_t)g.n[0] * jh : 0;
+  const unsigned hx_off = hx_on ? (unsigned)ih + (unsigned)g.n[0] * (unsigned)j : 0u;
+  const unsigned hy_off = hy_on ? (unsigned)i + (unsigned)g.n[0] * (unsigned)jh : 0u;
 
   auto E_at = [&](int p, int c, int xs, int ys) -> T { return eL[p][c][(ys + 1) * EW + xs + 1]; };
   // write a staged plane to LDS, zeroing slots outside the closure; the own
@@ -236,21 +274,21 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
     const int km = k0 - 1;
     const int pm = (km + 2) & 1, p0 = k0 & 1;
     T em[3], emr[3], ekr[3];
-    const Col plm = plane(g, km), pl0 = plane(g, k0);
-    const bool emv = load3(a, ocol, plm, em), ekv = load3(a, ocol, pl0, ek);
-    const bool emrv = load3(a, rcol, plm, emr), ekrv = load3(a, rcol, pl0, ekr);
+    const Col32 plm = plane32(g, km), pl0 = plane32(g, k0);
+    const bool emv = load3_32(a, ocol, plm, em), ekv = load3_32(a, ocol, pl0, ek);
+    const bool emrv = load3_32(a, rcol, plm, emr), ekrv = load3_32(a, rcol, pl0, ekr);
     put(pm, em, emv, emr, emrv);
     put(p0, ek, ekv, ekr, ekrv);
     lds_barrier();
     if (own && plm.valid) {
-      const size_t id = own_off + plm.off;
+      const unsigned id = own_off + plm.off;
       T dEz_dy = (E_at(pm, 2, tx, ty + 1) - em[2]) * idx;
       T dEy_dz = (ek[1] - em[1]) * idx;
       T dEx_dz = (ek[0] - em[0]) * idx;
       T dEz_dx = (E_at(pm, 2, tx + 1, ty) - em[2]) * idx;
       const int kmw = km < 0 ? km + g.n[2] : km;
       if (xl) {
-        const T q = xc[1][0][tx] * psi_at(a, 2, pb + nlny * (unsigned)kmw) + xc[1][1][tx] * dEz_dx;
+        const T q = xc[1][0][tx] * psi_ld(2, pb + nlny * (unsigned)kmw) + xc[1][1][tx] * dEz_dx;
         dEz_dx = xc[1][2][tx] * dEz_dx + q;
       }
       if (yl) dEz_dy = sty(2, j, lyo, i, kmw, dEz_dy, false);
@@ -258,13 +296,13 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
         dEy_dz = stz(2, i, j, kmw, dEy_dz, false);
         dEx_dz = stz(3, i, j, kmw, dEx_dz, false);
       }
-      hpx = a.H[0][id] - dt * (dEz_dy - dEy_dz);
-      hpy = a.H[1][id] - dt * (dEx_dz - dEz_dx);
+      hpx = ld32(a.H[0], id) - dt * (dEz_dy - dEy_dz);
+      hpy = ld32(a.H[1], id) - dt * (dEx_dz - dEz_dx);
     }
     // first prefetch: E(k0+1)
-    const Col pl1 = plane(g, k0 + 1);
-    nEov = load3(a, ocol, pl1, nEo);
-    nErv = load3(a, rcol, pl1, nEr);
+    const Col32 pl1 = plane32(g, k0 + 1);
+    nEov = load3_32(a, ocol, pl1, nEo);
+    nErv = load3_32(a, rcol, pl1, nEr);
     lds_barrier();
   }
 
@@ -272,15 +310,15 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
   T nH[3] = {T(0), T(0), T(0)}, nEps = T(0), nHx[2] = {T(0), T(0)}, nHy[2] = {T(0), T(0)};
   // unconditional loads from safe addresses (offsets are 0 for unused slots)
   auto prefetch_h = [&](int k) {
-    const size_t po = (size_t)min(k, g.n[2] - 1) * plane_sz;
-    nH[0] = a.H[0][own_off + po];
-    nH[1] = a.H[1][own_off + po];
-    nH[2] = a.H[2][own_off + po];
-    nEps = a.epsinv ? a.epsinv[own_off + po] : T(1);  // null: eps_r = 1 everywhere
-    nHx[0] = a.H[1][hx_off + po];
-    nHx[1] = a.H[2][hx_off + po];
-    nHy[0] = a.H[0][hy_off + po];
-    nHy[1] = a.H[2][hy_off + po];
+    const unsigned po = (unsigned)min(k, g.n[2] - 1) * plane_sz;
+    nH[0] = ld32(a.H[0], own_off + po);
+    nH[1] = ld32(a.H[1], own_off + po);
+    nH[2] = ld32(a.H[2], own_off + po);
+    nEps = a.epsinv ? ld32(a.epsinv, own_off + po) : T(1);  // null: eps_r = 1 everywhere
+    nHx[0] = ld32(a.H[1], hx_off + po);
+    nHx[1] = ld32(a.H[2], hx_off + po);
+    nHy[0] = ld32(a.H[0], hy_off + po);
+    nHy[1] = ld32(a.H[2], hy_off + po);
   };
   prefetch_h(k0);
   // psi of plane k for the x-layer cells, read one iteration ahead after the
@@ -302,25 +340,25 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
     if (xl) {
       const unsigned pk = pb + nlny * (unsigned)k;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) nP[q] = psi_at(a, q, pk);
-      if (hy_on) nPy = psi_at(a, 3, pby + nlny * (unsigned)k);
+      for (int q = 0; q < 4; ++q) nP[q] = psi_ld(q, pk);
+      if (hy_on) nPy = psi_ld(3, pby + nlny * (unsigned)k);
     }
     if (own && yl) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) nYo[q] = a.psi[oy + iy(q, i, lyo, k)];
+      for (int q = 0; q < 4; ++q) nYo[q] = ld32(a.psi, oy + iy(q, i, lyo, k));
     }
-    if (hx_on && yl) nXh[1] = a.psi[oy + iy(3, ih, lyo, k)];
+    if (hx_on && yl) nXh[1] = ld32(a.psi, oy + iy(3, ih, lyo, k));
     if (hy_on && yhl) {
-      nYh[0] = a.psi[oy + iy(2, i, lyh, k)];
-      nYh[1] = a.psi[oy + iy(3, i, lyh, k)];
+      nYh[0] = ld32(a.psi, oy + iy(2, i, lyh, k));
+      nYh[1] = ld32(a.psi, oy + iy(3, i, lyh, k));
     }
     if (zlay(k)) {
       if (own) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) nZo[q] = a.psi[oz + iz(q, i, j, k)];
+        for (int q = 0; q < 4; ++q) nZo[q] = ld32(a.psi, oz + iz(q, i, j, k));
       }
-      if (hx_on) nXh[0] = a.psi[oz + iz(3, ih, j, k)];
-      if (hy_on) nYh[2] = a.psi[oz + iz(2, i, jh, k)];
+      if (hx_on) nXh[0] = ld32(a.psi, oz + iz(3, ih, j, k));
+      if (hy_on) nYh[2] = ld32(a.psi, oz + iz(2, i, jh, k));
     }
   };
   // stretched derivative from a prefetched psi (the new psi in pn): y at LDS row
@@ -348,14 +386,14 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
     // prefetch the next plane while this one is computed (the last plane of the
     // chunk needs neither E(k+2) nor H(k+1))
     if (k + 1 < k1) {
-      const Col pl2 = plane(g, k + 2);
-      nEov = load3(a, ocol, pl2, nEo);
-      nErv = load3(a, rcol, pl2, nEr);
+      const Col32 pl2 = plane32(g, k + 2);
+      nEov = load3_32(a, ocol, pl2, nEo);
+      nErv = load3_32(a, rcol, pl2, nEr);
       prefetch_h(k + 1);
     }
     lds_barrier();
 
-    const size_t id = own_off + (size_t)k * plane_sz;
+    const unsigned id = own_off + (unsigned)k * plane_sz;
     // H^{n+1/2}(k) on the own cell
     if (own) {
       T dEz_dy = (E_at(p0, 2, tx, ty + 1) - ek[2]) * idx;
@@ -369,32 +407,32 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
         const T bh = xc[1][0][tx], ch = xc[1][1][tx], kh = xc[1][2][tx];
         const T qy = bh * nP[2] + ch * dEz_dx;
         const T qz = bh * nP[3] + ch * dEy_dx;
-        psi_at(b, 2, pk) = qy;
-        psi_at(b, 3, pk) = qz;
+        psi_st(2, pk, qy);
+        psi_st(3, pk, qz);
         dEz_dx = kh * dEz_dx + qy;
         dEy_dx = kh * dEy_dx + qz;
       }
       T pn;
       if (yl) {
         dEz_dy = fy(1, ty + 1, nYo[2], dEz_dy, pn);
-        b.psi[oy + iy(2, i, lyo, k)] = pn;
+        st32(b.psi, oy + iy(2, i, lyo, k), pn);
         dEx_dy = fy(1, ty + 1, nYo[3], dEx_dy, pn);
-        b.psi[oy + iy(3, i, lyo, k)] = pn;
+        st32(b.psi, oy + iy(3, i, lyo, k), pn);
       }
       if (zl) {
         dEy_dz = fz(1, k, nZo[2], dEy_dz, pn);
-        b.psi[oz + iz(2, i, j, k)] = pn;
+        st32(b.psi, oz + iz(2, i, j, k), pn);
         dEx_dz = fz(1, k, nZo[3], dEx_dz, pn);
-        b.psi[oz + iz(3, i, j, k)] = pn;
+        st32(b.psi, oz + iz(3, i, j, k), pn);
       }
       hx -= dt * (dEz_dy - dEy_dz);
       hy -= dt * (dEx_dz - dEz_dx);
       hz -= dt * (dEy_dx - dEx_dy);
       // streaming stores: the new fields are read again only in the next step,
       // long after this sweep has passed through the caches
-      __builtin_nontemporal_store(hx, &b.H[0][id]);
-      __builtin_nontemporal_store(hy, &b.H[1][id]);
-      __builtin_nontemporal_store(hz, &b.H[2][id]);
+      st32nt(b.H[0], id, hx);
+      st32nt(b.H[1], id, hy);
+      st32nt(b.H[2], id, hz);
     }
     hL[0][(ty + 1) * HW + tx + 1] = hx;
     hL[1][(ty + 1) * HW + tx + 1] = hy;
@@ -452,23 +490,23 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
         const T be = xc[0][0][tx], ce0 = xc[0][1][tx], ke = xc[0][2][tx];
         const T qy = be * nP[0] + ce0 * dHz_dx;
         const T qz = be * nP[1] + ce0 * dHy_dx;
-        psi_at(b, 0, pk) = qy;
-        psi_at(b, 1, pk) = qz;
+        psi_st(0, pk, qy);
+        psi_st(1, pk, qz);
         dHz_dx = ke * dHz_dx + qy;
         dHy_dx = ke * dHy_dx + qz;
       }
       T pn;
       if (yl) {
         dHz_dy = fy(0, ty + 1, nYo[0], dHz_dy, pn);
-        b.psi[oy + iy(0, i, lyo, k)] = pn;
+        st32(b.psi, oy + iy(0, i, lyo, k), pn);
         dHx_dy = fy(0, ty + 1, nYo[1], dHx_dy, pn);
-        b.psi[oy + iy(1, i, lyo, k)] = pn;
+        st32(b.psi, oy + iy(1, i, lyo, k), pn);
       }
       if (zl) {
         dHy_dz = fz(0, k, nZo[0], dHy_dz, pn);
-        b.psi[oz + iz(0, i, j, k)] = pn;
+        st32(b.psi, oz + iz(0, i, j, k), pn);
         dHx_dz = fz(0, k, nZo[1], dHx_dz, pn);
-        b.psi[oz + iz(1, i, j, k)] = pn;
+        st32(b.psi, oz + iz(1, i, j, k), pn);
       }
       const T cx = dHz_dy - dHy_dz;
       const T cy = dHx_dz - dHz_dx;
@@ -476,9 +514,9 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
       const T e0 = tangential_wall(g, 0, i, j, k) ? T(0) : ek[0] + ce * cx;
       const T e1 = tangential_wall(g, 1, i, j, k) ? T(0) : ek[1] + ce * cy;
       const T e2 = tangential_wall(g, 2, i, j, k) ? T(0) : ek[2] + ce * cz;
-      __builtin_nontemporal_store(e0, &b.E[0][id]);
-      __builtin_nontemporal_store(e1, &b.E[1][id]);
-      __builtin_nontemporal_store(e2, &b.E[2][id]);
+      st32nt(b.E[0], id, e0);
+      st32nt(b.E[1], id, e1);
+      st32nt(b.E[2], id, e2);
     }
     hpx = hx;
     hpy = hy;

@@ -229,6 +229,15 @@ def test_light_and_tiled_gather_agree_bitwise(precision, bc, lo):
     assert np.any(ea != 0.0)
 
 
+def test_fused_sweep_refuses_arrays_of_4_gib():
+    """The fused kernels address a field array by 32-bit byte offsets: a grid whose
+    FP32 arrays would reach 4 GiB (1024^3 cells) is refused before anything is
+    allocated, with a message that names the plain sweep."""
+    with pytest.raises(mlk().MlkError) as err:
+        mlk().Simulation((1024, 1024, 1024), precision="fp32", sweep="fused")
+    assert "plain sweep" in str(err.value)
+
+
 def test_ragged_mixed_boundaries_fp64():
     """x periodic with a ragged tail (nx not a multiple of 64), y metallic, z CPML; emitters
     whose windows wrap across the periodic axis."""
