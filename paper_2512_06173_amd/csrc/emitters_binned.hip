@@ -577,7 +577,10 @@ struct Acc<double> {
 
 // scatter; see the file comment.  Contributions are rounded to a fixed-point
 // grid chosen per bin and summed as integers in LDS: integer addition is exact
-// and order-independent, so the result is deterministic.  The grid is
+// and order-independent, so the result is deterministic.  In FP32 the Ex and Ey
+// sums of a cell share one 64-bit integer, Ey 2^32 + Ex: its sum is exact, and
+// since each component's sum stays below 2^30 in magnitude, Ex is the low 32 bits
+// read as a signed value and Ey the rest (two LDS atomics per cell, not three).  The grid is
 // 2^-BITS of a bound on any cell's sum (|amp| times the largest window weight,
 // summed over the bin's emitters): 2^-62 for FP64 fields, far below FP64
 // rounding; 2^-30 for FP32 fields, at the level of FP32 rounding of a cell's
@@ -605,6 +608,10 @@ __device__ __forceinline__ void scatter_body(const FieldPtrs<T>& f, const Geom& 
   // that two workgroups still fit one CU's LDS
   constexpr int kIdCap = sizeof(T) == 4 ? 4096 : 1024;
   __shared__ alignas(16) typename A::U sJ[3][CELLS];
+  // FP32: Ex and Ey share one 64-bit accumulator per cell (sJ[0] and sJ[1] reused),
+  // two LDS atomics per cell instead of three
+  constexpr bool kPackXY = sizeof(T) == 4;
+  unsigned long long* const sJxy = reinterpret_cast<unsigned long long*>(&sJ[0][0]);
   __shared__ WinRec<T> sW[kGroups];
   __shared__ T sAmp[kGroups][3];
   __shared__ unsigned sRun[kGroups];
@@ -730,8 +737,15 @@ __device__ __forceinline__ void scatter_body(const FieldPtrs<T>& f, const Geom& 
       for (int j = 0; j < kMaxWin; ++j) {
         if (j >= cj) break;
         const int s = pk + BX * j;
-        atomicAdd(&sJ[0][s], (typename A::U)A::round(cxk * wy0[j]));
-        atomicAdd(&sJ[1][s], (typename A::U)A::round(cyk * wy1[j]));
+        if constexpr (kPackXY) {
+          // Ex and Ey in one 64-bit integer, Ey 2^32 + Ex (both sums stay below 2^30)
+          const long long pxy = (long long)A::round(cyk * wy1[j]) * 4294967296LL +
+                                (long long)A::round(cxk * wy0[j]);
+          atomicAdd(sJxy + s, (unsigned long long)pxy);
+        } else {
+          atomicAdd(&sJ[0][s], (typename A::U)A::round(cxk * wy0[j]));
+          atomicAdd(&sJ[1][s], (typename A::U)A::round(cyk * wy1[j]));
+        }
         atomicAdd(&sJ[2][s], (typename A::U)A::round(czk * wy0[j]));
       }
     }
@@ -754,6 +768,14 @@ __device__ __forceinline__ void scatter_body(const FieldPtrs<T>& f, const Geom& 
     const bool in = li < ex && lj < ey && lk < ez;
 #pragma unroll
     for (int c = 0; c < 3; ++c) jv[r][c] = in ? (typename A::S)sJ[c][t] : 0;
+    if constexpr (kPackXY) {
+      // the packed sum is Ey 2^32 + Ex exactly; |Ex| < 2^31, so Ex is its low 32 bits
+      // read as a signed value, and Ey what remains
+      const long long pxy = in ? (long long)sJxy[t] : 0LL;
+      const int lx = (int)(unsigned)(unsigned long long)pxy;
+      jv[r][0] = lx;
+      jv[r][1] = (typename A::S)((pxy - (long long)lx) / 4294967296LL);
+    }
     const bool hit = in && (jv[r][0] | jv[r][1] | jv[r][2]) != 0;
     idw[r] = hit ? cell_index(g, x0 + li, y0 + lj, z0 + lk) : 0;
 #pragma unroll
