@@ -467,6 +467,36 @@ mlk_status build_bins(mlk_sim* s) {
     STCHK(read_unions<float>(s, worg, wn, wmax));
   else
     STCHK(read_unions<double>(s, worg, wn, wmax));
+  // FP32 gather: the eight emitters of a wavefront read their window rows from the
+  // staged tile at the same row and plane offsets, so lane i of emitter m reads word
+  // s_m + i + (a common offset), and emitters whose windows start in the same LDS
+  // banks conflict.  The bank of s_m is (x offset + tile width x y offset) mod 64 (the
+  // tile's plane stride is a multiple of 64 words).  Within a staged bin, the
+  // emitters are sorted by that bank and dealt to the wavefronts with a stride, so
+  // those of one wavefront (and of each half) start in banks spread around the 64.
+  // Only the assignment of emitters to lanes changes, not any result.
+  if (s->fp32) {
+    const int TXg = G[0] + 2 * kHalo;
+    std::vector<std::pair<int, int>> v;
+    for (int b = 0; b < s->gdense; ++b) {
+      const int q0 = gstart[b], q1 = gstart[b + 1], n = q1 - q0;
+      const int x0 = gorg[3 * b] - kHalo, y0 = gorg[3 * b + 1] - kHalo;
+      v.clear();
+      for (int q = q0; q < q1; ++q) {
+        const int e = gem[q];
+        v.push_back({((worg[3 * e] - x0) + TXg * (worg[3 * e + 1] - y0)) & 63, e});
+      }
+      std::stable_sort(v.begin(), v.end(), [](const std::pair<int, int>& x,
+                                              const std::pair<int, int>& y) {
+        return x.first < y.first;
+      });
+      const int nw = (n + 7) / 8;
+      int q = q0;
+      for (int w = 0; w < nw; ++w)
+        for (int k = 0; k < 8; ++k)
+          if (w + k * nw < n) gem[q++] = v[w + k * nw].second;
+    }
+  }
   struct Run {
     int bin, l0, d0, c;
   };

@@ -222,5 +222,13 @@ def test_tile_shape_changes_speed_not_results(tmp_path):
     assert d.autotune(cache) == t  # read back from the cache, layer mode included
     assert d.sweep_layers() == a.sweep_layers()
     import json
+    import re
     entries = json.load(open(cache))
     assert len(entries) == 1
+    # an entry written before the tile width was tuned (no "tx") reads as 64 wide
+    text = open(cache).read()
+    assert re.search(r', "tx": \d+', text)
+    open(cache, "w").write(re.sub(r', "tx": \d+', "", text))
+    e = mlk().from_workload(w)
+    e.set_tile_width(32)
+    assert e.autotune(cache) == (t[0], t[1], 64) and e.tile_width() == 64
