@@ -113,9 +113,12 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
     // same XCD: the cache lines that neighbouring x tiles share (the E ring's x = -1
     // and x = TX columns, the halo H column) are then read once into that XCD's L2.
     auto fold = [](int q, int n) { return (q & 1) ? n - 1 - (q >> 1) : (q >> 1); };
+    // Rows are dealt to the XCDs eight at a time; when their count is not a multiple
+    // of eight, the rows past the last multiple take their x tiles one after another.
     const int nch = nblocks / (ntx * nty);
+    const int r8 = nty * nch / 8 * 8;
     int r;
-    if ((nty * nch) % 8 == 0) {
+    if (bid_in < r8 * ntx) {
       const int xcd = bid_in % 8, m = bid_in / 8;
       tile_x = m % ntx;
       r = (m / ntx) * 8 + xcd;
