@@ -11,31 +11,12 @@
 
 namespace mlk {
 
-// Partial flux of block b of nb (grid-stride over the plane).
+// Partial flux of block b of nb (256 threads, grid-stride over the plane).
 template <typename T>
 __device__ __forceinline__ void flux_partial_body(const FieldPtrs<T>& f, const Geom& g,
                                                   const FluxPlane& fp, int b, int nb) {
-  const int a = fp.axis, u = (a + 1) % 3, v = (a + 2) % 3;
-  const int nu = g.n[u], nv = g.n[v];
   __shared__ double red[256];
-  double s = 0.0;
-  for (int t = b * blockDim.x + threadIdx.x; t < nu * nv; t += nb * blockDim.x) {
-    const int iu = t % nu, iv = t / nu;
-    const size_t id = plane_cell(g, a, fp.index, iu, iv);
-    const size_t jd = plane_cell(g, a, fp.index - 1, iu, iv);
-    const double Eu = 0.5 * (fp.Eu0[t] + (double)f.E[u][id]);
-    const double Ev = 0.5 * (fp.Ev0[t] + (double)f.E[v][id]);
-    const double Hv = 0.5 * ((double)f.H[v][id] + (double)f.H[v][jd]);
-    const double Hu = 0.5 * ((double)f.H[u][id] + (double)f.H[u][jd]);
-    s += Eu * Hv - Ev * Hu;
-  }
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) fp.partial[b] = red[0];
+  flux_partial_sum(f, g, fp, b, nb, red);
 }
 
 // Single block: probe samples, the flux total, then the step counter moves on.
@@ -178,8 +159,9 @@ static hipError_t launch_flux_save(const FieldPtrs<T>& f, const Geom& g, const F
 
 template <typename T>
 static hipError_t launch_finish(const FieldPtrs<T>& f, const Geom& g, const FluxPlane& fp,
-                                const Series& ser, int64_t* step, hipStream_t st) {
-  if (fp.on) {
+                                const Series& ser, int64_t* step, bool partials_done,
+                                hipStream_t st) {
+  if (fp.on && !partials_done) {
     hipLaunchKernelGGL(k_flux_partial<T>, dim3(fp.nblocks), dim3(256), 0, st, f, g, fp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -197,12 +179,12 @@ hipError_t flux_save_f32(const FieldPtrs<float>& f, const Geom& g, const FluxPla
   return launch_flux_save<float>(f, g, fp, st);
 }
 hipError_t finish_f64(const FieldPtrs<double>& f, const Geom& g, const FluxPlane& fp,
-                      const Series& ser, int64_t* step, hipStream_t st) {
-  return launch_finish<double>(f, g, fp, ser, step, st);
+                      const Series& ser, int64_t* step, bool partials_done, hipStream_t st) {
+  return launch_finish<double>(f, g, fp, ser, step, partials_done, st);
 }
 hipError_t finish_f32(const FieldPtrs<float>& f, const Geom& g, const FluxPlane& fp,
-                      const Series& ser, int64_t* step, hipStream_t st) {
-  return launch_finish<float>(f, g, fp, ser, step, st);
+                      const Series& ser, int64_t* step, bool partials_done, hipStream_t st) {
+  return launch_finish<float>(f, g, fp, ser, step, partials_done, st);
 }
 
 template <typename T>

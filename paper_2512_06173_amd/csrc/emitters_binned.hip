@@ -593,10 +593,14 @@ struct Acc<double> {
 // axis, set up on the host (see PairDesc): window offsets d0 .. d0+c-1 on the
 // bin-local cells l0 .. l0+c-1.  A window that wraps inside one bin (a periodic
 // axis no longer than the bin) is split into several pairs.
+//
+// Blocks from bins.nscatter on (when fp is given) form the flux partials of the plane
+// instead, in the accumulators' LDS.
 template <typename T, bool EPS = true>
 __device__ __forceinline__ void scatter_body(const FieldPtrs<T>& f, const Geom& g,
                                              const BinPtrs& bins, const WindowPtrs<T>& win,
-                                             const double* mudot, double amp0, int bid) {
+                                             const double* mudot, double amp0, int bid,
+                                             const FluxPlane* fp = nullptr) {
   using A = Acc<T>;
   constexpr int BX = BinCfg<T>::SX, BY = BinCfg<T>::SY, BZ = BinCfg<T>::SZ;
   constexpr int CELLS = BX * BY * BZ;
@@ -618,6 +622,11 @@ __device__ __forceinline__ void scatter_body(const FieldPtrs<T>& f, const Geom& 
   __shared__ int sId[kIdCap];
   __shared__ double sRed[NW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (fp && bid >= bins.nscatter) {  // uniform across the block
+    flux_partial_sum(f, g, *fp, bid - bins.nscatter, fp->nblocks,
+                     reinterpret_cast<double*>(&sJ[0][0]));
+    return;
+  }
   const int b = bins.sbin_id[bid];
   const int bx = b % bins.nbx, by = (b / bins.nbx) % bins.nby, bz = b / (bins.nbx * bins.nby);
   const int x0 = bx * BX, y0 = by * BY, z0 = bz * BZ;
@@ -796,6 +805,14 @@ __global__ __launch_bounds__(kThreads, 4) void k_scatter_bins(FieldPtrs<T> f, Ge
   scatter_body(f, g, bins, win, mudot, g.dt * g.inv_dx * g.inv_dx * g.inv_dx, blockIdx.x);
 }
 
+// The scatter with the flux partials of the plane in fp.nblocks more workgroups.
+template <typename T>
+__global__ __launch_bounds__(kThreads, 4) void k_scatter_flux(FieldPtrs<T> f, Geom g, BinPtrs bins,
+                                                           WindowPtrs<T> win,
+                                                           const double* mudot, FluxPlane fp) {
+  scatter_body(f, g, bins, win, mudot, g.dt * g.inv_dx * g.inv_dx * g.inv_dx, blockIdx.x, &fp);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads, 4) void k_scatter_batch(const ScatterJob<T>* jobs,
                                                             const int* start, int njobs,
@@ -866,10 +883,15 @@ hipError_t tls_step(const TlsPtrs& tls, double dt, const double* Et, double* mud
 
 template <typename T>
 static hipError_t launch_scatter(const FieldPtrs<T>& f, const Geom& g, const BinPtrs& b,
-                                 const WindowPtrs<T>& win, const double* mudot, hipStream_t st) {
+                                 const WindowPtrs<T>& win, const double* mudot,
+                                 const FluxPlane* fp, hipStream_t st) {
   if (b.nscatter <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scatter_bins<T>, dim3(b.nscatter), dim3(kThreads), 0, st, f, g, b, win,
-                     mudot);
+  if (fp && fp->on && fp->nblocks > 0)
+    hipLaunchKernelGGL(k_scatter_flux<T>, dim3(b.nscatter + fp->nblocks), dim3(kThreads), 0, st,
+                       f, g, b, win, mudot, *fp);
+  else
+    hipLaunchKernelGGL(k_scatter_bins<T>, dim3(b.nscatter), dim3(kThreads), 0, st, f, g, b, win,
+                       mudot);
   return hipGetLastError();
 }
 
@@ -886,12 +908,14 @@ hipError_t bin_gather_step_f32(const FieldPtrs<float>& f, const Geom& g, const B
   return launch_gather_step<float>(f, g, b, win, tls, Et, mudot, pop_off, ser, step, fp, st);
 }
 hipError_t bin_scatter_f64(const FieldPtrs<double>& f, const Geom& g, const BinPtrs& b,
-                           const WindowPtrs<double>& win, const double* mudot, hipStream_t st) {
-  return launch_scatter<double>(f, g, b, win, mudot, st);
+                           const WindowPtrs<double>& win, const double* mudot,
+                           const FluxPlane* fp, hipStream_t st) {
+  return launch_scatter<double>(f, g, b, win, mudot, fp, st);
 }
 hipError_t bin_scatter_f32(const FieldPtrs<float>& f, const Geom& g, const BinPtrs& b,
-                           const WindowPtrs<float>& win, const double* mudot, hipStream_t st) {
-  return launch_scatter<float>(f, g, b, win, mudot, st);
+                           const WindowPtrs<float>& win, const double* mudot,
+                           const FluxPlane* fp, hipStream_t st) {
+  return launch_scatter<float>(f, g, b, win, mudot, fp, st);
 }
 
 template <typename T>

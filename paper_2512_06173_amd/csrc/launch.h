@@ -71,10 +71,12 @@ hipError_t energy_f64(const FieldPtrs<double>& old, const FieldPtrs<double>& cur
                       const EnergyRec& er, const int64_t* step, hipStream_t st);
 hipError_t energy_f32(const FieldPtrs<float>& old, const FieldPtrs<float>& cur, size_t ncell,
                       const EnergyRec& er, const int64_t* step, hipStream_t st);
+// partials_done: the flux partials of this step are formed already (by the scatter
+// launch), so only the finishing block runs
 hipError_t finish_f64(const FieldPtrs<double>& f, const Geom& g, const FluxPlane& fp,
-                      const Series& ser, int64_t* step, hipStream_t st);
+                      const Series& ser, int64_t* step, bool partials_done, hipStream_t st);
 hipError_t finish_f32(const FieldPtrs<float>& f, const Geom& g, const FluxPlane& fp,
-                      const Series& ser, int64_t* step, hipStream_t st);
+                      const Series& ser, int64_t* step, bool partials_done, hipStream_t st);
 
 // fp: when given, the same launch saves the flux plane's E^n (needs ngather > 0)
 hipError_t bin_gather_step_f64(const FieldPtrs<double>& f, const Geom& g, const BinPtrs& b,
@@ -85,10 +87,14 @@ hipError_t bin_gather_step_f32(const FieldPtrs<float>& f, const Geom& g, const B
                                const WindowPtrs<float>& win, const TlsPtrs& tls, double* Et,
                                double* mudot, const int64_t* pop_off, const Series& ser,
                                const int64_t* step, const FluxPlane* fp, hipStream_t st);
+// fp: when given, fp->nblocks more workgroups of the same launch form the flux
+// partials of the plane (no window may reach the plane's E cells)
 hipError_t bin_scatter_f64(const FieldPtrs<double>& f, const Geom& g, const BinPtrs& b,
-                           const WindowPtrs<double>& win, const double* mudot, hipStream_t st);
+                           const WindowPtrs<double>& win, const double* mudot,
+                           const FluxPlane* fp, hipStream_t st);
 hipError_t bin_scatter_f32(const FieldPtrs<float>& f, const Geom& g, const BinPtrs& b,
-                           const WindowPtrs<float>& win, const double* mudot, hipStream_t st);
+                           const WindowPtrs<float>& win, const double* mudot,
+                           const FluxPlane* fp, hipStream_t st);
 // bin edge lengths (cells) of the gather (G) and scatter (S) bins for a field precision
 void bin_shape(bool fp32, int G[3], int S[3]);
 // Gather bins of at most this many emitters are light (stage only their windows).

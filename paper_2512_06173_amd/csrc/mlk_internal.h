@@ -279,6 +279,39 @@ __device__ __forceinline__ void flux_save_body(const FieldPtrs<T>& f, const Geom
   fp.Ev0[t] = (double)f.E[v][id];
 }
 
+// Partial flux of block b of nb: 256 threads a block, grid-stride over the plane,
+// summed in FP64 in red (256 doubles of LDS) in a fixed order, so the partials do not
+// depend on the launch that forms them.  Threads from 256 on (a larger block) only
+// take part in the barriers.
+template <typename T>
+__device__ __forceinline__ void flux_partial_sum(const FieldPtrs<T>& f, const Geom& g,
+                                                 const FluxPlane& fp, int b, int nb,
+                                                 double* red) {
+  const int a = fp.axis, u = (a + 1) % 3, v = (a + 2) % 3;
+  const int nu = g.n[u], nv = g.n[v];
+  const int tid = threadIdx.x;
+  if (tid < 256) {
+    double s = 0.0;
+    for (int t = b * 256 + tid; t < nu * nv; t += nb * 256) {
+      const int iu = t % nu, iv = t / nu;
+      const size_t id = plane_cell(g, a, fp.index, iu, iv);
+      const size_t jd = plane_cell(g, a, fp.index - 1, iu, iv);
+      const double Eu = 0.5 * (fp.Eu0[t] + (double)f.E[u][id]);
+      const double Ev = 0.5 * (fp.Ev0[t] + (double)f.E[v][id]);
+      const double Hv = 0.5 * ((double)f.H[v][id] + (double)f.H[v][jd]);
+      const double Hu = 0.5 * ((double)f.H[u][id] + (double)f.H[u][jd]);
+      s += Eu * Hv - Ev * Hu;
+    }
+    red[tid] = s;
+  }
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) fp.partial[b] = red[0];
+}
+
 
 // Binned emitter phase.
 // Gather bins: every emitter belongs to the bin of its centre cell; the

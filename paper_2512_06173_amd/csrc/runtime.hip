@@ -157,6 +157,9 @@ struct mlk_sim {
   int ngather = 0, nscatter = 0, gdense = 0, glight0 = 0, nlight = 0;
   // estimated work of each gather / scatter launch block (host; orders a batch's blocks)
   std::vector<float> gwork, swork;
+  // per axis, the planes that some emitter's union window reaches (the cells the
+  // scatter may change)
+  std::vector<unsigned char> wplane[3];
   int* d_gbin_org = nullptr;
   int* d_gbin_start = nullptr;
   int* d_gbin_em = nullptr;
@@ -467,6 +470,16 @@ mlk_status build_bins(mlk_sim* s) {
     STCHK(read_unions<float>(s, worg, wn, wmax));
   else
     STCHK(read_unions<double>(s, worg, wn, wmax));
+  for (int a = 0; a < 3; ++a) {
+    const int n = g.n[a];
+    s->wplane[a].assign(n, 0);
+    for (int e = 0; e < M; ++e)
+      for (int d = 0; d < wn[3 * e + a]; ++d) {
+        int q = worg[3 * e + a] + d;
+        if (g.periodic[a]) q = ((q % n) + n) % n;
+        if (q >= 0 && q < n) s->wplane[a][q] = 1;
+      }
+  }
   // FP32 gather: the eight emitters of a wavefront read their window rows from the
   // staged tile at the same row and plane offsets, so lane i of emitter m reads word
   // s_m + i + (a common offset), and emitters whose windows start in the same LDS
@@ -954,6 +967,12 @@ mlk_status enqueue_steps(mlk_sim* s, int64_t nsteps) {
   // the gather launch saves the flux plane too when it runs
   const bool fold_save = s->fp.on && s->nem > 0 && s->ngather > 0;
   const FluxPlane* fsave = fold_save ? &s->fp : nullptr;
+  // and the scatter launch forms the flux partials when no window reaches the plane
+  // (the owner write changes no cell the flux reads) and no pole pass runs between them
+  const bool fold_flux = binned && s->fp.on && s->npole == 0 && s->nscatter > 0 &&
+                         (int)s->wplane[s->fp.axis].size() == s->g.n[s->fp.axis] &&
+                         !s->wplane[s->fp.axis][s->fp.index];
+  const FluxPlane* fpart = fold_flux ? &s->fp : nullptr;
   for (int64_t q = 0; q < nsteps; ++q) {
     FieldPtrs<T> f = field_ptrs<T>(s);
     if (s->fp.on && !fold_save) {
@@ -996,8 +1015,10 @@ mlk_status enqueue_steps(mlk_sim* s, int64_t nsteps) {
       // in vacuum the owner write reads no 1/eps_r
       FieldPtrs<T> fs = f;
       if (s->vacuum) fs.epsinv = nullptr;
-      if constexpr (f32) HIPCHK(bin_scatter_f32(fs, s->g, bins, win, s->d_mudot, s->stream));
-      else HIPCHK(bin_scatter_f64(fs, s->g, bins, win, s->d_mudot, s->stream));
+      if constexpr (f32)
+        HIPCHK(bin_scatter_f32(fs, s->g, bins, win, s->d_mudot, fpart, s->stream));
+      else
+        HIPCHK(bin_scatter_f64(fs, s->g, bins, win, s->d_mudot, fpart, s->stream));
     } else if (s->nem > 0) {
       if constexpr (f32)
         HIPCHK(scatter_atomic_f32(f, s->g, win, s->nem, s->d_mudot, s->stream));
@@ -1012,8 +1033,8 @@ mlk_status enqueue_steps(mlk_sim* s, int64_t nsteps) {
     }
     mark_end(s, MLK_PHASE_POLES, t0);
     t0 = mark_begin(s, MLK_PHASE_DETECTORS);
-    if constexpr (f32) HIPCHK(finish_f32(f, s->g, s->fp, ser, s->d_step, s->stream));
-    else HIPCHK(finish_f64(f, s->g, s->fp, ser, s->d_step, s->stream));
+    if constexpr (f32) HIPCHK(finish_f32(f, s->g, s->fp, ser, s->d_step, fold_flux, s->stream));
+    else HIPCHK(finish_f64(f, s->g, s->fp, ser, s->d_step, fold_flux, s->stream));
     mark_end(s, MLK_PHASE_DETECTORS, t0);
   }
   return MLK_OK;

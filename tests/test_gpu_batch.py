@@ -52,6 +52,30 @@ def compare(sa, sb, w):
         assert np.array_equal(sa.populations(), sb.populations())
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_flux_partials_in_the_scatter_launch(precision):
+    """A sim alone forms the flux partials in its scatter launch when no emitter window
+    reaches the flux plane, else in a launch of their own; a batch member always takes
+    the latter.  The series must agree bit for bit either way: planes clear of every
+    window (z = 30, 4) and one that windows reach (z = 15), emitters in z 13..18."""
+    rng = np.random.default_rng(11)
+    for plane in (30, 4, 15):
+        w = W.batch_domain(rng, 40, max_emit=40, steps=0, precision=precision)
+        w.tls.pos[:, 2] = rng.uniform(13.0, 18.0, w.n_emitters)
+        w.flux = (2, plane)
+        say(f"[flux fold] {precision} plane z={plane}, {w.n_emitters} TLS")
+        solo = mlk().from_workload(w, sweep="fused")
+        mem = mlk().from_workload(w, sweep="fused")
+        solo.step(30)
+        with mlk().Batch([mem]) as b:
+            b.step(30)
+            b.sync()
+            compare(solo, mem, w)
+        assert np.all(np.isfinite(solo.flux_series())) and np.any(solo.flux_series() != 0)
+        solo.close()
+        mem.close()
+
+
 @pytest.mark.parametrize("sweep", ["fused", "plain"])
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_batch_equals_members_alone(precision, sweep):
