@@ -83,6 +83,35 @@ __device__ __forceinline__ bool load3_32(const FieldPtrs<T>& f, Col32 col, Col32
 // VGPRs without any in FP32, against 118 with all of them.  TX, the tile width, is
 // 64 (a row per wavefront) or 32 (two rows per wavefront: narrower tiles, more of
 // them, for domains too small to give 64-wide tiles enough workgroups).
+// Cost of a z-layer plane (its psi traffic and stretching) relative to an interior
+// plane in the full FP32 kernel, as measured at 256^3 (chunk trims of 0, 4, 8 and 12
+// planes: 4 was fastest).
+constexpr float kZLayerCost = 1.8f;
+
+// First plane of chunk c of nch over the box's planes [lo, hi) (c = nch gives hi), the
+// chunks cut at equal shares of the summed plane cost where z-layer planes cost
+// kZLayerCost times an interior one.  Every workgroup of a launch of the full kernel
+// runs at once (one per tile and chunk), so the launch lasts as long as its heaviest
+// workgroup: equal-length chunks left those holding the layer planes the heaviest.
+// Every workgroup evaluates the same expression for a boundary, so neighbouring
+// chunks agree on it; each chunk keeps at least one plane.
+__device__ __forceinline__ int chunk_start(const Geom& g, int lo, int hi, int c, int nch) {
+  if (c <= 0) return lo;
+  const int ez = hi - lo;
+  if (c >= nch) return hi;
+  // layer planes at the bottom [0, A) and the top [B, ez) of the box, counted from lo
+  const int A = min(max(g.nlo[2] - lo, 0), ez);
+  const int B = max(min(g.n[2] - g.nhi[2] - lo, ez), A);
+  const float r = kZLayerCost;
+  const float total = (float)ez + (r - 1.f) * (float)(A + ez - B);
+  const float y = total * (float)c / (float)nch;
+  float z;
+  if (y <= r * (float)A) z = y / r;
+  else if (y <= r * (float)A + (float)(B - A)) z = y - (r - 1.f) * (float)A;
+  else z = (float)B + (y - r * (float)A - (float)(B - A)) / r;
+  return lo + min(max((int)(z + 0.5f), c), ez - (nch - c));
+}
+
 template <typename T, int TX, int TY, int CPM = 2>
 __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtrs<T>& b,
                                            const Geom& g, const Box& box, int kz, int ntx,
@@ -101,7 +130,7 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
   __shared__ T xc[2][3][TX];  // x CPML b, c, 1/kappa of the tile's columns (E, H positions)
   __shared__ T yc[2][3][TY + 1];  // y CPML b, c, 1/kappa of rows y0-1 .. y0+TY-1
 
-  int tile_x, tile_y, chunk;
+  int tile_x, tile_y, chunk, k0, k1;
   if (CPM == 2 && sizeof(T) == 4 && (has_cpml(g, 1) || has_cpml(g, 2))) {
     // Heaviest first: the workgroups whose rows or planes lie in the y or z layers
     // carry the psi traffic and arithmetic and take longest.  Rows of tiles (a y tile
@@ -128,6 +157,8 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
     }
     chunk = fold(r % nch, nch);
     tile_y = fold(r / nch, nty);
+    k0 = chunk_start(g, box.lo[2], box.hi[2], chunk, nch);
+    k1 = chunk_start(g, box.lo[2], box.hi[2], chunk + 1, nch);
   } else {
     // XCD-aware tile order: consecutive blocks go to different XCDs; map the
     // blocks one XCD receives onto a contiguous range of tiles.
@@ -137,12 +168,13 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
     tile_x = bid % ntx;
     tile_y = (bid / ntx) % nty;
     chunk = bid / (ntx * nty);
+    k0 = box.lo[2] + chunk * kz;
+    k1 = min(k0 + kz, box.hi[2]);
   }
   // x tiles start on a 128-byte boundary at or below the box; the extra cells
   // below box.lo[0] are updated too (they belong to the CPML shell, whose own
   // pass overwrites them)
   const int x0 = (box.lo[0] & ~31) + tile_x * TX, y0 = box.lo[1] + tile_y * TY;
-  const int k0 = box.lo[2] + chunk * kz, k1 = min(k0 + kz, box.hi[2]);
 
   const int tx = threadIdx.x % TX, ty = threadIdx.x / TX, tid = threadIdx.x;
   const int i = x0 + tx, j = y0 + ty;
