@@ -168,8 +168,9 @@ __device__ __forceinline__ void fused_body(const FieldPtrs<T>& a, const FieldPtr
     tile_x = bid % ntx;
     tile_y = (bid / ntx) % nty;
     chunk = bid / (ntx * nty);
-    k0 = box.lo[2] + chunk * kz;
-    k1 = min(k0 + kz, box.hi[2]);
+    const int nch = nblocks / (ntx * nty);
+    k0 = chunk_start(g, box.lo[2], box.hi[2], chunk, nch);
+    k1 = chunk_start(g, box.lo[2], box.hi[2], chunk + 1, nch);
   }
   // x tiles start on a 128-byte boundary at or below the box; the extra cells
   // below box.lo[0] are updated too (they belong to the CPML shell, whose own
