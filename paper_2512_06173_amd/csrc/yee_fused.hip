@@ -83,18 +83,21 @@ __device__ __forceinline__ bool load3_32(const FieldPtrs<T>& f, Col32 col, Col32
 // VGPRs without any in FP32, against 118 with all of them.  TX, the tile width, is
 // 64 (a row per wavefront) or 32 (two rows per wavefront: narrower tiles, more of
 // them, for domains too small to give 64-wide tiles enough workgroups).
+
 // Cost of a z-layer plane (its psi traffic and stretching) relative to an interior
-// plane in the full FP32 kernel, as measured at 256^3 (chunk trims of 0, 4, 8 and 12
-// planes: 4 was fastest).
+// plane in the full FP32 kernel, as measured at 256^3: of first and last chunks
+// shortened by 0, 4, 8 or 12 planes, 4 was fastest (a cost of 1.8); costs of 1.5 to
+// 2.1 were slower.
 constexpr float kZLayerCost = 1.8f;
 
 // First plane of chunk c of nch over the box's planes [lo, hi) (c = nch gives hi), the
 // chunks cut at equal shares of the summed plane cost where z-layer planes cost
-// kZLayerCost times an interior one.  Every workgroup of a launch of the full kernel
-// runs at once (one per tile and chunk), so the launch lasts as long as its heaviest
-// workgroup: equal-length chunks left those holding the layer planes the heaviest.
-// Every workgroup evaluates the same expression for a boundary, so neighbouring
-// chunks agree on it; each chunk keeps at least one plane.
+// kZLayerCost times an interior one (without z layers in the box: equal depths to
+// within a plane).  At the tile shapes tuned for large grids a launch runs its
+// workgroups in one or two rounds, so it lasts about as long as its heaviest ones:
+// equal-length chunks left those holding the layer planes, or a ragged last chunk,
+// out of step with the rest.  Every workgroup evaluates the same expression for a
+// boundary, so neighbouring chunks agree on it; each chunk keeps at least one plane.
 __device__ __forceinline__ int chunk_start(const Geom& g, int lo, int hi, int c, int nch) {
   if (c <= 0) return lo;
   const int ez = hi - lo;
