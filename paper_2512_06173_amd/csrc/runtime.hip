@@ -2729,6 +2729,10 @@ mlk_status build_tables(mlk_batch* b, BatchTables<T> (&tab)[2]) {
     STCHK(make_order(t.gather, gw));
     STCHK(make_table(t.light, li));
     for (int k = 0; k < kTileSlots; ++k) {
+      // the smallest members first
+      std::stable_sort(fu[k].begin(), fu[k].end(), [](const FusedJob<T>& x, const FusedJob<T>& y) {
+        return x.nblocks < y.nblocks;
+      });
       STCHK(make_table(t.fused[k], fu[k]));
       bool lean = true;
       for (const FusedJob<T>& J : fu[k]) lean = lean && fused_cpm(J.g, J.box) <= 1;
