@@ -669,6 +669,19 @@ def test_fermi_golden_rule_decay_3d():
     assert abs(_rate(t, P[:, 0]) / G - 1) < 0.03
 
 
+@pytest.mark.slow
+def test_superradiance_3d_n_fold():
+    """3-D free space, N = 4 collocated TLS in the weak-excitation state of Sec. IV.A: the
+    emitters share one field and radiate as one dipole of N times the moment, so each
+    population decays at N times the single-emitter golden-rule rate of the test above."""
+    n, cp, steps, w0, mu, N = 48, 12, 5000, 0.25, 0.1, 4
+    G = w0 ** 3 * mu ** 2 / (3 * np.pi) * np.exp(-w0 ** 2)
+    t, P = _decay_run((n, n, n), ("cpml",) * 6, (cp,) * 6, [[n / 2] * 3] * N,
+                      [[0, 0, mu]] * N, steps)
+    for q in range(N):
+        assert abs(_rate(t, P[:, q]) / (N * G) - 1) < 0.03
+
+
 def test_excited_state_is_stationary():
     """|e> has rho01 = 0, so mu_dot = 0 and nothing is ever emitted (semiclassical): the
     probe stays exactly zero and the population stays 1 up to rounding."""
