@@ -2729,7 +2729,8 @@ mlk_status build_tables(mlk_batch* b, BatchTables<T> (&tab)[2]) {
     STCHK(make_order(t.gather, gw));
     STCHK(make_table(t.light, li));
     for (int k = 0; k < kTileSlots; ++k) {
-      // the smallest members first
+      // the smallest members first (by workgroups; measured a little faster than the
+      // members' own order, and than the largest first)
       std::stable_sort(fu[k].begin(), fu[k].end(), [](const FusedJob<T>& x, const FusedJob<T>& y) {
         return x.nblocks < y.nblocks;
       });
