@@ -457,7 +457,10 @@ mlk_status mlk_batch_destroy(mlk_batch* b);
 mlk_status mlk_batch_autotune(mlk_batch* b, const char* cache_path);
 
 /* Tile shape of the fused sweep: rows per workgroup ty (4, 8 or 16) and z planes
- * per workgroup kz (mlk_set_tuning), and the tile width, 64 (the default) or 32 x
+ * per workgroup kz (mlk_set_tuning; the sweep cuts the box's depth into depth/kz
+ * chunks, rounded up, of equal cost, z-layer planes weighing more than interior
+ * ones, so a chunk may hold a few planes more or less than kz), and the tile width,
+ * 64 (the default) or 32 x
  * cells per workgroup (mlk_set_tile_width: narrower tiles give small grids more
  * workgroups; EINVAL for other widths, EUNSUPPORTED when the sim is in layer mode 2
  * and the width leaves no fused box over every x column).  All MLK_ESTATE while the
