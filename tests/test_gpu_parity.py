@@ -200,6 +200,29 @@ def test_sweep_decompositions_agree_bitwise(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_chunk_cuts_do_not_change_results(precision):
+    """The fused sweep cuts the z extent of its box into chunks of equal cost (z-layer
+    planes weigh more), so chunk lengths differ from kz and from each other.  With
+    uneven z layers (3 planes at the bottom, 9 at the top), dielectric and sources, every
+    kz from one plane per chunk to the whole depth gives the plain sweep's fields bit
+    for bit (FP32: every layer in the fused kernel; FP64: the interior box)."""
+    w = _sources_workload((40, 24, 37), ("cpml",) * 6, (6, 5, 4, 7, 3, 9), precision, 0)
+    ref = mlk().from_workload(w, sweep="plain")
+    ref.step(30)
+    want = ref.fields()
+    for kz in (1, 3, 5, 8, 13, 37):
+        sim = mlk().from_workload(w, sweep="fused")
+        if precision == "fp32":
+            sim.set_sweep_layers(1)
+        sim.set_tuning(8, kz)
+        say(f"[chunks] {precision} kz={kz} box={sim.interior_box()}")
+        sim.step(30)
+        assert all(np.array_equal(x, y) for x, y in zip(want, sim.fields())), kz
+        sim.close()
+    ref.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("bc, lo", [("periodic", 40.2), ("pec", 8.2)])
 def test_light_and_tiled_gather_agree_bitwise(precision, bc, lo):
     """An emitter alone in its gather bin is gathered without a tile (a light bin); with
