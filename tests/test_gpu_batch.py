@@ -57,13 +57,14 @@ def test_flux_partials_in_the_scatter_launch(precision):
     """A sim alone forms the flux partials in its scatter launch when no emitter window
     reaches the flux plane, else in a launch of their own; a batch member always takes
     the latter.  The series must agree bit for bit either way: planes clear of every
-    window (z = 30, 4) and one that windows reach (z = 15), emitters in z 13..18."""
+    window (z = 30, 4; x = 30) and ones that windows reach (z = 15, x = 16), emitters
+    in 13..18 along the plane's axis."""
     rng = np.random.default_rng(11)
-    for plane in (30, 4, 15):
+    for axis, plane in ((2, 30), (2, 4), (2, 15), (0, 30), (0, 16)):
         w = W.batch_domain(rng, 40, max_emit=40, steps=0, precision=precision)
-        w.tls.pos[:, 2] = rng.uniform(13.0, 18.0, w.n_emitters)
-        w.flux = (2, plane)
-        say(f"[flux fold] {precision} plane z={plane}, {w.n_emitters} TLS")
+        w.tls.pos[:, axis] = rng.uniform(13.0, 18.0, w.n_emitters)
+        w.flux = (axis, plane)
+        say(f"[flux fold] {precision} plane {'xyz'[axis]}={plane}, {w.n_emitters} TLS")
         solo = mlk().from_workload(w, sweep="fused")
         mem = mlk().from_workload(w, sweep="fused")
         solo.step(30)
